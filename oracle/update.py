@@ -1,0 +1,70 @@
+"""Cheap SPAI update — test infrastructure.
+
+Paper, Section 2.3 (Table 1) and Section 2.4.  With P_1 a SPAI of the anchor
+A(1), the first approach enforces A(1) P_1 ~= A(l) P_l with P_l = Q_l P_1 and
+computes Q_l from the column-separable problem
+
+    min_Q ||A(1) - A(l) Q||_F^2 = sum_i || A(1) e_i - A(l) q_i ||_2^2.
+
+The paper leaves the sparsity pattern of Q open (it inherits an adaptive one
+from its SPAI library).  Two fixed readings are implemented:
+
+* ``diag``    q_i has the single entry i: q_i = <A(l) e_i, A(1) e_i> / ||A(l) e_i||^2,
+              and P_l = diag(q) P_1 is P_1 with row i scaled by q_i;
+* ``pattern`` q_i has the pattern J_i of the SPAI (same local problems as the
+              SPAI with right-hand side A(1) e_i); P_l is applied as Q_l (P_1 X).
+
+The second approach of Table 1 (anchor A(l-1), P_l = Q_l P_{l-1}) is given
+for comparison.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .spai import solve_column, dense_block
+from .sparse import transpose_pattern
+
+
+def diag_factors(n, rowptr, col, val_1, val_l):
+    """q_i = argmin_q ||A(1) e_i - q A(l) e_i||_2 for every i (both on one pattern).
+
+    The one-unknown least-squares problem has the closed form
+    q_i = <A(l) e_i, A(1) e_i> / <A(l) e_i, A(l) e_i>, written out here.
+    """
+    colptr, rowidx, slot = transpose_pattern(n, rowptr, col)
+    q = np.zeros(n)
+    for i in range(n):
+        s = slot[colptr[i]:colptr[i + 1]]
+        a_l = val_l[s]
+        a_1 = val_1[s]
+        num = 0.0
+        den = 0.0
+        for t in range(s.size):
+            num += a_l[t] * a_1[t]
+            den += a_l[t] * a_l[t]
+        q[i] = num / den
+    return q
+
+
+def update_diag(n, P_rowptr, P_val_1, q):
+    """P_l = diag(q) P_1: row i of P_1 scaled by q_i (same pattern)."""
+    out = np.array(P_val_1, dtype=np.float64, copy=True)
+    for i in range(n):
+        out[P_rowptr[i]:P_rowptr[i + 1]] *= q[i]
+    return out
+
+
+def update_pattern(n, rowptr, col, val_1, val_l, pat, columns=None):
+    """Q_l = argmin ||A(1) - A(l) Q||_F on the SPAI pattern; returns (Q values in pat's
+    CSR order, rho per column)."""
+    cols = range(n) if columns is None else columns
+    qv = np.full(pat.J_row.size, np.nan)
+    rho = np.full(n, np.nan)
+    for i in cols:
+        I = pat.I(i)
+        a1 = dense_block(n, rowptr, col, val_1, I, np.array([i]))[:, 0]
+        x, r = solve_column(n, rowptr, col, val_l, pat, i, rhs_full_column=lambda _I, a1=a1: a1)
+        a, b = pat.J_colptr[i], pat.J_colptr[i + 1]
+        qv[pat.P_slot[a:b]] = x
+        rho[i] = r
+    return qv, rho

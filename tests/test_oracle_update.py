@@ -1,0 +1,140 @@
+"""Pins of the oracle's cheap SPAI update (Section 2.3, Table 1; Section 2.4)."""
+import numpy as np
+import pytest
+
+from synth import config0, tiny_random_job, appendix1
+from oracle.assemble import Assembled
+from oracle.sparse import to_dense
+from oracle.spai import SpaiPattern, spai_build
+from oracle.update import diag_factors, update_diag, update_pattern
+from oracle.diagnostics import fro_from_residuals
+
+
+def _setup(job, explicit=None):
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col, explicit=explicit)
+    return asm, pat
+
+
+def _dense(n, pat, v):
+    return to_dense(n, pat.P_rowptr, pat.P_col, v)
+
+
+def test_same_point_gives_identity_bitwise():
+    """(i) p_l = p_1: q = 1 exactly, so P_l = P_1 bit for bit."""
+    job = tiny_random_job(21, 0.15, 1)
+    asm, pat = _setup(job)
+    v1 = asm.values(job.s, job.p_list[0])
+    pv1, _ = spai_build(job.n, asm.rowptr, asm.col, v1, pat)
+    q = diag_factors(job.n, asm.rowptr, asm.col, v1, v1.copy())
+    assert np.all(q == 1.0)
+    np.testing.assert_array_equal(update_diag(job.n, pat.P_rowptr, pv1, q), pv1)
+
+
+def test_full_patterns_give_exact_inverse():
+    """(ii) full Q and P_1 patterns: Q_l P_1 = A(l)^{-1}."""
+    job = tiny_random_job(18, 0.2, 2)
+    n = job.n
+    full = (np.arange(n + 1, dtype=np.int32) * n, np.tile(np.arange(n, dtype=np.int32), n))
+    asm, pat = _setup(job, explicit=full)
+    v1 = asm.values(job.s, job.p_list[0]); vl = asm.values(job.s, job.p_list[2])
+    pv1, _ = spai_build(n, asm.rowptr, asm.col, v1, pat)
+    qv, rho = update_pattern(n, asm.rowptr, asm.col, v1, vl, pat)
+    Pl = _dense(n, pat, qv) @ _dense(n, pat, pv1)
+    Al = to_dense(n, asm.rowptr, asm.col, vl)
+    kappa = np.linalg.cond(Al)
+    np.testing.assert_allclose(Pl, np.linalg.inv(Al), atol=1e-12 * kappa * np.abs(np.linalg.inv(Al)).max())
+    assert fro_from_residuals(rho) <= 1e-12 * kappa * np.linalg.norm(to_dense(n, asm.rowptr, asm.col, v1))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_update_two_sided_bound(seed):
+    """(iii) rebuilt <= updated <= ||I - A(1)P_1|| + ||A(1) - A(l)Q||_F ||P_1||_2 (U-diag)."""
+    job = tiny_random_job(26, 0.15, 20 + seed, npts=4)
+    n = job.n
+    asm, pat = _setup(job)
+    v1 = asm.values(job.s, job.p_list[0])
+    pv1, rho1 = spai_build(n, asm.rowptr, asm.col, v1, pat)
+    P1 = _dense(n, pat, pv1)
+    A1 = to_dense(n, asm.rowptr, asm.col, v1)
+    for p in job.p_list[1:]:
+        vl = asm.values(job.s, p)
+        Al = to_dense(n, asm.rowptr, asm.col, vl)
+        q = diag_factors(n, asm.rowptr, asm.col, v1, vl)
+        Pupd = _dense(n, pat, update_diag(n, pat.P_rowptr, pv1, q))
+        pvr, _ = spai_build(n, asm.rowptr, asm.col, vl, pat)
+        Preb = _dense(n, pat, pvr)
+        upd = np.linalg.norm(np.eye(n) - Al @ Pupd)
+        reb = np.linalg.norm(np.eye(n) - Al @ Preb)
+        bound = (np.linalg.norm(np.eye(n) - A1 @ P1)
+                 + np.linalg.norm(A1 - Al @ np.diag(q)) * np.linalg.norm(P1, 2))
+        assert reb <= upd * (1 + 1e-12)
+        assert upd <= bound * (1 + 1e-12)
+
+
+def test_diag_factor_is_one_column_lstsq():
+    """(v) each q_i equals the SVD least-squares solution of min ||A(1)e_i - q A(l)e_i||."""
+    job = tiny_random_job(23, 0.2, 5)
+    n = job.n
+    asm, _ = _setup(job)
+    v1 = asm.values(job.s, job.p_list[0]); vl = asm.values(job.s, job.p_list[1])
+    q = diag_factors(n, asm.rowptr, asm.col, v1, vl)
+    A1 = to_dense(n, asm.rowptr, asm.col, v1); Al = to_dense(n, asm.rowptr, asm.col, vl)
+    for i in range(n):
+        x, *_ = np.linalg.lstsq(Al[:, [i]], A1[:, i], rcond=None)
+        assert q[i] == pytest.approx(x[0], rel=1e-13)
+
+
+def test_pattern_update_columns_match_full_lstsq():
+    job = tiny_random_job(22, 0.15, 6)
+    n = job.n
+    asm, pat = _setup(job)
+    v1 = asm.values(job.s, job.p_list[0]); vl = asm.values(job.s, job.p_list[1])
+    qv, rho = update_pattern(n, asm.rowptr, asm.col, v1, vl, pat)
+    A1 = to_dense(n, asm.rowptr, asm.col, v1); Al = to_dense(n, asm.rowptr, asm.col, vl)
+    Q = _dense(n, pat, qv)
+    for i in range(n):
+        J = pat.J(i)
+        x, *_ = np.linalg.lstsq(Al[:, J], A1[:, i], rcond=None)
+        np.testing.assert_allclose(Q[J, i], x, rtol=1e-11, atol=1e-13)
+    # ||A(1) - A(l) Q||_F from the column residuals (Section 2.4, the last display)
+    assert np.linalg.norm(A1 - Al @ Q) == pytest.approx(fro_from_residuals(rho), rel=1e-10)
+
+
+def test_appendix1_pattern_update_is_identity_outside_leading_block():
+    """(iv) Appendix I: A(l) - A(1) lives in the leading 2x2 block, so Q e_i = e_i for i >= 2."""
+    job = appendix1(s=0.5)
+    n = job.n
+    asm, pat = _setup(job)
+    v1 = asm.values(0.5, job.p_list[0])
+    for p in job.p_list[1:]:
+        vl = asm.values(0.5, p)
+        cols = list(range(0, 12)) + [500, 1005]
+        qv, rho = update_pattern(n, asm.rowptr, asm.col, v1, vl, pat, columns=cols)
+        Q = _dense(n, pat, np.nan_to_num(qv))
+        for i in cols[2:]:
+            e = np.zeros(n); e[i] = 1.0
+            np.testing.assert_allclose(Q[:, i], e, atol=1e-14)
+            assert rho[i] <= 1e-13
+        # the leading block is the exact 2x2 solve A1(l)^{-1} A1(1)
+        Al = to_dense(n, asm.rowptr, asm.col, vl)[:2, :2]
+        A1 = to_dense(n, asm.rowptr, asm.col, v1)[:2, :2]
+        np.testing.assert_allclose(Q[:2, :2], np.linalg.solve(Al, A1), rtol=1e-13)
+
+
+def test_config0_update_quality_ratio():
+    """C0: the U-diag update stays within the two-sided bound along the whole sequence."""
+    job = config0()
+    n = job.n
+    asm, pat = _setup(job)
+    v1 = asm.values(1.0, job.p_list[0])
+    pv1, rho1 = spai_build(n, asm.rowptr, asm.col, v1, pat)
+    for p in job.p_list[1:]:
+        vl = asm.values(1.0, p)
+        q = diag_factors(n, asm.rowptr, asm.col, v1, vl)
+        # M = I and D1 = M, so A(l) = A(1) + dp I: q_i has the closed form
+        # (a_i . a_i + dp a_ii) / (a_i . a_i + 2 dp a_ii + dp^2), a_i = A(1) e_i
+        A1 = to_dense(n, asm.rowptr, asm.col, v1)
+        dp = p - job.p_list[0]
+        nn = np.sum(A1 * A1, axis=0); dd = np.diag(A1)
+        np.testing.assert_allclose(q, (nn + dp * dd) / (nn + 2 * dp * dd + dp * dp), rtol=1e-14)
