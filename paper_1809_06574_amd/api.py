@@ -1,0 +1,225 @@
+"""Thin Python objects over the C ABI, with PyTorch tensors as device memory.
+
+Only argument marshalling happens here: every step of assembly, SPAI,
+update and block GMRES runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import lib as L
+
+
+def _dev_i32(x, device):
+    return torch.as_tensor(x, dtype=torch.int32).to(device).contiguous()
+
+
+def _dev_f64(x, device):
+    return torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
+
+
+class Context:
+    """A device and the HIP stream all calls are ordered on."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        L.check(L.pmor_ctx_create(C.byref(h), device, C.c_void_p(self.stream.cuda_stream)), "pmor_ctx_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            L.pmor_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """A parametric system A(s,p) = s^2 M(p) + s D(p) + K(p) (terms by role)."""
+
+    def __init__(self, ctx: Context, terms: Dict[str, object]):
+        """``terms[role] = (rowptr, col, val)`` arrays (host or device) or an object with
+        ``rowptr``, ``col``, ``val`` attributes; roles M0, M1, D0, D1, K0, K1."""
+        self.ctx = ctx
+        dev = ctx.device
+        self._keep = []
+        csrs = [None] * L.PMOR_NROLES
+        n = None
+        for r, role in enumerate(L.ROLES):
+            if role not in terms:
+                continue
+            T = terms[role]
+            rp, ci, va = (T.rowptr, T.col, T.val) if hasattr(T, "rowptr") else T
+            rp, ci, va = _dev_i32(rp, dev), _dev_i32(ci, dev), _dev_f64(va, dev)
+            self._keep += [rp, ci, va]
+            n = rp.numel() - 1
+            csrs[r] = L.Csr(n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+        arr = (C.POINTER(L.Csr) * L.PMOR_NROLES)(*[C.pointer(c) if c is not None else None for c in csrs])
+        h = C.c_void_p()
+        L.check(L.pmor_problem_create(ctx.handle, arr, C.byref(h)), "pmor_problem_create")
+        self.handle = h
+        self._keep = []  # the library copied the terms
+        nn, nz = C.c_int32(), C.c_int32()
+        L.check(L.pmor_problem_info(h, C.byref(nn), C.byref(nz)), "pmor_problem_info")
+        self.n, self.nnz = nn.value, nz.value
+
+    def close(self):
+        if self.handle:
+            L.pmor_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- pattern / values -------------------------------------------------
+    def pattern(self):
+        dev = self.ctx.device
+        rp = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        mp = torch.empty(L.PMOR_NROLES * max(self.nnz, 1), dtype=torch.int32, device=dev)
+        L.check(L.pmor_problem_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), mp.data_ptr()), "pattern")
+        return rp, ci[: self.nnz], mp[: L.PMOR_NROLES * self.nnz].view(L.PMOR_NROLES, self.nnz)
+
+    def assemble(self, s: float, p: float) -> torch.Tensor:
+        out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.ctx.device)
+        L.check(L.pmor_assemble(self.handle, float(s), float(p), out.data_ptr()), "pmor_assemble")
+        return out[: self.nnz]
+
+    def spmm(self, aval: torch.Tensor, X: torch.Tensor, alpha=1.0, beta=0.0, Y=None) -> torch.Tensor:
+        k = X.shape[1]
+        if Y is None:
+            Y = torch.zeros_like(X)
+        L.check(L.pmor_spmm(self.handle, aval.data_ptr(), X.data_ptr(), X.stride(0), Y.data_ptr(), Y.stride(0), k,
+                            float(alpha), float(beta)), "pmor_spmm")
+        return Y
+
+    def table2_norms(self, s1, p1, s2, p2):
+        a, b = C.c_double(), C.c_double()
+        L.check(L.pmor_table2_norms(self.handle, s1, p1, s2, p2, C.byref(a), C.byref(b)), "pmor_table2_norms")
+        return a.value, b.value
+
+    # --- preconditioner / solve ------------------------------------------
+    def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False):
+        return Spai(self, s, p, pattern=pattern, precision=precision, update=update, stats=stats)
+
+    def block_solve(self, spai, s, p, B: torch.Tensor, m=30, tol=1e-8, max_cycles=20, X=None, raise_on_error=True):
+        n, k = B.shape
+        if X is None:
+            X = torch.empty((n, k), dtype=torch.float64, device=B.device)
+        st = L.Stats()
+        o = L.SolveOpts(m, max_cycles, tol)
+        rc = L.block_solve(self.handle, spai.handle if spai is not None else None, float(s), float(p), B.data_ptr(),
+                           B.stride(0), k, X.data_ptr(), X.stride(0), C.byref(o), C.byref(st))
+        if raise_on_error:
+            L.check(rc, "block_solve")
+        return X, st.as_dict(), rc
+
+    def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
+                       pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20):
+        n, k = B.shape
+        npts = len(p_list)
+        X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
+        sl = (C.c_double * npts)(*[float(x) for x in s_list])
+        pl = (C.c_double * npts)(*[float(x) for x in p_list])
+        so = _spai_opts(pattern, precision, update, self.ctx.device, self)
+        vo = L.SolveOpts(m, max_cycles, tol)
+        stats = (L.Stats * npts)()
+        pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
+        L.check(L.pmor_sequence_solve(self.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(),
+                                      X.stride(1), pol, C.byref(so), C.byref(vo), stats), "pmor_sequence_solve")
+        return X, [s.as_dict() for s in stats]
+
+
+def _spai_opts(pattern, precision, update, device, keeper):
+    o = L.SpaiOpts()
+    o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32}[precision]
+    o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN}[update]
+    if pattern is None:
+        o.pattern = L.PMOR_PAT_A
+    else:
+        cp, rw = _dev_i32(pattern[0], device), _dev_i32(pattern[1], device)
+        keeper._pat = (cp, rw)
+        o.pattern = L.PMOR_PAT_EXPLICIT
+        o.nnz_explicit = rw.numel()
+        o.pat_colptr = cp.data_ptr()
+        o.pat_row = rw.data_ptr()
+    return o
+
+
+class Spai:
+    """SPAI of A(s,p) on a pattern, with the first-approach update."""
+
+    def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False):
+        self.pb = pb
+        self.update_kind = update
+        o = _spai_opts(pattern, precision, update, pb.ctx.device, self)
+        h = C.c_void_p()
+        st = L.Stats()
+        rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), C.byref(st) if stats else None)
+        self.handle = h if h.value else None
+        self.last_stats = st.as_dict() if stats else None
+        L.check(rc, "spai_build")
+        nz, mj, mi = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(L.spai_info(self.handle, C.byref(nz), C.byref(mj), C.byref(mi)), "spai_info")
+        self.nnzP, self.maxJ, self.maxI = nz.value, mj.value, mi.value
+
+    def update(self, s, p, stats=False):
+        st = L.Stats()
+        L.check(L.spai_update(self.handle, float(s), float(p), C.byref(st) if stats else None), "spai_update")
+        self.last_stats = st.as_dict() if stats else None
+        return self.last_stats
+
+    def rebuild(self, s, p, stats=False):
+        st = L.Stats()
+        L.check(L.spai_rebuild(self.handle, float(s), float(p), C.byref(st) if stats else None), "spai_rebuild")
+        self.last_stats = st.as_dict() if stats else None
+        return self.last_stats
+
+    def export(self):
+        dev = self.pb.ctx.device
+        n = self.pb.n
+        rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(self.nnzP, dtype=torch.int32, device=dev)
+        va = torch.empty(self.nnzP, dtype=torch.float64, device=dev)
+        qlen = self.nnzP if self.update_kind == "pattern" else n
+        qv = torch.empty(qlen, dtype=torch.float64, device=dev)
+        rho = torch.empty(n, dtype=torch.float64, device=dev)
+        L.check(L.spai_export(self.handle, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), qv.data_ptr(),
+                              rho.data_ptr()), "spai_export")
+        return {"rowptr": rp, "col": ci, "val": va, "q": qv, "rho": rho}
+
+    def export_sets(self):
+        dev = self.pb.ctx.device
+        n = self.pb.n
+        nI = C.c_int64()
+        L.check(L.spai_export_sets(self.handle, None, None, None, None, C.byref(nI)), "spai_export_sets")
+        jc = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        jr = torch.empty(self.nnzP, dtype=torch.int32, device=dev)
+        ic = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        ir = torch.empty(max(nI.value, 1), dtype=torch.int32, device=dev)
+        L.check(L.spai_export_sets(self.handle, jc.data_ptr(), jr.data_ptr(), ic.data_ptr(), ir.data_ptr(),
+                                   C.byref(nI)), "spai_export_sets")
+        return jc, jr, ic, ir[: nI.value]
+
+    def close(self):
+        if self.handle:
+            L.spai_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,535 @@
+// Pattern setup on the device (integer work, bit-exact):
+//  * validation of the caller's term CSR arrays;
+//  * the union pattern of the terms plus the diagonal (the pattern of every
+//    A(s,p) = s^2 M(p) + s D(p) + K(p)), per-term slot maps, packed term values;
+//  * the CSC view of a pattern with its CSC -> CSR slot map;
+//  * the SPAI index sets: J_j (pattern of column j of P) and the shadow I_j
+//    (rows of A(:, J_j) holding a nonzero), and the buckets of columns by
+//    (|J_j|, |I_j|) that select the least-squares kernel.
+#include "common.hpp"
+
+namespace pmor {
+
+// ---------------------------------------------------------------------------
+// exclusive scan of n int64 counts (out may alias in); out[n] = total
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_tile(const int64_t* in, int64_t n, int64_t* out,
+                                                      int64_t* sums) {
+  __shared__ int64_t s[SCAN_T];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_I;
+  int64_t v[SCAN_I];
+  int64_t run = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i) {
+    int64_t x = (base + i < n) ? in[base + i] : 0;
+    v[i] = run;
+    run += x;
+  }
+  s[threadIdx.x] = run;
+  __syncthreads();
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    int64_t add = (threadIdx.x >= o) ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t excl = s[threadIdx.x] - run;
+#pragma unroll
+  for (int i = 0; i < SCAN_I; ++i)
+    if (base + i < n) out[base + i] = v[i] + excl;
+  if (threadIdx.x == SCAN_T - 1) sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_add(int64_t* out, int64_t n, const int64_t* offs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += offs[i / SCAN_TILE];
+}
+
+__global__ void k_set_total(int64_t* out, int64_t n, const int64_t* in_last, const int64_t* excl_last) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = *excl_last + *in_last;
+}
+
+// in and out have n+1 slots; in[0..n) are counts (in may alias out).
+int scan_exclusive(int64_t* buf, int64_t n, hipStream_t st) {
+  if (n == 0) {
+    PMOR_HIP(hipMemsetAsync(buf, 0, sizeof(int64_t), st));
+    return PMOR_OK;
+  }
+  int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  int64_t* sums = nullptr;
+  int64_t* last = nullptr;
+  PMOR_HIP(hipMalloc((void**)&sums, sizeof(int64_t) * (tiles + 1)));
+  PMOR_HIP(hipMalloc((void**)&last, sizeof(int64_t)));
+  PMOR_HIP(hipMemcpyAsync(last, buf + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(SCAN_T), 0, st, buf, n, buf, sums);
+  PMOR_HIP(hipGetLastError());
+  if (tiles > 1) {
+    PMOR_TRY(scan_exclusive(sums, tiles, st));
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, buf, n, sums);
+    PMOR_HIP(hipGetLastError());
+  } else {
+    PMOR_HIP(hipMemsetAsync(sums, 0, sizeof(int64_t), st));
+  }
+  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, st, buf, n, last, buf + n - 1);
+  PMOR_HIP(hipGetLastError());
+  PMOR_HIP(hipStreamSynchronize(st));
+  PMOR_HIP(hipFree(sums));
+  PMOR_HIP(hipFree(last));
+  return PMOR_OK;
+}
+
+__global__ void k_i64_to_i32(const int64_t* in, int32_t* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int32_t)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// validation of one CSR term: error bits in *err (1 rowptr, 2 range, 4 order)
+// ---------------------------------------------------------------------------
+__global__ void k_validate_csr(int n, int nnz, const int32_t* rowptr, const int32_t* col, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == 0 && rowptr[0] != 0) atomicOr(err, 1);
+  if (i == n) {
+    if (rowptr[n] != nnz) atomicOr(err, 1);
+    return;
+  }
+  int a = rowptr[i], b = rowptr[i + 1];
+  if (b < a || a < 0 || b > nnz) { atomicOr(err, 1); return; }
+  int prev = -1;
+  for (int e = a; e < b; ++e) {
+    int c = col[e];
+    if (c < 0 || c >= n) { atomicOr(err, 2); return; }
+    if (c <= prev) { atomicOr(err, 4); return; }
+    prev = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// union pattern
+// ---------------------------------------------------------------------------
+struct TermPtrs {
+  const int32_t* rowptr[PMOR_NROLES];
+  const int32_t* col[PMOR_NROLES];
+  const double* val[PMOR_NROLES];
+  int present[PMOR_NROLES];
+  int slot[PMOR_NROLES];
+};
+
+// Walks the sorted column lists of row i of every present term and the diagonal,
+// visiting each distinct column once in ascending order.
+template <bool FILL>
+__global__ void k_union(int n, TermPtrs t, int64_t* counts, const int32_t* rowptr_out, int32_t* col_out,
+                        int32_t* maps, double* tval, int64_t nnz_out, int* maxlen) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int cur[PMOR_NROLES], end[PMOR_NROLES];
+#pragma unroll
+  for (int r = 0; r < PMOR_NROLES; ++r) {
+    if (t.present[r]) { cur[r] = t.rowptr[r][i]; end[r] = t.rowptr[r][i + 1]; }
+    else { cur[r] = 0; end[r] = 0; }
+  }
+  bool diag_done = false;
+  int64_t pos = FILL ? rowptr_out[i] : 0;
+  int cnt = 0;
+  while (true) {
+    int cmin = 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < PMOR_NROLES; ++r)
+      if (cur[r] < end[r]) cmin = min(cmin, t.col[r][cur[r]]);
+    if (!diag_done) cmin = min(cmin, i);
+    if (cmin == 0x7fffffff) break;
+    if (cmin == i) diag_done = true;
+    if (FILL) {
+      col_out[pos] = cmin;
+#pragma unroll
+      for (int r = 0; r < PMOR_NROLES; ++r) {
+        int hit = (cur[r] < end[r] && t.col[r][cur[r]] == cmin) ? cur[r] : -1;
+        maps[(int64_t)r * nnz_out + pos] = hit;
+        if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + pos] = hit >= 0 ? t.val[r][hit] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PMOR_NROLES; ++r)
+      if (cur[r] < end[r] && t.col[r][cur[r]] == cmin) ++cur[r];
+    ++pos;
+    ++cnt;
+  }
+  if (!FILL) {
+    counts[i] = cnt;
+    atomicMax(maxlen, cnt);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSC view of a CSR pattern (transpose), rows ascending inside every column
+// ---------------------------------------------------------------------------
+__global__ void k_col_count(int n, const int32_t* rowptr, const int32_t* col, int64_t* ccount) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) atomicAdd((unsigned long long*)&ccount[col[e]], 1ull);
+}
+
+__global__ void k_col_fill(int n, const int32_t* rowptr, const int32_t* col, const int32_t* colptr,
+                           int32_t* cursor, int32_t* rowidx, int32_t* slot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    int c = col[e];
+    int q = colptr[c] + atomicAdd(&cursor[c], 1);
+    rowidx[q] = i;
+    slot[q] = e;
+  }
+}
+
+// insertion sort of every column by row (keys unique), carrying the slot map
+__global__ void k_col_sort(int n, const int32_t* colptr, int32_t* rowidx, int32_t* slot, int* maxlen) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int a = colptr[c], b = colptr[c + 1];
+  atomicMax(maxlen, b - a);
+  for (int q = a + 1; q < b; ++q) {
+    int r = rowidx[q], s = slot[q];
+    int p = q - 1;
+    while (p >= a && rowidx[p] > r) {
+      rowidx[p + 1] = rowidx[p];
+      slot[p + 1] = slot[p];
+      --p;
+    }
+    rowidx[p + 1] = r;
+    slot[p + 1] = s;
+  }
+}
+
+// pattern (n x n, nnz entries in CSR) -> CSC arrays allocated here
+int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
+                      int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st) {
+  int64_t* cc = nullptr;
+  int32_t* cursor = nullptr;
+  int* dmax = nullptr;
+  PMOR_HIP(hipMalloc((void**)&cc, sizeof(int64_t) * (n + 1)));
+  PMOR_HIP(hipMalloc((void**)&cursor, sizeof(int32_t) * (n + 1)));
+  PMOR_HIP(hipMalloc((void**)&dmax, sizeof(int)));
+  PMOR_HIP(hipMalloc((void**)colptr, sizeof(int32_t) * (n + 1)));
+  PMOR_HIP(hipMalloc((void**)rowidx, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(hipMalloc((void**)slot, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(hipMemsetAsync(cc, 0, sizeof(int64_t) * (n + 1), st));
+  PMOR_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (n + 1), st));
+  PMOR_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_col_count, dim3(g), dim3(256), 0, st, n, rowptr, col, cc);
+    PMOR_HIP(hipGetLastError());
+  }
+  PMOR_TRY(scan_exclusive(cc, n, st));
+  hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, cc, *colptr,
+                     (int64_t)n + 1);
+  PMOR_HIP(hipGetLastError());
+  if (n > 0) {
+    hipLaunchKernelGGL(k_col_fill, dim3(g), dim3(256), 0, st, n, rowptr, col, *colptr, cursor, *rowidx, *slot);
+    PMOR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_col_sort, dim3(g), dim3(256), 0, st, n, *colptr, *rowidx, *slot, dmax);
+    PMOR_HIP(hipGetLastError());
+  }
+  int hmax = 0;
+  PMOR_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  *maxcol = hmax;
+  PMOR_HIP(hipFree(cc));
+  PMOR_HIP(hipFree(cursor));
+  PMOR_HIP(hipFree(dmax));
+  return PMOR_OK;
+}
+
+int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  int* derr = nullptr;
+  PMOR_HIP(hipMalloc((void**)&derr, sizeof(int) * 2));
+  PMOR_HIP(hipMemsetAsync(derr, 0, sizeof(int) * 2, st));
+  TermPtrs tp{};
+  int nt = 0;
+  for (int r = 0; r < PMOR_NROLES; ++r) {
+    pb->role_slot[r] = -1;
+    tp.present[r] = 0;
+    tp.slot[r] = -1;
+    if (!terms[r]) continue;
+    const pmor_csr* T = terms[r];
+    tp.rowptr[r] = T->rowptr;
+    tp.col[r] = T->col;
+    tp.val[r] = T->val;
+    tp.present[r] = 1;
+    tp.slot[r] = nt;
+    pb->role_slot[r] = nt++;
+    hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, n, T->nnz,
+                       T->rowptr, T->col, derr);
+    PMOR_HIP(hipGetLastError());
+  }
+  pb->nterms = nt;
+  int herr = 0;
+  PMOR_HIP(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  if (herr) {
+    (void)hipFree(derr);
+    return fail(PMOR_EINVAL, std::string("malformed term CSR (") +
+                                 ((herr & 1) ? "rowptr " : "") + ((herr & 2) ? "column-range " : "") +
+                                 ((herr & 4) ? "column-order" : "") + ")");
+  }
+  int64_t* cnt = nullptr;
+  PMOR_HIP(hipMalloc((void**)&cnt, sizeof(int64_t) * (n + 1)));
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_union<false>, dim3(g), dim3(256), 0, st, n, tp, cnt, nullptr, nullptr, nullptr, nullptr,
+                     (int64_t)0, derr + 1);
+  PMOR_HIP(hipGetLastError());
+  PMOR_TRY(scan_exclusive(cnt, n, st));
+  int64_t nnz64 = 0;
+  int maxrow = 0;
+  PMOR_HIP(hipMemcpyAsync(&nnz64, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipMemcpyAsync(&maxrow, derr + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  if (nnz64 >= ((int64_t)1 << 31)) {
+    (void)hipFree(cnt); (void)hipFree(derr);
+    return fail(PMOR_EINVAL, "union pattern has 2^31 or more entries");
+  }
+  pb->nnz = (int32_t)nnz64;
+  pb->max_row_len = maxrow;
+  const int64_t nnz = nnz64;
+  PMOR_HIP(hipMalloc((void**)&pb->rowptr, sizeof(int32_t) * (n + 1)));
+  PMOR_HIP(hipMalloc((void**)&pb->col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(hipMalloc((void**)&pb->maps, sizeof(int32_t) * PMOR_NROLES * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(hipMalloc((void**)&pb->tval, sizeof(double) * (nt > 0 ? nt : 1) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(hipMalloc((void**)&pb->aval, sizeof(double) * (nnz > 0 ? nnz : 1)));
+  hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, cnt, pb->rowptr,
+                     (int64_t)n + 1);
+  PMOR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_union<true>, dim3(g), dim3(256), 0, st, n, tp, nullptr, pb->rowptr, pb->col, pb->maps,
+                     pb->tval, nnz, nullptr);
+  PMOR_HIP(hipGetLastError());
+  PMOR_HIP(hipStreamSynchronize(st));
+  PMOR_HIP(hipFree(cnt));
+  PMOR_HIP(hipFree(derr));
+  int maxcol = 0;
+  PMOR_TRY(transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st));
+  pb->max_col_len = maxcol;
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SPAI index sets
+// ---------------------------------------------------------------------------
+// explicit pattern check: sorted, in range, contains the diagonal (err bits 1, 2, 8)
+__global__ void k_validate_pattern(int n, int nnz, const int32_t* colptr, const int32_t* row, int* err) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > n) return;
+  if (j == 0 && colptr[0] != 0) atomicOr(err, 1);
+  if (j == n) { if (colptr[n] != nnz) atomicOr(err, 1); return; }
+  int a = colptr[j], b = colptr[j + 1];
+  if (b < a || a < 0 || b > nnz) { atomicOr(err, 1); return; }
+  int prev = -1;
+  bool diag = false;
+  for (int q = a; q < b; ++q) {
+    int r = row[q];
+    if (r < 0 || r >= n || r <= prev) { atomicOr(err, 2); return; }
+    diag |= (r == j);
+    prev = r;
+  }
+  if (!diag) atomicOr(err, 8);
+}
+
+// I_j = sorted union of the rows of A(:, c), c in J_j (k-way merge of CSC columns)
+template <bool FILL>
+__global__ void k_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
+                         const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow,
+                         int* maxJ, int* maxI) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
+  constexpr int MAXJ = 64;
+  if (nj > MAXJ) {
+    if (!FILL) { counts[j] = 0; atomicMax(maxJ, nj); }
+    return;
+  }
+  int cur[MAXJ], end[MAXJ];
+  for (int t = 0; t < nj; ++t) {
+    int c = Jrow[ja + t];
+    cur[t] = Acolptr[c];
+    end[t] = Acolptr[c + 1];
+  }
+  int64_t pos = FILL ? Icolptr[j] : 0;
+  int cnt = 0;
+  while (true) {
+    int rmin = 0x7fffffff;
+    for (int t = 0; t < nj; ++t)
+      if (cur[t] < end[t]) rmin = min(rmin, Arowidx[cur[t]]);
+    if (rmin == 0x7fffffff) break;
+    for (int t = 0; t < nj; ++t)
+      if (cur[t] < end[t] && Arowidx[cur[t]] == rmin) ++cur[t];
+    if (FILL) Irow[pos++] = rmin;
+    ++cnt;
+  }
+  if (!FILL) {
+    counts[j] = cnt;
+    atomicMax(maxJ, nj);
+    atomicMax(maxI, cnt);
+  }
+}
+
+// inv[map[q]] = q
+__global__ void k_invert_map(const int32_t* map, int64_t len, int32_t* inv) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < len) inv[map[q]] = (int32_t)q;
+}
+
+// bucket of a column: the least-squares kernel that takes it
+__host__ __device__ inline int bucket_of(int nj, int ni) {
+  if (nj <= 8 && ni <= 64) return 0;
+  if (nj <= 16 && ni <= 64) return 1;
+  if (nj <= 16 && ni <= 128) return 2;
+  if (nj <= 16 && ni <= 256) return 3;
+  if (nj <= 64 && ni <= 512) return 4;
+  return 7;  // unsupported
+}
+
+__global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* Icolptr, int* bcount) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int b = bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j]));
+  atomicAdd(&bcount[b], 1);
+}
+
+// stable fill: one workgroup of 1024 threads walks the columns in order
+__global__ __launch_bounds__(1024) void k_bucket_fill(int n, const int32_t* Jcolptr, const int64_t* Icolptr,
+                                                      const int* boff, int32_t* cols) {
+  __shared__ int cnt[8][1024];
+  __shared__ int base[8];
+  if (threadIdx.x < 8) base[threadIdx.x] = boff[threadIdx.x];
+  __syncthreads();
+  for (int start = 0; start < n; start += 1024) {
+    int j = start + threadIdx.x;
+    int b = (j < n) ? bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j])) : -1;
+    for (int q = 0; q < 8; ++q) cnt[q][threadIdx.x] = (b == q);
+    __syncthreads();
+    // inclusive scan per bucket (Hillis-Steele)
+    for (int o = 1; o < 1024; o <<= 1) {
+      int v[8];
+      for (int q = 0; q < 8; ++q) v[q] = (threadIdx.x >= o) ? cnt[q][threadIdx.x - o] : 0;
+      __syncthreads();
+      for (int q = 0; q < 8; ++q) cnt[q][threadIdx.x] += v[q];
+      __syncthreads();
+    }
+    if (b >= 0) cols[base[b] + cnt[b][threadIdx.x] - 1] = j;
+    __syncthreads();
+    if (threadIdx.x < 8) base[threadIdx.x] += cnt[threadIdx.x][1023];
+    __syncthreads();
+  }
+}
+
+int build_spai_sets(pmor_spai* h) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  int* dflag = nullptr;
+  PMOR_HIP(hipMalloc((void**)&dflag, sizeof(int) * 4));
+  PMOR_HIP(hipMemsetAsync(dflag, 0, sizeof(int) * 4, st));
+  unsigned g = (unsigned)((n + 255) / 256);
+  if (h->opts.pattern == PMOR_PAT_A) {
+    // J_j = pattern of column j of A; the union pattern holds the full diagonal,
+    // so this is the CSC view of A, and P's CSR pattern is A's own.
+    h->Jcolptr = pb->colptr; h->Jrow = pb->rowidx; h->own_J = false;
+    h->Prowptr = pb->rowptr; h->Pcol = pb->col; h->Pslot = pb->cscslot; h->own_P = false;
+    h->nnzP = pb->nnz;
+  } else {
+    if (!h->opts.pat_colptr || !h->opts.pat_row || h->opts.nnz_explicit < n) {
+      (void)hipFree(dflag);
+      return fail(PMOR_EINVAL, "explicit SPAI pattern: null arrays or fewer than n entries");
+    }
+    hipLaunchKernelGGL(k_validate_pattern, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, n,
+                       h->opts.nnz_explicit, h->opts.pat_colptr, h->opts.pat_row, dflag);
+    PMOR_HIP(hipGetLastError());
+    int herr = 0;
+    PMOR_HIP(hipMemcpyAsync(&herr, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));
+    if (herr) {
+      (void)hipFree(dflag);
+      return fail(PMOR_EINVAL, (herr & 8) ? "explicit SPAI pattern: a column lacks its diagonal"
+                                          : "explicit SPAI pattern: malformed CSC");
+    }
+    const int64_t nnzP = h->opts.nnz_explicit;
+    PMOR_HIP(hipMalloc((void**)&h->Jcolptr, sizeof(int32_t) * (n + 1)));
+    PMOR_HIP(hipMalloc((void**)&h->Jrow, sizeof(int32_t) * nnzP));
+    PMOR_HIP(hipMemcpyAsync(h->Jcolptr, h->opts.pat_colptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
+    PMOR_HIP(hipMemcpyAsync(h->Jrow, h->opts.pat_row, sizeof(int32_t) * nnzP, hipMemcpyDeviceToDevice, st));
+    h->own_J = true;
+    // the CSR of P is the transpose of the J sets (read as the CSR of P^T); the
+    // transpose's map runs from P's CSR positions to J positions, the least-squares
+    // kernels scatter the other way, so it is inverted
+    int mx = 0;
+    int32_t* back = nullptr;
+    PMOR_TRY(transpose_pattern(n, nnzP, h->Jcolptr, h->Jrow, &h->Prowptr, &h->Pcol, &back, &mx, st));
+    PMOR_HIP(hipMalloc((void**)&h->Pslot, sizeof(int32_t) * nnzP));
+    hipLaunchKernelGGL(k_invert_map, dim3((unsigned)((nnzP + 255) / 256)), dim3(256), 0, st, back, nnzP, h->Pslot);
+    PMOR_HIP(hipGetLastError());
+    PMOR_HIP(hipStreamSynchronize(st));
+    PMOR_HIP(hipFree(back));
+    h->own_P = true;
+    h->nnzP = (int32_t)nnzP;
+  }
+  // shadows
+  int64_t* cnt = nullptr;
+  PMOR_HIP(hipMalloc((void**)&cnt, sizeof(int64_t) * (n + 1)));
+  hipLaunchKernelGGL(k_shadow<false>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
+                     cnt, nullptr, nullptr, dflag + 1, dflag + 2);
+  PMOR_HIP(hipGetLastError());
+  int hm[2] = {0, 0};
+  PMOR_HIP(hipMemcpyAsync(hm, dflag + 1, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  h->maxJ = hm[0];
+  h->maxI = hm[1];
+  if (h->maxJ > 64 || h->maxI > 512) {
+    (void)hipFree(cnt); (void)hipFree(dflag);
+    return fail(PMOR_EINVAL, "SPAI pattern too large: |J_j| <= 64 and |I_j| <= 512 are supported (got " +
+                                 std::to_string(h->maxJ) + ", " + std::to_string(h->maxI) + ")");
+  }
+  PMOR_TRY(scan_exclusive(cnt, n, st));
+  PMOR_HIP(hipMemcpyAsync(&h->nI, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  h->Icolptr = cnt;
+  PMOR_HIP(hipMalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1)));
+  hipLaunchKernelGGL(k_shadow<true>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
+                     nullptr, h->Icolptr, h->Irow, nullptr, nullptr);
+  PMOR_HIP(hipGetLastError());
+  // buckets
+  int* bc = nullptr;
+  PMOR_HIP(hipMalloc((void**)&bc, sizeof(int) * 16));
+  PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 16, st));
+  hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, bc);
+  PMOR_HIP(hipGetLastError());
+  int hb[8];
+  PMOR_HIP(hipMemcpyAsync(hb, bc, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  int off = 0, nonempty = 0;
+  for (int b = 0; b < 8; ++b) {
+    h->bucket_count[b] = hb[b];
+    h->bucket_off[b] = off;
+    off += hb[b];
+    nonempty += hb[b] > 0;
+  }
+  h->nbuckets = 8;
+  h->identity_order = (hb[0] == n);
+  if (!h->identity_order) {
+    PMOR_HIP(hipMemcpyAsync(bc + 8, h->bucket_off, sizeof(int) * 8, hipMemcpyHostToDevice, st));
+    PMOR_HIP(hipMalloc((void**)&h->bucket_cols, sizeof(int32_t) * (n > 0 ? n : 1)));
+    hipLaunchKernelGGL(k_bucket_fill, dim3(1), dim3(1024), 0, st, n, h->Jcolptr, h->Icolptr, bc + 8,
+                       h->bucket_cols);
+    PMOR_HIP(hipGetLastError());
+  }
+  PMOR_HIP(hipStreamSynchronize(st));
+  PMOR_HIP(hipFree(bc));
+  PMOR_HIP(hipFree(dflag));
+  (void)nonempty;
+  return PMOR_OK;
+}
+
+}  // namespace pmor

@@ -1,0 +1,497 @@
+// SPAI least squares and the cheap update.
+//
+// SPAI (paper, Section 2.2): min ||I - A P||_F splits into one least-squares
+// problem per column, min ||e_j - A p_j||_2 with p_j supported on J_j; only the
+// shadow rows I_j of A(:, J_j) take part, giving the dense |I_j| x |J_j| problem
+// A(I_j, J_j) p = e_j(I_j).  The first-approach update (Section 2.3, Table 1;
+// Section 2.4) solves the same kind of column problems,
+// min ||A(1) e_i - A(l) q_i||_2, with A(1)'s column as right-hand side.
+//
+// Mapping: one wavefront per column.  Lane l holds rows l, l+64, ... of the
+// gathered block (in registers for |J| <= 16, in LDS above), the Householder
+// QR runs with one cross-lane reduction per reflector (the column norm and all
+// the inner products the reflector needs are summed together), then back
+// substitution broadcasts one unknown at a time.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace pmor {
+
+template <typename T> struct Eps;
+template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
+template <> struct Eps<float> { static constexpr double v = 1.1920928955078125e-07; };
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float readlane_d(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// value of column c in CSR row [e, ee) starting the search at e (monotone cursor)
+__device__ __forceinline__ double row_lookup(const int32_t* colidx, const double* val, int& e, int ee, int c) {
+  while (e < ee && colidx[e] < c) ++e;
+  return (e < ee && colidx[e] == c) ? val[e] : 0.0;
+}
+
+struct LsArgs {
+  int ncols;
+  const int32_t* cols;  // bucket column list, or null (then column = col_off + index)
+  int col_off;
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const double* aval;      // matrix of the least-squares problems (A or A(l))
+  const double* rhs_aval;  // null: right-hand side e_j; else A(1) values on the same pattern
+  const int32_t* Jcolptr;
+  const int32_t* Jrow;
+  const int64_t* Icolptr;
+  const int32_t* Irow;
+  const int32_t* Pslot;
+  double* out;     // values in P's CSR order
+  double* rho;     // per-column residual norm
+  int* bad_col;    // smallest singular column (atomicMin)
+};
+
+// ---------------------------------------------------------------------------
+// register kernel: |J| <= JMAX (<= 16), |I| <= 64 R
+// ---------------------------------------------------------------------------
+template <typename T, int JMAX, int R>
+__global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int wid = xcd_swizzle(blockIdx.x, gridDim.x) * 4 + wv;
+  if (wid >= a.ncols) return;
+  const int j = a.cols ? a.cols[wid] : a.col_off + wid;
+  const int jb = a.Jcolptr[j];
+  const int nj = a.Jcolptr[j + 1] - jb;
+  const int64_t ib = a.Icolptr[j];
+  const int ni = (int)(a.Icolptr[j + 1] - ib);
+
+  T A_[R][JMAX];
+  T b_[R];
+  // gather A(I_j, J_j) and the right-hand side
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int li = lane + 64 * r;
+    const int row = (li < ni) ? a.Irow[ib + li] : -1;
+#pragma unroll
+    for (int t = 0; t < JMAX; ++t) A_[r][t] = T(0);
+    b_[r] = T(0);
+    if (row >= 0) {
+      int e = a.rowptr[row];
+      const int ee = a.rowptr[row + 1];
+#pragma unroll
+      for (int t = 0; t < JMAX; ++t)
+        if (t < nj) A_[r][t] = (T)row_lookup(a.colidx, a.aval, e, ee, a.Jrow[jb + t]);
+      if (a.rhs_aval) {
+        int e2 = a.rowptr[row];
+        b_[r] = (T)row_lookup(a.colidx, a.rhs_aval, e2, ee, j);
+      } else {
+        b_[r] = (row == j) ? T(1) : T(0);
+      }
+    }
+  }
+  T maxR = T(0), minDiag = T(3.0e38);
+  // Householder QR, one reflector per column k
+#pragma unroll
+  for (int k = 0; k < JMAX; ++k) {
+    if (k < nj) {
+      T s[JMAX + 1];
+#pragma unroll
+      for (int c = 0; c <= JMAX; ++c) s[c] = T(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int li = lane + 64 * r;
+        if (li >= k) {
+          const T x = A_[r][k];
+#pragma unroll
+          for (int c = k; c < JMAX; ++c) s[c] += x * A_[r][c];
+          s[JMAX] += x * b_[r];
+        }
+      }
+#pragma unroll
+      for (int c = k; c <= JMAX; ++c)
+        if (c < nj || c == JMAX) s[c] = wave_sum(s[c]);
+      // row k < JMAX <= 16 lives in slot 0 of lane k
+      constexpr int kr = 0;
+      const int kl = k;
+      const T alpha = readlane_d(A_[kr][k], kl);
+      const T sig = s[k];
+      T beta = alpha;
+      if (sig != alpha * alpha) {
+        const T nrm = sqrt(sig);
+        beta = (alpha >= T(0)) ? -nrm : nrm;
+        const T denom = beta * (beta - alpha);
+        T f[JMAX + 1];
+#pragma unroll
+        for (int c = k + 1; c < JMAX; ++c)
+          if (c < nj) f[c] = (s[c] - beta * readlane_d(A_[kr][c], kl)) / denom;
+        f[JMAX] = (s[JMAX] - beta * readlane_d(b_[kr], kl)) / denom;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int li = lane + 64 * r;
+          if (li >= k) {
+            const T v = (li == k) ? (alpha - beta) : A_[r][k];
+#pragma unroll
+            for (int c = k + 1; c < JMAX; ++c)
+              if (c < nj) A_[r][c] -= f[c] * v;
+            b_[r] -= f[JMAX] * v;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int li = lane + 64 * r;
+        if (li == k) A_[r][k] = beta;
+        else if (li > k) A_[r][k] = T(0);
+      }
+      const T ab = beta < T(0) ? -beta : beta;
+      minDiag = ab < minDiag ? ab : minDiag;
+    }
+  }
+  // max |R| over the triangle (rows < nj live in slot 0 since nj <= 64)
+  {
+    T mx = T(0);
+    if (lane < nj) {
+#pragma unroll
+      for (int c = 0; c < JMAX; ++c)
+        if (c >= lane && c < nj) {
+          T v = A_[0][c] < T(0) ? -A_[0][c] : A_[0][c];
+          mx = v > mx ? v : mx;
+        }
+    }
+    maxR = wave_max(mx);
+  }
+  // back substitution R p = (Q^T b)(0:nj)
+  T mine = T(0);
+  T p[JMAX];
+#pragma unroll
+  for (int i = JMAX - 1; i >= 0; --i) {
+    if (i < nj) {
+      T acc = b_[0];
+#pragma unroll
+      for (int c = i + 1; c < JMAX; ++c)
+        if (c < nj) acc -= A_[0][c] * p[c];
+      const T pi = acc / A_[0][i];
+      p[i] = readlane_d(pi, i);
+      if (lane == i) mine = pi;
+    } else {
+      p[i] = T(0);
+    }
+  }
+  // residual: the part of Q^T b below row nj
+  T rr = T(0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int li = lane + 64 * r;
+    if (li >= nj && li < ni) rr += b_[r] * b_[r];
+  }
+  rr = wave_sum(rr);
+  if (lane < nj) a.out[a.Pslot[jb + lane]] = (double)mine;
+  if (lane == 0) {
+    a.rho[j] = sqrt((double)rr);
+    const bool singular = (ni < nj) || !(minDiag > T(10.0 * ni * Eps<T>::v) * maxR);
+    if (singular) atomicMin(a.bad_col, j);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS kernel: |J| <= 64, |I| <= 512; one wavefront per workgroup
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
+  extern __shared__ unsigned char smem_raw[];
+  T* S = reinterpret_cast<T*>(smem_raw);  // column-major [JM + 1][ldI]: A_hat then rhs
+  __shared__ double sv[66];
+  const int lane = threadIdx.x;
+  const int wid = blockIdx.x;
+  if (wid >= a.ncols) return;
+  const int j = a.cols ? a.cols[wid] : a.col_off + wid;
+  const int jb = a.Jcolptr[j];
+  const int nj = a.Jcolptr[j + 1] - jb;
+  const int64_t ib = a.Icolptr[j];
+  const int ni = (int)(a.Icolptr[j + 1] - ib);
+  T* B = S + (size_t)JM * ldI;
+  for (int li = lane; li < ni; li += 64) {
+    const int row = a.Irow[ib + li];
+    int e = a.rowptr[row];
+    const int ee = a.rowptr[row + 1];
+    for (int t = 0; t < nj; ++t) S[(size_t)t * ldI + li] = (T)row_lookup(a.colidx, a.aval, e, ee, a.Jrow[jb + t]);
+    if (a.rhs_aval) {
+      int e2 = a.rowptr[row];
+      B[li] = (T)row_lookup(a.colidx, a.rhs_aval, e2, ee, j);
+    } else {
+      B[li] = (row == j) ? T(1) : T(0);
+    }
+  }
+  __syncthreads();
+  T minDiag = T(3.0e38);
+  for (int k = 0; k < nj; ++k) {
+    // one reduction per reflector: s[c] = x . a_c for c in [k, nj) and x . b
+    for (int c = k; c <= nj; ++c) {
+      const T* colc = (c < nj) ? S + (size_t)c * ldI : B;
+      T part = T(0);
+      for (int li = k + lane; li < ni; li += 64) part += S[(size_t)k * ldI + li] * colc[li];
+      part = wave_sum(part);
+      if (lane == 0) sv[c - k] = (double)part;
+    }
+    __syncthreads();
+    const T alpha = S[(size_t)k * ldI + k];
+    const T sig = (T)sv[0];
+    T beta = alpha;
+    if (sig != alpha * alpha) {
+      const T nrm = sqrt(sig);
+      beta = (alpha >= T(0)) ? -nrm : nrm;
+      const T denom = beta * (beta - alpha);
+      for (int c = k + 1; c <= nj; ++c) {
+        T* colc = (c < nj) ? S + (size_t)c * ldI : B;
+        const T f = ((T)sv[c - k] - beta * colc[k]) / denom;
+        __syncthreads();
+        for (int li = k + lane; li < ni; li += 64) {
+          const T v = (li == k) ? (alpha - beta) : S[(size_t)k * ldI + li];
+          colc[li] -= f * v;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (lane == 0) S[(size_t)k * ldI + k] = beta;
+    for (int li = k + 1 + lane; li < ni; li += 64) S[(size_t)k * ldI + li] = T(0);
+    __syncthreads();
+    const T ab = beta < T(0) ? -beta : beta;
+    minDiag = ab < minDiag ? ab : minDiag;
+  }
+  T mx = T(0);
+  for (int q = lane; q < nj * nj; q += 64) {
+    const int r = q % nj, c = q / nj;
+    if (r <= c) {
+      T v = S[(size_t)c * ldI + r];
+      v = v < T(0) ? -v : v;
+      mx = v > mx ? v : mx;
+    }
+  }
+  const T maxR = wave_max(mx);
+  // back substitution, column oriented: y in B[0:nj]
+  for (int i = nj - 1; i >= 0; --i) {
+    __syncthreads();
+    const T pi = B[i] / S[(size_t)i * ldI + i];
+    __syncthreads();
+    if (lane == 0) B[i] = pi;
+    for (int r = lane; r < i; r += 64) B[r] -= S[(size_t)i * ldI + r] * pi;
+  }
+  __syncthreads();
+  T rr = T(0);
+  for (int li = nj + lane; li < ni; li += 64) rr += B[li] * B[li];
+  rr = wave_sum(rr);
+  for (int t = lane; t < nj; t += 64) a.out[a.Pslot[jb + t]] = (double)B[t];
+  if (lane == 0) {
+    a.rho[j] = sqrt((double)rr);
+    const bool singular = (ni < nj) || !(minDiag > T(10.0 * ni * Eps<T>::v) * maxR);
+    if (singular) atomicMin(a.bad_col, j);
+  }
+}
+
+template <typename T>
+static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st) {
+  if (a.ncols == 0) return PMOR_OK;
+  const unsigned g4 = (unsigned)((a.ncols + 3) / 4);
+  switch (b) {
+    case 0: hipLaunchKernelGGL((k_spai_reg<T, 8, 1>), dim3(g4), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_spai_reg<T, 16, 1>), dim3(g4), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_spai_reg<T, 16, 2>), dim3(g4), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_spai_reg<T, 16, 4>), dim3(g4), dim3(256), 0, st, a); break;
+    case 4: {
+      const int ldI = ((maxI + 7) / 8) * 8;
+      const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI;
+      if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
+      PMOR_TRY(allow_lds((const void*)k_spai_lds<T>, shm));
+      hipLaunchKernelGGL((k_spai_lds<T>), dim3((unsigned)a.ncols), dim3(64), shm, st, a, ldI, maxJ);
+      break;
+    }
+    default: return fail(PMOR_EINVAL, "column outside the supported SPAI pattern sizes");
+  }
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+__global__ void k_sumsq_partials(const double* x, int64_t n, double* part) {
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * x[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ void k_sum_in_order(const double* part, int np, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < np; ++i) acc += part[i];
+    *out = acc;
+  }
+}
+
+// sum of squares of x[0..n), deterministic; result left in dev_out[0]
+static int sumsq(const double* x, int64_t n, double* dev_scratch, hipStream_t st) {
+  const int np = 256;
+  hipLaunchKernelGGL(k_sumsq_partials, dim3(np), dim3(256), 0, st, x, n, dev_scratch + 1);
+  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, st, dev_scratch + 1, np, dev_scratch);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val, int32_t* bad_col,
+                double* fro2) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  int* dbad = reinterpret_cast<int*>(h->red);
+  const int big = 0x7fffffff;
+  PMOR_TRY(set_device_int(dbad, big, st));
+  LsArgs a{};
+  a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval; a.rhs_aval = rhs_aval;
+  a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
+  a.Pslot = h->Pslot; a.out = out_val; a.rho = h->rho; a.bad_col = dbad;
+  for (int b = 0; b < 5; ++b) {
+    if (h->bucket_count[b] == 0) continue;
+    a.ncols = h->bucket_count[b];
+    if (h->identity_order) { a.cols = nullptr; a.col_off = 0; }
+    else { a.cols = h->bucket_cols + h->bucket_off[b]; a.col_off = 0; }
+    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st));
+    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st));
+  }
+  if (bad_col || fro2) {
+    double* dsum = h->red + 1;
+    PMOR_TRY(sumsq(h->rho, pb->n, dsum, st));
+    int hbad = big;
+    double hs = 0.0;
+    PMOR_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipMemcpyAsync(&hs, dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));
+    if (bad_col) *bad_col = (hbad == big) ? -1 : hbad;
+    if (fro2) *fro2 = hs;
+  }
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// U-diag update: q_i = <A(l) e_i, A(1) e_i> / ||A(l) e_i||^2 and P_l = diag(q) P_1
+// ---------------------------------------------------------------------------
+__global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscslot, const double* al,
+                              const double* a1, const int32_t* Prowptr, const double* P1, double* Pl, double* q,
+                              double* rho, int* bad_col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double num = 0.0, den = 0.0, n11 = 0.0;
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    const double x = al[s], y = a1[s];
+    num += x * y;
+    den += x * x;
+    n11 += y * y;
+  }
+  const double qi = num / den;
+  if (!(den > 0.0)) atomicMin(bad_col, i);
+  q[i] = qi;
+  // ||A(1) e_i - q_i A(l) e_i||^2 = n11 - 2 q num + q^2 den
+  const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
+  rho[i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+  for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qi * P1[e];
+}
+
+int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  int* dbad = reinterpret_cast<int*>(h->red);
+  const int big = 0x7fffffff;
+  PMOR_TRY(set_device_int(dbad, big, st));
+  hipLaunchKernelGGL(k_update_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
+                     pb->cscslot, aval_l, h->aval1, h->Prowptr, h->P1val, h->Pval, h->Qval, h->rho, dbad);
+  PMOR_HIP(hipGetLastError());
+  if (bad_col || fro2) {
+    double* dsum = h->red + 1;
+    PMOR_TRY(sumsq(h->rho, n, dsum, st));
+    double hs = 0.0;
+    int hbad = big;
+    PMOR_HIP(hipMemcpyAsync(&hs, dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));
+    if (fro2) *fro2 = hs;
+    if (bad_col) *bad_col = (hbad == big) ? -1 : hbad;
+  }
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// assembly: a = sum_r c_r T_r on the union pattern (streaming)
+// ---------------------------------------------------------------------------
+struct Coefs {
+  double c[PMOR_NROLES];
+  int nt;
+};
+
+__global__ void k_assemble(int64_t nnz, const double* __restrict__ tval, Coefs cf, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int t = 0; t < cf.nt; ++t) acc += cf.c[t] * tval[(int64_t)t * nnz + e];
+    out[e] = acc;
+  }
+}
+
+int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* out, hipStream_t st) {
+  Coefs cf{};
+  cf.nt = pb->nterms;
+  for (int r = 0; r < PMOR_NROLES; ++r)
+    if (pb->role_slot[r] >= 0) cf.c[pb->role_slot[r]] = coef[r];
+  const int64_t nnz = pb->nnz;
+  if (nnz == 0) return PMOR_OK;
+  unsigned g = (unsigned)std::min<int64_t>((nnz + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(256), 0, st, nnz, pb->tval, cf, out);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Frobenius norms of Table 2: mode 0: ||a - b||^2, mode 1: ||I - A||^2 (a = A values)
+// ---------------------------------------------------------------------------
+__global__ void k_fro_partials(int n, const int32_t* rowptr, const int32_t* col, const double* a, const double* b,
+                               int mode, double* part) {
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    bool diag = false;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      double d;
+      if (mode == 0) d = a[e] - b[e];
+      else if (col[e] == i) { d = 1.0 - a[e]; diag = true; }
+      else d = a[e];
+      acc += d * d;
+    }
+    if (mode == 1 && !diag) acc += 1.0;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+int fro_norm2(pmor_problem* pb, const double* a, const double* b, int64_t, int mode, double* out_host) {
+  hipStream_t st = pb->ctx->stream;
+  double* scratch = nullptr;
+  PMOR_HIP(hipMalloc((void**)&scratch, sizeof(double) * 260));
+  hipLaunchKernelGGL(k_fro_partials, dim3(256), dim3(256), 0, st, pb->n, pb->rowptr, pb->col, a, b, mode,
+                     scratch + 1);
+  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, st, scratch + 1, 256, scratch);
+  PMOR_HIP(hipGetLastError());
+  PMOR_HIP(hipMemcpyAsync(out_host, scratch, sizeof(double), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  PMOR_HIP(hipFree(scratch));
+  return PMOR_OK;
+}
+
+}  // namespace pmor

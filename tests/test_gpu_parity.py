@@ -1,0 +1,307 @@
+"""GPU library vs CPU oracle, stage by stage, on the same seeded inputs.
+
+Bars: patterns, index sets and slot maps bit-exact; assembly within a few ulp;
+FP64 SPAI / update columns within 1e-10 relative; block GMRES X within 1e-10
+relative of the oracle run for the same number of block steps with the GPU's
+preconditioner, and every column at relative residual <= 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import config0, tiny_random_job, appendix1, grid_laplacian
+from synth.gen import _power_law_sizes, _nearest_pattern, _weighted_mdk, Job
+from oracle.assemble import Assembled, term_values_on_pattern
+from oracle.spai import SpaiPattern, spai_build, solve_column
+from oracle.update import diag_factors, update_diag, update_pattern
+from oracle.gmres import block_gmres
+from oracle.sparse import to_scipy
+from tests._helpers import np_, ctx as make_ctx, col_rel_err, gpu_P_apply
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    return make_ctx()
+
+
+def _jobs():
+    return [tiny_random_job(37, 0.1, 1), tiny_random_job(64, 0.06, 2, k=3),
+            tiny_random_job(131, 0.03, 3, roles=("M0", "M1", "D0", "D1", "K0", "K1")),
+            config0(), appendix1(s=0.5)]
+
+
+@pytest.mark.parametrize("ji", range(5))
+def test_union_pattern_and_maps_bitexact(ctx, ji):
+    from paper_1809_06574_amd import Problem
+    job = _jobs()[ji]
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    rp, ci, mp = pb.pattern()
+    assert pb.nnz == asm.nnz
+    np.testing.assert_array_equal(np_(rp), asm.rowptr)
+    np.testing.assert_array_equal(np_(ci), asm.col)
+    for r, role in enumerate(("M0", "M1", "D0", "D1", "K0", "K1")):
+        want = asm.maps.get(role, np.full(asm.nnz, -1, dtype=np.int32))
+        np.testing.assert_array_equal(np_(mp[r]), want, err_msg=role)
+
+
+@pytest.mark.parametrize("ji", range(5))
+def test_assembly_values(ctx, ji):
+    from paper_1809_06574_amd import Problem
+    job = _jobs()[ji]
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    tv = term_values_on_pattern(job.terms, asm.maps, asm.nnz)
+    s = job.s
+    for p in job.p_list[:2]:
+        got = np_(pb.assemble(s, p))
+        want = asm.values(s, p)
+        # few-ulp agreement relative to the magnitudes of the summed terms
+        coef = {"M0": s * s, "M1": s * s * p, "D0": s, "D1": s * p, "K0": 1.0, "K1": p}
+        scale = sum(np.abs(coef[r] * tv[r]) for r in coef)
+        assert np.all(np.abs(got - want) <= 8 * np.finfo(float).eps * scale)
+
+
+@pytest.mark.parametrize("ji", range(5))
+def test_spai_sets_and_values_f64(ctx, ji):
+    from paper_1809_06574_amd import Problem
+    job = _jobs()[ji]
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col)
+    h = pb.spai_build(job.s, job.p_list[0], stats=True)
+    jc, jr, ic, ir = h.export_sets()
+    np.testing.assert_array_equal(np_(jc), pat.J_colptr)
+    np.testing.assert_array_equal(np_(jr), pat.J_row)
+    np.testing.assert_array_equal(np_(ic), pat.I_colptr)
+    np.testing.assert_array_equal(np_(ir), pat.I_row)
+    exp = h.export()
+    np.testing.assert_array_equal(np_(exp["rowptr"]), pat.P_rowptr)
+    np.testing.assert_array_equal(np_(exp["col"]), pat.P_col)
+    val = asm.values(job.s, job.p_list[0])
+    pv, rho = spai_build(job.n, asm.rowptr, asm.col, val, pat)
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exp["val"]), pv)
+    assert err <= 1e-10, err
+    np.testing.assert_allclose(np_(exp["rho"]), rho, rtol=1e-8, atol=1e-12)
+    assert h.last_stats["fro_resid"] == pytest.approx(np.sqrt(np.sum(rho ** 2)), rel=1e-10)
+
+
+@pytest.mark.parametrize("ji", [0, 3])
+def test_spai_values_f32(ctx, ji):
+    from paper_1809_06574_amd import Problem
+    job = _jobs()[ji]
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col)
+    h = pb.spai_build(job.s, job.p_list[0], precision="f32")
+    exp = h.export()
+    val = asm.values(job.s, job.p_list[0])
+    pv, rho = spai_build(job.n, asm.rowptr, asm.col, val, pat)
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exp["val"]), pv)
+    assert err <= 1e-4, err
+    assert np.all(np_(exp["rho"]) <= (1 + 1e-4) * rho + 1e-5)
+
+
+@pytest.mark.parametrize("ji", [0, 1, 3])
+def test_update_diag_and_pattern(ctx, ji):
+    from paper_1809_06574_amd import Problem
+    job = _jobs()[ji]
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col)
+    v1 = asm.values(job.s, job.p_list[0])
+    vl = asm.values(job.s, job.p_list[-1])
+    pv1, _ = spai_build(job.n, asm.rowptr, asm.col, v1, pat)
+    # U-diag
+    h = pb.spai_build(job.s, job.p_list[0], update="diag")
+    h.update(job.s, job.p_list[-1])
+    exp = h.export()
+    q = diag_factors(job.n, asm.rowptr, asm.col, v1, vl)
+    np.testing.assert_allclose(np_(exp["q"]), q, rtol=1e-13)
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exp["val"]),
+                      update_diag(job.n, pat.P_rowptr, pv1, q))
+    assert err <= 1e-10, err
+    # same point: q == 1 bit for bit
+    h.update(job.s, job.p_list[0])
+    assert np.all(np_(h.export()["q"]) == 1.0)
+    # U-pattern
+    hp = pb.spai_build(job.s, job.p_list[0], update="pattern")
+    st = hp.update(job.s, job.p_list[-1], stats=True)
+    exq = hp.export()
+    qv, rho = update_pattern(job.n, asm.rowptr, asm.col, v1, vl, pat)
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exq["q"]), qv)
+    assert err <= 1e-10, err
+    assert st["fro_resid"] == pytest.approx(np.sqrt(np.sum(rho ** 2)), rel=1e-9, abs=1e-14)
+
+
+def _solve_and_check(ctx, job, p_idx=0, k=None, m=30, update=None, precision="f64", tol=1e-8, rebuild=False):
+    from paper_1809_06574_amd import Problem
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    h = pb.spai_build(job.s, job.p_list[0], update=update or "diag", precision=precision)
+    if p_idx != 0:
+        if rebuild:
+            h.rebuild(job.s, job.p_list[p_idx])
+        else:
+            h.update(job.s, job.p_list[p_idx])
+    B = job.B if k is None else job.B[:, :k]
+    Bd = torch.as_tensor(np.ascontiguousarray(B), device="cuda")
+    X, st, rc = pb.block_solve(h, job.s, job.p_list[p_idx], Bd, m=m, tol=tol)
+    Xg = np_(X)
+    A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(job.s, job.p_list[p_idx]))
+    # the true residual of the GPU solution, computed on the CPU
+    bn = np.linalg.norm(B, axis=0)
+    rel = np.linalg.norm(B - A @ Xg, axis=0) / np.where(bn > 0, bn, 1.0)
+    assert np.all(rel <= tol * 1.0001), (rel, st)
+    # oracle with the GPU's preconditioner, same number of block steps per cycle
+    exp = h.export()
+    Pf = gpu_P_apply(exp, job.n, update or "diag", q_active=(update == "pattern" and p_idx != 0 and not rebuild))
+    Xo, info = block_gmres(A.__matmul__, Pf, B, m=m, tol=tol, fixed_steps=st["cycle_steps"])
+    d = np.linalg.norm(Xg - Xo) / max(np.linalg.norm(Xo), 1e-300)
+    assert d <= 1e-10, (d, st)
+    return st
+
+
+def test_block_solve_config0_all_points(ctx):
+    job = config0()
+    for l in range(len(job.p_list)):
+        st = _solve_and_check(ctx, job, p_idx=l)
+        assert st["cycles"] >= 1 and st["steps"] <= 30
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8])
+def test_block_solve_block_sizes(ctx, k):
+    job = tiny_random_job(700, 0.006, 50 + k, k=k)
+    _solve_and_check(ctx, job, p_idx=1, m=20)
+
+
+def test_block_solve_pattern_update(ctx):
+    job = config0()
+    _solve_and_check(ctx, job, p_idx=3, update="pattern")
+
+
+def test_block_solve_restarts(ctx):
+    job = config0()
+    st = _solve_and_check(ctx, job, p_idx=0, m=4)
+    assert st["cycles"] > 1
+
+
+def test_appendix1_one_step(ctx):
+    """Appendix I: SPAI on pattern(A) is the exact inverse, so one block step; the
+    U-diag update of it is not exact any more and takes a second step."""
+    job = appendix1(s=0.5)
+    st = _solve_and_check(ctx, job, p_idx=2, tol=1e-10, rebuild=True)
+    assert st["steps"] == 1
+    st = _solve_and_check(ctx, job, p_idx=2, tol=1e-10)
+    assert st["steps"] == 2
+
+
+def test_zero_and_nan_columns(ctx):
+    from paper_1809_06574_amd import Problem
+    from paper_1809_06574_amd import lib as L
+    job = config0(k=3)
+    pb = Problem(ctx, job.terms)
+    h = pb.spai_build(1.0, 0.1)
+    B = np.array(job.B)
+    B[:, 1] = 0.0
+    X, st, rc = pb.block_solve(h, 1.0, 0.1, torch.as_tensor(B, device="cuda"))
+    Xh = np_(X)
+    assert np.all(Xh[:, 1] == 0.0) and st["relres"][1] == 0.0
+    asm = Assembled(job)
+    A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(1.0, 0.1))
+    assert np.linalg.norm(B - A @ Xh) <= 1e-8 * np.linalg.norm(B)
+    X0, st0, rc0 = pb.block_solve(h, 1.0, 0.1, torch.zeros((job.n, 2), dtype=torch.float64, device="cuda"))
+    assert rc0 == 0 and not np_(X0).any()
+    B[5, 0] = np.nan
+    _, _, rc = pb.block_solve(h, 1.0, 0.1, torch.as_tensor(B, device="cuda"), raise_on_error=False)
+    assert rc == L.PMOR_ENAN
+
+
+def test_not_converged_reports(ctx):
+    from paper_1809_06574_amd import Problem
+    from paper_1809_06574_amd import lib as L
+    job = config0()
+    pb = Problem(ctx, job.terms)
+    h = pb.spai_build(1.0, 0.1)
+    X, st, rc = pb.block_solve(h, 1.0, 0.1, torch.as_tensor(job.B, device="cuda"), m=2, max_cycles=1,
+                               raise_on_error=False)
+    assert rc == L.PMOR_ENOTCONV and st["cycles"] == 1 and st["steps"] == 2
+    assert all(np.isfinite(st["relres"][:2])) and max(st["relres"][:2]) > 1e-8
+
+
+def test_singular_column_reported(ctx):
+    from paper_1809_06574_amd import Problem
+    from paper_1809_06574_amd import lib as L
+    job = tiny_random_job(30, 0.15, 9)
+    # zero column 7 in every term: A(:, 7) = 0 structurally-present zeros
+    terms = {}
+    for role, T in job.terms.items():
+        v = T.val.copy()
+        v[T.col == 7] = 0.0
+        terms[role] = (T.rowptr, T.col, v)
+    pb = Problem(ctx, terms)
+    with pytest.raises(L.PmorError) as e:
+        pb.spai_build(job.s, job.p_list[0])
+    assert e.value.code == L.PMOR_ESINGULAR
+
+
+def _explicit_pattern_job(dims, seed):
+    rng = np.random.default_rng([777, seed])
+    terms = _weighted_mdk(dims, rng, 1e-3)
+    K = terms["K0"]
+    sizes = _power_law_sizes(rng, K.n)
+    sizes[:: max(1, K.n // 7)] = 40  # make sure the large buckets are used
+    pat = _nearest_pattern(K, sizes)
+    B = rng.standard_normal((K.n, 8))
+    return Job(f"explicit_{seed}", K.n, terms, 2.0, np.array([0.3, 0.32]), B, pattern=pat)
+
+
+@pytest.mark.parametrize("dims,prec", [((17, 13, 1), "f64"), ((7, 6, 5), "f64"), ((9, 8, 7), "f32")])
+def test_explicit_power_law_pattern(ctx, dims, prec):
+    from paper_1809_06574_amd import Problem
+    job = _explicit_pattern_job(dims, dims[0])
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col, explicit=job.pattern)
+    h = pb.spai_build(job.s, job.p_list[0], pattern=job.pattern, precision=prec)
+    jc, jr, ic, ir = h.export_sets()
+    np.testing.assert_array_equal(np_(ic), pat.I_colptr)
+    np.testing.assert_array_equal(np_(ir), pat.I_row)
+    exp = h.export()
+    np.testing.assert_array_equal(np_(exp["rowptr"]), pat.P_rowptr)
+    np.testing.assert_array_equal(np_(exp["col"]), pat.P_col)
+    val = asm.values(job.s, job.p_list[0])
+    pv, rho = spai_build(job.n, asm.rowptr, asm.col, val, pat)
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exp["val"]), pv)
+    assert err <= (1e-10 if prec == "f64" else 1e-3), err
+    Bd = torch.as_tensor(job.B, device="cuda")
+    X, st, rc = pb.block_solve(h, job.s, job.p_list[0], Bd)
+    A = to_scipy(job.n, asm.rowptr, asm.col, val)
+    rel = np.linalg.norm(job.B - A @ np_(X), axis=0) / np.linalg.norm(job.B, axis=0)
+    assert np.all(rel <= 1e-8)
+
+
+def test_table2_norms(ctx):
+    from paper_1809_06574_amd import Problem
+    job = config0()
+    pb = Problem(ctx, job.terms)
+    for p in job.p_list:
+        a, b = pb.table2_norms(1.0, 0.1, 1.0, p)
+        assert a == pytest.approx(np.sqrt(1024 * (p + 4.04) ** 2 + 3968 * 1.01 ** 2), rel=1e-12)
+        assert b == pytest.approx(abs(p - 0.1) * 32.0, rel=1e-12, abs=1e-14)
+
+
+def test_sequence_solve_policies(ctx):
+    from paper_1809_06574_amd import Problem
+    job = config0()
+    pb = Problem(ctx, job.terms)
+    Bd = torch.as_tensor(job.B, device="cuda")
+    asm = Assembled(job)
+    for policy in ("update", "rebuild"):
+        X, stats = pb.sequence_solve(Bd, [1.0] * 4, job.p_list, policy=policy)
+        for l, p in enumerate(job.p_list):
+            A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(1.0, p))
+            rel = np.linalg.norm(job.B - A @ np_(X[l]), axis=0) / np.linalg.norm(job.B, axis=0)
+            assert np.all(rel <= 1e-8), (policy, l, rel)
