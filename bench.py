@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Parametric solves per second at relative residual 1e-8: SPAI update vs rebuild.
+
+A step is one job of the sequence of Section 2.3 (eq. general_sq) on the
+3-D 7-point workload (64^3 grid, n = 262144, k = 4 right-hand sides, s = 2,
+20 points p_j in [0.1, 1]): pattern setup of A(s,p) = s^2 M + s D(p) + K,
+SPAI of A(p_1) and a block GMRES(30) solve, then for each later point the
+cheap first-approach update P_j = diag(q) P_1 and a solve, every column to
+relative residual <= 1e-8.  Inputs (term matrices, B) are resident on the GPU
+before the timed region.  `value` = solves/s of that policy over the timed
+steps; the rebuild policy (a fresh SPAI per point) and the plain path (one
+right-hand side per solve, a rebuild per point) are timed beside it, with the
+per-solve p50/p99 latency of each.
+
+The dominant kernel is timed with HIP events on the library's stream during
+the timed region (library kernel timer), giving the roofline object; the CPU
+oracle is timed on a bounded sample of the same job (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def run_job(pb_factory, job, B, policy, k_split=False, lat=None, Xbuf=None):
+    """One job; returns the number of parametric solves.  lat collects per-point seconds."""
+    import torch
+    s = job.s
+    t0 = time.perf_counter()
+    pb = pb_factory()
+    h = pb.spai_build(s, job.p_list[0])
+    n_solves = 0
+    for l, p in enumerate(job.p_list):
+        if l > 0:
+            t0 = time.perf_counter()
+            if policy == "update":
+                h.update(s, p)
+            else:
+                h.rebuild(s, p)
+        if k_split:
+            for c in range(B.shape[1]):
+                pb.block_solve(h, s, p, B[:, c:c + 1].contiguous())
+        else:
+            pb.block_solve(h, s, p, B, X=Xbuf)
+        n_solves += 1
+        if lat is not None:
+            lat.append(time.perf_counter() - t0)
+    h.close()
+    pb.close()
+    return n_solves
+
+
+def timed(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(steps):
+        n += fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, n
+
+
+def cpu_baseline(job, gpu_P):
+    """The oracle on a bounded sample of the job, scaled to solves/s."""
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = None
+    from oracle.assemble import Assembled
+    from oracle.spai import SpaiPattern, spai_build
+    from oracle.update import diag_factors, update_diag
+    from oracle.sparse import to_scipy
+    from oracle.gmres import block_gmres
+    t = time.perf_counter()
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col)
+    t_setup = time.perf_counter() - t
+    v1 = asm.values(job.s, job.p_list[0])
+    cols = np.arange(0, job.n, max(1, job.n // 2048))
+    t = time.perf_counter()
+    spai_build(job.n, asm.rowptr, asm.col, v1, pat, columns=cols)
+    t_build = (time.perf_counter() - t) * job.n / len(cols)
+    vl = asm.values(job.s, job.p_list[-1])
+    t = time.perf_counter()
+    q = diag_factors(job.n, asm.rowptr, asm.col, v1, vl)
+    Pl = update_diag(job.n, pat.P_rowptr, gpu_P, q)
+    t_upd = time.perf_counter() - t
+    A = to_scipy(job.n, asm.rowptr, asm.col, vl)
+    P = to_scipy(job.n, pat.P_rowptr, pat.P_col, Pl)
+    t = time.perf_counter()
+    _, info = block_gmres(A.__matmul__, P.__matmul__, job.B, m=30, tol=1e-8)
+    t_solve = time.perf_counter() - t
+    npts = len(job.p_list)
+    t_job = t_setup + t_build + (npts - 1) * t_upd + npts * t_solve
+    return {"value": npts / t_job, "unit": "solves/s", "cores": blas_threads or os.cpu_count(), "kind": "oracle",
+            "sample": (f"one {job.name} job scaled from: full pattern setup {t_setup:.2f}s, SPAI of "
+                       f"{len(cols)} of {job.n} columns ({t_build:.1f}s extrapolated), one U-diag update "
+                       f"{t_upd:.2f}s, one block GMRES(30) solve {t_solve:.2f}s ({sum(info.steps)} steps, "
+                       f"library-built P_1 as input); {npts} points, update policy"),
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="config1", choices=["config1", "config0"])
+    ap.add_argument("--roofline-kernel", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
+              "shard; --gpus above 1 is not supported (DESIGN.md describes how the path would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth import config0, config1
+    from paper_1809_06574_amd import Context, Problem, lib as L
+
+    job = config1() if args.workload == "config1" else config0()
+    ctx = Context(0)
+    dev = ctx.device
+    terms = {r: (torch.as_tensor(T.rowptr, device=dev), torch.as_tensor(T.col, device=dev),
+                 torch.as_tensor(T.val, device=dev)) for r, T in job.terms.items()}
+    B = torch.as_tensor(job.B, device=dev)
+    Xbuf = torch.empty_like(B)
+    torch.cuda.synchronize()
+
+    def factory():
+        return Problem(ctx, terms)
+
+    # warmup (also builds every lazily created buffer)
+    for _ in range(max(args.warmup, 0)):
+        run_job(factory, job, B, "update", Xbuf=Xbuf)
+
+    # the dominant kernel: one untimed job per kernel class, the one with the most device time
+    kinds = dict(L.PROF_KERNELS)
+    per_kernel = {}
+    if args.roofline_kernel == "auto":
+        for name, kid in kinds.items():
+            L.check(L.pmor_prof_set(ctx.handle, kid), "prof_set")
+            run_job(factory, job, B, "update", Xbuf=Xbuf)
+            n_, ms_, by_ = _prof_read(L, ctx)
+            per_kernel[name] = {"launches": n_, "total_ms": ms_, "avg_us": 1e3 * ms_ / max(n_, 1),
+                                "GBps": by_ / max(ms_ * 1e-3, 1e-12) / 1e9}
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["total_ms"])
+    else:
+        dom = args.roofline_kernel
+
+    # timed region: update policy, dominant kernel timed live
+    L.check(L.pmor_prof_set(ctx.handle, kinds[dom]), "prof_set")
+    lat_upd = []
+    t_upd, n_upd = timed(lambda: run_job(factory, job, B, "update", lat=lat_upd, Xbuf=Xbuf), args.steps)
+    nl, ms, by = _prof_read(L, ctx)
+    L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+    achieved = by / (ms * 1e-3) / 1e9
+    value = n_upd / t_upd
+
+    out = {"metric": "parametric solves/s at 1e-8 residual (SPAI-update vs rebuild); p50/p99 latency",
+           "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t_upd / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{job.name}: 3-D 7-point grid {'x'.join(map(str, job.meta['dims']))}, "
+                                  f"n={job.n}, nnz(A)={_nnz(factory)}, k={job.k}, "
+                                  f"{len(job.p_list)} points p in [{job.p_list[0]:.2f},{job.p_list[-1]:.2f}], "
+                                  f"s={job.s}, block GMRES(30) tol 1e-8, SPAI on pattern(A), update=U-diag",
+                      "policy": "update", "solves_per_step": n_upd // args.steps},
+           "latency_ms": {"p50": 1e3 * _pct(lat_upd, 50), "p99": 1e3 * _pct(lat_upd, 99)},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": nl,
+                        "avg_launch_us": 1e3 * ms / max(nl, 1),
+                        "bytes_per_launch": by / max(nl, 1)},
+           }
+    if per_kernel:
+        out["kernels"] = per_kernel
+
+    if not args.no_arms:
+        lat_reb = []
+        t_reb, n_reb = timed(lambda: run_job(factory, job, B, "rebuild", lat=lat_reb, Xbuf=Xbuf), args.steps)
+        lat_plain = []
+        t_pl, n_pl = timed(lambda: run_job(factory, job, B, "rebuild", k_split=True, lat=lat_plain), 1)
+        out["arms"] = {
+            "update": {"solves_per_s": value, "p50_ms": 1e3 * _pct(lat_upd, 50), "p99_ms": 1e3 * _pct(lat_upd, 99)},
+            "rebuild": {"solves_per_s": n_reb / t_reb, "p50_ms": 1e3 * _pct(lat_reb, 50),
+                        "p99_ms": 1e3 * _pct(lat_reb, 99)},
+            "plain_nonblock_rebuild": {"solves_per_s": n_pl / t_pl, "p50_ms": 1e3 * _pct(lat_plain, 50),
+                                       "p99_ms": 1e3 * _pct(lat_plain, 99)},
+        }
+        out["update_vs_rebuild"] = value / (n_reb / t_reb)
+        out["update_vs_plain"] = value / (n_pl / t_pl)
+
+    if not args.no_cpu_baseline:
+        pb = factory()
+        h = pb.spai_build(job.s, job.p_list[0])
+        P1 = h.export()["val"].cpu().numpy()
+        h.close(); pb.close()
+        out["cpu_baseline"] = cpu_baseline(job, P1)
+    print(json.dumps(out), flush=True)
+
+
+def _prof_read(L, ctx):
+    import ctypes as C
+    n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+    L.check(L.pmor_prof_read(ctx.handle, C.byref(n), C.byref(ms), C.byref(by)), "prof_read")
+    return n.value, ms.value, by.value
+
+
+def _nnz(factory):
+    pb = factory()
+    nnz = pb.nnz
+    pb.close()
+    return nnz
+
+
+if __name__ == "__main__":
+    main()

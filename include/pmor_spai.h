@@ -216,6 +216,22 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
 int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx,
               double* Y, int64_t ldy, int32_t k, double alpha, double beta);
 
+/* ---- kernel timing (benchmarks) ---------------------------------------- */
+/* Time every launch of one kernel class with HIP events recorded on the
+ * context's stream around it, and add up the algorithmic bytes each launch must
+ * move (the formulas are the library's roofline model).  kernel_id 0 turns the
+ * timing off.  Launches of block steps that a converged cycle skipped are not
+ * counted.  pmor_prof_read synchronises the stream, returns the totals since the
+ * last read and resets them. */
+#define PMOR_PROF_SPMM_A 1        /* W = A Z in a block step: 12 nnz + 4(n+1) + 16 n kp */
+#define PMOR_PROF_CGS_UPD_DOT 2   /* Gram-Schmidt pass 2: W -= V H; V^T W: 8 n kp (nblk + 2) */
+#define PMOR_PROF_CGS_DOT 3       /* Gram-Schmidt pass 1: V^T W: 8 n kp (nblk + 1) */
+#define PMOR_PROF_SPAI_LS 4       /* SPAI least squares: 12 nnz + 4 n + 4 (sum|I_j| + nnzP) + 8 nnzP + 8 n */
+#define PMOR_PROF_SPMM_P 5        /* Z = P V_j in a block step: 12 nnzP + 4(n+1) + 16 n kp */
+#define PMOR_PROF_CGS_UPD_GRAM 6  /* Gram-Schmidt pass 3: W -= V H; W^T W: 8 n kp (nblk + 2) */
+int pmor_prof_set(pmor_ctx* ctx, int kernel_id);
+int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
+
 /* ---- errors ------------------------------------------------------------ */
 const char* pmor_strerror(int code);
 const char* pmor_last_error(void);

@@ -5,8 +5,19 @@ sequences A(s, p_j) X = B of parametric model order reduction (Singh & Ahuja,
 "Preconditioned Linear Solves for Parametric Model Order Reduction").
 
 ``lib`` is the raw C ABI (include/pmor_spai.h); ``Context``, ``Problem`` and
-``Spai`` wrap it with PyTorch tensors as device memory.  Importing this
-package fails when libpmorspai.so has not been built.
+``Spai`` wrap it with PyTorch tensors as device memory.  They are loaded on
+first use, which raises ImportError when libpmorspai.so has not been built
+(``python -m paper_1809_06574_amd.build``); there is no fallback path.
 """
-from . import lib  # noqa: F401  (raises ImportError when the HIP library is missing)
-from .api import Context, Problem, Spai  # noqa: F401
+import importlib
+
+_LAZY = {"lib": ("lib", None), "Context": ("api", "Context"), "Problem": ("api", "Problem"),
+         "Spai": ("api", "Spai")}
+
+
+def __getattr__(name):
+    if name not in _LAZY:
+        raise AttributeError(name)
+    mod, attr = _LAZY[name]
+    m = importlib.import_module(f"{__name__}.{mod}")
+    return m if attr is None else getattr(m, attr)

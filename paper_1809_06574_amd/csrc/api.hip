@@ -41,6 +41,49 @@ int set_device_int(int* p, int v, hipStream_t st) {
   return PMOR_OK;
 }
 
+int prof_start(pmor_ctx* c, int kid) {
+  Profiler& P = c->prof;
+  if (P.kernel == 0 || P.kernel != kid) return -1;
+  ProfRec r{};
+  for (hipEvent_t* e : {&r.a, &r.b}) {
+    if (!P.spare.empty()) { *e = P.spare.back(); P.spare.pop_back(); }
+    else if (hipEventCreate(e) != hipSuccess) return -1;
+  }
+  r.valid = true;
+  P.recs.push_back(r);
+  return (int)P.recs.size() - 1;
+}
+
+void prof_stop(pmor_ctx* c, int idx, double bytes, int tag) {
+  if (idx < 0) return;
+  ProfRec& r = c->prof.recs[idx];
+  r.bytes = bytes;
+  r.tag = tag;
+}
+
+void prof_drop_from(pmor_ctx* c, int first_idx, int tag_limit) {
+  auto& recs = c->prof.recs;
+  for (size_t i = (first_idx < 0 ? 0 : first_idx); i < recs.size(); ++i)
+    if (recs[i].tag >= tag_limit) recs[i].valid = false;
+}
+
+static void prof_collect(pmor_ctx* c) {
+  Profiler& P = c->prof;
+  for (ProfRec& r : P.recs) {
+    if (r.valid) {
+      float ms = 0.f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        P.total_ms += ms;
+        P.total_bytes += r.bytes;
+        P.launches += 1;
+      }
+    }
+    P.spare.push_back(r.a);
+    P.spare.push_back(r.b);
+  }
+  P.recs.clear();
+}
+
 int ensure_assembled(pmor_problem* pb, double s, double p) {
   if (pb->have_cur && pb->cur_s == s && pb->cur_p == p) return PMOR_OK;
   double c[PMOR_NROLES];
@@ -185,6 +228,9 @@ int pmor_ctx_create(pmor_ctx** out, int device, void* hip_stream) {
 void pmor_ctx_destroy(pmor_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  prof_collect(c);
+  for (hipEvent_t e : c->prof.spare) (void)hipEventDestroy(e);
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
   for (int i = 0; i < 64; ++i)
@@ -444,12 +490,38 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
   return PMOR_OK;
 }
 
+int pmor_prof_set(pmor_ctx* ctx, int kernel_id) {
+  if (!ctx) return fail(PMOR_EINVAL, "ctx is NULL");
+  if (kernel_id < 0 || kernel_id > PMOR_PROF_CGS_UPD_GRAM) return fail(PMOR_EINVAL, "unknown kernel id");
+  prof_collect(ctx);
+  ctx->prof.kernel = kernel_id;
+  ctx->prof.launches = 0;
+  ctx->prof.total_ms = 0.0;
+  ctx->prof.total_bytes = 0.0;
+  return PMOR_OK;
+}
+
+int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes) {
+  if (!ctx) return fail(PMOR_EINVAL, "ctx is NULL");
+  PMOR_HIP(hipStreamSynchronize(ctx->stream));
+  prof_collect(ctx);
+  if (launches) *launches = ctx->prof.launches;
+  if (total_ms) *total_ms = ctx->prof.total_ms;
+  if (total_bytes) *total_bytes = ctx->prof.total_bytes;
+  ctx->prof.launches = 0;
+  ctx->prof.total_ms = 0.0;
+  ctx->prof.total_bytes = 0.0;
+  return PMOR_OK;
+}
+
 int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t k,
               double alpha, double beta) {
   if (!pb || !aval || !X || !Y) return fail(PMOR_EINVAL, "NULL argument");
   if (k < 1 || k > PMOR_KMAX || ldx < k || ldy < k) return fail(PMOR_EINVAL, "bad k or leading dimension");
+  const int pr = prof_start(pb->ctx, PMOR_PROF_SPMM_A);
   PMOR_TRY(launch_spmm(pb->n, pb->rowptr, pb->col, aval, X, ldx, Y, ldy, k, k, alpha, beta, Y, ldy, nullptr,
-                       pb->ctx->stream));
+                       pb->ctx->stream, pb->ctx, pr, 3));
+  prof_stop(pb->ctx, pr, 12.0 * pb->nnz + 4.0 * (pb->n + 1) + 16.0 * pb->n * k + (beta != 0.0 ? 8.0 * pb->n * k : 0.0), 0);
   PMOR_HIP(hipStreamSynchronize(pb->ctx->stream));
   return PMOR_OK;
 }

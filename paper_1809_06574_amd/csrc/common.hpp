@@ -2,6 +2,7 @@
 // error plumbing.  Host code and kernels of every translation unit include it.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -76,10 +77,27 @@ struct Workspace {
   double* Y = nullptr;      // (m kp) x kp, column-major
   double* part = nullptr;   // reduction partials
   double* part2 = nullptr;  // second-level partials
+  double* partg = nullptr;  // per-workgroup partial Gram matrices (two sweeps)
   size_t part_len = 0;
   DevState* st = nullptr;
   DevState* st_host = nullptr;  // pinned mirror
   size_t bytes = 0;
+};
+
+// HIP-event timing of one chosen kernel class on the context's stream, with the
+// algorithmic bytes each timed launch has to move (for roofline reports).
+struct ProfRec {
+  hipEvent_t a, b;
+  double bytes;
+  int tag;       // block step of the launch (skipped steps are discarded)
+  bool valid;
+};
+struct Profiler {
+  int kernel = 0;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> spare;
+  int64_t launches = 0;
+  double total_ms = 0.0, total_bytes = 0.0;
 };
 
 }  // namespace pmor
@@ -89,6 +107,7 @@ struct pmor_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evs[64] = {};       // step events of the Krylov look-ahead
+  pmor::Profiler prof;
 };
 
 struct pmor_problem {
@@ -149,12 +168,31 @@ inline void role_coefs(double s, double p, double c[PMOR_NROLES]) {
 }
 
 int ensure_assembled(pmor_problem* pb, double s, double p);
+// kernel timing: start returns a record index (-1 when kernel class `kid` is not profiled)
+int prof_start(pmor_ctx* c, int kid);
+void prof_stop(pmor_ctx* c, int idx, double bytes, int tag);
+void prof_drop_from(pmor_ctx* c, int first_idx, int tag_limit);
 // let kernel `fn` use `bytes` of dynamic LDS (above the 64 KiB default)
 int allow_lds(const void* fn, size_t bytes);
 // device int set by a one-thread kernel (no pageable host source)
 int set_device_int(int* p, int v, hipStream_t st);
 int ensure_workspace(pmor_problem* pb, int kp, int m);
 void free_workspace(pmor::Workspace& ws);
+
+// Kernel launch that, for a profiled record idx >= 0, lets the dispatch itself
+// timestamp the kernel into the record's events (part bit 1: start, bit 2: stop).
+template <typename F, typename... Args>
+inline void plaunch(pmor_ctx* c, int idx, int part, F kernel, dim3 g, dim3 b, uint32_t shm, hipStream_t s,
+                    Args... args) {
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (c && idx >= 0) {
+    const ProfRec& r = c->prof.recs[idx];
+    if (part & 1) ea = r.a;
+    if (part & 2) eb = r.b;
+  }
+  if (ea || eb) hipExtLaunchKernelGGL(kernel, g, b, shm, s, ea, eb, 0, args...);
+  else hipLaunchKernelGGL(kernel, g, b, shm, s, args...);
+}
 
 // launchers implemented in the kernel translation units
 int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* out, hipStream_t st);
@@ -166,7 +204,8 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
 int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val,
                 const double* X, int64_t ldx, double* Y, int64_t ldy, int kp, int kact,
                 double alpha, double beta, const double* Bsrc, int64_t ldb,
-                const DevState* st, hipStream_t stream);
+                const DevState* st, hipStream_t stream, pmor_ctx* pc = nullptr, int pidx = -1,
+                int ppart = 3);
 int fro_norm2(pmor_problem* pb, const double* a, const double* b, int64_t len, int mode,
               double* out_host);
 int krylov_solve(pmor_problem* pb, const pmor_spai* h, const double* B, int64_t ldb, int k,

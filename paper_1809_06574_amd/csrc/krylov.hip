@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace pmor {
@@ -51,6 +52,8 @@ struct KArgs {
   double* Y;
   double* part;
   double* part2;
+  double* partg0;    // per-workgroup partial Gram matrices of the sweep before the first scaling
+  double* partg1;    // ... and of the first scaling sweep
   DevState* st;
   int* hflag;        // host-mapped {steps, done}
   int nbl_mode;      // 0: st->j + 1 blocks, 1: none (initial QR), 2: st->j blocks (V Y)
@@ -76,10 +79,19 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
   __shared__ double s[8][33];
   const int e = threadIdx.x & 7, r = threadIdx.x >> 3;
   const int t = blockIdx.x * 8 + e;
-  double acc = 0.0;
-  if (t < L)
-    for (int g = r; g < G; g += 32) acc += part[(size_t)g * L + t];
-  s[e][r] = acc;
+  // four interleaved running sums (g = r + 32 (4q + u)), combined in a fixed order
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (t < L) {
+    int g = r;
+    for (; g + 96 < G; g += 128) {
+      a0 += part[(size_t)g * L + t];
+      a1 += part[(size_t)(g + 32) * L + t];
+      a2 += part[(size_t)(g + 64) * L + t];
+      a3 += part[(size_t)(g + 96) * L + t];
+    }
+    for (; g < G; g += 32) a0 += part[(size_t)g * L + t];
+  }
+  s[e][r] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int o = 16; o >= 1; o >>= 1) {
     if (r < o) s[e][r] += s[e][r + o];
@@ -94,10 +106,18 @@ __device__ void block_reduce_partials(const double* __restrict__ part, int L, in
   int R = 1;
   while (R * 2 * L <= 256) R *= 2;  // lanes per entry
   const int e = threadIdx.x % L, r = threadIdx.x / L;
-  double acc = 0.0;
-  if (r < R)
-    for (int g = r; g < G; g += R) acc += part[(size_t)g * L + e];
-  if (threadIdx.x < R * L) s[r * L + e] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (r < R) {
+    int g = r;
+    for (; g + 3 * R < G; g += 4 * R) {
+      a0 += part[(size_t)g * L + e];
+      a1 += part[(size_t)(g + R) * L + e];
+      a2 += part[(size_t)(g + 2 * R) * L + e];
+      a3 += part[(size_t)(g + 3 * R) * L + e];
+    }
+    for (; g < G; g += R) a0 += part[(size_t)g * L + e];
+  }
+  if (threadIdx.x < R * L) s[r * L + e] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int o = R / 2; o >= 1; o >>= 1) {
     if (r < o) s[r * L + e] += s[(r + o) * L + e];
@@ -138,6 +158,82 @@ __device__ bool chol_upper(const double* Gm, int kp, int kact, double thr2, doub
     }
   }
   return ok;
+}
+
+// Prologue of the first scaling sweep, run by every workgroup: the Gram matrix
+// of W from the previous sweep's partials, its Cholesky factor R1 and R1^{-1}
+// (in LDS), the scale max_c ||W_c|| of the deficiency test.  Workgroup 0 also
+// stores R1, the scale and the H column block (both passes' coefficients).
+__device__ void scale1_prologue(const KArgs& a, int kp, int G, double* sR, double* sRinv, int* sok) {
+  DevState* st = a.st;
+  __shared__ double sG[KMAX * KMAX];
+  block_reduce_partials(a.partg0, kp * kp, G, sG);
+  const int nbl = nblocks_of(a);
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < st->kact; ++c)
+      mx = fmax(mx, a.nbl_mode == 0 ? a.Hc1[nbl * kp * kp + c] : sG[c * kp + c]);
+    const double ws = sqrt(mx);
+    const double thr = 1e-14 * ws;
+    const bool ok = chol_upper(sG, kp, st->kact, thr * thr, sR, sRinv);
+    *sok = ok ? 1 : 0;
+    if (blockIdx.x == 0) {
+      st->wscale = ws;
+      st->deficient = ok ? 0 : 1;
+      for (int t = 0; t < kp * kp; ++t) st->R1[t] = sR[t];
+    }
+  }
+  if (blockIdx.x == 0 && a.nbl_mode == 0) {
+    const int j = st->j;
+    for (int t = threadIdx.x; t < nbl * kp * kp; t += blockDim.x) {
+      const int b = t / kp, c = t % kp;
+      a.Hbar[b + (int64_t)(j * kp + c) * a.ldh] = a.Hc1[t] + a.Hc2[t];
+    }
+  }
+  __syncthreads();
+}
+
+// Prologue of the final scaling sweep, run by every workgroup: R2 from the Gram
+// matrix of W R1^{-1}, H_{j+1,j} = R2 R1 (S of the initial block) and the
+// deficiency test |(R2 R1)_cc| <= 1e-14 max ||W_c||.  Workgroup 0 stores the
+// block into the Hessenberg matrix (or G) and the verdict into the state.
+__device__ void scale2_prologue(const KArgs& a, int kp, int G, double* sR2inv, int* sdef) {
+  DevState* st = a.st;
+  __shared__ double sG[KMAX * KMAX], sR2[KMAX * KMAX], sHs[KMAX * KMAX];
+  block_reduce_partials(a.partg1, kp * kp, G, sG);
+  if (threadIdx.x == 0) {
+    const int kact = st->kact;
+    bool ok = chol_upper(sG, kp, kact, 0.0, sR2, sR2inv) && !st->deficient;
+    for (int r = 0; r < kp; ++r)
+      for (int c = 0; c < kp; ++c) {
+        double x = 0.0;
+        if (r < kact && c < kact)
+          for (int t = r; t <= c; ++t) x += sR2[r * kp + t] * st->R1[t * kp + c];
+        sHs[r * kp + c] = x;
+      }
+    const double thr = 1e-14 * st->wscale;
+    for (int c = 0; c < kact; ++c)
+      if (!(fabs(sHs[c * kp + c]) > thr)) ok = false;
+    if (!ok)
+      for (int t = 0; t < kp * kp; ++t) sHs[t] = 0.0;
+    *sdef = ok ? 0 : 1;
+    if (blockIdx.x == 0) {
+      if (a.nbl_mode == 0) {
+        const int j = st->j;
+        const int r0 = (j + 1) * kp;
+        for (int r = 0; r < kp; ++r)
+          for (int c = 0; c < kp; ++c) a.Hbar[(r0 + r) + (int64_t)(j * kp + c) * a.ldh] = sHs[r * kp + c];
+      } else {
+        for (int r = 0; r < kp; ++r)
+          for (int c = 0; c < kp; ++c) a.G[r + (int64_t)c * a.ldg] = sHs[r * kp + c];
+      }
+      if (!ok) {
+        st->deficient = 1;
+        if (a.nbl_mode != 0) { st->breakdown = 1; st->done = 1; }
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -353,6 +449,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
     }
   } else {
     if (w == 0) {
+      double* gp = a.partg0 + (int64_t)g * KP * KP;
 #pragma unroll
       for (int h = 0; h < NT; ++h)
 #pragma unroll
@@ -360,7 +457,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
           double x = accg[h][h2];
           x += __shfl_xor(x, 4, 64);
           x += __shfl_xor(x, 8, 64);
-          if (((lane >> 2) & 3) == 0) mypart[(4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
+          if (((lane >> 2) & 3) == 0) gp[(4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
         }
     }
   }
@@ -369,7 +466,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
 // W <- W * M (M = a kp x kp upper-triangular inverse kept in DevState),
 // optionally with its Gram matrix; writes either W in place or a V block.
 template <int KP, int NW, bool GRAM>
-__global__ __launch_bounds__(64 * NW) void k_scale_mfma(KArgs a, int which) {
+__global__ __launch_bounds__(64 * NW) void k_scale_mfma(KArgs a, int Gprev) {
   constexpr int NT = KP / 4;
   DevState* st = a.st;
   if (st->done) return;
@@ -377,14 +474,14 @@ __global__ __launch_bounds__(64 * NW) void k_scale_mfma(KArgs a, int which) {
   const int G = gridDim.x, g = blockIdx.x;
   const int c4 = lane & 3, rsub = lane >> 2;
   const int nch = (a.n + 15) >> 4;
-  const double* M = (which == 0) ? st->R1inv : st->R2inv;
+  __shared__ double sR[KMAX * KMAX], sM[KMAX * KMAX];
+  __shared__ int sflag;
+  if (GRAM) scale1_prologue(a, KP, Gprev, sR, sM, &sflag);
+  else scale2_prologue(a, KP, Gprev, sM, &sflag);
   double* out;
   if (GRAM) out = a.W;
   else out = a.V + (int64_t)(a.out_block == 1 ? 0 : st->j + 1) * a.vstride;
-  const bool zero = (!GRAM) && st->deficient;
-  __shared__ double sM[KP * KP];
-  for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) sM[t] = M[t];
-  __syncthreads();
+  const bool zero = (!GRAM) && sflag;
   double accg[GRAM ? NT : 1][NT];
 #pragma unroll
   for (int h = 0; h < (GRAM ? NT : 1); ++h)
@@ -448,7 +545,141 @@ __global__ __launch_bounds__(64 * NW) void k_scale_mfma(KArgs a, int which) {
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
     double tot = 0.0;
     for (int q = 0; q < NW; ++q) tot += sg[q][t];
-    a.part[(int64_t)g * L + t] = tot;
+    a.partg1[(int64_t)g * L + t] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kp = 4, rows split over the wavefronts: each wavefront streams its own 16-row
+// tiles against every V block (at most RS_B), so all of a tile's loads are in
+// flight together and no LDS exchange is needed inside the loop.
+// ---------------------------------------------------------------------------
+constexpr int RS_B = 32;
+
+// sum of a per-wavefront row of L values over the NW wavefronts, in order,
+// written as this workgroup's partial row
+template <int NW>
+__device__ __forceinline__ void rs_store_partials(double (*sred)[RS_B * 16 + 4], int L, double* dst) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += 64 * NW) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) tot += sred[q][t];
+    dst[t] = tot;
+  }
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
+  DevState* st = a.st;
+  if (st->done) return;
+  const int nbl = nblocks_of(a);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int nch = (a.n + 15) >> 4;
+  __shared__ double sred[NW][RS_B * 16 + 4];
+  double acc[RS_B];
+#pragma unroll
+  for (int i = 0; i < RS_B; ++i) acc[i] = 0.0;
+  double wn = 0.0;
+  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += G * NW) {
+    const int64_t off = ((int64_t)ch << 6) + lane;  // 16 rows x 4 columns = 64 doubles
+    const bool valid = off < (int64_t)a.n * 4;
+    const double wt = valid ? a.W[off] : 0.0;
+    wn += wt * wt;
+    double v[RS_B];
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? a.V[(int64_t)i * a.vstride + off] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i)
+      if (i < nbl) acc[i] = mfma4(v[i], wt, acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < RS_B; ++i) {
+    double x = acc[i];
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 8, 64);
+    if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
+  }
+  wn += __shfl_xor(wn, 4, 64);
+  wn += __shfl_xor(wn, 8, 64);
+  wn += __shfl_xor(wn, 16, 64);
+  wn += __shfl_xor(wn, 32, 64);
+  if (lane < 4) sred[w][nbl * 16 + lane] = wn;
+  const int L = nbl * 16 + 4;
+  rs_store_partials<NW>(sred, L, a.part + (int64_t)g * L);
+}
+
+// Lane l of a 16 x 4 tile holds (row 16c + (l >> 2), column l & 3).  Used as the
+// A operand of v_mfma_f64_4x4x4f64 a tile contracts over the rows; the update
+// W - V H needs the rows as the M index instead, i.e. the 4 x 4 transpose inside
+// each group of 16 lanes: lane l takes the value of lane ((l & 3) << 4) | (l & 12) | (l >> 4).
+__device__ __forceinline__ double tile_transpose(double x, int lane) {
+  const int src = ((lane & 3) << 4) | (lane & 12) | (lane >> 4);
+  return __shfl(x, src, 64);
+}
+
+// W <- W - hsign V Hsrc for all blocks, then (DOT) V^T W or (GRAM) W^T W.  Both
+// the update and the inner products run on the FP64 MFMA: for the update the
+// transposed V tile is the A operand, -hsign H the B operand and W the
+// accumulator (D[i][j] at lane 16i + 4b + j is the tile's own layout).
+template <int NW, bool DOT, bool GRAM>
+__global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
+  DevState* st = a.st;
+  if (st->done && !a.ignore_done) return;
+  const int nbl = nblocks_of(a);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int nch = (a.n + 15) >> 4;
+  __shared__ double sred[(DOT || GRAM) ? NW : 1][RS_B * 16 + 4];
+  // B operand of block i: B[k][j] = -hsign H[4i + k][j], k = lane >> 4, j = lane & 3
+  __shared__ double sH[RS_B * 16];
+  for (int t = threadIdx.x; t < nbl * 16; t += blockDim.x) sH[t] = -a.hsign * a.Hsrc[t];
+  __syncthreads();
+  const double* hb = sH + (lane >> 4) * 4 + (lane & 3);
+  double acc[DOT ? RS_B : 1];
+#pragma unroll
+  for (int i = 0; i < (DOT ? RS_B : 1); ++i) acc[i] = 0.0;
+  double accg = 0.0;
+  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += G * NW) {
+    const int64_t off = ((int64_t)ch << 6) + lane;
+    const bool valid = off < (int64_t)a.n * 4;
+    const double wt = (valid && !a.zero_init) ? a.W[off] : 0.0;
+    double v[RS_B];
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? a.V[(int64_t)i * a.vstride + off] : 0.0;
+    double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
+#pragma unroll
+    for (int i = 0; i < RS_B; i += 2) {
+      if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
+      if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
+    }
+    const double wnew = u0 + u1;
+    if (valid && (nbl > 0 || a.zero_init)) a.W[off] = wnew;
+    if (DOT) {
+#pragma unroll
+      for (int i = 0; i < RS_B; ++i)
+        if (i < nbl) acc[i] = mfma4(v[i], wnew, acc[i]);
+    }
+    if (GRAM) accg = mfma4(wnew, wnew, accg);
+  }
+  if (DOT) {
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) {
+      double x = acc[i];
+      x += __shfl_xor(x, 4, 64);
+      x += __shfl_xor(x, 8, 64);
+      if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
+    }
+    const int L = nbl * 16;
+    rs_store_partials<NW>(sred, L, a.part + (int64_t)g * L);
+  }
+  if (GRAM) {
+    double x = accg;
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 8, 64);
+    if (((lane >> 2) & 3) == 0) sred[w][(lane >> 4) * 4 + (lane & 3)] = x;
+    rs_store_partials<NW>(sred, 16, a.partg0 + (int64_t)g * 16);
   }
 }
 
@@ -620,29 +851,33 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
     }
   } else {
     if (w == 0) {
+      double* gp = a.partg0 + (int64_t)g * KP * KP;
 #pragma unroll
       for (int x = 0; x < KP; ++x)
 #pragma unroll
         for (int y = 0; y < KP; ++y) {
           const double s = wave_sum(accg[x][y]);
-          if (lane == 0) mypart[x * KP + y] = s;
+          if (lane == 0) gp[x * KP + y] = s;
         }
     }
   }
 }
 
 template <int KP, int NW, bool GRAM>
-__global__ __launch_bounds__(64 * NW) void k_scale_row(KArgs a, int which) {
+__global__ __launch_bounds__(64 * NW) void k_scale_row(KArgs a, int Gprev) {
   DevState* st = a.st;
   if (st->done) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int G = gridDim.x, g = blockIdx.x;
   const int nch = (a.n + 63) >> 6;
-  const double* M = (which == 0) ? st->R1inv : st->R2inv;
+  __shared__ double sR[KMAX * KMAX], M[KMAX * KMAX];
+  __shared__ int sflag;
+  if (GRAM) scale1_prologue(a, KP, Gprev, sR, M, &sflag);
+  else scale2_prologue(a, KP, Gprev, M, &sflag);
   double* out;
   if (GRAM) out = a.W;
   else out = a.V + (int64_t)(a.out_block == 1 ? 0 : st->j + 1) * a.vstride;
-  const bool zero = (!GRAM) && st->deficient;
+  const bool zero = (!GRAM) && sflag;
   double Mr[KP][KP];
 #pragma unroll
   for (int x = 0; x < KP; ++x)
@@ -692,80 +927,13 @@ __global__ __launch_bounds__(64 * NW) void k_scale_row(KArgs a, int which) {
   for (int t = threadIdx.x; t < L; t += blockDim.x) {
     double tot = 0.0;
     for (int q = 0; q < NW; ++q) tot += sg[q][t];
-    a.part[(int64_t)g * L + t] = tot;
+    a.partg1[(int64_t)g * L + t] = tot;
   }
 }
 
 // ---------------------------------------------------------------------------
 // single-workgroup kernels: Cholesky steps, Hessenberg least squares, Y solve
 // ---------------------------------------------------------------------------
-// After the Gram matrix of pass 3 (or of the initial block): Cholesky R1; in an
-// Arnoldi step also store the H column block (both passes' coefficients).
-__global__ __launch_bounds__(256) void k_after_gram1(KArgs a, int kp, int G) {
-  DevState* st = a.st;
-  if (st->done) return;
-  const int nbl = nblocks_of(a);
-  const int j = st->j;
-  block_reduce_partials(a.part, kp * kp, G, a.Gram);
-  if (a.nbl_mode == 0) {
-    for (int t = threadIdx.x; t < nbl * kp * kp; t += blockDim.x) {
-      const int b = t / kp, c = t % kp;
-      a.Hbar[b + (int64_t)(j * kp + c) * a.ldh] = a.Hc1[t] + a.Hc2[t];
-    }
-    if (threadIdx.x == 0) {
-      double mx = 0.0;
-      for (int c = 0; c < st->kact; ++c) mx = fmax(mx, a.Hc1[nbl * kp * kp + c]);
-      st->wscale = sqrt(mx);
-    }
-  } else if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int c = 0; c < st->kact; ++c) mx = fmax(mx, a.Gram[c * kp + c]);
-    st->wscale = sqrt(mx);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double thr = 1e-14 * st->wscale;
-    const bool ok = chol_upper(a.Gram, kp, st->kact, thr * thr, st->R1, st->R1inv);
-    st->deficient = ok ? 0 : 1;
-  }
-}
-
-// After the Gram matrix of the scaled block: Cholesky R2, H_{j+1,j} = R2 R1 (or S
-// of the initial block), deficiency test |(R2 R1)_cc| <= 1e-14 max ||W_c||.
-__global__ __launch_bounds__(256) void k_after_gram2(KArgs a, int kp, int G) {
-  DevState* st = a.st;
-  if (st->done) return;
-  block_reduce_partials(a.part, kp * kp, G, a.Gram);
-  if (threadIdx.x != 0) return;
-  const int kact = st->kact;
-  bool ok = chol_upper(a.Gram, kp, kact, 0.0, st->R2, st->R2inv) && !st->deficient;
-  double Hs[KMAX * KMAX];
-  for (int r = 0; r < kp; ++r)
-    for (int c = 0; c < kp; ++c) {
-      double x = 0.0;
-      if (r < kact && c < kact)
-        for (int t = r; t <= c; ++t) x += st->R2[r * kp + t] * st->R1[t * kp + c];
-      Hs[r * kp + c] = x;
-    }
-  const double thr = 1e-14 * st->wscale;
-  for (int c = 0; c < kact; ++c)
-    if (!(fabs(Hs[c * kp + c]) > thr)) ok = false;
-  if (!ok) {
-    for (int t = 0; t < kp * kp; ++t) Hs[t] = 0.0;
-    st->deficient = 1;
-  }
-  if (a.nbl_mode == 0) {
-    const int j = st->j;
-    const int r0 = (j + 1) * kp;
-    for (int r = 0; r < kp; ++r)
-      for (int c = 0; c < kp; ++c) a.Hbar[(r0 + r) + (int64_t)(j * kp + c) * a.ldh] = Hs[r * kp + c];
-  } else {
-    for (int r = 0; r < kp; ++r)
-      for (int c = 0; c < kp; ++c) a.G[r + (int64_t)c * a.ldg] = Hs[r * kp + c];
-    if (!ok) { st->breakdown = 1; st->done = 1; }
-  }
-}
-
 // Householder update of the QR factorisation of the block Hessenberg matrix
 // for the new block column j, the transformed right-hand side G, and the
 // least-squares residual estimate of every column.  One wavefront.
@@ -792,20 +960,36 @@ __global__ __launch_bounds__(64) void k_hess(KArgs a) {
     gw[c * 2 * KP + r] = a.G[(q0 + r) + (int64_t)c * a.ldg];
   }
   __syncthreads();
-  // earlier reflectors, in order, on the new columns
+  // earlier reflectors, in order, on the new columns.  Reflector q touches rows
+  // q..q+KP; lane t keeps those KP+1 rows of its column in registers, row r at
+  // slot r mod (KP+1), retiring row q to LDS and taking in row q+KP+1 each time.
   if (lane < KP) {
     double* x = col + (size_t)lane * ldh;
-    for (int q = 0; q < q0; ++q) {
-      const double* v = rf + (size_t)q * RL;
-      const double tau = v[0];
-      if (tau == 0.0) continue;
-      double d = x[q];
+    double w[KP + 1];
 #pragma unroll
-      for (int r = 1; r <= KP; ++r) d = fma(v[r], x[q + r], d);
-      d *= tau;
-      x[q] -= d;
+    for (int i = 0; i <= KP; ++i) w[i] = x[i];
+    for (int base = 0; base < q0; base += KP + 1) {
 #pragma unroll
-      for (int r = 1; r <= KP; ++r) x[q + r] = fma(-d, v[r], x[q + r]);
+      for (int r = 0; r <= KP; ++r) {
+        const int q = base + r;
+        if (q < q0) {
+          const double* v = rf + (size_t)q * RL;
+          double d = w[r];
+#pragma unroll
+          for (int i = 1; i <= KP; ++i) d = fma(v[i], w[(r + i) % (KP + 1)], d);
+          d *= v[0];
+          w[r] -= d;
+#pragma unroll
+          for (int i = 1; i <= KP; ++i) w[(r + i) % (KP + 1)] = fma(-d, v[i], w[(r + i) % (KP + 1)]);
+          x[q] = w[r];
+          w[r] = (q + KP + 1 < nr) ? x[q + KP + 1] : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int pidx = 0; pidx <= KP; ++pidx) {
+      const int row = q0 + (((pidx - q0) % (KP + 1)) + (KP + 1)) % (KP + 1);
+      if (row < nr) x[row] = w[pidx];
     }
   }
   __syncthreads();
@@ -956,9 +1140,9 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__
                                               const int32_t* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ X, int64_t ldx, double* Y, int64_t ldy,
                                               double alpha, double beta, const double* Bsrc, int64_t ldb,
-                                              const DevState* st) {
+                                              const DevState* st, int vec) {
   if (st && st->done) return;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t row = gid / LPR;
   const int sub = (int)(gid % LPR);
   const bool valid = row < n;
@@ -967,12 +1151,36 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__
   for (int t = 0; t < KP; ++t) acc[t] = 0.0;
   if (valid) {
     const int e1 = rowptr[row + 1];
-    for (int e = rowptr[row] + sub; e < e1; e += LPR) {
-      const int c = col[e];
-      const double v = val[e];
-      const double* xr = X + (int64_t)c * ldx;
+    if constexpr (KP % 2 == 0) {
+      if (vec) {
+        for (int e = rowptr[row] + sub; e < e1; e += LPR) {
+          const int c = col[e];
+          const double v = val[e];
+          const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * ldx);
 #pragma unroll
-      for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+          for (int t = 0; t < KP / 2; ++t) {
+            const double2 x = xr[t];
+            acc[2 * t] = fma(v, x.x, acc[2 * t]);
+            acc[2 * t + 1] = fma(v, x.y, acc[2 * t + 1]);
+          }
+        }
+      } else {
+        for (int e = rowptr[row] + sub; e < e1; e += LPR) {
+          const int c = col[e];
+          const double v = val[e];
+          const double* xr = X + (int64_t)c * ldx;
+#pragma unroll
+          for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+        }
+      }
+    } else {
+      for (int e = rowptr[row] + sub; e < e1; e += LPR) {
+        const int c = col[e];
+        const double v = val[e];
+        const double* xr = X + (int64_t)c * ldx;
+#pragma unroll
+        for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+      }
     }
   }
 #pragma unroll
@@ -990,18 +1198,28 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__
   }
 }
 
-int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X, int64_t ldx,
-                double* Y, int64_t ldy, int kp, int kact, double alpha, double beta, const double* Bsrc,
-                int64_t ldb, const DevState* st, hipStream_t stream) {
-  (void)kact;
-  if (n == 0) return PMOR_OK;
-  constexpr int LPR = 4;
+// lanes per row of the CSR SpMM (1, 2, 4 or 8; 2 measured best for 7-point rows
+// at k = 1..8); PMOR_SPMM_LPR overrides the default
+static int spmm_lanes_per_row() {
+  static int lpr = [] {
+    const char* e = getenv("PMOR_SPMM_LPR");
+    const int v = e ? atoi(e) : 2;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 2;
+  }();
+  return lpr;
+}
+
+template <int LPR>
+static int launch_spmm_lpr(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X,
+                           int64_t ldx, double* Y, int64_t ldy, int kp, double alpha, double beta, const double* Bsrc,
+                           int64_t ldb, const DevState* st, hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
   const int64_t threads = (int64_t)n * LPR;
   const unsigned grid = (unsigned)((threads + 255) / 256);
+  const int vec = ((ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) ? 1 : 0;
   switch (kp) {
 #define SPMM_CASE(K) \
-    case K: hipLaunchKernelGGL((k_spmm<K, LPR>), dim3(grid), dim3(256), 0, stream, n, rowptr, col, val, X, ldx, Y, \
-                               ldy, alpha, beta, Bsrc, ldb, st); break;
+    case K: plaunch(pc, pidx, ppart, k_spmm<K, LPR>, dim3(grid), dim3(256), 0, stream, n, rowptr, col, val, X, ldx, \
+                    Y, ldy, alpha, beta, Bsrc, ldb, st, vec); break;
     SPMM_CASE(1) SPMM_CASE(2) SPMM_CASE(3) SPMM_CASE(4) SPMM_CASE(5) SPMM_CASE(6) SPMM_CASE(7) SPMM_CASE(8)
     SPMM_CASE(9) SPMM_CASE(10) SPMM_CASE(11) SPMM_CASE(12) SPMM_CASE(13) SPMM_CASE(14) SPMM_CASE(15) SPMM_CASE(16)
 #undef SPMM_CASE
@@ -1009,6 +1227,25 @@ int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* 
   }
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
+}
+
+int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X, int64_t ldx,
+                double* Y, int64_t ldy, int kp, int kact, double alpha, double beta, const double* Bsrc,
+                int64_t ldb, const DevState* st, hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
+  (void)kact;
+  if (n == 0) return PMOR_OK;
+  switch (spmm_lanes_per_row()) {
+    case 1: return launch_spmm_lpr<1>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+                                      pidx, ppart);
+    case 2: return launch_spmm_lpr<2>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+                                      pidx, ppart);
+    case 8: return launch_spmm_lpr<8>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+                                      pidx, ppart);
+    case 4: return launch_spmm_lpr<4>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+                                      pidx, ppart);
+    default: return launch_spmm_lpr<2>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+                                       pidx, ppart);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,15 +1311,16 @@ static int pad_kp(int k) {
   return 16;
 }
 
-static int row_grid(int n, int rows_per_tile) {
+static int row_grid(int n, int rows_per_tile, int gmax = 512) {
   const int tiles = (n + rows_per_tile - 1) / rows_per_tile;
-  int g = std::min(tiles, 512);
+  int g = std::min(tiles, gmax);
   if (g >= 8) g &= ~7;  // a multiple of 8 keeps the XCD swizzle exact
   return std::max(g, 1);
 }
 
 void free_workspace(Workspace& ws) {
-  double* bufs[] = {ws.V, ws.W, ws.Z, ws.T, ws.Bc, ws.Xc, ws.Hbar, ws.Hcol, ws.G, ws.refl, ws.Y, ws.part, ws.part2};
+  double* bufs[] = {ws.V, ws.W, ws.Z, ws.T, ws.Bc, ws.Xc, ws.Hbar, ws.Hcol, ws.G, ws.refl, ws.Y, ws.part, ws.part2,
+                    ws.partg};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (ws.st) (void)hipFree(ws.st);
@@ -1120,6 +1358,7 @@ int ensure_workspace(pmor_problem* pb, int kp, int m) {
   ws.part_len = (size_t)L;
   PMOR_TRY(alloc(&ws.part, (int64_t)MAX_RED_WG * L));
   PMOR_TRY(alloc(&ws.part2, (int64_t)(MAX_RED_WG / RED_GROUP + 1) * L));
+  PMOR_TRY(alloc(&ws.partg, (int64_t)2 * MAX_RED_WG * KMAX * KMAX));
   PMOR_HIP(hipMalloc((void**)&ws.st, sizeof(DevState)));
   PMOR_HIP(hipMemset(ws.st, 0, sizeof(DevState)));
   PMOR_HIP(hipHostMalloc((void**)&ws.st_host, sizeof(DevState) + 64, hipHostMallocMapped));
@@ -1141,27 +1380,32 @@ struct Launcher {
 
   // W <- (P) V_j etc. are done by spmm; these wrap the block kernels
   template <int KP, int NW, int BPW>
-  int dot() {
-    if (KP >= 4) hipLaunchKernelGGL((k_dot_mfma<(KP >= 4 ? KP : 4), NW, BPW>), dim3(G), dim3(64 * NW), 0, s, a);
-    else hipLaunchKernelGGL((k_dot_row<(KP < 4 ? KP : 1), NW, BPW>), dim3(G), dim3(64 * NW), 0, s, a);
+  int dot(int pidx = -1) {
+    pmor_ctx* c = pb->ctx;
+    if constexpr (KP == 4) plaunch(c, pidx, 3, k_dot4<NW>, dim3(G), dim3(64 * NW), 0, s, a);
+    else if constexpr (KP >= 4) plaunch(c, pidx, 3, k_dot_mfma<(KP >= 4 ? KP : 4), NW, BPW>, dim3(G), dim3(64 * NW), 0, s, a);
+    else plaunch(c, pidx, 3, k_dot_row<(KP < 4 ? KP : 1), NW, BPW>, dim3(G), dim3(64 * NW), 0, s, a);
     PMOR_HIP(hipGetLastError());
     return PMOR_OK;
   }
   template <int KP, int NW, int BPW, bool DOT, bool GRAM>
-  int upd(int nbl_max) {
+  int upd(int nbl_max, int pidx = -1) {
     const int per = (KP >= 4) ? (KP / 4) : KP;
     const size_t shm = sizeof(double) * ((size_t)nbl_max * KP * KP + (size_t)2 * NW * 64 * per);
-    if (KP >= 4)
-      hipLaunchKernelGGL((k_upd_mfma<(KP >= 4 ? KP : 4), NW, BPW, DOT, GRAM>), dim3(G), dim3(64 * NW), shm, s, a);
+    pmor_ctx* c = pb->ctx;
+    if constexpr (KP == 4)
+      plaunch(c, pidx, 3, k_upd4<NW, DOT, GRAM>, dim3(G), dim3(64 * NW), 0, s, a);
+    else if constexpr (KP >= 4)
+      plaunch(c, pidx, 3, k_upd_mfma<(KP >= 4 ? KP : 4), NW, BPW, DOT, GRAM>, dim3(G), dim3(64 * NW), (uint32_t)shm, s, a);
     else
-      hipLaunchKernelGGL((k_upd_row<(KP < 4 ? KP : 1), NW, BPW, DOT, GRAM>), dim3(G), dim3(64 * NW), shm, s, a);
+      plaunch(c, pidx, 3, k_upd_row<(KP < 4 ? KP : 1), NW, BPW, DOT, GRAM>, dim3(G), dim3(64 * NW), (uint32_t)shm, s, a);
     PMOR_HIP(hipGetLastError());
     return PMOR_OK;
   }
   template <int KP, int NW, bool GRAM>
-  int scale(int which) {
-    if (KP >= 4) hipLaunchKernelGGL((k_scale_mfma<(KP >= 4 ? KP : 4), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, which);
-    else hipLaunchKernelGGL((k_scale_row<(KP < 4 ? KP : 1), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, which);
+  int scale() {
+    if constexpr (KP >= 4) hipLaunchKernelGGL((k_scale_mfma<(KP >= 4 ? KP : 4), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, G);
+    else hipLaunchKernelGGL((k_scale_row<(KP < 4 ? KP : 1), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, G);
     PMOR_HIP(hipGetLastError());
     return PMOR_OK;
   }
@@ -1169,13 +1413,16 @@ struct Launcher {
 
 // preconditioner application Z = P_l X (P_l = Q P_1 when the pattern update is active)
 int apply_P(pmor_problem* pb, const pmor_spai* h, const double* X, double* Z, double* tmp, int kp, int kact,
-            const DevState* st, double beta, hipStream_t s) {
+            const DevState* st, double beta, hipStream_t s, int pidx = -1) {
   const int n = pb->n;
   if (h->q_active) {
-    PMOR_TRY(launch_spmm(n, h->Prowptr, h->Pcol, h->P1val, X, kp, tmp, kp, kp, kact, 1.0, 0.0, nullptr, 0, st, s));
-    return launch_spmm(n, h->Prowptr, h->Pcol, h->Qval, tmp, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s);
+    PMOR_TRY(launch_spmm(n, h->Prowptr, h->Pcol, h->P1val, X, kp, tmp, kp, kp, kact, 1.0, 0.0, nullptr, 0, st, s,
+                         pb->ctx, pidx, 1));
+    return launch_spmm(n, h->Prowptr, h->Pcol, h->Qval, tmp, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s, pb->ctx,
+                       pidx, 2);
   }
-  return launch_spmm(n, h->Prowptr, h->Pcol, h->Pval, X, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s);
+  return launch_spmm(n, h->Prowptr, h->Pcol, h->Pval, X, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s, pb->ctx, pidx,
+                     3);
 }
 
 }  // namespace
@@ -1189,19 +1436,20 @@ __global__ void k_copy_axpby(int64_t len, const double* X, double* Z, double bet
 template <int KP>
 static int run_cycles(pmor_problem* pb, const pmor_spai* h, int kact, const pmor_solve_opts& o, pmor_stats* stats,
                       const double* bnorm, int* steps_out, int* cycles_out, double* relres_out, int* status) {
-  constexpr int NW = (KP == 16) ? 16 : 4;
+  constexpr int NW = (KP == 16) ? 16 : (KP == 4 ? 8 : 4);
   constexpr int BPW = 32 / NW;  // V blocks per wavefront: m + 1 <= NW * BPW = 32
   Workspace& ws = pb->ws;
   hipStream_t s = pb->ctx->stream;
   const int n = pb->n, m = o.m;
   const int ldh = (m + 1) * KP;
-  Launcher L{pb, h, KP, m, s, KArgs{}, row_grid(n, KP >= 4 ? 16 : 64), nullptr};
+  Launcher L{pb, h, KP, m, s, KArgs{}, row_grid(n, KP >= 4 ? 16 : 64, KP == 4 ? 256 : 512), nullptr};
   KArgs& a = L.a;
   a.n = n; a.m = m; a.vstride = (int64_t)n * KP;
   a.V = ws.V; a.W = ws.W;
   a.Hc1 = ws.Hcol; a.Hc2 = ws.Hcol + (ldh * KP + KP); a.Gram = ws.Hcol + 2 * (ldh * KP + KP);
   a.Hbar = ws.Hbar; a.ldh = ldh; a.G = ws.G; a.ldg = ldh; a.refl = ws.refl; a.Y = ws.Y;
   a.part = ws.part; a.part2 = ws.part2; a.st = ws.st;
+  a.partg0 = ws.partg; a.partg1 = ws.partg + (int64_t)MAX_RED_WG * KMAX * KMAX;
   int* hflag = reinterpret_cast<int*>(reinterpret_cast<char*>(ws.st_host) + sizeof(DevState));
   int* hflag_dev = nullptr;
   PMOR_HIP(hipHostGetDevicePointer((void**)&hflag_dev, hflag, 0));
@@ -1228,37 +1476,45 @@ static int run_cycles(pmor_problem* pb, const pmor_spai* h, int kact, const pmor
   int total_steps = 0, cyc = 0;
   *status = PMOR_ENOTCONV;
   for (cyc = 0; cyc < o.max_cycles; ++cyc) {
+    const int prof_first = (int)pb->ctx->prof.recs.size();
     // initial block QR of W = R_0: V_0 S = W, S -> G(0:kp, :)
     hipLaunchKernelGGL(k_init_cycle, dim3(64), dim3(256), 0, s, a, KP);
     a.nbl_mode = 1; a.hsign = 1.0; a.Hsrc = ws.Hcol; a.zero_init = 0;
     PMOR_TRY((L.template upd<KP, NW, BPW, false, true>(1)));
-    hipLaunchKernelGGL(k_after_gram1, dim3(1), dim3(256), 0, s, a, KP, L.G);
-    PMOR_TRY((L.template scale<KP, NW, true>(0)));
-    hipLaunchKernelGGL(k_after_gram2, dim3(1), dim3(256), 0, s, a, KP, L.G);
+    PMOR_TRY((L.template scale<KP, NW, true>()));
     a.out_block = 1;
-    PMOR_TRY((L.template scale<KP, NW, false>(1)));
+    PMOR_TRY((L.template scale<KP, NW, false>()));
     a.out_block = 0;
     // Arnoldi steps
     for (int jj = 0; jj < m; ++jj) {
       // Z = P V_j ; W = A Z  (V_j is block jj; the kernels skip once the cycle is done)
       const double* Vj = ws.V + (int64_t)jj * blk;
-      if (h) PMOR_TRY(apply_P(pb, h, Vj, ws.Z, ws.T, KP, kact, ws.st, 0.0, s));
-      else hipLaunchKernelGGL(k_copy_axpby, dim3(fgrid), dim3(256), 0, s, blk, Vj, ws.Z, 0.0);
+      const double blkb = 8.0 * (double)n * KP;
+      int pr = prof_start(pb->ctx, PMOR_PROF_SPMM_P);
+      if (h) PMOR_TRY(apply_P(pb, h, Vj, ws.Z, ws.T, KP, kact, ws.st, 0.0, s, pr));
+      else plaunch(pb->ctx, pr, 3, k_copy_axpby, dim3(fgrid), dim3(256), 0, s, blk, (const double*)Vj, ws.Z, 0.0);
+      prof_stop(pb->ctx, pr, h ? 12.0 * h->nnzP + 4.0 * (n + 1) + 2 * blkb : 2 * blkb, jj);
+      pr = prof_start(pb->ctx, PMOR_PROF_SPMM_A);
       PMOR_TRY(launch_spmm(n, pb->rowptr, pb->col, pb->aval, ws.Z, KP, ws.W, KP, KP, kact, 1.0, 0.0, nullptr, 0,
-                           ws.st, s));
+                           ws.st, s, pb->ctx, pr, 3));
+      prof_stop(pb->ctx, pr, 12.0 * pb->nnz + 4.0 * (n + 1) + 2 * blkb, jj);
       a.nbl_mode = 0;
       const int L1 = (jj + 1) * KP * KP + KP, L2 = (jj + 1) * KP * KP;
-      PMOR_TRY((L.template dot<KP, NW, BPW>()));
+      pr = prof_start(pb->ctx, PMOR_PROF_CGS_DOT);
+      PMOR_TRY((L.template dot<KP, NW, BPW>(pr)));
+      prof_stop(pb->ctx, pr, blkb * (jj + 2), jj);
       hipLaunchKernelGGL(k_reduce_cols, dim3((L1 + 7) / 8), dim3(256), 0, s, ws.part, L1, L.G, a.Hc1, ws.st, 1);
       a.Hsrc = a.Hc1; a.hsign = 1.0;
-      PMOR_TRY((L.template upd<KP, NW, BPW, true, false>(jj + 1)));
+      pr = prof_start(pb->ctx, PMOR_PROF_CGS_UPD_DOT);
+      PMOR_TRY((L.template upd<KP, NW, BPW, true, false>(jj + 1, pr)));
+      prof_stop(pb->ctx, pr, blkb * (jj + 3), jj);
       hipLaunchKernelGGL(k_reduce_cols, dim3((L2 + 7) / 8), dim3(256), 0, s, ws.part, L2, L.G, a.Hc2, ws.st, 1);
       a.Hsrc = a.Hc2;
-      PMOR_TRY((L.template upd<KP, NW, BPW, false, true>(jj + 1)));
-      hipLaunchKernelGGL(k_after_gram1, dim3(1), dim3(256), 0, s, a, KP, L.G);
-      PMOR_TRY((L.template scale<KP, NW, true>(0)));
-      hipLaunchKernelGGL(k_after_gram2, dim3(1), dim3(256), 0, s, a, KP, L.G);
-      PMOR_TRY((L.template scale<KP, NW, false>(1)));
+      pr = prof_start(pb->ctx, PMOR_PROF_CGS_UPD_GRAM);
+      PMOR_TRY((L.template upd<KP, NW, BPW, false, true>(jj + 1, pr)));
+      prof_stop(pb->ctx, pr, blkb * (jj + 3), jj);
+      PMOR_TRY((L.template scale<KP, NW, true>()));
+      PMOR_TRY((L.template scale<KP, NW, false>()));
       hipLaunchKernelGGL((k_hess<KP>), dim3(1), dim3(64), hess_shm, s, a);
       PMOR_HIP(hipGetLastError());
       PMOR_HIP(hipEventRecord(evs[jj % 64], s));
@@ -1288,6 +1544,7 @@ static int run_cycles(pmor_problem* pb, const pmor_spai* h, int kact, const pmor
     PMOR_HIP(hipMemcpyAsync(ws.st_host, ws.st, offsetof(DevState, R1), hipMemcpyDeviceToHost, s));
     PMOR_HIP(hipStreamSynchronize(s));
     const DevState& hs = *ws.st_host;
+    prof_drop_from(pb->ctx, prof_first, hs.j);
     total_steps += hs.j;
     if (stats && cyc < PMOR_MAX_CYCLES) stats->cycle_steps[cyc] = hs.j;
     bool conv = true, nan = hs.nanflag != 0;

@@ -383,47 +383,52 @@ __global__ void k_invert_map(const int32_t* map, int64_t len, int32_t* inv) {
 }
 
 // bucket of a column: the least-squares kernel that takes it
+// (16 lanes per column with R rows each: |I| <= 16 R; the LDS kernel above)
 __host__ __device__ inline int bucket_of(int nj, int ni) {
-  if (nj <= 8 && ni <= 64) return 0;
-  if (nj <= 16 && ni <= 64) return 1;
-  if (nj <= 16 && ni <= 128) return 2;
-  if (nj <= 16 && ni <= 256) return 3;
-  if (nj <= 64 && ni <= 512) return 4;
+  if (nj <= 8 && ni <= 16) return 0;
+  if (nj <= 8 && ni <= 32) return 1;
+  if (nj <= 8 && ni <= 64) return 2;
+  if (nj <= 16 && ni <= 64) return 3;
+  if (nj <= 16 && ni <= 128) return 4;
+  if (nj <= 64 && ni <= 512) return 5;
   return 7;  // unsupported
 }
 
+// per-workgroup histogram in LDS, one global atomic per bucket and workgroup
 __global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* Icolptr, int* bcount) {
+  __shared__ int h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  __syncthreads();
   int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  int b = bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j]));
-  atomicAdd(&bcount[b], 1);
+  if (j < n) atomicAdd(&h[bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j]))], 1);
+  __syncthreads();
+  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
 }
 
-// stable fill: one workgroup of 1024 threads walks the columns in order
-__global__ __launch_bounds__(1024) void k_bucket_fill(int n, const int32_t* Jcolptr, const int64_t* Icolptr,
-                                                      const int* boff, int32_t* cols) {
-  __shared__ int cnt[8][1024];
-  __shared__ int base[8];
-  if (threadIdx.x < 8) base[threadIdx.x] = boff[threadIdx.x];
+// Fill the bucket lists: each workgroup counts its columns per bucket in LDS,
+// reserves a range per bucket with one atomic, and writes its columns there in
+// order.  The order of the workgroups' ranges inside a bucket may vary between
+// runs; every column is still solved on its own, so results do not depend on it.
+__global__ __launch_bounds__(256) void k_bucket_fill(int n, const int32_t* Jcolptr, const int64_t* Icolptr,
+                                                     const int* boff, int* cursor, int32_t* cols) {
+  __shared__ int cnt[8], base[8], pos[8][256];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = (j < n) ? bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j])) : -1;
+  for (int q = 0; q < 8; ++q) pos[q][threadIdx.x] = (b == q);
   __syncthreads();
-  for (int start = 0; start < n; start += 1024) {
-    int j = start + threadIdx.x;
-    int b = (j < n) ? bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j])) : -1;
-    for (int q = 0; q < 8; ++q) cnt[q][threadIdx.x] = (b == q);
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive scan per bucket
+    int v[8];
+    for (int q = 0; q < 8; ++q) v[q] = (threadIdx.x >= o) ? pos[q][threadIdx.x - o] : 0;
     __syncthreads();
-    // inclusive scan per bucket (Hillis-Steele)
-    for (int o = 1; o < 1024; o <<= 1) {
-      int v[8];
-      for (int q = 0; q < 8; ++q) v[q] = (threadIdx.x >= o) ? cnt[q][threadIdx.x - o] : 0;
-      __syncthreads();
-      for (int q = 0; q < 8; ++q) cnt[q][threadIdx.x] += v[q];
-      __syncthreads();
-    }
-    if (b >= 0) cols[base[b] + cnt[b][threadIdx.x] - 1] = j;
-    __syncthreads();
-    if (threadIdx.x < 8) base[threadIdx.x] += cnt[threadIdx.x][1023];
+    for (int q = 0; q < 8; ++q) pos[q][threadIdx.x] += v[q];
     __syncthreads();
   }
+  if (threadIdx.x < 8) {
+    cnt[threadIdx.x] = pos[threadIdx.x][255];
+    base[threadIdx.x] = cnt[threadIdx.x] ? boff[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]) : 0;
+  }
+  __syncthreads();
+  if (b >= 0) cols[base[b] + pos[b][threadIdx.x] - 1] = j;
 }
 
 int build_spai_sets(pmor_spai* h) {
@@ -517,11 +522,22 @@ int build_spai_sets(pmor_spai* h) {
     nonempty += hb[b] > 0;
   }
   h->nbuckets = 8;
-  h->identity_order = (hb[0] == n);
+  // when the largest column fits a register kernel, every column takes that one
+  // kernel in natural order (no lists, one launch)
+  const int bmax = bucket_of(h->maxJ, h->maxI);
+  h->identity_order = (bmax <= 4);
+  if (h->identity_order) {
+    for (int b = 0; b < 8; ++b) { h->bucket_count[b] = 0; h->bucket_off[b] = 0; }
+    h->bucket_count[bmax] = n;
+  }
+  for (int b = 0; b < 8; ++b) h->identity_order = h->identity_order || (hb[b] == n);
   if (!h->identity_order) {
-    PMOR_HIP(hipMemcpyAsync(bc + 8, h->bucket_off, sizeof(int) * 8, hipMemcpyHostToDevice, st));
+    int* hb_off = reinterpret_cast<int*>(bc) + 8;
+    for (int b = 0; b < 8; ++b) hb[b] = h->bucket_off[b];
+    PMOR_HIP(hipMemcpyAsync(hb_off, hb, sizeof(int) * 8, hipMemcpyHostToDevice, st));
+    PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 8, st));
     PMOR_HIP(hipMalloc((void**)&h->bucket_cols, sizeof(int32_t) * (n > 0 ? n : 1)));
-    hipLaunchKernelGGL(k_bucket_fill, dim3(1), dim3(1024), 0, st, n, h->Jcolptr, h->Icolptr, bc + 8,
+    hipLaunchKernelGGL(k_bucket_fill, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, hb_off, bc,
                        h->bucket_cols);
     PMOR_HIP(hipGetLastError());
   }

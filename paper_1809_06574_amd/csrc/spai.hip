@@ -56,14 +56,71 @@ struct LsArgs {
 };
 
 // ---------------------------------------------------------------------------
-// register kernel: |J| <= JMAX (<= 16), |I| <= 64 R
+// register kernel: 16 lanes (one DPP row) per column, four columns per
+// wavefront; |J| <= JMAX (<= 16), |I| <= 16 R.  Lane g of a row holds rows
+// g, g + 16, ... of the gathered block.  Sums use a DPP butterfly inside the row
+// (quad_perm xor 1, xor 2, row_half_mirror, row_mirror: every lane ends with the
+// same bits), broadcasts of row k < 16 use row_newbcast:k.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+template <typename T>
+__device__ __forceinline__ T row_sum(T x) {
+  x += dpp_row<0xB1>(x);   // quad_perm(1,0,3,2)
+  x += dpp_row<0x4E>(x);   // quad_perm(2,3,0,1)
+  x += dpp_row<0x141>(x);  // row_half_mirror
+  x += dpp_row<0x140>(x);  // row_mirror
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T row_max(T x) {
+  T y;
+  y = dpp_row<0xB1>(x); x = x > y ? x : y;
+  y = dpp_row<0x4E>(x); x = x > y ? x : y;
+  y = dpp_row<0x141>(x); x = x > y ? x : y;
+  y = dpp_row<0x140>(x); x = x > y ? x : y;
+  return x;
+}
+
+// value of lane k (0..15, a constant after unrolling) of this lane's row
+template <typename T>
+__device__ __forceinline__ T row_bcast(T x, int k) {
+  switch (k) {
+    case 0: return dpp_row<0x150>(x);
+    case 1: return dpp_row<0x151>(x);
+    case 2: return dpp_row<0x152>(x);
+    case 3: return dpp_row<0x153>(x);
+    case 4: return dpp_row<0x154>(x);
+    case 5: return dpp_row<0x155>(x);
+    case 6: return dpp_row<0x156>(x);
+    case 7: return dpp_row<0x157>(x);
+    case 8: return dpp_row<0x158>(x);
+    case 9: return dpp_row<0x159>(x);
+    case 10: return dpp_row<0x15A>(x);
+    case 11: return dpp_row<0x15B>(x);
+    case 12: return dpp_row<0x15C>(x);
+    case 13: return dpp_row<0x15D>(x);
+    case 14: return dpp_row<0x15E>(x);
+    default: return dpp_row<0x15F>(x);
+  }
+}
+
 template <typename T, int JMAX, int R>
 __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int wid = xcd_swizzle(blockIdx.x, gridDim.x) * 4 + wv;
-  if (wid >= a.ncols) return;
+  static_assert(JMAX <= 16, "row k of R must sit in lane k of the row");
+  const int gl = threadIdx.x & 15;
+  const int wid = (xcd_swizzle(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
+  if (wid >= a.ncols) return;  // whole 16-lane rows leave together
   const int j = a.cols ? a.cols[wid] : a.col_off + wid;
   const int jb = a.Jcolptr[j];
   const int nj = a.Jcolptr[j + 1] - jb;
@@ -75,7 +132,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
   // gather A(I_j, J_j) and the right-hand side
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int li = lane + 64 * r;
+    const int li = gl + 16 * r;
     const int row = (li < ni) ? a.Irow[ib + li] : -1;
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) A_[r][t] = T(0);
@@ -94,8 +151,9 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       }
     }
   }
-  T maxR = T(0), minDiag = T(3.0e38);
-  // Householder QR, one reflector per column k
+  T minDiag = T(3.0e38);
+  // Householder QR, one reflector per column k: one round of row sums gives the
+  // column norm and every inner product the reflector needs
 #pragma unroll
   for (int k = 0; k < JMAX; ++k) {
     if (k < nj) {
@@ -104,7 +162,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       for (int c = 0; c <= JMAX; ++c) s[c] = T(0);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int li = lane + 64 * r;
+        const int li = gl + 16 * r;
         if (li >= k) {
           const T x = A_[r][k];
 #pragma unroll
@@ -114,11 +172,8 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       }
 #pragma unroll
       for (int c = k; c <= JMAX; ++c)
-        if (c < nj || c == JMAX) s[c] = wave_sum(s[c]);
-      // row k < JMAX <= 16 lives in slot 0 of lane k
-      constexpr int kr = 0;
-      const int kl = k;
-      const T alpha = readlane_d(A_[kr][k], kl);
+        if (c < nj || c == JMAX) s[c] = row_sum(s[c]);
+      const T alpha = row_bcast(A_[0][k], k);
       const T sig = s[k];
       T beta = alpha;
       if (sig != alpha * alpha) {
@@ -128,11 +183,11 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
         T f[JMAX + 1];
 #pragma unroll
         for (int c = k + 1; c < JMAX; ++c)
-          if (c < nj) f[c] = (s[c] - beta * readlane_d(A_[kr][c], kl)) / denom;
-        f[JMAX] = (s[JMAX] - beta * readlane_d(b_[kr], kl)) / denom;
+          if (c < nj) f[c] = (s[c] - beta * row_bcast(A_[0][c], k)) / denom;
+        f[JMAX] = (s[JMAX] - beta * row_bcast(b_[0], k)) / denom;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int li = lane + 64 * r;
+          const int li = gl + 16 * r;
           if (li >= k) {
             const T v = (li == k) ? (alpha - beta) : A_[r][k];
 #pragma unroll
@@ -144,7 +199,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int li = lane + 64 * r;
+        const int li = gl + 16 * r;
         if (li == k) A_[r][k] = beta;
         else if (li > k) A_[r][k] = T(0);
       }
@@ -152,20 +207,18 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       minDiag = ab < minDiag ? ab : minDiag;
     }
   }
-  // max |R| over the triangle (rows < nj live in slot 0 since nj <= 64)
-  {
-    T mx = T(0);
-    if (lane < nj) {
+  // max |R| over the triangle (rows < nj <= 16 live in slot 0)
+  T mx = T(0);
+  if (gl < nj) {
 #pragma unroll
-      for (int c = 0; c < JMAX; ++c)
-        if (c >= lane && c < nj) {
-          T v = A_[0][c] < T(0) ? -A_[0][c] : A_[0][c];
-          mx = v > mx ? v : mx;
-        }
-    }
-    maxR = wave_max(mx);
+    for (int c = 0; c < JMAX; ++c)
+      if (c >= gl && c < nj) {
+        const T v = A_[0][c] < T(0) ? -A_[0][c] : A_[0][c];
+        mx = v > mx ? v : mx;
+      }
   }
-  // back substitution R p = (Q^T b)(0:nj)
+  const T maxR = row_max(mx);
+  // back substitution R p = (Q^T b)(0:nj), one unknown at a time
   T mine = T(0);
   T p[JMAX];
 #pragma unroll
@@ -176,8 +229,8 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       for (int c = i + 1; c < JMAX; ++c)
         if (c < nj) acc -= A_[0][c] * p[c];
       const T pi = acc / A_[0][i];
-      p[i] = readlane_d(pi, i);
-      if (lane == i) mine = pi;
+      p[i] = row_bcast(pi, i);
+      if (gl == i) mine = pi;
     } else {
       p[i] = T(0);
     }
@@ -186,12 +239,12 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
   T rr = T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int li = lane + 64 * r;
+    const int li = gl + 16 * r;
     if (li >= nj && li < ni) rr += b_[r] * b_[r];
   }
-  rr = wave_sum(rr);
-  if (lane < nj) a.out[a.Pslot[jb + lane]] = (double)mine;
-  if (lane == 0) {
+  rr = row_sum(rr);
+  if (gl < nj) a.out[a.Pslot[jb + gl]] = (double)mine;
+  if (gl == 0) {
     a.rho[j] = sqrt((double)rr);
     const bool singular = (ni < nj) || !(minDiag > T(10.0 * ni * Eps<T>::v) * maxR);
     if (singular) atomicMin(a.bad_col, j);
@@ -295,20 +348,21 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
 }
 
 template <typename T>
-static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st) {
+static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pmor_ctx* pc, int pidx, int part) {
   if (a.ncols == 0) return PMOR_OK;
-  const unsigned g4 = (unsigned)((a.ncols + 3) / 4);
+  const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
   switch (b) {
-    case 0: hipLaunchKernelGGL((k_spai_reg<T, 8, 1>), dim3(g4), dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_spai_reg<T, 16, 1>), dim3(g4), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_spai_reg<T, 16, 2>), dim3(g4), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_spai_reg<T, 16, 4>), dim3(g4), dim3(256), 0, st, a); break;
-    case 4: {
+    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1>, dim3(g16), dim3(256), 0, st, a); break;
+    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2>, dim3(g16), dim3(256), 0, st, a); break;
+    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4>, dim3(g16), dim3(256), 0, st, a); break;
+    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4>, dim3(g16), dim3(256), 0, st, a); break;
+    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8>, dim3(g16), dim3(256), 0, st, a); break;
+    case 5: {
       const int ldI = ((maxI + 7) / 8) * 8;
       const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
       PMOR_TRY(allow_lds((const void*)k_spai_lds<T>, shm));
-      hipLaunchKernelGGL((k_spai_lds<T>), dim3((unsigned)a.ncols), dim3(64), shm, st, a, ldI, maxJ);
+      plaunch(pc, pidx, part, k_spai_lds<T>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
       break;
     }
     default: return fail(PMOR_EINVAL, "column outside the supported SPAI pattern sizes");
@@ -356,14 +410,21 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
   a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval; a.rhs_aval = rhs_aval;
   a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
   a.Pslot = h->Pslot; a.out = out_val; a.rho = h->rho; a.bad_col = dbad;
-  for (int b = 0; b < 5; ++b) {
+  const int pr = prof_start(pb->ctx, PMOR_PROF_SPAI_LS);
+  int first_b = -1, last_b = -1;
+  for (int b = 0; b < 6; ++b)
+    if (h->bucket_count[b]) { if (first_b < 0) first_b = b; last_b = b; }
+  for (int b = 0; b < 6; ++b) {
     if (h->bucket_count[b] == 0) continue;
+    const int part = (b == first_b ? 1 : 0) | (b == last_b ? 2 : 0);
     a.ncols = h->bucket_count[b];
-    if (h->identity_order) { a.cols = nullptr; a.col_off = 0; }
+    if (h->identity_order) { a.cols = nullptr; a.col_off = 0; }  // every column sits in bucket b
     else { a.cols = h->bucket_cols + h->bucket_off[b]; a.col_off = 0; }
-    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st));
-    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st));
+    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
+    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
   }
+  prof_stop(pb->ctx, pr,
+            12.0 * pb->nnz + 4.0 * pb->n + 4.0 * ((double)h->nI + h->nnzP) + 8.0 * h->nnzP + 8.0 * pb->n, 0);
   if (bad_col || fro2) {
     double* dsum = h->red + 1;
     PMOR_TRY(sumsq(h->rho, pb->n, dsum, st));

@@ -28,6 +28,7 @@ PMOR_PAT_A, PMOR_PAT_EXPLICIT = 0, 1
 PMOR_F64, PMOR_F32 = 0, 1
 PMOR_UPD_DIAG, PMOR_UPD_PATTERN = 0, 1
 PMOR_REBUILD, PMOR_UPDATE = 0, 1
+PROF_KERNELS = {"spmm_a": 1, "cgs_upd_dot": 2, "cgs_dot": 3, "spai_ls": 4, "spmm_p": 5, "cgs_upd_gram": 6}
 
 
 class Csr(C.Structure):
@@ -83,6 +84,8 @@ _SIGS = {
                                       C.POINTER(SolveOpts), C.POINTER(Stats)]),
     "pmor_table2_norms": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
     "pmor_spmm": (C.c_int, [P, P, P, I64, P, I64, I32, D, D]),
+    "pmor_prof_set": (C.c_int, [P, C.c_int]),
+    "pmor_prof_read": (C.c_int, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]),
     "pmor_strerror": (C.c_char_p, [C.c_int]),
     "pmor_last_error": (C.c_char_p, []),
 }
