@@ -101,7 +101,7 @@ typedef struct pmor_spai_opts {
 } pmor_spai_opts;
 
 typedef struct pmor_solve_opts {
-  int32_t m;          /* block steps per cycle (restart length), 1..64         */
+  int32_t m;          /* block steps per cycle (restart length), 1..31         */
   int32_t max_cycles; /* cycles before PMOR_ENOTCONV, 1..PMOR_MAX_CYCLES        */
   double tol;         /* per-column relative residual ||b-Ax||/||b||           */
 } pmor_solve_opts;
@@ -117,7 +117,9 @@ typedef struct pmor_stats {
                              /* (U-diag: with Q = diag(q))                        */
   double t_assemble_ms;      /* device time of the assembly of A(s,p)            */
   double t_precond_ms;       /* device time of the build or update               */
-  double t_solve_ms;         /* wall time of block_solve                         */
+  double t_solve_ms;         /* block_solve: its wall time; batched calls: wall  */
+                             /* time from the call's start until this system's X */
+                             /* is final                                         */
 } pmor_stats;
 
 /* ---- context ----------------------------------------------------------- */
@@ -189,21 +191,110 @@ void spai_free(pmor_spai* h);
  * B that are zero get X = 0.  Converged when every column reaches
  * ||b_c - A x_c|| <= tol ||b_c||.  opts NULL: m = 30, tol = 1e-8,
  * max_cycles = 20.  Returns PMOR_ENOTCONV (X = last iterate),
- * PMOR_EBREAKDOWN or PMOR_ENAN on failure.  Synchronises the stream. */
+ * PMOR_EBREAKDOWN, or PMOR_ENAN (NaN/Inf in B: X = 0; in a residual: X = last
+ * iterate) on failure.  Synchronises the stream. */
 int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p,
                 const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
                 const pmor_solve_opts* opts, pmor_stats* stats);
 
+/* One system of pmor_batch_solve: A(s,p) of problem pb (assembled by the
+ * library), preconditioned by h's current preconditioner (or NULL), B and X as
+ * in block_solve. */
+typedef struct pmor_batch_item {
+  pmor_problem* pb;
+  const pmor_spai* h;
+  double s, p;
+  const double* B;
+  int64_t ldb;
+  int32_t k;
+  double* X;
+  int64_t ldx;
+} pmor_batch_item;
+
+/* Solve many independent systems together (the batching of the hot path):
+ * every system runs block GMRES(m) exactly as block_solve would, and all of them
+ * advance in lockstep, each kernel launch covering every unfinished system.  A
+ * system's result is bit-identical to its solve alone (its reductions depend on
+ * its own sizes only).  Items may share a problem at different points and may
+ * share a handle (its current preconditioner is used).  The block width is the
+ * largest k of the batch.  status (nitems, host, may be NULL) receives each
+ * system's code as block_solve would return it; stats: nitems entries or NULL.
+ * Returns PMOR_OK when every system converged, else the first failing system's
+ * code.  Device memory: about 8 (m + 6) kp n bytes per system plus nnz(A) values
+ * for each extra point of a shared problem.  Synchronises the stream. */
+int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems,
+                     const pmor_solve_opts* opts, pmor_stats* stats, int32_t* status);
+
 /* The whole sequence of Section 2.3 for points (s_list[l], p_list[l]),
- * l < npts: preconditioner at point 0 by spai_build, then for l >= 1 either
- * spai_update (PMOR_UPDATE) or spai_rebuild (PMOR_REBUILD), then block_solve.
+ * l < npts: P_1 = spai_build at point 0; for l >= 1 the first-approach update
+ * P_l = Q_l P_1 (PMOR_UPDATE) or a fresh SPAI of A(l) (PMOR_REBUILD).  The
+ * points are independent once P_1 exists, so their systems are solved together
+ * as in pmor_batch_solve (in groups sized to the free device memory).
  * X: npts consecutive n x k row-major blocks (ldx per block, block stride
- * n*ldx).  stats: npts entries (may be NULL).  Stops at the first error. */
+ * n*ldx).  stats: npts entries (may be NULL); t_solve_ms is the wall time from
+ * the call's start to the point's final X.  A point whose update or rebuild
+ * meets a singular column is not solved (PMOR_ESINGULAR, X untouched); the
+ * others are.  Returns the first failing point's code, else PMOR_OK. */
 int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k,
                         const double* s_list, const double* p_list, int32_t npts,
                         double* X, int64_t ldx, int32_t policy,
                         const pmor_spai_opts* sopts, const pmor_solve_opts* vopts,
                         pmor_stats* stats);
+
+/* ---- serving: continuous batching of sequence jobs ----------------------- */
+/* A server admits whole sequence jobs (one pmor_sequence_solve each) under a
+ * device-memory budget and solves the points of all admitted jobs in one
+ * persistent block GMRES engine: at every restart-cycle boundary finished
+ * points leave it and waiting points of any job join it.  A point's X is bit
+ * for bit what pmor_sequence_solve gives for it when it runs alone, whatever
+ * else shares the engine.  Single-threaded: all calls on one host thread. */
+typedef struct pmor_server pmor_server;
+
+typedef struct pmor_server_opts {
+  int64_t hbm_budget;   /* device bytes for the engine and admitted jobs; 0: 75% of free memory */
+  int64_t engine_rows;  /* sum of n over the systems the engine holds at once; 0: from the budget */
+  int32_t k;            /* widest job (the engine's block width), 1..PMOR_KMAX */
+  int32_t max_systems;  /* systems in the engine at once; 0: 64 */
+} pmor_server_opts;
+
+typedef struct pmor_job {
+  pmor_problem* pb;     /* owned by the caller, alive until the job is reported done */
+  const double* B;      /* n x k, ld ldb (device) */
+  int64_t ldb;
+  int32_t k;
+  const double* s_list; /* npts points (host; copied at submission) */
+  const double* p_list;
+  int32_t npts;
+  double* X;            /* npts blocks n x k, ld ldx, block stride n*ldx (device) */
+  int64_t ldx;
+  int32_t policy;       /* PMOR_UPDATE | PMOR_REBUILD */
+  pmor_stats* stats;    /* npts entries or NULL (host, written until the job is done); */
+                        /* t_solve_ms = submission to the point's final X            */
+} pmor_job;
+
+/* sopts, vopts: as pmor_sequence_solve (NULL: defaults).  The engine's
+ * buffers are allocated here.  PMOR_ENOMEM when the budget cannot hold them. */
+int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_spai_opts* sopts,
+                       const pmor_solve_opts* vopts, pmor_server** out);
+/* Jobs still held are dropped (their X undefined). */
+void pmor_server_destroy(pmor_server* sv);
+/* Queue a job (first in, first out).  PMOR_EADMIT when it can never be admitted:
+ * its device footprint exceeds the budget, n exceeds the engine's rows or k
+ * its block width.  *job_id (host) identifies it in pmor_server_step. */
+int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id);
+/* One scheduling round: admit queued jobs in order while their footprint fits
+ * the free budget (P_1, every point's A(l) and preconditioner are built then),
+ * move waiting points into the engine while rows and slots are free, run one
+ * restart cycle of every system in the engine, retire finished points and
+ * jobs.  done_ids / done_status (host, max_done entries): jobs finished since
+ * the last report with their first failing code (PMOR_OK when all points
+ * converged); *ndone their count (reports beyond max_done wait for the next
+ * call).  Returns an error only for failures of the server itself. */
+int pmor_server_step(pmor_server* sv, int64_t* done_ids, int32_t* done_status, int32_t max_done, int32_t* ndone);
+/* Host outputs, any may be NULL: queued jobs, admitted jobs, systems in the
+ * engine, device bytes reserved (engine + admitted jobs). */
+int pmor_server_info(const pmor_server* sv, int32_t* queued, int32_t* admitted, int32_t* running,
+                     int64_t* bytes_in_use);
 
 /* ---- diagnostics (Section 3.1, Table 2) -------------------------------- */
 /* ||I - A(s,p)||_F and ||A(s1,p1) - A(s2,p2)||_F (host outputs; synchronises). */
@@ -223,12 +314,13 @@ int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx
  * timing off.  Launches of block steps that a converged cycle skipped are not
  * counted.  pmor_prof_read synchronises the stream, returns the totals since the
  * last read and resets them. */
+/* Per system of a launch (n rows, kp block width, nblk V blocks swept): */
 #define PMOR_PROF_SPMM_A 1        /* W = A Z in a block step: 12 nnz + 4(n+1) + 16 n kp */
-#define PMOR_PROF_CGS_UPD_DOT 2   /* Gram-Schmidt pass 2: W -= V H; V^T W: 8 n kp (nblk + 2) */
-#define PMOR_PROF_CGS_DOT 3       /* Gram-Schmidt pass 1: V^T W: 8 n kp (nblk + 1) */
+#define PMOR_PROF_CGS_UPD_DOT 2   /* pass 2: W -= V H1; V^T W, W^T W: 8 n kp (nblk + 2) */
+#define PMOR_PROF_CGS_DOT 3       /* pass 1: V^T W, column norms: 8 n kp (nblk + 1) */
 #define PMOR_PROF_SPAI_LS 4       /* SPAI least squares: 12 nnz + 4 n + 4 (sum|I_j| + nnzP) + 8 nnzP + 8 n */
-#define PMOR_PROF_SPMM_P 5        /* Z = P V_j in a block step: 12 nnzP + 4(n+1) + 16 n kp */
-#define PMOR_PROF_CGS_UPD_GRAM 6  /* Gram-Schmidt pass 3: W -= V H; W^T W: 8 n kp (nblk + 2) */
+#define PMOR_PROF_SPMM_P 5        /* Z = P V_j, V_j = W1 R2^-1 written: 12 nnzP + 4(n+1) + 24 n kp */
+#define PMOR_PROF_CGS_UPD_GRAM 6  /* pass 3: W -= V H2; W R1^-1; Gram: 8 n kp (nblk + 2) */
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id);
 int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
 

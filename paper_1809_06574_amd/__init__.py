@@ -12,7 +12,8 @@ first use, which raises ImportError when libpmorspai.so has not been built
 import importlib
 
 _LAZY = {"lib": ("lib", None), "Context": ("api", "Context"), "Problem": ("api", "Problem"),
-         "Spai": ("api", "Spai")}
+         "Spai": ("api", "Spai"), "batch_solve": ("api", "batch_solve"),
+         "Server": ("api", "Server")}
 
 
 def __getattr__(name):

@@ -127,19 +127,47 @@ class Problem:
         return X, st.as_dict(), rc
 
     def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
-                       pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20):
+                       pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
+                       raise_on_error=True):
         n, k = B.shape
         npts = len(p_list)
-        X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
+        if X is None:
+            X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
         sl = (C.c_double * npts)(*[float(x) for x in s_list])
         pl = (C.c_double * npts)(*[float(x) for x in p_list])
         so = _spai_opts(pattern, precision, update, self.ctx.device, self)
         vo = L.SolveOpts(m, max_cycles, tol)
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
-        L.check(L.pmor_sequence_solve(self.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(),
-                                      X.stride(1), pol, C.byref(so), C.byref(vo), stats), "pmor_sequence_solve")
-        return X, [s.as_dict() for s in stats]
+        rc = L.pmor_sequence_solve(self.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(),
+                                   X.stride(1), pol, C.byref(so), C.byref(vo), stats)
+        if raise_on_error:
+            L.check(rc, "pmor_sequence_solve")
+            return X, [s.as_dict() for s in stats]
+        return X, [s.as_dict() for s in stats], rc
+
+
+def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_error=True):
+    """Solve independent systems together (pmor_batch_solve).  ``items``: sequence of
+    ``(problem, spai_or_None, s, p, B)`` or ``(problem, spai, s, p, B, X)``.
+    Returns (list of X, list of stats dicts, list of status codes, rc)."""
+    n_it = len(items)
+    arr = (L.BatchItem * max(n_it, 1))()
+    Xs = []
+    for i, itm in enumerate(items):
+        pb, sp, s, p, B = itm[:5]
+        X = itm[5] if len(itm) > 5 and itm[5] is not None else torch.empty(B.shape, dtype=torch.float64,
+                                                                              device=B.device)
+        Xs.append(X)
+        arr[i] = L.BatchItem(pb.handle, sp.handle if sp is not None else None, float(s), float(p), B.data_ptr(),
+                             B.stride(0), B.shape[1], X.data_ptr(), X.stride(0))
+    stats = (L.Stats * max(n_it, 1))()
+    status = (C.c_int32 * max(n_it, 1))()
+    o = L.SolveOpts(m, max_cycles, tol)
+    rc = L.pmor_batch_solve(ctx.handle, arr, n_it, C.byref(o), stats, status)
+    if raise_on_error:
+        L.check(rc, "pmor_batch_solve")
+    return Xs, [stats[i].as_dict() for i in range(n_it)], [status[i] for i in range(n_it)], rc
 
 
 def _spai_opts(pattern, precision, update, device, keeper):
@@ -216,6 +244,66 @@ class Spai:
     def close(self):
         if self.handle:
             L.spai_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of sequence jobs over one persistent engine (pmor_server_*)."""
+
+    def __init__(self, ctx: Context, k: int, hbm_budget: int = 0, engine_rows: int = 0, max_systems: int = 0,
+                 update="diag", precision="f64", m=30, tol=1e-8, max_cycles=20):
+        self.ctx = ctx
+        so = _spai_opts(None, precision, update, ctx.device, self)
+        vo = L.SolveOpts(m, max_cycles, tol)
+        opts = L.ServerOpts(int(hbm_budget), int(engine_rows), int(k), int(max_systems))
+        h = C.c_void_p()
+        L.check(L.pmor_server_create(ctx.handle, C.byref(opts), C.byref(so), C.byref(vo), C.byref(h)),
+                "pmor_server_create")
+        self.handle = h
+        self.jobs = {}
+
+    def submit(self, pb: Problem, B: torch.Tensor, s_list, p_list, policy="update", X=None):
+        """Queue a job; returns its id.  X (npts, n, k) is written when the job is reported done."""
+        n, k = B.shape
+        npts = len(p_list)
+        if X is None:
+            X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
+        sl = (C.c_double * npts)(*[float(x) for x in s_list])
+        pl = (C.c_double * npts)(*[float(x) for x in p_list])
+        stats = (L.Stats * npts)()
+        pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
+        job = L.Job(pb.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(), X.stride(1), pol, stats)
+        jid = C.c_int64()
+        L.check(L.pmor_server_submit(self.handle, C.byref(job), C.byref(jid)), "pmor_server_submit")
+        self.jobs[jid.value] = {"pb": pb, "B": B, "X": X, "stats": stats, "s": sl, "p": pl}
+        return jid.value
+
+    def step(self, max_done: int = 256):
+        """One scheduling round; returns [(job_id, status, X, stats dicts)] of finished jobs."""
+        ids = (C.c_int64 * max_done)()
+        sts = (C.c_int32 * max_done)()
+        nd = C.c_int32()
+        L.check(L.pmor_server_step(self.handle, ids, sts, max_done, C.byref(nd)), "pmor_server_step")
+        out = []
+        for i in range(nd.value):
+            rec = self.jobs.pop(ids[i])
+            out.append((ids[i], sts[i], rec["X"], [s.as_dict() for s in rec["stats"]]))
+        return out
+
+    def info(self):
+        q, a, r, b = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        L.check(L.pmor_server_info(self.handle, C.byref(q), C.byref(a), C.byref(r), C.byref(b)), "pmor_server_info")
+        return {"queued": q.value, "admitted": a.value, "running": r.value, "bytes": b.value}
+
+    def close(self):
+        if self.handle:
+            L.pmor_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

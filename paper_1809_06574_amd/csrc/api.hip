@@ -5,7 +5,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -58,13 +61,33 @@ void prof_stop(pmor_ctx* c, int idx, double bytes, int tag) {
   if (idx < 0) return;
   ProfRec& r = c->prof.recs[idx];
   r.bytes = bytes;
-  r.tag = tag;
+  r.tag = -1;  // not a block-step record: kept as is
+  (void)tag;
+  r.e0 = r.e1 = 0;
 }
 
-void prof_drop_from(pmor_ctx* c, int first_idx, int tag_limit) {
+void prof_stop_seg(pmor_ctx* c, int idx, int tag, int e0) {
+  if (idx < 0) return;
+  ProfRec& r = c->prof.recs[idx];
+  r.bytes = 0.0;
+  r.tag = tag;
+  r.e0 = e0;
+  r.e1 = (int)c->prof.ent.size();
+}
+
+void prof_resolve(pmor_ctx* c, int first_idx, const int* steps_of) {
   auto& recs = c->prof.recs;
-  for (size_t i = (first_idx < 0 ? 0 : first_idx); i < recs.size(); ++i)
-    if (recs[i].tag >= tag_limit) recs[i].valid = false;
+  const auto& ent = c->prof.ent;
+  for (size_t i = (first_idx < 0 ? 0 : first_idx); i < recs.size(); ++i) {
+    ProfRec& r = recs[i];
+    if (r.tag < 0) continue;
+    double b = 0.0;
+    for (int e = r.e0; e < r.e1; ++e)
+      if (steps_of[ent[e].first] > r.tag) b += ent[e].second;
+    r.bytes = b;
+    r.tag = -1;
+    if (b == 0.0) r.valid = false;  // every segment had finished: the launch only exited
+  }
 }
 
 static void prof_collect(pmor_ctx* c) {
@@ -82,6 +105,7 @@ static void prof_collect(pmor_ctx* c) {
     P.spare.push_back(r.b);
   }
   P.recs.clear();
+  P.ent.clear();
 }
 
 int ensure_assembled(pmor_problem* pb, double s, double p) {
@@ -179,6 +203,56 @@ static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
   return PMOR_OK;
 }
 
+static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* aval, const double* B, int64_t ldb,
+                         int k, double* X, int64_t ldx, pmor_stats* stats) {
+  SolveItem it{};
+  it.n = pb->n;
+  it.nnzA = pb->nnz;
+  it.arow = pb->rowptr;
+  it.acol = pb->col;
+  it.aval = aval;
+  it.pkind = 0;
+  if (h) {
+    it.pkind = h->q_active ? 2 : 1;
+    it.nnzP = h->nnzP;
+    it.prow = h->Prowptr;
+    it.pcol = h->Pcol;
+    it.pval = h->q_active ? h->P1val : h->Pval;
+    it.qval = h->Qval;
+  }
+  it.B = B;
+  it.ldb = ldb;
+  it.k = k;
+  it.X = X;
+  it.ldx = ldx;
+  it.stats = stats;
+  if (stats) {
+    stats->cycles = 0;
+    stats->steps = 0;
+    std::memset(stats->cycle_steps, 0, sizeof(stats->cycle_steps));
+  }
+  return it;
+}
+
+static int status_error(int st) {
+  switch (st) {
+    case PMOR_OK: return PMOR_OK;
+    case PMOR_ENOTCONV: return fail(st, "block GMRES did not converge within max_cycles");
+    case PMOR_EBREAKDOWN: return fail(st, "block breakdown: rank-deficient block with unconverged columns");
+    case PMOR_ENAN: return fail(st, "NaN or Inf in the right-hand side or a residual");
+    default: return st;
+  }
+}
+
+static int solve_opts_of(const pmor_solve_opts* opts, pmor_solve_opts* o) {
+  *o = pmor_solve_opts{30, 20, 1e-8};
+  if (opts) *o = *opts;
+  if (o->m < 1 || o->m > 31) return fail(PMOR_EINVAL, "m must be in 1..31");
+  if (o->max_cycles < 1 || o->max_cycles > PMOR_MAX_CYCLES) return fail(PMOR_EINVAL, "max_cycles out of range");
+  if (!(o->tol > 0.0) || !is_fin(o->tol)) return fail(PMOR_EINVAL, "tol must be positive");
+  return PMOR_OK;
+}
+
 }  // namespace pmor
 
 using namespace pmor;
@@ -235,6 +309,7 @@ void pmor_ctx_destroy(pmor_ctx* c) {
   (void)hipEventDestroy(c->ev1);
   for (int i = 0; i < 64; ++i)
     if (c->evs[i]) (void)hipEventDestroy(c->evs[i]);
+  engine_destroy(c->eng);
   delete c;
 }
 
@@ -278,7 +353,6 @@ void pmor_problem_destroy(pmor_problem* pb) {
     if (x) (void)hipFree(x);
   if (pb->tval) (void)hipFree(pb->tval);
   if (pb->aval) (void)hipFree(pb->aval);
-  free_workspace(pb->ws);
   delete pb;
 }
 
@@ -430,47 +504,551 @@ int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p, const 
   if (ldb < k || ldx < k) return fail(PMOR_EINVAL, "leading dimension smaller than k");
   if (h && h->pb != pb) return fail(PMOR_EINVAL, "preconditioner belongs to another problem");
   if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
-  pmor_solve_opts o{30, 20, 1e-8};
-  if (opts) o = *opts;
-  if (o.m < 1 || o.m > 31) return fail(PMOR_EINVAL, "m must be in 1..31");
-  if (o.max_cycles < 1 || o.max_cycles > PMOR_MAX_CYCLES) return fail(PMOR_EINVAL, "max_cycles out of range");
-  if (!(o.tol > 0.0) || !is_fin(o.tol)) return fail(PMOR_EINVAL, "tol must be positive");
+  pmor_solve_opts o;
+  PMOR_TRY(solve_opts_of(opts, &o));
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   auto t0 = std::chrono::steady_clock::now();
   PMOR_TRY(ensure_assembled(pb, s, p));
-  if (stats) std::memset(stats->cycle_steps, 0, sizeof(stats->cycle_steps));
-  int rc = krylov_solve(pb, h, B, ldb, k, X, ldx, o, stats);
+  SolveItem it = item_of(pb, h, pb->aval, B, ldb, k, X, ldx, stats);
+  PMOR_TRY(krylov_batch(pb->ctx, &it, 1, o));
   if (stats) {
     stats->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
+  return status_error(it.status);
+}
+
+int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems, const pmor_solve_opts* opts,
+                     pmor_stats* stats, int32_t* status) {
+  if (!ctx || (!items && nitems > 0)) return fail(PMOR_EINVAL, "NULL argument");
+  if (nitems < 0) return fail(PMOR_EINVAL, "nitems must not be negative");
+  pmor_solve_opts o;
+  PMOR_TRY(solve_opts_of(opts, &o));
+  for (int i = 0; i < nitems; ++i) {
+    const pmor_batch_item& b = items[i];
+    if (!b.pb || !b.B || !b.X) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": NULL argument");
+    if (b.pb->ctx != ctx) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": problem of another context");
+    if (b.k < 1 || b.k > PMOR_KMAX || b.ldb < b.k || b.ldx < b.k)
+      return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": bad k or leading dimension");
+    if (b.h && b.h->pb != b.pb) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": foreign preconditioner");
+    if (!is_fin(b.s) || !is_fin(b.p)) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": s, p not finite");
+  }
+  if (nitems == 0) return PMOR_OK;
+  PMOR_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  // A values: the problem's own buffer for its first point, private copies for other points
+  std::vector<SolveItem> it(nitems);
+  std::vector<double*> extra;
+  int rc = PMOR_OK;
+  for (int i = 0; i < nitems && rc == PMOR_OK; ++i) {
+    const pmor_batch_item& b = items[i];
+    const double* aval = nullptr;
+    for (int q = 0; q < i; ++q)
+      if (items[q].pb == b.pb && items[q].s == b.s && items[q].p == b.p) { aval = it[q].aval; break; }
+    if (!aval) {
+      bool first = true;
+      for (int q = 0; q < i; ++q)
+        if (items[q].pb == b.pb) first = false;
+      if (first) {
+        rc = ensure_assembled(b.pb, b.s, b.p);
+        aval = b.pb->aval;
+      } else {
+        double* buf = nullptr;
+        if (hipMalloc((void**)&buf, sizeof(double) * std::max<int64_t>(b.pb->nnz, 1)) != hipSuccess) {
+          (void)hipGetLastError();
+          rc = fail(PMOR_ENOMEM, "allocation of a point's A values failed");
+          break;
+        }
+        extra.push_back(buf);
+        double c[PMOR_NROLES];
+        role_coefs(b.s, b.p, c);
+        rc = launch_assemble(b.pb, c, buf, st);
+        aval = buf;
+      }
+    }
+    it[i] = item_of(b.pb, b.h, aval, b.B, b.ldb, b.k, b.X, b.ldx, stats ? &stats[i] : nullptr);
+  }
+  if (rc == PMOR_OK) rc = krylov_batch(ctx, it.data(), nitems, o);
+  for (double* x : extra) (void)hipFree(x);
+  if (rc != PMOR_OK) return rc;
+  int first_bad = PMOR_OK;
+  for (int i = 0; i < nitems; ++i) {
+    if (status) status[i] = it[i].status;
+    if (stats) stats[i].t_solve_ms = it[i].t_done_ms;
+    if (first_bad == PMOR_OK && it[i].status != PMOR_OK) first_bad = it[i].status;
+  }
+  return status_error(first_bad);
+}
+
+}  // extern "C"
+
+namespace pmor {
+
+// device buffers of a group of points of one sequence
+struct SeqBuffers {
+  double* aval = nullptr;   // group x nnz: A(l) values
+  double* pq = nullptr;     // group x nnzP: P_l, or Q_l for the pattern update
+  double* q = nullptr;      // n (U-diag factors, scratch)
+  double* rho = nullptr;    // n (U-diag column residuals, scratch)
+  double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
+  int* bad = nullptr;       // group
+  int64_t bytes = 0;
+  SeqBuffers() = default;
+  SeqBuffers(const SeqBuffers&) = delete;
+  SeqBuffers& operator=(const SeqBuffers&) = delete;
+  ~SeqBuffers() {
+    void* v[] = {aval, pq, q, rho, fro, bad};
+    for (void* x : v)
+      if (x) (void)hipFree(x);
+  }
+  int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n) {
+    auto al = [&](void** p, size_t b) {
+      b = std::max<size_t>(b, 8);
+      if (hipMalloc(p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PMOR_ENOMEM, "allocation of the sequence buffers failed");
+      }
+      bytes += (int64_t)b;
+      return PMOR_OK;
+    };
+    PMOR_TRY(al((void**)&aval, sizeof(double) * group * nnz));
+    PMOR_TRY(al((void**)&pq, sizeof(double) * group * nnzP));
+    PMOR_TRY(al((void**)&q, sizeof(double) * n));
+    PMOR_TRY(al((void**)&rho, sizeof(double) * n));
+    PMOR_TRY(al((void**)&fro, sizeof(double) * group * 260));
+    PMOR_TRY(al((void**)&bad, sizeof(int) * group));
+    return PMOR_OK;
+  }
+  static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n) {
+    return 8 * group * (nnz + nnzP) + 16 * n + 8 * 260 * group + 4 * group + 6 * 256;
+  }
+};
+
+// Points [l0, l0 + cnt) of a sequence whose P_1 (point 0) is h's anchor: A(l)
+// into sb.aval + t nnz, the point's preconditioner (P_1 for point 0, else the
+// first-approach update or, for the rebuild policy, a fresh SPAI) into
+// sb.pq + t nnzP, and the engine item of every point.  bad[t]: a singular
+// column of the point's least-squares problems, or -1.  stats (the sequence's
+// array, may be NULL) gets the assembly and preconditioner times, the residual
+// norm and bad_column of each point.  Synchronises the stream.
+static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const double* s_list, const double* p_list,
+                          int l0, int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
+                          pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
+  hipStream_t st = pb->ctx->stream;
+  const bool upat = h->opts.update == PMOR_UPD_PATTERN;
+  const int n = pb->n;
+  const int64_t nnz = pb->nnz, nnzP = h->nnzP;
+  std::vector<hipEvent_t> ev;
+  if (stats) {
+    ev.assign(2 * (size_t)cnt + 1, nullptr);
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { e = nullptr; (void)hipGetLastError(); }
+  }
+  auto rec = [&](size_t i) {
+    if (i < ev.size() && ev[i]) (void)hipEventRecord(ev[i], st);
+  };
+  std::vector<double> fro_host(cnt, 0.0);
+  int rc = PMOR_OK;
+  rec(0);
+  for (int t = 0; t < cnt && rc == PMOR_OK; ++t) {
+    const int l = l0 + t;
+    bad[t] = -1;
+    double* Al = sb.aval + (int64_t)t * nnz;
+    double* PQ = sb.pq + (int64_t)t * nnzP;
+    double c[PMOR_NROLES];
+    role_coefs(s_list[l], p_list[l], c);
+    rc = launch_assemble(pb, c, Al, st);
+    rec(1 + 2 * t);
+    if (rc != PMOR_OK) break;
+    SolveItem x = item_of(pb, nullptr, Al, B, ldb, k, X + (int64_t)l * n * ldx, ldx, stats ? &stats[l] : nullptr);
+    x.pkind = 1;
+    x.prow = h->Prowptr;
+    x.pcol = h->Pcol;
+    x.nnzP = nnzP;
+    x.tag = l;
+    if (l == 0) {
+      x.pval = h->P1val;
+      fro_host[t] = pre0.fro_resid * pre0.fro_resid;
+      bad[t] = pre0.bad_column;
+    } else if (policy == PMOR_UPDATE && !upat) {
+      rc = set_device_int(sb.bad + t, 0x7fffffff, st);
+      if (rc == PMOR_OK) rc = launch_update_diag(h, Al, PQ, sb.q, sb.rho, sb.bad + t);
+      if (rc == PMOR_OK && stats) rc = sumsq(sb.rho, n, sb.fro + (int64_t)t * 260, st);
+      x.pval = PQ;
+    } else {
+      int32_t b = -1;
+      double fro2 = 0.0;
+      rc = run_spai_ls(h, Al, policy == PMOR_UPDATE ? h->aval1 : nullptr, PQ, &b, stats ? &fro2 : nullptr);
+      bad[t] = b;
+      fro_host[t] = fro2;
+      if (policy == PMOR_UPDATE) { x.pkind = 2; x.pval = h->P1val; x.qval = PQ; }
+      else x.pval = PQ;
+    }
+    rec(2 + 2 * t);
+    items[t] = x;
+  }
+  if (rc == PMOR_OK && policy == PMOR_UPDATE && !upat) {
+    std::vector<int> bd(cnt, 0x7fffffff);
+    std::vector<double> fr2((size_t)cnt * 260, 0.0);
+    rc = hipMemcpyAsync(bd.data(), sb.bad, sizeof(int) * cnt, hipMemcpyDeviceToHost, st) == hipSuccess ? PMOR_OK
+                                                                                                  : PMOR_EHIP;
+    if (rc == PMOR_OK && stats)
+      rc = hipMemcpyAsync(fr2.data(), sb.fro, sizeof(double) * 260 * cnt, hipMemcpyDeviceToHost, st) == hipSuccess
+               ? PMOR_OK : PMOR_EHIP;
+    if (rc == PMOR_OK) rc = hipStreamSynchronize(st) == hipSuccess ? PMOR_OK : PMOR_EHIP;
+    if (rc != PMOR_OK) set_error("copy of the update verdicts failed");
+    for (int t = 0; t < cnt && rc == PMOR_OK; ++t) {
+      if (l0 + t == 0) continue;
+      bad[t] = (bd[t] == 0x7fffffff) ? -1 : bd[t];
+      fro_host[t] = fr2[(size_t)t * 260];
+    }
+  }
+  if (rc == PMOR_OK) rc = hipStreamSynchronize(st) == hipSuccess ? PMOR_OK : fail(PMOR_EHIP, "synchronise failed");
+  if (stats && rc == PMOR_OK) {
+    for (int t = 0; t < cnt; ++t) {
+      pmor_stats& S = stats[l0 + t];
+      float a = 0.f, b = 0.f;
+      if (ev[2 * t] && ev[1 + 2 * t]) (void)hipEventElapsedTime(&a, ev[2 * t], ev[1 + 2 * t]);
+      if (ev[1 + 2 * t] && ev[2 + 2 * t]) (void)hipEventElapsedTime(&b, ev[1 + 2 * t], ev[2 + 2 * t]);
+      S.t_assemble_ms = a;
+      S.t_precond_ms = b;
+      S.fro_resid = std::sqrt(fro_host[t]);
+      S.bad_column = bad[t];
+      if (l0 + t == 0) {
+        S.t_assemble_ms += pre0.t_assemble_ms;
+        S.t_precond_ms += pre0.t_precond_ms;
+      }
+    }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
   return rc;
 }
+
+static int sequence_checks(const pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
+                           const double* p_list, int32_t npts, const double* X, int64_t ldx, int32_t policy) {
+  if (!pb || !B || !X || !s_list || !p_list) return fail(PMOR_EINVAL, "NULL argument");
+  if (npts < 1) return fail(PMOR_EINVAL, "npts must be positive");
+  if (policy != PMOR_REBUILD && policy != PMOR_UPDATE) return fail(PMOR_EINVAL, "bad policy");
+  if (k < 1 || k > PMOR_KMAX || ldb < k || ldx < k) return fail(PMOR_EINVAL, "bad k or leading dimension");
+  for (int l = 0; l < npts; ++l)
+    if (!is_fin(s_list[l]) || !is_fin(p_list[l])) return fail(PMOR_EINVAL, "s and p must be finite");
+  return PMOR_OK;
+}
+
+}  // namespace pmor
+
+extern "C" {
 
 int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
                         const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
                         const pmor_spai_opts* sopts, const pmor_solve_opts* vopts, pmor_stats* stats) {
-  if (!pb || !B || !X || !s_list || !p_list) return fail(PMOR_EINVAL, "NULL argument");
-  if (npts < 1) return fail(PMOR_EINVAL, "npts must be positive");
-  if (policy != PMOR_REBUILD && policy != PMOR_UPDATE) return fail(PMOR_EINVAL, "bad policy");
+  PMOR_TRY(sequence_checks(pb, B, ldb, k, s_list, p_list, npts, X, ldx, policy));
+  pmor_solve_opts o;
+  PMOR_TRY(solve_opts_of(vopts, &o));
+  PMOR_HIP(hipSetDevice(pb->ctx->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  auto since = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
+  if (stats) std::memset(stats, 0, sizeof(pmor_stats) * npts);
+  pmor_stats pre0{};
+  pre0.bad_column = -1;
   pmor_spai* h = nullptr;
-  int rc = PMOR_OK;
-  for (int l = 0; l < npts && rc == PMOR_OK; ++l) {
-    pmor_stats* stl = stats ? &stats[l] : nullptr;
-    pmor_stats pre{};
-    if (l == 0) rc = spai_build(pb, s_list[0], p_list[0], sopts, &h, stl ? &pre : nullptr);
-    else if (policy == PMOR_UPDATE) rc = spai_update(h, s_list[l], p_list[l], stl ? &pre : nullptr);
-    else rc = spai_rebuild(h, s_list[l], p_list[l], stl ? &pre : nullptr);
+  int rc = spai_build(pb, s_list[0], p_list[0], sopts, &h, &pre0);
+  if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
+    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); }
+    spai_release(h);
+    return rc;
+  }
+  if (rc == PMOR_ESINGULAR) {  // no anchor: nothing can be solved
+    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); }
+    spai_release(h);
+    return rc;
+  }
+  const int n = pb->n;
+  const int64_t nnz = pb->nnz, nnzP = h->nnzP;
+  // points per group: A and P/Q values plus the Krylov blocks of one system
+  const int kp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+  const double per_point = 8.0 * (nnz + nnzP) + 8.0 * (double)n * kp * (o.m + 7) + 64.0 * 1024;
+  size_t fr = 0, tot = 0;
+  PMOR_HIP(hipMemGetInfo(&fr, &tot));
+  const int group = (int)std::max(1.0, std::min<double>(npts, 0.6 * (double)fr / per_point));
+  SeqBuffers sb;
+  rc = sb.alloc(group, nnz, nnzP, n);
+  if (rc != PMOR_OK) { spai_release(h); return rc; }
+  int first_bad = PMOR_OK;
+  for (int l0 = 0; l0 < npts && rc == PMOR_OK; l0 += group) {
+    const int cnt = std::min(group, npts - l0);
+    std::vector<SolveItem> it(cnt);
+    std::vector<int> bad(cnt, -1);
+    rc = prepare_points(pb, h, policy, s_list, p_list, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, it.data(),
+                        bad.data());
     if (rc != PMOR_OK) break;
-    rc = block_solve(pb, h, s_list[l], p_list[l], B, ldb, k, X + (int64_t)l * pb->n * ldx, ldx, vopts, stl);
-    if (stl) {
-      stl->fro_resid = pre.fro_resid;
-      stl->t_assemble_ms = pre.t_assemble_ms;
-      stl->t_precond_ms = pre.t_precond_ms;
-      stl->bad_column = pre.bad_column;
+    // solve the points whose preconditioner exists
+    std::vector<SolveItem> ok;
+    for (int t = 0; t < cnt; ++t) {
+      if (bad[t] >= 0) {
+        if (first_bad == PMOR_OK) {
+          first_bad = PMOR_ESINGULAR;
+          set_error("rank-deficient least-squares problem at point " + std::to_string(l0 + t) + ", column " +
+                    std::to_string(bad[t]));
+        }
+        if (stats) stats[l0 + t].t_solve_ms = since();
+        continue;
+      }
+      ok.push_back(it[t]);
+    }
+    const double t_start = since();
+    rc = krylov_batch(pb->ctx, ok.data(), (int)ok.size(), o);
+    if (rc != PMOR_OK) break;
+    for (const SolveItem& x : ok) {
+      if (stats) stats[x.tag].t_solve_ms = t_start + x.t_done_ms;
+      if (first_bad == PMOR_OK && x.status != PMOR_OK) {
+        first_bad = x.status;
+        (void)status_error(first_bad);
+      }
     }
   }
   spai_release(h);
-  return rc;
+  if (rc != PMOR_OK) return rc;
+  return first_bad;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serving: a queue of sequence jobs, admitted under a device-memory budget,
+// whose points share one persistent block GMRES engine
+// ---------------------------------------------------------------------------
+namespace pmor {
+struct ServerJob {
+  int64_t id = 0;
+  pmor_job job{};
+  std::vector<double> s_list, p_list;
+  double t_submit = 0.0;
+  int64_t footprint = 0;
+  pmor_spai* h = nullptr;
+  SeqBuffers sb;
+  std::vector<SolveItem> items;
+  std::vector<int> bad;
+  int remaining = 0;
+  int status = PMOR_OK;
+};
+
+// device bytes a job holds while admitted (an upper bound: the shadow sizes
+// are bounded by |J_j| times the longest column of A)
+static int64_t job_footprint(const pmor_problem* pb, int npts) {
+  const int64_t n = pb->n, nnz = pb->nnz, nnzP = pb->nnz;
+  const int64_t sumI = nnzP * std::max<int64_t>(pb->max_col_len, 1);
+  const int64_t spai = 8 * (3 * nnzP + nnz + 2 * n + 512) + 8 * (n + 1) + 4 * sumI +
+                       4 * (3 * (n + 1) + 3 * nnzP + n) + 4096;
+  return spai + SeqBuffers::estimate(npts, nnz, nnzP, n);
+}
+}  // namespace pmor
+
+struct pmor_server {
+  pmor_ctx* ctx = nullptr;
+  pmor_spai_opts sopts{};
+  pmor_solve_opts vopts{};
+  int k = 1;
+  int64_t budget = 0, engine_bytes = 0, in_use = 0, engine_rows = 0;
+  int max_systems = 64;
+  pmor::Engine* eng = nullptr;
+  pmor::Runner* run = nullptr;
+  std::deque<pmor::ServerJob*> queue;
+  std::map<int64_t, pmor::ServerJob*> jobs;  // admitted
+  std::deque<pmor::SolveItem*> waiting;
+  std::deque<std::pair<int64_t, int>> reports;
+  int64_t next_id = 1;
+};
+
+namespace pmor {
+static void job_finish(pmor_server* sv, ServerJob* J) {
+  spai_release(J->h);
+  J->h = nullptr;
+  sv->in_use -= J->footprint;
+  sv->reports.push_back({J->id, J->status});
+  sv->jobs.erase(J->id);
+  delete J;
+}
+
+// P_1, every point's A(l) and preconditioner; the points enter the waiting line
+static int job_admit(pmor_server* sv, ServerJob* J) {
+  const pmor_job& jb = J->job;
+  const int npts = jb.npts;
+  pmor_stats pre0{};
+  pre0.bad_column = -1;
+  sv->jobs[J->id] = J;
+  int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
+  if (rc == PMOR_OK) rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n);
+  J->items.assign(npts, SolveItem{});
+  J->bad.assign(npts, -1);
+  if (rc == PMOR_OK)
+    rc = prepare_points(jb.pb, J->h, jb.policy, J->s_list.data(), J->p_list.data(), 0, npts, jb.B, jb.ldb, jb.k,
+                        jb.X, jb.ldx, jb.stats, pre0, J->sb, J->items.data(), J->bad.data());
+  if (rc == PMOR_EHIP) return rc;
+  if (rc != PMOR_OK) {  // the job fails as a whole (singular anchor, no memory)
+    J->status = rc;
+    if (jb.stats)
+      for (int l = 0; l < npts; ++l) jb.stats[l].t_solve_ms = sv->run->now_ms() - J->t_submit;
+    job_finish(sv, J);
+    return PMOR_OK;
+  }
+  J->remaining = 0;
+  for (int l = 0; l < npts; ++l) {
+    if (J->bad[l] >= 0) {
+      if (J->status == PMOR_OK) J->status = PMOR_ESINGULAR;
+      if (jb.stats) jb.stats[l].t_solve_ms = sv->run->now_ms() - J->t_submit;
+      continue;
+    }
+    J->items[l].tag = (J->id << 20) | l;
+    sv->waiting.push_back(&J->items[l]);
+    ++J->remaining;
+  }
+  if (J->remaining == 0) job_finish(sv, J);
+  return PMOR_OK;
+}
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_spai_opts* sopts,
+                       const pmor_solve_opts* vopts, pmor_server** out) {
+  if (!ctx || !opts || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (opts->k < 1 || opts->k > PMOR_KMAX) return fail(PMOR_EINVAL, "k must be in 1..16");
+  if (opts->hbm_budget < 0 || opts->engine_rows < 0 || opts->max_systems < 0)
+    return fail(PMOR_EINVAL, "negative server size");
+  pmor_spai_opts so{};
+  so.pattern = PMOR_PAT_A;
+  so.precision = PMOR_F64;
+  so.update = PMOR_UPD_DIAG;
+  if (sopts) so = *sopts;
+  if (so.pattern != PMOR_PAT_A) return fail(PMOR_EINVAL, "the server builds SPAI on the pattern of A");
+  pmor_solve_opts o;
+  PMOR_TRY(solve_opts_of(vopts, &o));
+  PMOR_HIP(hipSetDevice(ctx->device));
+  size_t fr0 = 0, tot = 0;
+  PMOR_HIP(hipMemGetInfo(&fr0, &tot));
+  pmor_server* sv = new pmor_server();
+  sv->ctx = ctx;
+  sv->sopts = so;
+  sv->vopts = o;
+  sv->k = opts->k;
+  sv->budget = opts->hbm_budget > 0 ? opts->hbm_budget : (int64_t)(0.75 * (double)fr0);
+  sv->max_systems = opts->max_systems > 0 ? opts->max_systems : 64;
+  const int kp = opts->k <= 1 ? 1 : opts->k <= 2 ? 2 : opts->k <= 4 ? 4 : opts->k <= 8 ? 8 : 16;
+  sv->engine_rows = opts->engine_rows > 0 ? opts->engine_rows
+                                          : (int64_t)(0.4 * (double)sv->budget / (8.0 * kp * (o.m + 8)));
+  sv->eng = engine_new();
+  int rc = runner_create(ctx, sv->eng, opts->k, o, sv->engine_rows, sv->max_systems, &sv->run);
+  size_t fr1 = 0;
+  if (rc == PMOR_OK) rc = hipMemGetInfo(&fr1, &tot) == hipSuccess ? PMOR_OK : fail(PMOR_EHIP, "hipMemGetInfo");
+  if (rc == PMOR_OK) {
+    sv->engine_bytes = fr0 > fr1 ? (int64_t)(fr0 - fr1) : 0;
+    if (sv->engine_bytes > sv->budget) rc = fail(PMOR_ENOMEM, "the engine alone exceeds the memory budget");
+  }
+  if (rc != PMOR_OK) {
+    pmor_server_destroy(sv);
+    return rc;
+  }
+  *out = sv;
+  return PMOR_OK;
+}
+
+void pmor_server_destroy(pmor_server* sv) {
+  if (!sv) return;
+  (void)hipSetDevice(sv->ctx->device);
+  (void)hipStreamSynchronize(sv->ctx->stream);
+  delete sv->run;
+  engine_destroy(sv->eng);
+  for (auto& kv : sv->jobs) {
+    spai_release(kv.second->h);
+    delete kv.second;
+  }
+  for (ServerJob* J : sv->queue) delete J;
+  delete sv;
+}
+
+int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
+  if (!sv || !job) return fail(PMOR_EINVAL, "NULL argument");
+  PMOR_TRY(sequence_checks(job->pb, job->B, job->ldb, job->k, job->s_list, job->p_list, job->npts, job->X, job->ldx,
+                           job->policy));
+  if (job->pb->ctx != sv->ctx) return fail(PMOR_EINVAL, "problem of another context");
+  if (job->npts >= (1 << 20)) return fail(PMOR_EINVAL, "too many points in one job");
+  if (job->k > sv->k) return fail(PMOR_EADMIT, "job wider than the server's block width");
+  if ((int64_t)((job->pb->n + 15) / 16 * 16) > sv->engine_rows)
+    return fail(PMOR_EADMIT, "system larger than the server's engine");
+  ServerJob* J = new ServerJob();
+  J->job = *job;
+  J->s_list.assign(job->s_list, job->s_list + job->npts);
+  J->p_list.assign(job->p_list, job->p_list + job->npts);
+  J->footprint = job_footprint(job->pb, job->npts);
+  if (J->footprint + sv->engine_bytes > sv->budget) {
+    delete J;
+    return fail(PMOR_EADMIT, "job footprint exceeds the server's memory budget");
+  }
+  J->id = sv->next_id++;
+  J->t_submit = sv->run->now_ms();
+  if (job->stats) std::memset(job->stats, 0, sizeof(pmor_stats) * job->npts);
+  sv->queue.push_back(J);
+  if (job_id) *job_id = J->id;
+  return PMOR_OK;
+}
+
+int pmor_server_step(pmor_server* sv, int64_t* done_ids, int32_t* done_status, int32_t max_done, int32_t* ndone) {
+  if (!sv) return fail(PMOR_EINVAL, "NULL argument");
+  if (ndone) *ndone = 0;
+  PMOR_HIP(hipSetDevice(sv->ctx->device));
+  // jobs, in order, while their footprint fits
+  while (!sv->queue.empty()) {
+    ServerJob* J = sv->queue.front();
+    if (sv->in_use + J->footprint + sv->engine_bytes > sv->budget) break;
+    sv->queue.pop_front();
+    sv->in_use += J->footprint;
+    PMOR_TRY(job_admit(sv, J));
+  }
+  // waiting points into the engine while rows and slots are free
+  std::vector<SolveItem*> batch;
+  while (!sv->waiting.empty()) {
+    batch.push_back(sv->waiting.front());
+    if (!sv->run->can_admit(batch.data(), (int)batch.size())) {
+      batch.pop_back();
+      break;
+    }
+    sv->waiting.pop_front();
+  }
+  if (!batch.empty()) PMOR_TRY(sv->run->admit(batch.data(), (int)batch.size()));
+  // one restart cycle of every system in the engine
+  if (sv->run->busy() > 0) {
+    std::vector<SolveItem*> done;
+    PMOR_TRY(sv->run->cycle(done));
+    for (SolveItem* it : done) {
+      auto f = sv->jobs.find(it->tag >> 20);
+      if (f == sv->jobs.end()) continue;
+      ServerJob* J = f->second;
+      if (it->stats) it->stats->t_solve_ms = it->t_done_ms - J->t_submit;
+      if (J->status == PMOR_OK && it->status != PMOR_OK) J->status = it->status;
+      if (--J->remaining == 0) job_finish(sv, J);
+    }
+  }
+  int nd = 0;
+  while (!sv->reports.empty() && nd < max_done) {
+    if (done_ids) done_ids[nd] = sv->reports.front().first;
+    if (done_status) done_status[nd] = sv->reports.front().second;
+    sv->reports.pop_front();
+    ++nd;
+  }
+  if (ndone) *ndone = nd;
+  return PMOR_OK;
+}
+
+int pmor_server_info(const pmor_server* sv, int32_t* queued, int32_t* admitted, int32_t* running,
+                     int64_t* bytes_in_use) {
+  if (!sv) return fail(PMOR_EINVAL, "NULL argument");
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (admitted) *admitted = (int32_t)sv->jobs.size();
+  if (running) *running = sv->run ? sv->run->busy() : 0;
+  if (bytes_in_use) *bytes_in_use = sv->in_use + sv->engine_bytes;
+  return PMOR_OK;
 }
 
 int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double p2, double* fro_I_minus_A2,
@@ -519,8 +1097,8 @@ int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx
   if (!pb || !aval || !X || !Y) return fail(PMOR_EINVAL, "NULL argument");
   if (k < 1 || k > PMOR_KMAX || ldx < k || ldy < k) return fail(PMOR_EINVAL, "bad k or leading dimension");
   const int pr = prof_start(pb->ctx, PMOR_PROF_SPMM_A);
-  PMOR_TRY(launch_spmm(pb->n, pb->rowptr, pb->col, aval, X, ldx, Y, ldy, k, k, alpha, beta, Y, ldy, nullptr,
-                       pb->ctx->stream, pb->ctx, pr, 3));
+  PMOR_TRY(launch_spmm(pb->n, pb->rowptr, pb->col, aval, X, ldx, Y, ldy, k, alpha, beta, Y, ldy, pb->ctx->stream,
+                       pb->ctx, pr, 3));
   prof_stop(pb->ctx, pr, 12.0 * pb->nnz + 4.0 * (pb->n + 1) + 16.0 * pb->n * k + (beta != 0.0 ? 8.0 * pb->n * k : 0.0), 0);
   PMOR_HIP(hipStreamSynchronize(pb->ctx->stream));
   return PMOR_OK;

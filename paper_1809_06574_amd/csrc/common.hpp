@@ -33,12 +33,12 @@ int hip_fail(hipError_t e, const char* what);
   } while (0)
 
 // ---------------------------------------------------------------------------
-// device state shared by the Krylov kernels of one solve
+// Krylov engine: several independent systems ("segments") advance through the
+// block GMRES cycle in lockstep; every kernel launch covers all of them.
 // ---------------------------------------------------------------------------
 constexpr int KMAX = PMOR_KMAX;
-constexpr int RED_GROUP = 16;   // workgroups per first-level reduction group
-constexpr int MAX_RED_WG = 1024; // row-parallel kernels launch at most this many workgroups
 
+// per-segment device state of the current cycle
 struct DevState {
   int j;            // block steps completed in the current cycle
   int done;         // the cycle stops (converged, breakdown or max steps)
@@ -52,50 +52,51 @@ struct DevState {
   double wscale;    // max column norm of W = A Z of the current step
   double bnorm[KMAX];
   double est[KMAX]; // least-squares residual estimates / bnorm
-  double R1[KMAX * KMAX];    // Cholesky factor, pass 1 (row-major, upper)
-  double R1inv[KMAX * KMAX];
-  double R2[KMAX * KMAX];
-  double R2inv[KMAX * KMAX];
-  int counters[2 * MAX_RED_WG / RED_GROUP + 8];  // last-block reduction arrivals
+  double R1[KMAX * KMAX];     // first Cholesky factor of the step (row-major, upper)
+  double R2inv[KMAX * KMAX];  // inverse of the second factor: V_{j+1} = W1 R2inv
 };
 
-// ---------------------------------------------------------------------------
-// handles
-// ---------------------------------------------------------------------------
-struct Workspace {
-  int n = 0, kp = 0, m = 0;
-  double* V = nullptr;      // (m+1) blocks of n x kp
-  double* W = nullptr;      // n x kp
-  double* Z = nullptr;      // n x kp
-  double* T = nullptr;      // n x kp  (factored preconditioner temp / V Y)
-  double* Bc = nullptr;     // n x kp  compacted right-hand sides
-  double* Xc = nullptr;     // n x kp  compacted solution
-  double* Hbar = nullptr;   // ((m+1) kp) x (m kp), column-major
-  double* Hcol = nullptr;   // 2 x (m+1) kp x kp: CGS coefficients of both passes
-  double* G = nullptr;      // ((m+1) kp) x kp, column-major (E1 S transformed)
-  double* refl = nullptr;   // m kp reflectors, (kp + 2) doubles each
-  double* Y = nullptr;      // (m kp) x kp, column-major
-  double* part = nullptr;   // reduction partials
-  double* part2 = nullptr;  // second-level partials
-  double* partg = nullptr;  // per-workgroup partial Gram matrices (two sweeps)
-  size_t part_len = 0;
-  DevState* st = nullptr;
-  DevState* st_host = nullptr;  // pinned mirror
-  size_t bytes = 0;
+// one system of a batch (device copy read by every kernel)
+struct SegDesc {
+  int n;            // rows
+  int kact;         // active (nonzero) right-hand sides
+  int wg0, G;       // row-kernel workgroups [wg0, wg0 + G) of the logical grid
+  int sp0, spG;     // SpMM workgroups [sp0, sp0 + spG)
+  int pkind;        // preconditioner: 0 none, 1 P, 2 Q P_1 (factored)
+  int k;            // caller's columns
+  int64_t r0;       // first row of the segment in the concatenated blocks
+  const int32_t* arow;
+  const int32_t* acol;
+  const double* aval;
+  const int32_t* prow;
+  const int32_t* pcol;
+  const double* pval;   // P, or P_1 when pkind == 2
+  const double* qval;   // Q when pkind == 2
+  const double* B;
+  int64_t ldb;
+  double* X;
+  int64_t ldx;
+  int cmap[KMAX];   // compacted column c holds caller column cmap[c]
+  int cinv[KMAX];   // caller column c sits in compacted column cinv[c], or -1
+  double bnorm[KMAX];
 };
+
+struct Engine;
 
 // HIP-event timing of one chosen kernel class on the context's stream, with the
 // algorithmic bytes each timed launch has to move (for roofline reports).
 struct ProfRec {
   hipEvent_t a, b;
   double bytes;
-  int tag;       // block step of the launch (skipped steps are discarded)
+  int tag;       // block step of the launch (-1: not a block-step kernel)
   bool valid;
+  int e0, e1;    // per-segment byte entries [e0, e1) of a block-step launch
 };
 struct Profiler {
   int kernel = 0;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> spare;
+  std::vector<std::pair<int, double>> ent;  // (segment, bytes) of block-step launches
   int64_t launches = 0;
   double total_ms = 0.0, total_bytes = 0.0;
 };
@@ -108,6 +109,7 @@ struct pmor_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evs[64] = {};       // step events of the Krylov look-ahead
   pmor::Profiler prof;
+  pmor::Engine* eng = nullptr;   // Krylov engine buffers (grown on demand)
 };
 
 struct pmor_problem {
@@ -126,7 +128,6 @@ struct pmor_problem {
   double* aval = nullptr;      // values of the last assembled point
   double cur_s = 0, cur_p = 0;
   bool have_cur = false;
-  pmor::Workspace ws;
 };
 
 struct pmor_spai {
@@ -171,13 +172,15 @@ int ensure_assembled(pmor_problem* pb, double s, double p);
 // kernel timing: start returns a record index (-1 when kernel class `kid` is not profiled)
 int prof_start(pmor_ctx* c, int kid);
 void prof_stop(pmor_ctx* c, int idx, double bytes, int tag);
-void prof_drop_from(pmor_ctx* c, int first_idx, int tag_limit);
+void prof_stop_seg(pmor_ctx* c, int idx, int tag, int e0);
+// resolve the block-step records from first_idx on: a launch counts the bytes of
+// the segments that still worked at its step (steps_of[seg] > tag)
+void prof_resolve(pmor_ctx* c, int first_idx, const int* steps_of);
 // let kernel `fn` use `bytes` of dynamic LDS (above the 64 KiB default)
 int allow_lds(const void* fn, size_t bytes);
 // device int set by a one-thread kernel (no pageable host source)
 int set_device_int(int* p, int v, hipStream_t st);
-int ensure_workspace(pmor_problem* pb, int kp, int m);
-void free_workspace(pmor::Workspace& ws);
+void engine_destroy(Engine* e);
 
 // Kernel launch that, for a profiled record idx >= 0, lets the dispatch itself
 // timestamp the kernel into the record's events (part bit 1: start, bit 2: stop).
@@ -201,15 +204,61 @@ int build_spai_sets(pmor_spai* h);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
+// U-diag update into caller buffers (no host synchronisation): P_l = diag(q) P_1
+// into pl, q into q, column residuals into rho, the smallest failing column into
+// *dbad (device int, must hold INT_MAX beforehand)
+int launch_update_diag(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int* dbad);
 int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val,
-                const double* X, int64_t ldx, double* Y, int64_t ldy, int kp, int kact,
+                const double* X, int64_t ldx, double* Y, int64_t ldy, int k,
                 double alpha, double beta, const double* Bsrc, int64_t ldb,
-                const DevState* st, hipStream_t stream, pmor_ctx* pc = nullptr, int pidx = -1,
-                int ppart = 3);
+                hipStream_t stream, pmor_ctx* pc = nullptr, int pidx = -1, int ppart = 3);
+// sum of squares of x[0..n) into dev_scratch[0] (dev_scratch: 258 doubles), deterministic
+int sumsq(const double* x, int64_t n, double* dev_scratch, hipStream_t st);
 int fro_norm2(pmor_problem* pb, const double* a, const double* b, int64_t len, int mode,
               double* out_host);
-int krylov_solve(pmor_problem* pb, const pmor_spai* h, const double* B, int64_t ldb, int k,
-                 double* X, int64_t ldx, const pmor_solve_opts& o, pmor_stats* stats);
+// one system of a batched solve
+struct SolveItem {
+  int n;
+  int64_t nnzA, nnzP;
+  const int32_t* arow;
+  const int32_t* acol;
+  const double* aval;
+  int pkind;                  // 0 none, 1 P, 2 Q P_1
+  const int32_t* prow;
+  const int32_t* pcol;
+  const double* pval;
+  const double* qval;
+  const double* B;
+  int64_t ldb;
+  int k;
+  double* X;
+  int64_t ldx;
+  pmor_stats* stats;          // may be NULL
+  int status;                 // out: PMOR_OK / ENOTCONV / EBREAKDOWN / ENAN
+  double t_done_ms;           // out: host time from the engine's start to completion
+  int64_t tag;                // caller's bookkeeping
+};
+
+// A persistent block GMRES engine over a fixed block width: systems are
+// admitted between cycles into free rows and slots; each cycle() advances all
+// admitted systems by one restart cycle in lockstep; finished systems leave
+// with their X written and status set.
+struct Runner {
+  virtual ~Runner() {}
+  // PMOR_EADMIT (nothing admitted) when rows or slots are lacking; the items
+  // must stay valid until cycle() returns them
+  virtual int admit(SolveItem* const* items, int n) = 0;
+  virtual bool can_admit(SolveItem* const* items, int n) const = 0;
+  virtual int cycle(std::vector<SolveItem*>& done) = 0;
+  virtual int busy() const = 0;       // admitted, not yet returned
+  virtual double now_ms() const = 0;  // host time since the engine's start
+};
+Engine* engine_new();
+// an engine of block width pad(k) on buffers E for rows_cap concatenated rows and nslots systems
+int runner_create(pmor_ctx* ctx, Engine* E, int k, const pmor_solve_opts& o, int64_t rows_cap, int nslots,
+                  Runner** out);
+// block GMRES(m) for every item, all items in lockstep (one launch per kernel per step)
+int krylov_batch(pmor_ctx* ctx, SolveItem* items, int nitems, const pmor_solve_opts& o);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -255,52 +304,6 @@ __device__ __forceinline__ double quad_bcast(double x) {
 __device__ __forceinline__ int xcd_swizzle(int id, int G) {
   if ((G & 7) != 0) return id;
   return (id & 7) * (G >> 3) + (id >> 3);
-}
-
-// Deterministic two-level cross-workgroup sum.  Every workgroup of a kernel with
-// G workgroups writes L partial values at part[g*L .. g*L+L) and calls this
-// function (all threads).  The last workgroup of each group of RED_GROUP sums
-// its group in order into part2; the last group reducer sums the groups in order
-// into out[0..L).  Returns true in the single workgroup that produced out.
-__device__ __forceinline__ bool lastblock_sum(double* part, double* part2, int L, int G, int g,
-                                              int* counters, double* out) {
-  __shared__ int s_flag;
-  const int ngroups = (G + RED_GROUP - 1) / RED_GROUP;
-  const int grp = g / RED_GROUP;
-  const int gsize = min(RED_GROUP, G - grp * RED_GROUP);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_flag = (atomicAdd(&counters[grp], 1) == gsize - 1);
-  __syncthreads();
-  if (!s_flag) return false;
-  __threadfence();
-  for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double acc = 0.0;
-    for (int q = 0; q < gsize; ++q) acc += part[(size_t)(grp * RED_GROUP + q) * L + t];
-    if (ngroups == 1) out[t] = acc; else part2[(size_t)grp * L + t] = acc;
-  }
-  if (ngroups == 1) {
-    __syncthreads();
-    if (threadIdx.x == 0) counters[grp] = 0;
-    return true;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    counters[grp] = 0;
-    s_flag = (atomicAdd(&counters[ngroups], 1) == ngroups - 1);
-  }
-  __syncthreads();
-  if (!s_flag) return false;
-  __threadfence();
-  for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double acc = 0.0;
-    for (int q = 0; q < ngroups; ++q) acc += part2[(size_t)q * L + t];
-    out[t] = acc;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) counters[ngroups] = 0;
-  return true;
 }
 
 }  // namespace pmor

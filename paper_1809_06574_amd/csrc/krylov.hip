@@ -1,24 +1,36 @@
 // Block GMRES(m) with right preconditioning (paper, Section 2.1 and the
-// footnote of Section 2.2 on right preconditioning).
+// footnote of Section 2.2 on right preconditioning) for a batch of
+// independent systems ("segments") that advance through the cycle in lockstep:
+// every kernel launch below covers all unfinished segments of the batch.
 //
-// One block step j:   Z = P V_j;  W = A Z;
-//   classical Gram-Schmidt twice against [V_0..V_j] (H accumulates both passes);
-//   thin QR of W by Cholesky QR applied twice: V_{j+1} H_{j+1,j} = W;
-//   Householder update of the QR of the block Hessenberg matrix and the
-//   least-squares residual of every column (convergence test on the device).
-// End of cycle: Y = R^{-1} G;  X += P (V Y);  residual B - A X.
+// One block step j of every segment:
+//   Z = P V_j            V_j = W1 R2^{-1} is formed on the fly from the previous
+//                        step's W1 and written by this SpMM
+//   W = A Z
+//   pass 1:  H1 = [V_0..V_j]^T W and ||W_c||^2
+//   pass 2:  W' = W - V H1;   H2 = V^T W' and Gram(W')
+//   pass 3:  W'' = W' - V H2; R1 = chol(Gram(W') - H2^T H2); W1 = W'' R1^{-1}; Gram(W1)
+//   hess:    R2 = chol(Gram(W1)); H_{j+1,j} = R2 R1; Householder update of the
+//            QR of the block Hessenberg matrix, least-squares residual estimates.
+// Passes 1-2 are classical Gram-Schmidt with one reorthogonalisation; the thin
+// QR W'' = V_{j+1} H_{j+1,j} is Cholesky QR applied twice, its first Gram
+// matrix taken from Gram(W') by the identity W''^T W'' = W'^T W' - H2^T H2
+// (V^T V = I), so a step sweeps V three times.
+// Cycle start: the same pass-2/pass-3/hess kernels with no V blocks give V_0 S = R_0.
+// End of cycle: Y = R^{-1} G;  X += P (V Y);  residual B - A X and its norms.
 //
-// Layout: every n x kp block is row-major (kp contiguous doubles per row);
-// V holds (m+1) such blocks back to back.  The inner products V^T W and the
-// Gram matrices W^T W are tall-skinny contractions over the n rows done with
-// the FP64 MFMA v_mfma_f64_4x4x4f64 for kp in {4, 8, 16}: a wavefront takes 16
-// rows x 4 columns (512 contiguous bytes) per operand tile.  Lane l of such a
-// tile holds row 16c + (l >> 2), column (l & 3); with the instruction's
-// operand layout (A[i][k] at lane 16k + 4b + i, B[k][j] at lane 16k + 4b + j,
-// D[i][j] at lane 16i + 4b + j) the same register serves as A or B operand and
-// the four blocks b sum rows 4k + b.  kp in {1, 2} use one row per lane.
-// Cross-workgroup sums use a fixed two-level order (no floating-point atomics),
-// so every result is reproducible bit for bit.
+// Layout: every n x kp block is row-major (kp contiguous doubles per row); the
+// segments' rows are concatenated (each padded to 16 rows) and V holds (m+1)
+// such concatenated blocks.  The inner products V^T W and the Gram matrices
+// are tall-skinny contractions over the rows done with the FP64 MFMA
+// v_mfma_f64_4x4x4f64 for kp in {4, 8, 16}: a wavefront takes 16 rows x 4
+// columns (512 contiguous bytes) per operand tile.  Lane l of such a tile holds
+// row 16c + (l >> 2), column (l & 3); with the instruction's operand layout
+// (A[i][k] at lane 16k + 4b + i, B[k][j] at lane 16k + 4b + j, D[i][j] at lane
+// 16i + 4b + j) the same register serves as A or B operand and the four blocks b
+// sum rows 4k + b.  kp in {1, 2} use one row per lane.  Cross-workgroup sums
+// use a fixed two-level order per segment (no floating-point atomics): results
+// are reproducible bit for bit and independent of the other segments of a batch.
 #include "common.hpp"
 
 #include <algorithm>
@@ -26,6 +38,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 namespace pmor {
 
@@ -34,75 +47,106 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
 }
 
 struct KArgs {
-  int n;
   int m;
-  int64_t vstride;   // n * kp
+  int nbl;             // V blocks of the sweep; < 0: the segment's st->j (end of cycle)
+  int mode;            // 0: block step, 1: initial QR of the cycle
+  int zero_init;       // update kernels: start from W = 0
+  int ignore_done;     // run even when the segment's cycle is done (end-of-cycle V Y)
+  int ldh;             // rows of the Hessenberg matrix, (m + 1) kp
+  int64_t vstride;     // rows_total * kp
   double* V;
-  double* W;         // work block (input/output of the orthogonalisation)
-  const double* Hsrc;  // coefficients for the update kernels ([basis][rhs], row-major)
-  double hsign;      // the update computes W <- W - hsign * V Hsrc
-  double* Hc1;       // pass-1 coefficients (+ kp squared column norms of W)
-  double* Hc2;       // pass-2 coefficients
-  double* Gram;      // kp x kp Gram matrix
-  double* Hbar;
-  int ldh;
-  double* G;
-  int ldg;
-  double* refl;
-  double* Y;
-  double* part;
-  double* part2;
-  double* partg0;    // per-workgroup partial Gram matrices of the sweep before the first scaling
-  double* partg1;    // ... and of the first scaling sweep
+  double* W;           // work block (input/output of the sweeps)
+  const SegDesc* seg;
+  const int* wtab;     // logical workgroup of the row kernels -> segment (-1: padding)
+  const int* slist;    // segments of the one-workgroup-per-segment kernels
+  const double* Hsrc;  // update coefficients of segment s at Hsrc + s * hsrc_stride ([basis][rhs])
+  int64_t hsrc_stride;
+  double hsign;        // the update computes W <- W - hsign * V Hsrc
+  double* Hc;          // per segment: H1 (+ kp squared norms) at 0, H2 (+ Gram(W')) at hc2off
+  int64_t hcs, hc2off;
+  double* Hbar;        // block Hessenberg (column-major, ldh rows), per segment stride hbs
+  int64_t hbs;
+  double* G;           // transformed E1 S (column-major, ldh rows)
+  int64_t gs;
+  double* refl;        // Householder reflectors of the Hessenberg QR
+  int64_t rfs;
+  double* Y;           // R^{-1} G ([basis][rhs])
+  int64_t ys;
+  double* part;        // per-workgroup partial rows
+  int64_t lstride;
+  double* partg;       // per-workgroup Gram(W1) partials (kp x kp)
   DevState* st;
-  int* hflag;        // host-mapped {steps, done}
-  int nbl_mode;      // 0: st->j + 1 blocks, 1: none (initial QR), 2: st->j blocks (V Y)
-  int out_block;     // k_scale: 0 = V_{st->j + 1}, 1 = V_0
-  int zero_init;     // update kernels: start from W = 0
-  int ignore_done;   // run even when the cycle is marked done (end-of-cycle V Y)
+  int* hinfo;          // host-mapped {j, done, breakdown, nan} per segment
 };
 
-__device__ __forceinline__ int nblocks_of(const KArgs& a) {
-  return a.nbl_mode == 0 ? a.st->j + 1 : (a.nbl_mode == 1 ? 0 : a.st->j);
+// The segment of a row kernel's workgroup; false for padding workgroups and
+// (check_done) segments whose cycle is over.  Uniform over the workgroup.
+struct RowSeg {
+  int s, g, G, n, lg;
+  int64_t r0;
+};
+
+__device__ __forceinline__ bool row_seg(const KArgs& a, bool check_done, RowSeg& r) {
+  const int lg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int s = a.wtab[lg];
+  if (s < 0) return false;
+  if (check_done && a.st[s].done) return false;
+  const SegDesc& d = a.seg[s];
+  r.s = s;
+  r.g = lg - d.wg0;
+  r.G = d.G;
+  r.n = d.n;
+  r.lg = lg;
+  r.r0 = d.r0;
+  return true;
 }
+
+__device__ __forceinline__ int nblocks_of(const KArgs& a, int s) { return a.nbl >= 0 ? a.nbl : a.st[s].j; }
 
 // ---------------------------------------------------------------------------
 // cross-workgroup sums: every row-parallel kernel writes one partial row per
-// workgroup (part[g * L + t]); these kernels add them up in a fixed order (no
-// atomics, no inter-workgroup fences), so results are reproducible bit for bit.
+// workgroup (part[lg * lstride + t]); these kernels add a segment's rows up in a
+// fixed order (no atomics, no inter-workgroup fences).
 // ---------------------------------------------------------------------------
-// out[t] = sum_g part[g L + t]: 8 entries per workgroup, 32 lanes per entry, lane r
-// sums g = r, r + 32, ... in order, then a fixed tree over the lanes.
-__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int L, int G, double* out,
-                                                     const DevState* st, int check_done) {
-  if (check_done && st->done) return;
-  __shared__ double s[8][33];
+// out[s * ostride + ooff + t] = sum_g part[(wg0_s + g) lstride + t]; 8 entries per
+// workgroup, 32 lanes per entry, lane r sums g = r, r + 32, ... in order, then a
+// fixed tree over the lanes.  fixedG > 0: the segment at list position y owns
+// rows [y fixedG, (y + 1) fixedG).
+__global__ __launch_bounds__(256) void k_reduce_seg(const double* __restrict__ part, int64_t lstride, int L,
+                                                    const SegDesc* seg, const int* slist, int fixedG,
+                                                    const DevState* st, int check_done, double* out,
+                                                    int64_t ostride, int64_t ooff) {
+  const int s = slist[blockIdx.y];
+  if (check_done && st[s].done) return;
+  const int wg0 = fixedG > 0 ? (int)blockIdx.y * fixedG : seg[s].wg0;
+  const int G = fixedG > 0 ? fixedG : seg[s].G;
+  const double* p = part + (int64_t)wg0 * lstride;
+  __shared__ double sm[8][33];
   const int e = threadIdx.x & 7, r = threadIdx.x >> 3;
   const int t = blockIdx.x * 8 + e;
-  // four interleaved running sums (g = r + 32 (4q + u)), combined in a fixed order
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (t < L) {
     int g = r;
     for (; g + 96 < G; g += 128) {
-      a0 += part[(size_t)g * L + t];
-      a1 += part[(size_t)(g + 32) * L + t];
-      a2 += part[(size_t)(g + 64) * L + t];
-      a3 += part[(size_t)(g + 96) * L + t];
+      a0 += p[(int64_t)g * lstride + t];
+      a1 += p[(int64_t)(g + 32) * lstride + t];
+      a2 += p[(int64_t)(g + 64) * lstride + t];
+      a3 += p[(int64_t)(g + 96) * lstride + t];
     }
-    for (; g < G; g += 32) a0 += part[(size_t)g * L + t];
+    for (; g < G; g += 32) a0 += p[(int64_t)g * lstride + t];
   }
-  s[e][r] = (a0 + a1) + (a2 + a3);
+  sm[e][r] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int o = 16; o >= 1; o >>= 1) {
-    if (r < o) s[e][r] += s[e][r + o];
+    if (r < o) sm[e][r] += sm[e][r + o];
     __syncthreads();
   }
-  if (r == 0 && t < L) out[t] = s[e][0];
+  if (r == 0 && t < L) out[(int64_t)s * ostride + ooff + t] = sm[e][0];
 }
 
 // the same sum inside one workgroup of 256 threads, for L <= 256 (result in dst)
 __device__ void block_reduce_partials(const double* __restrict__ part, int L, int G, double* dst) {
-  __shared__ double s[256];
+  __shared__ double sr[256];
   int R = 1;
   while (R * 2 * L <= 256) R *= 2;  // lanes per entry
   const int e = threadIdx.x % L, r = threadIdx.x / L;
@@ -117,13 +161,13 @@ __device__ void block_reduce_partials(const double* __restrict__ part, int L, in
     }
     for (; g < G; g += R) a0 += part[(size_t)g * L + e];
   }
-  if (threadIdx.x < R * L) s[r * L + e] = (a0 + a1) + (a2 + a3);
+  if (threadIdx.x < R * L) sr[r * L + e] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   for (int o = R / 2; o >= 1; o >>= 1) {
-    if (r < o) s[r * L + e] += s[(r + o) * L + e];
+    if (r < o) sr[r * L + e] += sr[(r + o) * L + e];
     __syncthreads();
   }
-  if (threadIdx.x < L) dst[threadIdx.x] = s[threadIdx.x];
+  if (threadIdx.x < L) dst[threadIdx.x] = sr[threadIdx.x];
   __syncthreads();
 }
 
@@ -160,101 +204,218 @@ __device__ bool chol_upper(const double* Gm, int kp, int kact, double thr2, doub
   return ok;
 }
 
-// Prologue of the first scaling sweep, run by every workgroup: the Gram matrix
-// of W from the previous sweep's partials, its Cholesky factor R1 and R1^{-1}
-// (in LDS), the scale max_c ||W_c|| of the deficiency test.  Workgroup 0 also
-// stores R1, the scale and the H column block (both passes' coefficients).
-__device__ void scale1_prologue(const KArgs& a, int kp, int G, double* sR, double* sRinv, int* sok) {
-  DevState* st = a.st;
-  __shared__ double sG[KMAX * KMAX];
-  block_reduce_partials(a.partg0, kp * kp, G, sG);
-  const int nbl = nblocks_of(a);
-  if (threadIdx.x == 0) {
-    double mx = 0.0;
-    for (int c = 0; c < st->kact; ++c)
-      mx = fmax(mx, a.nbl_mode == 0 ? a.Hc1[nbl * kp * kp + c] : sG[c * kp + c]);
-    const double ws = sqrt(mx);
-    const double thr = 1e-14 * ws;
-    const bool ok = chol_upper(sG, kp, st->kact, thr * thr, sR, sRinv);
-    *sok = ok ? 1 : 0;
-    if (blockIdx.x == 0) {
-      st->wscale = ws;
-      st->deficient = ok ? 0 : 1;
-      for (int t = 0; t < kp * kp; ++t) st->R1[t] = sR[t];
-    }
-  }
-  if (blockIdx.x == 0 && a.nbl_mode == 0) {
-    const int j = st->j;
-    for (int t = threadIdx.x; t < nbl * kp * kp; t += blockDim.x) {
-      const int b = t / kp, c = t % kp;
-      a.Hbar[b + (int64_t)(j * kp + c) * a.ldh] = a.Hc1[t] + a.Hc2[t];
-    }
+// Pass-3 prologue, run by every workgroup of a segment: the Gram matrix of
+// W'' = W' - V H2 as Gram(W') - H2^T H2 (sH holds +-H2 in LDS, [basis][rhs]),
+// its Cholesky factor R1 and R1^{-1}, and the scale max_c ||W_c|| of the
+// deficiency test (block step: norms of pass 1; cycle start: of W itself).
+// The segment's first workgroup stores R1, the scale, the verdict and, in a
+// block step, the Hessenberg column block H1 + H2.
+template <int KP>
+__device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH, int nbl, double* sRinv) {
+  DevState* st = a.st + s;
+  const double* Hc1 = a.Hc + s * a.hcs;
+  const double* Hc2 = Hc1 + a.hc2off;
+  __shared__ double sG[KP * KP], sR[KP * KP];
+  for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) {
+    const int c1 = t / KP, c2 = t % KP;
+    double x = Hc2[nbl * KP * KP + t];
+    for (int b = 0; b < nbl * KP; ++b) x -= sH[b * KP + c1] * sH[b * KP + c2];
+    sG[t] = x;
   }
   __syncthreads();
-}
-
-// Prologue of the final scaling sweep, run by every workgroup: R2 from the Gram
-// matrix of W R1^{-1}, H_{j+1,j} = R2 R1 (S of the initial block) and the
-// deficiency test |(R2 R1)_cc| <= 1e-14 max ||W_c||.  Workgroup 0 stores the
-// block into the Hessenberg matrix (or G) and the verdict into the state.
-__device__ void scale2_prologue(const KArgs& a, int kp, int G, double* sR2inv, int* sdef) {
-  DevState* st = a.st;
-  __shared__ double sG[KMAX * KMAX], sR2[KMAX * KMAX], sHs[KMAX * KMAX];
-  block_reduce_partials(a.partg1, kp * kp, G, sG);
   if (threadIdx.x == 0) {
     const int kact = st->kact;
-    bool ok = chol_upper(sG, kp, kact, 0.0, sR2, sR2inv) && !st->deficient;
-    for (int r = 0; r < kp; ++r)
-      for (int c = 0; c < kp; ++c) {
-        double x = 0.0;
-        if (r < kact && c < kact)
-          for (int t = r; t <= c; ++t) x += sR2[r * kp + t] * st->R1[t * kp + c];
-        sHs[r * kp + c] = x;
-      }
-    const double thr = 1e-14 * st->wscale;
-    for (int c = 0; c < kact; ++c)
-      if (!(fabs(sHs[c * kp + c]) > thr)) ok = false;
-    if (!ok)
-      for (int t = 0; t < kp * kp; ++t) sHs[t] = 0.0;
-    *sdef = ok ? 0 : 1;
-    if (blockIdx.x == 0) {
-      if (a.nbl_mode == 0) {
-        const int j = st->j;
-        const int r0 = (j + 1) * kp;
-        for (int r = 0; r < kp; ++r)
-          for (int c = 0; c < kp; ++c) a.Hbar[(r0 + r) + (int64_t)(j * kp + c) * a.ldh] = sHs[r * kp + c];
-      } else {
-        for (int r = 0; r < kp; ++r)
-          for (int c = 0; c < kp; ++c) a.G[r + (int64_t)c * a.ldg] = sHs[r * kp + c];
-      }
-      if (!ok) {
-        st->deficient = 1;
-        if (a.nbl_mode != 0) { st->breakdown = 1; st->done = 1; }
-      }
+    double mx = 0.0;
+    for (int c = 0; c < kact; ++c) mx = fmax(mx, a.mode == 0 ? Hc1[nbl * KP * KP + c] : sG[c * KP + c]);
+    const double ws = sqrt(mx);
+    const double thr = 1e-14 * ws;
+    const bool ok = chol_upper(sG, KP, kact, thr * thr, sR, sRinv);
+    if (first) {
+      st->wscale = ws;
+      st->deficient = ok ? 0 : 1;
+      for (int t = 0; t < KP * KP; ++t) st->R1[t] = sR[t];
+    }
+  }
+  if (first && a.mode == 0) {
+    const int j = nbl - 1;
+    double* Hb = a.Hbar + s * a.hbs;
+    for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) {
+      const int b = t / KP, c = t % KP;
+      Hb[b + (int64_t)(j * KP + c) * a.ldh] = Hc1[t] + Hc2[t];
     }
   }
   __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// MFMA path (kp = 4, 8, 16): tiles of 16 rows x 4 columns
-// ---------------------------------------------------------------------------
-template <int KP, int NW, int BPW>
-struct Cfg {
-  static constexpr int NT = KP / 4;
-};
+// update-kernel modes
+constexpr int UPD_PLAIN = 0;  // W <- W - hsign V Hsrc                       (end-of-cycle V Y)
+constexpr int UPD_P2 = 1;     // ... then V^T W and Gram(W)                  (pass 2)
+constexpr int UPD_P3 = 2;     // prologue; W <- (W - V H2) R1^{-1}; Gram(W)  (pass 3)
 
-// pass 1: Hc1 = [V_0..V_j]^T W and the squared column norms of W
+// ---------------------------------------------------------------------------
+// kp = 4, rows split over the wavefronts: each wavefront streams its own 16-row
+// tiles against every V block (at most RS_B), so all of a tile's loads are in
+// flight together and no LDS exchange is needed inside the loop.
+// ---------------------------------------------------------------------------
+constexpr int RS_B = 32;
+constexpr int RS_ROW = RS_B * 16 + 16;
+
+// sum of a per-wavefront row of L values over the NW wavefronts, in order,
+// written as this workgroup's partial row
+template <int NW>
+__device__ __forceinline__ void rs_store_partials(double (*sred)[RS_ROW], int L, double* dst) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < L; t += 64 * NW) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) tot += sred[q][t];
+    dst[t] = tot;
+  }
+}
+
+// pass 1: partial [V_0..V_{nbl-1}]^T W (nbl 16 values) and ||W_c||^2 (4 values)
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
+  RowSeg r;
+  if (!row_seg(a, true, r)) return;
+  const int nbl = a.nbl;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nch = (r.n + 15) >> 4;
+  const double* W = a.W + r.r0 * 4;
+  const double* V = a.V + r.r0 * 4;
+  __shared__ double sred[NW][RS_ROW];
+  double acc[RS_B];
+#pragma unroll
+  for (int i = 0; i < RS_B; ++i) acc[i] = 0.0;
+  double wn = 0.0;
+  for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
+    const int64_t off = ((int64_t)ch << 6) + lane;  // 16 rows x 4 columns = 64 doubles
+    const bool valid = off < (int64_t)r.n * 4;
+    const double wt = valid ? W[off] : 0.0;
+    wn += wt * wt;
+    double v[RS_B];
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i)
+      if (i < nbl) acc[i] = mfma4(v[i], wt, acc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < RS_B; ++i) {
+    double x = acc[i];
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 8, 64);
+    if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
+  }
+  wn += __shfl_xor(wn, 4, 64);
+  wn += __shfl_xor(wn, 8, 64);
+  wn += __shfl_xor(wn, 16, 64);
+  wn += __shfl_xor(wn, 32, 64);
+  if (lane < 4) sred[w][nbl * 16 + lane] = wn;
+  rs_store_partials<NW>(sred, nbl * 16 + 4, a.part + (int64_t)r.lg * a.lstride);
+}
+
+// Lane l of a 16 x 4 tile holds (row 16c + (l >> 2), column l & 3).  Used as the
+// A operand of v_mfma_f64_4x4x4f64 a tile contracts over the rows; a product
+// tile x M (M 4 x 4) needs the rows as the M index instead, i.e. the 4 x 4
+// transpose inside each group of 16 lanes: lane l takes the value of lane
+// ((l & 3) << 4) | (l & 12) | (l >> 4).
+__device__ __forceinline__ double tile_transpose(double x, int lane) {
+  const int src = ((lane & 3) << 4) | (lane & 12) | (lane >> 4);
+  return __shfl(x, src, 64);
+}
+
+// W <- W - hsign V Hsrc over nbl blocks, then by MODE: nothing, pass 2 (V^T W
+// and Gram(W) partials) or pass 3 (W <- W R1^{-1} and Gram(W) partials).  The
+// update and the products run on the FP64 MFMA: the transposed V tile is the A
+// operand, -hsign H the B operand and W the accumulator (D[i][j] at lane
+// 16i + 4b + j is the tile's own layout).
+template <int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
+  constexpr bool DOT = MODE == UPD_P2, GRAM = MODE != UPD_PLAIN, P3 = MODE == UPD_P3;
+  RowSeg r;
+  if (!row_seg(a, !a.ignore_done, r)) return;
+  const int nbl = nblocks_of(a, r.s);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nch = (r.n + 15) >> 4;
+  double* W = a.W + r.r0 * 4;
+  const double* V = a.V + r.r0 * 4;
+  __shared__ double sred[GRAM ? NW : 1][RS_ROW];
+  // B operand of block i: B[k][j] = -hsign H[4i + k][j], k = lane >> 4, j = lane & 3
+  __shared__ double sH[RS_B * 16];
+  __shared__ double sRinv[P3 ? 16 : 1];
+  const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
+  for (int t = threadIdx.x; t < nbl * 16; t += blockDim.x) sH[t] = -a.hsign * Hs[t];
+  __syncthreads();
+  if constexpr (P3) p3_prologue<4>(a, r.s, r.g == 0, sH, nbl, sRinv);
+  const double* hb = sH + (lane >> 4) * 4 + (lane & 3);
+  double rb = 0.0;
+  if constexpr (P3) rb = sRinv[(lane >> 4) * 4 + (lane & 3)];
+  double acc[DOT ? RS_B : 1];
+#pragma unroll
+  for (int i = 0; i < (DOT ? RS_B : 1); ++i) acc[i] = 0.0;
+  double accg = 0.0;
+  const bool write = P3 || nbl > 0 || a.zero_init;
+  for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
+    const int64_t off = ((int64_t)ch << 6) + lane;
+    const bool valid = off < (int64_t)r.n * 4;
+    const double wt = (valid && !a.zero_init) ? W[off] : 0.0;
+    double v[RS_B];
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+    double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
+#pragma unroll
+    for (int i = 0; i < RS_B; i += 2) {
+      if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
+      if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
+    }
+    double wnew = u0 + u1;
+    if (P3) wnew = mfma4(tile_transpose(wnew, lane), rb, 0.0);
+    if (valid && write) W[off] = wnew;
+    if (DOT) {
+#pragma unroll
+      for (int i = 0; i < RS_B; ++i)
+        if (i < nbl) acc[i] = mfma4(v[i], wnew, acc[i]);
+    }
+    if (GRAM) accg = mfma4(wnew, wnew, accg);
+  }
+  if (!GRAM) return;
+  int L = 0;
+  if (DOT) {
+#pragma unroll
+    for (int i = 0; i < RS_B; ++i) {
+      double x = acc[i];
+      x += __shfl_xor(x, 4, 64);
+      x += __shfl_xor(x, 8, 64);
+      if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
+    }
+    L = nbl * 16;
+  }
+  double x = accg;
+  x += __shfl_xor(x, 4, 64);
+  x += __shfl_xor(x, 8, 64);
+  if (((lane >> 2) & 3) == 0) sred[w][L + (lane >> 4) * 4 + (lane & 3)] = x;
+  if (P3) rs_store_partials<NW>(sred, 16, a.partg + (int64_t)r.lg * 16);
+  else rs_store_partials<NW>(sred, L + 16, a.part + (int64_t)r.lg * a.lstride);
+}
+
+// ---------------------------------------------------------------------------
+// kp = 8, 16: the NW wavefronts of a workgroup share the rows of a 16-row tile
+// and split the V blocks (block i on wavefront i mod NW); their partial updates
+// meet in LDS in a fixed order.
+// ---------------------------------------------------------------------------
+// pass 1: partial H1 and the squared column norms of W
 template <int KP, int NW, int BPW>
 __global__ __launch_bounds__(64 * NW) void k_dot_mfma(KArgs a) {
   constexpr int NT = KP / 4;
-  DevState* st = a.st;
-  if (st->done) return;
-  const int nbl = nblocks_of(a);
+  RowSeg r;
+  if (!row_seg(a, true, r)) return;
+  const int nbl = a.nbl;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
   const int c4 = lane & 3, rsub = lane >> 2;
-  const int nch = (a.n + 15) >> 4;
+  const int nch = (r.n + 15) >> 4;
+  const double* W = a.W + r.r0 * KP;
+  const double* V = a.V + r.r0 * KP;
   double acc[BPW][NT][NT];
   double wn[NT];
 #pragma unroll
@@ -265,12 +426,12 @@ __global__ __launch_bounds__(64 * NW) void k_dot_mfma(KArgs a) {
       for (int h2 = 0; h2 < NT; ++h2) acc[bi][h][h2] = 0.0;
 #pragma unroll
   for (int h = 0; h < NT; ++h) wn[h] = 0.0;
-  for (int ch = xcd_swizzle(g, G); ch < nch; ch += G) {
+  for (int ch = r.g; ch < nch; ch += r.G) {
     const int row = (ch << 4) + rsub;
-    const bool valid = row < a.n;
+    const bool valid = row < r.n;
     double wt[NT];
 #pragma unroll
-    for (int h = 0; h < NT; ++h) wt[h] = valid ? a.W[(int64_t)row * KP + 4 * h + c4] : 0.0;
+    for (int h = 0; h < NT; ++h) wt[h] = valid ? W[(int64_t)row * KP + 4 * h + c4] : 0.0;
     if (w == 0) {
 #pragma unroll
       for (int h = 0; h < NT; ++h) wn[h] += wt[h] * wt[h];
@@ -279,7 +440,7 @@ __global__ __launch_bounds__(64 * NW) void k_dot_mfma(KArgs a) {
     for (int bi = 0; bi < BPW; ++bi) {
       const int i = w + NW * bi;
       if (i < nbl) {
-        const double* Vi = a.V + (int64_t)i * a.vstride + (int64_t)row * KP + c4;
+        const double* Vi = V + (int64_t)i * a.vstride + (int64_t)row * KP + c4;
 #pragma unroll
         for (int h = 0; h < NT; ++h) {
           const double v = valid ? Vi[4 * h] : 0.0;
@@ -289,8 +450,7 @@ __global__ __launch_bounds__(64 * NW) void k_dot_mfma(KArgs a) {
       }
     }
   }
-  const int L = nbl * KP * KP + KP;
-  double* mypart = a.part + (int64_t)g * L;
+  double* mypart = a.part + (int64_t)r.lg * a.lstride;
 #pragma unroll
   for (int bi = 0; bi < BPW; ++bi) {
     const int i = w + NW * bi;
@@ -320,26 +480,28 @@ __global__ __launch_bounds__(64 * NW) void k_dot_mfma(KArgs a) {
   }
 }
 
-// W <- W - hsign * [V_0..V_{nbl-1}] Hsrc, optionally followed by
-//   DOT:  Hc2 = [V..]^T W   (pass 2 of the Gram-Schmidt)
-//   GRAM: Gram = W^T W      (pass 3, or the first Cholesky QR sweep)
-// The workgroup's NW wavefronts share the rows of a tile and split the V
-// blocks; their partial updates meet in LDS (fixed order).
-template <int KP, int NW, int BPW, bool DOT, bool GRAM>
+// W <- W - hsign [V_0..V_{nbl-1}] Hsrc, then by MODE (see k_upd4).  Dynamic LDS:
+// hsign Hsrc (nbl_max KP^2) and the exchange buffer [2][NW][64][KP/4].
+template <int KP, int NW, int BPW, int MODE>
 __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
   constexpr int NT = KP / 4;
-  DevState* st = a.st;
-  if (st->done && !a.ignore_done) return;
-  const int nbl = nblocks_of(a);
+  constexpr bool DOT = MODE == UPD_P2, GRAM = MODE != UPD_PLAIN, P3 = MODE == UPD_P3;
+  RowSeg r;
+  if (!row_seg(a, !a.ignore_done, r)) return;
+  const int nbl = nblocks_of(a, r.s);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
   const int c4 = lane & 3, rsub = lane >> 2;
-  const int nch = (a.n + 15) >> 4;
+  const int nch = (r.n + 15) >> 4;
+  double* W = a.W + r.r0 * KP;
+  const double* V = a.V + r.r0 * KP;
   extern __shared__ double sh[];
   double* sH = sh;                          // nbl*KP x KP
   double* su = sh + (size_t)nbl * KP * KP;  // [2][NW][64][NT]
-  for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * a.Hsrc[t];
+  __shared__ double sRinv[P3 ? KP * KP : 1];
+  const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
+  for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * Hs[t];
   __syncthreads();
+  if constexpr (P3) p3_prologue<KP>(a, r.s, r.g == 0, sH, nbl, sRinv);
   double acc[DOT ? BPW : 1][NT][NT];
   double accg[GRAM ? NT : 1][NT];
 #pragma unroll
@@ -352,14 +514,15 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
   for (int h = 0; h < (GRAM ? NT : 1); ++h)
 #pragma unroll
     for (int h2 = 0; h2 < NT; ++h2) accg[h][h2] = 0.0;
+  const bool write = P3 || nbl > 0 || a.zero_init;
   int buf = 0;
-  for (int ch = xcd_swizzle(g, G); ch < nch; ch += G) {
+  for (int ch = r.g; ch < nch; ch += r.G) {
     const int row = (ch << 4) + rsub;
-    const bool valid = row < a.n;
+    const bool valid = row < r.n;
     double wt[NT], u[NT];
 #pragma unroll
     for (int h = 0; h < NT; ++h) {
-      wt[h] = (valid && !a.zero_init) ? a.W[(int64_t)row * KP + 4 * h + c4] : 0.0;
+      wt[h] = (valid && !a.zero_init) ? W[(int64_t)row * KP + 4 * h + c4] : 0.0;
       u[h] = 0.0;
     }
     double vt[BPW][NT];
@@ -367,7 +530,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
     for (int bi = 0; bi < BPW; ++bi) {
       const int i = w + NW * bi;
       if (i < nbl) {
-        const double* Vi = a.V + (int64_t)i * a.vstride + (int64_t)row * KP + c4;
+        const double* Vi = V + (int64_t)i * a.vstride + (int64_t)row * KP + c4;
 #pragma unroll
         for (int h = 0; h < NT; ++h) vt[bi][h] = valid ? Vi[4 * h] : 0.0;
         const double* Hi = sH + (size_t)i * KP * KP;
@@ -410,9 +573,34 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
 #pragma unroll
       for (int h = 0; h < NT; ++h) wnew[h] = wt[h] - u[h];
     }
-    if (w == 0 && valid && (nbl > 0 || a.zero_init)) {
+    if (P3 && w == 0) {
+      // W1 = W'' R1^{-1}: column 4 h2 + c4 of the row from the row's KP values
+      double o[NT];
 #pragma unroll
-      for (int h = 0; h < NT; ++h) a.W[(int64_t)row * KP + 4 * h + c4] = wnew[h];
+      for (int h2 = 0; h2 < NT; ++h2) o[h2] = 0.0;
+#pragma unroll
+      for (int h = 0; h < NT; ++h) {
+        const double x0 = quad_bcast<0>(wnew[h]);
+        const double x1 = quad_bcast<1>(wnew[h]);
+        const double x2 = quad_bcast<2>(wnew[h]);
+        const double x3 = quad_bcast<3>(wnew[h]);
+#pragma unroll
+        for (int h2 = 0; h2 < NT; ++h2) {
+          const int cc = 4 * h2 + c4;
+          double x = o[h2];
+          x = fma(x0, sRinv[(4 * h + 0) * KP + cc], x);
+          x = fma(x1, sRinv[(4 * h + 1) * KP + cc], x);
+          x = fma(x2, sRinv[(4 * h + 2) * KP + cc], x);
+          x = fma(x3, sRinv[(4 * h + 3) * KP + cc], x);
+          o[h2] = x;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NT; ++h) wnew[h] = o[h];
+    }
+    if (w == 0 && valid && write) {
+#pragma unroll
+      for (int h = 0; h < NT; ++h) W[(int64_t)row * KP + 4 * h + c4] = wnew[h];
     }
     if (DOT) {
 #pragma unroll
@@ -429,9 +617,9 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
         for (int h2 = 0; h2 < NT; ++h2) accg[h][h2] = mfma4(wnew[h], wnew[h2], accg[h][h2]);
     }
   }
-  if (!DOT && !GRAM) return;
-  const int L = DOT ? nbl * KP * KP : KP * KP;
-  double* mypart = a.part + (int64_t)g * L;
+  if (!GRAM) return;
+  double* mypart = P3 ? a.partg + (int64_t)r.lg * KP * KP : a.part + (int64_t)r.lg * a.lstride;
+  const int goff = P3 ? 0 : nbl * KP * KP;
   if (DOT) {
 #pragma unroll
     for (int bi = 0; bi < BPW; ++bi) {
@@ -447,253 +635,32 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
             mypart[(i * KP + 4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
         }
     }
-  } else {
-    if (w == 0) {
-      double* gp = a.partg0 + (int64_t)g * KP * KP;
-#pragma unroll
-      for (int h = 0; h < NT; ++h)
-#pragma unroll
-        for (int h2 = 0; h2 < NT; ++h2) {
-          double x = accg[h][h2];
-          x += __shfl_xor(x, 4, 64);
-          x += __shfl_xor(x, 8, 64);
-          if (((lane >> 2) & 3) == 0) gp[(4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
-        }
-    }
   }
-}
-
-// W <- W * M (M = a kp x kp upper-triangular inverse kept in DevState),
-// optionally with its Gram matrix; writes either W in place or a V block.
-template <int KP, int NW, bool GRAM>
-__global__ __launch_bounds__(64 * NW) void k_scale_mfma(KArgs a, int Gprev) {
-  constexpr int NT = KP / 4;
-  DevState* st = a.st;
-  if (st->done) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int c4 = lane & 3, rsub = lane >> 2;
-  const int nch = (a.n + 15) >> 4;
-  __shared__ double sR[KMAX * KMAX], sM[KMAX * KMAX];
-  __shared__ int sflag;
-  if (GRAM) scale1_prologue(a, KP, Gprev, sR, sM, &sflag);
-  else scale2_prologue(a, KP, Gprev, sM, &sflag);
-  double* out;
-  if (GRAM) out = a.W;
-  else out = a.V + (int64_t)(a.out_block == 1 ? 0 : st->j + 1) * a.vstride;
-  const bool zero = (!GRAM) && sflag;
-  double accg[GRAM ? NT : 1][NT];
+  if (w == 0) {
 #pragma unroll
-  for (int h = 0; h < (GRAM ? NT : 1); ++h)
-#pragma unroll
-    for (int h2 = 0; h2 < NT; ++h2) accg[h][h2] = 0.0;
-  const int stride = G * NW;
-  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += stride) {
-    const int row = (ch << 4) + rsub;
-    const bool valid = row < a.n;
-    double wt[NT], o[NT];
-#pragma unroll
-    for (int h = 0; h < NT; ++h) {
-      wt[h] = valid ? a.W[(int64_t)row * KP + 4 * h + c4] : 0.0;
-      o[h] = 0.0;
-    }
-#pragma unroll
-    for (int h = 0; h < NT; ++h) {
-      const double v0 = quad_bcast<0>(wt[h]);
-      const double v1 = quad_bcast<1>(wt[h]);
-      const double v2 = quad_bcast<2>(wt[h]);
-      const double v3 = quad_bcast<3>(wt[h]);
+    for (int h = 0; h < NT; ++h)
 #pragma unroll
       for (int h2 = 0; h2 < NT; ++h2) {
-        const int cc = 4 * h2 + c4;
-        double x = o[h2];
-        x = fma(v0, sM[(4 * h + 0) * KP + cc], x);
-        x = fma(v1, sM[(4 * h + 1) * KP + cc], x);
-        x = fma(v2, sM[(4 * h + 2) * KP + cc], x);
-        x = fma(v3, sM[(4 * h + 3) * KP + cc], x);
-        o[h2] = x;
+        double x = accg[h][h2];
+        x += __shfl_xor(x, 4, 64);
+        x += __shfl_xor(x, 8, 64);
+        if (((lane >> 2) & 3) == 0) mypart[goff + (4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
       }
-    }
-    if (zero) {
-#pragma unroll
-      for (int h = 0; h < NT; ++h) o[h] = 0.0;
-    }
-    if (valid) {
-#pragma unroll
-      for (int h = 0; h < NT; ++h) out[(int64_t)row * KP + 4 * h + c4] = o[h];
-    }
-    if (GRAM) {
-#pragma unroll
-      for (int h = 0; h < NT; ++h)
-#pragma unroll
-        for (int h2 = 0; h2 < NT; ++h2) accg[h][h2] = mfma4(o[h], o[h2], accg[h][h2]);
-    }
-  }
-  if (!GRAM) return;
-  __shared__ double sg[NW][KP * KP];
-#pragma unroll
-  for (int h = 0; h < NT; ++h)
-#pragma unroll
-    for (int h2 = 0; h2 < NT; ++h2) {
-      double x = accg[h][h2];
-      x += __shfl_xor(x, 4, 64);
-      x += __shfl_xor(x, 8, 64);
-      if (((lane >> 2) & 3) == 0) sg[w][(4 * h + (lane >> 4)) * KP + 4 * h2 + (lane & 3)] = x;
-    }
-  __syncthreads();
-  const int L = KP * KP;
-  for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double tot = 0.0;
-    for (int q = 0; q < NW; ++q) tot += sg[q][t];
-    a.partg1[(int64_t)g * L + t] = tot;
   }
 }
 
 // ---------------------------------------------------------------------------
-// kp = 4, rows split over the wavefronts: each wavefront streams its own 16-row
-// tiles against every V block (at most RS_B), so all of a tile's loads are in
-// flight together and no LDS exchange is needed inside the loop.
-// ---------------------------------------------------------------------------
-constexpr int RS_B = 32;
-
-// sum of a per-wavefront row of L values over the NW wavefronts, in order,
-// written as this workgroup's partial row
-template <int NW>
-__device__ __forceinline__ void rs_store_partials(double (*sred)[RS_B * 16 + 4], int L, double* dst) {
-  __syncthreads();
-  for (int t = threadIdx.x; t < L; t += 64 * NW) {
-    double tot = 0.0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) tot += sred[q][t];
-    dst[t] = tot;
-  }
-}
-
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
-  DevState* st = a.st;
-  if (st->done) return;
-  const int nbl = nblocks_of(a);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int nch = (a.n + 15) >> 4;
-  __shared__ double sred[NW][RS_B * 16 + 4];
-  double acc[RS_B];
-#pragma unroll
-  for (int i = 0; i < RS_B; ++i) acc[i] = 0.0;
-  double wn = 0.0;
-  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += G * NW) {
-    const int64_t off = ((int64_t)ch << 6) + lane;  // 16 rows x 4 columns = 64 doubles
-    const bool valid = off < (int64_t)a.n * 4;
-    const double wt = valid ? a.W[off] : 0.0;
-    wn += wt * wt;
-    double v[RS_B];
-#pragma unroll
-    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? a.V[(int64_t)i * a.vstride + off] : 0.0;
-#pragma unroll
-    for (int i = 0; i < RS_B; ++i)
-      if (i < nbl) acc[i] = mfma4(v[i], wt, acc[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < RS_B; ++i) {
-    double x = acc[i];
-    x += __shfl_xor(x, 4, 64);
-    x += __shfl_xor(x, 8, 64);
-    if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
-  }
-  wn += __shfl_xor(wn, 4, 64);
-  wn += __shfl_xor(wn, 8, 64);
-  wn += __shfl_xor(wn, 16, 64);
-  wn += __shfl_xor(wn, 32, 64);
-  if (lane < 4) sred[w][nbl * 16 + lane] = wn;
-  const int L = nbl * 16 + 4;
-  rs_store_partials<NW>(sred, L, a.part + (int64_t)g * L);
-}
-
-// Lane l of a 16 x 4 tile holds (row 16c + (l >> 2), column l & 3).  Used as the
-// A operand of v_mfma_f64_4x4x4f64 a tile contracts over the rows; the update
-// W - V H needs the rows as the M index instead, i.e. the 4 x 4 transpose inside
-// each group of 16 lanes: lane l takes the value of lane ((l & 3) << 4) | (l & 12) | (l >> 4).
-__device__ __forceinline__ double tile_transpose(double x, int lane) {
-  const int src = ((lane & 3) << 4) | (lane & 12) | (lane >> 4);
-  return __shfl(x, src, 64);
-}
-
-// W <- W - hsign V Hsrc for all blocks, then (DOT) V^T W or (GRAM) W^T W.  Both
-// the update and the inner products run on the FP64 MFMA: for the update the
-// transposed V tile is the A operand, -hsign H the B operand and W the
-// accumulator (D[i][j] at lane 16i + 4b + j is the tile's own layout).
-template <int NW, bool DOT, bool GRAM>
-__global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
-  DevState* st = a.st;
-  if (st->done && !a.ignore_done) return;
-  const int nbl = nblocks_of(a);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int nch = (a.n + 15) >> 4;
-  __shared__ double sred[(DOT || GRAM) ? NW : 1][RS_B * 16 + 4];
-  // B operand of block i: B[k][j] = -hsign H[4i + k][j], k = lane >> 4, j = lane & 3
-  __shared__ double sH[RS_B * 16];
-  for (int t = threadIdx.x; t < nbl * 16; t += blockDim.x) sH[t] = -a.hsign * a.Hsrc[t];
-  __syncthreads();
-  const double* hb = sH + (lane >> 4) * 4 + (lane & 3);
-  double acc[DOT ? RS_B : 1];
-#pragma unroll
-  for (int i = 0; i < (DOT ? RS_B : 1); ++i) acc[i] = 0.0;
-  double accg = 0.0;
-  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += G * NW) {
-    const int64_t off = ((int64_t)ch << 6) + lane;
-    const bool valid = off < (int64_t)a.n * 4;
-    const double wt = (valid && !a.zero_init) ? a.W[off] : 0.0;
-    double v[RS_B];
-#pragma unroll
-    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? a.V[(int64_t)i * a.vstride + off] : 0.0;
-    double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
-#pragma unroll
-    for (int i = 0; i < RS_B; i += 2) {
-      if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
-      if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
-    }
-    const double wnew = u0 + u1;
-    if (valid && (nbl > 0 || a.zero_init)) a.W[off] = wnew;
-    if (DOT) {
-#pragma unroll
-      for (int i = 0; i < RS_B; ++i)
-        if (i < nbl) acc[i] = mfma4(v[i], wnew, acc[i]);
-    }
-    if (GRAM) accg = mfma4(wnew, wnew, accg);
-  }
-  if (DOT) {
-#pragma unroll
-    for (int i = 0; i < RS_B; ++i) {
-      double x = acc[i];
-      x += __shfl_xor(x, 4, 64);
-      x += __shfl_xor(x, 8, 64);
-      if (i < nbl && ((lane >> 2) & 3) == 0) sred[w][i * 16 + (lane >> 4) * 4 + (lane & 3)] = x;
-    }
-    const int L = nbl * 16;
-    rs_store_partials<NW>(sred, L, a.part + (int64_t)g * L);
-  }
-  if (GRAM) {
-    double x = accg;
-    x += __shfl_xor(x, 4, 64);
-    x += __shfl_xor(x, 8, 64);
-    if (((lane >> 2) & 3) == 0) sred[w][(lane >> 4) * 4 + (lane & 3)] = x;
-    rs_store_partials<NW>(sred, 16, a.partg0 + (int64_t)g * 16);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// row-per-lane path (kp = 1, 2)
+// row-per-lane path (kp = 1, 2): wavefronts split the V blocks of 64-row tiles
 // ---------------------------------------------------------------------------
 template <int KP, int NW, int BPW>
 __global__ __launch_bounds__(64 * NW) void k_dot_row(KArgs a) {
-  DevState* st = a.st;
-  if (st->done) return;
-  const int nbl = nblocks_of(a);
+  RowSeg r;
+  if (!row_seg(a, true, r)) return;
+  const int nbl = a.nbl;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int nch = (a.n + 63) >> 6;
+  const int nch = (r.n + 63) >> 6;
+  const double* W = a.W + r.r0 * KP;
+  const double* V = a.V + r.r0 * KP;
   double acc[BPW][KP][KP];
   double wn[KP];
 #pragma unroll
@@ -704,12 +671,12 @@ __global__ __launch_bounds__(64 * NW) void k_dot_row(KArgs a) {
       for (int y = 0; y < KP; ++y) acc[bi][x][y] = 0.0;
 #pragma unroll
   for (int x = 0; x < KP; ++x) wn[x] = 0.0;
-  for (int ch = xcd_swizzle(g, G); ch < nch; ch += G) {
+  for (int ch = r.g; ch < nch; ch += r.G) {
     const int row = (ch << 6) + lane;
-    const bool valid = row < a.n;
+    const bool valid = row < r.n;
     double wt[KP];
 #pragma unroll
-    for (int x = 0; x < KP; ++x) wt[x] = valid ? a.W[(int64_t)row * KP + x] : 0.0;
+    for (int x = 0; x < KP; ++x) wt[x] = valid ? W[(int64_t)row * KP + x] : 0.0;
     if (w == 0) {
 #pragma unroll
       for (int x = 0; x < KP; ++x) wn[x] += wt[x] * wt[x];
@@ -720,15 +687,14 @@ __global__ __launch_bounds__(64 * NW) void k_dot_row(KArgs a) {
       if (i < nbl) {
 #pragma unroll
         for (int x = 0; x < KP; ++x) {
-          const double v = valid ? a.V[(int64_t)i * a.vstride + (int64_t)row * KP + x] : 0.0;
+          const double v = valid ? V[(int64_t)i * a.vstride + (int64_t)row * KP + x] : 0.0;
 #pragma unroll
           for (int y = 0; y < KP; ++y) acc[bi][x][y] += v * wt[y];
         }
       }
     }
   }
-  const int L = nbl * KP * KP + KP;
-  double* mypart = a.part + (int64_t)g * L;
+  double* mypart = a.part + (int64_t)r.lg * a.lstride;
 #pragma unroll
   for (int bi = 0; bi < BPW; ++bi) {
     const int i = w + NW * bi;
@@ -736,32 +702,37 @@ __global__ __launch_bounds__(64 * NW) void k_dot_row(KArgs a) {
     for (int x = 0; x < KP; ++x)
 #pragma unroll
       for (int y = 0; y < KP; ++y) {
-        const double s = wave_sum(acc[bi][x][y]);
-        if (i < nbl && lane == 0) mypart[(i * KP + x) * KP + y] = s;
+        const double sum = wave_sum(acc[bi][x][y]);
+        if (i < nbl && lane == 0) mypart[(i * KP + x) * KP + y] = sum;
       }
   }
   if (w == 0) {
 #pragma unroll
     for (int x = 0; x < KP; ++x) {
-      const double s = wave_sum(wn[x]);
-      if (lane == 0) mypart[nbl * KP * KP + x] = s;
+      const double sum = wave_sum(wn[x]);
+      if (lane == 0) mypart[nbl * KP * KP + x] = sum;
     }
   }
 }
 
-template <int KP, int NW, int BPW, bool DOT, bool GRAM>
+template <int KP, int NW, int BPW, int MODE>
 __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
-  DevState* st = a.st;
-  if (st->done && !a.ignore_done) return;
-  const int nbl = nblocks_of(a);
+  constexpr bool DOT = MODE == UPD_P2, GRAM = MODE != UPD_PLAIN, P3 = MODE == UPD_P3;
+  RowSeg r;
+  if (!row_seg(a, !a.ignore_done, r)) return;
+  const int nbl = nblocks_of(a, r.s);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int nch = (a.n + 63) >> 6;
+  const int nch = (r.n + 63) >> 6;
+  double* W = a.W + r.r0 * KP;
+  const double* V = a.V + r.r0 * KP;
   extern __shared__ double sh[];
   double* sH = sh;
   double* su = sh + (size_t)nbl * KP * KP;  // [2][NW][64][KP]
-  for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * a.Hsrc[t];
+  __shared__ double sRinv[P3 ? KP * KP : 1];
+  const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
+  for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * Hs[t];
   __syncthreads();
+  if constexpr (P3) p3_prologue<KP>(a, r.s, r.g == 0, sH, nbl, sRinv);
   double acc[DOT ? BPW : 1][KP][KP];
   double accg[GRAM ? KP : 1][KP];
 #pragma unroll
@@ -774,14 +745,15 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
   for (int x = 0; x < (GRAM ? KP : 1); ++x)
 #pragma unroll
     for (int y = 0; y < KP; ++y) accg[x][y] = 0.0;
+  const bool write = P3 || nbl > 0 || a.zero_init;
   int buf = 0;
-  for (int ch = xcd_swizzle(g, G); ch < nch; ch += G) {
+  for (int ch = r.g; ch < nch; ch += r.G) {
     const int row = (ch << 6) + lane;
-    const bool valid = row < a.n;
+    const bool valid = row < r.n;
     double wt[KP], u[KP];
 #pragma unroll
     for (int x = 0; x < KP; ++x) {
-      wt[x] = (valid && !a.zero_init) ? a.W[(int64_t)row * KP + x] : 0.0;
+      wt[x] = (valid && !a.zero_init) ? W[(int64_t)row * KP + x] : 0.0;
       u[x] = 0.0;
     }
     double vt[BPW][KP];
@@ -789,7 +761,8 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
     for (int bi = 0; bi < BPW; ++bi) {
       const int i = w + NW * bi;
 #pragma unroll
-      for (int x = 0; x < KP; ++x) vt[bi][x] = (i < nbl && valid) ? a.V[(int64_t)i * a.vstride + (int64_t)row * KP + x] : 0.0;
+      for (int x = 0; x < KP; ++x)
+        vt[bi][x] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + (int64_t)row * KP + x] : 0.0;
       if (i < nbl) {
         const double* Hi = sH + (size_t)i * KP * KP;
 #pragma unroll
@@ -815,9 +788,21 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
 #pragma unroll
       for (int x = 0; x < KP; ++x) wnew[x] = wt[x] - u[x];
     }
-    if (w == 0 && valid && (nbl > 0 || a.zero_init)) {
+    if (P3) {
+      double o[KP];
 #pragma unroll
-      for (int x = 0; x < KP; ++x) a.W[(int64_t)row * KP + x] = wnew[x];
+      for (int y = 0; y < KP; ++y) {
+        double t = 0.0;
+#pragma unroll
+        for (int x = 0; x < KP; ++x) t = fma(wnew[x], sRinv[x * KP + y], t);
+        o[y] = t;
+      }
+#pragma unroll
+      for (int y = 0; y < KP; ++y) wnew[y] = o[y];
+    }
+    if (w == 0 && valid && write) {
+#pragma unroll
+      for (int x = 0; x < KP; ++x) W[(int64_t)row * KP + x] = wnew[x];
     }
     if (DOT) {
 #pragma unroll
@@ -834,9 +819,9 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
         for (int y = 0; y < KP; ++y) accg[x][y] += wnew[x] * wnew[y];
     }
   }
-  if (!DOT && !GRAM) return;
-  const int L = DOT ? nbl * KP * KP : KP * KP;
-  double* mypart = a.part + (int64_t)g * L;
+  if (!GRAM) return;
+  double* mypart = P3 ? a.partg + (int64_t)r.lg * KP * KP : a.part + (int64_t)r.lg * a.lstride;
+  const int goff = P3 ? 0 : nbl * KP * KP;
   if (DOT) {
 #pragma unroll
     for (int bi = 0; bi < BPW; ++bi) {
@@ -845,119 +830,99 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
       for (int x = 0; x < KP; ++x)
 #pragma unroll
         for (int y = 0; y < KP; ++y) {
-          const double s = wave_sum(acc[bi][x][y]);
-          if (i < nbl && lane == 0) mypart[(i * KP + x) * KP + y] = s;
-        }
-    }
-  } else {
-    if (w == 0) {
-      double* gp = a.partg0 + (int64_t)g * KP * KP;
-#pragma unroll
-      for (int x = 0; x < KP; ++x)
-#pragma unroll
-        for (int y = 0; y < KP; ++y) {
-          const double s = wave_sum(accg[x][y]);
-          if (lane == 0) gp[x * KP + y] = s;
+          const double sum = wave_sum(acc[bi][x][y]);
+          if (i < nbl && lane == 0) mypart[(i * KP + x) * KP + y] = sum;
         }
     }
   }
-}
-
-template <int KP, int NW, bool GRAM>
-__global__ __launch_bounds__(64 * NW) void k_scale_row(KArgs a, int Gprev) {
-  DevState* st = a.st;
-  if (st->done) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int G = gridDim.x, g = blockIdx.x;
-  const int nch = (a.n + 63) >> 6;
-  __shared__ double sR[KMAX * KMAX], M[KMAX * KMAX];
-  __shared__ int sflag;
-  if (GRAM) scale1_prologue(a, KP, Gprev, sR, M, &sflag);
-  else scale2_prologue(a, KP, Gprev, M, &sflag);
-  double* out;
-  if (GRAM) out = a.W;
-  else out = a.V + (int64_t)(a.out_block == 1 ? 0 : st->j + 1) * a.vstride;
-  const bool zero = (!GRAM) && sflag;
-  double Mr[KP][KP];
-#pragma unroll
-  for (int x = 0; x < KP; ++x)
-#pragma unroll
-    for (int y = 0; y < KP; ++y) Mr[x][y] = M[x * KP + y];
-  double accg[GRAM ? KP : 1][KP];
-#pragma unroll
-  for (int x = 0; x < (GRAM ? KP : 1); ++x)
-#pragma unroll
-    for (int y = 0; y < KP; ++y) accg[x][y] = 0.0;
-  for (int ch = xcd_swizzle(g, G) * NW + w; ch < nch; ch += G * NW) {
-    const int row = (ch << 6) + lane;
-    const bool valid = row < a.n;
-    double wt[KP], o[KP];
-#pragma unroll
-    for (int x = 0; x < KP; ++x) { wt[x] = valid ? a.W[(int64_t)row * KP + x] : 0.0; o[x] = 0.0; }
+  if (w == 0) {
 #pragma unroll
     for (int x = 0; x < KP; ++x)
 #pragma unroll
-      for (int y = 0; y < KP; ++y) o[y] = fma(wt[x], Mr[x][y], o[y]);
-    if (zero) {
-#pragma unroll
-      for (int x = 0; x < KP; ++x) o[x] = 0.0;
-    }
-    if (valid) {
-#pragma unroll
-      for (int x = 0; x < KP; ++x) out[(int64_t)row * KP + x] = o[x];
-    }
-    if (GRAM) {
-#pragma unroll
-      for (int x = 0; x < KP; ++x)
-#pragma unroll
-        for (int y = 0; y < KP; ++y) accg[x][y] += o[x] * o[y];
-    }
-  }
-  if (!GRAM) return;
-  __shared__ double sg[NW][KP * KP];
-#pragma unroll
-  for (int x = 0; x < KP; ++x)
-#pragma unroll
-    for (int y = 0; y < KP; ++y) {
-      const double s = wave_sum(accg[x][y]);
-      if (lane == 0) sg[w][x * KP + y] = s;
-    }
-  __syncthreads();
-  const int L = KP * KP;
-  for (int t = threadIdx.x; t < L; t += blockDim.x) {
-    double tot = 0.0;
-    for (int q = 0; q < NW; ++q) tot += sg[q][t];
-    a.partg1[(int64_t)g * L + t] = tot;
+      for (int y = 0; y < KP; ++y) {
+        const double sum = wave_sum(accg[x][y]);
+        if (lane == 0) mypart[goff + x * KP + y] = sum;
+      }
   }
 }
 
 // ---------------------------------------------------------------------------
-// single-workgroup kernels: Cholesky steps, Hessenberg least squares, Y solve
+// one-workgroup-per-segment kernels: second Cholesky factor + Hessenberg least
+// squares, Y solve, cycle and state initialisation
 // ---------------------------------------------------------------------------
-// Householder update of the QR factorisation of the block Hessenberg matrix
-// for the new block column j, the transformed right-hand side G, and the
-// least-squares residual estimate of every column.  One wavefront.
+// Prologue: Gram(W1) from the pass-3 partials, R2 = chol(Gram(W1)), the
+// subdiagonal block H_{j+1,j} = R2 R1 and the deficiency test
+// |(R2 R1)_cc| <= 1e-14 max_c ||W_c||; R2^{-1} (zero when deficient) is kept for
+// the next step's V_{j+1} = W1 R2^{-1}.  Cycle start (mode 1): the block is S of
+// R_0 = V_0 S and goes to G.  Block step: Householder update of the QR
+// factorisation of the block Hessenberg matrix for the new block column j, the
+// transformed right-hand side G, and the least-squares residual of every column.
 template <int KP>
-__global__ __launch_bounds__(64) void k_hess(KArgs a) {
-  DevState* st = a.st;
+__global__ __launch_bounds__(256) void k_hess(KArgs a) {
+  const int s = a.slist[blockIdx.x];
+  DevState* st = a.st + s;
   if (st->done) return;
-  extern __shared__ double sh[];
+  const SegDesc& d = a.seg[s];
+  __shared__ double sG1[KP * KP], sR2[KP * KP], sR2inv[KP * KP], sHs[KP * KP];
+  __shared__ int sdef;
+  block_reduce_partials(a.partg + (int64_t)d.wg0 * KP * KP, KP * KP, d.G, sG1);
   const int j = st->j, m = st->m, kact = st->kact;
-  const int ldh = a.ldh;
-  const int q0 = j * KP, nr = (j + 2) * KP;
-  constexpr int RL = KP + 2;          // stored reflector: tau, v_1..v_KP, (unused)
-  double* col = sh;                   // [KP][ldh]
-  double* rf = col + (size_t)KP * ldh;  // [q0 + KP][RL]
-  double* gw = rf + (size_t)(q0 + KP) * RL;  // [KP][2 KP] window of G
   const int lane = threadIdx.x;
-  for (int t = lane; t < KP * nr; t += 64) {
-    const int c = t / nr, r = t % nr;
-    col[(size_t)c * ldh + r] = a.Hbar[r + (int64_t)(q0 + c) * ldh];
+  if (lane == 0) {
+    bool ok = chol_upper(sG1, KP, kact, 0.0, sR2, sR2inv) && !st->deficient;
+    for (int r = 0; r < KP; ++r)
+      for (int c = 0; c < KP; ++c) {
+        double x = 0.0;
+        if (r < kact && c < kact)
+          for (int t = r; t <= c; ++t) x += sR2[r * KP + t] * st->R1[t * KP + c];
+        sHs[r * KP + c] = x;
+      }
+    const double thr = 1e-14 * st->wscale;
+    for (int c = 0; c < kact; ++c)
+      if (!(fabs(sHs[c * KP + c]) > thr)) ok = false;
+    if (!ok)
+      for (int t = 0; t < KP * KP; ++t) { sHs[t] = 0.0; sR2inv[t] = 0.0; }
+    for (int t = 0; t < KP * KP; ++t) st->R2inv[t] = sR2inv[t];
+    sdef = ok ? 0 : 1;
+    if (!ok) st->deficient = 1;
   }
-  for (int t = lane; t < q0 * RL; t += 64) rf[t] = a.refl[t];
-  for (int t = lane; t < KP * 2 * KP; t += 64) {
+  __syncthreads();
+  const int ldh = a.ldh;
+  double* Hbar = a.Hbar + s * a.hbs;
+  double* Gs = a.G + s * a.gs;
+  double* refl = a.refl + s * a.rfs;
+  volatile int* hf = a.hinfo + 4 * s;
+  if (a.mode == 1) {
+    if (lane == 0) {
+      for (int r = 0; r < KP; ++r)
+        for (int c = 0; c < KP; ++c) Gs[r + (int64_t)c * ldh] = sHs[r * KP + c];
+      if (sdef) {
+        st->breakdown = 1;
+        st->done = 1;
+        hf[0] = 0;
+        hf[1] = 1;
+        hf[2] = 1;
+        hf[3] = st->nanflag;
+        __threadfence_system();
+      }
+    }
+    return;
+  }
+  extern __shared__ double sh[];
+  const int q0 = j * KP, nr = (j + 2) * KP;
+  constexpr int RL = KP + 2;                   // stored reflector: tau, v_1..v_KP, (unused)
+  double* col = sh;                            // [KP][ldh]
+  double* rf = col + (size_t)KP * ldh;         // [q0 + KP][RL]
+  double* gw = rf + (size_t)(q0 + KP) * RL;    // [KP][2 KP] window of G
+  const int r1 = (j + 1) * KP;
+  for (int t = lane; t < KP * nr; t += blockDim.x) {
+    const int c = t / nr, r = t % nr;
+    col[(size_t)c * ldh + r] = (r < r1) ? Hbar[r + (int64_t)(q0 + c) * ldh] : sHs[(r - r1) * KP + c];
+  }
+  for (int t = lane; t < q0 * RL; t += blockDim.x) rf[t] = refl[t];
+  for (int t = lane; t < KP * 2 * KP; t += blockDim.x) {
     const int c = t / (2 * KP), r = t % (2 * KP);
-    gw[c * 2 * KP + r] = a.G[(q0 + r) + (int64_t)c * a.ldg];
+    gw[c * 2 * KP + r] = Gs[(q0 + r) + (int64_t)c * ldh];
   }
   __syncthreads();
   // earlier reflectors, in order, on the new columns.  Reflector q touches rows
@@ -974,13 +939,13 @@ __global__ __launch_bounds__(64) void k_hess(KArgs a) {
         const int q = base + r;
         if (q < q0) {
           const double* v = rf + (size_t)q * RL;
-          double d = w[r];
+          double dd = w[r];
 #pragma unroll
-          for (int i = 1; i <= KP; ++i) d = fma(v[i], w[(r + i) % (KP + 1)], d);
-          d *= v[0];
-          w[r] -= d;
+          for (int i = 1; i <= KP; ++i) dd = fma(v[i], w[(r + i) % (KP + 1)], dd);
+          dd *= v[0];
+          w[r] -= dd;
 #pragma unroll
-          for (int i = 1; i <= KP; ++i) w[(r + i) % (KP + 1)] = fma(-d, v[i], w[(r + i) % (KP + 1)]);
+          for (int i = 1; i <= KP; ++i) w[(r + i) % (KP + 1)] = fma(-dd, v[i], w[(r + i) % (KP + 1)]);
           x[q] = w[r];
           w[r] = (q + KP + 1 < nr) ? x[q + KP + 1] : 0.0;
         }
@@ -1025,47 +990,50 @@ __global__ __launch_bounds__(64) void k_hess(KArgs a) {
       if (lane > t && lane < KP) { x = col + (size_t)lane * ldh; off = q; }
       else if (lane >= KP && lane < 2 * KP) { x = gw + (size_t)(lane - KP) * 2 * KP; off = t; }
       if (x) {
-        double d = x[off];
-        for (int r = 1; r <= KP; ++r) d = fma(v[r], x[off + r], d);
-        d *= tau;
-        x[off] -= d;
-        for (int r = 1; r <= KP; ++r) x[off + r] = fma(-d, v[r], x[off + r]);
+        double dd = x[off];
+        for (int r = 1; r <= KP; ++r) dd = fma(v[r], x[off + r], dd);
+        dd *= tau;
+        x[off] -= dd;
+        for (int r = 1; r <= KP; ++r) x[off + r] = fma(-dd, v[r], x[off + r]);
       }
     }
     __syncthreads();
   }
   // write back
-  for (int t = lane; t < KP * nr; t += 64) {
+  for (int t = lane; t < KP * nr; t += blockDim.x) {
     const int c = t / nr, r = t % nr;
-    a.Hbar[r + (int64_t)(q0 + c) * ldh] = col[(size_t)c * ldh + r];
+    Hbar[r + (int64_t)(q0 + c) * ldh] = col[(size_t)c * ldh + r];
   }
-  for (int t = lane; t < KP * RL; t += 64) a.refl[(size_t)q0 * RL + t] = rf[(size_t)q0 * RL + t];
-  for (int t = lane; t < KP * 2 * KP; t += 64) {
+  for (int t = lane; t < KP * RL; t += blockDim.x) refl[(size_t)q0 * RL + t] = rf[(size_t)q0 * RL + t];
+  for (int t = lane; t < KP * 2 * KP; t += blockDim.x) {
     const int c = t / (2 * KP), r = t % (2 * KP);
-    a.G[(q0 + r) + (int64_t)c * a.ldg] = gw[c * 2 * KP + r];
+    Gs[(q0 + r) + (int64_t)c * ldh] = gw[c * 2 * KP + r];
   }
   __syncthreads();
   if (lane == 0) {
     bool done = true;
     for (int c = 0; c < kact; ++c) {
-      double s = 0.0;
-      for (int r = KP; r < 2 * KP; ++r) s += gw[c * 2 * KP + r] * gw[c * 2 * KP + r];
-      const double e = sqrt(s) / st->bnorm[c];
+      double sq = 0.0;
+      for (int r = KP; r < 2 * KP; ++r) sq += gw[c * 2 * KP + r] * gw[c * 2 * KP + r];
+      const double e = sqrt(sq) / st->bnorm[c];
       st->est[c] = e;
       if (!(e <= st->tol)) done = false;
       if (e != e) st->nanflag = 1;
     }
+    bool brk = false;
     if (st->deficient) {
-      if (!done) st->breakdown = 1;
+      if (!done) brk = true;
       done = true;
     }
     if (st->nanflag) done = true;
     if (j + 1 >= m) done = true;
+    if (brk) st->breakdown = 1;
     st->j = j + 1;
     st->done = done ? 1 : 0;
-    volatile int* hf = a.hflag;
     hf[0] = j + 1;
     hf[1] = done ? 1 : 0;
+    hf[2] = st->breakdown;
+    hf[3] = st->nanflag;
     __threadfence_system();
   }
 }
@@ -1075,22 +1043,26 @@ __global__ __launch_bounds__(64) void k_hess(KArgs a) {
 // through LDS.
 template <int KP>
 __global__ __launch_bounds__(256) void k_ysolve(KArgs a, int PW) {
-  DevState* st = a.st;
+  const int s = a.slist[blockIdx.x];
+  const DevState* st = a.st + s;
   const int J = st->j * KP;
   const int kact = st->kact;
+  const double* Hbar = a.Hbar + s * a.hbs;
+  const double* Gs = a.G + s * a.gs;
+  double* Y = a.Y + s * a.ys;
   extern __shared__ double sh[];
   double* g = sh;                       // [J][KP]
   double* Rp = g + (size_t)J * KP;      // [PW][J] panel, column-major
   for (int t = threadIdx.x; t < J * KP; t += blockDim.x) {
     const int r = t / KP, c = t % KP;
-    g[t] = a.G[r + (int64_t)c * a.ldg];
+    g[t] = Gs[r + (int64_t)c * a.ldh];
   }
   for (int p1 = J; p1 > 0; p1 -= PW) {
     const int p0 = p1 - PW > 0 ? p1 - PW : 0;
     __syncthreads();
     for (int t = threadIdx.x; t < (p1 - p0) * p1; t += blockDim.x) {
       const int cc = t / p1, r = t % p1;
-      Rp[(size_t)cc * J + r] = a.Hbar[r + (int64_t)(p0 + cc) * a.ldh];
+      Rp[(size_t)cc * J + r] = Hbar[r + (int64_t)(p0 + cc) * a.ldh];
     }
     __syncthreads();
     for (int i = p1 - 1; i >= p0; --i) {
@@ -1108,40 +1080,199 @@ __global__ __launch_bounds__(256) void k_ysolve(KArgs a, int PW) {
       __syncthreads();
     }
   }
-  for (int t = threadIdx.x; t < J * KP; t += blockDim.x) a.Y[t] = g[t];
+  for (int t = threadIdx.x; t < J * KP; t += blockDim.x) Y[t] = g[t];
 }
 
 // cycle start: G = 0, step counters reset
-__global__ void k_init_cycle(KArgs a, int kp) {
-  DevState* st = a.st;
+__global__ __launch_bounds__(256) void k_init_cycle(KArgs a, int kp) {
+  const int s = a.slist[blockIdx.x];
+  DevState* st = a.st + s;
+  double* Gs = a.G + s * a.gs;
   const int rows = (a.m + 1) * kp;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < rows * kp; t += gridDim.x * blockDim.x) {
+  for (int t = threadIdx.x; t < rows * kp; t += blockDim.x) {
     const int r = t % rows, c = t / rows;
-    a.G[r + (int64_t)c * a.ldg] = 0.0;
+    Gs[r + (int64_t)c * a.ldh] = 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
     st->j = 0;
     st->done = 0;
     st->deficient = 0;
     st->breakdown = 0;
     st->nanflag = 0;
-    volatile int* hf = a.hflag;
+    volatile int* hf = a.hinfo + 4 * s;
     hf[0] = 0;
     hf[1] = 0;
+    hf[2] = 0;
+    hf[3] = 0;
     __threadfence_system();
   }
 }
 
+// per-solve state from the segment descriptor
+__global__ void k_state_init(const SegDesc* seg, const int* slist, DevState* st, int m, double tol) {
+  const int s = slist[blockIdx.x];
+  DevState* x = st + s;
+  const int kact = seg[s].kact;
+  if (threadIdx.x == 0) {
+    x->j = 0; x->done = 0; x->deficient = 0; x->breakdown = 0;
+    x->kact = kact; x->m = m; x->nanflag = 0; x->pad0 = 0;
+    x->tol = tol; x->wscale = 0.0;
+  }
+  if (threadIdx.x < KMAX) {
+    x->bnorm[threadIdx.x] = (threadIdx.x < kact) ? seg[s].bnorm[threadIdx.x] : 1.0;
+    x->est[threadIdx.x] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
-// CSR SpMM: Y = alpha A X + beta Bsrc (row-major blocks), LPR lanes per row
+// CSR SpMM over the segments of a batch: Y = alpha Op X + beta Bsrc (kp-wide
+// row-major blocks of the concatenated layout), LPR lanes per row.  Op is the
+// segment's A (which 0), its preconditioner (which 1: identity without one,
+// P_1 into Yalt for a factored Q P_1) or Q (which 2, factored segments only).
+// CONV: X holds W1 of the previous step; the kernel multiplies by the segment's
+// R2^{-1} (M) on the fly, Y = Op (W1 M) = (Op W1) M, and writes V_j = W1 M.
+// ---------------------------------------------------------------------------
+struct SpArgs {
+  const SegDesc* seg;
+  const int* stab;      // logical SpMM workgroup -> segment (-1: padding)
+  const DevState* st;
+  int which;
+  int check_done;
+  const double* X;
+  double* Y;
+  double* Yalt;
+  const double* Bsrc;
+  double alpha, beta;
+  double* Vout;
+  int vec;              // X rows may be read as double2
+};
+
+template <int KP, int LPR, bool CONV>
+__global__ __launch_bounds__(256) void k_spmm_seg(SpArgs a) {
+  const int lg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int s = a.stab[lg];
+  if (s < 0) return;
+  if (a.check_done && a.st[s].done) return;
+  const SegDesc& d = a.seg[s];
+  const int pk = d.pkind;
+  const int32_t* rp;
+  const int32_t* cl;
+  const double* vl;
+  bool ident = false;
+  double* Y = a.Y;
+  double alpha = a.alpha, beta = a.beta;
+  const double* Bsrc = a.Bsrc;
+  if (a.which == 0) {
+    rp = d.arow; cl = d.acol; vl = d.aval;
+  } else if (a.which == 1) {
+    ident = (pk == 0);
+    rp = d.prow; cl = d.pcol; vl = d.pval;
+    if (pk == 2) { Y = a.Yalt; alpha = 1.0; beta = 0.0; Bsrc = nullptr; }
+  } else {
+    if (pk != 2) return;
+    rp = d.prow; cl = d.pcol; vl = d.qval;
+  }
+  __shared__ double sM[CONV ? KP * KP : 1];
+  if constexpr (CONV) {
+    for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) sM[t] = a.st[s].R2inv[t];
+    __syncthreads();
+  }
+  const int64_t base = d.r0 * KP;
+  const double* X = a.X + base;
+  Y += base;
+  const int local = (lg - d.sp0) * (256 / LPR) + (int)threadIdx.x / LPR;
+  const int sub = (int)threadIdx.x % LPR;
+  const bool valid = local < d.n;
+  double acc[KP];
+#pragma unroll
+  for (int t = 0; t < KP; ++t) acc[t] = 0.0;
+  if (valid) {
+    if (ident) {
+      if (sub == 0) {
+#pragma unroll
+        for (int t = 0; t < KP; ++t) acc[t] = X[(int64_t)local * KP + t];
+      }
+    } else {
+      const int e1 = rp[local + 1];
+      if constexpr (KP % 2 == 0) {
+        if (a.vec) {
+          for (int e = rp[local] + sub; e < e1; e += LPR) {
+            const int c = cl[e];
+            const double v = vl[e];
+            const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * KP);
+#pragma unroll
+            for (int t = 0; t < KP / 2; ++t) {
+              const double2 x = xr[t];
+              acc[2 * t] = fma(v, x.x, acc[2 * t]);
+              acc[2 * t + 1] = fma(v, x.y, acc[2 * t + 1]);
+            }
+          }
+        } else {
+          for (int e = rp[local] + sub; e < e1; e += LPR) {
+            const int c = cl[e];
+            const double v = vl[e];
+            const double* xr = X + (int64_t)c * KP;
+#pragma unroll
+            for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+          }
+        }
+      } else {
+        for (int e = rp[local] + sub; e < e1; e += LPR) {
+          const int c = cl[e];
+          const double v = vl[e];
+          const double* xr = X + (int64_t)c * KP;
+#pragma unroll
+          for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < LPR; o <<= 1)
+#pragma unroll
+    for (int t = 0; t < KP; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
+  if (!valid) return;
+  const int64_t ro = (int64_t)local * KP;
+  if constexpr (CONV) {
+    double xr[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) xr[u] = X[ro + u];
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      if ((t % LPR) == sub) {
+        double y = 0.0, v = 0.0;
+#pragma unroll
+        for (int u = 0; u <= t; ++u) {
+          y = fma(acc[u], sM[u * KP + t], y);
+          v = fma(xr[u], sM[u * KP + t], v);
+        }
+        a.Vout[base + ro + t] = v;
+        double o = alpha * y;
+        if (beta != 0.0) o = fma(beta, Bsrc[base + ro + t], o);
+        Y[ro + t] = o;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      if ((t % LPR) == sub) {
+        double o = alpha * acc[t];
+        if (beta != 0.0) o = fma(beta, Bsrc[base + ro + t], o);
+        Y[ro + t] = o;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// single-matrix CSR SpMM with caller leading dimensions (pmor_spmm):
+// Y = alpha A X + beta Bsrc, LPR lanes per row
 // ---------------------------------------------------------------------------
 template <int KP, int LPR>
 __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ X, int64_t ldx, double* Y, int64_t ldy,
-                                              double alpha, double beta, const double* Bsrc, int64_t ldb,
-                                              const DevState* st, int vec) {
-  if (st && st->done) return;
+                                              double alpha, double beta, const double* Bsrc, int64_t ldb) {
   const int64_t gid = (int64_t)xcd_swizzle(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t row = gid / LPR;
   const int sub = (int)(gid % LPR);
@@ -1151,36 +1282,12 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__
   for (int t = 0; t < KP; ++t) acc[t] = 0.0;
   if (valid) {
     const int e1 = rowptr[row + 1];
-    if constexpr (KP % 2 == 0) {
-      if (vec) {
-        for (int e = rowptr[row] + sub; e < e1; e += LPR) {
-          const int c = col[e];
-          const double v = val[e];
-          const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * ldx);
+    for (int e = rowptr[row] + sub; e < e1; e += LPR) {
+      const int c = col[e];
+      const double v = val[e];
+      const double* xr = X + (int64_t)c * ldx;
 #pragma unroll
-          for (int t = 0; t < KP / 2; ++t) {
-            const double2 x = xr[t];
-            acc[2 * t] = fma(v, x.x, acc[2 * t]);
-            acc[2 * t + 1] = fma(v, x.y, acc[2 * t + 1]);
-          }
-        }
-      } else {
-        for (int e = rowptr[row] + sub; e < e1; e += LPR) {
-          const int c = col[e];
-          const double v = val[e];
-          const double* xr = X + (int64_t)c * ldx;
-#pragma unroll
-          for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
-        }
-      }
-    } else {
-      for (int e = rowptr[row] + sub; e < e1; e += LPR) {
-        const int c = col[e];
-        const double v = val[e];
-        const double* xr = X + (int64_t)c * ldx;
-#pragma unroll
-        for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
-      }
+      for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
     }
   }
 #pragma unroll
@@ -1211,15 +1318,14 @@ static int spmm_lanes_per_row() {
 
 template <int LPR>
 static int launch_spmm_lpr(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X,
-                           int64_t ldx, double* Y, int64_t ldy, int kp, double alpha, double beta, const double* Bsrc,
-                           int64_t ldb, const DevState* st, hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
+                           int64_t ldx, double* Y, int64_t ldy, int k, double alpha, double beta, const double* Bsrc,
+                           int64_t ldb, hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
   const int64_t threads = (int64_t)n * LPR;
   const unsigned grid = (unsigned)((threads + 255) / 256);
-  const int vec = ((ldx % 2) == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0) ? 1 : 0;
-  switch (kp) {
+  switch (k) {
 #define SPMM_CASE(K) \
     case K: plaunch(pc, pidx, ppart, k_spmm<K, LPR>, dim3(grid), dim3(256), 0, stream, n, rowptr, col, val, X, ldx, \
-                    Y, ldy, alpha, beta, Bsrc, ldb, st, vec); break;
+                    Y, ldy, alpha, beta, Bsrc, ldb); break;
     SPMM_CASE(1) SPMM_CASE(2) SPMM_CASE(3) SPMM_CASE(4) SPMM_CASE(5) SPMM_CASE(6) SPMM_CASE(7) SPMM_CASE(8)
     SPMM_CASE(9) SPMM_CASE(10) SPMM_CASE(11) SPMM_CASE(12) SPMM_CASE(13) SPMM_CASE(14) SPMM_CASE(15) SPMM_CASE(16)
 #undef SPMM_CASE
@@ -1230,20 +1336,17 @@ static int launch_spmm_lpr(int n, const int32_t* rowptr, const int32_t* col, con
 }
 
 int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X, int64_t ldx,
-                double* Y, int64_t ldy, int kp, int kact, double alpha, double beta, const double* Bsrc,
-                int64_t ldb, const DevState* st, hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
-  (void)kact;
+                double* Y, int64_t ldy, int k, double alpha, double beta, const double* Bsrc, int64_t ldb,
+                hipStream_t stream, pmor_ctx* pc, int pidx, int ppart) {
   if (n == 0) return PMOR_OK;
   switch (spmm_lanes_per_row()) {
-    case 1: return launch_spmm_lpr<1>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
-                                      pidx, ppart);
-    case 2: return launch_spmm_lpr<2>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
-                                      pidx, ppart);
-    case 8: return launch_spmm_lpr<8>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
-                                      pidx, ppart);
-    case 4: return launch_spmm_lpr<4>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
-                                      pidx, ppart);
-    default: return launch_spmm_lpr<2>(n, rowptr, col, val, X, ldx, Y, ldy, kp, alpha, beta, Bsrc, ldb, st, stream, pc,
+    case 1: return launch_spmm_lpr<1>(n, rowptr, col, val, X, ldx, Y, ldy, k, alpha, beta, Bsrc, ldb, stream, pc, pidx,
+                                      ppart);
+    case 4: return launch_spmm_lpr<4>(n, rowptr, col, val, X, ldx, Y, ldy, k, alpha, beta, Bsrc, ldb, stream, pc, pidx,
+                                      ppart);
+    case 8: return launch_spmm_lpr<8>(n, rowptr, col, val, X, ldx, Y, ldy, k, alpha, beta, Bsrc, ldb, stream, pc, pidx,
+                                      ppart);
+    default: return launch_spmm_lpr<2>(n, rowptr, col, val, X, ldx, Y, ldy, k, alpha, beta, Bsrc, ldb, stream, pc,
                                        pidx, ppart);
   }
 }
@@ -1251,57 +1354,236 @@ int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* 
 // ---------------------------------------------------------------------------
 // column norms, gather/scatter of the compacted right-hand sides
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_colnorm2(int n, const double* X, int64_t ldx, int k, double* part,
-                                                  double* part2, int* counters, double* out) {
-  __shared__ double sw[4][KMAX];
-  double acc[KMAX];
-  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
-  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < n; row += gridDim.x * blockDim.x)
-    for (int c = 0; c < k; ++c) {
-      const double x = X[(int64_t)row * ldx + c];
+// squared column norms of the segment's W (row kernel grid, 256 threads)
+template <int KP>
+__global__ __launch_bounds__(256) void k_colnorm_seg(KArgs a) {
+  RowSeg r;
+  if (!row_seg(a, false, r)) return;
+  const double* W = a.W + r.r0 * KP;
+  __shared__ double sw[4][KP];
+  double acc[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+  for (int row = r.g * 256 + (int)threadIdx.x; row < r.n; row += r.G * 256) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      const double x = W[(int64_t)row * KP + c];
       acc[c] += x * x;
     }
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int c = 0; c < k; ++c) {
-    const double s = wave_sum(acc[c]);
-    if (lane == 0) sw[w][c] = s;
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    const double sum = wave_sum(acc[c]);
+    if (lane == 0) sw[w][c] = sum;
   }
   __syncthreads();
-  if (threadIdx.x < k) part[(int64_t)blockIdx.x * k + threadIdx.x] =
-      sw[0][threadIdx.x] + sw[1][threadIdx.x] + sw[2][threadIdx.x] + sw[3][threadIdx.x];
+  if (threadIdx.x < KP)
+    a.part[(int64_t)r.lg * a.lstride + threadIdx.x] =
+        (sw[0][threadIdx.x] + sw[1][threadIdx.x]) + (sw[2][threadIdx.x] + sw[3][threadIdx.x]);
 }
 
-struct ColMap {
-  int idx[KMAX];
+// squared column norms of the caller's B of every listed segment: workgroup
+// (x, y) writes partials part[(y gridDim.x + x) KMAX + c]
+__global__ __launch_bounds__(256) void k_bnorm(const SegDesc* seg, const int* slist, double* part) {
+  const SegDesc& d = seg[slist[blockIdx.y]];
+  __shared__ double sw[4][KMAX];
+  double acc[KMAX];
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < d.n; row += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+      if (c < d.k) {
+        const double x = d.B[row * d.ldb + c];
+        acc[c] += x * x;
+      }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KMAX; ++c) {
+    const double sum = wave_sum(acc[c]);
+    if (lane == 0) sw[w][c] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < KMAX)
+    part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * KMAX + threadIdx.x] =
+        (sw[0][threadIdx.x] + sw[1][threadIdx.x]) + (sw[2][threadIdx.x] + sw[3][threadIdx.x]);
+}
+
+// Bc = W = compacted B, Xc = 0 for every listed segment
+__global__ __launch_bounds__(256) void k_gather_seg(const SegDesc* seg, const int* slist, int kp, double* Bc,
+                                                    double* W, double* Xc) {
+  const SegDesc& d = seg[slist[blockIdx.y]];
+  const int64_t len = (int64_t)d.n * kp;
+  const int64_t base = d.r0 * kp;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = t / kp;
+    const int c = (int)(t % kp);
+    const double b = (c < d.kact) ? d.B[row * d.ldb + d.cmap[c]] : 0.0;
+    Bc[base + t] = b;
+    W[base + t] = b;
+    Xc[base + t] = 0.0;
+  }
+}
+
+// caller's X from the compacted solution (columns without a compacted slot get 0)
+__global__ __launch_bounds__(256) void k_scatter_seg(const SegDesc* seg, const int* slist, int kp, const double* Xc) {
+  const SegDesc& d = seg[slist[blockIdx.y]];
+  const int64_t len = (int64_t)d.n * d.k;
+  const int64_t base = d.r0 * kp;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = t / d.k;
+    const int c = (int)(t % d.k);
+    const int ci = d.cinv[c];
+    d.X[row * d.ldx + c] = (ci >= 0) ? Xc[base + row * kp + ci] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: engine buffers
+// ---------------------------------------------------------------------------
+struct DBuf {
+  double* p = nullptr;
+  int64_t cap = 0;
 };
 
-__global__ void k_gather_cols(int n, const double* B, int64_t ldb, int kp, int kact, ColMap cm, double* Bc) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * kp) return;
-  const int64_t row = t / kp;
-  const int c = (int)(t % kp);
-  Bc[t] = (c < kact) ? B[row * ldb + cm.idx[c]] : 0.0;
+struct Engine {
+  DBuf V, W, Z, T, Bc, Xc, Hc, Hbar, G, refl, Y, nrm, part, partg;
+  DevState* st = nullptr;
+  int64_t st_cap = 0;
+  SegDesc* seg_d = nullptr;
+  SegDesc* seg_h = nullptr;   // pinned staging
+  int64_t seg_cap = 0, seg_h_cap = 0;
+  int* tab_d = nullptr;
+  int* tab_h = nullptr;       // pinned staging
+  int64_t tab_cap = 0, tab_h_cap = 0;
+  int* hinfo_h = nullptr;     // host-mapped, 4 ints per segment
+  int* hinfo_d = nullptr;
+  int64_t hinfo_cap = 0;
+  double* nrm_h = nullptr;    // pinned, KMAX per segment
+  int64_t nrm_h_cap = 0;
+  // strides of the per-segment arrays for the current (kp, m)
+  int ldh = 0;
+  int64_t hcs = 0, hc2off = 0, hbs = 0, gs = 0, rfs = 0, ys = 0, lstride = 0;
+};
+
+static int grow(DBuf& b, int64_t need) {
+  need = std::max<int64_t>(need, 1);
+  if (need <= b.cap) return PMOR_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  if (hipMalloc((void**)&b.p, sizeof(double) * need) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(PMOR_ENOMEM, "device allocation of the Krylov workspace failed");
+  }
+  b.cap = need;
+  return PMOR_OK;
 }
 
-__global__ void k_scatter_cols(int n, const double* Xc, int kp, int k, ColMap inv, double* X, int64_t ldx) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * k) return;
-  const int64_t row = t / k;
-  const int c = (int)(t % k);
-  X[row * ldx + c] = (inv.idx[c] >= 0) ? Xc[row * kp + inv.idx[c]] : 0.0;
+template <typename Tp>
+static int grow_host(Tp** p, int64_t& cap, int64_t need, unsigned flags) {
+  need = std::max<int64_t>(need, 1);
+  if (need <= cap) return PMOR_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  cap = 0;
+  if (hipHostMalloc((void**)p, sizeof(Tp) * need, flags) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(PMOR_ENOMEM, "pinned host allocation failed");
+  }
+  std::memset(*p, 0, sizeof(Tp) * need);
+  cap = need;
+  return PMOR_OK;
 }
 
-__global__ void k_fill(double* x, int64_t n, double v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = v;
+template <typename Tp>
+static int grow_dev(Tp** p, int64_t& cap, int64_t need) {
+  need = std::max<int64_t>(need, 1);
+  if (need <= cap) return PMOR_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  cap = 0;
+  if (hipMalloc((void**)p, sizeof(Tp) * need) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(PMOR_ENOMEM, "device allocation of the Krylov state failed");
+  }
+  cap = need;
+  return PMOR_OK;
+}
+
+void engine_destroy(Engine* e) {
+  if (!e) return;
+  DBuf* bufs[] = {&e->V, &e->W, &e->Z, &e->T, &e->Bc, &e->Xc, &e->Hc, &e->Hbar, &e->G, &e->refl, &e->Y,
+                  &e->nrm, &e->part, &e->partg};
+  for (DBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (e->st) (void)hipFree(e->st);
+  if (e->seg_d) (void)hipFree(e->seg_d);
+  if (e->tab_d) (void)hipFree(e->tab_d);
+  if (e->seg_h) (void)hipHostFree(e->seg_h);
+  if (e->tab_h) (void)hipHostFree(e->tab_h);
+  if (e->hinfo_h) (void)hipHostFree(e->hinfo_h);
+  if (e->nrm_h) (void)hipHostFree(e->nrm_h);
+  delete e;
+}
+
+// buffers for nseg segments over `rows` concatenated rows, `wgs` row-kernel
+// workgroups and `tabints` table entries
+static int engine_reserve(Engine& E, int kp, int m, int64_t rows, int nseg, int64_t wgs, int64_t tabints) {
+  const int64_t kp2 = (int64_t)kp * kp;
+  E.ldh = (m + 1) * kp;
+  E.hc2off = (m + 2) * kp2 + KMAX;
+  E.hcs = 2 * E.hc2off;
+  E.hbs = (int64_t)E.ldh * m * kp;
+  E.gs = (int64_t)E.ldh * kp;
+  E.rfs = (int64_t)(m + 1) * kp * (kp + 2);
+  E.ys = (int64_t)E.ldh * kp;
+  E.lstride = (m + 1) * kp2 + KMAX;
+  const int64_t blk = rows * kp;
+  PMOR_TRY(grow(E.V, (m + 1) * blk));
+  PMOR_TRY(grow(E.W, blk));
+  PMOR_TRY(grow(E.Z, blk));
+  PMOR_TRY(grow(E.T, blk));
+  PMOR_TRY(grow(E.Bc, blk));
+  PMOR_TRY(grow(E.Xc, blk));
+  PMOR_TRY(grow(E.Hc, nseg * E.hcs));
+  PMOR_TRY(grow(E.Hbar, nseg * E.hbs));
+  PMOR_TRY(grow(E.G, nseg * E.gs));
+  PMOR_TRY(grow(E.refl, nseg * E.rfs));
+  PMOR_TRY(grow(E.Y, nseg * E.ys));
+  PMOR_TRY(grow(E.nrm, (int64_t)nseg * KMAX));
+  PMOR_TRY(grow(E.part, std::max<int64_t>(wgs * E.lstride, (int64_t)nseg * 64 * KMAX)));
+  PMOR_TRY(grow(E.partg, wgs * kp2));
+  PMOR_TRY(grow_dev(&E.st, E.st_cap, nseg));
+  PMOR_TRY(grow_dev(&E.seg_d, E.seg_cap, nseg));
+  PMOR_TRY(grow_dev(&E.tab_d, E.tab_cap, tabints));
+  PMOR_TRY(grow_host(&E.seg_h, E.seg_h_cap, nseg, hipHostMallocDefault));
+  PMOR_TRY(grow_host(&E.tab_h, E.tab_h_cap, tabints, hipHostMallocDefault));
+  if ((int64_t)4 * nseg > E.hinfo_cap) {
+    PMOR_TRY(grow_host(&E.hinfo_h, E.hinfo_cap, (int64_t)4 * nseg, hipHostMallocMapped));
+    PMOR_HIP(hipHostGetDevicePointer((void**)&E.hinfo_d, E.hinfo_h, 0));
+  }
+  PMOR_TRY(grow_host(&E.nrm_h, E.nrm_h_cap, (int64_t)nseg * KMAX, hipHostMallocDefault));
+  return PMOR_OK;
 }
 
 // ---------------------------------------------------------------------------
-// host side
+// host side: launch configuration per block size
 // ---------------------------------------------------------------------------
-static int* dev_counters(DevState* st) {
-  return reinterpret_cast<int*>(reinterpret_cast<char*>(st) + offsetof(DevState, counters));
-}
+template <int KP>
+struct Fam {
+  static constexpr bool RS = (KP == 4);   // rows split over wavefronts
+  static constexpr bool ROW = (KP < 4);   // one row per lane
+  static constexpr int NW = (KP == 4 || KP == 16) ? 8 : 4;
+  static constexpr int BPW = 32 / NW;     // V blocks per wavefront: m + 1 <= 32
+  static constexpr int ROWS = RS ? 16 * NW : (ROW ? 64 : 16);  // rows per workgroup iteration
+  static constexpr int GMAX = RS ? 256 : 512;
+};
 
 static int pad_kp(int k) {
   if (k <= 1) return 1;
@@ -1311,328 +1593,546 @@ static int pad_kp(int k) {
   return 16;
 }
 
-static int row_grid(int n, int rows_per_tile, int gmax = 512) {
-  const int tiles = (n + rows_per_tile - 1) / rows_per_tile;
-  int g = std::min(tiles, gmax);
-  if (g >= 8) g &= ~7;  // a multiple of 8 keeps the XCD swizzle exact
-  return std::max(g, 1);
-}
-
-void free_workspace(Workspace& ws) {
-  double* bufs[] = {ws.V, ws.W, ws.Z, ws.T, ws.Bc, ws.Xc, ws.Hbar, ws.Hcol, ws.G, ws.refl, ws.Y, ws.part, ws.part2,
-                    ws.partg};
-  for (double* b : bufs)
-    if (b) (void)hipFree(b);
-  if (ws.st) (void)hipFree(ws.st);
-  if (ws.st_host) (void)hipHostFree(ws.st_host);
-  ws = Workspace{};
-}
-
-int ensure_workspace(pmor_problem* pb, int kp, int m) {
-  Workspace& ws = pb->ws;
-  if (ws.V && ws.n == pb->n && ws.kp == kp && ws.m >= m) return PMOR_OK;
-  free_workspace(ws);
-  const int64_t n = pb->n;
-  ws.n = pb->n; ws.kp = kp; ws.m = m;
-  const int64_t blk = std::max<int64_t>(n * kp, 1);
-  const int64_t rows = (int64_t)(m + 1) * kp;
-  auto alloc = [&](double** p, int64_t count) -> int {
-    hipError_t e = hipMalloc((void**)p, sizeof(double) * std::max<int64_t>(count, 1));
-    if (e != hipSuccess) return fail(PMOR_ENOMEM, "device allocation of the Krylov workspace failed");
-    ws.bytes += sizeof(double) * count;
-    return PMOR_OK;
-  };
-  PMOR_TRY(alloc(&ws.V, (m + 1) * blk));
-  PMOR_TRY(alloc(&ws.W, blk));
-  PMOR_TRY(alloc(&ws.Z, blk));
-  PMOR_TRY(alloc(&ws.T, blk));
-  PMOR_TRY(alloc(&ws.Bc, blk));
-  PMOR_TRY(alloc(&ws.Xc, blk));
-  PMOR_TRY(alloc(&ws.Hbar, rows * m * kp));
-  // Hc1 | Hc2 (coefficients + kp norms each) | Gram (kp x kp) | residual norms (KMAX)
-  PMOR_TRY(alloc(&ws.Hcol, 2 * (rows * kp + kp) + kp * kp + 2 * KMAX));
-  PMOR_TRY(alloc(&ws.G, rows * kp));
-  PMOR_TRY(alloc(&ws.refl, (int64_t)m * kp * (kp + 2) + kp * (kp + 2)));
-  PMOR_TRY(alloc(&ws.Y, rows * kp));
-  const int64_t L = rows * kp + kp + KMAX;
-  ws.part_len = (size_t)L;
-  PMOR_TRY(alloc(&ws.part, (int64_t)MAX_RED_WG * L));
-  PMOR_TRY(alloc(&ws.part2, (int64_t)(MAX_RED_WG / RED_GROUP + 1) * L));
-  PMOR_TRY(alloc(&ws.partg, (int64_t)2 * MAX_RED_WG * KMAX * KMAX));
-  PMOR_HIP(hipMalloc((void**)&ws.st, sizeof(DevState)));
-  PMOR_HIP(hipMemset(ws.st, 0, sizeof(DevState)));
-  PMOR_HIP(hipHostMalloc((void**)&ws.st_host, sizeof(DevState) + 64, hipHostMallocMapped));
-  std::memset(ws.st_host, 0, sizeof(DevState) + 64);
-  return PMOR_OK;
-}
-
-namespace {
-
-struct Launcher {
-  pmor_problem* pb;
-  const pmor_spai* h;
-  int kp;
-  int m;
-  hipStream_t s;
-  KArgs a;
-  int G;   // workgroups of the row-parallel kernels
-  int* hflag_dev;
-
-  // W <- (P) V_j etc. are done by spmm; these wrap the block kernels
-  template <int KP, int NW, int BPW>
-  int dot(int pidx = -1) {
-    pmor_ctx* c = pb->ctx;
-    if constexpr (KP == 4) plaunch(c, pidx, 3, k_dot4<NW>, dim3(G), dim3(64 * NW), 0, s, a);
-    else if constexpr (KP >= 4) plaunch(c, pidx, 3, k_dot_mfma<(KP >= 4 ? KP : 4), NW, BPW>, dim3(G), dim3(64 * NW), 0, s, a);
-    else plaunch(c, pidx, 3, k_dot_row<(KP < 4 ? KP : 1), NW, BPW>, dim3(G), dim3(64 * NW), 0, s, a);
-    PMOR_HIP(hipGetLastError());
-    return PMOR_OK;
-  }
-  template <int KP, int NW, int BPW, bool DOT, bool GRAM>
-  int upd(int nbl_max, int pidx = -1) {
-    const int per = (KP >= 4) ? (KP / 4) : KP;
-    const size_t shm = sizeof(double) * ((size_t)nbl_max * KP * KP + (size_t)2 * NW * 64 * per);
-    pmor_ctx* c = pb->ctx;
-    if constexpr (KP == 4)
-      plaunch(c, pidx, 3, k_upd4<NW, DOT, GRAM>, dim3(G), dim3(64 * NW), 0, s, a);
-    else if constexpr (KP >= 4)
-      plaunch(c, pidx, 3, k_upd_mfma<(KP >= 4 ? KP : 4), NW, BPW, DOT, GRAM>, dim3(G), dim3(64 * NW), (uint32_t)shm, s, a);
-    else
-      plaunch(c, pidx, 3, k_upd_row<(KP < 4 ? KP : 1), NW, BPW, DOT, GRAM>, dim3(G), dim3(64 * NW), (uint32_t)shm, s, a);
-    PMOR_HIP(hipGetLastError());
-    return PMOR_OK;
-  }
-  template <int KP, int NW, bool GRAM>
-  int scale() {
-    if constexpr (KP >= 4) hipLaunchKernelGGL((k_scale_mfma<(KP >= 4 ? KP : 4), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, G);
-    else hipLaunchKernelGGL((k_scale_row<(KP < 4 ? KP : 1), NW, GRAM>), dim3(G), dim3(64 * NW), 0, s, a, G);
-    PMOR_HIP(hipGetLastError());
-    return PMOR_OK;
-  }
-};
-
-// preconditioner application Z = P_l X (P_l = Q P_1 when the pattern update is active)
-int apply_P(pmor_problem* pb, const pmor_spai* h, const double* X, double* Z, double* tmp, int kp, int kact,
-            const DevState* st, double beta, hipStream_t s, int pidx = -1) {
-  const int n = pb->n;
-  if (h->q_active) {
-    PMOR_TRY(launch_spmm(n, h->Prowptr, h->Pcol, h->P1val, X, kp, tmp, kp, kp, kact, 1.0, 0.0, nullptr, 0, st, s,
-                         pb->ctx, pidx, 1));
-    return launch_spmm(n, h->Prowptr, h->Pcol, h->Qval, tmp, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s, pb->ctx,
-                       pidx, 2);
-  }
-  return launch_spmm(n, h->Prowptr, h->Pcol, h->Pval, X, kp, Z, kp, kp, kact, 1.0, beta, Z, kp, st, s, pb->ctx, pidx,
-                     3);
-}
-
-}  // namespace
-
-// identity "matrix" for the unpreconditioned case: a copy kernel
-__global__ void k_copy_axpby(int64_t len, const double* X, double* Z, double beta) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
-    Z[i] = (beta != 0.0) ? Z[i] * beta + X[i] : X[i];
+// row-kernel workgroups of an n-row segment: at least two iterations each,
+// at most GMAX, a multiple of 8 from 8 on; a function of n and kp only, so a
+// segment's sums do not depend on the batch it runs in
+static int row_wgs(int n, int rows_per_iter, int gmax) {
+  int64_t g = ((int64_t)n + 2 * rows_per_iter - 1) / (2 * rows_per_iter);
+  g = std::min<int64_t>(std::max<int64_t>(g, 1), gmax);
+  if (g >= 8) g &= ~7;
+  return (int)g;
 }
 
 template <int KP>
-static int run_cycles(pmor_problem* pb, const pmor_spai* h, int kact, const pmor_solve_opts& o, pmor_stats* stats,
-                      const double* bnorm, int* steps_out, int* cycles_out, double* relres_out, int* status) {
-  constexpr int NW = (KP == 16) ? 16 : (KP == 4 ? 8 : 4);
-  constexpr int BPW = 32 / NW;  // V blocks per wavefront: m + 1 <= NW * BPW = 32
-  Workspace& ws = pb->ws;
-  hipStream_t s = pb->ctx->stream;
-  const int n = pb->n, m = o.m;
-  const int ldh = (m + 1) * KP;
-  Launcher L{pb, h, KP, m, s, KArgs{}, row_grid(n, KP >= 4 ? 16 : 64, KP == 4 ? 256 : 512), nullptr};
-  KArgs& a = L.a;
-  a.n = n; a.m = m; a.vstride = (int64_t)n * KP;
-  a.V = ws.V; a.W = ws.W;
-  a.Hc1 = ws.Hcol; a.Hc2 = ws.Hcol + (ldh * KP + KP); a.Gram = ws.Hcol + 2 * (ldh * KP + KP);
-  a.Hbar = ws.Hbar; a.ldh = ldh; a.G = ws.G; a.ldg = ldh; a.refl = ws.refl; a.Y = ws.Y;
-  a.part = ws.part; a.part2 = ws.part2; a.st = ws.st;
-  a.partg0 = ws.partg; a.partg1 = ws.partg + (int64_t)MAX_RED_WG * KMAX * KMAX;
-  int* hflag = reinterpret_cast<int*>(reinterpret_cast<char*>(ws.st_host) + sizeof(DevState));
-  int* hflag_dev = nullptr;
-  PMOR_HIP(hipHostGetDevicePointer((void**)&hflag_dev, hflag, 0));
-  a.hflag = hflag_dev;
-  // per-solve device state
-  DevState& init = *ws.st_host;
-  std::memset(&init, 0, offsetof(DevState, counters));
-  init.kact = kact; init.m = m; init.tol = o.tol;
-  for (int c = 0; c < KMAX; ++c) init.bnorm[c] = (c < kact) ? bnorm[c] : 1.0;
-  PMOR_HIP(hipMemcpyAsync(ws.st, &init, offsetof(DevState, counters), hipMemcpyHostToDevice, s));
-  const int64_t blk = (int64_t)n * KP;
-  const unsigned fgrid = (unsigned)std::min<int64_t>((blk + 255) / 256, 4096);
-  // X = 0, W = R_0 = B
-  hipLaunchKernelGGL(k_fill, dim3(fgrid), dim3(256), 0, s, ws.Xc, blk, 0.0);
-  hipLaunchKernelGGL(k_copy_axpby, dim3(fgrid), dim3(256), 0, s, blk, ws.Bc, ws.W, 0.0);
-  PMOR_HIP(hipGetLastError());
-  const size_t hess_shm = sizeof(double) * ((size_t)KP * ldh + (size_t)(m * KP + KP) * (KP + 2) + 2 * KP * KP);
-  const int ys_pw = (KP >= 16) ? 8 : 32;
-  const size_t ys_shm = sizeof(double) * ((size_t)m * KP * KP + (size_t)ys_pw * m * KP);
-  PMOR_TRY(allow_lds((const void*)k_hess<KP>, hess_shm));
-  PMOR_TRY(allow_lds((const void*)k_ysolve<KP>, ys_shm));
-  hipEvent_t* evs = pb->ctx->evs;
-  const int LOOKAHEAD = 2;
-  int total_steps = 0, cyc = 0;
-  *status = PMOR_ENOTCONV;
-  for (cyc = 0; cyc < o.max_cycles; ++cyc) {
-    const int prof_first = (int)pb->ctx->prof.recs.size();
-    // initial block QR of W = R_0: V_0 S = W, S -> G(0:kp, :)
-    hipLaunchKernelGGL(k_init_cycle, dim3(64), dim3(256), 0, s, a, KP);
-    a.nbl_mode = 1; a.hsign = 1.0; a.Hsrc = ws.Hcol; a.zero_init = 0;
-    PMOR_TRY((L.template upd<KP, NW, BPW, false, true>(1)));
-    PMOR_TRY((L.template scale<KP, NW, true>()));
-    a.out_block = 1;
-    PMOR_TRY((L.template scale<KP, NW, false>()));
-    a.out_block = 0;
-    // Arnoldi steps
+static void launch_dot(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a) {
+  using F = Fam<KP>;
+  if constexpr (F::RS) plaunch(c, pidx, 3, k_dot4<F::NW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  else if constexpr (F::ROW) plaunch(c, pidx, 3, k_dot_row<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  else plaunch(c, pidx, 3, k_dot_mfma<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+}
+
+template <int KP>
+static size_t upd_shm(int nbl_max) {
+  using F = Fam<KP>;
+  if constexpr (F::RS) return 0;
+  const int per = F::ROW ? KP : KP / 4;
+  return sizeof(double) * ((size_t)nbl_max * KP * KP + (size_t)2 * F::NW * 64 * per);
+}
+
+template <int KP, int MODE>
+static const void* upd_fn() {
+  using F = Fam<KP>;
+  if constexpr (F::RS) return (const void*)k_upd4<F::NW, MODE>;
+  else if constexpr (F::ROW) return (const void*)k_upd_row<KP, F::NW, F::BPW, MODE>;
+  else return (const void*)k_upd_mfma<KP, F::NW, F::BPW, MODE>;
+}
+
+template <int KP, int MODE>
+static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a, int nbl_max) {
+  using F = Fam<KP>;
+  const uint32_t shm = (uint32_t)upd_shm<KP>(nbl_max);
+  if constexpr (F::RS) plaunch(c, pidx, 3, k_upd4<F::NW, MODE>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  else if constexpr (F::ROW)
+    plaunch(c, pidx, 3, k_upd_row<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
+  else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
+}
+
+template <int KP, bool CONV>
+static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int lpr, hipStream_t s, const SpArgs& a) {
+  switch (lpr) {
+    case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(256), 0, s, a); break;
+    case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(256), 0, s, a); break;
+    case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(256), 0, s, a); break;
+    default: plaunch(c, pidx, part, k_spmm_seg<KP, 2, CONV>, dim3(grid), dim3(256), 0, s, a); break;
+  }
+}
+
+static unsigned chunks(int64_t len, int64_t per, unsigned cap) {
+  const int64_t g = (len + per - 1) / per;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+
+// ---------------------------------------------------------------------------
+// host side: the persistent engine.  Systems are admitted between cycles into
+// free row ranges and segment slots; every cycle advances all admitted systems
+// in lockstep; finished systems leave (X written) at the end of a cycle.
+// ---------------------------------------------------------------------------
+template <int KP>
+class RunnerT final : public Runner {
+  using F = Fam<KP>;
+
+ public:
+  RunnerT(pmor_ctx* c, Engine* e, const pmor_solve_opts& o, int64_t rows_cap, int nslots)
+      : ctx_(c), E_(*e), o_(o), rows_cap_((rows_cap + 15) / 16 * 16), nslots_(nslots) {}
+
+  int init() {
+    lpr_ = spmm_lanes_per_row();
+    sp_rows_ = 256 / lpr_;
+    const int64_t wg_cap = rows_cap_ / (2 * F::ROWS) + nslots_ + 8;
+    const int64_t sp_cap = rows_cap_ / sp_rows_ + nslots_ + 8;
+    PMOR_TRY(engine_reserve(E_, KP, o_.m, std::max<int64_t>(rows_cap_, 16), nslots_, wg_cap,
+                            wg_cap + sp_cap + 2 * (int64_t)nslots_ + 8));
+    item_.assign(nslots_, nullptr);
+    r0_.assign(nslots_, 0);
+    nrows_.assign(nslots_, 0);
+    Gw_.assign(nslots_, 0);
+    Gs_.assign(nslots_, 0);
+    cyc_.assign(nslots_, 0);
+    steps_of_.assign(nslots_, 0);
+    for (int s = nslots_ - 1; s >= 0; --s) free_slots_.push_back(s);
+    free_rows_.clear();
+    free_rows_.push_back({0, rows_cap_});
+    const int m = o_.m;
+    hess_shm_ = sizeof(double) * ((size_t)KP * E_.ldh + (size_t)(m * KP + KP) * (KP + 2) + 2 * KP * KP);
+    ys_pw_ = (KP >= 16) ? 8 : 32;
+    ys_shm_ = sizeof(double) * ((size_t)m * KP * KP + (size_t)ys_pw_ * m * KP);
+    PMOR_TRY(allow_lds((const void*)k_hess<KP>, hess_shm_));
+    PMOR_TRY(allow_lds((const void*)k_ysolve<KP>, ys_shm_));
+    PMOR_TRY(allow_lds(upd_fn<KP, UPD_PLAIN>(), upd_shm<KP>(m)));
+    PMOR_TRY(allow_lds(upd_fn<KP, UPD_P2>(), upd_shm<KP>(m)));
+    PMOR_TRY(allow_lds(upd_fn<KP, UPD_P3>(), upd_shm<KP>(m)));
+    t0_ = std::chrono::steady_clock::now();
+    return PMOR_OK;
+  }
+
+  int busy() const override { return (int)(act_.size() + pending_.size()); }
+  double now_ms() const override {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+  }
+
+  bool can_admit(SolveItem* const* items, int n) const override {
+    if ((int)free_slots_.size() < n) return false;
+    std::vector<std::pair<int64_t, int64_t>> fr = free_rows_;
+    for (int q = 0; q < n; ++q)
+      if (take_rows(fr, rows_of(items[q]->n)) < 0) return false;
+    return true;
+  }
+
+  int admit(SolveItem* const* items, int n) override {
+    if (n <= 0) return PMOR_OK;
+    for (int q = 0; q < n; ++q)
+      if (items[q]->k > KP || items[q]->k < 1) return fail(PMOR_EINVAL, "system wider than the engine's block");
+    if (!can_admit(items, n)) return fail(PMOR_EADMIT, "no free rows or slots in the Krylov engine");
+    hipStream_t s = ctx_->stream;
+    PMOR_HIP(hipStreamSynchronize(s));
+    std::vector<int> ns(n);
+    for (int q = 0; q < n; ++q) {
+      SolveItem* it = items[q];
+      const int sl = free_slots_.back();
+      free_slots_.pop_back();
+      ns[q] = sl;
+      item_[sl] = it;
+      nrows_[sl] = rows_of(it->n);
+      r0_[sl] = take_rows(free_rows_, nrows_[sl]);
+      Gw_[sl] = row_wgs(it->n, F::ROWS, F::GMAX);
+      Gs_[sl] = (int)(((int64_t)it->n + sp_rows_ - 1) / sp_rows_);
+      cyc_[sl] = 0;
+      SegDesc& d = E_.seg_h[sl];
+      std::memset(&d, 0, sizeof(d));
+      d.n = it->n;
+      d.k = it->k;
+      d.r0 = r0_[sl];
+      d.G = Gw_[sl];
+      d.spG = Gs_[sl];
+      d.pkind = it->pkind;
+      d.arow = it->arow; d.acol = it->acol; d.aval = it->aval;
+      d.prow = it->prow; d.pcol = it->pcol; d.pval = it->pval; d.qval = it->qval;
+      d.B = it->B; d.ldb = it->ldb;
+      d.X = it->X; d.ldx = it->ldx;
+      E_.tab_h[q] = sl;
+      it->status = PMOR_OK;
+      it->t_done_ms = 0.0;
+    }
+    // norms of the caller's columns
+    PMOR_HIP(hipMemcpyAsync(E_.seg_d, E_.seg_h, sizeof(SegDesc) * nslots_, hipMemcpyHostToDevice, s));
+    PMOR_HIP(hipMemcpyAsync(E_.tab_d, E_.tab_h, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_bnorm, dim3(64, n), dim3(256), 0, s, (const SegDesc*)E_.seg_d, (const int*)E_.tab_d,
+                       E_.part.p);
+    hipLaunchKernelGGL(k_reduce_seg, dim3((KMAX + 7) / 8, n), dim3(256), 0, s, (const double*)E_.part.p,
+                       (int64_t)KMAX, KMAX, (const SegDesc*)E_.seg_d, (const int*)E_.tab_d, 64, (const DevState*)E_.st,
+                       0, E_.nrm.p, (int64_t)KMAX, (int64_t)0);
+    PMOR_HIP(hipGetLastError());
+    PMOR_HIP(hipMemcpyAsync(E_.nrm_h, E_.nrm.p, sizeof(double) * nslots_ * KMAX, hipMemcpyDeviceToHost, s));
+    PMOR_HIP(hipStreamSynchronize(s));
+    std::vector<int> fresh;
+    int64_t maxn = 1;
+    for (int q = 0; q < n; ++q) {
+      const int sl = ns[q];
+      SolveItem* it = item_[sl];
+      SegDesc& d = E_.seg_h[sl];
+      int kact = 0;
+      bool nan = false;
+      for (int c = 0; c < KMAX; ++c) { d.cinv[c] = -1; d.cmap[c] = 0; d.bnorm[c] = 1.0; }
+      for (int c = 0; c < d.k; ++c) {
+        const double b = E_.nrm_h[(int64_t)sl * KMAX + c];
+        if (!std::isfinite(b)) { nan = true; continue; }
+        if (b > 0.0) {
+          d.cinv[c] = kact;
+          d.cmap[kact] = c;
+          d.bnorm[kact] = std::sqrt(b);
+          ++kact;
+        }
+      }
+      if (nan) {
+        kact = 0;
+        for (int c = 0; c < KMAX; ++c) d.cinv[c] = -1;
+      }
+      d.kact = kact;
+      it->status = nan ? PMOR_ENAN : PMOR_OK;
+      if (pmor_stats* st = it->stats) {
+        st->k = d.k;
+        st->cycles = 0;
+        st->steps = 0;
+        std::memset(st->cycle_steps, 0, sizeof(st->cycle_steps));
+        for (int c = 0; c < PMOR_KMAX; ++c) st->relres[c] = 0.0;
+      }
+      if (kact > 0) {
+        fresh.push_back(sl);
+        maxn = std::max<int64_t>(maxn, it->n);
+      } else {
+        pending_.push_back(sl);  // X = 0, returned by the next cycle
+      }
+    }
+    PMOR_HIP(hipMemcpyAsync(E_.seg_d, E_.seg_h, sizeof(SegDesc) * nslots_, hipMemcpyHostToDevice, s));
+    const int nf = (int)fresh.size();
+    if (nf > 0) {
+      for (int t = 0; t < nf; ++t) E_.tab_h[t] = fresh[t];
+      PMOR_HIP(hipMemcpyAsync(E_.tab_d, E_.tab_h, sizeof(int) * nf, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_gather_seg, dim3(chunks(maxn * KP, 256, 2048), nf), dim3(256), 0, s,
+                         (const SegDesc*)E_.seg_d, (const int*)E_.tab_d, KP, E_.Bc.p, E_.W.p, E_.Xc.p);
+      hipLaunchKernelGGL(k_state_init, dim3(nf), dim3(64), 0, s, (const SegDesc*)E_.seg_d, (const int*)E_.tab_d,
+                         E_.st, o_.m, o_.tol);
+      PMOR_HIP(hipGetLastError());
+      for (int sl : fresh) act_.push_back(sl);
+    }
+    return PMOR_OK;
+  }
+
+  int cycle(std::vector<SolveItem*>& done) override {
+    hipStream_t s = ctx_->stream;
+    const int m = o_.m;
+    // the staging buffers are rewritten only after the copies that read them are done
+    PMOR_HIP(hipStreamSynchronize(s));
+    std::vector<int> fin;  // slots finished in this call
+    const int nact = (int)act_.size();
+    int64_t Gtot = 0, SPtot = 0;
+    int* sl = E_.tab_h;
+    if (nact > 0) {
+      int64_t g = 0;
+      int* wtab = E_.tab_h;
+      for (int i : act_) {
+        E_.seg_h[i].wg0 = (int)g;
+        for (int q = 0; q < Gw_[i]; ++q) wtab[g++] = i;
+      }
+      Gtot = (g + 7) / 8 * 8;
+      while (g < Gtot) wtab[g++] = -1;
+      int* stab = wtab + Gtot;
+      int64_t q = 0;
+      for (int i : act_) {
+        E_.seg_h[i].sp0 = (int)q;
+        for (int t = 0; t < Gs_[i]; ++t) stab[q++] = i;
+      }
+      SPtot = (q + 7) / 8 * 8;
+      while (q < SPtot) stab[q++] = -1;
+      sl = stab + SPtot;
+      bool anyq = false;
+      for (int t = 0; t < nact; ++t) {
+        sl[t] = act_[t];
+        if (item_[act_[t]]->pkind == 2) anyq = true;
+      }
+      PMOR_HIP(hipMemcpyAsync(E_.seg_d, E_.seg_h, sizeof(SegDesc) * nslots_, hipMemcpyHostToDevice, s));
+      PMOR_HIP(hipMemcpyAsync(E_.tab_d, E_.tab_h, sizeof(int) * (Gtot + SPtot + nact), hipMemcpyHostToDevice, s));
+      PMOR_TRY(run_cycle(Gtot, SPtot, nact, anyq));
+      // verdicts
+      const double t_now = now_ms();
+      std::vector<int> next;
+      for (int i : act_) {
+        SolveItem* it = item_[i];
+        const volatile int* hf = E_.hinfo_h + 4 * i;
+        const int j = hf[0], brk = hf[2], nanf = hf[3];
+        steps_of_[i] = j;
+        const SegDesc& d = E_.seg_h[i];
+        bool conv = true, nan = nanf != 0;
+        double rel[KMAX];
+        for (int c = 0; c < d.kact; ++c) {
+          rel[c] = std::sqrt(E_.nrm_h[(int64_t)i * KMAX + c]) / d.bnorm[c];
+          if (!(rel[c] <= o_.tol)) conv = false;
+          if (!std::isfinite(rel[c])) nan = true;
+        }
+        const int cyc = cyc_[i]++;
+        if (pmor_stats* st = it->stats) {
+          if (cyc < PMOR_MAX_CYCLES) st->cycle_steps[cyc] = j;
+          st->cycles = cyc + 1;
+          st->steps += j;
+          for (int c = 0; c < d.k; ++c) st->relres[c] = (d.cinv[c] >= 0) ? rel[d.cinv[c]] : 0.0;
+        }
+        bool over = true;
+        if (nan) it->status = PMOR_ENAN;
+        else if (conv) it->status = PMOR_OK;
+        else if (brk) it->status = PMOR_EBREAKDOWN;
+        else if (cyc_[i] >= o_.max_cycles) it->status = PMOR_ENOTCONV;
+        else over = false;
+        if (over) {
+          it->t_done_ms = t_now;
+          fin.push_back(i);
+        } else {
+          next.push_back(i);
+        }
+      }
+      prof_resolve(ctx_, prof_first_, steps_of_.data());
+      act_.swap(next);
+    }
+    for (int i : pending_) {
+      item_[i]->t_done_ms = now_ms();
+      fin.push_back(i);
+    }
+    pending_.clear();
+    // X of the finished systems (staging region after this cycle's tables)
+    if (!fin.empty()) {
+      const int64_t off = Gtot + SPtot + nact;
+      int* fl = E_.tab_h + off;
+      int64_t maxnk = 1;
+      for (size_t t = 0; t < fin.size(); ++t) {
+        fl[t] = fin[t];
+        maxnk = std::max<int64_t>(maxnk, (int64_t)item_[fin[t]]->n * item_[fin[t]]->k);
+      }
+      PMOR_HIP(hipMemcpyAsync(E_.tab_d + off, fl, sizeof(int) * fin.size(), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_scatter_seg, dim3(chunks(maxnk, 256, 2048), (unsigned)fin.size()), dim3(256), 0, s,
+                         (const SegDesc*)E_.seg_d, (const int*)(E_.tab_d + off), KP, (const double*)E_.Xc.p);
+      PMOR_HIP(hipGetLastError());
+      PMOR_HIP(hipStreamSynchronize(s));
+      for (int i : fin) {
+        done.push_back(item_[i]);
+        item_[i] = nullptr;
+        give_rows(r0_[i], nrows_[i]);
+        free_slots_.push_back(i);
+      }
+    }
+    return PMOR_OK;
+  }
+
+ private:
+  static int64_t rows_of(int n) { return std::max<int64_t>(16, ((int64_t)n + 15) / 16 * 16); }
+
+  // first fit over the free row ranges; -1 when nothing fits
+  static int64_t take_rows(std::vector<std::pair<int64_t, int64_t>>& fr, int64_t need) {
+    for (size_t t = 0; t < fr.size(); ++t)
+      if (fr[t].second >= need) {
+        const int64_t at = fr[t].first;
+        fr[t].first += need;
+        fr[t].second -= need;
+        if (fr[t].second == 0) fr.erase(fr.begin() + t);
+        return at;
+      }
+    return -1;
+  }
+
+  void give_rows(int64_t at, int64_t len) {
+    auto& fr = free_rows_;
+    size_t t = 0;
+    while (t < fr.size() && fr[t].first < at) ++t;
+    fr.insert(fr.begin() + t, {at, len});
+    if (t + 1 < fr.size() && fr[t].first + fr[t].second == fr[t + 1].first) {
+      fr[t].second += fr[t + 1].second;
+      fr.erase(fr.begin() + t + 1);
+    }
+    if (t > 0 && fr[t - 1].first + fr[t - 1].second == fr[t].first) {
+      fr[t - 1].second += fr[t].second;
+      fr.erase(fr.begin() + t);
+    }
+  }
+
+  // one restart cycle of every active segment (tables already uploaded)
+  int run_cycle(int64_t Gtot, int64_t SPtot, int nact, bool anyq) {
+    hipStream_t s = ctx_->stream;
+    const int m = o_.m;
+    Engine& E = E_;
+    KArgs a{};
+    a.m = m;
+    a.ldh = E.ldh;
+    a.vstride = rows_cap_ * KP;
+    a.V = E.V.p; a.W = E.W.p;
+    a.seg = E.seg_d;
+    a.Hc = E.Hc.p; a.hcs = E.hcs; a.hc2off = E.hc2off;
+    a.Hbar = E.Hbar.p; a.hbs = E.hbs;
+    a.G = E.G.p; a.gs = E.gs;
+    a.refl = E.refl.p; a.rfs = E.rfs;
+    a.Y = E.Y.p; a.ys = E.ys;
+    a.part = E.part.p; a.lstride = E.lstride;
+    a.partg = E.partg.p;
+    a.st = E.st;
+    a.hinfo = E.hinfo_d;
+    a.wtab = E.tab_d;
+    a.slist = E.tab_d + Gtot + SPtot;
+    const int* stab_d = E.tab_d + Gtot;
+    const unsigned gR = (unsigned)Gtot, gS = (unsigned)SPtot;
+    const int lpr = lpr_;
+    pmor_ctx* ctx = ctx_;
+    Profiler& prof = ctx->prof;
+    auto prof_seg = [&](int pr, int tag, auto bytes_of) {
+      if (pr < 0) return;
+      const int e0 = (int)prof.ent.size();
+      for (int i : act_) prof.ent.push_back({i, bytes_of(i)});
+      prof_stop_seg(ctx, pr, tag, e0);
+    };
+    auto blkb = [&](int i) { return 8.0 * (double)item_[i]->n * KP; };
+    // initial block QR of R_0: V_0 S = R_0 (S -> G)
+    hipLaunchKernelGGL(k_init_cycle, dim3(nact), dim3(256), 0, s, a, KP);
+    a.mode = 1; a.nbl = 0; a.zero_init = 0; a.ignore_done = 0; a.W = E.W.p;
+    a.Hsrc = E.Hc.p + E.hc2off; a.hsrc_stride = E.hcs; a.hsign = 1.0;
+    launch_upd<KP, UPD_P2>(ctx, -1, gR, s, a, 0);
+    hipLaunchKernelGGL(k_reduce_seg, dim3((KP * KP + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
+                       E.lstride, KP * KP, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p,
+                       E.hcs, E.hc2off);
+    launch_upd<KP, UPD_P3>(ctx, -1, gR, s, a, 0);
+    hipLaunchKernelGGL((k_hess<KP>), dim3(nact), dim3(256), 0, s, a);
+    PMOR_HIP(hipGetLastError());
+    a.mode = 0;
+    prof_first_ = (int)prof.recs.size();
+    hipEvent_t* evs = ctx->evs;
+    const int LOOKAHEAD = 2;
     for (int jj = 0; jj < m; ++jj) {
-      // Z = P V_j ; W = A Z  (V_j is block jj; the kernels skip once the cycle is done)
-      const double* Vj = ws.V + (int64_t)jj * blk;
-      const double blkb = 8.0 * (double)n * KP;
-      int pr = prof_start(pb->ctx, PMOR_PROF_SPMM_P);
-      if (h) PMOR_TRY(apply_P(pb, h, Vj, ws.Z, ws.T, KP, kact, ws.st, 0.0, s, pr));
-      else plaunch(pb->ctx, pr, 3, k_copy_axpby, dim3(fgrid), dim3(256), 0, s, blk, (const double*)Vj, ws.Z, 0.0);
-      prof_stop(pb->ctx, pr, h ? 12.0 * h->nnzP + 4.0 * (n + 1) + 2 * blkb : 2 * blkb, jj);
-      pr = prof_start(pb->ctx, PMOR_PROF_SPMM_A);
-      PMOR_TRY(launch_spmm(n, pb->rowptr, pb->col, pb->aval, ws.Z, KP, ws.W, KP, KP, kact, 1.0, 0.0, nullptr, 0,
-                           ws.st, s, pb->ctx, pr, 3));
-      prof_stop(pb->ctx, pr, 12.0 * pb->nnz + 4.0 * (n + 1) + 2 * blkb, jj);
-      a.nbl_mode = 0;
-      const int L1 = (jj + 1) * KP * KP + KP, L2 = (jj + 1) * KP * KP;
-      pr = prof_start(pb->ctx, PMOR_PROF_CGS_DOT);
-      PMOR_TRY((L.template dot<KP, NW, BPW>(pr)));
-      prof_stop(pb->ctx, pr, blkb * (jj + 2), jj);
-      hipLaunchKernelGGL(k_reduce_cols, dim3((L1 + 7) / 8), dim3(256), 0, s, ws.part, L1, L.G, a.Hc1, ws.st, 1);
-      a.Hsrc = a.Hc1; a.hsign = 1.0;
-      pr = prof_start(pb->ctx, PMOR_PROF_CGS_UPD_DOT);
-      PMOR_TRY((L.template upd<KP, NW, BPW, true, false>(jj + 1, pr)));
-      prof_stop(pb->ctx, pr, blkb * (jj + 3), jj);
-      hipLaunchKernelGGL(k_reduce_cols, dim3((L2 + 7) / 8), dim3(256), 0, s, ws.part, L2, L.G, a.Hc2, ws.st, 1);
-      a.Hsrc = a.Hc2;
-      pr = prof_start(pb->ctx, PMOR_PROF_CGS_UPD_GRAM);
-      PMOR_TRY((L.template upd<KP, NW, BPW, false, true>(jj + 1, pr)));
-      prof_stop(pb->ctx, pr, blkb * (jj + 3), jj);
-      PMOR_TRY((L.template scale<KP, NW, true>()));
-      PMOR_TRY((L.template scale<KP, NW, false>()));
-      hipLaunchKernelGGL((k_hess<KP>), dim3(1), dim3(64), hess_shm, s, a);
+      // Z = P V_j (V_j = W1 R2^{-1} written on the way); W = A Z
+      SpArgs sp{E.seg_d, stab_d, E.st, 1, 1, E.W.p, E.Z.p, E.T.p, nullptr, 1.0, 0.0,
+                E.V.p + (int64_t)jj * a.vstride, 1};
+      int pr = prof_start(ctx, PMOR_PROF_SPMM_P);
+      launch_spmm_seg<KP, true>(ctx, pr, anyq ? 1 : 3, gS, lpr, s, sp);
+      if (anyq) {
+        SpArgs sq{E.seg_d, stab_d, E.st, 2, 1, E.T.p, E.Z.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};
+        launch_spmm_seg<KP, false>(ctx, pr, 2, gS, lpr, s, sq);
+      }
+      prof_seg(pr, jj, [&](int i) {
+        const double mat = 12.0 * item_[i]->nnzP + 4.0 * (item_[i]->n + 1);
+        if (item_[i]->pkind == 0) return 3.0 * blkb(i);
+        if (item_[i]->pkind == 1) return mat + 3.0 * blkb(i);
+        return 2.0 * mat + 5.0 * blkb(i);
+      });
+      SpArgs sa{E.seg_d, stab_d, E.st, 0, 1, E.Z.p, E.W.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};
+      pr = prof_start(ctx, PMOR_PROF_SPMM_A);
+      launch_spmm_seg<KP, false>(ctx, pr, 3, gS, lpr, s, sa);
+      prof_seg(pr, jj, [&](int i) { return 12.0 * item_[i]->nnzA + 4.0 * (item_[i]->n + 1) + 2.0 * blkb(i); });
+      a.nbl = jj + 1;
+      const int L1 = (jj + 1) * KP * KP + KP, L2 = (jj + 1) * KP * KP + KP * KP;
+      pr = prof_start(ctx, PMOR_PROF_CGS_DOT);
+      launch_dot<KP>(ctx, pr, gR, s, a);
+      prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 2); });
+      hipLaunchKernelGGL(k_reduce_seg, dim3((L1 + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
+                         E.lstride, L1, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p, E.hcs,
+                         (int64_t)0);
+      a.Hsrc = E.Hc.p; a.hsrc_stride = E.hcs; a.hsign = 1.0;
+      pr = prof_start(ctx, PMOR_PROF_CGS_UPD_DOT);
+      launch_upd<KP, UPD_P2>(ctx, pr, gR, s, a, jj + 1);
+      prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 3); });
+      hipLaunchKernelGGL(k_reduce_seg, dim3((L2 + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
+                         E.lstride, L2, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p, E.hcs,
+                         E.hc2off);
+      a.Hsrc = E.Hc.p + E.hc2off;
+      pr = prof_start(ctx, PMOR_PROF_CGS_UPD_GRAM);
+      launch_upd<KP, UPD_P3>(ctx, pr, gR, s, a, jj + 1);
+      prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 3); });
+      hipLaunchKernelGGL((k_hess<KP>), dim3(nact), dim3(256), hess_shm_, s, a);
       PMOR_HIP(hipGetLastError());
       PMOR_HIP(hipEventRecord(evs[jj % 64], s));
       if (jj >= LOOKAHEAD) {
         PMOR_HIP(hipEventSynchronize(evs[(jj - LOOKAHEAD) % 64]));
-        if (((volatile int*)hflag)[1]) break;
+        bool all = true;
+        for (int i : act_)
+          if (!((volatile int*)E.hinfo_h)[4 * i + 1]) { all = false; break; }
+        if (all) break;
       }
     }
     // Y, X += P (V Y)
-    hipLaunchKernelGGL((k_ysolve<KP>), dim3(1), dim3(256), ys_shm, s, a, ys_pw);
-    a.nbl_mode = 2; a.Hsrc = ws.Y; a.hsign = -1.0; a.zero_init = 1; a.W = ws.T; a.ignore_done = 1;
-    PMOR_TRY((L.template upd<KP, NW, BPW, false, false>(m)));
-    a.W = ws.W; a.zero_init = 0; a.ignore_done = 0;
-    if (h) PMOR_TRY(apply_P(pb, h, ws.T, ws.Xc, ws.Z, KP, kact, nullptr, 1.0, s));
-    else hipLaunchKernelGGL(k_copy_axpby, dim3(fgrid), dim3(256), 0, s, blk, ws.T, ws.Xc, 1.0);
-    // residual R = B - A X into W, and its column norms
-    PMOR_TRY(launch_spmm(n, pb->rowptr, pb->col, pb->aval, ws.Xc, KP, ws.W, KP, KP, kact, -1.0, 1.0, ws.Bc, KP,
-                         nullptr, s));
-    double* nrm_dev = ws.Hcol + 2 * (ldh * KP + KP) + KP * KP;  // the residual-norm slots after the Gram matrix
-    const int cg = std::min(row_grid(n, 256), 256);
-    hipLaunchKernelGGL(k_colnorm2, dim3(cg), dim3(256), 0, s, n, ws.W, (int64_t)KP, KP, ws.part, ws.part2,
-                       dev_counters(ws.st), nrm_dev);
-    hipLaunchKernelGGL(k_reduce_cols, dim3((KP + 7) / 8), dim3(256), 0, s, ws.part, KP, cg, nrm_dev, ws.st, 0);
-    PMOR_HIP(hipGetLastError());
-    double nrm2[KMAX];
-    PMOR_HIP(hipMemcpyAsync(nrm2, nrm_dev, sizeof(double) * KP, hipMemcpyDeviceToHost, s));
-    PMOR_HIP(hipMemcpyAsync(ws.st_host, ws.st, offsetof(DevState, R1), hipMemcpyDeviceToHost, s));
-    PMOR_HIP(hipStreamSynchronize(s));
-    const DevState& hs = *ws.st_host;
-    prof_drop_from(pb->ctx, prof_first, hs.j);
-    total_steps += hs.j;
-    if (stats && cyc < PMOR_MAX_CYCLES) stats->cycle_steps[cyc] = hs.j;
-    bool conv = true, nan = hs.nanflag != 0;
-    for (int c = 0; c < kact; ++c) {
-      relres_out[c] = std::sqrt(nrm2[c]) / bnorm[c];
-      if (!(relres_out[c] <= o.tol)) conv = false;
-      if (std::isnan(relres_out[c]) || std::isinf(relres_out[c])) nan = true;
+    hipLaunchKernelGGL((k_ysolve<KP>), dim3(nact), dim3(256), ys_shm_, s, a, ys_pw_);
+    a.nbl = -1; a.Hsrc = E.Y.p; a.hsrc_stride = E.ys; a.hsign = -1.0; a.zero_init = 1; a.ignore_done = 1;
+    a.W = E.T.p;
+    launch_upd<KP, UPD_PLAIN>(ctx, -1, gR, s, a, m);
+    a.W = E.W.p; a.zero_init = 0; a.ignore_done = 0;
+    SpArgs sx{E.seg_d, stab_d, E.st, 1, 0, E.T.p, E.Xc.p, E.Z.p, E.Xc.p, 1.0, 1.0, nullptr, 1};
+    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sx);
+    if (anyq) {
+      SpArgs sx2{E.seg_d, stab_d, E.st, 2, 0, E.Z.p, E.Xc.p, nullptr, E.Xc.p, 1.0, 1.0, nullptr, 1};
+      launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sx2);
     }
-    if (nan) { *status = PMOR_ENAN; ++cyc; break; }
-    if (conv) { *status = PMOR_OK; ++cyc; break; }
-    if (hs.breakdown) { *status = PMOR_EBREAKDOWN; ++cyc; break; }
+    // residual R = B - A X into W, and its column norms
+    SpArgs sr{E.seg_d, stab_d, E.st, 0, 0, E.Xc.p, E.W.p, nullptr, E.Bc.p, -1.0, 1.0, nullptr, 1};
+    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sr);
+    hipLaunchKernelGGL((k_colnorm_seg<KP>), dim3(gR), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_reduce_seg, dim3((KP + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p, E.lstride,
+                       KP, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 0, E.nrm.p, (int64_t)KMAX,
+                       (int64_t)0);
+    PMOR_HIP(hipGetLastError());
+    PMOR_HIP(hipMemcpyAsync(E.nrm_h, E.nrm.p, sizeof(double) * nslots_ * KMAX, hipMemcpyDeviceToHost, s));
+    PMOR_HIP(hipStreamSynchronize(s));
+    return PMOR_OK;
   }
-  *steps_out = total_steps;
-  *cycles_out = cyc;
+
+  pmor_ctx* ctx_;
+  Engine& E_;
+  pmor_solve_opts o_;
+  int64_t rows_cap_;
+  int nslots_;
+  int lpr_ = 2, sp_rows_ = 128;
+  size_t hess_shm_ = 0, ys_shm_ = 0;
+  int ys_pw_ = 32;
+  int prof_first_ = 0;
+  std::vector<SolveItem*> item_;
+  std::vector<int64_t> r0_, nrows_;
+  std::vector<int> Gw_, Gs_, cyc_, steps_of_;
+  std::vector<int> act_, pending_, free_slots_;
+  std::vector<std::pair<int64_t, int64_t>> free_rows_;
+  std::chrono::steady_clock::time_point t0_;
+};
+
+int runner_create(pmor_ctx* ctx, Engine* E, int k, const pmor_solve_opts& o, int64_t rows_cap, int nslots,
+                  Runner** out) {
+  *out = nullptr;
+  const int kp = pad_kp(std::max(k, 1));
+  if (o.m < 1 || o.m + 1 > 32) return fail(PMOR_EINVAL, "restart length m must be in 1..31");
+  if ((int64_t)(o.m + 1) * kp * kp > 8192) return fail(PMOR_EINVAL, "m and k too large for the Hessenberg kernel");
+  if (nslots < 1) return fail(PMOR_EINVAL, "the engine needs at least one slot");
+  Runner* r = nullptr;
+  int rc = PMOR_OK;
+  switch (kp) {
+#define RUNNER_CASE(K)                                          \
+    case K: {                                                   \
+      auto* t = new RunnerT<K>(ctx, E, o, rows_cap, nslots);    \
+      rc = t->init();                                           \
+      r = t;                                                    \
+      break;                                                    \
+    }
+    RUNNER_CASE(1) RUNNER_CASE(2) RUNNER_CASE(4) RUNNER_CASE(8) RUNNER_CASE(16)
+#undef RUNNER_CASE
+    default: return fail(PMOR_EINVAL, "bad block size");
+  }
+  if (rc != PMOR_OK) {
+    delete r;
+    return rc;
+  }
+  *out = r;
   return PMOR_OK;
 }
 
-int krylov_solve(pmor_problem* pb, const pmor_spai* h, const double* B, int64_t ldb, int k, double* X,
-                 int64_t ldx, const pmor_solve_opts& o, pmor_stats* stats) {
-  hipStream_t s = pb->ctx->stream;
-  const int n = pb->n;
-  const int kp = pad_kp(k);
-  if (o.m + 1 > 32) return fail(PMOR_EINVAL, "restart length m must be <= 31");
-  if ((int64_t)(o.m + 1) * kp * kp > 8192) return fail(PMOR_EINVAL, "m and k too large for the Hessenberg kernel");
-  PMOR_TRY(ensure_workspace(pb, kp, o.m));
-  Workspace& ws = pb->ws;
-  // norms of the caller's columns
-  double* nrm_dev = ws.Hcol;
-  const int cg = std::min(row_grid(n, 256), 256);
-  hipLaunchKernelGGL(k_colnorm2, dim3(cg), dim3(256), 0, s, n, B, ldb, k, ws.part, ws.part2, dev_counters(ws.st),
-                     nrm_dev);
-  hipLaunchKernelGGL(k_reduce_cols, dim3((k + 7) / 8), dim3(256), 0, s, ws.part, k, cg, nrm_dev, ws.st, 0);
-  PMOR_HIP(hipGetLastError());
-  double bn[KMAX];
-  PMOR_HIP(hipMemcpyAsync(bn, nrm_dev, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  PMOR_HIP(hipStreamSynchronize(s));
-  ColMap act{}, inv{};
-  int kact = 0;
-  double bnorm[KMAX];
-  for (int c = 0; c < k; ++c) {
-    inv.idx[c] = -1;
-    if (std::isnan(bn[c]) || std::isinf(bn[c])) return fail(PMOR_ENAN, "NaN or Inf in the right-hand side");
-    if (bn[c] > 0.0) {
-      inv.idx[c] = kact;
-      act.idx[kact] = c;
-      bnorm[kact] = std::sqrt(bn[c]);
-      ++kact;
-    }
+Engine* engine_new() { return new Engine(); }
+
+int krylov_batch(pmor_ctx* ctx, SolveItem* items, int nitems, const pmor_solve_opts& o) {
+  if (nitems <= 0) return PMOR_OK;
+  int kmax = 1;
+  int64_t rows = 0;
+  for (int i = 0; i < nitems; ++i) {
+    kmax = std::max(kmax, items[i].k);
+    rows += std::max<int64_t>(16, ((int64_t)items[i].n + 15) / 16 * 16);
   }
-  if (stats) {
-    stats->k = k;
-    for (int c = 0; c < PMOR_KMAX; ++c) stats->relres[c] = 0.0;
-  }
-  const int64_t blk = (int64_t)n * kp;
-  if (kact == 0) {
-    hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)(((int64_t)n * k + 255) / 256)), dim3(256), 0, s, n, ws.Xc,
-                       kp, k, inv, X, ldx);
-    PMOR_HIP(hipGetLastError());
-    PMOR_HIP(hipStreamSynchronize(s));
-    if (stats) { stats->cycles = 0; stats->steps = 0; }
-    return PMOR_OK;
-  }
-  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, n, B, ldb, kp, kact, act,
-                     ws.Bc);
-  PMOR_HIP(hipGetLastError());
-  int steps = 0, cycles = 0, status = PMOR_OK;
-  double relres[KMAX];
-  switch (kp) {
-    case 1: PMOR_TRY(run_cycles<1>(pb, h, kact, o, stats, bnorm, &steps, &cycles, relres, &status)); break;
-    case 2: PMOR_TRY(run_cycles<2>(pb, h, kact, o, stats, bnorm, &steps, &cycles, relres, &status)); break;
-    case 4: PMOR_TRY(run_cycles<4>(pb, h, kact, o, stats, bnorm, &steps, &cycles, relres, &status)); break;
-    case 8: PMOR_TRY(run_cycles<8>(pb, h, kact, o, stats, bnorm, &steps, &cycles, relres, &status)); break;
-    case 16: PMOR_TRY(run_cycles<16>(pb, h, kact, o, stats, bnorm, &steps, &cycles, relres, &status)); break;
-    default: return fail(PMOR_EINVAL, "bad block size");
-  }
-  hipLaunchKernelGGL(k_scatter_cols, dim3((unsigned)(((int64_t)n * k + 255) / 256)), dim3(256), 0, s, n, ws.Xc, kp, k,
-                     inv, X, ldx);
-  PMOR_HIP(hipGetLastError());
-  PMOR_HIP(hipStreamSynchronize(s));
-  if (stats) {
-    stats->cycles = cycles;
-    stats->steps = steps;
-    for (int c = 0; c < k; ++c) stats->relres[c] = (inv.idx[c] >= 0) ? relres[inv.idx[c]] : 0.0;
-  }
-  if (status == PMOR_ENOTCONV) return fail(status, "block GMRES did not converge within max_cycles");
-  if (status == PMOR_EBREAKDOWN) return fail(status, "block breakdown: rank-deficient block with unconverged columns");
-  if (status == PMOR_ENAN) return fail(status, "NaN or Inf in a residual");
-  return PMOR_OK;
+  if (!ctx->eng) ctx->eng = new Engine();
+  Runner* r = nullptr;
+  PMOR_TRY(runner_create(ctx, ctx->eng, kmax, o, rows, nitems, &r));
+  std::vector<SolveItem*> ptrs(nitems);
+  for (int i = 0; i < nitems; ++i) ptrs[i] = &items[i];
+  int rc = r->admit(ptrs.data(), nitems);
+  std::vector<SolveItem*> done;
+  while (rc == PMOR_OK && r->busy() > 0) rc = r->cycle(done);
+  delete r;
+  return rc;
 }
 
 }  // namespace pmor

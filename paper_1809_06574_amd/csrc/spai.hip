@@ -390,8 +390,8 @@ __global__ void k_sum_in_order(const double* part, int np, double* out) {
   }
 }
 
-// sum of squares of x[0..n), deterministic; result left in dev_out[0]
-static int sumsq(const double* x, int64_t n, double* dev_scratch, hipStream_t st) {
+// sum of squares of x[0..n), deterministic; result left in dev_scratch[0]
+int sumsq(const double* x, int64_t n, double* dev_scratch, hipStream_t st) {
   const int np = 256;
   hipLaunchKernelGGL(k_sumsq_partials, dim3(np), dim3(256), 0, st, x, n, dev_scratch + 1);
   hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, st, dev_scratch + 1, np, dev_scratch);
@@ -464,6 +464,16 @@ __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscsl
   for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qi * P1[e];
 }
 
+int launch_update_diag(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int* dbad) {
+  pmor_problem* pb = h->pb;
+  const int n = pb->n;
+  if (n == 0) return PMOR_OK;
+  hipLaunchKernelGGL(k_update_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb->ctx->stream, n, pb->colptr,
+                     pb->cscslot, aval_l, h->aval1, h->Prowptr, h->P1val, pl, q, rho, dbad);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2) {
   pmor_problem* pb = h->pb;
   hipStream_t st = pb->ctx->stream;
@@ -471,9 +481,7 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
   int* dbad = reinterpret_cast<int*>(h->red);
   const int big = 0x7fffffff;
   PMOR_TRY(set_device_int(dbad, big, st));
-  hipLaunchKernelGGL(k_update_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
-                     pb->cscslot, aval_l, h->aval1, h->Prowptr, h->P1val, h->Pval, h->Qval, h->rho, dbad);
-  PMOR_HIP(hipGetLastError());
+  PMOR_TRY(launch_update_diag(h, aval_l, h->Pval, h->Qval, h->rho, dbad));
   if (bad_col || fro2) {
     double* dsum = h->red + 1;
     PMOR_TRY(sumsq(h->rho, n, dsum, st));

@@ -45,6 +45,15 @@ class SolveOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("max_cycles", C.c_int32), ("tol", C.c_double)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("pb", C.c_void_p), ("h", C.c_void_p), ("s", C.c_double), ("p", C.c_double),
+                ("B", C.c_void_p), ("ldb", C.c_int64), ("k", C.c_int32), ("X", C.c_void_p), ("ldx", C.c_int64)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("engine_rows", C.c_int64), ("k", C.c_int32), ("max_systems", C.c_int32)]
+
+
 class Stats(C.Structure):
     _fields_ = [("k", C.c_int32), ("cycles", C.c_int32), ("steps", C.c_int32), ("bad_column", C.c_int32),
                 ("cycle_steps", C.c_int32 * PMOR_MAX_CYCLES), ("relres", C.c_double * PMOR_KMAX),
@@ -63,6 +72,13 @@ P = C.c_void_p
 I32, I64, D = C.c_int32, C.c_int64, C.c_double
 PP = C.POINTER(C.c_void_p)
 
+
+class Job(C.Structure):
+    _fields_ = [("pb", C.c_void_p), ("B", C.c_void_p), ("ldb", C.c_int64), ("k", C.c_int32),
+                ("s_list", C.POINTER(C.c_double)), ("p_list", C.POINTER(C.c_double)), ("npts", C.c_int32),
+                ("X", C.c_void_p), ("ldx", C.c_int64), ("policy", C.c_int32), ("stats", C.POINTER(Stats))]
+
+
 _SIGS = {
     "pmor_ctx_create": (C.c_int, [PP, C.c_int, P]),
     "pmor_ctx_destroy": (None, [P]),
@@ -80,8 +96,15 @@ _SIGS = {
     "spai_export_sets": (C.c_int, [P, P, P, P, P, C.POINTER(I64)]),
     "spai_free": (None, [P]),
     "block_solve": (C.c_int, [P, P, D, D, P, I64, I32, P, I64, C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "pmor_batch_solve": (C.c_int, [P, C.POINTER(BatchItem), I32, C.POINTER(SolveOpts), C.POINTER(Stats),
+                                   C.POINTER(I32)]),
     "pmor_sequence_solve": (C.c_int, [P, P, I64, I32, P, P, I32, P, I64, I32, C.POINTER(SpaiOpts),
                                       C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "pmor_server_create": (C.c_int, [P, C.POINTER(ServerOpts), C.POINTER(SpaiOpts), C.POINTER(SolveOpts), PP]),
+    "pmor_server_destroy": (None, [P]),
+    "pmor_server_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(I64)]),
+    "pmor_server_step": (C.c_int, [P, C.POINTER(I64), C.POINTER(I32), I32, C.POINTER(I32)]),
+    "pmor_server_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]),
     "pmor_table2_norms": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
     "pmor_spmm": (C.c_int, [P, P, P, I64, P, I64, I32, D, D]),
     "pmor_prof_set": (C.c_int, [P, C.c_int]),

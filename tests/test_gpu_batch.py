@@ -1,0 +1,158 @@
+"""Batched solves: several independent systems in one lockstep block GMRES.
+
+Each system of a batch must give bit for bit the X it gets when solved alone
+(its sums depend on its own sizes only), every column must reach the 1e-8
+relative residual, and the X must match the oracle's block GMRES run for the
+same number of block steps with the GPU's preconditioner (1e-10 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import config0, tiny_random_job
+from synth.gen import _power_law_sizes, _nearest_pattern, _weighted_mdk, Job
+from oracle.assemble import Assembled
+from oracle.gmres import block_gmres
+from oracle.sparse import to_scipy
+from tests._helpers import np_, ctx as make_ctx, gpu_P_apply
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    return make_ctx()
+
+
+def _residuals(job, s, p, X):
+    asm = Assembled(job)
+    A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(s, p))
+    B = job.B
+    nb = np.linalg.norm(B, axis=0)
+    return np.linalg.norm(B - A @ X, axis=0) / np.where(nb > 0, nb, 1.0), A
+
+
+def _oracle_parity(job, s, p, h, Xg, st, update_kind="diag", q_active=False, m=30):
+    rel, A = _residuals(job, s, p, Xg)
+    assert np.all(rel <= 1e-8), rel
+    Pf = gpu_P_apply(h.export(), job.n, update_kind, q_active) if h is not None else (lambda X: X)
+    Xo, _ = block_gmres(A.__matmul__, Pf, job.B, m=m, tol=1e-8, fixed_steps=st["cycle_steps"])
+    d = np.linalg.norm(Xg - Xo) / max(np.linalg.norm(Xo), 1e-300)
+    assert d <= 1e-10, (d, st)
+
+
+def _systems(ctx):
+    from paper_1809_06574_amd import Problem
+    jobs = [tiny_random_job(300, 0.02, 11, k=2), config0(), tiny_random_job(515, 0.012, 12, k=2),
+            tiny_random_job(129, 0.05, 13, k=2)]
+    out = []
+    for i, job in enumerate(jobs):
+        pb = Problem(ctx, job.terms)
+        upd = "pattern" if i == 2 else "diag"
+        h = pb.spai_build(job.s, job.p_list[0], update=upd)
+        p = job.p_list[1]
+        if i != 3:
+            h.update(job.s, p)
+        out.append((job, pb, None if i == 3 else h, p, upd))
+    return out
+
+
+def test_batch_bitwise_equals_alone(ctx):
+    from paper_1809_06574_amd import batch_solve
+    sy = _systems(ctx)
+    items = [(pb, h, job.s, p, torch.as_tensor(job.B, device="cuda")) for job, pb, h, p, _ in sy]
+    Xs, stats, status, rc = batch_solve(ctx, items)
+    assert rc == 0 and all(x == 0 for x in status)
+    for (job, pb, h, p, upd), Xb, sb in zip(sy, Xs, stats):
+        Xa, sa, _ = pb.block_solve(h, job.s, p, torch.as_tensor(job.B, device="cuda"))
+        assert torch.equal(Xa, Xb), job.name
+        assert sa["cycle_steps"] == sb["cycle_steps"]
+        _oracle_parity(job, job.s, p, h, np_(Xb), sb, upd, q_active=(upd == "pattern"))
+
+
+def test_batch_mixed_block_widths(ctx):
+    """k = 1 and k = 3 systems share a kp = 4 batch; each matches its oracle."""
+    from paper_1809_06574_amd import Problem, batch_solve
+    jobs = [tiny_random_job(400, 0.015, 21, k=1), tiny_random_job(333, 0.02, 22, k=3)]
+    items, hs = [], []
+    for job in jobs:
+        pb = Problem(ctx, job.terms)
+        h = pb.spai_build(job.s, job.p_list[0])
+        hs.append((pb, h))
+        items.append((pb, h, job.s, job.p_list[0], torch.as_tensor(job.B, device="cuda")))
+    Xs, stats, status, rc = batch_solve(ctx, items, m=20)
+    assert rc == 0
+    for job, (pb, h), X, st in zip(jobs, hs, Xs, stats):
+        _oracle_parity(job, job.s, job.p_list[0], h, np_(X), st, m=20)
+
+
+def test_batch_shared_problem_points(ctx):
+    """Items of one problem at different points (the library assembles each)."""
+    from paper_1809_06574_amd import Problem, batch_solve
+    job = config0()
+    pb = Problem(ctx, job.terms)
+    B = torch.as_tensor(job.B, device="cuda")
+    items = [(pb, None, job.s, p, B) for p in job.p_list]
+    Xs, stats, status, rc = batch_solve(ctx, items)
+    assert rc == 0
+    for p, X, st in zip(job.p_list, Xs, stats):
+        Xa, sa, _ = pb.block_solve(None, job.s, p, B)
+        assert torch.equal(Xa, X)
+        _oracle_parity(job, job.s, p, None, np_(X), st)
+
+
+@pytest.mark.parametrize("policy,update", [("update", "diag"), ("update", "pattern"), ("rebuild", "diag")])
+def test_sequence_batched_equals_pointwise(ctx, policy, update):
+    from paper_1809_06574_amd import Problem
+    job = tiny_random_job(600, 0.004, 31, k=2, npts=5)
+    pb = Problem(ctx, job.terms)
+    B = torch.as_tensor(job.B, device="cuda")
+    s_list = [job.s] * len(job.p_list)
+    X, stats = pb.sequence_solve(B, s_list, job.p_list, policy=policy, update=update)
+    h = pb.spai_build(job.s, job.p_list[0], update=update)
+    for l, p in enumerate(job.p_list):
+        if l > 0:
+            (h.update if policy == "update" else h.rebuild)(job.s, p)
+        Xa, sa, _ = pb.block_solve(h, job.s, p, B)
+        assert torch.equal(Xa, X[l]), (policy, update, l)
+        assert sa["cycle_steps"] == stats[l]["cycle_steps"]
+        rel, _ = _residuals(job, job.s, p, np_(X[l]))
+        assert np.all(rel <= 1e-8)
+        assert stats[l]["t_solve_ms"] > 0
+
+
+def _power_law_system(i, dims):
+    rng = np.random.default_rng([2024, i])
+    terms = _weighted_mdk(dims, rng, 1e-3)
+    K = terms["K0"]
+    pat = _nearest_pattern(K, _power_law_sizes(rng, K.n))
+    p = float(rng.uniform(0.1, 1.0))
+    B = rng.standard_normal((K.n, 8))
+    return Job(f"powerlaw_{i}", K.n, terms, 2.0, np.array([p, p + 0.02]), B, pattern=pat)
+
+
+def test_batch_power_law_systems(ctx):
+    """Systems of several sizes with power-law SPAI patterns, k = 8, in one batch;
+    the update of each at its second point."""
+    from paper_1809_06574_amd import Problem, batch_solve
+    shapes = [(23, 17, 1), (9, 8, 6), (40, 31, 1), (7, 7, 7), (11, 10, 9), (30, 29, 1)]
+    jobs = [_power_law_system(i, d) for i, d in enumerate(shapes)]
+    sys_ = []
+    for job in jobs:
+        pb = Problem(ctx, job.terms)
+        h = pb.spai_build(job.s, job.p_list[0], pattern=job.pattern)
+        h.update(job.s, job.p_list[1])
+        sys_.append((pb, h))
+    items = [(pb, h, job.s, job.p_list[1], torch.as_tensor(job.B, device="cuda")) for job, (pb, h) in zip(jobs, sys_)]
+    Xs, stats, status, rc = batch_solve(ctx, items)
+    assert rc == 0
+    for q, (job, (pb, h), X, st) in enumerate(zip(jobs, sys_, Xs, stats)):
+        if q % 2 == 0:
+            _oracle_parity(job, job.s, job.p_list[1], h, np_(X), st)
+        else:
+            rel, _ = _residuals(job, job.s, job.p_list[1], np_(X))
+            assert np.all(rel <= 1e-8), rel
+    # the same systems alone: bit for bit
+    for (pb, h), job, X in zip(sys_[:2], jobs[:2], Xs[:2]):
+        Xa, _, _ = pb.block_solve(h, job.s, job.p_list[1], torch.as_tensor(job.B, device="cuda"))
+        assert torch.equal(Xa, X)
