@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--roofline-kernel", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
+    ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
+    ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
@@ -222,6 +224,10 @@ def main():
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
 
+    if args.serve_jobs > 0:
+        rhos = [float(x) for x in args.serve_rho.split(",")]
+        out["serving"] = serve_bench(ctx, rhos, args.serve_jobs)
+
     if not args.no_cpu_baseline:
         pb = factory()
         h = pb.spai_build(job.s, job.p_list[0])
@@ -229,6 +235,86 @@ def main():
         h.close(); pb.close()
         out["cpu_baseline"] = cpu_baseline(job, P1)
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, seed_base=0):
+    """Sequence jobs of the serving workload (n uniform over 32x32x16, 64x32x32, 64^3,
+    128x128x64; 20 points p0 + 0.02 j; k = 4) arriving as a Poisson process at
+    rate rho * mu_hat, served by one pmor_server (continuous batching).  mu_hat =
+    jobs/s of the server when n_cal jobs of the same mix arrive together.
+    Returns the report dict."""
+    import torch
+    from synth import config4_job
+    from paper_1809_06574_amd import Problem, Server
+
+    dev = ctx.device
+    cache = {}
+
+    def job_dev(jid):
+        if jid not in cache:
+            job = config4_job(jid)
+            terms = {r: (torch.as_tensor(T.rowptr, device=dev), torch.as_tensor(T.col, device=dev),
+                         torch.as_tensor(T.val, device=dev)) for r, T in job.terms.items()}
+            cache[jid] = (job, terms, torch.as_tensor(job.B, device=dev))
+        return cache[jid]
+
+    def run(jids, arrivals, keep=()):
+        sv = Server(ctx, k=4, engine_rows=engine_rows, max_systems=128)
+        t0 = time.perf_counter()
+        nxt, sub, fin, kept, meta = 0, {}, {}, {}, {}
+        solve_lat = []
+        while len(fin) < len(jids):
+            now = time.perf_counter() - t0
+            while nxt < len(jids) and arrivals[nxt] <= now:
+                job, terms, B = job_dev(jids[nxt])
+                t_arr = t0 + arrivals[nxt]
+                pb = Problem(ctx, terms)
+                jid = sv.submit(pb, B, [job.s] * len(job.p_list), job.p_list)
+                sub[jid] = (nxt, t_arr, time.perf_counter(), job.n)
+                nxt += 1
+            inf = sv.info()
+            if inf["queued"] + inf["admitted"] + inf["running"] == 0:
+                if nxt < len(jids):
+                    time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+                continue
+            for jid, status, X, stats in sv.step():
+                q, t_arr, t_sub, n = sub[jid]
+                fin[q] = (time.perf_counter() - t_arr, status, n)
+                solve_lat += [(t_sub - t_arr) + st["t_solve_ms"] * 1e-3 for st in stats]
+                if q in keep:
+                    kept[q] = X.clone()
+        makespan = time.perf_counter() - t0
+        sv.close()
+        return makespan, fin, solve_lat, kept
+
+    rng = np.random.default_rng(1004 + seed_base)
+    cal = list(range(10_000, 10_000 + n_cal))
+    mk, _, _, _ = run(cal, [0.0] * n_cal)
+    mu_hat = n_cal / mk
+    rep = {"mu_hat_jobs_per_s": mu_hat, "calibration": f"{n_cal} jobs of the mix submitted at once: {mk:.2f} s",
+           "jobs_per_run": n_jobs, "points_per_job": 20, "k": 4, "rho": {}}
+    for rho in rhos:
+        lam = rho * mu_hat
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=n_jobs))
+        arr -= arr[0]
+        jids = list(range(n_jobs))
+        keep = tuple(range(0, n_jobs, max(1, n_jobs // alone)))[:alone] if rho == rhos[-1] else ()
+        mk, fin, slat, kept = run(jids, list(arr), keep)
+        jl = [v[0] for v in fin.values()]
+        ok = all(v[1] == 0 for v in fin.values())
+        rep["rho"][str(rho)] = {
+            "arrival_rate_jobs_per_s": lam, "makespan_s": mk, "all_converged": ok,
+            "solves_per_s": 20 * n_jobs / mk, "jobs_per_s": n_jobs / mk,
+            "job_latency_ms": {"p50": 1e3 * _pct(jl, 50), "p99": 1e3 * _pct(jl, 99)},
+            "solve_latency_ms": {"p50": 1e3 * _pct(slat, 50), "p99": 1e3 * _pct(slat, 99)}}
+        if kept:
+            same = []
+            for q, Xm in kept.items():
+                _, _, _, ka = run([jids[q]], [0.0], keep=(0,))
+                same.append(bool(torch.equal(ka[0], Xm)))
+            rep["rho"][str(rho)]["alone_vs_mix_bitwise"] = {"jobs": len(same), "equal": all(same)}
+        cache.clear()
+    return rep
 
 
 def _prof_read(L, ctx):

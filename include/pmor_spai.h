@@ -70,6 +70,8 @@ enum pmor_role { PMOR_M0 = 0, PMOR_M1 = 1, PMOR_D0 = 2, PMOR_D1 = 3, PMOR_K0 = 4
 /* Arithmetic of the per-column least-squares problems: */
 #define PMOR_F64 0
 #define PMOR_F32 1
+#define PMOR_F16S 2   /* gathered block rounded to FP16 with a power-of-two scale per */
+                      /* column, arithmetic in FP32                               */
 /* Update kinds (pattern of Q_l, which the paper leaves open): */
 #define PMOR_UPD_DIAG 0     /* q_i has the single entry i: P_l = diag(q) P_1  */
 #define PMOR_UPD_PATTERN 1  /* q_i on the SPAI pattern J_i, applied as Q_l(P_1 X) */
@@ -92,7 +94,7 @@ typedef struct pmor_csr {
 
 typedef struct pmor_spai_opts {
   int32_t pattern;            /* PMOR_PAT_A or PMOR_PAT_EXPLICIT                */
-  int32_t precision;          /* PMOR_F64 or PMOR_F32                           */
+  int32_t precision;          /* PMOR_F64, PMOR_F32 or PMOR_F16S                */
   int32_t update;             /* PMOR_UPD_DIAG or PMOR_UPD_PATTERN              */
   int32_t nnz_explicit;       /* entries of the explicit pattern                */
   const int32_t* pat_colptr;  /* device, n+1; column j of P may hold rows       */

@@ -172,7 +172,7 @@ def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_err
 
 def _spai_opts(pattern, precision, update, device, keeper):
     o = L.SpaiOpts()
-    o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32}[precision]
+    o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32, "f16s": L.PMOR_F16S}[precision]
     o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN}[update]
     if pattern is None:
         o.pattern = L.PMOR_PAT_A

@@ -394,7 +394,8 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   o.update = PMOR_UPD_DIAG;
   if (opts) o = *opts;
   if (o.pattern != PMOR_PAT_A && o.pattern != PMOR_PAT_EXPLICIT) return fail(PMOR_EINVAL, "bad pattern kind");
-  if (o.precision != PMOR_F64 && o.precision != PMOR_F32) return fail(PMOR_EINVAL, "bad precision");
+  if (o.precision != PMOR_F64 && o.precision != PMOR_F32 && o.precision != PMOR_F16S)
+    return fail(PMOR_EINVAL, "bad precision");
   if (o.update != PMOR_UPD_DIAG && o.update != PMOR_UPD_PATTERN) return fail(PMOR_EINVAL, "bad update kind");
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   pmor_spai* h = new pmor_spai();

@@ -12,6 +12,8 @@
 // QR runs with one cross-lane reduction per reflector (the column norm and all
 // the inner products the reflector needs are summed together), then back
 // substitution broadcasts one unknown at a time.
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 
 #include "common.hpp"
@@ -115,7 +117,20 @@ __device__ __forceinline__ T row_bcast(T x, int k) {
   }
 }
 
-template <typename T, int JMAX, int R>
+// FP16 storage with a power-of-two scale per column: x -> half(x 2^-e) 2^e,
+// e = ilogb(max|x|) + 1 so the scaled column lies in (-1, 1); the arithmetic
+// stays in FP32.
+struct Q16Scale {
+  float sc, isc;
+};
+__device__ __forceinline__ Q16Scale q16_scale(float mx) {
+  if (!(mx > 0.0f) || !(mx < 3.0e38f)) return {1.0f, 1.0f};
+  const int e = ilogbf(mx) + 1;
+  return {ldexpf(1.0f, -e), ldexpf(1.0f, e)};
+}
+__device__ __forceinline__ float q16(float x, Q16Scale q) { return __half2float(__float2half_rn(x * q.sc)) * q.isc; }
+
+template <typename T, int JMAX, int R, bool Q16 = false>
 __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
   static_assert(JMAX <= 16, "row k of R must sit in lane k of the row");
   const int gl = threadIdx.x & 15;
@@ -149,6 +164,27 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       } else {
         b_[r] = (row == j) ? T(1) : T(0);
       }
+    }
+  }
+  if constexpr (Q16) {
+#pragma unroll
+    for (int t = 0; t < JMAX; ++t) {
+      if (t < nj) {
+        T mx = T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) mx = fmaxf(mx, fabsf(A_[r][t]));
+        const Q16Scale q = q16_scale(row_max(mx));
+#pragma unroll
+        for (int r = 0; r < R; ++r) A_[r][t] = q16(A_[r][t], q);
+      }
+    }
+    if (a.rhs_aval) {
+      T mx = T(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) mx = fmaxf(mx, fabsf(b_[r]));
+      const Q16Scale q = q16_scale(row_max(mx));
+#pragma unroll
+      for (int r = 0; r < R; ++r) b_[r] = q16(b_[r], q);
     }
   }
   T minDiag = T(3.0e38);
@@ -254,7 +290,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
 // ---------------------------------------------------------------------------
 // LDS kernel: |J| <= 64, |I| <= 512; one wavefront per workgroup
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool Q16 = false>
 __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   extern __shared__ unsigned char smem_raw[];
   T* S = reinterpret_cast<T*>(smem_raw);  // column-major [JM + 1][ldI]: A_hat then rhs
@@ -281,6 +317,17 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
     }
   }
   __syncthreads();
+  if constexpr (Q16) {
+    for (int t = 0; t <= nj; ++t) {
+      if (t == nj && !a.rhs_aval) break;
+      T* colt = (t < nj) ? S + (size_t)t * ldI : B;
+      T mx = T(0);
+      for (int li = lane; li < ni; li += 64) mx = fmaxf(mx, fabsf(colt[li]));
+      const Q16Scale q = q16_scale(wave_max(mx));
+      for (int li = lane; li < ni; li += 64) colt[li] = q16(colt[li], q);
+    }
+    __syncthreads();
+  }
   T minDiag = T(3.0e38);
   for (int k = 0; k < nj; ++k) {
     // one reduction per reflector: s[c] = x . a_c for c in [k, nj) and x . b
@@ -347,22 +394,22 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   }
 }
 
-template <typename T>
+template <typename T, bool Q16 = false>
 static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pmor_ctx* pc, int pidx, int part) {
   if (a.ncols == 0) return PMOR_OK;
   const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
   switch (b) {
-    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1>, dim3(g16), dim3(256), 0, st, a); break;
-    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2>, dim3(g16), dim3(256), 0, st, a); break;
-    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4>, dim3(g16), dim3(256), 0, st, a); break;
-    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4>, dim3(g16), dim3(256), 0, st, a); break;
-    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8>, dim3(g16), dim3(256), 0, st, a); break;
+    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16>, dim3(g16), dim3(256), 0, st, a); break;
+    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16>, dim3(g16), dim3(256), 0, st, a); break;
+    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
+    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
+    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16>, dim3(g16), dim3(256), 0, st, a); break;
     case 5: {
       const int ldI = ((maxI + 7) / 8) * 8;
       const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
-      PMOR_TRY(allow_lds((const void*)k_spai_lds<T>, shm));
-      plaunch(pc, pidx, part, k_spai_lds<T>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
+      PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16>, shm));
+      plaunch(pc, pidx, part, k_spai_lds<T, Q16>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
       break;
     }
     default: return fail(PMOR_EINVAL, "column outside the supported SPAI pattern sizes");
@@ -421,6 +468,8 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
     if (h->identity_order) { a.cols = nullptr; a.col_off = 0; }  // every column sits in bucket b
     else { a.cols = h->bucket_cols + h->bucket_off[b]; a.col_off = 0; }
     if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
+    else if (h->opts.precision == PMOR_F16S)
+      PMOR_TRY((launch_bucket<float, true>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part)));
     else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
   }
   prof_stop(pb->ctx, pr,

@@ -25,7 +25,7 @@ PMOR_NROLES = 6
 PMOR_MAX_CYCLES = 64
 ROLES = ("M0", "M1", "D0", "D1", "K0", "K1")
 PMOR_PAT_A, PMOR_PAT_EXPLICIT = 0, 1
-PMOR_F64, PMOR_F32 = 0, 1
+PMOR_F64, PMOR_F32, PMOR_F16S = 0, 1, 2
 PMOR_UPD_DIAG, PMOR_UPD_PATTERN = 0, 1
 PMOR_REBUILD, PMOR_UPDATE = 0, 1
 PROF_KERNELS = {"spmm_a": 1, "cgs_upd_dot": 2, "cgs_dot": 3, "spai_ls": 4, "spmm_p": 5, "cgs_upd_gram": 6}
