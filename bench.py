@@ -139,6 +139,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
     ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
+    ap.add_argument("--c2-systems", type=int, default=32, help="systems of the batch run (0: none)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -223,6 +224,9 @@ def main():
         out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
+
+    if args.c2_systems > 0:
+        out["batch_systems"] = c2_bench(ctx, args.c2_systems)
 
     if args.serve_jobs > 0:
         rhos = [float(x) for x in args.serve_rho.split(",")]
@@ -315,6 +319,63 @@ def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, se
             rep["rho"][str(rho)]["alone_vs_mix_bitwise"] = {"jobs": len(same), "equal": all(same)}
         cache.clear()
     return rep
+
+
+def _c2_system(i):
+    from synth.gen import config2_system
+    return config2_system(i)
+
+
+def c2_bench(ctx, nsys):
+    """Independent systems of the batch workload (n in [4096, 65536], 2-D/3-D,
+    k = 8, power-law SPAI patterns of 5..40 nodes): P_1 at p, the U-diag update
+    at p + 0.02, then the nsys solves at p + 0.02 together (pmor_batch_solve)
+    and one after another (block_solve)."""
+    import torch
+    import multiprocessing as mp
+    from paper_1809_06574_amd import Problem, batch_solve
+
+    # the generator runs in fresh interpreters (no fork of a process that holds the GPU)
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        jobs = pool.map(_c2_system, range(nsys))
+    dev = ctx.device
+    pbs, hs, Bs = [], [], []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for job in jobs:
+        pb = Problem(ctx, job.terms)
+        h = pb.spai_build(job.s, job.p_list[0], pattern=job.pattern)
+        h.update(job.s, job.p_list[1])
+        pbs.append(pb)
+        hs.append(h)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t
+    for job in jobs:
+        Bs.append(torch.as_tensor(job.B, device=dev))
+    items = [(pb, h, job.s, job.p_list[1], B) for pb, h, job, B in zip(pbs, hs, jobs, Bs)]
+    batch_solve(ctx, items)  # warm the engine buffers
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Xs, stats, status, rc = batch_solve(ctx, items)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    for pb, h, job, B in zip(pbs, hs, jobs, Bs):
+        pb.block_solve(h, job.s, job.p_list[1], B)
+    torch.cuda.synchronize()
+    t_point = time.perf_counter() - t
+    ns = [job.n for job in jobs]
+    out = {"systems": nsys, "n_min": min(ns), "n_max": max(ns), "k": 8,
+           "pattern_sizes": "power law t^-2 on [5, 40]", "all_converged": all(x == 0 for x in status),
+           "steps_total": int(sum(st["steps"] for st in stats)),
+           "setup_pattern_spai_update_s": t_prep,
+           "batched_solves_per_s": nsys / t_batch, "pointwise_solves_per_s": nsys / t_point,
+           "batched_vs_pointwise": t_point / t_batch}
+    for h in hs:
+        h.close()
+    for pb in pbs:
+        pb.close()
+    return out
 
 
 def _prof_read(L, ctx):
