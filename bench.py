@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
     ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
     ap.add_argument("--c2-systems", type=int, default=32, help="systems of the batch run (0: none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -147,6 +149,12 @@ def main():
               "shard; --gpus above 1 is not supported (DESIGN.md describes how the path would shard).",
               file=sys.stderr)
         sys.exit(2)
+
+    import tempfile
+    tune_file = os.environ.get("PMOR_TUNE_CACHE")
+    if tune_file is None:  # record what the library's tuner chooses in this run
+        tune_file = os.path.join(tempfile.mkdtemp(prefix="pmor_tune_"), "tune.json")
+        os.environ["PMOR_TUNE_CACHE"] = tune_file
 
     import torch
     from synth import config0, config1
@@ -163,6 +171,14 @@ def main():
 
     def factory():
         return Problem(ctx, terms)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # warmup (also builds every lazily created buffer)
     for _ in range(max(args.warmup, 0)):
@@ -238,6 +254,11 @@ def main():
         P1 = h.export()["val"].cpu().numpy()
         h.close(); pb.close()
         out["cpu_baseline"] = cpu_baseline(job, P1)
+    try:
+        with open(tune_file) as f:
+            out["tuning"] = json.load(f)
+    except (OSError, ValueError):
+        out["tuning"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -37,7 +37,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 namespace pmor {
@@ -274,7 +278,7 @@ __device__ __forceinline__ void rs_store_partials(double (*sred)[RS_ROW], int L,
 }
 
 // pass 1: partial [V_0..V_{nbl-1}]^T W (nbl 16 values) and ||W_c||^2 (4 values)
-template <int NW>
+template <int NW, int NB>
 __global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
   RowSeg r;
   if (!row_seg(a, true, r)) return;
@@ -284,24 +288,24 @@ __global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
   const double* W = a.W + r.r0 * 4;
   const double* V = a.V + r.r0 * 4;
   __shared__ double sred[NW][RS_ROW];
-  double acc[RS_B];
+  double acc[NB];
 #pragma unroll
-  for (int i = 0; i < RS_B; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
   double wn = 0.0;
   for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
     const int64_t off = ((int64_t)ch << 6) + lane;  // 16 rows x 4 columns = 64 doubles
     const bool valid = off < (int64_t)r.n * 4;
     const double wt = valid ? W[off] : 0.0;
     wn += wt * wt;
-    double v[RS_B];
+    double v[NB];
 #pragma unroll
-    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
 #pragma unroll
-    for (int i = 0; i < RS_B; ++i)
+    for (int i = 0; i < NB; ++i)
       if (i < nbl) acc[i] = mfma4(v[i], wt, acc[i]);
   }
 #pragma unroll
-  for (int i = 0; i < RS_B; ++i) {
+  for (int i = 0; i < NB; ++i) {
     double x = acc[i];
     x += __shfl_xor(x, 4, 64);
     x += __shfl_xor(x, 8, 64);
@@ -330,7 +334,7 @@ __device__ __forceinline__ double tile_transpose(double x, int lane) {
 // update and the products run on the FP64 MFMA: the transposed V tile is the A
 // operand, -hsign H the B operand and W the accumulator (D[i][j] at lane
 // 16i + 4b + j is the tile's own layout).
-template <int NW, int MODE>
+template <int NW, int MODE, int NB>
 __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   constexpr bool DOT = MODE == UPD_P2, GRAM = MODE != UPD_PLAIN, P3 = MODE == UPD_P3;
   RowSeg r;
@@ -351,21 +355,21 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   const double* hb = sH + (lane >> 4) * 4 + (lane & 3);
   double rb = 0.0;
   if constexpr (P3) rb = sRinv[(lane >> 4) * 4 + (lane & 3)];
-  double acc[DOT ? RS_B : 1];
+  double acc[DOT ? NB : 1];
 #pragma unroll
-  for (int i = 0; i < (DOT ? RS_B : 1); ++i) acc[i] = 0.0;
+  for (int i = 0; i < (DOT ? NB : 1); ++i) acc[i] = 0.0;
   double accg = 0.0;
   const bool write = P3 || nbl > 0 || a.zero_init;
   for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
     const int64_t off = ((int64_t)ch << 6) + lane;
     const bool valid = off < (int64_t)r.n * 4;
     const double wt = (valid && !a.zero_init) ? W[off] : 0.0;
-    double v[RS_B];
+    double v[NB];
 #pragma unroll
-    for (int i = 0; i < RS_B; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
     double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
 #pragma unroll
-    for (int i = 0; i < RS_B; i += 2) {
+    for (int i = 0; i < NB; i += 2) {
       if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
       if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
     }
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
     if (valid && write) W[off] = wnew;
     if (DOT) {
 #pragma unroll
-      for (int i = 0; i < RS_B; ++i)
+      for (int i = 0; i < NB; ++i)
         if (i < nbl) acc[i] = mfma4(v[i], wnew, acc[i]);
     }
     if (GRAM) accg = mfma4(wnew, wnew, accg);
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   int L = 0;
   if (DOT) {
 #pragma unroll
-    for (int i = 0; i < RS_B; ++i) {
+    for (int i = 0; i < NB; ++i) {
       double x = acc[i];
       x += __shfl_xor(x, 4, 64);
       x += __shfl_xor(x, 8, 64);
@@ -1147,8 +1151,10 @@ struct SpArgs {
   int vec;              // X rows may be read as double2
 };
 
+constexpr int SP_ROWS = 64;  // rows per SpMM workgroup (64 LPR threads)
+
 template <int KP, int LPR, bool CONV>
-__global__ __launch_bounds__(256) void k_spmm_seg(SpArgs a) {
+__global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
   const int lg = xcd_swizzle(blockIdx.x, gridDim.x);
   const int s = a.stab[lg];
   if (s < 0) return;
@@ -1180,7 +1186,7 @@ __global__ __launch_bounds__(256) void k_spmm_seg(SpArgs a) {
   const int64_t base = d.r0 * KP;
   const double* X = a.X + base;
   Y += base;
-  const int local = (lg - d.sp0) * (256 / LPR) + (int)threadIdx.x / LPR;
+  const int local = (lg - d.sp0) * SP_ROWS + (int)threadIdx.x / LPR;
   const int sub = (int)threadIdx.x % LPR;
   const bool valid = local < d.n;
   double acc[KP];
@@ -1315,6 +1321,83 @@ static int spmm_lanes_per_row() {
   }();
   return lpr;
 }
+
+// SpMM lanes-per-row tuning for the batched engine.  One value per (block
+// width, operator: A or the preconditioner), fixed for the process once
+// chosen, so a system's result never depends on the batch it runs in.
+// PMOR_SPMM_LPR pins every value; otherwise the first batch that needs a value
+// times the four candidates on its own matrices and keeps the fastest.
+// PMOR_TUNE_CACHE names a JSON file of the choices: read before tuning,
+// rewritten after it.
+namespace tune {
+static std::mutex mu;
+static std::map<std::string, int> table;
+static bool loaded = false;
+
+static std::string key(int kp, int which) {
+  return std::string(which == 0 ? "spmm_lanes_A_kp" : "spmm_lanes_P_kp") + std::to_string(kp);
+}
+
+// the cache is a flat JSON object of "name": integer pairs
+static void load_locked() {
+  if (loaded) return;
+  loaded = true;
+  const char* f = getenv("PMOR_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "r");
+  if (!fp) return;
+  std::string txt;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), fp)) > 0) txt.append(buf, got);
+  fclose(fp);
+  size_t i = 0;
+  while ((i = txt.find('"', i)) != std::string::npos) {
+    const size_t j = txt.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string name = txt.substr(i + 1, j - i - 1);
+    size_t c = txt.find(':', j);
+    if (c == std::string::npos) break;
+    const int v = atoi(txt.c_str() + c + 1);
+    if (v == 1 || v == 2 || v == 4 || v == 8) table[name] = v;
+    i = c + 1;
+  }
+}
+
+static void save_locked() {
+  const char* f = getenv("PMOR_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "w");
+  if (!fp) return;
+  fprintf(fp, "{");
+  bool first = true;
+  for (const auto& kv : table) {
+    fprintf(fp, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  fprintf(fp, "\n}\n");
+  fclose(fp);
+}
+
+// the chosen value, or 0 when it still has to be measured
+static int get(int kp, int which) {
+  if (getenv("PMOR_SPMM_LPR")) return spmm_lanes_per_row();
+  std::lock_guard<std::mutex> g(mu);
+  load_locked();
+  auto it = table.find(key(kp, which));
+  return it == table.end() ? 0 : it->second;
+}
+
+// first writer wins, so every batch of the process sees one value
+static int put(int kp, int which, int v) {
+  std::lock_guard<std::mutex> g(mu);
+  auto it = table.find(key(kp, which));
+  if (it != table.end()) return it->second;
+  table[key(kp, which)] = v;
+  save_locked();
+  return v;
+}
+}  // namespace tune
 
 template <int LPR>
 static int launch_spmm_lpr(int n, const int32_t* rowptr, const int32_t* col, const double* val, const double* X,
@@ -1603,10 +1686,20 @@ static int row_wgs(int n, int rows_per_iter, int gmax) {
   return (int)g;
 }
 
+// V blocks held in registers by the kp = 4 kernels: the smallest of 8, 16, 24,
+// 32 that covers the sweep (fewer registers, more wavefronts in flight)
+static int rs_nb(int nbl_max) { return nbl_max <= 8 ? 8 : (nbl_max <= 16 ? 16 : (nbl_max <= 24 ? 24 : 32)); }
+
 template <int KP>
-static void launch_dot(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a) {
+static void launch_dot(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a, int nbl_max) {
   using F = Fam<KP>;
-  if constexpr (F::RS) plaunch(c, pidx, 3, k_dot4<F::NW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  if constexpr (F::RS) {
+    const int nb = rs_nb(nbl_max);
+    if (nb == 8) plaunch(c, pidx, 3, k_dot4<F::NW, 8>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else if (nb == 16) plaunch(c, pidx, 3, k_dot4<F::NW, 16>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else if (nb == 24) plaunch(c, pidx, 3, k_dot4<F::NW, 24>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else plaunch(c, pidx, 3, k_dot4<F::NW, 32>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  }
   else if constexpr (F::ROW) plaunch(c, pidx, 3, k_dot_row<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
   else plaunch(c, pidx, 3, k_dot_mfma<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
 }
@@ -1622,7 +1715,7 @@ static size_t upd_shm(int nbl_max) {
 template <int KP, int MODE>
 static const void* upd_fn() {
   using F = Fam<KP>;
-  if constexpr (F::RS) return (const void*)k_upd4<F::NW, MODE>;
+  if constexpr (F::RS) return (const void*)k_upd4<F::NW, MODE, 32>;
   else if constexpr (F::ROW) return (const void*)k_upd_row<KP, F::NW, F::BPW, MODE>;
   else return (const void*)k_upd_mfma<KP, F::NW, F::BPW, MODE>;
 }
@@ -1631,8 +1724,13 @@ template <int KP, int MODE>
 static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a, int nbl_max) {
   using F = Fam<KP>;
   const uint32_t shm = (uint32_t)upd_shm<KP>(nbl_max);
-  if constexpr (F::RS) plaunch(c, pidx, 3, k_upd4<F::NW, MODE>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-  else if constexpr (F::ROW)
+  if constexpr (F::RS) {
+    const int nb = rs_nb(nbl_max);
+    if (nb == 8) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 8>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else if (nb == 16) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 16>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else if (nb == 24) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 24>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    else plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 32>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  } else if constexpr (F::ROW)
     plaunch(c, pidx, 3, k_upd_row<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
   else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
 }
@@ -1640,10 +1738,10 @@ static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, cons
 template <int KP, bool CONV>
 static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int lpr, hipStream_t s, const SpArgs& a) {
   switch (lpr) {
-    case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(256), 0, s, a); break;
-    case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(256), 0, s, a); break;
-    case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(256), 0, s, a); break;
-    default: plaunch(c, pidx, part, k_spmm_seg<KP, 2, CONV>, dim3(grid), dim3(256), 0, s, a); break;
+    case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(64 * 1), 0, s, a); break;
+    case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(64 * 4), 0, s, a); break;
+    case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(64 * 8), 0, s, a); break;
+    default: plaunch(c, pidx, part, k_spmm_seg<KP, 2, CONV>, dim3(grid), dim3(128), 0, s, a); break;
   }
 }
 
@@ -1667,8 +1765,7 @@ class RunnerT final : public Runner {
       : ctx_(c), E_(*e), o_(o), rows_cap_((rows_cap + 15) / 16 * 16), nslots_(nslots) {}
 
   int init() {
-    lpr_ = spmm_lanes_per_row();
-    sp_rows_ = 256 / lpr_;
+    sp_rows_ = SP_ROWS;
     const int64_t wg_cap = rows_cap_ / (2 * F::ROWS) + nslots_ + 8;
     const int64_t sp_cap = rows_cap_ / sp_rows_ + nslots_ + 8;
     PMOR_TRY(engine_reserve(E_, KP, o_.m, std::max<int64_t>(rows_cap_, 16), nslots_, wg_cap,
@@ -1843,6 +1940,9 @@ class RunnerT final : public Runner {
       }
       PMOR_HIP(hipMemcpyAsync(E_.seg_d, E_.seg_h, sizeof(SegDesc) * nslots_, hipMemcpyHostToDevice, s));
       PMOR_HIP(hipMemcpyAsync(E_.tab_d, E_.tab_h, sizeof(int) * (Gtot + SPtot + nact), hipMemcpyHostToDevice, s));
+      bool anyp = false;
+      for (int i : act_) anyp = anyp || item_[i]->pkind != 0;
+      PMOR_TRY(resolve_lanes(Gtot, SPtot, anyp));
       PMOR_TRY(run_cycle(Gtot, SPtot, nact, anyq));
       // verdicts
       const double t_now = now_ms();
@@ -1943,6 +2043,37 @@ class RunnerT final : public Runner {
     }
   }
 
+  // SpMM lanes per row for A and the preconditioner: the process-wide choice,
+  // measured here on this batch's matrices when none exists yet (the buffers T
+  // and Z are free at a cycle boundary)
+  int resolve_lanes(int64_t Gtot, int64_t SPtot, bool anyp) {
+    for (int which = 0; which < 2; ++which) {
+      int& lpr = which == 0 ? lprA_ : lprP_;
+      if (lpr != 0 || (which == 1 && !anyp)) continue;
+      int v = tune::get(KP, which);
+      if (v == 0) {
+        hipStream_t s = ctx_->stream;
+        SpArgs sp{E_.seg_d, E_.tab_d + Gtot, E_.st, which, 0, E_.W.p, E_.T.p, E_.Z.p, nullptr, 1.0, 0.0, nullptr, 1};
+        float best_ms = 3.0e38f;
+        v = 2;
+        for (int L : {1, 2, 4, 8}) {
+          for (int r = 0; r < 2; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);
+          PMOR_HIP(hipEventRecord(ctx_->ev0, s));
+          for (int r = 0; r < 3; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);
+          PMOR_HIP(hipEventRecord(ctx_->ev1, s));
+          PMOR_HIP(hipEventSynchronize(ctx_->ev1));
+          float ms = 0.f;
+          PMOR_HIP(hipEventElapsedTime(&ms, ctx_->ev0, ctx_->ev1));
+          if (ms < best_ms) { best_ms = ms; v = L; }
+        }
+        PMOR_HIP(hipGetLastError());
+        v = tune::put(KP, which, v);
+      }
+      lpr = v;
+    }
+    return PMOR_OK;
+  }
+
   // one restart cycle of every active segment (tables already uploaded)
   int run_cycle(int64_t Gtot, int64_t SPtot, int nact, bool anyq) {
     hipStream_t s = ctx_->stream;
@@ -1967,7 +2098,7 @@ class RunnerT final : public Runner {
     a.slist = E.tab_d + Gtot + SPtot;
     const int* stab_d = E.tab_d + Gtot;
     const unsigned gR = (unsigned)Gtot, gS = (unsigned)SPtot;
-    const int lpr = lpr_;
+    const int lprA = lprA_ ? lprA_ : 2, lprP = lprP_ ? lprP_ : 2;
     pmor_ctx* ctx = ctx_;
     Profiler& prof = ctx->prof;
     auto prof_seg = [&](int pr, int tag, auto bytes_of) {
@@ -1997,10 +2128,10 @@ class RunnerT final : public Runner {
       SpArgs sp{E.seg_d, stab_d, E.st, 1, 1, E.W.p, E.Z.p, E.T.p, nullptr, 1.0, 0.0,
                 E.V.p + (int64_t)jj * a.vstride, 1};
       int pr = prof_start(ctx, PMOR_PROF_SPMM_P);
-      launch_spmm_seg<KP, true>(ctx, pr, anyq ? 1 : 3, gS, lpr, s, sp);
+      launch_spmm_seg<KP, true>(ctx, pr, anyq ? 1 : 3, gS, lprP, s, sp);
       if (anyq) {
         SpArgs sq{E.seg_d, stab_d, E.st, 2, 1, E.T.p, E.Z.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};
-        launch_spmm_seg<KP, false>(ctx, pr, 2, gS, lpr, s, sq);
+        launch_spmm_seg<KP, false>(ctx, pr, 2, gS, lprP, s, sq);
       }
       prof_seg(pr, jj, [&](int i) {
         const double mat = 12.0 * item_[i]->nnzP + 4.0 * (item_[i]->n + 1);
@@ -2010,12 +2141,12 @@ class RunnerT final : public Runner {
       });
       SpArgs sa{E.seg_d, stab_d, E.st, 0, 1, E.Z.p, E.W.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};
       pr = prof_start(ctx, PMOR_PROF_SPMM_A);
-      launch_spmm_seg<KP, false>(ctx, pr, 3, gS, lpr, s, sa);
+      launch_spmm_seg<KP, false>(ctx, pr, 3, gS, lprA, s, sa);
       prof_seg(pr, jj, [&](int i) { return 12.0 * item_[i]->nnzA + 4.0 * (item_[i]->n + 1) + 2.0 * blkb(i); });
       a.nbl = jj + 1;
       const int L1 = (jj + 1) * KP * KP + KP, L2 = (jj + 1) * KP * KP + KP * KP;
       pr = prof_start(ctx, PMOR_PROF_CGS_DOT);
-      launch_dot<KP>(ctx, pr, gR, s, a);
+      launch_dot<KP>(ctx, pr, gR, s, a, jj + 1);
       prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 2); });
       hipLaunchKernelGGL(k_reduce_seg, dim3((L1 + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
                          E.lstride, L1, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p, E.hcs,
@@ -2049,14 +2180,14 @@ class RunnerT final : public Runner {
     launch_upd<KP, UPD_PLAIN>(ctx, -1, gR, s, a, m);
     a.W = E.W.p; a.zero_init = 0; a.ignore_done = 0;
     SpArgs sx{E.seg_d, stab_d, E.st, 1, 0, E.T.p, E.Xc.p, E.Z.p, E.Xc.p, 1.0, 1.0, nullptr, 1};
-    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sx);
+    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lprP, s, sx);
     if (anyq) {
       SpArgs sx2{E.seg_d, stab_d, E.st, 2, 0, E.Z.p, E.Xc.p, nullptr, E.Xc.p, 1.0, 1.0, nullptr, 1};
-      launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sx2);
+      launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lprP, s, sx2);
     }
     // residual R = B - A X into W, and its column norms
     SpArgs sr{E.seg_d, stab_d, E.st, 0, 0, E.Xc.p, E.W.p, nullptr, E.Bc.p, -1.0, 1.0, nullptr, 1};
-    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lpr, s, sr);
+    launch_spmm_seg<KP, false>(ctx, -1, 3, gS, lprA, s, sr);
     hipLaunchKernelGGL((k_colnorm_seg<KP>), dim3(gR), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_reduce_seg, dim3((KP + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p, E.lstride,
                        KP, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 0, E.nrm.p, (int64_t)KMAX,
@@ -2072,7 +2203,8 @@ class RunnerT final : public Runner {
   pmor_solve_opts o_;
   int64_t rows_cap_;
   int nslots_;
-  int lpr_ = 2, sp_rows_ = 128;
+  int sp_rows_ = SP_ROWS;
+  int lprA_ = 0, lprP_ = 0;  // SpMM lanes per row for A and for the preconditioner
   size_t hess_shm_ = 0, ys_shm_ = 0;
   int ys_pw_ = 32;
   int prof_first_ = 0;
