@@ -129,6 +129,12 @@ typedef struct pmor_stats {
  * `hip_stream` (a hipStream_t; NULL = the null stream).  Errors: PMOR_EHIP
  * when the device cannot be selected, PMOR_EINVAL for out == NULL. */
 int pmor_ctx_create(pmor_ctx** out, int device, void* hip_stream);
+/* Destroy calls may come in any order: the context lives on until its
+ * problems and servers are destroyed, a problem until its preconditioners and
+ * server jobs are.  Device memory the library releases is kept in a process-wide cache and
+ * handed out again (on the stream that released it at once, on another stream
+ * once the release has completed on the device); a failed allocation empties
+ * the cache and retries. */
 void pmor_ctx_destroy(pmor_ctx* ctx);
 /* Re-point the context at another stream of the same device. */
 int pmor_ctx_set_stream(pmor_ctx* ctx, void* hip_stream);

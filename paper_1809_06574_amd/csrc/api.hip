@@ -140,15 +140,18 @@ struct Timer {
 
 static void spai_release(pmor_spai* h) {
   if (!h) return;
-  if (h->own_J) { (void)hipFree(h->Jcolptr); (void)hipFree(h->Jrow); }
-  if (h->own_P) { (void)hipFree(h->Prowptr); (void)hipFree(h->Pcol); (void)hipFree(h->Pslot); }
+  (void)hipSetDevice(h->pb->ctx->device);
+  hipStream_t s = h->pb->ctx->stream;
+  if (h->own_J) { dfree(h->Jcolptr, s); dfree(h->Jrow, s); }
+  if (h->own_P) { dfree(h->Prowptr, s); dfree(h->Pcol, s); dfree(h->Pslot, s); }
   double* d[] = {h->Pval, h->P1val, h->Qval, h->aval1, h->rho, h->red};
-  for (double* x : d)
-    if (x) (void)hipFree(x);
-  if (h->Icolptr) (void)hipFree(h->Icolptr);
-  if (h->Irow) (void)hipFree(h->Irow);
-  if (h->bucket_cols) (void)hipFree(h->bucket_cols);
+  for (double* x : d) dfree(x, s);
+  dfree(h->Icolptr, s);
+  dfree(h->Irow, s);
+  dfree(h->bucket_cols, s);
+  pmor_problem* pb = h->pb;
   delete h;
+  pb_unref(pb);
 }
 
 __global__ void k_copy(const double* a, double* b, int64_t n) {
@@ -300,7 +303,17 @@ int pmor_ctx_create(pmor_ctx** out, int device, void* hip_stream) {
 }
 
 void pmor_ctx_destroy(pmor_ctx* c) {
-  if (!c) return;
+  if (c) ctx_unref(c);
+}
+
+}  // extern "C"
+
+namespace pmor {
+
+void ctx_ref(pmor_ctx* c) { ++c->refs; }
+
+void ctx_unref(pmor_ctx* c) {
+  if (--c->refs > 0) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   prof_collect(c);
@@ -312,6 +325,25 @@ void pmor_ctx_destroy(pmor_ctx* c) {
   engine_destroy(c->eng);
   delete c;
 }
+
+void pb_ref(pmor_problem* pb) { ++pb->refs; }
+
+void pb_unref(pmor_problem* pb) {
+  if (--pb->refs > 0) return;
+  pmor_ctx* c = pb->ctx;
+  (void)hipSetDevice(c->device);
+  hipStream_t s = c->stream;
+  int32_t* ip[] = {pb->rowptr, pb->col, pb->maps, pb->colptr, pb->rowidx, pb->cscslot};
+  for (int32_t* x : ip) dfree(x, s);
+  dfree(pb->tval, s);
+  dfree(pb->aval, s);
+  delete pb;
+  ctx_unref(c);
+}
+
+}  // namespace pmor
+
+extern "C" {
 
 int pmor_ctx_set_stream(pmor_ctx* c, void* hip_stream) {
   if (!c) return fail(PMOR_EINVAL, "ctx is NULL");
@@ -336,6 +368,7 @@ int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_proble
   PMOR_HIP(hipSetDevice(ctx->device));
   pmor_problem* pb = new pmor_problem();
   pb->ctx = ctx;
+  ctx_ref(ctx);
   pb->n = n;
   int rc = build_union_pattern(pb, terms);
   if (rc != PMOR_OK) {
@@ -347,13 +380,7 @@ int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_proble
 }
 
 void pmor_problem_destroy(pmor_problem* pb) {
-  if (!pb) return;
-  int32_t* ip[] = {pb->rowptr, pb->col, pb->maps, pb->colptr, pb->rowidx, pb->cscslot};
-  for (int32_t* x : ip)
-    if (x) (void)hipFree(x);
-  if (pb->tval) (void)hipFree(pb->tval);
-  if (pb->aval) (void)hipFree(pb->aval);
-  delete pb;
+  if (pb) pb_unref(pb);
 }
 
 int pmor_problem_info(const pmor_problem* pb, int32_t* n, int32_t* nnz) {
@@ -400,12 +427,13 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   pmor_spai* h = new pmor_spai();
   h->pb = pb;
+  pb_ref(pb);
   h->opts = o;
   int rc = build_spai_sets(h);
   if (rc == PMOR_OK) {
     const int64_t n = pb->n;
     auto al = [&](double** p, int64_t cnt) {
-      return hipMalloc((void**)p, sizeof(double) * std::max<int64_t>(cnt, 1)) == hipSuccess;
+      return dmalloc((void**)p, sizeof(double) * std::max<int64_t>(cnt, 1), pb->ctx->stream) == hipSuccess;
     };
     bool ok = al(&h->Pval, h->nnzP) && al(&h->P1val, h->nnzP) &&
               al(&h->Qval, o.update == PMOR_UPD_PATTERN ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
@@ -554,7 +582,7 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
         aval = b.pb->aval;
       } else {
         double* buf = nullptr;
-        if (hipMalloc((void**)&buf, sizeof(double) * std::max<int64_t>(b.pb->nnz, 1)) != hipSuccess) {
+        if (dmalloc((void**)&buf, sizeof(double) * std::max<int64_t>(b.pb->nnz, 1), st) != hipSuccess) {
           (void)hipGetLastError();
           rc = fail(PMOR_ENOMEM, "allocation of a point's A values failed");
           break;
@@ -569,7 +597,7 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
     it[i] = item_of(b.pb, b.h, aval, b.B, b.ldb, b.k, b.X, b.ldx, stats ? &stats[i] : nullptr);
   }
   if (rc == PMOR_OK) rc = krylov_batch(ctx, it.data(), nitems, o);
-  for (double* x : extra) (void)hipFree(x);
+  for (double* x : extra) dfree(x, st);
   if (rc != PMOR_OK) return rc;
   int first_bad = PMOR_OK;
   for (int i = 0; i < nitems; ++i) {
@@ -593,18 +621,19 @@ struct SeqBuffers {
   double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
   int* bad = nullptr;       // group
   int64_t bytes = 0;
+  hipStream_t stream = nullptr;
   SeqBuffers() = default;
   SeqBuffers(const SeqBuffers&) = delete;
   SeqBuffers& operator=(const SeqBuffers&) = delete;
   ~SeqBuffers() {
     void* v[] = {aval, pq, q, rho, fro, bad};
-    for (void* x : v)
-      if (x) (void)hipFree(x);
+    for (void* x : v) dfree(x, stream);
   }
-  int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n) {
+  int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n, hipStream_t s) {
+    stream = s;
     auto al = [&](void** p, size_t b) {
       b = std::max<size_t>(b, 8);
-      if (hipMalloc(p, b) != hipSuccess) {
+      if (dmalloc(p, b, stream) != hipSuccess) {
         (void)hipGetLastError();
         return fail(PMOR_ENOMEM, "allocation of the sequence buffers failed");
       }
@@ -773,7 +802,7 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   PMOR_HIP(hipMemGetInfo(&fr, &tot));
   const int group = (int)std::max(1.0, std::min<double>(npts, 0.6 * (double)fr / per_point));
   SeqBuffers sb;
-  rc = sb.alloc(group, nnz, nnzP, n);
+  rc = sb.alloc(group, nnz, nnzP, n, pb->ctx->stream);
   if (rc != PMOR_OK) { spai_release(h); return rc; }
   int first_bad = PMOR_OK;
   for (int l0 = 0; l0 < npts && rc == PMOR_OK; l0 += group) {
@@ -865,6 +894,7 @@ namespace pmor {
 static void job_finish(pmor_server* sv, ServerJob* J) {
   spai_release(J->h);
   J->h = nullptr;
+  pb_unref(J->job.pb);
   sv->in_use -= J->footprint;
   sv->reports.push_back({J->id, J->status});
   sv->jobs.erase(J->id);
@@ -879,7 +909,7 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   pre0.bad_column = -1;
   sv->jobs[J->id] = J;
   int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
-  if (rc == PMOR_OK) rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n);
+  if (rc == PMOR_OK) rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n, sv->ctx->stream);
   J->items.assign(npts, SolveItem{});
   J->bad.assign(npts, -1);
   if (rc == PMOR_OK)
@@ -931,6 +961,7 @@ int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_s
   PMOR_HIP(hipMemGetInfo(&fr0, &tot));
   pmor_server* sv = new pmor_server();
   sv->ctx = ctx;
+  ctx_ref(ctx);
   sv->sopts = so;
   sv->vopts = o;
   sv->k = opts->k;
@@ -963,10 +994,16 @@ void pmor_server_destroy(pmor_server* sv) {
   engine_destroy(sv->eng);
   for (auto& kv : sv->jobs) {
     spai_release(kv.second->h);
+    pb_unref(kv.second->job.pb);
     delete kv.second;
   }
-  for (ServerJob* J : sv->queue) delete J;
+  for (ServerJob* J : sv->queue) {
+    pb_unref(J->job.pb);
+    delete J;
+  }
+  pmor_ctx* c = sv->ctx;
   delete sv;
+  ctx_unref(c);
 }
 
 int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
@@ -989,6 +1026,7 @@ int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
   }
   J->id = sv->next_id++;
   J->t_submit = sv->run->now_ms();
+  pb_ref(job->pb);
   if (job->stats) std::memset(job->stats, 0, sizeof(pmor_stats) * job->npts);
   sv->queue.push_back(J);
   if (job_id) *job_id = J->id;
@@ -1056,14 +1094,14 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
                       double* fro_A1_minus_A2) {
   if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
   double* tmp = nullptr;
-  PMOR_HIP(hipMalloc((void**)&tmp, sizeof(double) * std::max<int64_t>(pb->nnz, 1)));
+  PMOR_HIP(dmalloc((void**)&tmp, sizeof(double) * std::max<int64_t>(pb->nnz, 1), pb->ctx->stream));
   PMOR_TRY(ensure_assembled(pb, s1, p1));
   PMOR_TRY(dcopy(pb->aval, tmp, pb->nnz, pb->ctx->stream));
   PMOR_TRY(ensure_assembled(pb, s2, p2));
   double a = 0.0, b = 0.0;
   PMOR_TRY(fro_norm2(pb, pb->aval, nullptr, pb->nnz, 1, &a));
   PMOR_TRY(fro_norm2(pb, tmp, pb->aval, pb->nnz, 0, &b));
-  (void)hipFree(tmp);
+  dfree(tmp, pb->ctx->stream);
   if (fro_I_minus_A2) *fro_I_minus_A2 = std::sqrt(a);
   if (fro_A1_minus_A2) *fro_A1_minus_A2 = std::sqrt(b);
   return PMOR_OK;

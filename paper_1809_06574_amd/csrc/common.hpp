@@ -104,6 +104,7 @@ struct Profiler {
 }  // namespace pmor
 
 struct pmor_ctx {
+  int refs = 1;                  // the caller's reference + one per problem and server
   int device = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -113,6 +114,7 @@ struct pmor_ctx {
 };
 
 struct pmor_problem {
+  int refs = 1;                // the caller's reference + one per preconditioner and queued job
   pmor_ctx* ctx = nullptr;
   int32_t n = 0, nnz = 0;
   int32_t* rowptr = nullptr;   // union pattern, CSR
@@ -167,6 +169,19 @@ inline void role_coefs(double s, double p, double c[PMOR_NROLES]) {
   c[PMOR_K0] = 1.0;
   c[PMOR_K1] = p;
 }
+
+// Lifetimes: a context lives until its caller and every problem and server of
+// it have let it go; a problem until its caller and every preconditioner and
+// server job of it have.  Destroy calls may therefore come in any order.
+void ctx_ref(pmor_ctx* c);
+void ctx_unref(pmor_ctx* c);
+void pb_ref(pmor_problem* pb);
+void pb_unref(pmor_problem* pb);
+
+// device memory of the library: a cache with stream-ordered reuse (memory.hip)
+hipError_t dmalloc(void** p, size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+void dtrim();
 
 int ensure_assembled(pmor_problem* pb, double s, double p);
 // kernel timing: start returns a record index (-1 when kernel class `kid` is not profiled)

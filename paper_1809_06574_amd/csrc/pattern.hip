@@ -60,8 +60,8 @@ int scan_exclusive(int64_t* buf, int64_t n, hipStream_t st) {
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
   int64_t* sums = nullptr;
   int64_t* last = nullptr;
-  PMOR_HIP(hipMalloc((void**)&sums, sizeof(int64_t) * (tiles + 1)));
-  PMOR_HIP(hipMalloc((void**)&last, sizeof(int64_t)));
+  PMOR_HIP(dmalloc((void**)&sums, sizeof(int64_t) * (tiles + 1), st));
+  PMOR_HIP(dmalloc((void**)&last, sizeof(int64_t), st));
   PMOR_HIP(hipMemcpyAsync(last, buf + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)tiles), dim3(SCAN_T), 0, st, buf, n, buf, sums);
   PMOR_HIP(hipGetLastError());
@@ -75,8 +75,8 @@ int scan_exclusive(int64_t* buf, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, st, buf, n, last, buf + n - 1);
   PMOR_HIP(hipGetLastError());
   PMOR_HIP(hipStreamSynchronize(st));
-  PMOR_HIP(hipFree(sums));
-  PMOR_HIP(hipFree(last));
+  dfree(sums, st);
+  dfree(last, st);
   return PMOR_OK;
 }
 
@@ -209,12 +209,12 @@ int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* 
   int64_t* cc = nullptr;
   int32_t* cursor = nullptr;
   int* dmax = nullptr;
-  PMOR_HIP(hipMalloc((void**)&cc, sizeof(int64_t) * (n + 1)));
-  PMOR_HIP(hipMalloc((void**)&cursor, sizeof(int32_t) * (n + 1)));
-  PMOR_HIP(hipMalloc((void**)&dmax, sizeof(int)));
-  PMOR_HIP(hipMalloc((void**)colptr, sizeof(int32_t) * (n + 1)));
-  PMOR_HIP(hipMalloc((void**)rowidx, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
-  PMOR_HIP(hipMalloc((void**)slot, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(dmalloc((void**)&cc, sizeof(int64_t) * (n + 1), st));
+  PMOR_HIP(dmalloc((void**)&cursor, sizeof(int32_t) * (n + 1), st));
+  PMOR_HIP(dmalloc((void**)&dmax, sizeof(int), st));
+  PMOR_HIP(dmalloc((void**)colptr, sizeof(int32_t) * (n + 1), st));
+  PMOR_HIP(dmalloc((void**)rowidx, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
+  PMOR_HIP(dmalloc((void**)slot, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
   PMOR_HIP(hipMemsetAsync(cc, 0, sizeof(int64_t) * (n + 1), st));
   PMOR_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (n + 1), st));
   PMOR_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
@@ -237,9 +237,9 @@ int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* 
   PMOR_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   *maxcol = hmax;
-  PMOR_HIP(hipFree(cc));
-  PMOR_HIP(hipFree(cursor));
-  PMOR_HIP(hipFree(dmax));
+  dfree(cc, st);
+  dfree(cursor, st);
+  dfree(dmax, st);
   return PMOR_OK;
 }
 
@@ -247,7 +247,7 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   hipStream_t st = pb->ctx->stream;
   const int n = pb->n;
   int* derr = nullptr;
-  PMOR_HIP(hipMalloc((void**)&derr, sizeof(int) * 2));
+  PMOR_HIP(dmalloc((void**)&derr, sizeof(int) * 2, st));
   PMOR_HIP(hipMemsetAsync(derr, 0, sizeof(int) * 2, st));
   TermPtrs tp{};
   int nt = 0;
@@ -272,13 +272,13 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   PMOR_HIP(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   if (herr) {
-    (void)hipFree(derr);
+    dfree(derr, st);
     return fail(PMOR_EINVAL, std::string("malformed term CSR (") +
                                  ((herr & 1) ? "rowptr " : "") + ((herr & 2) ? "column-range " : "") +
                                  ((herr & 4) ? "column-order" : "") + ")");
   }
   int64_t* cnt = nullptr;
-  PMOR_HIP(hipMalloc((void**)&cnt, sizeof(int64_t) * (n + 1)));
+  PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
   unsigned g = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_union<false>, dim3(g), dim3(256), 0, st, n, tp, cnt, nullptr, nullptr, nullptr, nullptr,
                      (int64_t)0, derr + 1);
@@ -290,17 +290,17 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   PMOR_HIP(hipMemcpyAsync(&maxrow, derr + 1, sizeof(int), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   if (nnz64 >= ((int64_t)1 << 31)) {
-    (void)hipFree(cnt); (void)hipFree(derr);
+    dfree(cnt, st); dfree(derr, st);
     return fail(PMOR_EINVAL, "union pattern has 2^31 or more entries");
   }
   pb->nnz = (int32_t)nnz64;
   pb->max_row_len = maxrow;
   const int64_t nnz = nnz64;
-  PMOR_HIP(hipMalloc((void**)&pb->rowptr, sizeof(int32_t) * (n + 1)));
-  PMOR_HIP(hipMalloc((void**)&pb->col, sizeof(int32_t) * (nnz > 0 ? nnz : 1)));
-  PMOR_HIP(hipMalloc((void**)&pb->maps, sizeof(int32_t) * PMOR_NROLES * (nnz > 0 ? nnz : 1)));
-  PMOR_HIP(hipMalloc((void**)&pb->tval, sizeof(double) * (nt > 0 ? nt : 1) * (nnz > 0 ? nnz : 1)));
-  PMOR_HIP(hipMalloc((void**)&pb->aval, sizeof(double) * (nnz > 0 ? nnz : 1)));
+  PMOR_HIP(dmalloc((void**)&pb->rowptr, sizeof(int32_t) * (n + 1), st));
+  PMOR_HIP(dmalloc((void**)&pb->col, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
+  PMOR_HIP(dmalloc((void**)&pb->maps, sizeof(int32_t) * PMOR_NROLES * (nnz > 0 ? nnz : 1), st));
+  PMOR_HIP(dmalloc((void**)&pb->tval, sizeof(double) * (nt > 0 ? nt : 1) * (nnz > 0 ? nnz : 1), st));
+  PMOR_HIP(dmalloc((void**)&pb->aval, sizeof(double) * (nnz > 0 ? nnz : 1), st));
   hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, cnt, pb->rowptr,
                      (int64_t)n + 1);
   PMOR_HIP(hipGetLastError());
@@ -308,8 +308,8 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
                      pb->tval, nnz, nullptr);
   PMOR_HIP(hipGetLastError());
   PMOR_HIP(hipStreamSynchronize(st));
-  PMOR_HIP(hipFree(cnt));
-  PMOR_HIP(hipFree(derr));
+  dfree(cnt, st);
+  dfree(derr, st);
   int maxcol = 0;
   PMOR_TRY(transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st));
   pb->max_col_len = maxcol;
@@ -436,7 +436,7 @@ int build_spai_sets(pmor_spai* h) {
   hipStream_t st = pb->ctx->stream;
   const int n = pb->n;
   int* dflag = nullptr;
-  PMOR_HIP(hipMalloc((void**)&dflag, sizeof(int) * 4));
+  PMOR_HIP(dmalloc((void**)&dflag, sizeof(int) * 4, st));
   PMOR_HIP(hipMemsetAsync(dflag, 0, sizeof(int) * 4, st));
   unsigned g = (unsigned)((n + 255) / 256);
   if (h->opts.pattern == PMOR_PAT_A) {
@@ -447,7 +447,7 @@ int build_spai_sets(pmor_spai* h) {
     h->nnzP = pb->nnz;
   } else {
     if (!h->opts.pat_colptr || !h->opts.pat_row || h->opts.nnz_explicit < n) {
-      (void)hipFree(dflag);
+      dfree(dflag, st);
       return fail(PMOR_EINVAL, "explicit SPAI pattern: null arrays or fewer than n entries");
     }
     hipLaunchKernelGGL(k_validate_pattern, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, n,
@@ -457,13 +457,13 @@ int build_spai_sets(pmor_spai* h) {
     PMOR_HIP(hipMemcpyAsync(&herr, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
     PMOR_HIP(hipStreamSynchronize(st));
     if (herr) {
-      (void)hipFree(dflag);
+      dfree(dflag, st);
       return fail(PMOR_EINVAL, (herr & 8) ? "explicit SPAI pattern: a column lacks its diagonal"
                                           : "explicit SPAI pattern: malformed CSC");
     }
     const int64_t nnzP = h->opts.nnz_explicit;
-    PMOR_HIP(hipMalloc((void**)&h->Jcolptr, sizeof(int32_t) * (n + 1)));
-    PMOR_HIP(hipMalloc((void**)&h->Jrow, sizeof(int32_t) * nnzP));
+    PMOR_HIP(dmalloc((void**)&h->Jcolptr, sizeof(int32_t) * (n + 1), st));
+    PMOR_HIP(dmalloc((void**)&h->Jrow, sizeof(int32_t) * nnzP, st));
     PMOR_HIP(hipMemcpyAsync(h->Jcolptr, h->opts.pat_colptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, st));
     PMOR_HIP(hipMemcpyAsync(h->Jrow, h->opts.pat_row, sizeof(int32_t) * nnzP, hipMemcpyDeviceToDevice, st));
     h->own_J = true;
@@ -473,17 +473,17 @@ int build_spai_sets(pmor_spai* h) {
     int mx = 0;
     int32_t* back = nullptr;
     PMOR_TRY(transpose_pattern(n, nnzP, h->Jcolptr, h->Jrow, &h->Prowptr, &h->Pcol, &back, &mx, st));
-    PMOR_HIP(hipMalloc((void**)&h->Pslot, sizeof(int32_t) * nnzP));
+    PMOR_HIP(dmalloc((void**)&h->Pslot, sizeof(int32_t) * nnzP, st));
     hipLaunchKernelGGL(k_invert_map, dim3((unsigned)((nnzP + 255) / 256)), dim3(256), 0, st, back, nnzP, h->Pslot);
     PMOR_HIP(hipGetLastError());
     PMOR_HIP(hipStreamSynchronize(st));
-    PMOR_HIP(hipFree(back));
+    dfree(back, st);
     h->own_P = true;
     h->nnzP = (int32_t)nnzP;
   }
   // shadows
   int64_t* cnt = nullptr;
-  PMOR_HIP(hipMalloc((void**)&cnt, sizeof(int64_t) * (n + 1)));
+  PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
   hipLaunchKernelGGL(k_shadow<false>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
                      cnt, nullptr, nullptr, dflag + 1, dflag + 2);
   PMOR_HIP(hipGetLastError());
@@ -493,7 +493,7 @@ int build_spai_sets(pmor_spai* h) {
   h->maxJ = hm[0];
   h->maxI = hm[1];
   if (h->maxJ > 64 || h->maxI > 512) {
-    (void)hipFree(cnt); (void)hipFree(dflag);
+    dfree(cnt, st); dfree(dflag, st);
     return fail(PMOR_EINVAL, "SPAI pattern too large: |J_j| <= 64 and |I_j| <= 512 are supported (got " +
                                  std::to_string(h->maxJ) + ", " + std::to_string(h->maxI) + ")");
   }
@@ -501,13 +501,13 @@ int build_spai_sets(pmor_spai* h) {
   PMOR_HIP(hipMemcpyAsync(&h->nI, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   h->Icolptr = cnt;
-  PMOR_HIP(hipMalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1)));
+  PMOR_HIP(dmalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1), st));
   hipLaunchKernelGGL(k_shadow<true>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
                      nullptr, h->Icolptr, h->Irow, nullptr, nullptr);
   PMOR_HIP(hipGetLastError());
   // buckets
   int* bc = nullptr;
-  PMOR_HIP(hipMalloc((void**)&bc, sizeof(int) * 16));
+  PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 16, st));
   PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 16, st));
   hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, bc);
   PMOR_HIP(hipGetLastError());
@@ -536,14 +536,14 @@ int build_spai_sets(pmor_spai* h) {
     for (int b = 0; b < 8; ++b) hb[b] = h->bucket_off[b];
     PMOR_HIP(hipMemcpyAsync(hb_off, hb, sizeof(int) * 8, hipMemcpyHostToDevice, st));
     PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 8, st));
-    PMOR_HIP(hipMalloc((void**)&h->bucket_cols, sizeof(int32_t) * (n > 0 ? n : 1)));
+    PMOR_HIP(dmalloc((void**)&h->bucket_cols, sizeof(int32_t) * (n > 0 ? n : 1), st));
     hipLaunchKernelGGL(k_bucket_fill, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, hb_off, bc,
                        h->bucket_cols);
     PMOR_HIP(hipGetLastError());
   }
   PMOR_HIP(hipStreamSynchronize(st));
-  PMOR_HIP(hipFree(bc));
-  PMOR_HIP(hipFree(dflag));
+  dfree(bc, st);
+  dfree(dflag, st);
   (void)nonempty;
   return PMOR_OK;
 }

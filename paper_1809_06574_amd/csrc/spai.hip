@@ -429,19 +429,23 @@ __global__ void k_sumsq_partials(const double* x, int64_t n, double* part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-__global__ void k_sum_in_order(const double* part, int np, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double acc = 0.0;
-    for (int i = 0; i < np; ++i) acc += part[i];
-    *out = acc;
+// out = sum of part[0..np), np <= 256, by a fixed tree (one workgroup of 256)
+__global__ __launch_bounds__(256) void k_sum_in_order(const double* part, int np, double* out) {
+  __shared__ double s[256];
+  s[threadIdx.x] = (int)threadIdx.x < np ? part[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = s[0];
 }
 
 // sum of squares of x[0..n), deterministic; result left in dev_scratch[0]
 int sumsq(const double* x, int64_t n, double* dev_scratch, hipStream_t st) {
   const int np = 256;
   hipLaunchKernelGGL(k_sumsq_partials, dim3(np), dim3(256), 0, st, x, n, dev_scratch + 1);
-  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, st, dev_scratch + 1, np, dev_scratch);
+  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(256), 0, st, dev_scratch + 1, np, dev_scratch);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }
@@ -601,14 +605,14 @@ __global__ void k_fro_partials(int n, const int32_t* rowptr, const int32_t* col,
 int fro_norm2(pmor_problem* pb, const double* a, const double* b, int64_t, int mode, double* out_host) {
   hipStream_t st = pb->ctx->stream;
   double* scratch = nullptr;
-  PMOR_HIP(hipMalloc((void**)&scratch, sizeof(double) * 260));
+  PMOR_HIP(dmalloc((void**)&scratch, sizeof(double) * 260, st));
   hipLaunchKernelGGL(k_fro_partials, dim3(256), dim3(256), 0, st, pb->n, pb->rowptr, pb->col, a, b, mode,
                      scratch + 1);
-  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(1), 0, st, scratch + 1, 256, scratch);
+  hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(256), 0, st, scratch + 1, 256, scratch);
   PMOR_HIP(hipGetLastError());
   PMOR_HIP(hipMemcpyAsync(out_host, scratch, sizeof(double), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
-  PMOR_HIP(hipFree(scratch));
+  dfree(scratch, st);
   return PMOR_OK;
 }
 
