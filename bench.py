@@ -135,6 +135,139 @@ def cpu_baseline(job, gpu_P):
             "host_cpus": os.cpu_count()}
 
 
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="config1", choices=["config1", "config0"])
+    ap.add_argument("--roofline-kernel", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
+    ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
+    ap.add_argument("--c2-systems", type=int, default=32, help="systems of the batch run (0: none)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
+    ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
+              "shard; --gpus above 1 is not supported (DESIGN.md describes how the path would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import tempfile
+    tune_file = os.environ.get("PMOR_TUNE_CACHE")
+    if tune_file is None:  # record what the library's tuner chooses in this run
+        tune_file = os.path.join(tempfile.mkdtemp(prefix="pmor_tune_"), "tune.json")
+        os.environ["PMOR_TUNE_CACHE"] = tune_file
+
+    import torch
+    from synth import config0, config1
+    from paper_1809_06574_amd import Context, Problem, lib as L
+
+    job = config1() if args.workload == "config1" else config0()
+    ctx = Context(0)
+    dev = ctx.device
+    terms = {r: (torch.as_tensor(T.rowptr, device=dev), torch.as_tensor(T.col, device=dev),
+                 torch.as_tensor(T.val, device=dev)) for r, T in job.terms.items()}
+    B = torch.as_tensor(job.B, device=dev)
+    Xbuf = torch.empty((len(job.p_list),) + tuple(B.shape), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def factory():
+        return Problem(ctx, terms)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # warmup (also builds every lazily created buffer)
+    for _ in range(max(args.warmup, 0)):
+        run_job(factory, job, B, "update", Xbuf=Xbuf)
+
+    # the dominant kernel: one untimed job per kernel class, the one with the most device time
+    kinds = dict(L.PROF_KERNELS)
+    per_kernel = {}
+    if args.roofline_kernel == "auto":
+        for name, kid in kinds.items():
+            L.check(L.pmor_prof_set(ctx.handle, kid), "prof_set")
+            run_job(factory, job, B, "update", Xbuf=Xbuf)
+            n_, ms_, by_ = _prof_read(L, ctx)
+            per_kernel[name] = {"launches": n_, "total_ms": ms_, "avg_us": 1e3 * ms_ / max(n_, 1),
+                                "GBps": by_ / max(ms_ * 1e-3, 1e-12) / 1e9}
+        dom = max(per_kernel, key=lambda k: per_kernel[k]["total_ms"])
+    else:
+        dom = args.roofline_kernel
+
+    # timed region: update policy, dominant kernel timed live
+    L.check(L.pmor_prof_set(ctx.handle, kinds[dom]), "prof_set")
+    lat_upd = []
+    t_upd, n_upd = timed(lambda: run_job(factory, job, B, "update", lat=lat_upd, Xbuf=Xbuf), args.steps)
+    nl, ms, by = _prof_read(L, ctx)
+    L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+    achieved = by / (ms * 1e-3) / 1e9
+    value = n_upd / t_upd
+
+    out = {"metric": "parametric solves/s at 1e-8 residual (SPAI-update vs rebuild); p50/p99 latency",
+           "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t_upd / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{job.name}: 3-D 7-point grid {'x'.join(map(str, job.meta['dims']))}, "
+                                  f"n={job.n}, nnz(A)={_nnz(factory)}, k={job.k}, "
+                                  f"{len(job.p_list)} points p in [{job.p_list[0]:.2f},{job.p_list[-1]:.2f}], "
+                                  f"s={job.s}, block GMRES(30) tol 1e-8, SPAI on pattern(A), update=U-diag",
+                      "policy": "update", "execution": "points of a job solved together (pmor_sequence_solve)",
+                      "solves_per_step": n_upd // args.steps},
+           "latency_ms": {"p50": 1e3 * _pct(lat_upd, 50), "p99": 1e3 * _pct(lat_upd, 99)},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom), "launches": nl,
+                        "avg_launch_us": 1e3 * ms / max(nl, 1),
+                        "bytes_per_launch": by / max(nl, 1)},
+           }
+    if per_kernel:
+        out["kernels"] = per_kernel
+
+    if not args.no_arms:
+        arms = {"update_batched": (value, lat_upd)}
+        for name, policy, mode, steps in (("rebuild_batched", "rebuild", "batched", args.steps),
+                                          ("update_pointwise", "update", "pointwise", 1),
+                                          ("rebuild_pointwise", "rebuild", "pointwise", 1),
+                                          ("plain_nonblock_rebuild", "rebuild", "plain", 1)):
+            lat = []
+            t_a, n_a = timed(lambda: run_job(factory, job, B, policy, mode=mode, lat=lat, Xbuf=Xbuf), steps)
+            arms[name] = (n_a / t_a, lat)
+        out["arms"] = {k: {"solves_per_s": v, "p50_ms": 1e3 * _pct(l, 50), "p99_ms": 1e3 * _pct(l, 99)}
+                       for k, (v, l) in arms.items()}
+        out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]
+        out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
+        out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
+
+    if args.c2_systems > 0:
+        out["batch_systems"] = c2_bench(ctx, args.c2_systems)
+
+    if args.serve_jobs > 0:
+        rhos = [float(x) for x in args.serve_rho.split(",")]
+        out["serving"] = serve_bench(ctx, rhos, args.serve_jobs)
+
+    if not args.no_cpu_baseline:
+        pb = factory()
+        h = pb.spai_build(job.s, job.p_list[0])
+        P1 = h.export()["val"].cpu().numpy()
+        h.close(); pb.close()
+        out["cpu_baseline"] = cpu_baseline(job, P1)
+    try:
+        with open(tune_file) as f:
+            out["tuning"] = json.load(f)
+    except (OSError, ValueError):
+        out["tuning"] = None
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, seed_base=0):
     """Sequence jobs of the serving workload (n uniform over 32x32x16, 64x32x32, 64^3,
     128x128x64; 20 points p0 + 0.02 j; k = 4) arriving as a Poisson process at

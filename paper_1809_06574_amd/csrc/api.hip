@@ -113,6 +113,7 @@ int ensure_assembled(pmor_problem* pb, double s, double p) {
   double c[PMOR_NROLES];
   role_coefs(s, p, c);
   PMOR_TRY(launch_assemble(pb, c, pb->aval, pb->ctx->stream));
+  PMOR_TRY(to_sell(pb->sell, pb->aval, pb->aval_s, pb->ctx->stream));
   pb->cur_s = s;
   pb->cur_p = p;
   pb->have_cur = true;
@@ -149,6 +150,10 @@ static void spai_release(pmor_spai* h) {
   dfree(h->Icolptr, s);
   dfree(h->Irow, s);
   dfree(h->bucket_cols, s);
+  dfree(h->Pval_s, s);
+  dfree(h->P1val_s, s);
+  dfree(h->Qval_s, s);
+  if (h->own_psell) free_sell(&h->psell, s);
   pmor_problem* pb = h->pb;
   delete h;
   pb_unref(pb);
@@ -191,6 +196,8 @@ static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
   double fro2 = 0.0;
   PMOR_TRY(run_spai_ls(h, pb->aval, nullptr, h->P1val, &bad, stats ? &fro2 : nullptr));
   PMOR_TRY(dcopy(h->P1val, h->Pval, h->nnzP, st));
+  PMOR_TRY(to_sell(h->psell, h->P1val, h->P1val_s, st));
+  PMOR_TRY(to_sell(h->psell, h->P1val, h->Pval_s, st));
   if (h->opts.update == PMOR_UPD_DIAG) PMOR_TRY(dfill(h->Qval, pb->n, 1.0, st));
   h->q_active = false;
   h->s1 = s;
@@ -206,14 +213,16 @@ static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
   return PMOR_OK;
 }
 
-static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* aval, const double* B, int64_t ldb,
-                         int k, double* X, int64_t ldx, pmor_stats* stats) {
+static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* aval, const double* aval_s,
+                         const double* B, int64_t ldb, int k, double* X, int64_t ldx, pmor_stats* stats) {
   SolveItem it{};
   it.n = pb->n;
   it.nnzA = pb->nnz;
   it.arow = pb->rowptr;
   it.acol = pb->col;
   it.aval = aval;
+  it.asell = &pb->sell;
+  it.aval_s = aval_s;
   it.pkind = 0;
   if (h) {
     it.pkind = h->q_active ? 2 : 1;
@@ -222,6 +231,9 @@ static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* ava
     it.pcol = h->Pcol;
     it.pval = h->q_active ? h->P1val : h->Pval;
     it.qval = h->Qval;
+    it.psell = &h->psell;
+    it.pval_s = h->q_active ? h->P1val_s : h->Pval_s;
+    it.qval_s = h->Qval_s;
   }
   it.B = B;
   it.ldb = ldb;
@@ -337,6 +349,8 @@ void pb_unref(pmor_problem* pb) {
   for (int32_t* x : ip) dfree(x, s);
   dfree(pb->tval, s);
   dfree(pb->aval, s);
+  dfree(pb->aval_s, s);
+  free_sell(&pb->sell, s);
   delete pb;
   ctx_unref(c);
 }
@@ -438,6 +452,9 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
     bool ok = al(&h->Pval, h->nnzP) && al(&h->P1val, h->nnzP) &&
               al(&h->Qval, o.update == PMOR_UPD_PATTERN ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
               al(&h->rho, n) && al(&h->red, 512);
+    if (ok && h->psell.cap > 0)
+      ok = al(&h->Pval_s, h->psell.cap) && al(&h->P1val_s, h->psell.cap) &&
+           (o.update != PMOR_UPD_PATTERN || al(&h->Qval_s, h->psell.cap));
     rc = ok ? build_into(h, s, p, stats) : fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
   if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
@@ -460,8 +477,10 @@ int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
   double fro2 = 0.0;
   if (h->opts.update == PMOR_UPD_DIAG) {
     PMOR_TRY(run_update_diag(h, pb->aval, &bad, stats ? &fro2 : nullptr));
+    PMOR_TRY(to_sell(h->psell, h->Pval, h->Pval_s, pb->ctx->stream));
   } else {
     PMOR_TRY(run_spai_ls(h, pb->aval, h->aval1, h->Qval, &bad, stats ? &fro2 : nullptr));
+    PMOR_TRY(to_sell(h->psell, h->Qval, h->Qval_s, pb->ctx->stream));
     h->q_active = true;
   }
   const double t_pre = tp.stop();
@@ -538,7 +557,7 @@ int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p, const 
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   auto t0 = std::chrono::steady_clock::now();
   PMOR_TRY(ensure_assembled(pb, s, p));
-  SolveItem it = item_of(pb, h, pb->aval, B, ldb, k, X, ldx, stats);
+  SolveItem it = item_of(pb, h, pb->aval, pb->aval_s, B, ldb, k, X, ldx, stats);
   PMOR_TRY(krylov_batch(pb->ctx, &it, 1, o));
   if (stats) {
     stats->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -571,8 +590,13 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
   for (int i = 0; i < nitems && rc == PMOR_OK; ++i) {
     const pmor_batch_item& b = items[i];
     const double* aval = nullptr;
+    const double* aval_s = nullptr;
     for (int q = 0; q < i; ++q)
-      if (items[q].pb == b.pb && items[q].s == b.s && items[q].p == b.p) { aval = it[q].aval; break; }
+      if (items[q].pb == b.pb && items[q].s == b.s && items[q].p == b.p) {
+        aval = it[q].aval;
+        aval_s = it[q].aval_s;
+        break;
+      }
     if (!aval) {
       bool first = true;
       for (int q = 0; q < i; ++q)
@@ -580,9 +604,11 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
       if (first) {
         rc = ensure_assembled(b.pb, b.s, b.p);
         aval = b.pb->aval;
+        aval_s = b.pb->aval_s;
       } else {
+        const int64_t cap = b.pb->sell.cap;
         double* buf = nullptr;
-        if (dmalloc((void**)&buf, sizeof(double) * std::max<int64_t>(b.pb->nnz, 1), st) != hipSuccess) {
+        if (dmalloc((void**)&buf, sizeof(double) * (std::max<int64_t>(b.pb->nnz, 1) + cap), st) != hipSuccess) {
           (void)hipGetLastError();
           rc = fail(PMOR_ENOMEM, "allocation of a point's A values failed");
           break;
@@ -592,9 +618,14 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
         role_coefs(b.s, b.p, c);
         rc = launch_assemble(b.pb, c, buf, st);
         aval = buf;
+        if (rc == PMOR_OK && cap > 0) {
+          double* bs = buf + std::max<int64_t>(b.pb->nnz, 1);
+          rc = to_sell(b.pb->sell, buf, bs, st);
+          aval_s = bs;
+        }
       }
     }
-    it[i] = item_of(b.pb, b.h, aval, b.B, b.ldb, b.k, b.X, b.ldx, stats ? &stats[i] : nullptr);
+    it[i] = item_of(b.pb, b.h, aval, aval_s, b.B, b.ldb, b.k, b.X, b.ldx, stats ? &stats[i] : nullptr);
   }
   if (rc == PMOR_OK) rc = krylov_batch(ctx, it.data(), nitems, o);
   for (double* x : extra) dfree(x, st);
@@ -616,6 +647,9 @@ namespace pmor {
 struct SeqBuffers {
   double* aval = nullptr;   // group x nnz: A(l) values
   double* pq = nullptr;     // group x nnzP: P_l, or Q_l for the pattern update
+  double* aval_s = nullptr; // group x capA: A(l) in the sliced ELL layout (when the problem has one)
+  double* pq_s = nullptr;   // group x capP: P_l / Q_l in the sliced ELL layout
+  int64_t capA = 0, capP = 0;
   double* q = nullptr;      // n (U-diag factors, scratch)
   double* rho = nullptr;    // n (U-diag column residuals, scratch)
   double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
@@ -626,11 +660,13 @@ struct SeqBuffers {
   SeqBuffers(const SeqBuffers&) = delete;
   SeqBuffers& operator=(const SeqBuffers&) = delete;
   ~SeqBuffers() {
-    void* v[] = {aval, pq, q, rho, fro, bad};
+    void* v[] = {aval, pq, q, rho, fro, bad, aval_s, pq_s};
     for (void* x : v) dfree(x, stream);
   }
-  int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n, hipStream_t s) {
+  int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n, hipStream_t s, int64_t capa = 0, int64_t capp = 0) {
     stream = s;
+    capA = capa;
+    capP = capp;
     auto al = [&](void** p, size_t b) {
       b = std::max<size_t>(b, 8);
       if (dmalloc(p, b, stream) != hipSuccess) {
@@ -646,10 +682,12 @@ struct SeqBuffers {
     PMOR_TRY(al((void**)&rho, sizeof(double) * n));
     PMOR_TRY(al((void**)&fro, sizeof(double) * group * 260));
     PMOR_TRY(al((void**)&bad, sizeof(int) * group));
+    if (capA > 0) PMOR_TRY(al((void**)&aval_s, sizeof(double) * group * capA));
+    if (capP > 0) PMOR_TRY(al((void**)&pq_s, sizeof(double) * group * capP));
     return PMOR_OK;
   }
-  static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n) {
-    return 8 * group * (nnz + nnzP) + 16 * n + 8 * 260 * group + 4 * group + 6 * 256;
+  static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n, int64_t capa = 0, int64_t capp = 0) {
+    return 8 * group * (nnz + nnzP + capa + capp) + 16 * n + 8 * 260 * group + 4 * group + 8 * 256;
   }
 };
 
@@ -687,16 +725,22 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
     double c[PMOR_NROLES];
     role_coefs(s_list[l], p_list[l], c);
     rc = launch_assemble(pb, c, Al, st);
+    double* Al_s = sb.capA > 0 ? sb.aval_s + (int64_t)t * sb.capA : nullptr;
+    double* PQ_s = sb.capP > 0 ? sb.pq_s + (int64_t)t * sb.capP : nullptr;
+    if (rc == PMOR_OK && Al_s) rc = to_sell(pb->sell, Al, Al_s, st);
     rec(1 + 2 * t);
     if (rc != PMOR_OK) break;
-    SolveItem x = item_of(pb, nullptr, Al, B, ldb, k, X + (int64_t)l * n * ldx, ldx, stats ? &stats[l] : nullptr);
+    SolveItem x = item_of(pb, nullptr, Al, Al_s, B, ldb, k, X + (int64_t)l * n * ldx, ldx,
+                          stats ? &stats[l] : nullptr);
     x.pkind = 1;
     x.prow = h->Prowptr;
     x.pcol = h->Pcol;
     x.nnzP = nnzP;
+    x.psell = &h->psell;
     x.tag = l;
     if (l == 0) {
       x.pval = h->P1val;
+      x.pval_s = h->P1val_s;
       fro_host[t] = pre0.fro_resid * pre0.fro_resid;
       bad[t] = pre0.bad_column;
     } else if (policy == PMOR_UPDATE && !upat) {
@@ -704,15 +748,25 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
       if (rc == PMOR_OK) rc = launch_update_diag(h, Al, PQ, sb.q, sb.rho, sb.bad + t);
       if (rc == PMOR_OK && stats) rc = sumsq(sb.rho, n, sb.fro + (int64_t)t * 260, st);
       x.pval = PQ;
+      x.pval_s = PQ_s;
     } else {
       int32_t b = -1;
       double fro2 = 0.0;
       rc = run_spai_ls(h, Al, policy == PMOR_UPDATE ? h->aval1 : nullptr, PQ, &b, stats ? &fro2 : nullptr);
       bad[t] = b;
       fro_host[t] = fro2;
-      if (policy == PMOR_UPDATE) { x.pkind = 2; x.pval = h->P1val; x.qval = PQ; }
-      else x.pval = PQ;
+      if (policy == PMOR_UPDATE) {
+        x.pkind = 2;
+        x.pval = h->P1val;
+        x.pval_s = h->P1val_s;
+        x.qval = PQ;
+        x.qval_s = PQ_s;
+      } else {
+        x.pval = PQ;
+        x.pval_s = PQ_s;
+      }
     }
+    if (rc == PMOR_OK && PQ_s && l > 0) rc = to_sell(h->psell, PQ, PQ_s, st);
     rec(2 + 2 * t);
     items[t] = x;
   }
@@ -797,12 +851,13 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
   // points per group: A and P/Q values plus the Krylov blocks of one system
   const int kp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-  const double per_point = 8.0 * (nnz + nnzP) + 8.0 * (double)n * kp * (o.m + 7) + 64.0 * 1024;
+  const double per_point = 8.0 * (nnz + nnzP + pb->sell.cap + h->psell.cap) + 8.0 * (double)n * kp * (o.m + 7) +
+                           64.0 * 1024;
   size_t fr = 0, tot = 0;
   PMOR_HIP(hipMemGetInfo(&fr, &tot));
   const int group = (int)std::max(1.0, std::min<double>(npts, 0.6 * (double)fr / per_point));
   SeqBuffers sb;
-  rc = sb.alloc(group, nnz, nnzP, n, pb->ctx->stream);
+  rc = sb.alloc(group, nnz, nnzP, n, pb->ctx->stream, pb->sell.cap, h->psell.cap);
   if (rc != PMOR_OK) { spai_release(h); return rc; }
   int first_bad = PMOR_OK;
   for (int l0 = 0; l0 < npts && rc == PMOR_OK; l0 += group) {
@@ -870,7 +925,8 @@ static int64_t job_footprint(const pmor_problem* pb, int npts) {
   const int64_t sumI = nnzP * std::max<int64_t>(pb->max_col_len, 1);
   const int64_t spai = 8 * (3 * nnzP + nnz + 2 * n + 512) + 8 * (n + 1) + 4 * sumI +
                        4 * (3 * (n + 1) + 3 * nnzP + n) + 4096;
-  return spai + SeqBuffers::estimate(npts, nnz, nnzP, n);
+  const int64_t cap = pb->sell.cap;
+  return spai + 3 * 8 * cap + SeqBuffers::estimate(npts, nnz, nnzP, n, cap, cap);
 }
 }  // namespace pmor
 
@@ -909,7 +965,8 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   pre0.bad_column = -1;
   sv->jobs[J->id] = J;
   int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
-  if (rc == PMOR_OK) rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n, sv->ctx->stream);
+  if (rc == PMOR_OK)
+    rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n, sv->ctx->stream, jb.pb->sell.cap, J->h->psell.cap);
   J->items.assign(npts, SolveItem{});
   J->bad.assign(npts, -1);
   if (rc == PMOR_OK)
@@ -972,10 +1029,8 @@ int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_s
                                           : (int64_t)(0.4 * (double)sv->budget / (8.0 * kp * (o.m + 8)));
   sv->eng = engine_new();
   int rc = runner_create(ctx, sv->eng, opts->k, o, sv->engine_rows, sv->max_systems, &sv->run);
-  size_t fr1 = 0;
-  if (rc == PMOR_OK) rc = hipMemGetInfo(&fr1, &tot) == hipSuccess ? PMOR_OK : fail(PMOR_EHIP, "hipMemGetInfo");
   if (rc == PMOR_OK) {
-    sv->engine_bytes = fr0 > fr1 ? (int64_t)(fr0 - fr1) : 0;
+    sv->engine_bytes = engine_bytes(sv->eng);
     if (sv->engine_bytes > sv->budget) rc = fail(PMOR_ENOMEM, "the engine alone exceeds the memory budget");
   }
   if (rc != PMOR_OK) {

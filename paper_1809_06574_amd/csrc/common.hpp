@@ -56,6 +56,19 @@ struct DevState {
   double R2inv[KMAX * KMAX];  // inverse of the second factor: V_{j+1} = W1 R2inv
 };
 
+// Sliced ELL view of a CSR pattern for the engine's SpMM: 64-row slices,
+// column-major inside a slice (entry k of row r at ptr[r/64] + 64 k + r%64);
+// padding entries point at their own row with value 0.  Built only when the
+// padding stays small (stencil-like rows); cap = 0 means no view.
+struct SellView {
+  int32_t ns = 0;            // slices
+  int64_t cap = 0;           // stored entries (with padding)
+  int32_t* ptr = nullptr;    // ns + 1 slice offsets
+  int32_t* wid = nullptr;    // ns slice widths
+  int32_t* col = nullptr;    // cap columns
+  int32_t* map = nullptr;    // cap: CSR position of the entry, -1 for padding
+};
+
 // one system of a batch (device copy read by every kernel)
 struct SegDesc {
   int n;            // rows
@@ -72,6 +85,16 @@ struct SegDesc {
   const int32_t* pcol;
   const double* pval;   // P, or P_1 when pkind == 2
   const double* qval;   // Q when pkind == 2
+  // sliced ELL copies (a_sp == nullptr / p_sp == nullptr: use the CSR arrays)
+  const int32_t* a_sp;
+  const int32_t* a_sw;
+  const int32_t* a_sc;
+  const double* a_sv;
+  const int32_t* p_sp;
+  const int32_t* p_sw;
+  const int32_t* p_sc;
+  const double* p_sv;
+  const double* q_sv;
   const double* B;
   int64_t ldb;
   double* X;
@@ -128,6 +151,8 @@ struct pmor_problem {
   int32_t* cscslot = nullptr;  // CSC position -> CSR position
   int32_t max_row_len = 0, max_col_len = 0;
   double* aval = nullptr;      // values of the last assembled point
+  pmor::SellView sell;         // sliced ELL view of the pattern (engine SpMM)
+  double* aval_s = nullptr;    // aval in the sliced ELL layout
   double cur_s = 0, cur_p = 0;
   bool have_cur = false;
 };
@@ -156,6 +181,11 @@ struct pmor_spai {
   bool identity_order = true;
   bool q_active = false;     // U-pattern update applied (apply Q (P_1 x))
   double s1 = 0, p1 = 0;
+  pmor::SellView psell;      // sliced ELL view of P's pattern (the problem's for PAT_A)
+  bool own_psell = false;
+  double* Pval_s = nullptr;  // Pval, P1val, Qval in the sliced ELL layout
+  double* P1val_s = nullptr;
+  double* Qval_s = nullptr;
 };
 
 namespace pmor {
@@ -216,6 +246,12 @@ inline void plaunch(pmor_ctx* c, int idx, int part, F kernel, dim3 g, dim3 b, ui
 int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* out, hipStream_t st);
 int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms);
 int build_spai_sets(pmor_spai* h);
+// sliced ELL view of a CSR pattern when its padding is at most max_fill x nnz (else v->cap = 0)
+int build_sell(int n, const int32_t* rowptr, const int32_t* col, int64_t nnz, double max_fill, SellView* v,
+               hipStream_t st);
+void free_sell(SellView* v, hipStream_t st);
+// dst (v->cap) = src (CSR order) permuted into the view; padding 0
+int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
@@ -243,6 +279,11 @@ struct SolveItem {
   const int32_t* pcol;
   const double* pval;
   const double* qval;
+  const SellView* asell;      // sliced ELL views (NULL or cap 0: none) and values in them
+  const double* aval_s;
+  const SellView* psell;
+  const double* pval_s;
+  const double* qval_s;
   const double* B;
   int64_t ldb;
   int k;
@@ -269,6 +310,7 @@ struct Runner {
   virtual double now_ms() const = 0;  // host time since the engine's start
 };
 Engine* engine_new();
+int64_t engine_bytes(const Engine* e);
 // an engine of block width pad(k) on buffers E for rows_cap concatenated rows and nslots systems
 int runner_create(pmor_ctx* ctx, Engine* E, int k, const pmor_solve_opts& o, int64_t rows_cap, int nslots,
                   Runner** out);

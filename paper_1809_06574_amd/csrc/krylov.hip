@@ -1164,19 +1164,26 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
   const int32_t* rp;
   const int32_t* cl;
   const double* vl;
+  const int32_t* sp;   // sliced ELL view, or nullptr for CSR
+  const int32_t* sw;
+  const int32_t* sc;
+  const double* sv;
   bool ident = false;
   double* Y = a.Y;
   double alpha = a.alpha, beta = a.beta;
   const double* Bsrc = a.Bsrc;
   if (a.which == 0) {
     rp = d.arow; cl = d.acol; vl = d.aval;
+    sp = d.a_sp; sw = d.a_sw; sc = d.a_sc; sv = d.a_sv;
   } else if (a.which == 1) {
     ident = (pk == 0);
     rp = d.prow; cl = d.pcol; vl = d.pval;
+    sp = d.p_sp; sw = d.p_sw; sc = d.p_sc; sv = d.p_sv;
     if (pk == 2) { Y = a.Yalt; alpha = 1.0; beta = 0.0; Bsrc = nullptr; }
   } else {
     if (pk != 2) return;
     rp = d.prow; cl = d.pcol; vl = d.qval;
+    sp = d.p_sp; sw = d.p_sw; sc = d.p_sc; sv = d.q_sv;
   }
   __shared__ double sM[CONV ? KP * KP : 1];
   if constexpr (CONV) {
@@ -1197,6 +1204,29 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
       if (sub == 0) {
 #pragma unroll
         for (int t = 0; t < KP; ++t) acc[t] = X[(int64_t)local * KP + t];
+      }
+    } else if (sp) {
+      // sliced ELL: entry k of the row at ptr[slice] + 64 k + row % 64; the LPR
+      // lanes of a row take k = sub, sub + LPR, ...; matrix data streams once
+      const int64_t base = sp[local >> 6] + (local & 63);
+      const int w = sw[local >> 6];
+      for (int k = sub; k < w; k += LPR) {
+        const int64_t q = base + (int64_t)k * 64;
+        const int c = __builtin_nontemporal_load(sc + q);
+        const double v = __builtin_nontemporal_load(sv + q);
+        if constexpr (KP % 2 == 0) {
+          const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * KP);
+#pragma unroll
+          for (int t = 0; t < KP / 2; ++t) {
+            const double2 x = xr[t];
+            acc[2 * t] = fma(v, x.x, acc[2 * t]);
+            acc[2 * t + 1] = fma(v, x.y, acc[2 * t + 1]);
+          }
+        } else {
+          const double* xr = X + (int64_t)c * KP;
+#pragma unroll
+          for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+        }
       }
     } else {
       const int e1 = rp[local + 1];
@@ -1549,6 +1579,7 @@ struct Engine {
   // strides of the per-segment arrays for the current (kp, m)
   int ldh = 0;
   int64_t hcs = 0, hc2off = 0, hbs = 0, gs = 0, rfs = 0, ys = 0, lstride = 0;
+  int64_t bytes = 0;  // device bytes held
 };
 
 static int grow(DBuf& b, int64_t need) {
@@ -1652,6 +1683,11 @@ static int engine_reserve(Engine& E, int kp, int m, int64_t rows, int nseg, int6
     PMOR_HIP(hipHostGetDevicePointer((void**)&E.hinfo_d, E.hinfo_h, 0));
   }
   PMOR_TRY(grow_host(&E.nrm_h, E.nrm_h_cap, (int64_t)nseg * KMAX, hipHostMallocDefault));
+  int64_t b = 0;
+  for (const DBuf* d : {&E.V, &E.W, &E.Z, &E.T, &E.Bc, &E.Xc, &E.Hc, &E.Hbar, &E.G, &E.refl, &E.Y, &E.nrm, &E.part,
+                        &E.partg})
+    b += 8 * d->cap;
+  E.bytes = b + (int64_t)sizeof(DevState) * E.st_cap + (int64_t)sizeof(SegDesc) * E.seg_cap + 4 * E.tab_cap;
   return PMOR_OK;
 }
 
@@ -1835,6 +1871,13 @@ class RunnerT final : public Runner {
       d.pkind = it->pkind;
       d.arow = it->arow; d.acol = it->acol; d.aval = it->aval;
       d.prow = it->prow; d.pcol = it->pcol; d.pval = it->pval; d.qval = it->qval;
+      if (it->asell && it->asell->cap > 0 && it->aval_s) {
+        d.a_sp = it->asell->ptr; d.a_sw = it->asell->wid; d.a_sc = it->asell->col; d.a_sv = it->aval_s;
+      }
+      if (it->pkind != 0 && it->psell && it->psell->cap > 0 && it->pval_s && (it->pkind != 2 || it->qval_s)) {
+        d.p_sp = it->psell->ptr; d.p_sw = it->psell->wid; d.p_sc = it->psell->col; d.p_sv = it->pval_s;
+        d.q_sv = it->qval_s;
+      }
       d.B = it->B; d.ldb = it->ldb;
       d.X = it->X; d.ldx = it->ldx;
       E_.tab_h[q] = sl;
@@ -2246,6 +2289,7 @@ int runner_create(pmor_ctx* ctx, Engine* E, int k, const pmor_solve_opts& o, int
 }
 
 Engine* engine_new() { return new Engine(); }
+int64_t engine_bytes(const Engine* e) { return e ? e->bytes : 0; }
 
 int krylov_batch(pmor_ctx* ctx, SolveItem* items, int nitems, const pmor_solve_opts& o) {
   if (nitems <= 0) return PMOR_OK;

@@ -6,6 +6,8 @@
 //  * the SPAI index sets: J_j (pattern of column j of P) and the shadow I_j
 //    (rows of A(:, J_j) holding a nonzero), and the buckets of columns by
 //    (|J_j|, |I_j|) that select the least-squares kernel.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace pmor {
@@ -313,6 +315,8 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   int maxcol = 0;
   PMOR_TRY(transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st));
   pb->max_col_len = maxcol;
+  PMOR_TRY(build_sell(n, pb->rowptr, pb->col, nnz, 1.25, &pb->sell, st));
+  if (pb->sell.cap > 0) PMOR_HIP(dmalloc((void**)&pb->aval_s, sizeof(double) * pb->sell.cap, st));
   return PMOR_OK;
 }
 
@@ -444,6 +448,7 @@ int build_spai_sets(pmor_spai* h) {
     // so this is the CSC view of A, and P's CSR pattern is A's own.
     h->Jcolptr = pb->colptr; h->Jrow = pb->rowidx; h->own_J = false;
     h->Prowptr = pb->rowptr; h->Pcol = pb->col; h->Pslot = pb->cscslot; h->own_P = false;
+    h->psell = pb->sell; h->own_psell = false;
     h->nnzP = pb->nnz;
   } else {
     if (!h->opts.pat_colptr || !h->opts.pat_row || h->opts.nnz_explicit < n) {
@@ -480,6 +485,8 @@ int build_spai_sets(pmor_spai* h) {
     dfree(back, st);
     h->own_P = true;
     h->nnzP = (int32_t)nnzP;
+    PMOR_TRY(build_sell(n, h->Prowptr, h->Pcol, nnzP, 1.25, &h->psell, st));
+    h->own_psell = true;
   }
   // shadows
   int64_t* cnt = nullptr;
@@ -545,6 +552,101 @@ int build_spai_sets(pmor_spai* h) {
   dfree(bc, st);
   dfree(dflag, st);
   (void)nonempty;
+  return PMOR_OK;
+}
+
+}  // namespace pmor
+
+// ---------------------------------------------------------------------------
+// sliced ELL view of a CSR pattern (the engine's SpMM layout)
+// ---------------------------------------------------------------------------
+namespace pmor {
+
+// width of each 64-row slice (longest row), times 64, one wavefront per slice
+__global__ __launch_bounds__(64) void k_sell_width(int n, const int32_t* rowptr, int64_t* w64) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  int len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
+  for (int o = 32; o >= 1; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+  if (threadIdx.x == 0) w64[blockIdx.x] = (int64_t)len * 64;
+}
+
+__global__ __launch_bounds__(64) void k_sell_fill(int n, const int32_t* rowptr, const int32_t* col,
+                                                  const int64_t* off, int32_t* ptr, int32_t* wid, int32_t* scol,
+                                                  int32_t* smap) {
+  const int s = blockIdx.x, lane = threadIdx.x, r = s * 64 + lane;
+  const int64_t base = off[s];
+  const int w = (int)((off[s + 1] - base) / 64);
+  if (lane == 0) {
+    ptr[s] = (int32_t)base;
+    wid[s] = w;
+    if (s == (int)gridDim.x - 1) ptr[s + 1] = (int32_t)off[s + 1];
+  }
+  const int e0 = r < n ? rowptr[r] : 0;
+  const int len = r < n ? rowptr[r + 1] - e0 : 0;
+  for (int k = 0; k < w; ++k) {
+    const int64_t q = base + (int64_t)k * 64 + lane;
+    if (k < len) {
+      scol[q] = col[e0 + k];
+      smap[q] = e0 + k;
+    } else {
+      scol[q] = r < n ? r : 0;
+      smap[q] = -1;
+    }
+  }
+}
+
+__global__ void k_to_sell(int64_t cap, const int32_t* __restrict__ map, const double* __restrict__ src,
+                          double* __restrict__ dst) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = map[q];
+    dst[q] = e >= 0 ? src[e] : 0.0;
+  }
+}
+
+int build_sell(int n, const int32_t* rowptr, const int32_t* col, int64_t nnz, double max_fill, SellView* v,
+               hipStream_t st) {
+  *v = SellView{};
+  if (n <= 0) return PMOR_OK;
+  (void)col;
+  const int ns = (n + 63) / 64;
+  int64_t* w64 = nullptr;
+  PMOR_HIP(dmalloc((void**)&w64, sizeof(int64_t) * (ns + 1), st));
+  hipLaunchKernelGGL(k_sell_width, dim3(ns), dim3(64), 0, st, n, rowptr, w64);
+  PMOR_HIP(hipGetLastError());
+  PMOR_TRY(scan_exclusive(w64, ns, st));
+  int64_t cap = 0;
+  PMOR_HIP(hipMemcpyAsync(&cap, w64 + ns, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  if (cap <= 0 || (double)cap > max_fill * (double)nnz + 64.0 || cap >= ((int64_t)1 << 31)) {
+    dfree(w64, st);
+    return PMOR_OK;  // too much padding: the CSR arrays serve
+  }
+  v->ns = ns;
+  v->cap = cap;
+  PMOR_HIP(dmalloc((void**)&v->ptr, sizeof(int32_t) * (ns + 1), st));
+  PMOR_HIP(dmalloc((void**)&v->wid, sizeof(int32_t) * ns, st));
+  PMOR_HIP(dmalloc((void**)&v->col, sizeof(int32_t) * cap, st));
+  PMOR_HIP(dmalloc((void**)&v->map, sizeof(int32_t) * cap, st));
+  hipLaunchKernelGGL(k_sell_fill, dim3(ns), dim3(64), 0, st, n, rowptr, col, (const int64_t*)w64, v->ptr, v->wid,
+                     v->col, v->map);
+  PMOR_HIP(hipGetLastError());
+  dfree(w64, st);
+  return PMOR_OK;
+}
+
+void free_sell(SellView* v, hipStream_t st) {
+  dfree(v->ptr, st);
+  dfree(v->wid, st);
+  dfree(v->col, st);
+  dfree(v->map, st);
+  *v = SellView{};
+}
+
+int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st) {
+  if (v.cap <= 0) return PMOR_OK;
+  const unsigned g = (unsigned)std::min<int64_t>((v.cap + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_to_sell, dim3(g), dim3(256), 0, st, v.cap, (const int32_t*)v.map, src, dst);
+  PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }
 
