@@ -342,19 +342,109 @@ __global__ void k_validate_pattern(int n, int nnz, const int32_t* colptr, const 
   if (!diag) atomicOr(err, 8);
 }
 
-// I_j = sorted union of the rows of A(:, c), c in J_j (k-way merge of CSC columns)
+// I_j = sorted union of the rows of A(:, c), c in J_j.
+//
+// Columns whose candidate list (sum of |A(:, c)|, c in J_j) fits SH_CAP: one
+// wavefront per column copies the candidates into LDS, sorts them (bitonic)
+// and keeps the distinct rows.  Longer lists: a k-way merge of the CSC columns
+// by one lane (k_shadow_merge, called for those columns only).
+constexpr int SH_CAP = 2048;
+
+__device__ __forceinline__ int shadow_total(int nj, int ja, const int32_t* Jrow, const int32_t* Acolptr, int lane) {
+  int tot = 0;
+  for (int t = lane; t < nj; t += 64) {
+    const int c = Jrow[ja + t];
+    tot += Acolptr[c + 1] - Acolptr[c];
+  }
+  for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  return tot;
+}
+
 template <bool FILL>
-__global__ void k_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
-                         const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow,
-                         int* maxJ, int* maxI) {
+__global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolptr, const int32_t* Jrow,
+                                                    const int32_t* Acolptr, const int32_t* Arowidx, int64_t* counts,
+                                                    const int64_t* Icolptr, int32_t* Irow, int* maxJ, int* maxI) {
+  __shared__ int buf[SH_CAP];
+  const int lane = threadIdx.x;
+  int mj = 0, mi = 0;
+  for (int j = blockIdx.x; j < n; j += gridDim.x) {
+    const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
+    if (nj > 64) {  // unsupported; reported through maxJ
+      if (!FILL && lane == 0) counts[j] = 0;
+      mj = max(mj, nj);
+      continue;
+    }
+    const int total = shadow_total(nj, ja, Jrow, Acolptr, lane);
+    if (total > SH_CAP) continue;  // k_shadow_merge
+    // candidate offsets: lane t owns column t of J_j
+    int len = 0, c0 = 0;
+    if (lane < nj) {
+      const int c = Jrow[ja + lane];
+      c0 = Acolptr[c];
+      len = Acolptr[c + 1] - c0;
+    }
+    int incl = len;  // inclusive scan over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int off = incl - len;
+    int P = 1;
+    while (P < total) P <<= 1;
+    for (int q = 0; q < len; ++q) buf[off + q] = Arowidx[c0 + q];
+    for (int i = total + lane; i < P; i += 64) buf[i] = 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = lane; i < P; i += 64) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const int a = buf[i], b = buf[ixj];
+            if ((a > b) == ((i & k) == 0)) {
+              buf[i] = b;
+              buf[ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    // distinct rows, in order
+    int64_t pos = FILL ? Icolptr[j] : 0;
+    int cnt = 0;
+    for (int i0 = 0; i0 < total; i0 += 64) {
+      const int i = i0 + lane;
+      const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
+      const unsigned long long m = __ballot(keep);
+      if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
+      cnt += __popcll(m);
+    }
+    __syncthreads();
+    if (!FILL && lane == 0) counts[j] = cnt;
+    mj = max(mj, nj);
+    mi = max(mi, cnt);
+  }
+  if (!FILL && lane == 0) {
+    atomicMax(maxJ, mj);
+    atomicMax(maxI, mi);
+  }
+}
+
+// the columns with more than SH_CAP candidates: k-way merge of the CSC columns, one lane per column
+template <bool FILL>
+__global__ void k_shadow_merge(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
+                               const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow,
+                               int* maxJ, int* maxI) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
   constexpr int MAXJ = 64;
-  if (nj > MAXJ) {
-    if (!FILL) { counts[j] = 0; atomicMax(maxJ, nj); }
-    return;
+  if (nj > MAXJ) return;
+  int total = 0;
+  for (int t = 0; t < nj; ++t) {
+    const int c = Jrow[ja + t];
+    total += Acolptr[c + 1] - Acolptr[c];
   }
+  if (total <= SH_CAP) return;
   int cur[MAXJ], end[MAXJ];
   for (int t = 0; t < nj; ++t) {
     int c = Jrow[ja + t];
@@ -378,6 +468,20 @@ __global__ void k_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, con
     atomicMax(maxJ, nj);
     atomicMax(maxI, cnt);
   }
+}
+
+template <bool FILL>
+static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
+                         const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow, int* maxJ,
+                         int* maxI, hipStream_t st) {
+  if (n <= 0) return PMOR_OK;
+  const unsigned gs = (unsigned)std::min(n, 16384);
+  hipLaunchKernelGGL(k_shadow_sort<FILL>, dim3(gs), dim3(64), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
+                     Icolptr, Irow, maxJ, maxI);
+  hipLaunchKernelGGL(k_shadow_merge<FILL>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Jcolptr, Jrow,
+                     Acolptr, Arowidx, counts, Icolptr, Irow, maxJ, maxI);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
 }
 
 // inv[map[q]] = q
@@ -491,9 +595,8 @@ int build_spai_sets(pmor_spai* h) {
   // shadows
   int64_t* cnt = nullptr;
   PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
-  hipLaunchKernelGGL(k_shadow<false>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
-                     cnt, nullptr, nullptr, dflag + 1, dflag + 2);
-  PMOR_HIP(hipGetLastError());
+  PMOR_TRY(launch_shadow<false>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, cnt, nullptr, nullptr, dflag + 1,
+                                dflag + 2, st));
   int hm[2] = {0, 0};
   PMOR_HIP(hipMemcpyAsync(hm, dflag + 1, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
@@ -509,9 +612,8 @@ int build_spai_sets(pmor_spai* h) {
   PMOR_HIP(hipStreamSynchronize(st));
   h->Icolptr = cnt;
   PMOR_HIP(dmalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1), st));
-  hipLaunchKernelGGL(k_shadow<true>, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx,
-                     nullptr, h->Icolptr, h->Irow, nullptr, nullptr);
-  PMOR_HIP(hipGetLastError());
+  PMOR_TRY(launch_shadow<true>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, nullptr, h->Icolptr, h->Irow, nullptr,
+                               nullptr, st));
   // buckets
   int* bc = nullptr;
   PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 16, st));
