@@ -42,9 +42,14 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace pmor {
+
+// streaming load: the basis and the work block are far larger than the caches
+// and are not reread by the same kernel
+__device__ __forceinline__ double ldnt(const double* p) { return __builtin_nontemporal_load(p); }
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -262,12 +267,11 @@ constexpr int UPD_P3 = 2;     // prologue; W <- (W - V H2) R1^{-1}; Gram(W)  (pa
 // flight together and no LDS exchange is needed inside the loop.
 // ---------------------------------------------------------------------------
 constexpr int RS_B = 32;
-constexpr int RS_ROW = RS_B * 16 + 16;
 
 // sum of a per-wavefront row of L values over the NW wavefronts, in order,
 // written as this workgroup's partial row
-template <int NW>
-__device__ __forceinline__ void rs_store_partials(double (*sred)[RS_ROW], int L, double* dst) {
+template <int NW, int ROW>
+__device__ __forceinline__ void rs_store_partials(double (*sred)[ROW], int L, double* dst) {
   __syncthreads();
   for (int t = threadIdx.x; t < L; t += 64 * NW) {
     double tot = 0.0;
@@ -287,7 +291,8 @@ __global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
   const int nch = (r.n + 15) >> 4;
   const double* W = a.W + r.r0 * 4;
   const double* V = a.V + r.r0 * 4;
-  __shared__ double sred[NW][RS_ROW];
+  constexpr int ROW = NB * 16 + 16;
+  __shared__ double sred[NW][ROW];
   double acc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = 0.0;
@@ -295,11 +300,11 @@ __global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
   for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
     const int64_t off = ((int64_t)ch << 6) + lane;  // 16 rows x 4 columns = 64 doubles
     const bool valid = off < (int64_t)r.n * 4;
-    const double wt = valid ? W[off] : 0.0;
+    const double wt = valid ? ldnt(W + off) : 0.0;
     wn += wt * wt;
     double v[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? ldnt(V + (int64_t)i * a.vstride + off) : 0.0;
 #pragma unroll
     for (int i = 0; i < NB; ++i)
       if (i < nbl) acc[i] = mfma4(v[i], wt, acc[i]);
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(64 * NW) void k_dot4(KArgs a) {
   wn += __shfl_xor(wn, 16, 64);
   wn += __shfl_xor(wn, 32, 64);
   if (lane < 4) sred[w][nbl * 16 + lane] = wn;
-  rs_store_partials<NW>(sred, nbl * 16 + 4, a.part + (int64_t)r.lg * a.lstride);
+  rs_store_partials<NW, ROW>(sred, nbl * 16 + 4, a.part + (int64_t)r.lg * a.lstride);
 }
 
 // Lane l of a 16 x 4 tile holds (row 16c + (l >> 2), column l & 3).  Used as the
@@ -344,7 +349,8 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   const int nch = (r.n + 15) >> 4;
   double* W = a.W + r.r0 * 4;
   const double* V = a.V + r.r0 * 4;
-  __shared__ double sred[GRAM ? NW : 1][RS_ROW];
+  constexpr int ROW = (DOT ? NB * 16 : 0) + 16;
+  __shared__ double sred[GRAM ? NW : 1][ROW];
   // B operand of block i: B[k][j] = -hsign H[4i + k][j], k = lane >> 4, j = lane & 3
   __shared__ double sH[RS_B * 16];
   __shared__ double sRinv[P3 ? 16 : 1];
@@ -361,12 +367,12 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   double accg = 0.0;
   const bool write = P3 || nbl > 0 || a.zero_init;
   for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
-    const int64_t off = ((int64_t)ch << 6) + lane;
-    const bool valid = off < (int64_t)r.n * 4;
-    const double wt = (valid && !a.zero_init) ? W[off] : 0.0;
+    const int64_t e = ((int64_t)ch << 6) + lane;
+    const bool valid = e < (int64_t)r.n * 4;
+    const double wt = (valid && !a.zero_init) ? ldnt(W + e) : 0.0;
     double v[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? V[(int64_t)i * a.vstride + off] : 0.0;
+    for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? ldnt(V + (int64_t)i * a.vstride + e) : 0.0;
     double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
 #pragma unroll
     for (int i = 0; i < NB; i += 2) {
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
     }
     double wnew = u0 + u1;
     if (P3) wnew = mfma4(tile_transpose(wnew, lane), rb, 0.0);
-    if (valid && write) W[off] = wnew;
+    if (valid && write) W[e] = wnew;
     if (DOT) {
 #pragma unroll
       for (int i = 0; i < NB; ++i)
@@ -399,8 +405,8 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   x += __shfl_xor(x, 4, 64);
   x += __shfl_xor(x, 8, 64);
   if (((lane >> 2) & 3) == 0) sred[w][L + (lane >> 4) * 4 + (lane & 3)] = x;
-  if (P3) rs_store_partials<NW>(sred, 16, a.partg + (int64_t)r.lg * 16);
-  else rs_store_partials<NW>(sred, L + 16, a.part + (int64_t)r.lg * a.lstride);
+  if (P3) rs_store_partials<NW, ROW>(sred, 16, a.partg + (int64_t)r.lg * 16);
+  else rs_store_partials<NW, ROW>(sred, L + 16, a.part + (int64_t)r.lg * a.lstride);
 }
 
 // ---------------------------------------------------------------------------
@@ -1701,7 +1707,7 @@ struct Fam {
   static constexpr int NW = (KP == 4 || KP == 16) ? 8 : 4;
   static constexpr int BPW = 32 / NW;     // V blocks per wavefront: m + 1 <= 32
   static constexpr int ROWS = RS ? 16 * NW : (ROW ? 64 : 16);  // rows per workgroup iteration
-  static constexpr int GMAX = RS ? 256 : 512;
+  static constexpr int GMAX = RS ? 128 : 512;
 };
 
 static int pad_kp(int k) {
@@ -1722,19 +1728,31 @@ static int row_wgs(int n, int rows_per_iter, int gmax) {
   return (int)g;
 }
 
-// V blocks held in registers by the kp = 4 kernels: the smallest of 8, 16, 24,
-// 32 that covers the sweep (fewer registers, more wavefronts in flight)
-static int rs_nb(int nbl_max) { return nbl_max <= 8 ? 8 : (nbl_max <= 16 ? 16 : (nbl_max <= 24 ? 24 : 32)); }
+// V blocks held in registers by the kp = 4 kernels: the smallest multiple of 4
+// that covers the sweep (fewer registers, more wavefronts in flight)
+static int rs_nb(int nbl_max) { return std::min(32, std::max(4, (nbl_max + 3) / 4 * 4)); }
+
+template <typename Fn>
+static void with_nb(int nb, Fn&& fn) {
+  switch (nb) {
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 12: fn(std::integral_constant<int, 12>{}); break;
+    case 16: fn(std::integral_constant<int, 16>{}); break;
+    case 20: fn(std::integral_constant<int, 20>{}); break;
+    case 24: fn(std::integral_constant<int, 24>{}); break;
+    case 28: fn(std::integral_constant<int, 28>{}); break;
+    default: fn(std::integral_constant<int, 32>{}); break;
+  }
+}
 
 template <int KP>
 static void launch_dot(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, const KArgs& a, int nbl_max) {
   using F = Fam<KP>;
   if constexpr (F::RS) {
-    const int nb = rs_nb(nbl_max);
-    if (nb == 8) plaunch(c, pidx, 3, k_dot4<F::NW, 8>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else if (nb == 16) plaunch(c, pidx, 3, k_dot4<F::NW, 16>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else if (nb == 24) plaunch(c, pidx, 3, k_dot4<F::NW, 24>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else plaunch(c, pidx, 3, k_dot4<F::NW, 32>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    with_nb(rs_nb(nbl_max), [&](auto nb) {
+      plaunch(c, pidx, 3, k_dot4<F::NW, decltype(nb)::value>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    });
   }
   else if constexpr (F::ROW) plaunch(c, pidx, 3, k_dot_row<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
   else plaunch(c, pidx, 3, k_dot_mfma<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
@@ -1761,11 +1779,9 @@ static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, cons
   using F = Fam<KP>;
   const uint32_t shm = (uint32_t)upd_shm<KP>(nbl_max);
   if constexpr (F::RS) {
-    const int nb = rs_nb(nbl_max);
-    if (nb == 8) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 8>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else if (nb == 16) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 16>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else if (nb == 24) plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 24>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-    else plaunch(c, pidx, 3, k_upd4<F::NW, MODE, 32>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    with_nb(rs_nb(nbl_max), [&](auto nb) {
+      plaunch(c, pidx, 3, k_upd4<F::NW, MODE, decltype(nb)::value>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    });
   } else if constexpr (F::ROW)
     plaunch(c, pidx, 3, k_upd_row<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
   else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
