@@ -150,7 +150,6 @@ static void spai_release(pmor_spai* h) {
   dfree(h->Icolptr, s);
   dfree(h->Irow, s);
   dfree(h->bucket_cols, s);
-  dfree(h->Pval_s, s);
   dfree(h->P1val_s, s);
   dfree(h->Qval_s, s);
   if (h->own_psell) free_sell(&h->psell, s);
@@ -197,9 +196,9 @@ static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
   PMOR_TRY(run_spai_ls(h, pb->aval, nullptr, h->P1val, &bad, stats ? &fro2 : nullptr));
   PMOR_TRY(dcopy(h->P1val, h->Pval, h->nnzP, st));
   PMOR_TRY(to_sell(h->psell, h->P1val, h->P1val_s, st));
-  PMOR_TRY(to_sell(h->psell, h->P1val, h->Pval_s, st));
   if (h->opts.update == PMOR_UPD_DIAG) PMOR_TRY(dfill(h->Qval, pb->n, 1.0, st));
   h->q_active = false;
+  h->d_active = false;
   h->s1 = s;
   h->p1 = p;
   const double t_pre = tp.stop();
@@ -225,14 +224,16 @@ static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* ava
   it.aval_s = aval_s;
   it.pkind = 0;
   if (h) {
-    it.pkind = h->q_active ? 2 : 1;
+    it.pkind = h->q_active ? 2 : (h->d_active ? 3 : 1);
     it.nnzP = h->nnzP;
     it.prow = h->Prowptr;
     it.pcol = h->Pcol;
-    it.pval = h->q_active ? h->P1val : h->Pval;
+    const bool fac = h->q_active || h->d_active;
+    it.pval = fac ? h->P1val : h->Pval;
     it.qval = h->Qval;
+    it.prs = h->d_active ? h->Qval : nullptr;
     it.psell = &h->psell;
-    it.pval_s = h->q_active ? h->P1val_s : h->Pval_s;
+    it.pval_s = h->P1val_s;  // Pval equals P1val unless an update is applied
     it.qval_s = h->Qval_s;
   }
   it.B = B;
@@ -453,7 +454,7 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
               al(&h->Qval, o.update == PMOR_UPD_PATTERN ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
               al(&h->rho, n) && al(&h->red, 512);
     if (ok && h->psell.cap > 0)
-      ok = al(&h->Pval_s, h->psell.cap) && al(&h->P1val_s, h->psell.cap) &&
+      ok = al(&h->P1val_s, h->psell.cap) &&
            (o.update != PMOR_UPD_PATTERN || al(&h->Qval_s, h->psell.cap));
     rc = ok ? build_into(h, s, p, stats) : fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
@@ -476,8 +477,9 @@ int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
   int32_t bad = -1;
   double fro2 = 0.0;
   if (h->opts.update == PMOR_UPD_DIAG) {
+    // P_l = diag(q) P_1 is also written out (export); solves apply the factors
     PMOR_TRY(run_update_diag(h, pb->aval, &bad, stats ? &fro2 : nullptr));
-    PMOR_TRY(to_sell(h->psell, h->Pval, h->Pval_s, pb->ctx->stream));
+    h->d_active = true;
   } else {
     PMOR_TRY(run_spai_ls(h, pb->aval, h->aval1, h->Qval, &bad, stats ? &fro2 : nullptr));
     PMOR_TRY(to_sell(h->psell, h->Qval, h->Qval_s, pb->ctx->stream));
@@ -650,7 +652,7 @@ struct SeqBuffers {
   double* aval_s = nullptr; // group x capA: A(l) in the sliced ELL layout (when the problem has one)
   double* pq_s = nullptr;   // group x capP: P_l / Q_l in the sliced ELL layout
   int64_t capA = 0, capP = 0;
-  double* q = nullptr;      // n (U-diag factors, scratch)
+  double* q = nullptr;      // group x n: U-diag factors q_l (P_l = diag(q_l) P_1)
   double* rho = nullptr;    // n (U-diag column residuals, scratch)
   double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
   int* bad = nullptr;       // group
@@ -678,7 +680,7 @@ struct SeqBuffers {
     };
     PMOR_TRY(al((void**)&aval, sizeof(double) * group * nnz));
     PMOR_TRY(al((void**)&pq, sizeof(double) * group * nnzP));
-    PMOR_TRY(al((void**)&q, sizeof(double) * n));
+    PMOR_TRY(al((void**)&q, sizeof(double) * group * n));
     PMOR_TRY(al((void**)&rho, sizeof(double) * n));
     PMOR_TRY(al((void**)&fro, sizeof(double) * group * 260));
     PMOR_TRY(al((void**)&bad, sizeof(int) * group));
@@ -687,7 +689,7 @@ struct SeqBuffers {
     return PMOR_OK;
   }
   static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n, int64_t capa = 0, int64_t capp = 0) {
-    return 8 * group * (nnz + nnzP + capa + capp) + 16 * n + 8 * 260 * group + 4 * group + 8 * 256;
+    return 8 * group * (nnz + nnzP + capa + capp + n) + 8 * n + 8 * 260 * group + 4 * group + 8 * 256;
   }
 };
 
@@ -744,11 +746,15 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
       fro_host[t] = pre0.fro_resid * pre0.fro_resid;
       bad[t] = pre0.bad_column;
     } else if (policy == PMOR_UPDATE && !upat) {
+      // P_l = diag(q_l) P_1 stays factored: the engine scales the rows of P_1 X
+      double* ql = sb.q + (int64_t)t * n;
       rc = set_device_int(sb.bad + t, 0x7fffffff, st);
-      if (rc == PMOR_OK) rc = launch_update_diag(h, Al, PQ, sb.q, sb.rho, sb.bad + t);
+      if (rc == PMOR_OK) rc = launch_update_diag(h, Al, nullptr, ql, sb.rho, sb.bad + t);
       if (rc == PMOR_OK && stats) rc = sumsq(sb.rho, n, sb.fro + (int64_t)t * 260, st);
-      x.pval = PQ;
-      x.pval_s = PQ_s;
+      x.pkind = 3;
+      x.pval = h->P1val;
+      x.pval_s = h->P1val_s;
+      x.prs = ql;
     } else {
       int32_t b = -1;
       double fro2 = 0.0;
@@ -766,7 +772,7 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
         x.pval_s = PQ_s;
       }
     }
-    if (rc == PMOR_OK && PQ_s && l > 0) rc = to_sell(h->psell, PQ, PQ_s, st);
+    if (rc == PMOR_OK && PQ_s && l > 0 && x.pkind != 3) rc = to_sell(h->psell, PQ, PQ_s, st);
     rec(2 + 2 * t);
     items[t] = x;
   }
@@ -851,13 +857,16 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
   // points per group: A and P/Q values plus the Krylov blocks of one system
   const int kp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-  const double per_point = 8.0 * (nnz + nnzP + pb->sell.cap + h->psell.cap) + 8.0 * (double)n * kp * (o.m + 7) +
+  // the U-diag update keeps P_l factored: no per-point P values
+  const bool rowq = policy == PMOR_UPDATE && h->opts.update != PMOR_UPD_PATTERN;
+  const int64_t nnzPp = rowq ? 0 : nnzP, capPp = rowq ? 0 : h->psell.cap;
+  const double per_point = 8.0 * (nnz + nnzPp + pb->sell.cap + capPp + n) + 8.0 * (double)n * kp * (o.m + 7) +
                            64.0 * 1024;
   size_t fr = 0, tot = 0;
   PMOR_HIP(hipMemGetInfo(&fr, &tot));
   const int group = (int)std::max(1.0, std::min<double>(npts, 0.6 * (double)fr / per_point));
   SeqBuffers sb;
-  rc = sb.alloc(group, nnz, nnzP, n, pb->ctx->stream, pb->sell.cap, h->psell.cap);
+  rc = sb.alloc(group, nnz, nnzPp, n, pb->ctx->stream, pb->sell.cap, capPp);
   if (rc != PMOR_OK) { spai_release(h); return rc; }
   int first_bad = PMOR_OK;
   for (int l0 = 0; l0 < npts && rc == PMOR_OK; l0 += group) {
@@ -920,13 +929,18 @@ struct ServerJob {
 
 // device bytes a job holds while admitted (an upper bound: the shadow sizes
 // are bounded by |J_j| times the longest column of A)
-static int64_t job_footprint(const pmor_problem* pb, int npts) {
+static int64_t job_footprint(const pmor_problem* pb, int npts, bool rowq) {
   const int64_t n = pb->n, nnz = pb->nnz, nnzP = pb->nnz;
   const int64_t sumI = nnzP * std::max<int64_t>(pb->max_col_len, 1);
   const int64_t spai = 8 * (3 * nnzP + nnz + 2 * n + 512) + 8 * (n + 1) + 4 * sumI +
                        4 * (3 * (n + 1) + 3 * nnzP + n) + 4096;
   const int64_t cap = pb->sell.cap;
-  return spai + 3 * 8 * cap + SeqBuffers::estimate(npts, nnz, nnzP, n, cap, cap);
+  return spai + 3 * 8 * cap + SeqBuffers::estimate(npts, nnz, rowq ? 0 : nnzP, n, cap, rowq ? 0 : cap);
+}
+
+// the U-diag update policy keeps every P_l factored (no per-point P values)
+static bool rows_scaled(int policy, const pmor_spai_opts& so) {
+  return policy == PMOR_UPDATE && so.update != PMOR_UPD_PATTERN;
 }
 }  // namespace pmor
 
@@ -966,7 +980,8 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   sv->jobs[J->id] = J;
   int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
   if (rc == PMOR_OK)
-    rc = J->sb.alloc(npts, jb.pb->nnz, J->h->nnzP, jb.pb->n, sv->ctx->stream, jb.pb->sell.cap, J->h->psell.cap);
+    rc = J->sb.alloc(npts, jb.pb->nnz, rows_scaled(jb.policy, J->h->opts) ? 0 : J->h->nnzP, jb.pb->n,
+                     sv->ctx->stream, jb.pb->sell.cap, rows_scaled(jb.policy, J->h->opts) ? 0 : J->h->psell.cap);
   J->items.assign(npts, SolveItem{});
   J->bad.assign(npts, -1);
   if (rc == PMOR_OK)
@@ -1074,7 +1089,7 @@ int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
   J->job = *job;
   J->s_list.assign(job->s_list, job->s_list + job->npts);
   J->p_list.assign(job->p_list, job->p_list + job->npts);
-  J->footprint = job_footprint(job->pb, job->npts);
+  J->footprint = job_footprint(job->pb, job->npts, rows_scaled(job->policy, sv->sopts));
   if (J->footprint + sv->engine_bytes > sv->budget) {
     delete J;
     return fail(PMOR_EADMIT, "job footprint exceeds the server's memory budget");

@@ -75,7 +75,7 @@ struct SegDesc {
   int kact;         // active (nonzero) right-hand sides
   int wg0, G;       // row-kernel workgroups [wg0, wg0 + G) of the logical grid
   int sp0, spG;     // SpMM workgroups [sp0, sp0 + spG)
-  int pkind;        // preconditioner: 0 none, 1 P, 2 Q P_1 (factored)
+  int pkind;        // preconditioner: 0 none, 1 P, 2 Q P_1 (factored), 3 diag(q) P_1 (row-scaled)
   int k;            // caller's columns
   int64_t r0;       // first row of the segment in the concatenated blocks
   const int32_t* arow;
@@ -85,6 +85,7 @@ struct SegDesc {
   const int32_t* pcol;
   const double* pval;   // P, or P_1 when pkind == 2
   const double* qval;   // Q when pkind == 2
+  const double* prs;    // q when pkind == 3 (n row scales)
   // sliced ELL copies (a_sp == nullptr / p_sp == nullptr: use the CSR arrays)
   const int32_t* a_sp;
   const int32_t* a_sw;
@@ -180,11 +181,11 @@ struct pmor_spai {
   int nbuckets = 0;
   bool identity_order = true;
   bool q_active = false;     // U-pattern update applied (apply Q (P_1 x))
+  bool d_active = false;     // U-diag update applied (apply diag(q) (P_1 x), q in Qval)
   double s1 = 0, p1 = 0;
   pmor::SellView psell;      // sliced ELL view of P's pattern (the problem's for PAT_A)
   bool own_psell = false;
-  double* Pval_s = nullptr;  // Pval, P1val, Qval in the sliced ELL layout
-  double* P1val_s = nullptr;
+  double* P1val_s = nullptr;  // P1val (= Pval before an update) and Qval in the sliced ELL layout
   double* Qval_s = nullptr;
 };
 
@@ -274,11 +275,12 @@ struct SolveItem {
   const int32_t* arow;
   const int32_t* acol;
   const double* aval;
-  int pkind;                  // 0 none, 1 P, 2 Q P_1
+  int pkind;                  // 0 none, 1 P, 2 Q P_1, 3 diag(q) P_1
   const int32_t* prow;
   const int32_t* pcol;
   const double* pval;
   const double* qval;
+  const double* prs;          // q of diag(q) P_1 (pkind 3)
   const SellView* asell;      // sliced ELL views (NULL or cap 0: none) and values in them
   const double* aval_s;
   const SellView* psell;

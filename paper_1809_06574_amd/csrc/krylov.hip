@@ -1274,6 +1274,11 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
 #pragma unroll
     for (int t = 0; t < KP; ++t) acc[t] += __shfl_xor(acc[t], o, 64);
   if (!valid) return;
+  if (a.which == 1 && pk == 3) {  // P = diag(q) P_1: scale the row of P_1 X
+    const double qs = d.prs[local];
+#pragma unroll
+    for (int t = 0; t < KP; ++t) acc[t] *= qs;
+  }
   const int64_t ro = (int64_t)local * KP;
   if constexpr (CONV) {
     double xr[KP];
@@ -1886,7 +1891,7 @@ class RunnerT final : public Runner {
       d.spG = Gs_[sl];
       d.pkind = it->pkind;
       d.arow = it->arow; d.acol = it->acol; d.aval = it->aval;
-      d.prow = it->prow; d.pcol = it->pcol; d.pval = it->pval; d.qval = it->qval;
+      d.prow = it->prow; d.pcol = it->pcol; d.pval = it->pval; d.qval = it->qval; d.prs = it->prs;
       if (it->asell && it->asell->cap > 0 && it->aval_s) {
         d.a_sp = it->asell->ptr; d.a_sw = it->asell->wid; d.a_sc = it->asell->col; d.a_sv = it->aval_s;
       }
@@ -2196,6 +2201,7 @@ class RunnerT final : public Runner {
         const double mat = 12.0 * item_[i]->nnzP + 4.0 * (item_[i]->n + 1);
         if (item_[i]->pkind == 0) return 3.0 * blkb(i);
         if (item_[i]->pkind == 1) return mat + 3.0 * blkb(i);
+        if (item_[i]->pkind == 3) return mat + 8.0 * item_[i]->n + 3.0 * blkb(i);
         return 2.0 * mat + 5.0 * blkb(i);
       });
       SpArgs sa{E.seg_d, stab_d, E.st, 0, 1, E.Z.p, E.W.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};

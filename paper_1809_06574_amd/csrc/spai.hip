@@ -494,6 +494,7 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
 
 // ---------------------------------------------------------------------------
 // U-diag update: q_i = <A(l) e_i, A(1) e_i> / ||A(l) e_i||^2 and P_l = diag(q) P_1
+// (P_l written only when Pl is not NULL; the engine can also apply the factors)
 // ---------------------------------------------------------------------------
 __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscslot, const double* al,
                               const double* a1, const int32_t* Prowptr, const double* P1, double* Pl, double* q,
@@ -514,7 +515,8 @@ __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscsl
   // ||A(1) e_i - q_i A(l) e_i||^2 = n11 - 2 q num + q^2 den
   const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
   rho[i] = sqrt(r2 > 0.0 ? r2 : 0.0);
-  for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qi * P1[e];
+  if (Pl)
+    for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qi * P1[e];
 }
 
 int launch_update_diag(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int* dbad) {
