@@ -1213,13 +1213,16 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
       }
     } else if (sp) {
       // sliced ELL: entry k of the row at ptr[slice] + 64 k + row % 64; the LPR
-      // lanes of a row take k = sub, sub + LPR, ...; matrix data streams once
+      // lanes of a row take k = sub, sub + LPR, ...  The pattern (columns) and
+      // a factored P_1 are shared by the points of a sequence and stay cached;
+      // a point's own values stream (nontemporal)
       const int64_t base = sp[local >> 6] + (local & 63);
       const int w = sw[local >> 6];
+      const bool own = !(a.which == 1 && (pk == 2 || pk == 3));
       for (int k = sub; k < w; k += LPR) {
         const int64_t q = base + (int64_t)k * 64;
-        const int c = __builtin_nontemporal_load(sc + q);
-        const double v = __builtin_nontemporal_load(sv + q);
+        const int c = sc[q];
+        const double v = own ? __builtin_nontemporal_load(sv + q) : sv[q];
         if constexpr (KP % 2 == 0) {
           const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * KP);
 #pragma unroll
