@@ -342,24 +342,80 @@ __global__ void k_validate_pattern(int n, int nnz, const int32_t* colptr, const 
   if (!diag) atomicOr(err, 8);
 }
 
-// I_j = sorted union of the rows of A(:, c), c in J_j.
-//
-// Columns whose candidate list (sum of |A(:, c)|, c in J_j) fits SH_CAP: one
-// wavefront per column copies the candidates into LDS, sorts them (bitonic)
-// and keeps the distinct rows.  Longer lists: a k-way merge of the CSC columns
-// by one lane (k_shadow_merge, called for those columns only).
+// I_j = sorted union of the rows of A(:, c), c in J_j, by the size of J_j:
+//  - |J_j| <= SH_SMALL: one lane merges the |J_j| sorted CSC columns with its
+//    cursors and column heads in registers (stencil-like patterns);
+//  - larger J_j whose candidate list (sum of |A(:, c)|) fits SH_CAP: one
+//    wavefront copies the candidates into LDS, sorts them (bitonic) and keeps
+//    the distinct rows;
+//  - longer candidate lists: a k-way merge by one lane with the cursors in
+//    memory (rare).
+// Columns with |J_j| > SH_JMAX are not supported; they report count 0 and
+// their |J_j| through maxJ, which the caller turns into an error.
+constexpr int SH_SMALL = 8;
 constexpr int SH_CAP = 2048;
+constexpr int SH_JMAX = 64;
 
-__device__ __forceinline__ int shadow_total(int nj, int ja, const int32_t* Jrow, const int32_t* Acolptr, int lane) {
-  int tot = 0;
-  for (int t = lane; t < nj; t += 64) {
-    const int c = Jrow[ja + t];
-    tot += Acolptr[c + 1] - Acolptr[c];
-  }
-  for (int o = 32; o >= 1; o >>= 1) tot += __shfl_xor(tot, o, 64);
-  return tot;
+__device__ __forceinline__ int wave_max(int x) {
+  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+  return x;
 }
 
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_shadow_small(int n, const int32_t* Jcolptr, const int32_t* Jrow,
+                                                      const int32_t* Acolptr, const int32_t* Arowidx,
+                                                      int64_t* counts, const int64_t* Icolptr, int32_t* Irow,
+                                                      int* maxJ, int* maxI) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int nj = 0, cnt = 0;
+  if (j < n) {
+    const int ja = Jcolptr[j];
+    nj = Jcolptr[j + 1] - ja;
+    if (nj <= SH_SMALL) {
+      int cur[SH_SMALL], end[SH_SMALL], head[SH_SMALL];
+#pragma unroll
+      for (int t = 0; t < SH_SMALL; ++t) {
+        cur[t] = 0;
+        end[t] = 0;
+        if (t < nj) {
+          const int c = Jrow[ja + t];
+          cur[t] = Acolptr[c];
+          end[t] = Acolptr[c + 1];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < SH_SMALL; ++t) head[t] = cur[t] < end[t] ? Arowidx[cur[t]] : 0x7fffffff;
+      int64_t pos = FILL ? Icolptr[j] : 0;
+      while (true) {
+        int rmin = 0x7fffffff;
+#pragma unroll
+        for (int t = 0; t < SH_SMALL; ++t) rmin = min(rmin, head[t]);
+        if (rmin == 0x7fffffff) break;
+#pragma unroll
+        for (int t = 0; t < SH_SMALL; ++t)
+          if (head[t] == rmin) {
+            ++cur[t];
+            head[t] = cur[t] < end[t] ? Arowidx[cur[t]] : 0x7fffffff;
+          }
+        if (FILL) Irow[pos + cnt] = rmin;
+        ++cnt;
+      }
+      if (!FILL) counts[j] = cnt;
+    } else {
+      nj = 0;  // another kernel's column
+    }
+  }
+  if (!FILL) {
+    const int mj = wave_max(nj), mi = wave_max(cnt);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMax(maxJ, mj);
+      atomicMax(maxI, mi);
+    }
+  }
+}
+
+// columns SH_SMALL < |J_j| <= SH_JMAX with at most SH_CAP candidates; a block
+// scans 64 columns at a time and sorts the qualifying ones one after another
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolptr, const int32_t* Jrow,
                                                     const int32_t* Acolptr, const int32_t* Arowidx, int64_t* counts,
@@ -367,65 +423,75 @@ __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolpt
   __shared__ int buf[SH_CAP];
   const int lane = threadIdx.x;
   int mj = 0, mi = 0;
-  for (int j = blockIdx.x; j < n; j += gridDim.x) {
-    const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
-    if (nj > 64) {  // unsupported; reported through maxJ
-      if (!FILL && lane == 0) counts[j] = 0;
-      mj = max(mj, nj);
-      continue;
+  for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
+    const int jl = j0 + lane;
+    const int njl = jl < n ? Jcolptr[jl + 1] - Jcolptr[jl] : 0;
+    if (njl > SH_JMAX) {  // unsupported; reported through maxJ
+      if (!FILL) counts[jl] = 0;
+      mj = max(mj, njl);
     }
-    const int total = shadow_total(nj, ja, Jrow, Acolptr, lane);
-    if (total > SH_CAP) continue;  // k_shadow_merge
-    // candidate offsets: lane t owns column t of J_j
-    int len = 0, c0 = 0;
-    if (lane < nj) {
-      const int c = Jrow[ja + lane];
-      c0 = Acolptr[c];
-      len = Acolptr[c + 1] - c0;
-    }
-    int incl = len;  // inclusive scan over the lanes
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    const int off = incl - len;
-    int P = 1;
-    while (P < total) P <<= 1;
-    for (int q = 0; q < len; ++q) buf[off + q] = Arowidx[c0 + q];
-    for (int i = total + lane; i < P; i += 64) buf[i] = 0x7fffffff;
-    __syncthreads();
-    for (int k = 2; k <= P; k <<= 1)
-      for (int jj = k >> 1; jj > 0; jj >>= 1) {
-        for (int i = lane; i < P; i += 64) {
-          const int ixj = i ^ jj;
-          if (ixj > i) {
-            const int a = buf[i], b = buf[ixj];
-            if ((a > b) == ((i & k) == 0)) {
-              buf[i] = b;
-              buf[ixj] = a;
+    unsigned long long todo = __ballot(njl > SH_SMALL && njl <= SH_JMAX);
+    while (todo) {
+      const int b = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const int j = j0 + b;
+      const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
+      // lane t owns column t of J_j
+      int len = 0, c0 = 0;
+      if (lane < nj) {
+        const int c = Jrow[ja + lane];
+        c0 = Acolptr[c];
+        len = Acolptr[c + 1] - c0;
+      }
+      int incl = len;  // inclusive scan over the lanes
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      const int total = __shfl(incl, 63, 64);
+      if (total > SH_CAP) continue;  // k_shadow_merge
+      const int off = incl - len;
+      int P = 1;
+      while (P < total) P <<= 1;
+      for (int q = 0; q < len; ++q) buf[off + q] = Arowidx[c0 + q];
+      for (int i = total + lane; i < P; i += 64) buf[i] = 0x7fffffff;
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1)
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+          for (int i = lane; i < P; i += 64) {
+            const int ixj = i ^ jj;
+            if (ixj > i) {
+              const int x = buf[i], y = buf[ixj];
+              if ((x > y) == ((i & k) == 0)) {
+                buf[i] = y;
+                buf[ixj] = x;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
+      // distinct rows, in order
+      int64_t pos = FILL ? Icolptr[j] : 0;
+      int cnt = 0;
+      for (int i0 = 0; i0 < total; i0 += 64) {
+        const int i = i0 + lane;
+        const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
+        const unsigned long long m = __ballot(keep);
+        if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
+        cnt += __popcll(m);
       }
-    // distinct rows, in order
-    int64_t pos = FILL ? Icolptr[j] : 0;
-    int cnt = 0;
-    for (int i0 = 0; i0 < total; i0 += 64) {
-      const int i = i0 + lane;
-      const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
-      const unsigned long long m = __ballot(keep);
-      if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
-      cnt += __popcll(m);
+      __syncthreads();
+      if (!FILL && lane == 0) counts[j] = cnt;
+      mj = max(mj, nj);
+      mi = max(mi, cnt);
     }
-    __syncthreads();
-    if (!FILL && lane == 0) counts[j] = cnt;
-    mj = max(mj, nj);
-    mi = max(mi, cnt);
   }
-  if (!FILL && lane == 0) {
-    atomicMax(maxJ, mj);
-    atomicMax(maxI, mi);
+  if (!FILL) {
+    mj = wave_max(mj);
+    if (lane == 0) {
+      atomicMax(maxJ, mj);
+      atomicMax(maxI, mi);
+    }
   }
 }
 
@@ -437,15 +503,14 @@ __global__ void k_shadow_merge(int n, const int32_t* Jcolptr, const int32_t* Jro
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
-  constexpr int MAXJ = 64;
-  if (nj > MAXJ) return;
+  if (nj <= SH_SMALL || nj > SH_JMAX) return;
   int total = 0;
   for (int t = 0; t < nj; ++t) {
     const int c = Jrow[ja + t];
     total += Acolptr[c + 1] - Acolptr[c];
   }
   if (total <= SH_CAP) return;
-  int cur[MAXJ], end[MAXJ];
+  int cur[SH_JMAX], end[SH_JMAX];
   for (int t = 0; t < nj; ++t) {
     int c = Jrow[ja + t];
     cur[t] = Acolptr[c];
@@ -475,11 +540,14 @@ static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, con
                          const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow, int* maxJ,
                          int* maxI, hipStream_t st) {
   if (n <= 0) return PMOR_OK;
-  const unsigned gs = (unsigned)std::min(n, 16384);
+  const unsigned g1 = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_shadow_small<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
+                     Icolptr, Irow, maxJ, maxI);
+  const unsigned gs = (unsigned)std::min((n + 63) / 64, 8192);
   hipLaunchKernelGGL(k_shadow_sort<FILL>, dim3(gs), dim3(64), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
                      Icolptr, Irow, maxJ, maxI);
-  hipLaunchKernelGGL(k_shadow_merge<FILL>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, Jcolptr, Jrow,
-                     Acolptr, Arowidx, counts, Icolptr, Irow, maxJ, maxI);
+  hipLaunchKernelGGL(k_shadow_merge<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
+                     Icolptr, Irow, maxJ, maxI);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }

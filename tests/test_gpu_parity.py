@@ -283,6 +283,62 @@ def test_explicit_power_law_pattern(ctx, dims, prec):
     assert np.all(rel <= 1e-8)
 
 
+def _dense_block_job():
+    """A with a dense 250 x 12 block in its leading columns and an explicit
+    pattern whose J_j take three size classes: |J_j| <= 8 (most columns),
+    9..64 with short candidate lists, and J_j holding the 12 dense columns,
+    whose candidate lists (over 3000 rows before deduplication) exceed the
+    LDS sort of the shadow kernels."""
+    from synth.gen import _coo_to_csr
+    n = 600
+    rng = np.random.default_rng([778, 1])
+    rr, cc, vv = [], [], []
+    for i in range(n):
+        for j, v in ((i - 1, -1.0), (i, 8.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                rr.append(i); cc.append(j); vv.append(v)
+    br, bc = np.meshgrid(np.arange(250), np.arange(12), indexing="ij")
+    keep = np.abs(br - bc) > 1
+    rr += list(br[keep]); cc += list(bc[keep]); vv += list(0.1 * rng.standard_normal(int(keep.sum())))
+    K = _coo_to_csr(n, np.array(rr), np.array(cc), np.array(vv))
+    M = _coo_to_csr(n, np.arange(n), np.arange(n), np.ones(n))
+    colptr, rows = [0], []
+    for j in range(n):
+        if j < 20:
+            J = set(range(12)) | {j}
+        elif 300 <= j < 330:
+            J = set(range(j - 6, j + 7))
+        else:
+            J = {x for x in (j - 1, j, j + 1) if 0 <= x < n}
+        rows += sorted(J)
+        colptr.append(len(rows))
+    pat = (np.array(colptr, dtype=np.int64), np.array(rows, dtype=np.int32))
+    B = rng.standard_normal((n, 2))
+    return Job("dense_block", n, {"M0": M, "K0": K}, 1.0, np.array([0.5]), B, pattern=pat)
+
+
+def test_shadow_sets_all_size_classes(ctx):
+    from paper_1809_06574_amd import Problem
+    job = _dense_block_job()
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col, explicit=job.pattern)
+    lens = np.diff(pat.J_colptr)
+    assert lens.max() > 8 and lens.min() <= 8
+    assert np.diff(pat.I_colptr).max() <= 512
+    h = pb.spai_build(job.s, job.p_list[0], pattern=job.pattern)
+    jc, jr, ic, ir = h.export_sets()
+    np.testing.assert_array_equal(np_(jc), pat.J_colptr)
+    np.testing.assert_array_equal(np_(jr), pat.J_row)
+    np.testing.assert_array_equal(np_(ic), pat.I_colptr)
+    np.testing.assert_array_equal(np_(ir), pat.I_row)
+    val = asm.values(job.s, job.p_list[0])
+    pv, rho = spai_build(job.n, asm.rowptr, asm.col, val, pat)
+    exp = h.export()
+    err = col_rel_err(job.n, pat.J_colptr, pat.P_slot, np_(exp["val"]), pv)
+    assert err <= 1e-10, err
+
+
 def test_table2_norms(ctx):
     from paper_1809_06574_amd import Problem
     job = config0()
