@@ -653,7 +653,7 @@ struct SeqBuffers {
   double* pq_s = nullptr;   // group x capP: P_l / Q_l in the sliced ELL layout
   int64_t capA = 0, capP = 0;
   double* q = nullptr;      // group x n: U-diag factors q_l (P_l = diag(q_l) P_1)
-  double* rho = nullptr;    // n (U-diag column residuals, scratch)
+  double* rho = nullptr;    // group x n: U-diag column residuals
   double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
   int* bad = nullptr;       // group
   int64_t bytes = 0;
@@ -681,7 +681,7 @@ struct SeqBuffers {
     PMOR_TRY(al((void**)&aval, sizeof(double) * group * nnz));
     PMOR_TRY(al((void**)&pq, sizeof(double) * group * nnzP));
     PMOR_TRY(al((void**)&q, sizeof(double) * group * n));
-    PMOR_TRY(al((void**)&rho, sizeof(double) * n));
+    PMOR_TRY(al((void**)&rho, sizeof(double) * group * n));
     PMOR_TRY(al((void**)&fro, sizeof(double) * group * 260));
     PMOR_TRY(al((void**)&bad, sizeof(int) * group));
     if (capA > 0) PMOR_TRY(al((void**)&aval_s, sizeof(double) * group * capA));
@@ -689,9 +689,117 @@ struct SeqBuffers {
     return PMOR_OK;
   }
   static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n, int64_t capa = 0, int64_t capp = 0) {
-    return 8 * group * (nnz + nnzP + capa + capp + n) + 8 * n + 8 * 260 * group + 4 * group + 8 * 256;
+    return 8 * group * (nnz + nnzP + capa + capp + 2 * n) + 8 * 260 * group + 4 * group + 8 * 256;
   }
 };
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static SolveItem point_item(pmor_problem* pb, pmor_spai* h, const double* Al, const double* Al_s, const double* B,
+                            int64_t ldb, int k, double* X, int64_t ldx, int l, pmor_stats* stats) {
+  SolveItem x = item_of(pb, nullptr, Al, Al_s, B, ldb, k, X + (int64_t)l * pb->n * ldx, ldx,
+                        stats ? &stats[l] : nullptr);
+  x.pkind = 1;
+  x.prow = h->Prowptr;
+  x.pcol = h->Pcol;
+  x.nnzP = h->nnzP;
+  x.psell = &h->psell;
+  x.pval = h->P1val;
+  x.pval_s = h->P1val_s;
+  x.tag = l;
+  return x;
+}
+
+// prepare_points for the U-diag update: every A(l) (straight into the sliced
+// ELL layout when the problem has one, else in CSR order) and every factor
+// q_l in launches of PTS_MAX points; P_l = diag(q_l) P_1 stays factored and
+// the engine scales the rows of P_1 X.  The batch's assembly and update times
+// are shared evenly among its points in stats.
+static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_list, const double* p_list, int l0,
+                               int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
+                               pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items,
+                               int* bad) {
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  const bool sell = sb.capA > 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (stats)
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) { e = nullptr; (void)hipGetLastError(); }
+  auto rec = [&](int i) {
+    if (ev[i]) (void)hipEventRecord(ev[i], st);
+  };
+  int rc = PMOR_OK;
+  rec(0);
+  for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
+    const int m = std::min(PTS_MAX, cnt - c0);
+    rc = sell ? launch_assemble_pts(pb, s_list + l0 + c0, p_list + l0 + c0, m, &pb->sell,
+                                    sb.aval_s + (int64_t)c0 * sb.capA, sb.capA, st)
+              : launch_assemble_pts(pb, s_list + l0 + c0, p_list + l0 + c0, m, nullptr,
+                                    sb.aval + (int64_t)c0 * pb->nnz, pb->nnz, st);
+  }
+  rec(1);
+  if (rc == PMOR_OK) {
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, sb.bad, cnt, 0x7fffffff);
+    if (hipGetLastError() != hipSuccess) rc = fail(PMOR_EHIP, "launch failed");
+  }
+  for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
+    const int m = std::min(PTS_MAX, cnt - c0);
+    rc = launch_update_diag_pts(h, s_list + l0 + c0, p_list + l0 + c0, m, sb.q + (int64_t)c0 * n,
+                                sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+  }
+  if (rc == PMOR_OK && stats) rc = sumsq_pts(sb.rho, n, cnt, sb.fro, 260, st);
+  rec(2);
+  std::vector<int> bd(cnt, 0x7fffffff);
+  std::vector<double> fr2(stats ? (size_t)cnt * 260 : 0, 0.0);
+  if (rc == PMOR_OK) {
+    bool ok = hipMemcpyAsync(bd.data(), sb.bad, sizeof(int) * cnt, hipMemcpyDeviceToHost, st) == hipSuccess;
+    if (ok && stats)
+      ok = hipMemcpyAsync(fr2.data(), sb.fro, sizeof(double) * 260 * cnt, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) rc = fail(PMOR_EHIP, "copy of the update verdicts failed");
+  }
+  float ta = 0.f, tp = 0.f;
+  if (rc == PMOR_OK && ev[0] && ev[1] && ev[2]) {
+    (void)hipEventElapsedTime(&ta, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&tp, ev[1], ev[2]);
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc != PMOR_OK) return rc;
+  for (int t = 0; t < cnt; ++t) {
+    const int l = l0 + t;
+    const double* Al = sell ? nullptr : sb.aval + (int64_t)t * pb->nnz;
+    const double* Al_s = sell ? sb.aval_s + (int64_t)t * sb.capA : nullptr;
+    SolveItem x = point_item(pb, h, Al, Al_s, B, ldb, k, X, ldx, l, stats);
+    double fro2 = 0.0;
+    if (l == 0) {
+      bad[t] = pre0.bad_column;
+      fro2 = pre0.fro_resid * pre0.fro_resid;
+    } else {
+      x.pkind = 3;
+      x.prs = sb.q + (int64_t)t * n;
+      bad[t] = (bd[t] == 0x7fffffff) ? -1 : bd[t];
+      if (stats) fro2 = fr2[(size_t)t * 260];
+    }
+    items[t] = x;
+    if (stats) {
+      pmor_stats& S = stats[l];
+      S.t_assemble_ms = ta / cnt;
+      S.t_precond_ms = l == 0 ? 0.0 : tp / cnt;
+      S.fro_resid = std::sqrt(fro2);
+      S.bad_column = bad[t];
+      if (l == 0) {
+        S.t_assemble_ms += pre0.t_assemble_ms;
+        S.t_precond_ms += pre0.t_precond_ms;
+      }
+    }
+  }
+  return PMOR_OK;
+}
 
 // Points [l0, l0 + cnt) of a sequence whose P_1 (point 0) is h's anchor: A(l)
 // into sb.aval + t nnz, the point's preconditioner (P_1 for point 0, else the
@@ -703,9 +811,9 @@ struct SeqBuffers {
 static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const double* s_list, const double* p_list,
                           int l0, int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
                           pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
+  if (policy == PMOR_UPDATE && h->opts.update != PMOR_UPD_PATTERN)
+    return prepare_points_diag(pb, h, s_list, p_list, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, items, bad);
   hipStream_t st = pb->ctx->stream;
-  const bool upat = h->opts.update == PMOR_UPD_PATTERN;
-  const int n = pb->n;
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
   std::vector<hipEvent_t> ev;
   if (stats) {
@@ -732,29 +840,10 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
     if (rc == PMOR_OK && Al_s) rc = to_sell(pb->sell, Al, Al_s, st);
     rec(1 + 2 * t);
     if (rc != PMOR_OK) break;
-    SolveItem x = item_of(pb, nullptr, Al, Al_s, B, ldb, k, X + (int64_t)l * n * ldx, ldx,
-                          stats ? &stats[l] : nullptr);
-    x.pkind = 1;
-    x.prow = h->Prowptr;
-    x.pcol = h->Pcol;
-    x.nnzP = nnzP;
-    x.psell = &h->psell;
-    x.tag = l;
+    SolveItem x = point_item(pb, h, Al, Al_s, B, ldb, k, X, ldx, l, stats);
     if (l == 0) {
-      x.pval = h->P1val;
-      x.pval_s = h->P1val_s;
       fro_host[t] = pre0.fro_resid * pre0.fro_resid;
       bad[t] = pre0.bad_column;
-    } else if (policy == PMOR_UPDATE && !upat) {
-      // P_l = diag(q_l) P_1 stays factored: the engine scales the rows of P_1 X
-      double* ql = sb.q + (int64_t)t * n;
-      rc = set_device_int(sb.bad + t, 0x7fffffff, st);
-      if (rc == PMOR_OK) rc = launch_update_diag(h, Al, nullptr, ql, sb.rho, sb.bad + t);
-      if (rc == PMOR_OK && stats) rc = sumsq(sb.rho, n, sb.fro + (int64_t)t * 260, st);
-      x.pkind = 3;
-      x.pval = h->P1val;
-      x.pval_s = h->P1val_s;
-      x.prs = ql;
     } else {
       int32_t b = -1;
       double fro2 = 0.0;
@@ -772,25 +861,9 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
         x.pval_s = PQ_s;
       }
     }
-    if (rc == PMOR_OK && PQ_s && l > 0 && x.pkind != 3) rc = to_sell(h->psell, PQ, PQ_s, st);
+    if (rc == PMOR_OK && PQ_s && l > 0) rc = to_sell(h->psell, PQ, PQ_s, st);
     rec(2 + 2 * t);
     items[t] = x;
-  }
-  if (rc == PMOR_OK && policy == PMOR_UPDATE && !upat) {
-    std::vector<int> bd(cnt, 0x7fffffff);
-    std::vector<double> fr2((size_t)cnt * 260, 0.0);
-    rc = hipMemcpyAsync(bd.data(), sb.bad, sizeof(int) * cnt, hipMemcpyDeviceToHost, st) == hipSuccess ? PMOR_OK
-                                                                                                  : PMOR_EHIP;
-    if (rc == PMOR_OK && stats)
-      rc = hipMemcpyAsync(fr2.data(), sb.fro, sizeof(double) * 260 * cnt, hipMemcpyDeviceToHost, st) == hipSuccess
-               ? PMOR_OK : PMOR_EHIP;
-    if (rc == PMOR_OK) rc = hipStreamSynchronize(st) == hipSuccess ? PMOR_OK : PMOR_EHIP;
-    if (rc != PMOR_OK) set_error("copy of the update verdicts failed");
-    for (int t = 0; t < cnt && rc == PMOR_OK; ++t) {
-      if (l0 + t == 0) continue;
-      bad[t] = (bd[t] == 0x7fffffff) ? -1 : bd[t];
-      fro_host[t] = fr2[(size_t)t * 260];
-    }
   }
   if (rc == PMOR_OK) rc = hipStreamSynchronize(st) == hipSuccess ? PMOR_OK : fail(PMOR_EHIP, "synchronise failed");
   if (stats && rc == PMOR_OK) {
@@ -860,13 +933,15 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   // the U-diag update keeps P_l factored: no per-point P values
   const bool rowq = policy == PMOR_UPDATE && h->opts.update != PMOR_UPD_PATTERN;
   const int64_t nnzPp = rowq ? 0 : nnzP, capPp = rowq ? 0 : h->psell.cap;
-  const double per_point = 8.0 * (nnz + nnzPp + pb->sell.cap + capPp + n) + 8.0 * (double)n * kp * (o.m + 7) +
+  // and A(l) only in the sliced ELL layout when it has one
+  const int64_t nnzA = (rowq && pb->sell.cap > 0) ? 0 : nnz;
+  const double per_point = 8.0 * (nnzA + nnzPp + pb->sell.cap + capPp + 2 * n) + 8.0 * (double)n * kp * (o.m + 7) +
                            64.0 * 1024;
   size_t fr = 0, tot = 0;
   PMOR_HIP(hipMemGetInfo(&fr, &tot));
   const int group = (int)std::max(1.0, std::min<double>(npts, 0.6 * (double)fr / per_point));
   SeqBuffers sb;
-  rc = sb.alloc(group, nnz, nnzPp, n, pb->ctx->stream, pb->sell.cap, capPp);
+  rc = sb.alloc(group, nnzA, nnzPp, n, pb->ctx->stream, pb->sell.cap, capPp);
   if (rc != PMOR_OK) { spai_release(h); return rc; }
   int first_bad = PMOR_OK;
   for (int l0 = 0; l0 < npts && rc == PMOR_OK; l0 += group) {
@@ -935,7 +1010,8 @@ static int64_t job_footprint(const pmor_problem* pb, int npts, bool rowq) {
   const int64_t spai = 8 * (3 * nnzP + nnz + 2 * n + 512) + 8 * (n + 1) + 4 * sumI +
                        4 * (3 * (n + 1) + 3 * nnzP + n) + 4096;
   const int64_t cap = pb->sell.cap;
-  return spai + 3 * 8 * cap + SeqBuffers::estimate(npts, nnz, rowq ? 0 : nnzP, n, cap, rowq ? 0 : cap);
+  return spai + 3 * 8 * cap + SeqBuffers::estimate(npts, (rowq && cap > 0) ? 0 : nnz, rowq ? 0 : nnzP, n, cap,
+                                                   rowq ? 0 : cap);
 }
 
 // the U-diag update policy keeps every P_l factored (no per-point P values)
@@ -979,9 +1055,11 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   pre0.bad_column = -1;
   sv->jobs[J->id] = J;
   int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
-  if (rc == PMOR_OK)
-    rc = J->sb.alloc(npts, jb.pb->nnz, rows_scaled(jb.policy, J->h->opts) ? 0 : J->h->nnzP, jb.pb->n,
-                     sv->ctx->stream, jb.pb->sell.cap, rows_scaled(jb.policy, J->h->opts) ? 0 : J->h->psell.cap);
+  if (rc == PMOR_OK) {
+    const bool rq = rows_scaled(jb.policy, J->h->opts);
+    rc = J->sb.alloc(npts, (rq && jb.pb->sell.cap > 0) ? 0 : jb.pb->nnz, rq ? 0 : J->h->nnzP, jb.pb->n,
+                     sv->ctx->stream, jb.pb->sell.cap, rq ? 0 : J->h->psell.cap);
+  }
   J->items.assign(npts, SolveItem{});
   J->bad.assign(npts, -1);
   if (rc == PMOR_OK)

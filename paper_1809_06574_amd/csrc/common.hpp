@@ -256,6 +256,16 @@ int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
+// points of a sequence, at most PTS_MAX per call (s_list, p_list: host arrays of cnt):
+// A(l) into out + l * ostride (CSR order, or the sliced ELL layout of sv when not NULL);
+// the U-diag factors q_l, rho_l (stride n) and the first zero column into bad[l]
+// (bad must hold 0x7fffffff); per-point sums of squares into out[l * ostride]
+constexpr int PTS_MAX = 8;
+int launch_assemble_pts(pmor_problem* pb, const double* s_list, const double* p_list, int cnt, const SellView* sv,
+                        double* out, int64_t ostride, hipStream_t st);
+int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
+                           int* bad, hipStream_t st);
+int sumsq_pts(const double* x, int64_t n, int cnt, double* out, int64_t ostride, hipStream_t st);
 // U-diag update into caller buffers (no host synchronisation): P_l = diag(q) P_1
 // into pl, q into q, column residuals into rho, the smallest failing column into
 // *dbad (device int, must hold INT_MAX beforehand)

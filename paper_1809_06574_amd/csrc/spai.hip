@@ -581,6 +581,150 @@ int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* ou
 }
 
 // ---------------------------------------------------------------------------
+// the points of a sequence, PTS_MAX per launch: A(l) (into the CSR order or
+// straight into the sliced ELL layout) and the U-diag factors, with the term
+// values read once for all points of the launch.  A(l) is formed exactly as by
+// k_assemble (same terms, same order), so the results match the one-point
+// calls bit for bit.
+// ---------------------------------------------------------------------------
+struct PtsCoefs {
+  double c[PTS_MAX][PMOR_NROLES];  // by term slot
+  int cnt, nt;
+};
+
+static PtsCoefs pts_coefs(const pmor_problem* pb, const double* s_list, const double* p_list, int cnt) {
+  PtsCoefs pc{};
+  pc.cnt = cnt;
+  pc.nt = pb->nterms;
+  for (int l = 0; l < cnt; ++l) {
+    double c[PMOR_NROLES];
+    role_coefs(s_list[l], p_list[l], c);
+    for (int r = 0; r < PMOR_NROLES; ++r)
+      if (pb->role_slot[r] >= 0) pc.c[l][pb->role_slot[r]] = c[r];
+  }
+  return pc;
+}
+
+// out[l * ostride + q] = A(l) at CSR position map[q] (q itself when map is NULL), 0 where map[q] < 0
+__global__ void k_assemble_pts(int64_t len, const int32_t* __restrict__ map, int64_t nnz,
+                               const double* __restrict__ tval, PtsCoefs pc, double* __restrict__ out,
+                               int64_t ostride) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = map ? (int64_t)map[q] : q;
+    double tv[PMOR_NROLES];
+#pragma unroll
+    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = (e >= 0 && t < pc.nt) ? tval[(int64_t)t * nnz + e] : 0.0;
+    for (int l = 0; l < pc.cnt; ++l) {
+      double acc = 0.0;
+      for (int t = 0; t < pc.nt; ++t) acc += pc.c[l][t] * tv[t];
+      out[(int64_t)l * ostride + q] = e >= 0 ? acc : 0.0;
+    }
+  }
+}
+
+int launch_assemble_pts(pmor_problem* pb, const double* s_list, const double* p_list, int cnt, const SellView* sv,
+                        double* out, int64_t ostride, hipStream_t st) {
+  const int64_t len = sv ? sv->cap : pb->nnz;
+  if (len == 0 || cnt <= 0) return PMOR_OK;
+  if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one assembly launch");
+  const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
+  const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_assemble_pts, dim3(g), dim3(256), 0, st, len, sv ? (const int32_t*)sv->map : nullptr,
+                     pb->nnz, pb->tval, pc, out, ostride);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+// U-diag factors of the points of pc: q_l(i), rho_l(i) = ||A(1) e_i - q_l(i) A(l) e_i||
+// and the first column with ||A(l) e_i|| = 0 (atomicMin into bad[l])
+__global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* cscslot, int64_t nnz,
+                                  const double* __restrict__ tval, PtsCoefs pc, const double* __restrict__ a1,
+                                  double* q, double* rho, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double num[PTS_MAX], den[PTS_MAX];
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = 0.0;
+  double n11 = 0.0;
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    double tv[PMOR_NROLES];
+#pragma unroll
+    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    const double y = a1[s];
+#pragma unroll
+    for (int l = 0; l < PTS_MAX; ++l) {
+      if (l < pc.cnt) {
+        double x = 0.0;
+        for (int t = 0; t < pc.nt; ++t) x += pc.c[l][t] * tv[t];
+        num[l] += x * y;
+        den[l] += x * x;
+      }
+    }
+    n11 += y * y;
+  }
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) {
+    if (l < pc.cnt) {
+      const double qi = num[l] / den[l];
+      if (!(den[l] > 0.0)) atomicMin(bad + l, i);
+      q[(int64_t)l * n + i] = qi;
+      const double r2 = n11 - 2.0 * qi * num[l] + qi * qi * den[l];
+      rho[(int64_t)l * n + i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+    }
+  }
+}
+
+int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
+                           int* bad, hipStream_t st) {
+  pmor_problem* pb = h->pb;
+  const int n = pb->n;
+  if (n == 0 || cnt <= 0) return PMOR_OK;
+  if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one update launch");
+  const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
+  hipLaunchKernelGGL(k_update_diag_pts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
+                     pb->cscslot, pb->nnz, pb->tval, pc, h->aval1, q, rho, bad);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+// per point l < cnt: out[l * ostride] = sum of squares of x[l * n ...], with the
+// partition and the summation tree of sumsq (partials at out + l * ostride + 1)
+__global__ void k_sumsq_partials_pts(const double* x, int64_t n, double* out, int64_t ostride) {
+  __shared__ double s[4];
+  const double* xl = x + (int64_t)blockIdx.y * n;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += xl[i] * xl[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.y * ostride + 1 + blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(256) void k_sum_in_order_pts(double* out, int64_t ostride, int np) {
+  double* o = out + (int64_t)blockIdx.x * ostride;
+  __shared__ double s[256];
+  s[threadIdx.x] = (int)threadIdx.x < np ? o[1 + threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int k = 128; k >= 1; k >>= 1) {
+    if ((int)threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) o[0] = s[0];
+}
+
+int sumsq_pts(const double* x, int64_t n, int cnt, double* out, int64_t ostride, hipStream_t st) {
+  if (cnt <= 0) return PMOR_OK;
+  if (ostride < 257) return fail(PMOR_EINVAL, "sum-of-squares stride too small");
+  const int np = 256;
+  hipLaunchKernelGGL(k_sumsq_partials_pts, dim3(np, cnt), dim3(256), 0, st, x, n, out, ostride);
+  hipLaunchKernelGGL(k_sum_in_order_pts, dim3(cnt), dim3(256), 0, st, out, ostride, np);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Frobenius norms of Table 2: mode 0: ||a - b||^2, mode 1: ||I - A||^2 (a = A values)
 // ---------------------------------------------------------------------------
 __global__ void k_fro_partials(int n, const int32_t* rowptr, const int32_t* col, const double* a, const double* b,
