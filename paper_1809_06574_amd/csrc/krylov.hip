@@ -1156,13 +1156,14 @@ struct SpArgs {
   double alpha, beta;
   double* Vout;
   int vec;              // X rows may be read as double2
+  int linear;           // take workgroups in launch order (else the per-XCD remap)
 };
 
 constexpr int SP_ROWS = 64;  // rows per SpMM workgroup (64 LPR threads)
 
 template <int KP, int LPR, bool CONV>
 __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
-  const int lg = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int lg = a.linear ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, gridDim.x);
   const int s = a.stab[lg];
   if (s < 0) return;
   if (a.check_done && a.st[s].done) return;
@@ -1796,8 +1797,14 @@ static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, cons
   else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
 }
 
+// SpMM launches of at least this many workgroups take them in launch order
+constexpr unsigned SPMM_LINEAR_MIN = 16384;
+
 template <int KP, bool CONV>
-static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int lpr, hipStream_t s, const SpArgs& a) {
+static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int lpr, hipStream_t s,
+                            const SpArgs& a0) {
+  SpArgs a = a0;
+  a.linear = grid >= SPMM_LINEAR_MIN ? 1 : 0;
   switch (lpr) {
     case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(64 * 1), 0, s, a); break;
     case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(64 * 4), 0, s, a); break;
