@@ -1218,25 +1218,57 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
       // lanes of a row take k = sub, sub + LPR, ...  The pattern (columns) and
       // a factored P_1 are shared by the points of a sequence and stay cached;
       // a point's own values stream (nontemporal)
+      // Entries go in batches of EB: all column and value loads, then all X
+      // rows, then the products in entry order (fewer dependent memory waits)
       const int64_t base = sp[local >> 6] + (local & 63);
       const int w = sw[local >> 6];
       const bool own = !(a.which == 1 && (pk == 2 || pk == 3));
-      for (int k = sub; k < w; k += LPR) {
-        const int64_t q = base + (int64_t)k * 64;
-        const int c = sc[q];
-        const double v = own ? __builtin_nontemporal_load(sv + q) : sv[q];
-        if constexpr (KP % 2 == 0) {
-          const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c * KP);
+      constexpr int EB = KP <= 4 ? 8 : (KP == 8 ? 4 : 2);
+      for (int k0 = sub; k0 < w; k0 += EB * LPR) {
+        int c[EB];
+        double v[EB];
 #pragma unroll
-          for (int t = 0; t < KP / 2; ++t) {
-            const double2 x = xr[t];
-            acc[2 * t] = fma(v, x.x, acc[2 * t]);
-            acc[2 * t + 1] = fma(v, x.y, acc[2 * t + 1]);
+        for (int t = 0; t < EB; ++t) {
+          const int k = k0 + t * LPR;
+          const int64_t q = base + (int64_t)k * 64;
+          c[t] = local;
+          v[t] = 0.0;
+          if (k < w) {
+            c[t] = sc[q];
+            v[t] = own ? __builtin_nontemporal_load(sv + q) : sv[q];
+          }
+        }
+        if constexpr (KP % 2 == 0) {
+          double2 xv[EB][KP / 2];
+#pragma unroll
+          for (int t = 0; t < EB; ++t) {
+            const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c[t] * KP);
+#pragma unroll
+            for (int u = 0; u < KP / 2; ++u) xv[t][u] = xr[u];
+          }
+#pragma unroll
+          for (int t = 0; t < EB; ++t) {
+            if (k0 + t * LPR < w) {
+#pragma unroll
+              for (int u = 0; u < KP / 2; ++u) {
+                acc[2 * u] = fma(v[t], xv[t][u].x, acc[2 * u]);
+                acc[2 * u + 1] = fma(v[t], xv[t][u].y, acc[2 * u + 1]);
+              }
+            }
           }
         } else {
-          const double* xr = X + (int64_t)c * KP;
+          double xv[EB][KP];
 #pragma unroll
-          for (int t = 0; t < KP; ++t) acc[t] = fma(v, xr[t], acc[t]);
+          for (int t = 0; t < EB; ++t)
+#pragma unroll
+            for (int u = 0; u < KP; ++u) xv[t][u] = X[(int64_t)c[t] * KP + u];
+#pragma unroll
+          for (int t = 0; t < EB; ++t) {
+            if (k0 + t * LPR < w) {
+#pragma unroll
+              for (int u = 0; u < KP; ++u) acc[u] = fma(v[t], xv[t][u], acc[u]);
+            }
+          }
         }
       }
     } else {
