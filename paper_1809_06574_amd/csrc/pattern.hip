@@ -76,8 +76,7 @@ int scan_exclusive(int64_t* buf, int64_t n, hipStream_t st) {
   }
   hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, st, buf, n, last, buf + n - 1);
   PMOR_HIP(hipGetLastError());
-  PMOR_HIP(hipStreamSynchronize(st));
-  dfree(sums, st);
+  dfree(sums, st);  // stream-ordered: reused only after the kernels above
   dfree(last, st);
   return PMOR_OK;
 }
@@ -125,43 +124,51 @@ struct TermPtrs {
 template <bool FILL>
 __global__ void k_union(int n, TermPtrs t, int64_t* counts, const int32_t* rowptr_out, int32_t* col_out,
                         int32_t* maps, double* tval, int64_t nnz_out, int* maxlen) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int cur[PMOR_NROLES], end[PMOR_NROLES];
-#pragma unroll
-  for (int r = 0; r < PMOR_NROLES; ++r) {
-    if (t.present[r]) { cur[r] = t.rowptr[r][i]; end[r] = t.rowptr[r][i + 1]; }
-    else { cur[r] = 0; end[r] = 0; }
-  }
-  bool diag_done = false;
-  int64_t pos = FILL ? rowptr_out[i] : 0;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
-  while (true) {
-    int cmin = 0x7fffffff;
+  if (i < n) {
+    // cursors and the column at each cursor (INT_MAX once a list is done)
+    int cur[PMOR_NROLES], end[PMOR_NROLES], head[PMOR_NROLES];
 #pragma unroll
-    for (int r = 0; r < PMOR_NROLES; ++r)
-      if (cur[r] < end[r]) cmin = min(cmin, t.col[r][cur[r]]);
-    if (!diag_done) cmin = min(cmin, i);
-    if (cmin == 0x7fffffff) break;
-    if (cmin == i) diag_done = true;
-    if (FILL) {
-      col_out[pos] = cmin;
-#pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r) {
-        int hit = (cur[r] < end[r] && t.col[r][cur[r]] == cmin) ? cur[r] : -1;
-        maps[(int64_t)r * nnz_out + pos] = hit;
-        if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + pos] = hit >= 0 ? t.val[r][hit] : 0.0;
+    for (int r = 0; r < PMOR_NROLES; ++r) {
+      cur[r] = 0;
+      end[r] = 0;
+      if (t.present[r]) {
+        cur[r] = t.rowptr[r][i];
+        end[r] = t.rowptr[r][i + 1];
       }
     }
 #pragma unroll
-    for (int r = 0; r < PMOR_NROLES; ++r)
-      if (cur[r] < end[r] && t.col[r][cur[r]] == cmin) ++cur[r];
-    ++pos;
-    ++cnt;
+    for (int r = 0; r < PMOR_NROLES; ++r) head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
+    bool diag_done = false;
+    const int64_t pos0 = FILL ? rowptr_out[i] : 0;
+    while (true) {
+      int cmin = diag_done ? 0x7fffffff : i;
+#pragma unroll
+      for (int r = 0; r < PMOR_NROLES; ++r) cmin = min(cmin, head[r]);
+      if (cmin == 0x7fffffff) break;
+      if (cmin == i) diag_done = true;
+      const int64_t pos = pos0 + cnt;
+      if (FILL) col_out[pos] = cmin;
+#pragma unroll
+      for (int r = 0; r < PMOR_NROLES; ++r) {
+        const bool hit = head[r] == cmin;
+        if (FILL) {
+          maps[(int64_t)r * nnz_out + pos] = hit ? cur[r] : -1;
+          if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + pos] = hit ? t.val[r][cur[r]] : 0.0;
+        }
+        if (hit) {
+          ++cur[r];
+          head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
+        }
+      }
+      ++cnt;
+    }
+    if (!FILL) counts[i] = cnt;
   }
   if (!FILL) {
-    counts[i] = cnt;
-    atomicMax(maxlen, cnt);
+    for (int o = 32; o >= 1; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxlen, cnt);
   }
 }
 
@@ -535,14 +542,19 @@ __global__ void k_shadow_merge(int n, const int32_t* Jcolptr, const int32_t* Jro
   }
 }
 
+// jmax: an upper bound of |J_j| known on the host, or -1
 template <bool FILL>
 static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
                          const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow, int* maxJ,
-                         int* maxI, hipStream_t st) {
+                         int* maxI, int jmax, hipStream_t st) {
   if (n <= 0) return PMOR_OK;
   const unsigned g1 = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_shadow_small<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
                      Icolptr, Irow, maxJ, maxI);
+  if (jmax >= 0 && jmax <= SH_SMALL) {
+    PMOR_HIP(hipGetLastError());
+    return PMOR_OK;
+  }
   const unsigned gs = (unsigned)std::min((n + 63) / 64, 8192);
   hipLaunchKernelGGL(k_shadow_sort<FILL>, dim3(gs), dim3(64), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
                      Icolptr, Irow, maxJ, maxI);
@@ -577,6 +589,17 @@ __global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* Ico
   __syncthreads();
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) atomicAdd(&h[bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j]))], 1);
+  __syncthreads();
+  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
+}
+
+// the same from the shadow sizes before their scan (counts[j] = |I_j|)
+__global__ void k_bucket_count_cnt(int n, const int32_t* Jcolptr, const int64_t* counts, int* bcount) {
+  __shared__ int h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  __syncthreads();
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) atomicAdd(&h[bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)counts[j])], 1);
   __syncthreads();
   if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
 }
@@ -660,37 +683,36 @@ int build_spai_sets(pmor_spai* h) {
     PMOR_TRY(build_sell(n, h->Prowptr, h->Pcol, nnzP, 1.25, &h->psell, st));
     h->own_psell = true;
   }
-  // shadows
+  // shadows: sizes, the bucket histogram and the sizes' scan, read back in one
+  // synchronisation; then the rows
+  const int jmax = h->opts.pattern == PMOR_PAT_A ? pb->max_col_len : -1;
   int64_t* cnt = nullptr;
   PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
   PMOR_TRY(launch_shadow<false>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, cnt, nullptr, nullptr, dflag + 1,
-                                dflag + 2, st));
-  int hm[2] = {0, 0};
-  PMOR_HIP(hipMemcpyAsync(hm, dflag + 1, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-  PMOR_HIP(hipStreamSynchronize(st));
-  h->maxJ = hm[0];
-  h->maxI = hm[1];
-  if (h->maxJ > 64 || h->maxI > 512) {
-    dfree(cnt, st); dfree(dflag, st);
-    return fail(PMOR_EINVAL, "SPAI pattern too large: |J_j| <= 64 and |I_j| <= 512 are supported (got " +
-                                 std::to_string(h->maxJ) + ", " + std::to_string(h->maxI) + ")");
-  }
-  PMOR_TRY(scan_exclusive(cnt, n, st));
-  PMOR_HIP(hipMemcpyAsync(&h->nI, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  PMOR_HIP(hipStreamSynchronize(st));
-  h->Icolptr = cnt;
-  PMOR_HIP(dmalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1), st));
-  PMOR_TRY(launch_shadow<true>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, nullptr, h->Icolptr, h->Irow, nullptr,
-                               nullptr, st));
-  // buckets
+                                dflag + 2, jmax, st));
   int* bc = nullptr;
   PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 16, st));
   PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 16, st));
-  hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, bc);
+  hipLaunchKernelGGL(k_bucket_count_cnt, dim3(g), dim3(256), 0, st, n, h->Jcolptr, cnt, bc);
   PMOR_HIP(hipGetLastError());
+  PMOR_TRY(scan_exclusive(cnt, n, st));
+  int hm[2] = {0, 0};
   int hb[8];
+  PMOR_HIP(hipMemcpyAsync(hm, dflag + 1, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipMemcpyAsync(hb, bc, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipMemcpyAsync(&h->nI, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
+  h->maxJ = hm[0];
+  h->maxI = hm[1];
+  h->Icolptr = cnt;
+  if (h->maxJ > 64 || h->maxI > 512) {
+    dfree(bc, st); dfree(dflag, st);
+    return fail(PMOR_EINVAL, "SPAI pattern too large: |J_j| <= 64 and |I_j| <= 512 are supported (got " +
+                                 std::to_string(h->maxJ) + ", " + std::to_string(h->maxI) + ")");
+  }
+  PMOR_HIP(dmalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1), st));
+  PMOR_TRY(launch_shadow<true>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, nullptr, h->Icolptr, h->Irow, nullptr,
+                               nullptr, jmax, st));
   int off = 0, nonempty = 0;
   for (int b = 0; b < 8; ++b) {
     h->bucket_count[b] = hb[b];
@@ -717,8 +739,8 @@ int build_spai_sets(pmor_spai* h) {
     hipLaunchKernelGGL(k_bucket_fill, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, hb_off, bc,
                        h->bucket_cols);
     PMOR_HIP(hipGetLastError());
+    PMOR_HIP(hipStreamSynchronize(st));  // hb (host stack) was the source of a copy
   }
-  PMOR_HIP(hipStreamSynchronize(st));
   dfree(bc, st);
   dfree(dflag, st);
   (void)nonempty;
