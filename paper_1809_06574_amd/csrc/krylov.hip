@@ -87,6 +87,7 @@ struct KArgs {
   DevState* st;
   int* hinfo;          // host-mapped {j, done, breakdown, nan} per segment
   int swz;             // row kernels: remap the workgroup index per XCD (few workgroups)
+  const double* Hsrc1; // kp = 4 pass 3: pass 2's coefficients (same layout and stride as Hsrc)
 };
 
 // The segment of a row kernel's workgroup; false for padding workgroups and
@@ -261,6 +262,9 @@ __device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH,
 constexpr int UPD_PLAIN = 0;  // W <- W - hsign V Hsrc                       (end-of-cycle V Y)
 constexpr int UPD_P2 = 1;     // ... then V^T W and Gram(W)                  (pass 2)
 constexpr int UPD_P3 = 2;     // prologue; W <- (W - V H2) R1^{-1}; Gram(W)  (pass 3)
+// (kp = 4: pass 2 keeps W' = W - V H1 in registers only, and pass 3 forms it
+// again from W with the same operations in the same order, so W' is bit for
+// bit the vector pass 2 saw; a block write per step is saved)
 
 // ---------------------------------------------------------------------------
 // kp = 4, rows split over the wavefronts: each wavefront streams its own 16-row
@@ -354,19 +358,25 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
   __shared__ double sred[GRAM ? NW : 1][ROW];
   // B operand of block i: B[k][j] = -hsign H[4i + k][j], k = lane >> 4, j = lane & 3
   __shared__ double sH[RS_B * 16];
+  __shared__ double sH1[P3 ? RS_B * 16 : 1];  // pass 3: pass 2's B operands (-H1)
   __shared__ double sRinv[P3 ? 16 : 1];
   const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
   for (int t = threadIdx.x; t < nbl * 16; t += blockDim.x) sH[t] = -a.hsign * Hs[t];
+  if constexpr (P3) {
+    const double* H1 = a.Hsrc1 + r.s * a.hsrc_stride;
+    for (int t = threadIdx.x; t < nbl * 16; t += blockDim.x) sH1[t] = -1.0 * H1[t];
+  }
   __syncthreads();
   if constexpr (P3) p3_prologue<4>(a, r.s, r.g == 0, sH, nbl, sRinv);
   const double* hb = sH + (lane >> 4) * 4 + (lane & 3);
+  const double* hb1 = sH1 + (P3 ? (lane >> 4) * 4 + (lane & 3) : 0);
   double rb = 0.0;
   if constexpr (P3) rb = sRinv[(lane >> 4) * 4 + (lane & 3)];
   double acc[DOT ? NB : 1];
 #pragma unroll
   for (int i = 0; i < (DOT ? NB : 1); ++i) acc[i] = 0.0;
   double accg = 0.0;
-  const bool write = P3 || nbl > 0 || a.zero_init;
+  const bool write = P3 || (MODE == UPD_PLAIN && (nbl > 0 || a.zero_init));
   for (int ch = r.g * NW + w; ch < nch; ch += r.G * NW) {
     const int64_t e = ((int64_t)ch << 6) + lane;
     const bool valid = e < (int64_t)r.n * 4;
@@ -375,10 +385,28 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? ldnt(V + (int64_t)i * a.vstride + e) : 0.0;
     double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
+    if constexpr (P3) {
+      // W' = W - V H1 exactly as pass 2 formed it; the tiles are kept transposed
 #pragma unroll
-    for (int i = 0; i < NB; i += 2) {
-      if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
-      if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
+      for (int i = 0; i < NB; ++i) v[i] = tile_transpose(v[i], lane);
+#pragma unroll
+      for (int i = 0; i < NB; i += 2) {
+        if (i < nbl) u0 = mfma4(v[i], hb1[16 * i], u0);
+        if (i + 1 < nbl) u1 = mfma4(v[i + 1], hb1[16 * (i + 1)], u1);
+      }
+      u0 = u0 + u1;
+      u1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < NB; i += 2) {
+        if (i < nbl) u0 = mfma4(v[i], hb[16 * i], u0);
+        if (i + 1 < nbl) u1 = mfma4(v[i + 1], hb[16 * (i + 1)], u1);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; i += 2) {
+        if (i < nbl) u0 = mfma4(tile_transpose(v[i], lane), hb[16 * i], u0);
+        if (i + 1 < nbl) u1 = mfma4(tile_transpose(v[i + 1], lane), hb[16 * (i + 1)], u1);
+      }
     }
     double wnew = u0 + u1;
     if (P3) wnew = mfma4(tile_transpose(wnew, lane), rb, 0.0);
@@ -2223,7 +2251,7 @@ class RunnerT final : public Runner {
     // initial block QR of R_0: V_0 S = R_0 (S -> G)
     hipLaunchKernelGGL(k_init_cycle, dim3(nact), dim3(256), 0, s, a, KP);
     a.mode = 1; a.nbl = 0; a.zero_init = 0; a.ignore_done = 0; a.W = E.W.p;
-    a.Hsrc = E.Hc.p + E.hc2off; a.hsrc_stride = E.hcs; a.hsign = 1.0;
+    a.Hsrc = E.Hc.p + E.hc2off; a.hsrc_stride = E.hcs; a.hsign = 1.0; a.Hsrc1 = E.Hc.p;
     launch_upd<KP, UPD_P2>(ctx, -1, gR, s, a, 0);
     hipLaunchKernelGGL(k_reduce_seg, dim3((KP * KP + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
                        E.lstride, KP * KP, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p,
@@ -2267,11 +2295,13 @@ class RunnerT final : public Runner {
       a.Hsrc = E.Hc.p; a.hsrc_stride = E.hcs; a.hsign = 1.0;
       pr = prof_start(ctx, PMOR_PROF_CGS_UPD_DOT);
       launch_upd<KP, UPD_P2>(ctx, pr, gR, s, a, jj + 1);
-      prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 3); });
+      // kp = 4: W' stays in registers (pass 3 forms it again)
+      prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + (F::RS ? 2 : 3)); });
       hipLaunchKernelGGL(k_reduce_seg, dim3((L2 + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
                          E.lstride, L2, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p, E.hcs,
                          E.hc2off);
       a.Hsrc = E.Hc.p + E.hc2off;
+      a.Hsrc1 = E.Hc.p;
       pr = prof_start(ctx, PMOR_PROF_CGS_UPD_GRAM);
       launch_upd<KP, UPD_P3>(ctx, pr, gR, s, a, jj + 1);
       prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 3); });
