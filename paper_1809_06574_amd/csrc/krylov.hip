@@ -1345,7 +1345,32 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
     for (int t = 0; t < KP; ++t) acc[t] *= qs;
   }
   const int64_t ro = (int64_t)local * KP;
-  if constexpr (CONV) {
+  if constexpr (CONV && LPR == 1 && KP % 2 == 0) {
+    // one lane owns the row: both outputs leave as 16-byte stores
+    double xr[KP], vo[KP], yo[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) xr[u] = X[ro + u];
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      double y = 0.0, v = 0.0;
+#pragma unroll
+      for (int u = 0; u <= t; ++u) {
+        y = fma(acc[u], sM[u * KP + t], y);
+        v = fma(xr[u], sM[u * KP + t], v);
+      }
+      vo[t] = v;
+      double o = alpha * y;
+      if (beta != 0.0) o = fma(beta, Bsrc[base + ro + t], o);
+      yo[t] = o;
+    }
+    double2* vd = reinterpret_cast<double2*>(a.Vout + base + ro);
+    double2* yd = reinterpret_cast<double2*>(Y + ro);
+#pragma unroll
+    for (int t = 0; t < KP / 2; ++t) {
+      vd[t] = make_double2(vo[2 * t], vo[2 * t + 1]);
+      yd[t] = make_double2(yo[2 * t], yo[2 * t + 1]);
+    }
+  } else if constexpr (CONV) {
     double xr[KP];
 #pragma unroll
     for (int u = 0; u < KP; ++u) xr[u] = X[ro + u];
@@ -1364,6 +1389,17 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
         Y[ro + t] = o;
       }
     }
+  } else if constexpr (LPR == 1 && KP % 2 == 0) {
+    double yo[KP];
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      double o = alpha * acc[t];
+      if (beta != 0.0) o = fma(beta, Bsrc[base + ro + t], o);
+      yo[t] = o;
+    }
+    double2* yd = reinterpret_cast<double2*>(Y + ro);
+#pragma unroll
+    for (int t = 0; t < KP / 2; ++t) yd[t] = make_double2(yo[2 * t], yo[2 * t + 1]);
   } else {
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
