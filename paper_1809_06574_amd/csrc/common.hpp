@@ -54,6 +54,7 @@ struct DevState {
   double est[KMAX]; // least-squares residual estimates / bnorm
   double R1[KMAX * KMAX];     // first Cholesky factor of the step (row-major, upper)
   double R2inv[KMAX * KMAX];  // inverse of the second factor: V_{j+1} = W1 R2inv
+  double R1inv[KMAX * KMAX];  // inverse of the first factor (pass 3: W1 = W'' R1inv)
 };
 
 // Sliced ELL view of a CSR pattern for the engine's SpMM: 64-row slices,

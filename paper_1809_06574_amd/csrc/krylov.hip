@@ -215,12 +215,13 @@ __device__ bool chol_upper(const double* Gm, int kp, int kact, double thr2, doub
   return ok;
 }
 
-// Pass-3 prologue, run by every workgroup of a segment: the Gram matrix of
+// Pass-3 set-up of a segment (k_p3_setup for kp != 4; every pass-3 workgroup
+// for kp = 4, where it is cheap next to the sweep): the Gram matrix of
 // W'' = W' - V H2 as Gram(W') - H2^T H2 (sH holds +-H2 in LDS, [basis][rhs]),
 // its Cholesky factor R1 and R1^{-1}, and the scale max_c ||W_c|| of the
 // deficiency test (block step: norms of pass 1; cycle start: of W itself).
-// The segment's first workgroup stores R1, the scale, the verdict and, in a
-// block step, the Hessenberg column block H1 + H2.
+// Stores R1, the scale, the verdict and, in a block step, the Hessenberg
+// column block H1 + H2 (when first).
 template <int KP>
 __device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH, int nbl, double* sRinv) {
   DevState* st = a.st + s;
@@ -255,6 +256,28 @@ __device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH,
       Hb[b + (int64_t)(j * KP + c) * a.ldh] = Hc1[t] + Hc2[t];
     }
   }
+  __syncthreads();
+}
+
+// pass-3 set-up of every active segment, once, before the pass-3 sweep of the
+// kp = 1, 2, 8, 16 kernels: their workgroups then only load R1^{-1} (dynamic
+// LDS: nbl_max KP^2 doubles)
+template <int KP>
+__global__ __launch_bounds__(256) void k_p3_setup(KArgs a) {
+  const int s = a.slist[blockIdx.x];
+  if (!a.ignore_done && a.st[s].done) return;
+  const int nbl = nblocks_of(a, s);
+  extern __shared__ double sH[];
+  __shared__ double sRinv[KP * KP];
+  const double* Hs = a.Hsrc + s * a.hsrc_stride;
+  for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = Hs[t];
+  __syncthreads();
+  p3_prologue<KP>(a, s, true, sH, nbl, sRinv);
+  for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) a.st[s].R1inv[t] = sRinv[t];
+}
+
+__device__ __forceinline__ void load_r1inv(const KArgs& a, int s, int kp2, double* sRinv) {
+  for (int t = threadIdx.x; t < kp2; t += blockDim.x) sRinv[t] = a.st[s].R1inv[t];
   __syncthreads();
 }
 
@@ -540,7 +563,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_mfma(KArgs a) {
   const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
   for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * Hs[t];
   __syncthreads();
-  if constexpr (P3) p3_prologue<KP>(a, r.s, r.g == 0, sH, nbl, sRinv);
+  if constexpr (P3) load_r1inv(a, r.s, KP * KP, sRinv);
   double acc[DOT ? BPW : 1][NT][NT];
   double accg[GRAM ? NT : 1][NT];
 #pragma unroll
@@ -771,7 +794,7 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
   const double* Hs = a.Hsrc + r.s * a.hsrc_stride;
   for (int t = threadIdx.x; t < nbl * KP * KP; t += blockDim.x) sH[t] = a.hsign * Hs[t];
   __syncthreads();
-  if constexpr (P3) p3_prologue<KP>(a, r.s, r.g == 0, sH, nbl, sRinv);
+  if constexpr (P3) load_r1inv(a, r.s, KP * KP, sRinv);
   double acc[DOT ? BPW : 1][KP][KP];
   double accg[GRAM ? KP : 1][KP];
 #pragma unroll
@@ -2292,6 +2315,7 @@ class RunnerT final : public Runner {
     hipLaunchKernelGGL(k_reduce_seg, dim3((KP * KP + 7) / 8, nact), dim3(256), 0, s, (const double*)E.part.p,
                        E.lstride, KP * KP, (const SegDesc*)E.seg_d, a.slist, 0, (const DevState*)E.st, 1, E.Hc.p,
                        E.hcs, E.hc2off);
+    if (!F::RS) hipLaunchKernelGGL(k_p3_setup<KP>, dim3(nact), dim3(256), 8, s, a);
     launch_upd<KP, UPD_P3>(ctx, -1, gR, s, a, 0);
     hipLaunchKernelGGL((k_hess<KP>), dim3(nact), dim3(256), 0, s, a);
     PMOR_HIP(hipGetLastError());
@@ -2338,6 +2362,8 @@ class RunnerT final : public Runner {
                          E.hc2off);
       a.Hsrc = E.Hc.p + E.hc2off;
       a.Hsrc1 = E.Hc.p;
+      if (!F::RS)  // kp = 4: every pass-3 workgroup does the set-up itself (measured faster)
+        hipLaunchKernelGGL(k_p3_setup<KP>, dim3(nact), dim3(256), sizeof(double) * (jj + 1) * KP * KP, s, a);
       pr = prof_start(ctx, PMOR_PROF_CGS_UPD_GRAM);
       launch_upd<KP, UPD_P3>(ctx, pr, gR, s, a, jj + 1);
       prof_seg(pr, jj, [&](int i) { return blkb(i) * (jj + 3); });
