@@ -1836,7 +1836,7 @@ struct Fam {
   static constexpr int NW = (KP == 4 || KP == 16) ? 8 : 4;
   static constexpr int BPW = 32 / NW;     // V blocks per wavefront: m + 1 <= 32
   static constexpr int ROWS = RS ? 16 * NW : (ROW ? 64 : 16);  // rows per workgroup iteration
-  static constexpr int GMAX = RS ? 128 : 512;
+  static constexpr int GMAX = ROW ? 512 : 128;  // kp >= 4: 128 (long streams per wavefront, few partial rows)
 };
 
 static int pad_kp(int k) {
