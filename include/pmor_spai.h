@@ -240,7 +240,10 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
  * as in pmor_batch_solve (in groups sized to the free device memory).
  * X: npts consecutive n x k row-major blocks (ldx per block, block stride
  * n*ldx).  stats: npts entries (may be NULL); t_solve_ms is the wall time from
- * the call's start to the point's final X.  A point whose update or rebuild
+ * the call's start to the point's final X.  With the U-diag update the A(l)
+ * values and the factors q_l are formed for up to 8 points per launch, and
+ * P_l = diag(q_l) P_1 is applied in that factored form; t_assemble_ms and
+ * t_precond_ms then hold equal shares of those launches.  A point whose update or rebuild
  * meets a singular column is not solved (PMOR_ESINGULAR, X untouched); the
  * others are.  Returns the first failing point's code, else PMOR_OK. */
 int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k,

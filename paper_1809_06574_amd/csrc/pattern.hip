@@ -582,19 +582,9 @@ __host__ __device__ inline int bucket_of(int nj, int ni) {
   return 7;  // unsupported
 }
 
-// per-workgroup histogram in LDS, one global atomic per bucket and workgroup
-__global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* Icolptr, int* bcount) {
-  __shared__ int h[8];
-  if (threadIdx.x < 8) h[threadIdx.x] = 0;
-  __syncthreads();
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) atomicAdd(&h[bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j]))], 1);
-  __syncthreads();
-  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
-}
-
-// the same from the shadow sizes before their scan (counts[j] = |I_j|)
-__global__ void k_bucket_count_cnt(int n, const int32_t* Jcolptr, const int64_t* counts, int* bcount) {
+// columns per (|J_j|, |I_j|) bucket from the shadow sizes before their scan
+// (counts[j] = |I_j|): a histogram in LDS, one global atomic per bucket and workgroup
+__global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* counts, int* bcount) {
   __shared__ int h[8];
   if (threadIdx.x < 8) h[threadIdx.x] = 0;
   __syncthreads();
@@ -693,7 +683,7 @@ int build_spai_sets(pmor_spai* h) {
   int* bc = nullptr;
   PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 16, st));
   PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 16, st));
-  hipLaunchKernelGGL(k_bucket_count_cnt, dim3(g), dim3(256), 0, st, n, h->Jcolptr, cnt, bc);
+  hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, n, h->Jcolptr, cnt, bc);
   PMOR_HIP(hipGetLastError());
   PMOR_TRY(scan_exclusive(cnt, n, st));
   int hm[2] = {0, 0};
