@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
     ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
-    ap.add_argument("--c2-systems", type=int, default=32, help="systems of the batch run (0: none)")
+    ap.add_argument("--c2-systems", type=int, default=512, help="systems of the batch run (0: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
