@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
     ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
     ap.add_argument("--c2-systems", type=int, default=512, help="systems of the batch run (0: none)")
+    ap.add_argument("--no-precisions", action="store_true", help="skip the least-squares precision runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
@@ -247,6 +248,9 @@ def main():
         out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
+
+    if not args.no_precisions:
+        out["precisions"] = c3_bench(factory, job, B)
 
     if args.c2_systems > 0:
         out["batch_systems"] = c2_bench(ctx, args.c2_systems)
@@ -358,6 +362,37 @@ def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, se
 def _c2_system(i):
     from synth.gen import config2_system
     return config2_system(i)
+
+
+def c3_bench(factory, job, B):
+    """The C1 job with the SPAI least squares in FP64, FP32 and FP16s (update
+    policy, points solved together): throughput, the P_1 build time and its
+    residual ||I - A P_1||_F, block steps per point, and how far each X lies
+    from the FP64 run's."""
+    import torch
+    npts = len(job.p_list)
+    out, ref = {}, None
+    for prec in ("f64", "f32", "f16s"):
+        def one():
+            pb = factory()
+            X, st = pb.sequence_solve(B, [job.s] * npts, job.p_list, policy="update", precision=prec)
+            pb.close()
+            return X, st
+        one()  # untimed: this precision's kernels and buffers
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        X, st = one()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if ref is None:
+            ref = X.clone()
+        dx = max(float(torch.linalg.norm(X[l] - ref[l]) / torch.linalg.norm(ref[l])) for l in range(npts))
+        out[prec] = {"solves_per_s": npts / dt, "p1_build_ms": st[0]["t_precond_ms"],
+                     "fro_I_minus_AP1": st[0]["fro_resid"],
+                     "steps_per_point": sum(sum(s["cycle_steps"]) for s in st) / npts,
+                     "max_rel_dX_vs_f64": dx,
+                     "max_relres": max(max(s["relres"]) for s in st)}
+    return out
 
 
 def c2_bench(ctx, nsys):
