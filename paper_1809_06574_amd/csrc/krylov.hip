@@ -1861,6 +1861,32 @@ static int row_wgs(int n, int rows_per_iter, int gmax) {
 // that covers the sweep (fewer registers, more wavefronts in flight)
 static int rs_nb(int nbl_max) { return std::min(32, std::max(4, (nbl_max + 3) / 4 * 4)); }
 
+// V blocks per wavefront of the kp = 1, 2, 8, 16 kernels, which take block
+// i = w + NW bi: the fewest instantiated counts (1..4 for 8 wavefronts, 2, 4,
+// 6, 8 for 4) that cover the sweep's nbl_max <= NW BPW blocks.  A smaller count
+// holds fewer registers (more wavefronts in flight) and leaves every sum as it
+// is: each wavefront still takes its blocks in the same order.
+template <int NW, typename Fn>
+static void with_bpw(int nbl_max, Fn&& fn) {
+  const int need = (nbl_max + NW - 1) / NW;
+  if constexpr (NW == 8) {
+    switch (need) {
+      case 0: case 1: fn(std::integral_constant<int, 1>{}); break;
+      case 2: fn(std::integral_constant<int, 2>{}); break;
+      case 3: fn(std::integral_constant<int, 3>{}); break;
+      default: fn(std::integral_constant<int, 4>{}); break;
+    }
+  } else {
+    static_assert(NW == 4, "4 or 8 wavefronts");
+    switch (need) {
+      case 0: case 1: case 2: fn(std::integral_constant<int, 2>{}); break;
+      case 3: case 4: fn(std::integral_constant<int, 4>{}); break;
+      case 5: case 6: fn(std::integral_constant<int, 6>{}); break;
+      default: fn(std::integral_constant<int, 8>{}); break;
+    }
+  }
+}
+
 template <typename Fn>
 static void with_nb(int nb, Fn&& fn) {
   switch (nb) {
@@ -1883,8 +1909,12 @@ static void launch_dot(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, cons
       plaunch(c, pidx, 3, k_dot4<F::NW, decltype(nb)::value>, dim3(grid), dim3(64 * F::NW), 0, s, a);
     });
   }
-  else if constexpr (F::ROW) plaunch(c, pidx, 3, k_dot_row<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
-  else plaunch(c, pidx, 3, k_dot_mfma<KP, F::NW, F::BPW>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+  else
+    with_bpw<F::NW>(nbl_max, [&](auto b) {
+      constexpr int B = decltype(b)::value;
+      if constexpr (F::ROW) plaunch(c, pidx, 3, k_dot_row<KP, F::NW, B>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+      else plaunch(c, pidx, 3, k_dot_mfma<KP, F::NW, B>, dim3(grid), dim3(64 * F::NW), 0, s, a);
+    });
 }
 
 template <int KP>
@@ -1895,12 +1925,21 @@ static size_t upd_shm(int nbl_max) {
   return sizeof(double) * ((size_t)nbl_max * KP * KP + (size_t)2 * F::NW * 64 * per);
 }
 
+// the update kernels that can need more than 64 KiB of dynamic LDS (kp != 4)
 template <int KP, int MODE>
-static const void* upd_fn() {
+static int allow_upd_lds(int m) {
   using F = Fam<KP>;
-  if constexpr (F::RS) return (const void*)k_upd4<F::NW, MODE, 32>;
-  else if constexpr (F::ROW) return (const void*)k_upd_row<KP, F::NW, F::BPW, MODE>;
-  else return (const void*)k_upd_mfma<KP, F::NW, F::BPW, MODE>;
+  int rc = PMOR_OK;
+  if constexpr (!F::RS)
+    for (int nb = 0; nb <= F::NW * F::BPW; nb += F::NW)
+      with_bpw<F::NW>(nb, [&](auto b) {
+        constexpr int B = decltype(b)::value;
+        const void* fn;
+        if constexpr (F::ROW) fn = (const void*)k_upd_row<KP, F::NW, B, MODE>;
+        else fn = (const void*)k_upd_mfma<KP, F::NW, B, MODE>;
+        if (rc == PMOR_OK) rc = allow_lds(fn, upd_shm<KP>(m));
+      });
+  return rc;
 }
 
 template <int KP, int MODE>
@@ -1911,9 +1950,12 @@ static void launch_upd(pmor_ctx* c, int pidx, unsigned grid, hipStream_t s, cons
     with_nb(rs_nb(nbl_max), [&](auto nb) {
       plaunch(c, pidx, 3, k_upd4<F::NW, MODE, decltype(nb)::value>, dim3(grid), dim3(64 * F::NW), 0, s, a);
     });
-  } else if constexpr (F::ROW)
-    plaunch(c, pidx, 3, k_upd_row<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
-  else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, F::BPW, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
+  } else
+    with_bpw<F::NW>(nbl_max, [&](auto b) {
+      constexpr int B = decltype(b)::value;
+      if constexpr (F::ROW) plaunch(c, pidx, 3, k_upd_row<KP, F::NW, B, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
+      else plaunch(c, pidx, 3, k_upd_mfma<KP, F::NW, B, MODE>, dim3(grid), dim3(64 * F::NW), shm, s, a);
+    });
 }
 
 // SpMM launches of at least this many workgroups take them in launch order
@@ -1973,9 +2015,9 @@ class RunnerT final : public Runner {
     ys_shm_ = sizeof(double) * ((size_t)m * KP * KP + (size_t)ys_pw_ * m * KP);
     PMOR_TRY(allow_lds((const void*)k_hess<KP>, hess_shm_));
     PMOR_TRY(allow_lds((const void*)k_ysolve<KP>, ys_shm_));
-    PMOR_TRY(allow_lds(upd_fn<KP, UPD_PLAIN>(), upd_shm<KP>(m)));
-    PMOR_TRY(allow_lds(upd_fn<KP, UPD_P2>(), upd_shm<KP>(m)));
-    PMOR_TRY(allow_lds(upd_fn<KP, UPD_P3>(), upd_shm<KP>(m)));
+    PMOR_TRY((allow_upd_lds<KP, UPD_PLAIN>(m)));
+    PMOR_TRY((allow_upd_lds<KP, UPD_P2>(m)));
+    PMOR_TRY((allow_upd_lds<KP, UPD_P3>(m)));
     t0_ = std::chrono::steady_clock::now();
     return PMOR_OK;
   }
