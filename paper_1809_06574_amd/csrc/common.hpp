@@ -66,7 +66,7 @@ struct SellView {
   int64_t cap = 0;           // stored entries (with padding)
   int32_t* ptr = nullptr;    // ns + 1 slice offsets
   int32_t* wid = nullptr;    // ns slice widths
-  int32_t* col = nullptr;    // cap columns
+  int32_t* col = nullptr;    // cap columns, -1 for padding (a padded slot gathers nothing)
   int32_t* map = nullptr;    // cap: CSR position of the entry, -1 for padding
 };
 
@@ -249,6 +249,11 @@ int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* ou
 int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms);
 int build_spai_sets(pmor_spai* h);
 // sliced ELL view of a CSR pattern when its padding is at most max_fill x nnz (else v->cap = 0)
+// stored slots (padding included) allowed per nonzero before the CSR arrays
+// serve instead: a padded slot costs its 12 bytes of column and value only
+constexpr double SELL_MAX_FILL = 2.0;
+// SELL_MAX_FILL, or PMOR_SELL_MAX_FILL when set (0: always the CSR arrays)
+double sell_max_fill();
 int build_sell(int n, const int32_t* rowptr, const int32_t* col, int64_t nnz, double max_fill, SellView* v,
                hipStream_t st);
 void free_sell(SellView* v, hipStream_t st);

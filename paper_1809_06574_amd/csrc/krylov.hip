@@ -1211,6 +1211,10 @@ struct SpArgs {
 };
 
 constexpr int SP_ROWS = 64;  // rows per SpMM workgroup (64 LPR threads)
+// SpMM variants of the batched engine: 1, 2, 4, 8 lanes per row taking the
+// row's entries in turn (k_spmm_seg), or the column split (k_spmm_cs)
+constexpr int SPMM_COLSPLIT = 16;
+static bool spmm_variant_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == SPMM_COLSPLIT; }
 
 template <int KP, int LPR, bool CONV>
 __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
@@ -1270,7 +1274,8 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
       // a factored P_1 are shared by the points of a sequence and stay cached;
       // a point's own values stream (nontemporal)
       // Entries go in batches of EB: all column and value loads, then all X
-      // rows, then the products in entry order (fewer dependent memory waits)
+      // rows, then the products in entry order (fewer dependent memory waits).
+      // Padded slots (column -1, value 0) gather nothing
       const int64_t base = sp[local >> 6] + (local & 63);
       const int w = sw[local >> 6];
       const bool own = !(a.which == 1 && (pk == 2 || pk == 3));
@@ -1282,7 +1287,7 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
         for (int t = 0; t < EB; ++t) {
           const int k = k0 + t * LPR;
           const int64_t q = base + (int64_t)k * 64;
-          c[t] = local;
+          c[t] = -1;  // past the slice width, or a padded slot: no gather
           v[t] = 0.0;
           if (k < w) {
             c[t] = sc[q];
@@ -1293,9 +1298,9 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
           double2 xv[EB][KP / 2];
 #pragma unroll
           for (int t = 0; t < EB; ++t) {
-            const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)c[t] * KP);
+            const double2* xr = reinterpret_cast<const double2*>(X + (int64_t)(c[t] < 0 ? 0 : c[t]) * KP);
 #pragma unroll
-            for (int u = 0; u < KP / 2; ++u) xv[t][u] = xr[u];
+            for (int u = 0; u < KP / 2; ++u) xv[t][u] = c[t] >= 0 ? xr[u] : make_double2(0.0, 0.0);
           }
 #pragma unroll
           for (int t = 0; t < EB; ++t) {
@@ -1312,7 +1317,7 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
 #pragma unroll
           for (int t = 0; t < EB; ++t)
 #pragma unroll
-            for (int u = 0; u < KP; ++u) xv[t][u] = X[(int64_t)c[t] * KP + u];
+            for (int u = 0; u < KP; ++u) xv[t][u] = c[t] >= 0 ? X[(int64_t)c[t] * KP + u] : 0.0;
 #pragma unroll
           for (int t = 0; t < EB; ++t) {
             if (k0 + t * LPR < w) {
@@ -1436,6 +1441,184 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Column-split SpMM over the segments of a batch: the operands and result of
+// k_spmm_seg, bit for bit its one-lane-per-row sums (every column adds the
+// row's entries in order).  L = KP / 2 lanes share a row and lane sub owns its
+// column pair (2 sub, 2 sub + 1), so the X row an entry gathers is one
+// contiguous 16 L-byte access of the group instead of KP / 2 accesses of one
+// lane; the group's column and value loads take L different entries (R rounds
+// per batch) and are passed round by shuffles.  kp = 1: one lane, one column.
+// ---------------------------------------------------------------------------
+template <int KP>
+struct CsShape {
+  static constexpr int L = KP >= 2 ? KP / 2 : 1;  // lanes per row
+  static constexpr int C = KP >= 2 ? 2 : 1;       // columns per lane
+  static constexpr int R = KP <= 2 ? 8 : (KP == 4 ? 4 : (KP == 8 ? 2 : 1));  // rounds per batch
+};
+
+template <int KP, bool CONV>
+__global__ __launch_bounds__(64 * CsShape<KP>::L) void k_spmm_cs(SpArgs a) {
+  constexpr int L = CsShape<KP>::L, C = CsShape<KP>::C, R = CsShape<KP>::R, EB = L * R;
+  const int lg = a.linear ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, gridDim.x);
+  const int s = a.stab[lg];
+  if (s < 0) return;
+  if (a.check_done && a.st[s].done) return;
+  const SegDesc& d = a.seg[s];
+  const int pk = d.pkind;
+  const int32_t *rp, *cl, *sp, *sw, *sc;
+  const double *vl, *sv;
+  bool ident = false;
+  double* Y = a.Y;
+  double alpha = a.alpha, beta = a.beta;
+  const double* Bsrc = a.Bsrc;
+  if (a.which == 0) {
+    rp = d.arow; cl = d.acol; vl = d.aval;
+    sp = d.a_sp; sw = d.a_sw; sc = d.a_sc; sv = d.a_sv;
+  } else if (a.which == 1) {
+    ident = (pk == 0);
+    rp = d.prow; cl = d.pcol; vl = d.pval;
+    sp = d.p_sp; sw = d.p_sw; sc = d.p_sc; sv = d.p_sv;
+    if (pk == 2) { Y = a.Yalt; alpha = 1.0; beta = 0.0; Bsrc = nullptr; }
+  } else {
+    if (pk != 2) return;
+    rp = d.prow; cl = d.pcol; vl = d.qval;
+    sp = d.p_sp; sw = d.p_sw; sc = d.p_sc; sv = d.q_sv;
+  }
+  __shared__ double sM[CONV ? KP * KP : 1];
+  if constexpr (CONV) {
+    for (int t = threadIdx.x; t < KP * KP; t += blockDim.x) sM[t] = a.st[s].R2inv[t];
+    __syncthreads();
+  }
+  const int64_t base = d.r0 * KP;
+  const double* X = a.X + base;
+  Y += base;
+  const int local = (lg - d.sp0) * SP_ROWS + (int)threadIdx.x / L;
+  const int sub = (int)threadIdx.x % L;
+  const int g0 = ((int)threadIdx.x & 63) - sub;  // first lane of the row's group
+  // every lane of a group shares `local`, so groups are wholly valid or not
+  if (local >= d.n) return;
+  const int64_t ro = (int64_t)local * KP + C * sub;  // this lane's first column
+  double acc[C];
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] = 0.0;
+  // one batch: entry j of the group's EB came from lane g0 + j % L, round j / L
+  auto batch = [&](const int (&cm)[R], const double (&vm)[R]) {
+    int c[EB];
+    double v[EB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        c[r * L + t] = L > 1 ? __shfl(cm[r], g0 + t, 64) : cm[r];
+        v[r * L + t] = L > 1 ? __shfl(vm[r], g0 + t, 64) : vm[r];
+      }
+    if constexpr (C == 2) {
+      const double2* X2 = reinterpret_cast<const double2*>(X);
+      double2 x[EB];
+#pragma unroll
+      for (int j = 0; j < EB; ++j) x[j] = c[j] >= 0 ? X2[(int64_t)c[j] * L + sub] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < EB; ++j) {
+        acc[0] = fma(v[j], x[j].x, acc[0]);
+        acc[1] = fma(v[j], x[j].y, acc[1]);
+      }
+    } else {
+      double x[EB];
+#pragma unroll
+      for (int j = 0; j < EB; ++j) x[j] = c[j] >= 0 ? X[c[j]] : 0.0;
+#pragma unroll
+      for (int j = 0; j < EB; ++j) acc[0] = fma(v[j], x[j], acc[0]);
+    }
+  };
+  if (ident) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) acc[q] = X[ro + q];
+  } else if (sp) {
+    // sliced ELL (64-row slices, padded slots hold column -1)
+    const int64_t sb = sp[local >> 6] + (local & 63);
+    const int w = sw[local >> 6];
+    const bool own = !(a.which == 1 && (pk == 2 || pk == 3));
+    for (int k0 = 0; k0 < w; k0 += EB) {
+      int cm[R];
+      double vm[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = k0 + r * L + sub;
+        const int64_t q = sb + (int64_t)k * 64;
+        cm[r] = -1;
+        vm[r] = 0.0;
+        if (k < w) {
+          cm[r] = sc[q];
+          vm[r] = own ? __builtin_nontemporal_load(sv + q) : sv[q];
+        }
+      }
+      batch(cm, vm);
+    }
+  } else {
+    const int e0 = rp[local], e1 = rp[local + 1];
+    for (int k0 = e0; k0 < e1; k0 += EB) {
+      int cm[R];
+      double vm[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = k0 + r * L + sub;
+        cm[r] = -1;
+        vm[r] = 0.0;
+        if (e < e1) {
+          cm[r] = cl[e];
+          vm[r] = vl[e];
+        }
+      }
+      batch(cm, vm);
+    }
+  }
+  if (a.which == 1 && pk == 3) {  // P = diag(q) P_1: scale the row of P_1 X
+    const double qs = d.prs[local];
+#pragma unroll
+    for (int q = 0; q < C; ++q) acc[q] *= qs;
+  }
+  double o[C];
+  if constexpr (CONV) {
+    // the row's KP values of Op W1 and of W1 from the group, then this lane's
+    // columns of (Op W1) M and W1 M (M upper triangular)
+    double xr[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) xr[q] = X[ro + q];
+    double fa[KP], fx[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+      fa[u] = L > 1 ? __shfl(acc[u % C], g0 + u / C, 64) : acc[u % C];
+      fx[u] = L > 1 ? __shfl(xr[u % C], g0 + u / C, 64) : xr[u % C];
+    }
+    double vo[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int t = C * sub + q;
+      double y = 0.0, v = 0.0;
+#pragma unroll
+      for (int u = 0; u < KP; ++u)
+        if (u <= t) {
+          y = fma(fa[u], sM[u * KP + t], y);
+          v = fma(fx[u], sM[u * KP + t], v);
+        }
+      vo[q] = v;
+      o[q] = alpha * y;
+      if (beta != 0.0) o[q] = fma(beta, Bsrc[base + ro + q], o[q]);
+    }
+    if constexpr (C == 2) *reinterpret_cast<double2*>(a.Vout + base + ro) = make_double2(vo[0], vo[1]);
+    else a.Vout[base + ro] = vo[0];
+  } else {
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      o[q] = alpha * acc[q];
+      if (beta != 0.0) o[q] = fma(beta, Bsrc[base + ro + q], o[q]);
+    }
+  }
+  if constexpr (C == 2) *reinterpret_cast<double2*>(Y + ro) = make_double2(o[0], o[1]);
+  else Y[ro] = o[0];
+}
+
+// ---------------------------------------------------------------------------
 // single-matrix CSR SpMM with caller leading dimensions (pmor_spmm):
 // Y = alpha A X + beta Bsrc, LPR lanes per row
 // ---------------------------------------------------------------------------
@@ -1477,21 +1660,23 @@ __global__ __launch_bounds__(256) void k_spmm(int n, const int32_t* __restrict__
 }
 
 // lanes per row of the CSR SpMM (1, 2, 4 or 8; 2 measured best for 7-point rows
-// at k = 1..8); PMOR_SPMM_LPR overrides the default
+// at k = 1..8); PMOR_SPMM_LPR overrides the default (16: the engine's column
+// split, and 2 lanes for the single-matrix SpMM)
 static int spmm_lanes_per_row() {
   static int lpr = [] {
     const char* e = getenv("PMOR_SPMM_LPR");
     const int v = e ? atoi(e) : 2;
-    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 2;
+    return spmm_variant_ok(v) ? v : 2;
   }();
   return lpr;
 }
 
-// SpMM lanes-per-row tuning for the batched engine.  One value per (block
-// width, operator: A or the preconditioner), fixed for the process once
-// chosen, so a system's result never depends on the batch it runs in.
-// PMOR_SPMM_LPR pins every value; otherwise the first batch that needs a value
-// times the four candidates on its own matrices and keeps the fastest.
+// SpMM variant tuning for the batched engine.  One value per (block width,
+// operator: A or the preconditioner), fixed for the process once chosen, so a
+// system's result never depends on the batch it runs in.  PMOR_SPMM_LPR pins
+// every value; otherwise the first batch that needs a value times the five
+// candidates (1, 2, 4, 8 lanes per row, column split) on its own matrices and
+// keeps the fastest.
 // PMOR_TUNE_CACHE names a JSON file of the choices: read before tuning,
 // rewritten after it.
 namespace tune {
@@ -1524,7 +1709,7 @@ static void load_locked() {
     size_t c = txt.find(':', j);
     if (c == std::string::npos) break;
     const int v = atoi(txt.c_str() + c + 1);
-    if (v == 1 || v == 2 || v == 4 || v == 8) table[name] = v;
+    if (spmm_variant_ok(v)) table[name] = v;
     i = c + 1;
   }
 }
@@ -1967,6 +2152,9 @@ static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int 
   SpArgs a = a0;
   a.linear = grid >= SPMM_LINEAR_MIN ? 1 : 0;
   switch (lpr) {
+    case SPMM_COLSPLIT:
+      plaunch(c, pidx, part, k_spmm_cs<KP, CONV>, dim3(grid), dim3(64 * CsShape<KP>::L), 0, s, a);
+      break;
     case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(64 * 1), 0, s, a); break;
     case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(64 * 4), 0, s, a); break;
     case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(64 * 8), 0, s, a); break;
@@ -2279,7 +2467,8 @@ class RunnerT final : public Runner {
     }
   }
 
-  // SpMM lanes per row for A and the preconditioner: the process-wide choice,
+  // SpMM variant (lanes per row, or the column split) for A and the
+  // preconditioner: the process-wide choice,
   // measured here on this batch's matrices when none exists yet (the buffers T
   // and Z are free at a cycle boundary)
   int resolve_lanes(int64_t Gtot, int64_t SPtot, bool anyp) {
@@ -2292,7 +2481,7 @@ class RunnerT final : public Runner {
         SpArgs sp{E_.seg_d, E_.tab_d + Gtot, E_.st, which, 0, E_.W.p, E_.T.p, E_.Z.p, nullptr, 1.0, 0.0, nullptr, 1};
         float best_ms = 3.0e38f;
         v = 2;
-        for (int L : {1, 2, 4, 8}) {
+        for (int L : {1, 2, 4, 8, SPMM_COLSPLIT}) {
           for (int r = 0; r < 2; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);
           PMOR_HIP(hipEventRecord(ctx_->ev0, s));
           for (int r = 0; r < 3; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);

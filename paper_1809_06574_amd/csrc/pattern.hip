@@ -7,6 +7,7 @@
 //    (rows of A(:, J_j) holding a nonzero), and the buckets of columns by
 //    (|J_j|, |I_j|) that select the least-squares kernel.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -322,7 +323,7 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   int maxcol = 0;
   PMOR_TRY(transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st));
   pb->max_col_len = maxcol;
-  PMOR_TRY(build_sell(n, pb->rowptr, pb->col, nnz, 1.25, &pb->sell, st));
+  PMOR_TRY(build_sell(n, pb->rowptr, pb->col, nnz, sell_max_fill(), &pb->sell, st));
   if (pb->sell.cap > 0) PMOR_HIP(dmalloc((void**)&pb->aval_s, sizeof(double) * pb->sell.cap, st));
   return PMOR_OK;
 }
@@ -670,7 +671,7 @@ int build_spai_sets(pmor_spai* h) {
     dfree(back, st);
     h->own_P = true;
     h->nnzP = (int32_t)nnzP;
-    PMOR_TRY(build_sell(n, h->Prowptr, h->Pcol, nnzP, 1.25, &h->psell, st));
+    PMOR_TRY(build_sell(n, h->Prowptr, h->Pcol, nnzP, sell_max_fill(), &h->psell, st));
     h->own_psell = true;
   }
   // shadows: sizes, the bucket histogram and the sizes' scan, read back in one
@@ -771,7 +772,7 @@ __global__ __launch_bounds__(64) void k_sell_fill(int n, const int32_t* rowptr, 
       scol[q] = col[e0 + k];
       smap[q] = e0 + k;
     } else {
-      scol[q] = r < n ? r : 0;
+      scol[q] = -1;
       smap[q] = -1;
     }
   }
@@ -783,6 +784,11 @@ __global__ void k_to_sell(int64_t cap, const int32_t* __restrict__ map, const do
     const int32_t e = map[q];
     dst[q] = e >= 0 ? src[e] : 0.0;
   }
+}
+
+double sell_max_fill() {
+  const char* e = getenv("PMOR_SELL_MAX_FILL");
+  return e ? atof(e) : SELL_MAX_FILL;
 }
 
 int build_sell(int n, const int32_t* rowptr, const int32_t* col, int64_t nnz, double max_fill, SellView* v,
