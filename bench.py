@@ -188,6 +188,7 @@ def main():
         del src, dst
 
     # warmup (also builds every lazily created buffer)
+    _note("warmup")
     for _ in range(max(args.warmup, 0)):
         run_job(factory, job, B, "update", Xbuf=Xbuf)
 
@@ -206,6 +207,7 @@ def main():
         dom = args.roofline_kernel
 
     # timed region: update policy, dominant kernel timed live
+    _note(f"timed jobs (dominant kernel {dom})")
     L.check(L.pmor_prof_set(ctx.handle, kinds[dom]), "prof_set")
     lat_upd = []
     t_upd, n_upd = timed(lambda: run_job(factory, job, B, "update", lat=lat_upd, Xbuf=Xbuf), args.steps)
@@ -234,6 +236,7 @@ def main():
         out["kernels"] = per_kernel
 
     if not args.no_arms:
+        _note("arms")
         arms = {"update_batched": (value, lat_upd)}
         for name, policy, mode, steps in (("rebuild_batched", "rebuild", "batched", args.steps),
                                           ("update_pointwise", "update", "pointwise", 1),
@@ -250,16 +253,19 @@ def main():
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
 
     if not args.no_precisions:
+        _note("least-squares precisions")
         out["precisions"] = c3_bench(factory, job, B)
 
     if args.c2_systems > 0:
         out["batch_systems"] = c2_bench(ctx, args.c2_systems)
 
     if args.serve_jobs > 0:
+        _note("serving")
         rhos = [float(x) for x in args.serve_rho.split(",")]
         out["serving"] = serve_bench(ctx, rhos, args.serve_jobs)
 
     if not args.no_cpu_baseline:
+        _note("cpu baseline")
         pb = factory()
         h = pb.spai_build(job.s, job.p_list[0])
         P1 = h.export()["val"].cpu().numpy()
@@ -395,6 +401,11 @@ def c3_bench(factory, job, B):
     return out
 
 
+def _note(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def c2_bench(ctx, nsys):
     """Independent systems of the batch workload (n in [4096, 65536], 2-D/3-D,
     k = 8, power-law SPAI patterns of 5..40 nodes): P_1 at p, the U-diag update
@@ -405,8 +416,13 @@ def c2_bench(ctx, nsys):
     from paper_1809_06574_amd import Problem, batch_solve
 
     # the generator runs in fresh interpreters (no fork of a process that holds the GPU)
+    _note(f"batch workload: generating {nsys} systems")
+    jobs = []
     with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-        jobs = pool.map(_c2_system, range(nsys))
+        for job in pool.imap(_c2_system, range(nsys), chunksize=4):
+            jobs.append(job)
+            if len(jobs) % 64 == 0:
+                _note(f"batch workload: {len(jobs)}/{nsys} systems generated")
     dev = ctx.device
     pbs, hs, Bs = [], [], []
     torch.cuda.synchronize()
