@@ -409,21 +409,26 @@ __global__ __launch_bounds__(64 * NW) void k_upd4(KArgs a) {
     for (int i = 0; i < NB; ++i) v[i] = (i < nbl && valid) ? ldnt(V + (int64_t)i * a.vstride + e) : 0.0;
     double u0 = wt, u1 = 0.0;  // two accumulation chains, added at the end
     if constexpr (P3) {
-      // W' = W - V H1 exactly as pass 2 formed it; the tiles are kept transposed
+      // W' = W - V H1 exactly as pass 2 formed it (chains u0, u1), and -V H2
+      // in two chains of its own that start from zero (s0, s1), so the four
+      // chains run side by side; then W'' = W' + (-V H2).  The tiles are kept
+      // transposed.
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int i = 0; i < NB; ++i) v[i] = tile_transpose(v[i], lane);
 #pragma unroll
       for (int i = 0; i < NB; i += 2) {
-        if (i < nbl) u0 = mfma4(v[i], hb1[16 * i], u0);
-        if (i + 1 < nbl) u1 = mfma4(v[i + 1], hb1[16 * (i + 1)], u1);
+        if (i < nbl) {
+          u0 = mfma4(v[i], hb1[16 * i], u0);
+          s0 = mfma4(v[i], hb[16 * i], s0);
+        }
+        if (i + 1 < nbl) {
+          u1 = mfma4(v[i + 1], hb1[16 * (i + 1)], u1);
+          s1 = mfma4(v[i + 1], hb[16 * (i + 1)], s1);
+        }
       }
       u0 = u0 + u1;
-      u1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < NB; i += 2) {
-        if (i < nbl) u0 = mfma4(v[i], hb[16 * i], u0);
-        if (i + 1 < nbl) u1 = mfma4(v[i + 1], hb[16 * (i + 1)], u1);
-      }
+      u1 = s0 + s1;
     } else {
 #pragma unroll
       for (int i = 0; i < NB; i += 2) {
