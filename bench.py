@@ -38,7 +38,7 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None):
+def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None, approach="first", steps=None):
     """One job; returns the number of parametric solves.  lat collects, per point,
     the seconds from the job's submission until the point's X is final.
 
@@ -46,6 +46,8 @@ def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None):
                and all points' block GMRES solved together;
     pointwise: point after point, spai_update/spai_rebuild then block_solve;
     plain:     point after point, spai_rebuild then one non-block GMRES per column.
+    approach:  the update's anchor (Table 1): "first" A(1), "second" A(l-1).
+    steps collects the block steps of every point (batched mode).
     """
     s = job.s
     npts = len(job.p_list)
@@ -53,7 +55,9 @@ def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None):
     pb = pb_factory()
     if mode == "batched":
         t_call = time.perf_counter()
-        _, stats = pb.sequence_solve(B, [s] * npts, job.p_list, policy=policy, X=Xbuf)
+        _, stats = pb.sequence_solve(B, [s] * npts, job.p_list, policy=policy, X=Xbuf, approach=approach)
+        if steps is not None:
+            steps += [sum(st["cycle_steps"]) for st in stats]
         if lat is not None:
             lat += [(t_call - t_job) + st["t_solve_ms"] * 1e-3 for st in stats]
         pb.close()
@@ -246,8 +250,18 @@ def main():
             lat = []
             t_a, n_a = timed(lambda: run_job(factory, job, B, policy, mode=mode, lat=lat, Xbuf=Xbuf), steps)
             arms[name] = (n_a / t_a, lat)
+        # the second approach of Table 1 (anchor A(l-1)) as an ablation, and the
+        # block steps per point of both approaches
+        st_first, st_second = [], []
+        run_job(factory, job, B, "update", Xbuf=Xbuf, steps=st_first)
+        run_job(factory, job, B, "update", Xbuf=Xbuf, approach="second", steps=st_second)
+        lat = []
+        t_a, n_a = timed(lambda: run_job(factory, job, B, "update", lat=lat, Xbuf=Xbuf, approach="second"),
+                         args.steps)
+        arms["update_second_approach_batched"] = (n_a / t_a, lat)
         out["arms"] = {k: {"solves_per_s": v, "p50_ms": 1e3 * _pct(l, 50), "p99_ms": 1e3 * _pct(l, 99)}
                        for k, (v, l) in arms.items()}
+        out["update_approaches"] = {"steps_per_point_first": st_first, "steps_per_point_second": st_second}
         out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]

@@ -75,6 +75,12 @@ enum pmor_role { PMOR_M0 = 0, PMOR_M1 = 1, PMOR_D0 = 2, PMOR_D1 = 3, PMOR_K0 = 4
 /* Update kinds (pattern of Q_l, which the paper leaves open): */
 #define PMOR_UPD_DIAG 0     /* q_i has the single entry i: P_l = diag(q) P_1  */
 #define PMOR_UPD_PATTERN 1  /* q_i on the SPAI pattern J_i, applied as Q_l(P_1 X) */
+/* Update approaches (Section 2.3, Table 1): */
+#define PMOR_APPROACH_FIRST 0   /* anchor A(1): Q_l = argmin ||A(1) - A(l) Q||_F,  */
+                                /* P_l = Q_l P_1 (the paper's choice)              */
+#define PMOR_APPROACH_SECOND 1  /* anchor A(l-1): Q_l = argmin ||A(l-1) - A(l) Q||_F,*/
+                                /* P_l = Q_l P_{l-1}; built for PMOR_UPD_DIAG only, */
+                                /* where it is the row scaling diag(q_l ... q_2) P_1 */
 /* Sequence policies: */
 #define PMOR_REBUILD 0      /* a new SPAI of A(l) for every point              */
 #define PMOR_UPDATE 1       /* SPAI of A(1), then P_l = Q_l P_1                */
@@ -100,6 +106,7 @@ typedef struct pmor_spai_opts {
   const int32_t* pat_colptr;  /* device, n+1; column j of P may hold rows       */
   const int32_t* pat_row;     /* pat_row[pat_colptr[j]..pat_colptr[j+1]), sorted,*/
                               /* must contain j                                  */
+  int32_t approach;           /* PMOR_APPROACH_FIRST (0) or PMOR_APPROACH_SECOND */
 } pmor_spai_opts;
 
 typedef struct pmor_solve_opts {
@@ -170,9 +177,14 @@ int pmor_assemble(pmor_problem* pb, double s, double p, double* val);
  * PMOR_EINVAL when a column's |J_j| or |I_j| exceeds the supported 64 / 256. */
 int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
                pmor_spai** out, pmor_stats* stats);
-/* First-approach update at (s,p): Q = argmin ||A(1) - A(s,p) Q||_F on the
- * handle's update pattern; then P = Q P_1 (anchor unchanged).  Errors as
- * spai_build. */
+/* Update at (s,p) (Table 1).  First approach: Q = argmin ||A(1) - A(s,p) Q||_F
+ * on the handle's update pattern, then P = Q P_1 (anchor unchanged).  Second
+ * approach (U-diag only): q = argmin ||A(prev) - A(s,p) diag(q)||_F, A(prev)
+ * being the previous update's (or the build's) matrix, then P = diag(q) P_prev,
+ * kept as P_1 with its rows scaled by the running product of the q's; the
+ * anchor moves to (s,p).  rho: the step's own residuals
+ * ||A(prev) e_i - q_i A(s,p) e_i||.  Errors as spai_build; spai_build returns
+ * PMOR_EINVAL for the second approach with PMOR_UPD_PATTERN. */
 int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats);
 /* Recompute the SPAI of A(s,p) in place (the rebuild policy); the anchor is
  * moved to (s,p). */
@@ -180,7 +192,8 @@ int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats);
 /* The current preconditioner.  P in CSR: rowptr (n+1), col (nnzP), val (nnzP);
  * for PMOR_UPD_PATTERN after an update, val holds P_1 and qval holds Q (same
  * CSR pattern), and the preconditioner is Q P_1; for PMOR_UPD_DIAG, qval (n)
- * holds the diagonal q of the last update (ones before).  rho (n): per-column
+ * holds the row scale of P_1 (the last update's q, or with the second approach
+ * the product of the q's since the build; ones before any update).  rho (n): per-column
  * least-squares residual of the last build or update.  Any output may be NULL;
  * device pointers. */
 int spai_info(const pmor_spai* h, int32_t* nnzP, int32_t* maxJ, int32_t* maxI);
@@ -234,8 +247,10 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
                      const pmor_solve_opts* opts, pmor_stats* stats, int32_t* status);
 
 /* The whole sequence of Section 2.3 for points (s_list[l], p_list[l]),
- * l < npts: P_1 = spai_build at point 0; for l >= 1 the first-approach update
- * P_l = Q_l P_1 (PMOR_UPDATE) or a fresh SPAI of A(l) (PMOR_REBUILD).  The
+ * l < npts: P_1 = spai_build at point 0; for l >= 1 the update P_l = Q_l P_1
+ * (PMOR_UPDATE; with sopts->approach = PMOR_APPROACH_SECOND, P_l = Q_l P_{l-1}
+ * anchored at A(l-1), bit for bit as a chain of spai_update calls gives it) or a
+ * fresh SPAI of A(l) (PMOR_REBUILD).  The
  * points are independent once P_1 exists, so their systems are solved together
  * as in pmor_batch_solve (in groups sized to the free device memory).
  * X: npts consecutive n x k row-major blocks (ldx per block, block stride

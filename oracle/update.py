@@ -14,8 +14,9 @@ from its SPAI library).  Two fixed readings are implemented:
 * ``pattern`` q_i has the pattern J_i of the SPAI (same local problems as the
               SPAI with right-hand side A(1) e_i); P_l is applied as Q_l (P_1 X).
 
-The second approach of Table 1 (anchor A(l-1), P_l = Q_l P_{l-1}) is given
-for comparison.
+The second approach of Table 1 (right column: anchor A(l-1), Q_l from
+min ||A(l-1) - A(l) Q||_F and P_l = Q_l P_{l-1}) is given for comparison, with
+the ``diag`` reading of Q (``second_approach_diag``).
 """
 from __future__ import annotations
 
@@ -68,3 +69,22 @@ def update_pattern(n, rowptr, col, val_1, val_l, pat, columns=None):
         qv[pat.P_slot[a:b]] = x
         rho[i] = r
     return qv, rho
+
+
+def second_approach_diag(n, rowptr, col, vals, P_rowptr, P_val_1):
+    """The second approach of Table 1 with a diagonal Q, over a sequence.
+
+    vals[0], vals[1], ...: the values of A(1), A(2), ... on one pattern (A(1)
+    is the matrix P_1 was built for).  For l >= 2 (vals index l - 1 >= 1):
+    q_l = diag_factors(A(l-1), A(l)), i.e. the anchor is the previous matrix,
+    and P_l = diag(q_l) P_{l-1}, taken literally as a row scaling of the
+    previous preconditioner.  Returns the list [P_1, P_2, ...] of values in
+    P's CSR order and the list [None, q_2, q_3, ...] of the step factors.
+    """
+    Ps = [np.array(P_val_1, dtype=np.float64, copy=True)]
+    qs = [None]
+    for l in range(1, len(vals)):
+        q = diag_factors(n, rowptr, col, vals[l - 1], vals[l])
+        Ps.append(update_diag(n, P_rowptr, Ps[-1], q))
+        qs.append(q)
+    return Ps, qs

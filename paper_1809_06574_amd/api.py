@@ -111,8 +111,9 @@ class Problem:
         return a.value, b.value
 
     # --- preconditioner / solve ------------------------------------------
-    def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False):
-        return Spai(self, s, p, pattern=pattern, precision=precision, update=update, stats=stats)
+    def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False, approach="first"):
+        return Spai(self, s, p, pattern=pattern, precision=precision, update=update, stats=stats,
+                    approach=approach)
 
     def block_solve(self, spai, s, p, B: torch.Tensor, m=30, tol=1e-8, max_cycles=20, X=None, raise_on_error=True):
         n, k = B.shape
@@ -128,14 +129,14 @@ class Problem:
 
     def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
                        pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
-                       raise_on_error=True):
+                       raise_on_error=True, approach="first"):
         n, k = B.shape
         npts = len(p_list)
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
         sl = (C.c_double * npts)(*[float(x) for x in s_list])
         pl = (C.c_double * npts)(*[float(x) for x in p_list])
-        so = _spai_opts(pattern, precision, update, self.ctx.device, self)
+        so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach)
         vo = L.SolveOpts(m, max_cycles, tol)
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
@@ -170,10 +171,11 @@ def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_err
     return Xs, [stats[i].as_dict() for i in range(n_it)], [status[i] for i in range(n_it)], rc
 
 
-def _spai_opts(pattern, precision, update, device, keeper):
+def _spai_opts(pattern, precision, update, device, keeper, approach="first"):
     o = L.SpaiOpts()
     o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32, "f16s": L.PMOR_F16S}[precision]
     o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN}[update]
+    o.approach = {"first": L.PMOR_APPROACH_FIRST, "second": L.PMOR_APPROACH_SECOND}[approach]
     if pattern is None:
         o.pattern = L.PMOR_PAT_A
     else:
@@ -187,12 +189,15 @@ def _spai_opts(pattern, precision, update, device, keeper):
 
 
 class Spai:
-    """SPAI of A(s,p) on a pattern, with the first-approach update."""
+    """SPAI of A(s,p) on a pattern, with the update of Table 1 (first approach by
+    default; approach="second" anchors each update at the previous point)."""
 
-    def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False):
+    def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False,
+                 approach="first"):
         self.pb = pb
         self.update_kind = update
-        o = _spai_opts(pattern, precision, update, pb.ctx.device, self)
+        self.approach = approach
+        o = _spai_opts(pattern, precision, update, pb.ctx.device, self, approach)
         h = C.c_void_p()
         st = L.Stats()
         rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), C.byref(st) if stats else None)

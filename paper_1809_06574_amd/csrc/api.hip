@@ -439,6 +439,10 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   if (o.precision != PMOR_F64 && o.precision != PMOR_F32 && o.precision != PMOR_F16S)
     return fail(PMOR_EINVAL, "bad precision");
   if (o.update != PMOR_UPD_DIAG && o.update != PMOR_UPD_PATTERN) return fail(PMOR_EINVAL, "bad update kind");
+  if (o.approach != PMOR_APPROACH_FIRST && o.approach != PMOR_APPROACH_SECOND)
+    return fail(PMOR_EINVAL, "bad update approach");
+  if (o.approach == PMOR_APPROACH_SECOND && o.update != PMOR_UPD_DIAG)
+    return fail(PMOR_EINVAL, "the second update approach is built for the U-diag update only");
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   pmor_spai* h = new pmor_spai();
   h->pb = pb;
@@ -654,6 +658,7 @@ struct SeqBuffers {
   int64_t capA = 0, capP = 0;
   double* q = nullptr;      // group x n: U-diag factors q_l (P_l = diag(q_l) P_1)
   double* rho = nullptr;    // group x n: U-diag column residuals
+  double* carry = nullptr;  // n: second approach, the running row scale of the group's last point
   double* fro = nullptr;    // group x 260 (sum-of-squares scratch)
   int* bad = nullptr;       // group
   int64_t bytes = 0;
@@ -662,7 +667,7 @@ struct SeqBuffers {
   SeqBuffers(const SeqBuffers&) = delete;
   SeqBuffers& operator=(const SeqBuffers&) = delete;
   ~SeqBuffers() {
-    void* v[] = {aval, pq, q, rho, fro, bad, aval_s, pq_s};
+    void* v[] = {aval, pq, q, rho, carry, fro, bad, aval_s, pq_s};
     for (void* x : v) dfree(x, stream);
   }
   int alloc(int group, int64_t nnz, int64_t nnzP, int64_t n, hipStream_t s, int64_t capa = 0, int64_t capp = 0) {
@@ -682,6 +687,7 @@ struct SeqBuffers {
     PMOR_TRY(al((void**)&pq, sizeof(double) * group * nnzP));
     PMOR_TRY(al((void**)&q, sizeof(double) * group * n));
     PMOR_TRY(al((void**)&rho, sizeof(double) * group * n));
+    PMOR_TRY(al((void**)&carry, sizeof(double) * n));
     PMOR_TRY(al((void**)&fro, sizeof(double) * group * 260));
     PMOR_TRY(al((void**)&bad, sizeof(int) * group));
     if (capA > 0) PMOR_TRY(al((void**)&aval_s, sizeof(double) * group * capA));
@@ -689,7 +695,7 @@ struct SeqBuffers {
     return PMOR_OK;
   }
   static int64_t estimate(int group, int64_t nnz, int64_t nnzP, int64_t n, int64_t capa = 0, int64_t capp = 0) {
-    return 8 * group * (nnz + nnzP + capa + capp + 2 * n) + 8 * 260 * group + 4 * group + 8 * 256;
+    return 8 * group * (nnz + nnzP + capa + capp + 2 * n) + 8 * n + 8 * 260 * group + 4 * group + 8 * 256;
   }
 };
 
@@ -746,10 +752,19 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, sb.bad, cnt, 0x7fffffff);
     if (hipGetLastError() != hipSuccess) rc = fail(PMOR_EHIP, "launch failed");
   }
-  for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
-    const int m = std::min(PTS_MAX, cnt - c0);
-    rc = launch_update_diag_pts(h, s_list + l0 + c0, p_list + l0 + c0, m, sb.q + (int64_t)c0 * n,
-                                sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+  if (h->opts.approach == PMOR_APPROACH_SECOND) {
+    // anchors A(l-1): the points in order, the running scale carried across launches
+    for (int c0 = std::max(0, 1 - l0); c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
+      const int m = std::min(PTS_MAX, cnt - c0);
+      rc = launch_update_diag_chain(h, s_list, p_list, l0 + c0, m, sb.carry, sb.q + (int64_t)c0 * n,
+                                    sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+    }
+  } else {
+    for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
+      const int m = std::min(PTS_MAX, cnt - c0);
+      rc = launch_update_diag_pts(h, s_list + l0 + c0, p_list + l0 + c0, m, sb.q + (int64_t)c0 * n,
+                                  sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+    }
   }
   if (rc == PMOR_OK && stats) rc = sumsq_pts(sb.rho, n, cnt, sb.fro, 260, st);
   rec(2);

@@ -275,7 +275,10 @@ int sumsq_pts(const double* x, int64_t n, int cnt, double* out, int64_t ostride,
 // U-diag update into caller buffers (no host synchronisation): P_l = diag(q) P_1
 // into pl, q into q, column residuals into rho, the smallest failing column into
 // *dbad (device int, must hold INT_MAX beforehand)
-int launch_update_diag(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int* dbad);
+int launch_update_diag(pmor_spai* h, const double* aval_l, const double* anchor, const double* qprev, double* pl,
+                       double* q, double* rho, int* dbad);
+int launch_update_diag_chain(pmor_spai* h, const double* s_list, const double* p_list, int l0, int cnt, double* carry,
+                             double* q, double* rho, int* bad, hipStream_t st);
 int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val,
                 const double* X, int64_t ldx, double* Y, int64_t ldy, int k,
                 double alpha, double beta, const double* Bsrc, int64_t ldb,

@@ -493,12 +493,16 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
 }
 
 // ---------------------------------------------------------------------------
-// U-diag update: q_i = <A(l) e_i, A(1) e_i> / ||A(l) e_i||^2 and P_l = diag(q) P_1
-// (P_l written only when Pl is not NULL; the engine can also apply the factors)
+// U-diag update: q_i = <A(l) e_i, a e_i> / ||A(l) e_i||^2 against the anchor a
+// (A(1) for the first approach, A(l-1) for the second), and P_l = diag(q) P_1.
+// qprev (second approach): the running row scale of the previous update, so
+// that q holds qprev_i q_i and P_l = diag(qprev q) P_1 = diag(q) P_{l-1}.  rho:
+// the step's own residual ||a e_i - q_i A(l) e_i||.  (P_l written only when Pl
+// is not NULL; the engine can also apply the factors.)
 // ---------------------------------------------------------------------------
 __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscslot, const double* al,
-                              const double* a1, const int32_t* Prowptr, const double* P1, double* Pl, double* q,
-                              double* rho, int* bad_col) {
+                              const double* a1, const double* qprev, const int32_t* Prowptr, const double* P1,
+                              double* Pl, double* q, double* rho, int* bad_col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double num = 0.0, den = 0.0, n11 = 0.0;
@@ -511,22 +515,29 @@ __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscsl
   }
   const double qi = num / den;
   if (!(den > 0.0)) atomicMin(bad_col, i);
-  q[i] = qi;
-  // ||A(1) e_i - q_i A(l) e_i||^2 = n11 - 2 q num + q^2 den
+  const double qe = qprev ? qprev[i] * qi : qi;
+  q[i] = qe;
+  // ||a e_i - q_i A(l) e_i||^2 = n11 - 2 q num + q^2 den
   const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
   rho[i] = sqrt(r2 > 0.0 ? r2 : 0.0);
   if (Pl)
-    for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qi * P1[e];
+    for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qe * P1[e];
 }
 
-int launch_update_diag(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int* dbad) {
+int launch_update_diag(pmor_spai* h, const double* aval_l, const double* anchor, const double* qprev, double* pl,
+                       double* q, double* rho, int* dbad) {
   pmor_problem* pb = h->pb;
   const int n = pb->n;
   if (n == 0) return PMOR_OK;
   hipLaunchKernelGGL(k_update_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pb->ctx->stream, n, pb->colptr,
-                     pb->cscslot, aval_l, h->aval1, h->Prowptr, h->P1val, pl, q, rho, dbad);
+                     pb->cscslot, aval_l, anchor, qprev, h->Prowptr, h->P1val, pl, q, rho, dbad);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
+}
+
+__global__ void k_copy_vals(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
 }
 
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2) {
@@ -536,7 +547,14 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
   int* dbad = reinterpret_cast<int*>(h->red);
   const int big = 0x7fffffff;
   PMOR_TRY(set_device_int(dbad, big, st));
-  PMOR_TRY(launch_update_diag(h, aval_l, h->Pval, h->Qval, h->rho, dbad));
+  // the second approach chains the scales and moves the anchor (aval1) to A(l)
+  const bool second = h->opts.approach == PMOR_APPROACH_SECOND;
+  PMOR_TRY(launch_update_diag(h, aval_l, h->aval1, second ? h->Qval : nullptr, h->Pval, h->Qval, h->rho, dbad));
+  if (second) {
+    const unsigned g = (unsigned)std::min<int64_t>((pb->nnz + 255) / 256, 4096);
+    if (pb->nnz > 0) hipLaunchKernelGGL(k_copy_vals, dim3(g), dim3(256), 0, st, aval_l, h->aval1, (int64_t)pb->nnz);
+    PMOR_HIP(hipGetLastError());
+  }
   if (bad_col || fro2) {
     double* dsum = h->red + 1;
     PMOR_TRY(sumsq(h->rho, n, dsum, st));
@@ -589,6 +607,12 @@ int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* ou
 // ---------------------------------------------------------------------------
 struct PtsCoefs {
   double c[PTS_MAX][PMOR_NROLES];  // by term slot
+  int cnt, nt;
+};
+
+// the anchor point and up to PTS_MAX points of a second-approach chain
+struct ChainCoefs {
+  double c[PTS_MAX + 1][PMOR_NROLES];  // by term slot
   int cnt, nt;
 };
 
@@ -684,6 +708,78 @@ int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_l
   const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
   hipLaunchKernelGGL(k_update_diag_pts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
                      pb->cscslot, pb->nnz, pb->tval, pc, h->aval1, q, rho, bad);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
+// Second approach over points l0 .. l0 + cnt - 1 of a sequence (l0 >= 1, cnt
+// <= PTS_MAX): for each point the anchor is the previous point, q_l from
+// ||A(l-1) e_i - q A(l) e_i|| and the running scale q_l q_{l-1} ... q_1 into q
+// (row t), with the step residual into rho.  Both matrices come from the term
+// values with the points' coefficients (pc.c[0]: point l0 - 1, pc.c[t + 1]:
+// point l0 + t), each entry once, by the sums of k_assemble, so the factors
+// are bit for bit those of a chain of single updates.  carry (n): the running
+// scale of point l0 - 1 (ones for l0 = 1), replaced by the last point's.
+__global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t* cscslot, int64_t nnz,
+                                    const double* __restrict__ tval, ChainCoefs pc, int l0, double* carry,
+                                    double* q, double* rho, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double num[PTS_MAX], den[PTS_MAX], n11[PTS_MAX];
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = n11[l] = 0.0;
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    double tv[PMOR_NROLES];
+#pragma unroll
+    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    double y = 0.0;  // anchor value (point l0 - 1)
+    for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
+#pragma unroll
+    for (int l = 0; l < PTS_MAX; ++l) {
+      if (l < pc.cnt) {
+        double x = 0.0;
+        for (int t = 0; t < pc.nt; ++t) x += pc.c[l + 1][t] * tv[t];
+        num[l] += x * y;
+        den[l] += x * x;
+        n11[l] += y * y;
+        y = x;  // the next point's anchor
+      }
+    }
+  }
+  double qc = l0 >= 2 ? carry[i] : 1.0;
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) {
+    if (l < pc.cnt) {
+      const double qi = num[l] / den[l];
+      if (!(den[l] > 0.0)) atomicMin(bad + l, i);
+      qc = qc * qi;
+      q[(int64_t)l * n + i] = qc;
+      const double r2 = n11[l] - 2.0 * qi * num[l] + qi * qi * den[l];
+      rho[(int64_t)l * n + i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+    }
+  }
+  carry[i] = qc;
+}
+
+int launch_update_diag_chain(pmor_spai* h, const double* s_list, const double* p_list, int l0, int cnt, double* carry,
+                             double* q, double* rho, int* bad, hipStream_t st) {
+  pmor_problem* pb = h->pb;
+  const int n = pb->n;
+  if (n == 0 || cnt <= 0) return PMOR_OK;
+  if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one update launch");
+  if (l0 < 1) return fail(PMOR_EINVAL, "the update chain starts after the anchor point");
+  ChainCoefs pc{};
+  pc.cnt = cnt;
+  pc.nt = pb->nterms;
+  for (int t = 0; t <= cnt; ++t) {
+    double c[PMOR_NROLES];
+    role_coefs(s_list[l0 - 1 + t], p_list[l0 - 1 + t], c);
+    for (int r = 0; r < PMOR_NROLES; ++r)
+      if (pb->role_slot[r] >= 0) pc.c[t][pb->role_slot[r]] = c[r];
+  }
+  hipLaunchKernelGGL(k_update_diag_chain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
+                     pb->cscslot, pb->nnz, pb->tval, pc, l0, carry, q, rho, bad);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }

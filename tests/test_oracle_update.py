@@ -138,3 +138,59 @@ def test_config0_update_quality_ratio():
         dp = p - job.p_list[0]
         nn = np.sum(A1 * A1, axis=0); dd = np.diag(A1)
         np.testing.assert_allclose(q, (nn + dp * dd) / (nn + 2 * dp * dd + dp * dp), rtol=1e-14)
+
+
+# ---- second approach (Table 1, right column: anchor A(l-1), P_l = Q_l P_{l-1}) ----
+
+def test_second_approach_first_step_is_the_first_approach():
+    """At l = 2 both approaches anchor at A(1): the same P_2 bit for bit."""
+    from oracle.update import second_approach_diag
+    job = tiny_random_job(23, 0.15, 41, npts=4)
+    asm, pat = _setup(job)
+    vals = [asm.values(job.s, p) for p in job.p_list]
+    pv1, _ = spai_build(job.n, asm.rowptr, asm.col, vals[0], pat)
+    Ps, qs = second_approach_diag(job.n, asm.rowptr, asm.col, vals, pat.P_rowptr, pv1)
+    q_first = diag_factors(job.n, asm.rowptr, asm.col, vals[0], vals[1])
+    np.testing.assert_array_equal(qs[1], q_first)
+    np.testing.assert_array_equal(Ps[1], update_diag(job.n, pat.P_rowptr, pv1, q_first))
+    # later points differ from the first approach (the anchors differ)
+    q3_first = diag_factors(job.n, asm.rowptr, asm.col, vals[0], vals[2])
+    assert not np.allclose(Ps[2], update_diag(job.n, pat.P_rowptr, pv1, q3_first), rtol=1e-12, atol=0)
+
+
+def test_second_approach_diagonal_matrices_telescope_to_the_inverse():
+    """Diagonal A(l) = diag(d_l): P_1 = diag(1/d_1), the step factors are
+    q_l = d_{l-1} / d_l, and their product telescopes, so P_L = diag(1/d_L) =
+    A(L)^{-1} (as the first approach gives it)."""
+    from oracle.update import second_approach_diag
+    n, L = 40, 7
+    rng = np.random.default_rng(5)
+    d = [rng.uniform(0.5, 3.0, n) * rng.choice([-1.0, 1.0], n) for _ in range(L)]
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    Ps, qs = second_approach_diag(n, rowptr, col, d, rowptr, 1.0 / d[0])
+    for l in range(1, L):
+        np.testing.assert_allclose(qs[l], d[l - 1] / d[l], rtol=1e-15)
+        np.testing.assert_allclose(Ps[l], 1.0 / d[l], rtol=4e-15 * l)
+        q_first = diag_factors(n, rowptr, col, d[0], d[l])
+        np.testing.assert_allclose(Ps[l], update_diag(n, rowptr, 1.0 / d[0], q_first), rtol=4e-15 * l)
+
+
+def test_second_approach_dense_brute_force():
+    """Each step as a dense one-unknown least squares per column
+    (numpy.linalg.lstsq on A(l)(:, i) against A(l-1)(:, i)), the products
+    diag(q_l) P_{l-1} formed densely."""
+    from oracle.update import second_approach_diag
+    job = tiny_random_job(16, 0.2, 43, npts=5)
+    n = job.n
+    asm, pat = _setup(job)
+    vals = [asm.values(job.s, p) for p in job.p_list]
+    pv1, _ = spai_build(n, asm.rowptr, asm.col, vals[0], pat)
+    Ps, _ = second_approach_diag(n, asm.rowptr, asm.col, vals, pat.P_rowptr, pv1)
+    P = _dense(n, pat, pv1)
+    for l in range(1, len(vals)):
+        Aprev = to_dense(n, asm.rowptr, asm.col, vals[l - 1])
+        Al = to_dense(n, asm.rowptr, asm.col, vals[l])
+        q = np.array([np.linalg.lstsq(Al[:, [i]], Aprev[:, i], rcond=None)[0][0] for i in range(n)])
+        P = np.diag(q) @ P
+        np.testing.assert_allclose(_dense(n, pat, Ps[l]), P, rtol=1e-13, atol=1e-15 * np.abs(P).max())
