@@ -107,6 +107,11 @@ typedef struct pmor_spai_opts {
   const int32_t* pat_row;     /* pat_row[pat_colptr[j]..pat_colptr[j+1]), sorted,*/
                               /* must contain j                                  */
   int32_t approach;           /* PMOR_APPROACH_FIRST (0) or PMOR_APPROACH_SECOND */
+  double reanchor_tol;        /* pmor_sequence_solve, U-diag first approach: a   */
+                              /* point l whose update misfit                     */
+                              /* ||A(a) - A(l) Q||_F / ||A(a)||_F against the    */
+                              /* current anchor a exceeds this gets a fresh SPAI */
+                              /* and anchors the later points (0: never)         */
 } pmor_spai_opts;
 
 typedef struct pmor_solve_opts {
@@ -129,6 +134,9 @@ typedef struct pmor_stats {
   double t_solve_ms;         /* block_solve: its wall time; batched calls: wall  */
                              /* time from the call's start until this system's X */
                              /* is final                                         */
+  int32_t anchor;            /* pmor_sequence_solve: the point whose SPAI this   */
+                             /* point's preconditioner is updated from (itself   */
+                             /* when rebuilt); 0 elsewhere                        */
 } pmor_stats;
 
 /* ---- context ----------------------------------------------------------- */
@@ -260,7 +268,13 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
  * P_l = diag(q_l) P_1 is applied in that factored form; t_assemble_ms and
  * t_precond_ms then hold equal shares of those launches.  A point whose update or rebuild
  * meets a singular column is not solved (PMOR_ESINGULAR, X untouched); the
- * others are.  Returns the first failing point's code, else PMOR_OK. */
+ * others are.  sopts->reanchor_tol > 0 (PMOR_UPDATE, U-diag, first approach;
+ * PMOR_EINVAL otherwise): before any solve the points are scanned in order and
+ * each point whose update misfit against the current anchor exceeds the
+ * tolerance becomes a new anchor (a fresh SPAI, later points updated from it);
+ * the runs between anchors are then solved as sequences of their own, and
+ * stats[l].anchor names each point's anchor.  Returns the first failing
+ * point's code, else PMOR_OK. */
 int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k,
                         const double* s_list, const double* p_list, int32_t npts,
                         double* X, int64_t ldx, int32_t policy,
@@ -298,8 +312,9 @@ typedef struct pmor_job {
                         /* t_solve_ms = submission to the point's final X            */
 } pmor_job;
 
-/* sopts, vopts: as pmor_sequence_solve (NULL: defaults).  The engine's
- * buffers are allocated here.  PMOR_ENOMEM when the budget cannot hold them. */
+/* sopts, vopts: as pmor_sequence_solve (NULL: defaults; reanchor_tol must be
+ * 0).  The engine's buffers are allocated here.  PMOR_ENOMEM when the budget
+ * cannot hold them. */
 int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_spai_opts* sopts,
                        const pmor_solve_opts* vopts, pmor_server** out);
 /* Jobs still held are dropped (their X undefined). */

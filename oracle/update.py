@@ -88,3 +88,32 @@ def second_approach_diag(n, rowptr, col, vals, P_rowptr, P_val_1):
         Ps.append(update_diag(n, P_rowptr, Ps[-1], q))
         qs.append(q)
     return Ps, qs
+
+
+def misfit_diag(n, rowptr, col, val_a, val_l):
+    """Relative misfit of the U-diag update of A(l) against the anchor A(a):
+    ||A(a) - A(l) diag(q)||_F / ||A(a)||_F with q = diag_factors(A(a), A(l)),
+    summed column by column on the pattern."""
+    q = diag_factors(n, rowptr, col, val_a, val_l)
+    colptr, rowidx, slot = transpose_pattern(n, rowptr, col)
+    num = 0.0
+    for i in range(n):
+        s = slot[colptr[i]:colptr[i + 1]]
+        d = val_a[s] - q[i] * val_l[s]
+        num += float(d @ d)
+    return float(np.sqrt(num) / np.linalg.norm(val_a))
+
+
+def plan_anchors(n, rowptr, col, vals, tol):
+    """Re-anchoring of a sequence (first approach, U-diag): point 0 is the first
+    anchor; the points are taken in order and a point whose misfit against the
+    current anchor exceeds tol (or is not finite) becomes the next anchor (its
+    preconditioner is rebuilt and later points are updated from it)."""
+    anchors = [0]
+    a = 0
+    for l in range(1, len(vals)):
+        r = misfit_diag(n, rowptr, col, vals[a], vals[l])
+        if not (r <= tol):
+            anchors.append(l)
+            a = l
+    return anchors

@@ -129,14 +129,14 @@ class Problem:
 
     def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
                        pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
-                       raise_on_error=True, approach="first"):
+                       raise_on_error=True, approach="first", reanchor_tol=0.0):
         n, k = B.shape
         npts = len(p_list)
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
         sl = (C.c_double * npts)(*[float(x) for x in s_list])
         pl = (C.c_double * npts)(*[float(x) for x in p_list])
-        so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach)
+        so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach, reanchor_tol)
         vo = L.SolveOpts(m, max_cycles, tol)
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
@@ -171,8 +171,9 @@ def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_err
     return Xs, [stats[i].as_dict() for i in range(n_it)], [status[i] for i in range(n_it)], rc
 
 
-def _spai_opts(pattern, precision, update, device, keeper, approach="first"):
+def _spai_opts(pattern, precision, update, device, keeper, approach="first", reanchor_tol=0.0):
     o = L.SpaiOpts()
+    o.reanchor_tol = float(reanchor_tol)
     o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32, "f16s": L.PMOR_F16S}[precision]
     o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN}[update]
     o.approach = {"first": L.PMOR_APPROACH_FIRST, "second": L.PMOR_APPROACH_SECOND}[approach]

@@ -913,31 +913,86 @@ static int sequence_checks(const pmor_problem* pb, const double* B, int64_t ldb,
   return PMOR_OK;
 }
 
-}  // namespace pmor
+// Anchors of a re-anchored sequence (U-diag, first approach): point 0, then,
+// scanning the points in order, every point l whose update misfit
+// ||A(a) - A(l) diag(q)||_F exceeds tol ||A(a)||_F against the current anchor
+// a.  The misfit is the root sum of the update's column residuals (formed for
+// up to PTS_MAX points per launch, read back once per launch); a non-finite
+// misfit also re-anchors (the rebuild there reports a singular column).
+static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_list, int npts, double tol,
+                        std::vector<int>* anchors) {
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  const int64_t nnz = pb->nnz;
+  double *Aa = nullptr, *q = nullptr, *rho = nullptr, *fro = nullptr, *nrm = nullptr;
+  int* bad = nullptr;
+  struct Free {
+    std::vector<void*> v;
+    hipStream_t s;
+    ~Free() {
+      for (void* x : v) dfree(x, s);
+    }
+  } keep{{}, st};
+  auto al = [&](void** x, size_t b) {
+    if (dmalloc(x, std::max<size_t>(b, 8), st) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    keep.v.push_back(*x);
+    return true;
+  };
+  if (!al((void**)&Aa, sizeof(double) * nnz) || !al((void**)&q, sizeof(double) * PTS_MAX * n) ||
+      !al((void**)&rho, sizeof(double) * PTS_MAX * n) || !al((void**)&fro, sizeof(double) * PTS_MAX * 260) ||
+      !al((void**)&nrm, sizeof(double) * 260) || !al((void**)&bad, sizeof(int) * PTS_MAX))
+    return fail(PMOR_ENOMEM, "allocation of the re-anchoring scratch failed");
+  int a = 0, l = 1;
+  while (l < npts) {
+    double c[PMOR_NROLES];
+    role_coefs(s_list[a], p_list[a], c);
+    PMOR_TRY(launch_assemble(pb, c, Aa, st));
+    PMOR_TRY(sumsq(Aa, nnz, nrm, st));
+    double na2 = 0.0;
+    PMOR_HIP(hipMemcpyAsync(&na2, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    int found = -1;
+    for (int c0 = l; c0 < npts && found < 0; c0 += PTS_MAX) {
+      const int m = std::min(PTS_MAX, npts - c0);
+      PMOR_TRY(launch_update_diag_pts_anchor(pb, Aa, s_list + c0, p_list + c0, m, q, rho, bad, st));
+      PMOR_TRY(sumsq_pts(rho, n, m, fro, 260, st));
+      std::vector<double> f((size_t)m * 260);
+      PMOR_HIP(hipMemcpyAsync(f.data(), fro, sizeof(double) * 260 * m, hipMemcpyDeviceToHost, st));
+      PMOR_HIP(hipStreamSynchronize(st));
+      for (int t = 0; t < m && found < 0; ++t)
+        if (!(f[(size_t)t * 260] <= tol * tol * na2)) found = c0 + t;
+    }
+    if (found < 0) break;
+    anchors->push_back(found);
+    a = found;
+    l = found + 1;
+  }
+  return PMOR_OK;
+}
 
-extern "C" {
-
-int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
+// One run of a sequence: P_1 built at its first point, the others updated
+// from it (or rebuilt).  lbase: the run's first point in the caller's sequence
+// (stats[].anchor, messages); t0: the call's start.
+static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
                         const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
-                        const pmor_spai_opts* sopts, const pmor_solve_opts* vopts, pmor_stats* stats) {
-  PMOR_TRY(sequence_checks(pb, B, ldb, k, s_list, p_list, npts, X, ldx, policy));
-  pmor_solve_opts o;
-  PMOR_TRY(solve_opts_of(vopts, &o));
-  PMOR_HIP(hipSetDevice(pb->ctx->device));
-  const auto t0 = std::chrono::steady_clock::now();
+                        const pmor_spai_opts* sopts, const pmor_solve_opts& o, pmor_stats* stats, int lbase,
+                        std::chrono::steady_clock::time_point t0) {
   auto since = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
-  if (stats) std::memset(stats, 0, sizeof(pmor_stats) * npts);
+  if (stats)
+    for (int l = 0; l < npts; ++l) stats[l].anchor = policy == PMOR_UPDATE ? lbase : lbase + l;
   pmor_stats pre0{};
   pre0.bad_column = -1;
   pmor_spai* h = nullptr;
   int rc = spai_build(pb, s_list[0], p_list[0], sopts, &h, &pre0);
   if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
-    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); }
+    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); stats[0].anchor = lbase; }
     spai_release(h);
     return rc;
   }
   if (rc == PMOR_ESINGULAR) {  // no anchor: nothing can be solved
-    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); }
+    if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); stats[0].anchor = lbase; }
     spai_release(h);
     return rc;
   }
@@ -972,7 +1027,7 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
       if (bad[t] >= 0) {
         if (first_bad == PMOR_OK) {
           first_bad = PMOR_ESINGULAR;
-          set_error("rank-deficient least-squares problem at point " + std::to_string(l0 + t) + ", column " +
+          set_error("rank-deficient least-squares problem at point " + std::to_string(lbase + l0 + t) + ", column " +
                     std::to_string(bad[t]));
         }
         if (stats) stats[l0 + t].t_solve_ms = since();
@@ -993,6 +1048,40 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   }
   spai_release(h);
   if (rc != PMOR_OK) return rc;
+  return first_bad;
+}
+
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
+                        const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
+                        const pmor_spai_opts* sopts, const pmor_solve_opts* vopts, pmor_stats* stats) {
+  PMOR_TRY(sequence_checks(pb, B, ldb, k, s_list, p_list, npts, X, ldx, policy));
+  pmor_solve_opts o;
+  PMOR_TRY(solve_opts_of(vopts, &o));
+  const double tol = sopts ? sopts->reanchor_tol : 0.0;
+  if (!(tol >= 0.0) || !is_fin(tol)) return fail(PMOR_EINVAL, "reanchor_tol must be finite and >= 0");
+  if (tol > 0.0 && (policy != PMOR_UPDATE || sopts->update != PMOR_UPD_DIAG || sopts->approach != PMOR_APPROACH_FIRST))
+    return fail(PMOR_EINVAL, "re-anchoring is built for the U-diag update with the first approach");
+  PMOR_HIP(hipSetDevice(pb->ctx->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  if (stats) std::memset(stats, 0, sizeof(pmor_stats) * npts);
+  std::vector<int> anchors{0};
+  if (tol > 0.0) PMOR_TRY(plan_anchors(pb, s_list, p_list, npts, tol, &anchors));
+  anchors.push_back(npts);
+  int first_bad = PMOR_OK;
+  for (size_t a = 0; a + 1 < anchors.size(); ++a) {
+    const int l0 = anchors[a], cnt = anchors[a + 1] - l0;
+    const int rc = sequence_run(pb, B, ldb, k, s_list + l0, p_list + l0, cnt, X + (int64_t)l0 * pb->n * ldx, ldx,
+                                policy, sopts, o, stats ? stats + l0 : nullptr, l0, t0);
+    if (rc == PMOR_ESINGULAR || rc == PMOR_ENOTCONV || rc == PMOR_EBREAKDOWN || rc == PMOR_ENAN) {
+      if (first_bad == PMOR_OK) first_bad = rc;
+    } else if (rc != PMOR_OK) {
+      return rc;
+    }
+  }
   return first_bad;
 }
 
@@ -1119,6 +1208,7 @@ int pmor_server_create(pmor_ctx* ctx, const pmor_server_opts* opts, const pmor_s
   so.update = PMOR_UPD_DIAG;
   if (sopts) so = *sopts;
   if (so.pattern != PMOR_PAT_A) return fail(PMOR_EINVAL, "the server builds SPAI on the pattern of A");
+  if (so.reanchor_tol != 0.0) return fail(PMOR_EINVAL, "re-anchoring is built for pmor_sequence_solve only");
   pmor_solve_opts o;
   PMOR_TRY(solve_opts_of(vopts, &o));
   PMOR_HIP(hipSetDevice(ctx->device));

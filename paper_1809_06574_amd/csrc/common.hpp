@@ -272,6 +272,9 @@ int launch_assemble_pts(pmor_problem* pb, const double* s_list, const double* p_
 int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
                            int* bad, hipStream_t st);
 int sumsq_pts(const double* x, int64_t n, int cnt, double* out, int64_t ostride, hipStream_t st);
+// U-diag factors and column residuals of up to PTS_MAX points against the anchor values given
+int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const double* s_list, const double* p_list,
+                                  int cnt, double* q, double* rho, int* bad, hipStream_t st);
 // U-diag update into caller buffers (no host synchronisation): P_l = diag(q) P_1
 // into pl, q into q, column residuals into rho, the smallest failing column into
 // *dbad (device int, must hold INT_MAX beforehand)

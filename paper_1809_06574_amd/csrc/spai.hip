@@ -699,17 +699,21 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
   }
 }
 
-int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
-                           int* bad, hipStream_t st) {
-  pmor_problem* pb = h->pb;
+int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const double* s_list, const double* p_list,
+                                  int cnt, double* q, double* rho, int* bad, hipStream_t st) {
   const int n = pb->n;
   if (n == 0 || cnt <= 0) return PMOR_OK;
   if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one update launch");
   const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
   hipLaunchKernelGGL(k_update_diag_pts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
-                     pb->cscslot, pb->nnz, pb->tval, pc, h->aval1, q, rho, bad);
+                     pb->cscslot, pb->nnz, pb->tval, pc, anchor, q, rho, bad);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
+}
+
+int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
+                           int* bad, hipStream_t st) {
+  return launch_update_diag_pts_anchor(h->pb, h->aval1, s_list, p_list, cnt, q, rho, bad, st);
 }
 
 // Second approach over points l0 .. l0 + cnt - 1 of a sequence (l0 >= 1, cnt

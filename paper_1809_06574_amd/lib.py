@@ -40,7 +40,7 @@ class Csr(C.Structure):
 class SpaiOpts(C.Structure):
     _fields_ = [("pattern", C.c_int32), ("precision", C.c_int32), ("update", C.c_int32),
                 ("nnz_explicit", C.c_int32), ("pat_colptr", C.c_void_p), ("pat_row", C.c_void_p),
-                ("approach", C.c_int32)]
+                ("approach", C.c_int32), ("reanchor_tol", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -60,14 +60,14 @@ class Stats(C.Structure):
     _fields_ = [("k", C.c_int32), ("cycles", C.c_int32), ("steps", C.c_int32), ("bad_column", C.c_int32),
                 ("cycle_steps", C.c_int32 * PMOR_MAX_CYCLES), ("relres", C.c_double * PMOR_KMAX),
                 ("fro_resid", C.c_double), ("t_assemble_ms", C.c_double), ("t_precond_ms", C.c_double),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("anchor", C.c_int32)]
 
     def as_dict(self):
         return {"k": self.k, "cycles": self.cycles, "steps": self.steps, "bad_column": self.bad_column,
                 "cycle_steps": list(self.cycle_steps[: max(self.cycles, 0)]),
                 "relres": list(self.relres[: self.k]), "fro_resid": self.fro_resid,
                 "t_assemble_ms": self.t_assemble_ms, "t_precond_ms": self.t_precond_ms,
-                "t_solve_ms": self.t_solve_ms}
+                "t_solve_ms": self.t_solve_ms, "anchor": self.anchor}
 
 
 P = C.c_void_p

@@ -194,3 +194,33 @@ def test_second_approach_dense_brute_force():
         q = np.array([np.linalg.lstsq(Al[:, [i]], Aprev[:, i], rcond=None)[0][0] for i in range(n)])
         P = np.diag(q) @ P
         np.testing.assert_allclose(_dense(n, pat, Ps[l]), P, rtol=1e-13, atol=1e-15 * np.abs(P).max())
+
+
+# ---- re-anchoring (rebuild P where the first-approach update misfits) ----
+
+def test_misfit_is_the_dense_frobenius_ratio():
+    from oracle.update import misfit_diag
+    job = tiny_random_job(19, 0.2, 44, npts=3)
+    n = job.n
+    asm, _ = _setup(job)
+    va, vl = asm.values(job.s, job.p_list[0]), asm.values(job.s, job.p_list[2])
+    q = diag_factors(n, asm.rowptr, asm.col, va, vl)
+    Aa, Al = to_dense(n, asm.rowptr, asm.col, va), to_dense(n, asm.rowptr, asm.col, vl)
+    want = np.linalg.norm(Aa - Al @ np.diag(q), "fro") / np.linalg.norm(Aa, "fro")
+    assert misfit_diag(n, asm.rowptr, asm.col, va, vl) == pytest.approx(want, rel=1e-12)
+    assert misfit_diag(n, asm.rowptr, asm.col, va, va.copy()) == 0.0
+
+
+def test_plan_anchors_limits_and_a_jump():
+    from oracle.update import misfit_diag, plan_anchors
+    job = tiny_random_job(30, 0.15, 45)
+    n = job.n
+    asm, _ = _setup(job)
+    ps = [0.1, 0.11, 0.12, 3.0, 3.01, 3.02]
+    vals = [asm.values(job.s, p) for p in ps]
+    assert plan_anchors(n, asm.rowptr, asm.col, vals, np.inf) == [0]
+    assert plan_anchors(n, asm.rowptr, asm.col, vals, 0.0) == list(range(len(ps)))
+    small = max(misfit_diag(n, asm.rowptr, asm.col, vals[a], vals[b]) for a, b in ((0, 1), (0, 2), (3, 4), (3, 5)))
+    big = misfit_diag(n, asm.rowptr, asm.col, vals[0], vals[3])
+    assert big > 10 * small
+    assert plan_anchors(n, asm.rowptr, asm.col, vals, np.sqrt(small * big)) == [0, 3]
