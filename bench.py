@@ -38,7 +38,8 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None, approach="first", steps=None):
+def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None, approach="first", steps=None,
+            update="diag", adapt_ep=0.0):
     """One job; returns the number of parametric solves.  lat collects, per point,
     the seconds from the job's submission until the point's X is final.
 
@@ -46,7 +47,8 @@ def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None, app
                and all points' block GMRES solved together;
     pointwise: point after point, spai_update/spai_rebuild then block_solve;
     plain:     point after point, spai_rebuild then one non-block GMRES per column.
-    approach:  the update's anchor (Table 1): "first" A(1), "second" A(l-1).
+    approach:  the update's anchor (Table 1): "first" A(1), "second" A(l-1);
+    update:    the pattern of Q ("diag", "pattern", "adaptive" with adapt_ep).
     steps collects the block steps of every point (batched mode).
     """
     s = job.s
@@ -55,7 +57,8 @@ def run_job(pb_factory, job, B, policy, mode="batched", lat=None, Xbuf=None, app
     pb = pb_factory()
     if mode == "batched":
         t_call = time.perf_counter()
-        _, stats = pb.sequence_solve(B, [s] * npts, job.p_list, policy=policy, X=Xbuf, approach=approach)
+        _, stats = pb.sequence_solve(B, [s] * npts, job.p_list, policy=policy, X=Xbuf, approach=approach,
+                                     update=update, adapt_ep=adapt_ep)
         if steps is not None:
             steps += [sum(st["cycle_steps"]) for st in stats]
         if lat is not None:
@@ -264,9 +267,20 @@ def main():
         t_a, n_a = timed(lambda: run_job(factory, job, B, "update", lat=lat, Xbuf=Xbuf, approach="second"),
                          args.steps)
         arms["update_second_approach_batched"] = (n_a / t_a, lat)
+        # the adaptive Q pattern at the paper's MSPAI tolerance (1e-4) and at 0.02
+        st_adapt = {}
+        for tag, ep in (("1e-4", 1e-4), ("0.02", 0.02)):
+            st_adapt[tag] = []
+            run_job(factory, job, B, "update", Xbuf=Xbuf, update="adaptive", adapt_ep=ep, steps=st_adapt[tag])
+            lat = []
+            t_a, n_a = timed(lambda: run_job(factory, job, B, "update", lat=lat, Xbuf=Xbuf, update="adaptive",
+                                             adapt_ep=ep), args.steps)
+            arms[f"update_adaptive_ep{tag}_batched"] = (n_a / t_a, lat)
         out["arms"] = {k: {"solves_per_s": v, "p50_ms": 1e3 * _pct(l, 50), "p99_ms": 1e3 * _pct(l, 99)}
                        for k, (v, l) in arms.items()}
         out["update_approaches"] = {"steps_per_point_first": st_first, "steps_per_point_second": st_second,
+                                    "steps_per_point_adaptive_ep1e-4": st_adapt["1e-4"],
+                                    "steps_per_point_adaptive_ep0.02": st_adapt["0.02"],
                                     "first_update_misfit_max": max(misfit) if misfit else 0.0,
                                     "first_update_misfit_last": misfit[-1] if misfit else 0.0}
         out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]

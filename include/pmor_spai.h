@@ -75,6 +75,9 @@ enum pmor_role { PMOR_M0 = 0, PMOR_M1 = 1, PMOR_D0 = 2, PMOR_D1 = 3, PMOR_K0 = 4
 /* Update kinds (pattern of Q_l, which the paper leaves open): */
 #define PMOR_UPD_DIAG 0     /* q_i has the single entry i: P_l = diag(q) P_1  */
 #define PMOR_UPD_PATTERN 1  /* q_i on the SPAI pattern J_i, applied as Q_l(P_1 X) */
+#define PMOR_UPD_ADAPTIVE 2 /* q_i diagonal, escalated to J_i (the U-pattern least */
+                            /* squares) where ||A(1)e_i - q_i A(l)e_i|| >         */
+                            /* adapt_ep ||A(1)e_i||; applied as Q_l(P_1 X)        */
 /* Update approaches (Section 2.3, Table 1): */
 #define PMOR_APPROACH_FIRST 0   /* anchor A(1): Q_l = argmin ||A(1) - A(l) Q||_F,  */
                                 /* P_l = Q_l P_1 (the paper's choice)              */
@@ -112,6 +115,7 @@ typedef struct pmor_spai_opts {
                               /* ||A(a) - A(l) Q||_F / ||A(a)||_F against the    */
                               /* current anchor a exceeds this gets a fresh SPAI */
                               /* and anchors the later points (0: never)         */
+  double adapt_ep;            /* PMOR_UPD_ADAPTIVE: escalation threshold >= 0    */
 } pmor_spai_opts;
 
 typedef struct pmor_solve_opts {
@@ -198,8 +202,10 @@ int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats);
  * moved to (s,p). */
 int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats);
 /* The current preconditioner.  P in CSR: rowptr (n+1), col (nnzP), val (nnzP);
- * for PMOR_UPD_PATTERN after an update, val holds P_1 and qval holds Q (same
- * CSR pattern), and the preconditioner is Q P_1; for PMOR_UPD_DIAG, qval (n)
+ * for PMOR_UPD_PATTERN and PMOR_UPD_ADAPTIVE after an update, val holds P_1
+ * and qval holds Q (same CSR pattern; an adaptive column that was not
+ * escalated holds q_i on its diagonal and zeros), and the preconditioner is
+ * Q P_1; for PMOR_UPD_DIAG, qval (n)
  * holds the row scale of P_1 (the last update's q, or with the second approach
  * the product of the q's since the build; ones before any update).  rho (n): per-column
  * least-squares residual of the last build or update.  Any output may be NULL;

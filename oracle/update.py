@@ -117,3 +117,34 @@ def plan_anchors(n, rowptr, col, vals, tol):
             anchors.append(l)
             a = l
     return anchors
+
+
+def update_adaptive(n, rowptr, col, val_1, val_l, pat, ep):
+    """Adaptive pattern of Q (a reading of the paper's adaptive MSPAI pattern):
+    every column first takes the diagonal factor q_i of ``diag_factors``; a
+    column whose misfit ||A(1) e_i - q_i A(l) e_i|| exceeds ep ||A(1) e_i|| is
+    escalated to the SPAI pattern J_i and solved as in ``update_pattern``.
+    Returns (Q values in pat's CSR order, rho per column, escalated columns)."""
+    q = diag_factors(n, rowptr, col, val_1, val_l)
+    colptr, rowidx, slot = transpose_pattern(n, rowptr, col)
+    qv = np.zeros(pat.J_row.size)
+    rho = np.zeros(n)
+    esc = []
+    for i in range(n):
+        s = slot[colptr[i]:colptr[i + 1]]
+        a1 = val_1[s]
+        d = a1 - q[i] * val_l[s]
+        r = float(np.sqrt(d @ d))
+        if not (r <= ep * float(np.sqrt(a1 @ a1))):
+            esc.append(i)
+            continue
+        a, b = pat.J_colptr[i], pat.J_colptr[i + 1]
+        qv[pat.P_slot[a:b][pat.J_row[a:b] == i]] = q[i]
+        rho[i] = r
+    if esc:
+        qe, re = update_pattern(n, rowptr, col, val_1, val_l, pat, columns=esc)
+        for i in esc:
+            a, b = pat.J_colptr[i], pat.J_colptr[i + 1]
+            qv[pat.P_slot[a:b]] = qe[pat.P_slot[a:b]]
+            rho[i] = re[i]
+    return qv, rho, esc

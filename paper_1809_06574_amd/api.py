@@ -111,9 +111,10 @@ class Problem:
         return a.value, b.value
 
     # --- preconditioner / solve ------------------------------------------
-    def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False, approach="first"):
+    def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False, approach="first",
+                   adapt_ep=0.0):
         return Spai(self, s, p, pattern=pattern, precision=precision, update=update, stats=stats,
-                    approach=approach)
+                    approach=approach, adapt_ep=adapt_ep)
 
     def block_solve(self, spai, s, p, B: torch.Tensor, m=30, tol=1e-8, max_cycles=20, X=None, raise_on_error=True):
         n, k = B.shape
@@ -129,14 +130,14 @@ class Problem:
 
     def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
                        pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
-                       raise_on_error=True, approach="first", reanchor_tol=0.0):
+                       raise_on_error=True, approach="first", reanchor_tol=0.0, adapt_ep=0.0):
         n, k = B.shape
         npts = len(p_list)
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
         sl = (C.c_double * npts)(*[float(x) for x in s_list])
         pl = (C.c_double * npts)(*[float(x) for x in p_list])
-        so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach, reanchor_tol)
+        so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach, reanchor_tol, adapt_ep)
         vo = L.SolveOpts(m, max_cycles, tol)
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
@@ -171,11 +172,12 @@ def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_err
     return Xs, [stats[i].as_dict() for i in range(n_it)], [status[i] for i in range(n_it)], rc
 
 
-def _spai_opts(pattern, precision, update, device, keeper, approach="first", reanchor_tol=0.0):
+def _spai_opts(pattern, precision, update, device, keeper, approach="first", reanchor_tol=0.0, adapt_ep=0.0):
     o = L.SpaiOpts()
     o.reanchor_tol = float(reanchor_tol)
+    o.adapt_ep = float(adapt_ep)
     o.precision = {"f64": L.PMOR_F64, "f32": L.PMOR_F32, "f16s": L.PMOR_F16S}[precision]
-    o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN}[update]
+    o.update = {"diag": L.PMOR_UPD_DIAG, "pattern": L.PMOR_UPD_PATTERN, "adaptive": L.PMOR_UPD_ADAPTIVE}[update]
     o.approach = {"first": L.PMOR_APPROACH_FIRST, "second": L.PMOR_APPROACH_SECOND}[approach]
     if pattern is None:
         o.pattern = L.PMOR_PAT_A
@@ -194,11 +196,11 @@ class Spai:
     default; approach="second" anchors each update at the previous point)."""
 
     def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False,
-                 approach="first"):
+                 approach="first", adapt_ep=0.0):
         self.pb = pb
         self.update_kind = update
         self.approach = approach
-        o = _spai_opts(pattern, precision, update, pb.ctx.device, self, approach)
+        o = _spai_opts(pattern, precision, update, pb.ctx.device, self, approach, adapt_ep=adapt_ep)
         h = C.c_void_p()
         st = L.Stats()
         rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), C.byref(st) if stats else None)
@@ -227,7 +229,7 @@ class Spai:
         rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
         ci = torch.empty(self.nnzP, dtype=torch.int32, device=dev)
         va = torch.empty(self.nnzP, dtype=torch.float64, device=dev)
-        qlen = self.nnzP if self.update_kind == "pattern" else n
+        qlen = n if self.update_kind == "diag" else self.nnzP
         qv = torch.empty(qlen, dtype=torch.float64, device=dev)
         rho = torch.empty(n, dtype=torch.float64, device=dev)
         L.check(L.spai_export(self.handle, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), qv.data_ptr(),

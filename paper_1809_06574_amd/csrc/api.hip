@@ -152,6 +152,8 @@ static void spai_release(pmor_spai* h) {
   dfree(h->bucket_cols, s);
   dfree(h->P1val_s, s);
   dfree(h->Qval_s, s);
+  dfree(h->esc_list, s);
+  dfree(h->esc_cnt, s);
   if (h->own_psell) free_sell(&h->psell, s);
   pmor_problem* pb = h->pb;
   delete h;
@@ -438,7 +440,10 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   if (o.pattern != PMOR_PAT_A && o.pattern != PMOR_PAT_EXPLICIT) return fail(PMOR_EINVAL, "bad pattern kind");
   if (o.precision != PMOR_F64 && o.precision != PMOR_F32 && o.precision != PMOR_F16S)
     return fail(PMOR_EINVAL, "bad precision");
-  if (o.update != PMOR_UPD_DIAG && o.update != PMOR_UPD_PATTERN) return fail(PMOR_EINVAL, "bad update kind");
+  if (o.update != PMOR_UPD_DIAG && o.update != PMOR_UPD_PATTERN && o.update != PMOR_UPD_ADAPTIVE)
+    return fail(PMOR_EINVAL, "bad update kind");
+  if (o.update == PMOR_UPD_ADAPTIVE && !(o.adapt_ep >= 0.0 && is_fin(o.adapt_ep)))
+    return fail(PMOR_EINVAL, "adapt_ep must be finite and >= 0");
   if (o.approach != PMOR_APPROACH_FIRST && o.approach != PMOR_APPROACH_SECOND)
     return fail(PMOR_EINVAL, "bad update approach");
   if (o.approach == PMOR_APPROACH_SECOND && o.update != PMOR_UPD_DIAG)
@@ -455,11 +460,15 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
       return dmalloc((void**)p, sizeof(double) * std::max<int64_t>(cnt, 1), pb->ctx->stream) == hipSuccess;
     };
     bool ok = al(&h->Pval, h->nnzP) && al(&h->P1val, h->nnzP) &&
-              al(&h->Qval, o.update == PMOR_UPD_PATTERN ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
+              al(&h->Qval, o.update != PMOR_UPD_DIAG ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
               al(&h->rho, n) && al(&h->red, 512);
     if (ok && h->psell.cap > 0)
       ok = al(&h->P1val_s, h->psell.cap) &&
-           (o.update != PMOR_UPD_PATTERN || al(&h->Qval_s, h->psell.cap));
+           (o.update == PMOR_UPD_DIAG || al(&h->Qval_s, h->psell.cap));
+    if (ok && o.update == PMOR_UPD_ADAPTIVE)
+      ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), pb->ctx->stream) ==
+               hipSuccess &&
+           dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * 8, pb->ctx->stream) == hipSuccess;
     rc = ok ? build_into(h, s, p, stats) : fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
   if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
@@ -485,7 +494,9 @@ int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
     PMOR_TRY(run_update_diag(h, pb->aval, &bad, stats ? &fro2 : nullptr));
     h->d_active = true;
   } else {
-    PMOR_TRY(run_spai_ls(h, pb->aval, h->aval1, h->Qval, &bad, stats ? &fro2 : nullptr));
+    if (h->opts.update == PMOR_UPD_ADAPTIVE)
+      PMOR_TRY(run_update_adaptive(h, pb->aval, h->Qval, &bad, stats ? &fro2 : nullptr, nullptr));
+    else PMOR_TRY(run_spai_ls(h, pb->aval, h->aval1, h->Qval, &bad, stats ? &fro2 : nullptr));
     PMOR_TRY(to_sell(h->psell, h->Qval, h->Qval_s, pb->ctx->stream));
     h->q_active = true;
   }
@@ -522,11 +533,11 @@ int spai_export(const pmor_spai* h, int32_t* rowptr, int32_t* col, double* val, 
   if (rowptr) PMOR_HIP(hipMemcpyAsync(rowptr, h->Prowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
   if (col) PMOR_HIP(hipMemcpyAsync(col, h->Pcol, sizeof(int32_t) * h->nnzP, hipMemcpyDeviceToDevice, s));
   if (val) {
-    const double* src = (h->opts.update == PMOR_UPD_PATTERN) ? h->P1val : h->Pval;
+    const double* src = (h->opts.update != PMOR_UPD_DIAG) ? h->P1val : h->Pval;
     PMOR_HIP(hipMemcpyAsync(val, src, sizeof(double) * h->nnzP, hipMemcpyDeviceToDevice, s));
   }
   if (qval) {
-    const int64_t len = (h->opts.update == PMOR_UPD_PATTERN) ? h->nnzP : n;
+    const int64_t len = (h->opts.update != PMOR_UPD_DIAG) ? h->nnzP : n;
     PMOR_HIP(hipMemcpyAsync(qval, h->Qval, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
   }
   if (rho) PMOR_HIP(hipMemcpyAsync(rho, h->rho, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -826,7 +837,7 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
 static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const double* s_list, const double* p_list,
                           int l0, int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
                           pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
-  if (policy == PMOR_UPDATE && h->opts.update != PMOR_UPD_PATTERN)
+  if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG)
     return prepare_points_diag(pb, h, s_list, p_list, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, items, bad);
   hipStream_t st = pb->ctx->stream;
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
@@ -862,7 +873,9 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
     } else {
       int32_t b = -1;
       double fro2 = 0.0;
-      rc = run_spai_ls(h, Al, policy == PMOR_UPDATE ? h->aval1 : nullptr, PQ, &b, stats ? &fro2 : nullptr);
+      if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_ADAPTIVE)
+        rc = run_update_adaptive(h, Al, PQ, &b, stats ? &fro2 : nullptr, nullptr);
+      else rc = run_spai_ls(h, Al, policy == PMOR_UPDATE ? h->aval1 : nullptr, PQ, &b, stats ? &fro2 : nullptr);
       bad[t] = b;
       fro_host[t] = fro2;
       if (policy == PMOR_UPDATE) {
@@ -1001,7 +1014,7 @@ static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   // points per group: A and P/Q values plus the Krylov blocks of one system
   const int kp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
   // the U-diag update keeps P_l factored: no per-point P values
-  const bool rowq = policy == PMOR_UPDATE && h->opts.update != PMOR_UPD_PATTERN;
+  const bool rowq = policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG;
   const int64_t nnzPp = rowq ? 0 : nnzP, capPp = rowq ? 0 : h->psell.cap;
   // and A(l) only in the sliced ELL layout when it has one
   const int64_t nnzA = (rowq && pb->sell.cap > 0) ? 0 : nnz;
@@ -1120,7 +1133,7 @@ static int64_t job_footprint(const pmor_problem* pb, int npts, bool rowq) {
 
 // the U-diag update policy keeps every P_l factored (no per-point P values)
 static bool rows_scaled(int policy, const pmor_spai_opts& so) {
-  return policy == PMOR_UPDATE && so.update != PMOR_UPD_PATTERN;
+  return policy == PMOR_UPDATE && so.update == PMOR_UPD_DIAG;
 }
 }  // namespace pmor
 

@@ -174,6 +174,8 @@ struct pmor_spai {
   double* P1val = nullptr;   // anchor SPAI P_1
   double* Qval = nullptr;    // U-pattern: Q (P's CSR order); U-diag: q (n)
   double* aval1 = nullptr;   // anchor A(1)
+  int32_t* esc_list = nullptr;  // adaptive update: escalated columns, per bucket at its offset (n)
+  int32_t* esc_cnt = nullptr;   // adaptive update: escalated columns per bucket (8)
   double* rho = nullptr;     // per-column least-squares residuals
   double* red = nullptr;     // reduction scratch
   int32_t* bucket_cols = nullptr;  // columns sorted into buckets
@@ -262,6 +264,10 @@ int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
+// adaptive Q (PMOR_UPD_ADAPTIVE): Q in P's CSR order into qout, residuals into h->rho;
+// *n_esc (may be NULL) = escalated columns
+int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_t* bad_col, double* fro2,
+                        int64_t* n_esc);
 // points of a sequence, at most PTS_MAX per call (s_list, p_list: host arrays of cnt):
 // A(l) into out + l * ostride (CSR order, or the sliced ELL layout of sv when not NULL);
 // the U-diag factors q_l, rho_l (stride n) and the first zero column into bad[l]

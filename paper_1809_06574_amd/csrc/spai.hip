@@ -570,6 +570,108 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive update pattern: every column first takes its U-diag factor q_i;
+// a column whose diagonal misfit ||A(1) e_i - q_i A(l) e_i|| exceeds
+// ep ||A(1) e_i|| (or is not finite) is escalated to the SPAI pattern J_i, the
+// U-pattern least squares with right-hand side A(1) e_i.  Q in P's CSR order: a
+// kept column holds q_i on its diagonal and zeros elsewhere, an escalated
+// column the least-squares values.
+// ---------------------------------------------------------------------------
+__global__ void k_update_adaptive_diag(int n, const int32_t* colptr, const int32_t* cscslot, const double* al,
+                                       const double* a1, double ep, const int32_t* Jcolptr, const int32_t* Jrow,
+                                       const int32_t* Pslot, double* qout, double* rho, int* esc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double num = 0.0, den = 0.0, n11 = 0.0;
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    const double x = al[s], y = a1[s];
+    num += x * y;
+    den += x * x;
+    n11 += y * y;
+  }
+  const double qi = num / den;
+  const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
+  const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+  const bool up = !(r <= ep * sqrt(n11));
+  esc[i] = up ? 1 : 0;
+  rho[i] = up ? 0.0 : r;
+  for (int e = Jcolptr[i]; e < Jcolptr[i + 1]; ++e) qout[Pslot[e]] = (!up && Jrow[e] == i) ? qi : 0.0;
+}
+
+// the escalated columns of a bucket (column list, or 0..cnt-1 when NULL) into
+// out[0..*count); their order follows the atomics, and every column is solved
+// on its own, so the values do not depend on it
+__global__ void k_compact_cols(int cnt, const int32_t* cols, const int* esc, int32_t* out, int* count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const int c = cols ? cols[j] : j;
+  if (esc[c]) out[atomicAdd(count, 1)] = c;
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_t* bad_col, double* fro2,
+                        int64_t* n_esc) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n;
+  int* dbad = reinterpret_cast<int*>(h->red);
+  const int big = 0x7fffffff;
+  PMOR_TRY(set_device_int(dbad, big, st));
+  int* flags = h->esc_list + n;
+  if (n > 0)
+    hipLaunchKernelGGL(k_update_adaptive_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
+                       pb->cscslot, aval_l, h->aval1, h->opts.adapt_ep, h->Jcolptr, h->Jrow, h->Pslot, qout, h->rho,
+                       flags);
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, h->esc_cnt, 8);
+  for (int b = 0; b < 6; ++b) {
+    const int cnt = h->bucket_count[b];
+    if (cnt == 0) continue;
+    const int32_t* cols = h->identity_order ? nullptr : h->bucket_cols + h->bucket_off[b];
+    const int off = h->identity_order ? 0 : h->bucket_off[b];
+    hipLaunchKernelGGL(k_compact_cols, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, cnt, cols, flags,
+                       h->esc_list + off, h->esc_cnt + b);
+  }
+  PMOR_HIP(hipGetLastError());
+  int hc[8] = {0};
+  PMOR_HIP(hipMemcpyAsync(hc, h->esc_cnt, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  int64_t tot = 0;
+  LsArgs a{};
+  a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval_l; a.rhs_aval = h->aval1;
+  a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
+  a.Pslot = h->Pslot; a.out = qout; a.rho = h->rho; a.bad_col = dbad;
+  for (int b = 0; b < 6; ++b) {
+    if (hc[b] == 0) continue;
+    tot += hc[b];
+    a.ncols = hc[b];
+    a.cols = h->esc_list + (h->identity_order ? 0 : h->bucket_off[b]);
+    a.col_off = 0;
+    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0));
+    else if (h->opts.precision == PMOR_F16S)
+      PMOR_TRY((launch_bucket<float, true>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0)));
+    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0));
+  }
+  if (n_esc) *n_esc = tot;
+  if (bad_col || fro2) {
+    double* dsum = h->red + 1;
+    PMOR_TRY(sumsq(h->rho, n, dsum, st));
+    int hbad = big;
+    double hs = 0.0;
+    PMOR_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipMemcpyAsync(&hs, dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));
+    if (bad_col) *bad_col = (hbad == big) ? -1 : hbad;
+    if (fro2) *fro2 = hs;
+  }
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // assembly: a = sum_r c_r T_r on the union pattern (streaming)
 // ---------------------------------------------------------------------------
 struct Coefs {

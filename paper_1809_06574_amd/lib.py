@@ -26,7 +26,7 @@ PMOR_MAX_CYCLES = 64
 ROLES = ("M0", "M1", "D0", "D1", "K0", "K1")
 PMOR_PAT_A, PMOR_PAT_EXPLICIT = 0, 1
 PMOR_F64, PMOR_F32, PMOR_F16S = 0, 1, 2
-PMOR_UPD_DIAG, PMOR_UPD_PATTERN = 0, 1
+PMOR_UPD_DIAG, PMOR_UPD_PATTERN, PMOR_UPD_ADAPTIVE = 0, 1, 2
 PMOR_REBUILD, PMOR_UPDATE = 0, 1
 PMOR_APPROACH_FIRST, PMOR_APPROACH_SECOND = 0, 1
 PROF_KERNELS = {"spmm_a": 1, "cgs_upd_dot": 2, "cgs_dot": 3, "spai_ls": 4, "spmm_p": 5, "cgs_upd_gram": 6}
@@ -40,7 +40,7 @@ class Csr(C.Structure):
 class SpaiOpts(C.Structure):
     _fields_ = [("pattern", C.c_int32), ("precision", C.c_int32), ("update", C.c_int32),
                 ("nnz_explicit", C.c_int32), ("pat_colptr", C.c_void_p), ("pat_row", C.c_void_p),
-                ("approach", C.c_int32), ("reanchor_tol", C.c_double)]
+                ("approach", C.c_int32), ("reanchor_tol", C.c_double), ("adapt_ep", C.c_double)]
 
 
 class SolveOpts(C.Structure):

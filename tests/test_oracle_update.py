@@ -224,3 +224,39 @@ def test_plan_anchors_limits_and_a_jump():
     big = misfit_diag(n, asm.rowptr, asm.col, vals[0], vals[3])
     assert big > 10 * small
     assert plan_anchors(n, asm.rowptr, asm.col, vals, np.sqrt(small * big)) == [0, 3]
+
+
+# ---- adaptive Q pattern (diagonal, escalated to J_i where the diagonal misfits) ----
+
+def test_adaptive_limits_and_monotone_misfit():
+    """ep = inf keeps every column diagonal (Q = diag(q)); ep = 0 escalates
+    every column with a nonzero misfit (Q = the U-pattern Q); in between each
+    column is one of the two, and the escalated columns' residuals are at most
+    their diagonal misfit (J_i holds i, so the diagonal is a candidate of the
+    pattern least squares)."""
+    from oracle.update import update_adaptive
+    job = tiny_random_job(24, 0.15, 46, npts=3)
+    n = job.n
+    asm, pat = _setup(job)
+    v1, vl = asm.values(job.s, job.p_list[0]), asm.values(job.s, job.p_list[2])
+    q = diag_factors(n, asm.rowptr, asm.col, v1, vl)
+    qd, rd, esc = update_adaptive(n, asm.rowptr, asm.col, v1, vl, pat, np.inf)
+    assert esc == []
+    np.testing.assert_array_equal(_dense(n, pat, qd), np.diag(q))
+    qp, rp = update_pattern(n, asm.rowptr, asm.col, v1, vl, pat)
+    qa, ra, esc0 = update_adaptive(n, asm.rowptr, asm.col, v1, vl, pat, 0.0)
+    assert esc0 == [i for i in range(n) if rd[i] > 0] and len(esc0) >= n - 2
+    for i in esc0:
+        a, b = pat.J_colptr[i], pat.J_colptr[i + 1]
+        np.testing.assert_array_equal(qa[pat.P_slot[a:b]], qp[pat.P_slot[a:b]])
+        assert ra[i] == rp[i]
+    assert np.all(rp <= rd * (1 + 1e-12) + 1e-15)
+    ratios = rd / np.array([np.linalg.norm(to_dense(n, asm.rowptr, asm.col, v1)[:, i]) for i in range(n)])
+    ep = float(np.median(ratios))
+    qm, rm, escm = update_adaptive(n, asm.rowptr, asm.col, v1, vl, pat, ep)
+    assert 0 < len(escm) < n and set(escm) == set(np.nonzero(ratios > ep)[0].tolist())
+    for i in range(n):
+        a, b = pat.J_colptr[i], pat.J_colptr[i + 1]
+        src = qp if i in escm else qd
+        np.testing.assert_array_equal(qm[pat.P_slot[a:b]], src[pat.P_slot[a:b]])
+    assert np.sqrt(np.sum(rp ** 2)) <= np.sqrt(np.sum(rm ** 2)) <= np.sqrt(np.sum(rd ** 2))
