@@ -1,6 +1,7 @@
 """MI355X (gfx950) library for preconditioned parametric linear solves.
 
-SPAI preconditioner, its cheap first-approach update and block GMRES for the
+SPAI preconditioner, its cheap update (first approach by default; the second
+approach, an adaptive Q pattern and re-anchoring as options) and block GMRES for the
 sequences A(s, p_j) X = B of parametric model order reduction (Singh & Ahuja,
 "Preconditioned Linear Solves for Parametric Model Order Reduction").
 

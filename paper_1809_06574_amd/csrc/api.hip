@@ -829,7 +829,7 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
 
 // Points [l0, l0 + cnt) of a sequence whose P_1 (point 0) is h's anchor: A(l)
 // into sb.aval + t nnz, the point's preconditioner (P_1 for point 0, else the
-// first-approach update or, for the rebuild policy, a fresh SPAI) into
+// update (Table 1, as the handle's options say) or, for the rebuild policy, a fresh SPAI) into
 // sb.pq + t nnzP, and the engine item of every point.  bad[t]: a singular
 // column of the point's least-squares problems, or -1.  stats (the sequence's
 // array, may be NULL) gets the assembly and preconditioner times, the residual
