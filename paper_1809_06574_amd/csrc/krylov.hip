@@ -1215,14 +1215,18 @@ struct SpArgs {
   int linear;           // take workgroups in launch order (else the per-XCD remap)
 };
 
-constexpr int SP_ROWS = 64;  // rows per SpMM workgroup (64 LPR threads)
+// rows per SpMM workgroup: 128 for kp <= 4 (a row's X is at most 32 bytes, and
+// twice the rows per workgroup keep more of the gathered rows in its CU's L1),
+// 64 for kp 8 and 16
+template <int KP>
+constexpr int sp_rows() { return KP <= 4 ? 128 : 64; }
 // SpMM variants of the batched engine: 1, 2, 4, 8 lanes per row taking the
 // row's entries in turn (k_spmm_seg), or the column split (k_spmm_cs)
 constexpr int SPMM_COLSPLIT = 16;
 static bool spmm_variant_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == SPMM_COLSPLIT; }
 
 template <int KP, int LPR, bool CONV>
-__global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
+__global__ __launch_bounds__(sp_rows<KP>() * LPR) void k_spmm_seg(SpArgs a) {
   const int lg = a.linear ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, gridDim.x);
   const int s = a.stab[lg];
   if (s < 0) return;
@@ -1261,7 +1265,7 @@ __global__ __launch_bounds__(64 * LPR) void k_spmm_seg(SpArgs a) {
   const int64_t base = d.r0 * KP;
   const double* X = a.X + base;
   Y += base;
-  const int local = (lg - d.sp0) * SP_ROWS + (int)threadIdx.x / LPR;
+  const int local = (lg - d.sp0) * sp_rows<KP>() + (int)threadIdx.x / LPR;
   const int sub = (int)threadIdx.x % LPR;
   const bool valid = local < d.n;
   double acc[KP];
@@ -1464,7 +1468,7 @@ struct CsShape {
 };
 
 template <int KP, bool CONV>
-__global__ __launch_bounds__(64 * CsShape<KP>::L) void k_spmm_cs(SpArgs a) {
+__global__ __launch_bounds__(sp_rows<KP>() * CsShape<KP>::L) void k_spmm_cs(SpArgs a) {
   constexpr int L = CsShape<KP>::L, C = CsShape<KP>::C, R = CsShape<KP>::R, EB = L * R;
   const int lg = a.linear ? (int)blockIdx.x : xcd_swizzle(blockIdx.x, gridDim.x);
   const int s = a.stab[lg];
@@ -1499,7 +1503,7 @@ __global__ __launch_bounds__(64 * CsShape<KP>::L) void k_spmm_cs(SpArgs a) {
   const int64_t base = d.r0 * KP;
   const double* X = a.X + base;
   Y += base;
-  const int local = (lg - d.sp0) * SP_ROWS + (int)threadIdx.x / L;
+  const int local = (lg - d.sp0) * sp_rows<KP>() + (int)threadIdx.x / L;
   const int sub = (int)threadIdx.x % L;
   const int g0 = ((int)threadIdx.x & 63) - sub;  // first lane of the row's group
   // every lane of a group shares `local`, so groups are wholly valid or not
@@ -2161,14 +2165,15 @@ static void launch_spmm_seg(pmor_ctx* c, int pidx, int part, unsigned grid, int 
                             const SpArgs& a0) {
   SpArgs a = a0;
   a.linear = grid >= SPMM_LINEAR_MIN ? 1 : 0;
+  constexpr int R = sp_rows<KP>();
   switch (lpr) {
     case SPMM_COLSPLIT:
-      plaunch(c, pidx, part, k_spmm_cs<KP, CONV>, dim3(grid), dim3(64 * CsShape<KP>::L), 0, s, a);
+      plaunch(c, pidx, part, k_spmm_cs<KP, CONV>, dim3(grid), dim3(R * CsShape<KP>::L), 0, s, a);
       break;
-    case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(64 * 1), 0, s, a); break;
-    case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(64 * 4), 0, s, a); break;
-    case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(64 * 8), 0, s, a); break;
-    default: plaunch(c, pidx, part, k_spmm_seg<KP, 2, CONV>, dim3(grid), dim3(128), 0, s, a); break;
+    case 1: plaunch(c, pidx, part, k_spmm_seg<KP, 1, CONV>, dim3(grid), dim3(R * 1), 0, s, a); break;
+    case 4: plaunch(c, pidx, part, k_spmm_seg<KP, 4, CONV>, dim3(grid), dim3(R * 4), 0, s, a); break;
+    case 8: plaunch(c, pidx, part, k_spmm_seg<KP, 8, CONV>, dim3(grid), dim3(R * 8), 0, s, a); break;
+    default: plaunch(c, pidx, part, k_spmm_seg<KP, 2, CONV>, dim3(grid), dim3(R * 2), 0, s, a); break;
   }
 }
 
@@ -2192,7 +2197,7 @@ class RunnerT final : public Runner {
       : ctx_(c), E_(*e), o_(o), rows_cap_((rows_cap + 15) / 16 * 16), nslots_(nslots) {}
 
   int init() {
-    sp_rows_ = SP_ROWS;
+    sp_rows_ = sp_rows<KP>();
     const int64_t wg_cap = rows_cap_ / (2 * F::ROWS) + nslots_ + 8;
     const int64_t sp_cap = rows_cap_ / sp_rows_ + nslots_ + 8;
     PMOR_TRY(engine_reserve(E_, KP, o_.m, std::max<int64_t>(rows_cap_, 16), nslots_, wg_cap,
@@ -2649,7 +2654,7 @@ class RunnerT final : public Runner {
   pmor_solve_opts o_;
   int64_t rows_cap_;
   int nslots_;
-  int sp_rows_ = SP_ROWS;
+  int sp_rows_ = 64;
   int lprA_ = 0, lprP_ = 0;  // SpMM lanes per row for A and for the preconditioner
   size_t hess_shm_ = 0, ys_shm_ = 0;
   int ys_pw_ = 32;
