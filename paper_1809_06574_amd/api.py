@@ -265,9 +265,9 @@ class Server:
     """Continuous batching of sequence jobs over one persistent engine (pmor_server_*)."""
 
     def __init__(self, ctx: Context, k: int, hbm_budget: int = 0, engine_rows: int = 0, max_systems: int = 0,
-                 update="diag", precision="f64", m=30, tol=1e-8, max_cycles=20):
+                 update="diag", precision="f64", m=30, tol=1e-8, max_cycles=20, approach="first", adapt_ep=0.0):
         self.ctx = ctx
-        so = _spai_opts(None, precision, update, ctx.device, self)
+        so = _spai_opts(None, precision, update, ctx.device, self, approach, adapt_ep=adapt_ep)
         vo = L.SolveOpts(m, max_cycles, tol)
         opts = L.ServerOpts(int(hbm_budget), int(engine_rows), int(k), int(max_systems))
         h = C.c_void_p()

@@ -120,3 +120,22 @@ def test_budget_admits_one_job_at_a_time(ctx):
         sv.submit(pb_big, Bb, [2.0] * 3, [0.1, 0.2, 0.3])
     assert e.value.code == L.PMOR_EADMIT
     sv.close()
+
+
+@pytest.mark.parametrize("kind", [{"update": "pattern"}, {"update": "adaptive", "adapt_ep": 0.02},
+                                  {"approach": "second"}])
+def test_served_update_variants_match_sequence_solve(ctx, kind):
+    """The U-pattern and adaptive updates and the second approach through the
+    server: every job bit for bit its pmor_sequence_solve result."""
+    from paper_1809_06574_amd import Problem
+    jobs = [_job(q) for q in (1, 2, 4)]
+    mix = _serve(ctx, jobs, submit_at=[0, 0, 2], policy="update", max_systems=12, **kind)
+    for q, job in enumerate(jobs):
+        status, X, stats = mix[q]
+        assert status == 0, (q, status)
+        _check_residuals(job, X)
+        pb = Problem(ctx, job.terms)
+        B = torch.as_tensor(job.B, device="cuda")
+        Xs, _ = pb.sequence_solve(B, [job.s] * len(job.p_list), job.p_list, policy="update", **kind)
+        assert torch.equal(Xs, X), (q, kind)
+        pb.close()
