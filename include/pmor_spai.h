@@ -101,10 +101,16 @@ typedef struct pmor_csr {
   const double* val;     /* nnz */
 } pmor_csr;
 
+/* Options of a preconditioner (spai_build) and of the sequence and server
+ * calls.  A zero-filled struct selects the defaults of each field (pattern of
+ * A, FP64, U-diag, first approach, no re-anchoring).  PMOR_EINVAL for values
+ * outside the ranges below, for the second approach or re-anchoring with
+ * another update kind, and for re-anchoring outside pmor_sequence_solve. */
 typedef struct pmor_spai_opts {
   int32_t pattern;            /* PMOR_PAT_A or PMOR_PAT_EXPLICIT                */
   int32_t precision;          /* PMOR_F64, PMOR_F32 or PMOR_F16S                */
-  int32_t update;             /* PMOR_UPD_DIAG or PMOR_UPD_PATTERN              */
+  int32_t update;             /* PMOR_UPD_DIAG, PMOR_UPD_PATTERN or             */
+                              /* PMOR_UPD_ADAPTIVE                               */
   int32_t nnz_explicit;       /* entries of the explicit pattern                */
   const int32_t* pat_colptr;  /* device, n+1; column j of P may hold rows       */
   const int32_t* pat_row;     /* pat_row[pat_colptr[j]..pat_colptr[j+1]), sorted,*/
