@@ -966,6 +966,7 @@ static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_
     PMOR_TRY(sumsq(Aa, nnz, nrm, st));
     double na2 = 0.0;
     PMOR_HIP(hipMemcpyAsync(&na2, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));  // na2 is read below; no copy into it may outlive an early return
     int found = -1;
     for (int c0 = l; c0 < npts && found < 0; c0 += PTS_MAX) {
       const int m = std::min(PTS_MAX, npts - c0);
