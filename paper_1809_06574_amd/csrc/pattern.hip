@@ -121,55 +121,90 @@ struct TermPtrs {
 };
 
 // Walks the sorted column lists of row i of every present term and the diagonal,
-// visiting each distinct column once in ascending order.
-template <bool FILL>
-__global__ void k_union(int n, TermPtrs t, int64_t* counts, const int32_t* rowptr_out, int32_t* col_out,
-                        int32_t* maps, double* tval, int64_t nnz_out, int* maxlen) {
+// visiting each distinct column once in ascending order: counts[i] = the
+// number of distinct columns, maxlen = the longest row.
+__global__ void k_union_count(int n, TermPtrs t, int64_t* counts, int* maxlen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (i < n) {
-    // cursors and the column at each cursor (INT_MAX once a list is done)
     int cur[PMOR_NROLES], end[PMOR_NROLES], head[PMOR_NROLES];
 #pragma unroll
     for (int r = 0; r < PMOR_NROLES; ++r) {
-      cur[r] = 0;
-      end[r] = 0;
-      if (t.present[r]) {
-        cur[r] = t.rowptr[r][i];
-        end[r] = t.rowptr[r][i + 1];
-      }
+      cur[r] = t.present[r] ? t.rowptr[r][i] : 0;
+      end[r] = t.present[r] ? t.rowptr[r][i + 1] : 0;
+      head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
     }
-#pragma unroll
-    for (int r = 0; r < PMOR_NROLES; ++r) head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
     bool diag_done = false;
-    const int64_t pos0 = FILL ? rowptr_out[i] : 0;
     while (true) {
       int cmin = diag_done ? 0x7fffffff : i;
 #pragma unroll
       for (int r = 0; r < PMOR_NROLES; ++r) cmin = min(cmin, head[r]);
       if (cmin == 0x7fffffff) break;
       if (cmin == i) diag_done = true;
-      const int64_t pos = pos0 + cnt;
-      if (FILL) col_out[pos] = cmin;
 #pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r) {
-        const bool hit = head[r] == cmin;
-        if (FILL) {
-          maps[(int64_t)r * nnz_out + pos] = hit ? cur[r] : -1;
-          if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + pos] = hit ? t.val[r][cur[r]] : 0.0;
-        }
-        if (hit) {
+      for (int r = 0; r < PMOR_NROLES; ++r)
+        if (head[r] == cmin) {
           ++cur[r];
           head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
         }
-      }
       ++cnt;
     }
-    if (!FILL) counts[i] = cnt;
+    counts[i] = cnt;
   }
-  if (!FILL) {
-    for (int o = 32; o >= 1; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxlen, cnt);
+  for (int o = 32; o >= 1; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxlen, cnt);
+}
+
+// One thread per entry of the union pattern: entry e is the k-th distinct
+// column of its row r (the same walk as k_union_count, stopped at the k-th
+// column), so the outputs (columns, the slot maps of every role, the term
+// values on the union pattern) leave as coalesced stores.  A row holds a few
+// entries, so each thread's walk is short.
+// row_of[e] = the row of entry e
+__global__ void k_row_of(int n, const int32_t* __restrict__ rowptr, int32_t* __restrict__ row_of) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) row_of[e] = i;
+}
+
+__global__ void k_union_fill(int n, TermPtrs t, const int32_t* __restrict__ rowptr_out,
+                             const int32_t* row_of, int64_t nnz_out, int32_t* col_out, int32_t* maps,
+                             double* tval) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz_out;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = row_of[e];
+    const int k = (int)(e - rowptr_out[i]);
+    int cur[PMOR_NROLES], end[PMOR_NROLES], head[PMOR_NROLES];
+#pragma unroll
+    for (int r = 0; r < PMOR_NROLES; ++r) {
+      cur[r] = t.present[r] ? t.rowptr[r][i] : 0;
+      end[r] = t.present[r] ? t.rowptr[r][i + 1] : 0;
+      head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
+    }
+    bool diag_done = false;
+    for (int cnt = 0;; ++cnt) {
+      int cmin = diag_done ? 0x7fffffff : i;
+#pragma unroll
+      for (int r = 0; r < PMOR_NROLES; ++r) cmin = min(cmin, head[r]);
+      if (cmin == 0x7fffffff) break;  // not reached for k < the row's length
+      if (cmin == i) diag_done = true;
+      if (cnt == k) {
+        col_out[e] = cmin;
+#pragma unroll
+        for (int r = 0; r < PMOR_NROLES; ++r) {
+          const bool hit = head[r] == cmin;
+          maps[(int64_t)r * nnz_out + e] = hit ? cur[r] : -1;
+          if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + e] = hit ? t.val[r][cur[r]] : 0.0;
+        }
+        break;
+      }
+#pragma unroll
+      for (int r = 0; r < PMOR_NROLES; ++r)
+        if (head[r] == cmin) {
+          ++cur[r];
+          head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
+        }
+    }
   }
 }
 
@@ -290,8 +325,7 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   int64_t* cnt = nullptr;
   PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
   unsigned g = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_union<false>, dim3(g), dim3(256), 0, st, n, tp, cnt, nullptr, nullptr, nullptr, nullptr,
-                     (int64_t)0, derr + 1);
+  hipLaunchKernelGGL(k_union_count, dim3(g), dim3(256), 0, st, n, tp, cnt, derr + 1);
   PMOR_HIP(hipGetLastError());
   PMOR_TRY(scan_exclusive(cnt, n, st));
   int64_t nnz64 = 0;
@@ -314,8 +348,13 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, cnt, pb->rowptr,
                      (int64_t)n + 1);
   PMOR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_union<true>, dim3(g), dim3(256), 0, st, n, tp, nullptr, pb->rowptr, pb->col, pb->maps,
-                     pb->tval, nnz, nullptr);
+  if (nnz > 0) {
+    // the row of every entry goes into pb->col first (each fill thread reads its
+    // own entry's row there before it writes the column)
+    hipLaunchKernelGGL(k_row_of, dim3(g), dim3(256), 0, st, n, pb->rowptr, pb->col);
+    hipLaunchKernelGGL(k_union_fill, dim3((unsigned)std::min<int64_t>((nnz + 255) / 256, 65536)), dim3(256), 0, st,
+                       n, tp, pb->rowptr, pb->col, nnz, pb->col, pb->maps, pb->tval);
+  }
   PMOR_HIP(hipGetLastError());
   PMOR_HIP(hipStreamSynchronize(st));
   dfree(cnt, st);
