@@ -10,7 +10,8 @@ Parametric Model Order Reduction"):
                 column (Section 2.2), solved by Householder QR.
 * ``update``    the cheap SPAI update, first approach: min ||A(1) - A(l) Q||_F,
                 P_l = Q P_1 (Section 2.3, Table 1; Section 2.4); second approach
-                as an ablation (Table 1, right column).
+                as an ablation (Table 1, right column); the adaptive Q pattern
+                and the re-anchoring plan (readings where the paper is silent).
 * ``gmres``     block GMRES(m) with right preconditioning (Section 2.1 and its
                 footnote on right preconditioning).
 * ``diagnostics`` the norms of Table 2 and ||I - A P||_F.
