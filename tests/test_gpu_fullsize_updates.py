@@ -1,13 +1,15 @@
 """The update options at the full grid size (64^3, n = 262144, k = 4, 20 points),
 solved as the benchmark's comparison runs solve them (pmor_sequence_solve,
-update policy, all points together): the second approach of Table 1 and the
-adaptive Q pattern.
+update policy, all points together): the second approach of Table 1, the
+adaptive Q pattern and re-anchoring.
 
 Bars: every column of every point at true relative residual <= 1e-8; the
 second approach's running row scale and P_l after three chained updates
 within 1e-12 relative of the oracle's literal chain diag(q_l) P_{l-1} (the
 library keeps diag(q_l ... q_2) P_1: the same factors in another rounding
-order); the adaptive run's per-point stats in the same form as the U-diag run.
+order); the adaptive run's per-point stats in the same form as the U-diag run;
+the re-anchoring plan equal to the oracle's, each run between anchors bit for
+bit the same points solved as a sequence of their own.
 """
 import numpy as np
 import pytest
@@ -16,7 +18,7 @@ import torch
 from synth import config1
 from oracle.assemble import Assembled
 from oracle.spai import SpaiPattern
-from oracle.update import second_approach_diag
+from oracle.update import plan_anchors, second_approach_diag
 from oracle.sparse import to_scipy
 from tests._helpers import np_, col_rel_err
 
@@ -78,3 +80,31 @@ def test_c1_adaptive_true_residual_every_point(c1):
     torch.cuda.synchronize()
     _check_residuals(job, asm, np_(X))
     assert all(st["cycles"] >= 1 and st["k"] == job.B.shape[1] for st in stats)
+
+
+def test_c1_reanchoring_first_eight_points(c1):
+    """Re-anchoring on the grid job's first 8 points: the U-diag misfit grows by
+    about 8.7e-4 per point, so tol = 3e-3 keeps points 1..3 on anchor 0 (misfit
+    <= 2.6e-3) and re-anchors at point 4 (3.5e-3); the oracle's plan decides."""
+    job, asm, pb, B = c1
+    ps = list(job.p_list[:8])
+    tol = 3e-3
+    vals = [asm.values(job.s, p) for p in ps]
+    plan = plan_anchors(job.n, asm.rowptr, asm.col, vals, tol)
+    assert plan == [0, 4]
+    X, st = pb.sequence_solve(B, [job.s] * len(ps), ps, policy="update", reanchor_tol=tol)
+    torch.cuda.synchronize()
+    assert [s["anchor"] for s in st] == [0] * 4 + [4] * 4
+    for a, b in ((0, 4), (4, 8)):
+        Xr, sr = pb.sequence_solve(B, [job.s] * (b - a), ps[a:b], policy="update")
+        for t in range(b - a):
+            assert torch.equal(Xr[t], X[a + t]), (a, t)
+            assert sr[t]["cycle_steps"] == st[a + t]["cycle_steps"]
+            if t > 0:
+                assert st[a + t]["fro_resid"] / np.linalg.norm(vals[a]) <= tol
+    bn = np.linalg.norm(job.B, axis=0)
+    Xh = np_(X)
+    for l, p in enumerate(ps):
+        A = to_scipy(job.n, asm.rowptr, asm.col, vals[l])
+        rel = np.linalg.norm(job.B - A @ Xh[l], axis=0) / bn
+        assert np.all(rel <= 1e-8 * 1.0001), (l, rel)
