@@ -1,7 +1,7 @@
 """The update options at the full grid size (64^3, n = 262144, k = 4, 20 points),
 solved as the benchmark's comparison runs solve them (pmor_sequence_solve,
-update policy, all points together): the second approach of Table 1, the
-adaptive Q pattern and re-anchoring.
+update policy, all points together): the U-pattern update, the second
+approach of Table 1, the adaptive Q pattern and re-anchoring.
 
 Bars: every column of every point at true relative residual <= 1e-8; the
 second approach's running row scale and P_l after three chained updates
@@ -18,7 +18,7 @@ import torch
 from synth import config1
 from oracle.assemble import Assembled
 from oracle.spai import SpaiPattern
-from oracle.update import plan_anchors, second_approach_diag
+from oracle.update import plan_anchors, second_approach_diag, update_pattern
 from oracle.sparse import to_scipy
 from tests._helpers import np_, col_rel_err
 
@@ -108,3 +108,31 @@ def test_c1_reanchoring_first_eight_points(c1):
         A = to_scipy(job.n, asm.rowptr, asm.col, vals[l])
         rel = np.linalg.norm(job.B - A @ Xh[l], axis=0) / bn
         assert np.all(rel <= 1e-8 * 1.0001), (l, rel)
+
+
+def test_c1_pattern_update_sampled_columns_and_residuals(c1):
+    """U-pattern Q of the last point against the first: sampled columns (grid
+    corners and random ones) within 1e-10 of the oracle's column solves, their
+    least-squares residuals within 1e-9; the 20-point sequence with the
+    U-pattern update at residual <= 1e-8 everywhere."""
+    job, asm, pb, B = c1
+    n = job.n
+    pat = SpaiPattern(n, asm.rowptr, asm.col)
+    v1, vl = asm.values(job.s, job.p_list[0]), asm.values(job.s, job.p_list[-1])
+    h = pb.spai_build(job.s, job.p_list[0], update="pattern")
+    h.update(job.s, job.p_list[-1])
+    exp = h.export()
+    rng = np.random.default_rng(2027)
+    cols = np.unique(np.concatenate([[0, 63, 4095, 4096 * 63, n - 1], rng.integers(0, n, 160)]))
+    qv, rho = update_pattern(n, asm.rowptr, asm.col, v1, vl, pat, columns=[int(c) for c in cols])
+    gq, grho = np_(exp["q"]), np_(exp["rho"])
+    worst = 0.0
+    for j in cols:
+        s = pat.P_slot[pat.J_colptr[j]:pat.J_colptr[j + 1]]
+        worst = max(worst, np.linalg.norm(gq[s] - qv[s]) / np.linalg.norm(qv[s]))
+    assert worst <= 1e-10, worst
+    np.testing.assert_allclose(grho[cols], rho[cols], rtol=1e-9, atol=1e-14)
+    h.close()
+    X, stats = pb.sequence_solve(B, [job.s] * len(job.p_list), job.p_list, policy="update", update="pattern")
+    torch.cuda.synchronize()
+    _check_residuals(job, asm, np_(X))
