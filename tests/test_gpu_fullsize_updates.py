@@ -1,7 +1,8 @@
 """The update options at the full grid size (64^3, n = 262144, k = 4, 20 points),
 solved as the benchmark's comparison runs solve them (pmor_sequence_solve,
 update policy, all points together): the U-pattern update, the second
-approach of Table 1, the adaptive Q pattern and re-anchoring.
+approach of Table 1, the adaptive Q pattern, re-anchoring and the least
+squares in FP32 and FP16s.
 
 Bars: every column of every point at true relative residual <= 1e-8; the
 second approach's running row scale and P_l after three chained updates
@@ -136,3 +137,38 @@ def test_c1_pattern_update_sampled_columns_and_residuals(c1):
     X, stats = pb.sequence_solve(B, [job.s] * len(job.p_list), job.p_list, policy="update", update="pattern")
     torch.cuda.synchronize()
     _check_residuals(job, asm, np_(X))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_c1_least_squares_precisions(c1, prec):
+    """The C1 job with the SPAI least squares in FP32 or FP16s (the precision
+    comparison the benchmark runs): sampled columns of P_1 against the FP64
+    oracle (FP32 within 1e-4 relative; FP16s under rho_gpu <= 1.05 rho + 1e-3),
+    and the 20-point sequence at residual <= 1e-8 with X within 1e-6 of the
+    FP64 run."""
+    from oracle.spai import solve_column
+    job, asm, pb, B = c1
+    n = job.n
+    pat = SpaiPattern(n, asm.rowptr, asm.col)
+    val = asm.values(job.s, job.p_list[0])
+    h = pb.spai_build(job.s, job.p_list[0], precision=prec)
+    exp = h.export()
+    gv, grho = np_(exp["val"]), np_(exp["rho"])
+    rng = np.random.default_rng(2028)
+    cols = np.unique(np.concatenate([[0, 63, 4095, 4096 * 63, n - 1], rng.integers(0, n, 100)]))
+    worst = 0.0
+    for j in cols:
+        x, rho = solve_column(n, asm.rowptr, asm.col, val, pat, int(j))
+        s = pat.P_slot[pat.J_colptr[j]:pat.J_colptr[j + 1]]
+        worst = max(worst, np.linalg.norm(gv[s] - x) / np.linalg.norm(x))
+        assert grho[j] <= 1.05 * rho + 1e-3, (j, grho[j], rho)
+    if prec == "f32":
+        assert worst <= 1e-4, worst
+    h.close()
+    s_list = [job.s] * len(job.p_list)
+    X, _ = pb.sequence_solve(B, s_list, job.p_list, policy="update", precision=prec)
+    X64, _ = pb.sequence_solve(B, s_list, job.p_list, policy="update")
+    torch.cuda.synchronize()
+    Xh, X64h = np_(X), np_(X64)
+    _check_residuals(job, asm, Xh)
+    assert np.linalg.norm(Xh - X64h) / np.linalg.norm(X64h) <= 1e-6
