@@ -171,7 +171,7 @@ def test_block_solve_config0_all_points(ctx):
         assert st["cycles"] >= 1 and st["steps"] <= 30
 
 
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8, 13, 16])
 def test_block_solve_block_sizes(ctx, k):
     job = tiny_random_job(700, 0.006, 50 + k, k=k)
     _solve_and_check(ctx, job, p_idx=1, m=20)
@@ -361,3 +361,47 @@ def test_sequence_solve_policies(ctx):
             A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(1.0, p))
             rel = np.linalg.norm(job.B - A @ np_(X[l]), axis=0) / np.linalg.norm(job.B, axis=0)
             assert np.all(rel <= 1e-8), (policy, l, rel)
+
+
+def test_empty_and_out_of_range_arguments(ctx):
+    """Empty and out-of-range inputs: no points, k = 0 or above 16, a leading
+    dimension below k, a non-finite s, a preconditioner of another problem are
+    rejected with PMOR_EINVAL before any work; an empty batch is a no-op."""
+    import ctypes as C
+    from paper_1809_06574_amd import Problem
+    from paper_1809_06574_amd import lib as L
+    job = tiny_random_job(40, 0.1, 3)
+    pb = Problem(ctx, job.terms)
+    pb2 = Problem(ctx, job.terms)
+    h = pb.spai_build(job.s, job.p_list[0])
+    B = torch.as_tensor(np.ascontiguousarray(job.B), device="cuda")
+    X = torch.zeros_like(B)
+    so = L.SolveOpts(30, 20, 1e-8)
+    st = L.Stats()
+
+    def solve(hh, s, k, ldb, ldx):
+        return L.block_solve(pb.handle, hh, s, 0.5, B.data_ptr(), ldb, k, X.data_ptr(), ldx, C.byref(so),
+                             C.byref(st))
+
+    for k in (0, 17, -1):
+        assert solve(h.handle, job.s, k, max(k, 1), max(k, 1)) == L.PMOR_EINVAL, k
+    assert solve(h.handle, job.s, 2, 1, 2) == L.PMOR_EINVAL
+    assert solve(h.handle, float("nan"), 2, 2, 2) == L.PMOR_EINVAL
+    assert solve(h.handle, float("inf"), 2, 2, 2) == L.PMOR_EINVAL
+    h2 = pb2.spai_build(job.s, job.p_list[0])
+    assert solve(h2.handle, job.s, 2, 2, 2) == L.PMOR_EINVAL
+    # a sequence of no points
+    sl = (C.c_double * 1)(job.s)
+    vo = L.SolveOpts(30, 20, 1e-8)
+    rc = L.pmor_sequence_solve(pb.handle, B.data_ptr(), 2, 2, sl, sl, 0, X.data_ptr(), 2, L.PMOR_UPDATE, None,
+                               C.byref(vo), None)
+    assert rc == L.PMOR_EINVAL
+    # an empty batch
+    assert L.pmor_batch_solve(ctx.handle, None, 0, C.byref(vo), None, None) == L.PMOR_OK
+    assert L.pmor_batch_solve(ctx.handle, None, -1, C.byref(vo), None, None) == L.PMOR_EINVAL
+    # nothing was written, and the library still solves afterwards
+    assert torch.count_nonzero(X).item() == 0
+    Xs, sts, rc = pb.block_solve(h, job.s, job.p_list[0], B)
+    assert rc == L.PMOR_OK
+    for x in (h, h2, pb, pb2):
+        x.close()
