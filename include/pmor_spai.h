@@ -51,7 +51,7 @@ extern "C" {
 #define PMOR_EINVAL (-1)     /* invalid argument or malformed CSR              */
 #define PMOR_ENOMEM (-2)     /* device allocation failed                       */
 #define PMOR_ENOTCONV (-3)   /* max cycles reached; X holds the last iterate   */
-#define PMOR_EBREAKDOWN (-4) /* rank-deficient block with unconverged columns  */
+#define PMOR_EBREAKDOWN (-4) /* dependent residual block at a cycle start      */
 #define PMOR_ESINGULAR (-5)  /* a local least-squares problem is rank deficient*/
 #define PMOR_ENAN (-6)       /* NaN or Inf met in a residual                   */
 #define PMOR_EHIP (-7)       /* HIP runtime error (text in pmor_last_error)    */
@@ -161,7 +161,9 @@ int pmor_ctx_create(pmor_ctx** out, int device, void* hip_stream);
  * once the release has completed on the device); a failed allocation empties
  * the cache and retries. */
 void pmor_ctx_destroy(pmor_ctx* ctx);
-/* Re-point the context at another stream of the same device. */
+/* Re-point the context at another stream of the same device.  Synchronises the
+ * old stream first, so work queued there (and device memory released on it)
+ * is complete before anything is ordered on the new one. */
 int pmor_ctx_set_stream(pmor_ctx* ctx, void* hip_stream);
 
 /* ---- problem (one parametric system, Section 1.1 eq. (1)) ---------------- */
@@ -231,9 +233,17 @@ void spai_free(pmor_spai* h);
  * row-major device blocks (k in 1..PMOR_KMAX); B is not modified.  Columns of
  * B that are zero get X = 0.  Converged when every column reaches
  * ||b_c - A x_c|| <= tol ||b_c||.  opts NULL: m = 30, tol = 1e-8,
- * max_cycles = 20.  Returns PMOR_ENOTCONV (X = last iterate),
- * PMOR_EBREAKDOWN, or PMOR_ENAN (NaN/Inf in B: X = 0; in a residual: X = last
- * iterate) on failure.  Synchronises the stream. */
+ * max_cycles = 20.  Dependent columns (the paper assumes a block Krylov space
+ * of full dimension, Section 2.1): a block whose thin QR Y = Q S has a column
+ * with S_cc <= 1e-6 ||y_c|| (within that sine of the span of the columns
+ * before it) is dependent.  At a cycle start (Y the residual block, e.g. two
+ * equal columns of B) the solve ends with PMOR_EBREAKDOWN and X = the last
+ * iterate.  In a block step (Y the new block after Gram-Schmidt, also
+ * deficient when S_cc <= 1e-14 max ||W_c|| before Gram-Schmidt) the cycle ends
+ * there, its least-squares solution updates X and the solve restarts.
+ * Returns PMOR_ENOTCONV (X = last iterate), PMOR_EBREAKDOWN, or PMOR_ENAN
+ * (NaN/Inf in B: X = 0; in a residual: X = last iterate) on failure.
+ * Synchronises the stream. */
 int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p,
                 const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
                 const pmor_solve_opts* opts, pmor_stats* stats);

@@ -18,9 +18,24 @@ here.  Steps, in order:
 4. X = X + P [V_1..V_j] Y_j and go to 1 (a restart) unless converged.
 
 Zero columns of B have the solution 0 and are left out of the block.
-A QR pivot |R_cc| <= 1e-14 max_c ||W_c|| marks a rank-deficient block; the
-cycle then takes H_{j+1,j} = 0 and stops, and the solve reports a breakdown if
-the least-squares residual is not yet below the tolerance.
+
+Dependent columns (the paper is silent; Section 2.1 only assumes the block
+Krylov space has full dimension).  For a block Y with thin QR Y = Q S, the
+ratio |S_cc| / ||y_c|| is the sine of the angle between column c and the span
+of the columns before it.
+* Cycle start: when a column of the residual block has a sine <= DEP_SINE
+  (1e-6), the block is dependent (an exact or near duplicate right-hand side
+  column, say).  Restarting cannot change that, so the solve stops with a
+  breakdown and X keeps its current value, unless every column has already
+  converged.  DEP_SINE sits well above the sine that Cholesky QR in FP64 can
+  still resolve (about 1e-7 for blocks of up to 2^22 rows), so a solver using
+  the Gram matrix and one using Householder reach the same verdict.
+* Block step: the new block W (after Gram-Schmidt) is deficient when a column
+  has a sine <= DEP_SINE, or |S_cc| <= 1e-14 max_c ||W_c|| with the norms
+  taken before Gram-Schmidt (the block Krylov space stopped growing in that
+  direction, e.g. a right-hand side inside an invariant subspace of A P).  The
+  cycle takes H_{j+1,j} = 0 and ends there; its least-squares solution
+  updates X as usual, and an unconverged solve restarts from the new residual.
 """
 from __future__ import annotations
 
@@ -28,6 +43,9 @@ import dataclasses
 from typing import Callable, List, Optional
 
 import numpy as np
+
+DEP_SINE = 1e-6  # sine below which a block column counts as dependent on the ones before it
+STEP_DEF = 1e-14  # pivot of a new block, relative to max ||W_c|| before Gram-Schmidt
 
 
 @dataclasses.dataclass
@@ -45,6 +63,13 @@ def qr_positive(W):
     Q, R = np.linalg.qr(W, mode="reduced")
     d = np.where(np.diag(R) < 0.0, -1.0, 1.0)
     return Q * d[None, :], R * d[:, None]
+
+
+def column_sines(Y, R):
+    """|R_cc| / ||y_c|| for the thin QR Y = Q R: the sine of the angle between
+    column c and the span of columns 0..c-1 (NaN for a zero column)."""
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.abs(np.diag(R)) / np.linalg.norm(Y, axis=0)
 
 
 def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30,
@@ -80,6 +105,10 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
         if cycle == ncycles:
             break
         V1, S = qr_positive(R)
+        if not np.all(column_sines(R, S) > DEP_SINE):
+            info.breakdown = True
+            info.steps.append(0)
+            break
         V = [V1]
         Hbar = np.zeros(((m + 1) * k, m * k))
         G = np.zeros(((m + 1) * k, k))
@@ -97,7 +126,8 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
                 W = W - Vcat @ Hp
                 Hbar[: (j + 1) * k, j * k:(j + 1) * k] += Hp
             Vn, Hd = qr_positive(W)
-            deficient = np.abs(np.diag(Hd)).min() <= 1e-14 * wscale
+            deficient = (np.abs(np.diag(Hd)).min() <= STEP_DEF * wscale
+                         or not np.all(column_sines(W, Hd) > DEP_SINE))
             if deficient:
                 Hd = np.zeros((k, k))
                 Vn = np.zeros((n, k))
@@ -111,15 +141,12 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
             j_done = j + 1
             done = np.all(est <= tol)
             if deficient:
-                info.breakdown = not done
                 break
             if fixed_steps is None and done:
                 break
         info.steps.append(j_done)
         info.hessenbergs.append(Hbar[: (j_done + 1) * k, : j_done * k].copy())
         X = X + P_apply(np.hstack(V[:j_done]) @ Y)
-        if info.breakdown:
-            break
     R = Bc - A_apply(X)
     rel = np.linalg.norm(R, axis=0) / bnorm
     info.relres[active] = rel

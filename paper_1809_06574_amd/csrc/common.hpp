@@ -37,13 +37,18 @@ int hip_fail(hipError_t e, const char* what);
 // block GMRES cycle in lockstep; every kernel launch covers all of them.
 // ---------------------------------------------------------------------------
 constexpr int KMAX = PMOR_KMAX;
+// A block column whose sine to the span of the columns before it is at most
+// this is dependent.  Cholesky QR in FP64 resolves sines down to about 1e-7 for
+// blocks of up to 2^22 rows (the Gram matrix carries a relative rounding error
+// of about sqrt(n) eps), so the verdict does not hinge on the QR algorithm.
+constexpr double kDepSine = 1e-6;
 
 // per-segment device state of the current cycle
 struct DevState {
   int j;            // block steps completed in the current cycle
   int done;         // the cycle stops (converged, breakdown or max steps)
   int deficient;    // rank-deficient W met in the current step
-  int breakdown;    // deficient with unconverged columns
+  int breakdown;    // deficient residual block at the cycle start
   int kact;         // active right-hand sides (<= kp)
   int m;            // restart length
   int nanflag;

@@ -220,8 +220,12 @@ __device__ bool chol_upper(const double* Gm, int kp, int kact, double thr2, doub
 // W'' = W' - V H2 as Gram(W') - H2^T H2 (sH holds +-H2 in LDS, [basis][rhs]),
 // its Cholesky factor R1 and R1^{-1}, and the scale max_c ||W_c|| of the
 // deficiency test (block step: norms of pass 1; cycle start: of W itself).
-// Stores R1, the scale, the verdict and, in a block step, the Hessenberg
-// column block H1 + H2 (when first).
+// The block is deficient when a column's sine to the span of the columns
+// before it, R1_cc / ||w_c||, is at most kDepSine, or (block step only) a
+// pivot is at most 1e-14 max_c ||W_c||.  The sine test is scale-free, so a
+// residual column that converged far ahead of the others does not trip it at
+// a cycle start.  Stores R1, the scale, the verdict and, in a block step, the
+// Hessenberg column block H1 + H2 (when first).
 template <int KP>
 __device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH, int nbl, double* sRinv) {
   DevState* st = a.st + s;
@@ -240,8 +244,10 @@ __device__ void p3_prologue(const KArgs& a, int s, bool first, const double* sH,
     double mx = 0.0;
     for (int c = 0; c < kact; ++c) mx = fmax(mx, a.mode == 0 ? Hc1[nbl * KP * KP + c] : sG[c * KP + c]);
     const double ws = sqrt(mx);
-    const double thr = 1e-14 * ws;
-    const bool ok = chol_upper(sG, KP, kact, thr * thr, sR, sRinv);
+    const double thr = a.mode == 0 ? 1e-14 * ws : 0.0;
+    bool ok = chol_upper(sG, KP, kact, thr * thr, sR, sRinv);
+    for (int c = 0; c < kact; ++c)
+      if (!(sR[c * KP + c] > kDepSine * sqrt(sG[c * KP + c]))) ok = false;
     if (first) {
       st->wscale = ws;
       st->deficient = ok ? 0 : 1;
@@ -919,9 +925,12 @@ __global__ __launch_bounds__(64 * NW) void k_upd_row(KArgs a) {
 // ---------------------------------------------------------------------------
 // Prologue: Gram(W1) from the pass-3 partials, R2 = chol(Gram(W1)), the
 // subdiagonal block H_{j+1,j} = R2 R1 and the deficiency test
-// |(R2 R1)_cc| <= 1e-14 max_c ||W_c||; R2^{-1} (zero when deficient) is kept for
-// the next step's V_{j+1} = W1 R2^{-1}.  Cycle start (mode 1): the block is S of
-// R_0 = V_0 S and goes to G.  Block step: Householder update of the QR
+// |(R2 R1)_cc| <= 1e-14 max_c ||W_c|| (block steps); R2^{-1} (zero when
+// deficient) is kept for the next step's V_{j+1} = W1 R2^{-1}.  Cycle start
+// (mode 1): the block is S of R_0 = V_0 S and goes to G; a deficient R_0 ends
+// the solve with a breakdown.  A deficient block step ends the cycle only (its
+// least-squares solution still updates X, and the solve restarts).  Block
+// step: Householder update of the QR
 // factorisation of the block Hessenberg matrix for the new block column j, the
 // transformed right-hand side G, and the least-squares residual of every column.
 template <int KP>
@@ -944,7 +953,7 @@ __global__ __launch_bounds__(256) void k_hess(KArgs a) {
           for (int t = r; t <= c; ++t) x += sR2[r * KP + t] * st->R1[t * KP + c];
         sHs[r * KP + c] = x;
       }
-    const double thr = 1e-14 * st->wscale;
+    const double thr = a.mode == 0 ? 1e-14 * st->wscale : 0.0;
     for (int c = 0; c < kact; ++c)
       if (!(fabs(sHs[c * KP + c]) > thr)) ok = false;
     if (!ok)
@@ -1087,14 +1096,9 @@ __global__ __launch_bounds__(256) void k_hess(KArgs a) {
       if (!(e <= st->tol)) done = false;
       if (e != e) st->nanflag = 1;
     }
-    bool brk = false;
-    if (st->deficient) {
-      if (!done) brk = true;
-      done = true;
-    }
+    if (st->deficient) done = true;
     if (st->nanflag) done = true;
     if (j + 1 >= m) done = true;
-    if (brk) st->breakdown = 1;
     st->j = j + 1;
     st->done = done ? 1 : 0;
     hf[0] = j + 1;
@@ -1687,12 +1691,15 @@ static int spmm_lanes_per_row() {
 
 // SpMM variant tuning for the batched engine.  One value per (block width,
 // operator: A or the preconditioner), fixed for the process once chosen, so a
-// system's result never depends on the batch it runs in.  PMOR_SPMM_LPR pins
-// every value; otherwise the first batch that needs a value times the five
-// candidates (1, 2, 4, 8 lanes per row, column split) on its own matrices and
-// keeps the fastest.
-// PMOR_TUNE_CACHE names a JSON file of the choices: read before tuning,
-// rewritten after it.
+// system's result never depends on the batch it runs in.  The tuner chooses
+// only between variants that add a row's entries in the same order (one lane
+// per row and the column split), so its choice never changes a result bit;
+// 2, 4 and 8 lanes per row split a row's sum and give other roundings, and run
+// only when PMOR_SPMM_LPR pins them.  Without the pin the first batch that
+// needs a value times the two candidates on its own matrices and keeps the
+// faster.  PMOR_TUNE_CACHE names a JSON file of the choices: read before
+// tuning (entries other than 1 and the column split are ignored), rewritten
+// after it.
 namespace tune {
 static std::mutex mu;
 static std::map<std::string, int> table;
@@ -1723,7 +1730,7 @@ static void load_locked() {
     size_t c = txt.find(':', j);
     if (c == std::string::npos) break;
     const int v = atoi(txt.c_str() + c + 1);
-    if (spmm_variant_ok(v)) table[name] = v;
+    if (v == 1 || v == SPMM_COLSPLIT) table[name] = v;
     i = c + 1;
   }
 }
@@ -2495,8 +2502,8 @@ class RunnerT final : public Runner {
         hipStream_t s = ctx_->stream;
         SpArgs sp{E_.seg_d, E_.tab_d + Gtot, E_.st, which, 0, E_.W.p, E_.T.p, E_.Z.p, nullptr, 1.0, 0.0, nullptr, 1};
         float best_ms = 3.0e38f;
-        v = 2;
-        for (int L : {1, 2, 4, 8, SPMM_COLSPLIT}) {
+        v = SPMM_COLSPLIT;
+        for (int L : {1, SPMM_COLSPLIT}) {
           for (int r = 0; r < 2; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);
           PMOR_HIP(hipEventRecord(ctx_->ev0, s));
           for (int r = 0; r < 3; ++r) launch_spmm_seg<KP, false>(nullptr, -1, 3, (unsigned)SPtot, L, s, sp);

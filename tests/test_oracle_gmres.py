@@ -8,7 +8,8 @@ from synth import config0, tiny_random_job, appendix1
 from oracle.assemble import Assembled
 from oracle.sparse import to_dense, to_scipy
 from oracle.spai import SpaiPattern, spai_build
-from oracle.gmres import block_gmres, qr_positive
+from oracle.gmres import block_gmres, qr_positive, column_sines, DEP_SINE
+from oracle.update import update_pattern
 from oracle.pipeline import JobOracle
 
 
@@ -157,3 +158,107 @@ def test_sequence_update_vs_rebuild_config0():
         assert np.all(u["info"].relres <= 1e-8)
         d = np.linalg.norm(u["X"] - r["X"]) / np.linalg.norm(r["X"])
         assert d <= 1e-7
+
+
+def test_column_sines_brute_force():
+    """The sine of each column against the span of the columns before it equals the
+    relative residual of its least-squares projection onto them (SVD lstsq)."""
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((40, 5))
+    Y[:, 2] = Y[:, 0] - 2.0 * Y[:, 1] + 1e-9 * rng.standard_normal(40)
+    Y[:, 3] *= 1e-12  # a tiny but independent column keeps a sine of order one
+    Y[:, 4] = Y[:, 3] * 3.0  # an exact multiple of a tiny column
+    _, R = qr_positive(Y)
+    got = column_sines(Y, R)
+    Yn = Y / np.linalg.norm(Y, axis=0)  # the sine does not depend on column scales
+    for c in range(5):
+        if c == 0:
+            want = 1.0
+        else:
+            coef, *_ = np.linalg.lstsq(Yn[:, :c], Yn[:, c], rcond=None)
+            want = np.linalg.norm(Yn[:, c] - Yn[:, :c] @ coef)
+        assert abs(got[c] - want) <= 1e-12 + 1e-5 * want, (c, got[c], want)
+    assert got[2] < 1e-8 and got[3] > 0.1 and got[4] < 1e-12
+
+
+def _c0_matrix():
+    job = config0()
+    orc = JobOracle(job)
+    _, A = orc.A(job.p_list[0])
+    return job, A
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-10, 1e-3])
+def test_dependent_rhs_columns(eps):
+    """A right-hand side that duplicates another up to eps: the residual block is
+    dependent (sine <= 1e-6) for eps = 0 and 1e-10, so the solve stops at the first
+    cycle start with X = 0; the verdict agrees with the smallest singular value of
+    the column-normalised block (for two unit columns at angle t it is about t/sqrt 2).
+    At eps = 1e-3 the block is independent and the solve converges to the LU solution."""
+    job, A = _c0_matrix()
+    rng = np.random.default_rng(77)
+    b = job.B[:, 0]
+    B = np.column_stack([b, b + eps * np.linalg.norm(b) * rng.standard_normal(job.n) / np.sqrt(job.n)])
+    X, info = block_gmres(A.__matmul__, _ident, B, m=30, tol=1e-8)
+    smin = np.linalg.svd(B / np.linalg.norm(B, axis=0), compute_uv=False)[-1]
+    dependent = np.sqrt(2.0) * smin <= DEP_SINE
+    assert dependent == (eps < 1e-6)
+    if dependent:
+        assert info.breakdown and info.steps == [0] and not info.converged and not X.any()
+    else:
+        assert info.converged and not info.breakdown
+        X_lu = np.linalg.solve(A.toarray(), B)
+        assert np.linalg.norm(X - X_lu) / np.linalg.norm(X_lu) <= 1e-7
+
+
+def test_rhs_in_invariant_subspace_ends_cycle_then_restarts():
+    """b_1 is a combination of two eigenvectors of the symmetric C0 matrix, so its
+    Krylov space has dimension 2 (a textbook fact: the grade of b_1 is 2).  Without a
+    preconditioner the block Krylov space stops growing at the second block step: the
+    first cycle ends there with b_1 solved exactly, and the restart finishes b_2."""
+    job, A = _c0_matrix()
+    Ad = A.toarray()
+    w, U = np.linalg.eigh(Ad)
+    b1 = U[:, 3] + 0.5 * U[:, 700]
+    B = np.column_stack([b1, job.B[:, 1]])
+    X, info = block_gmres(A.__matmul__, _ident, B, m=30, tol=1e-10, max_cycles=10)
+    assert info.steps[0] == 2 and len(info.steps) >= 2
+    assert info.converged and not info.breakdown
+    assert info.ls_history[1][0] <= 1e-13  # b_1 solved within the first cycle
+    X_lu = np.linalg.solve(Ad, B)
+    assert np.linalg.norm(X - X_lu) / np.linalg.norm(X_lu) <= 1e-9
+    # x_1 is the eigen-expansion of b_1
+    x1 = U[:, 3] / w[3] + 0.5 * U[:, 700] / w[700]
+    assert np.linalg.norm(X[:, 0] - x1) <= 1e-10 * np.linalg.norm(x1)
+
+
+def test_pipeline_pattern_update_branch():
+    """JobOracle.run with the U-pattern update uses Q_l P_1, Q_l column by column the
+    dense least squares min ||A(1)e_i - A(l)(:, J_i) q||_2 (SVD lstsq): its X equals
+    a block GMRES run with that dense Q_l P_1 for the same block steps, and every
+    point converges to the dense LU solution."""
+    job = tiny_random_job(48, 0.08, 17, k=2, npts=3)
+    orc = JobOracle(job)
+    out = orc.run(policy="update", update_kind="pattern", m=10, tol=1e-10)
+    n = job.n
+    val1, A1 = orc.A(job.p_list[0])
+    P1 = orc.P(orc.spai(val1)[0]).toarray()
+    pat = orc.pat
+    for l, res in enumerate(out):
+        vall, Al = orc.A(job.p_list[l])
+        Ald, A1d = Al.toarray(), A1.toarray()
+        if l == 0:
+            Pl = P1
+        else:
+            Q = np.zeros((n, n))
+            for i in range(n):
+                J = pat.J_row[pat.J_colptr[i]:pat.J_colptr[i + 1]]
+                q, *_ = np.linalg.lstsq(Ald[:, J], A1d[:, i], rcond=None)
+                Q[J, i] = q
+            Pl = Q @ P1
+        Xd, _ = block_gmres(Al.__matmul__, lambda V, Pl=Pl: Pl @ V, job.B, m=10, tol=1e-10,
+                            fixed_steps=res["info"].steps)
+        assert np.linalg.norm(res["X"] - Xd) <= 1e-11 * np.linalg.norm(Xd), l
+        assert res["info"].converged
+        X_lu = np.linalg.solve(Ald, job.B)
+        assert np.linalg.norm(res["X"] - X_lu) <= 1e-8 * np.linalg.cond(Ald) * np.linalg.norm(X_lu)
