@@ -505,21 +505,27 @@ __global__ void k_update_diag(int n, const int32_t* colptr, const int32_t* cscsl
                               double* Pl, double* q, double* rho, int* bad_col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double num = 0.0, den = 0.0, n11 = 0.0;
+  double num = 0.0, den = 0.0;
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
     const double x = al[s], y = a1[s];
     num += x * y;
     den += x * x;
-    n11 += y * y;
   }
   const double qi = num / den;
   if (!(den > 0.0)) atomicMin(bad_col, i);
   const double qe = qprev ? qprev[i] * qi : qi;
   q[i] = qe;
-  // ||a e_i - q_i A(l) e_i||^2 = n11 - 2 q num + q^2 den
-  const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
-  rho[i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+  // ||a e_i - q_i A(l) e_i|| summed entry by entry once q_i is known (the
+  // expanded form ||a e_i||^2 - 2 q num + q^2 den cancels when the fit is
+  // tight)
+  double r2 = 0.0;
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    const double d = a1[s] - qi * al[s];
+    r2 += d * d;
+  }
+  rho[i] = sqrt(r2);
   if (Pl)
     for (int e = Prowptr[i]; e < Prowptr[i + 1]; ++e) Pl[e] = qe * P1[e];
 }
@@ -591,8 +597,13 @@ __global__ void k_update_adaptive_diag(int n, const int32_t* colptr, const int32
     n11 += y * y;
   }
   const double qi = num / den;
-  const double r2 = n11 - 2.0 * qi * num + qi * qi * den;
-  const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+  double r2 = 0.0;  // entry by entry, as in k_update_diag
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    const double d = a1[s] - qi * al[s];
+    r2 += d * d;
+  }
+  const double r = sqrt(r2);
   const bool up = !(r <= ep * sqrt(n11));
   esc[i] = up ? 1 : 0;
   rho[i] = up ? 0.0 : r;
@@ -771,7 +782,6 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
   double num[PTS_MAX], den[PTS_MAX];
 #pragma unroll
   for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = 0.0;
-  double n11 = 0.0;
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
     double tv[PMOR_NROLES];
@@ -787,16 +797,37 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
         den[l] += x * x;
       }
     }
-    n11 += y * y;
+  }
+  double qv[PTS_MAX], r2[PTS_MAX];
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) {
+    qv[l] = l < pc.cnt ? num[l] / den[l] : 0.0;
+    r2[l] = 0.0;
+  }
+  // residuals entry by entry once the factors are known (the column's entries
+  // were just read, so the second pass hits the caches)
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    double tv[PMOR_NROLES];
+#pragma unroll
+    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    const double y = a1[s];
+#pragma unroll
+    for (int l = 0; l < PTS_MAX; ++l) {
+      if (l < pc.cnt) {
+        double x = 0.0;
+        for (int t = 0; t < pc.nt; ++t) x += pc.c[l][t] * tv[t];
+        const double d = y - qv[l] * x;
+        r2[l] += d * d;
+      }
+    }
   }
 #pragma unroll
   for (int l = 0; l < PTS_MAX; ++l) {
     if (l < pc.cnt) {
-      const double qi = num[l] / den[l];
       if (!(den[l] > 0.0)) atomicMin(bad + l, i);
-      q[(int64_t)l * n + i] = qi;
-      const double r2 = n11 - 2.0 * qi * num[l] + qi * qi * den[l];
-      rho[(int64_t)l * n + i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+      q[(int64_t)l * n + i] = qv[l];
+      rho[(int64_t)l * n + i] = sqrt(r2[l]);
     }
   }
 }
@@ -831,9 +862,9 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
                                     double* q, double* rho, int* bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double num[PTS_MAX], den[PTS_MAX], n11[PTS_MAX];
+  double num[PTS_MAX], den[PTS_MAX];
 #pragma unroll
-  for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = n11[l] = 0.0;
+  for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = 0.0;
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
     double tv[PMOR_NROLES];
@@ -848,8 +879,32 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
         for (int t = 0; t < pc.nt; ++t) x += pc.c[l + 1][t] * tv[t];
         num[l] += x * y;
         den[l] += x * x;
-        n11[l] += y * y;
         y = x;  // the next point's anchor
+      }
+    }
+  }
+  double qv[PTS_MAX], r2[PTS_MAX];
+#pragma unroll
+  for (int l = 0; l < PTS_MAX; ++l) {
+    qv[l] = l < pc.cnt ? num[l] / den[l] : 0.0;
+    r2[l] = 0.0;
+  }
+  // step residuals ||A(l-1) e_i - q_l A(l) e_i|| entry by entry
+  for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
+    const int s = cscslot[e];
+    double tv[PMOR_NROLES];
+#pragma unroll
+    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    double y = 0.0;
+    for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
+#pragma unroll
+    for (int l = 0; l < PTS_MAX; ++l) {
+      if (l < pc.cnt) {
+        double x = 0.0;
+        for (int t = 0; t < pc.nt; ++t) x += pc.c[l + 1][t] * tv[t];
+        const double d = y - qv[l] * x;
+        r2[l] += d * d;
+        y = x;
       }
     }
   }
@@ -857,12 +912,10 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
 #pragma unroll
   for (int l = 0; l < PTS_MAX; ++l) {
     if (l < pc.cnt) {
-      const double qi = num[l] / den[l];
       if (!(den[l] > 0.0)) atomicMin(bad + l, i);
-      qc = qc * qi;
+      qc = qc * qv[l];
       q[(int64_t)l * n + i] = qc;
-      const double r2 = n11[l] - 2.0 * qi * num[l] + qi * qi * den[l];
-      rho[(int64_t)l * n + i] = sqrt(r2 > 0.0 ? r2 : 0.0);
+      rho[(int64_t)l * n + i] = sqrt(r2[l]);
     }
   }
   carry[i] = qc;

@@ -98,3 +98,41 @@ def test_adaptive_sequence_equals_chain_of_single_updates(ctx):
         pb.spai_build(job.s, job.p_list[0], update="adaptive", adapt_ep=-1.0)
     h.close()
     pb.close()
+
+
+def test_adaptive_threshold_near_1e8(ctx):
+    """p_l within 1e-7 of p_1: the diagonal misfit ratios are about 1e-8, where the
+    expanded form of the residual would be rounding noise.  With ep in a gap of those
+    ratios the escalated columns and Q are the oracle's (which forms a - q a_l)."""
+    import dataclasses
+    from paper_1809_06574_amd import Problem
+    base = tiny_random_job(300, 0.02, 82, k=2, npts=3)
+    p1 = float(base.p_list[0])
+    job = dataclasses.replace(base, p_list=np.array([p1, p1 + 2e-7, p1 + 1e-7]))
+    n = job.n
+    asm = Assembled(job)
+    pat = SpaiPattern(n, asm.rowptr, asm.col)
+    v1, vl = asm.values(job.s, job.p_list[0]), asm.values(job.s, job.p_list[2])
+    ep = _ep_in_gap(n, asm, v1, vl)
+    assert 1e-10 < ep < 1e-6, ep
+    qv, rho, esc = update_adaptive(n, asm.rowptr, asm.col, v1, vl, pat, ep)
+    assert 0 < len(esc) < n
+    pb = Problem(ctx, job.terms)
+    h = pb.spai_build(job.s, job.p_list[0], update="adaptive", adapt_ep=ep)
+    st = h.update(job.s, job.p_list[2], stats=True)
+    exp = h.export()
+    got = np_(exp["q"])
+    err = col_rel_err(n, pat.J_colptr, pat.P_slot, got, qv)
+    assert err <= 1e-10, err
+    # the escalated set: a kept column has zeros off its diagonal
+    rows = pat.J_row
+    esc_gpu = []
+    for i in range(n):
+        sl = pat.P_slot[pat.J_colptr[i]:pat.J_colptr[i + 1]]
+        off = rows[pat.J_colptr[i]:pat.J_colptr[i + 1]] != i
+        if np.any(got[sl][off] != 0.0):
+            esc_gpu.append(i)
+    assert sorted(esc_gpu) == sorted(int(i) for i in esc)
+    assert st["fro_resid"] == pytest.approx(np.sqrt(np.sum(rho ** 2)), rel=1e-6)
+    h.close()
+    pb.close()
