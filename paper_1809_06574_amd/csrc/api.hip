@@ -364,6 +364,9 @@ extern "C" {
 
 int pmor_ctx_set_stream(pmor_ctx* c, void* hip_stream) {
   if (!c) return fail(PMOR_EINVAL, "ctx is NULL");
+  // work queued on the old stream (and the device memory it released into the
+  // cache) completes before anything is ordered on the new one
+  PMOR_HIP(hipStreamSynchronize(c->stream));
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   return PMOR_OK;
 }
@@ -1362,13 +1365,17 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
   if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
   double* tmp = nullptr;
   PMOR_HIP(dmalloc((void**)&tmp, sizeof(double) * std::max<int64_t>(pb->nnz, 1), pb->ctx->stream));
-  PMOR_TRY(ensure_assembled(pb, s1, p1));
-  PMOR_TRY(dcopy(pb->aval, tmp, pb->nnz, pb->ctx->stream));
-  PMOR_TRY(ensure_assembled(pb, s2, p2));
   double a = 0.0, b = 0.0;
-  PMOR_TRY(fro_norm2(pb, pb->aval, nullptr, pb->nnz, 1, &a));
-  PMOR_TRY(fro_norm2(pb, tmp, pb->aval, pb->nnz, 0, &b));
+  const int rc = [&]() -> int {
+    PMOR_TRY(ensure_assembled(pb, s1, p1));
+    PMOR_TRY(dcopy(pb->aval, tmp, pb->nnz, pb->ctx->stream));
+    PMOR_TRY(ensure_assembled(pb, s2, p2));
+    PMOR_TRY(fro_norm2(pb, pb->aval, nullptr, pb->nnz, 1, &a));
+    PMOR_TRY(fro_norm2(pb, tmp, pb->aval, pb->nnz, 0, &b));
+    return PMOR_OK;
+  }();
   dfree(tmp, pb->ctx->stream);
+  if (rc != PMOR_OK) return rc;
   if (fro_I_minus_A2) *fro_I_minus_A2 = std::sqrt(a);
   if (fro_A1_minus_A2) *fro_A1_minus_A2 = std::sqrt(b);
   return PMOR_OK;
