@@ -364,6 +364,19 @@ int pmor_server_info(const pmor_server* sv, int32_t* queued, int32_t* admitted, 
 int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double p2,
                       double* fro_I_minus_A2, double* fro_A1_minus_A2);
 
+/* The same two norms for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that decide on re-anchoring per point,
+ * harnesses that forbid hipMalloc): no hipMalloc, hipFree or other allocating
+ * routine on this path.  Both norms are formed in one pass over the term
+ * values (A(s1,p1) and A(s2,p2) are not assembled, the problem's assembled
+ * values are left as they are) and their partial sums go to a fixed 4,112-byte
+ * device array of the library, one per GPU, held until the process ends; it
+ * fits every problem size, so no size is rejected.  Calls that overlap on one
+ * GPU race for that array.  Host outputs; synchronises the stream.  Errors:
+ * PMOR_EINVAL (pb NULL), PMOR_EHIP. */
+int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2, double p2,
+                              double* fro_I_minus_A2, double* fro_A1_minus_A2);
+
 /* ---- kernel-level entry points (timing and parity) --------------------- */
 /* Y = beta*Y + alpha*A(s,p)-values-on-pattern * X, with the values in aval
  * (device, nnz) on pb's pattern; X, Y: n x k row-major, ld >= k. */

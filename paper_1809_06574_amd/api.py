@@ -110,6 +110,13 @@ class Problem:
         L.check(L.pmor_table2_norms(self.handle, s1, p1, s2, p2, C.byref(a), C.byref(b)), "pmor_table2_norms")
         return a.value, b.value
 
+    def table2_norms_noalloc(self, s1, p1, s2, p2):
+        """As table2_norms, through the entry point that allocates no device memory."""
+        a, b = C.c_double(), C.c_double()
+        L.check(L.pmor_table2_norms_noalloc(self.handle, s1, p1, s2, p2, C.byref(a), C.byref(b)),
+                "pmor_table2_norms_noalloc")
+        return a.value, b.value
+
     # --- preconditioner / solve ------------------------------------------
     def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False, approach="first",
                    adapt_ep=0.0):

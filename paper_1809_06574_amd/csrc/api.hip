@@ -7,6 +7,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -271,6 +272,91 @@ static int solve_opts_of(const pmor_solve_opts* opts, pmor_solve_opts* o) {
   return PMOR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free Table 2 norms (pmor_table2_norms_noalloc).  Its partial sums
+// live in a fixed device array of this file, `scratch`, instead of memory the
+// library allocates: 2 x kT2Parts partials and the 2 sums (4,112 bytes, whatever
+// the size of the problem).  Each GPU holds its own copy of the array until
+// the process ends; its device address is taken once per device when a context
+// is created on it (the array's name in host code is not a device address).
+// Every call on a GPU overwrites the whole array before reading it, so nothing
+// has to start at zero; calls that overlap on one GPU race for it.
+// ---------------------------------------------------------------------------
+constexpr int kT2Parts = 256;                    // workgroups, one partial of each norm per workgroup
+constexpr int kScratchDoubles = 2 * kT2Parts + 2;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `device` (current), taken once
+static int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(PMOR_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PMOR_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(PMOR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return PMOR_OK;
+}
+
+struct T2Coefs {
+  double c1[PMOR_NROLES], c2[PMOR_NROLES];
+  int nt;
+};
+
+// Both Table 2 norms straight from the term values: per entry, a1 and a2 are
+// the assembled values of the two points (the sums of k_assemble, in its term
+// order), added into ||A1 - A2||_F^2 and ||I - A2||_F^2 row by row, one partial
+// of each per workgroup (the row split and in-workgroup order of
+// k_fro_partials).  part[0..G): ||I - A2||^2, part[G..2G): ||A1 - A2||^2.
+__global__ __launch_bounds__(256) void k_table2_partials(int n, const int32_t* __restrict__ rowptr,
+                                                         const int32_t* __restrict__ col, int64_t nnz,
+                                                         const double* __restrict__ tval, T2Coefs cf,
+                                                         double* __restrict__ part) {
+  __shared__ double s[2][4];
+  double accI = 0.0, accD = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    bool diag = false;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      double a1 = 0.0, a2 = 0.0;
+      for (int t = 0; t < cf.nt; ++t) a1 += cf.c1[t] * tval[(int64_t)t * nnz + e];
+      for (int t = 0; t < cf.nt; ++t) a2 += cf.c2[t] * tval[(int64_t)t * nnz + e];
+      const double d = a1 - a2;
+      accD += d * d;
+      double x;
+      if (col[e] == i) { x = 1.0 - a2; diag = true; }
+      else x = a2;
+      accI += x * x;
+    }
+    if (!diag) accI += 1.0;
+  }
+  accI = wave_sum(accI);
+  accD = wave_sum(accD);
+  if ((threadIdx.x & 63) == 0) {
+    s[0][threadIdx.x >> 6] = accI;
+    s[1][threadIdx.x >> 6] = accD;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s[0][0] + s[0][1] + s[0][2] + s[0][3];
+    part[gridDim.x + blockIdx.x] = s[1][0] + s[1][1] + s[1][2] + s[1][3];
+  }
+}
+
+// out[b] = sum of part[b G .. b G + G) in a fixed tree order, b = blockIdx.x (G <= 256)
+__global__ __launch_bounds__(256) void k_table2_sums(const double* __restrict__ part, int G, double* __restrict__ out) {
+  __shared__ double s[256];
+  s[threadIdx.x] = (int)threadIdx.x < G ? part[(int64_t)blockIdx.x * G + threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
 }  // namespace pmor
 
 using namespace pmor;
@@ -301,6 +387,7 @@ int pmor_ctx_create(pmor_ctx** out, int device, void* hip_stream) {
   PMOR_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(PMOR_EHIP, "device index out of range");
   PMOR_HIP(hipSetDevice(device));
+  PMOR_TRY(scratch_setup(device));
   pmor_ctx* c = new pmor_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1378,6 +1465,36 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
   if (rc != PMOR_OK) return rc;
   if (fro_I_minus_A2) *fro_I_minus_A2 = std::sqrt(a);
   if (fro_A1_minus_A2) *fro_A1_minus_A2 = std::sqrt(b);
+  return PMOR_OK;
+}
+
+int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2, double p2,
+                              double* fro_I_minus_A2, double* fro_A1_minus_A2) {
+  if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
+  const int dev = pb->ctx->device;
+  double* scr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+  if (!scr) return fail(PMOR_EHIP, "no scratch address for the context's device");
+  static_assert(kT2Parts <= 256, "k_table2_sums adds at most 256 partials");
+  T2Coefs cf{};
+  cf.nt = pb->nterms;
+  double c1[PMOR_NROLES], c2[PMOR_NROLES];
+  role_coefs(s1, p1, c1);
+  role_coefs(s2, p2, c2);
+  for (int r = 0; r < PMOR_NROLES; ++r)
+    if (pb->role_slot[r] >= 0) {
+      cf.c1[pb->role_slot[r]] = c1[r];
+      cf.c2[pb->role_slot[r]] = c2[r];
+    }
+  hipStream_t st = pb->ctx->stream;
+  hipLaunchKernelGGL(k_table2_partials, dim3(kT2Parts), dim3(256), 0, st, pb->n, pb->rowptr, pb->col,
+                     (int64_t)pb->nnz, pb->tval, cf, scr);
+  hipLaunchKernelGGL(k_table2_sums, dim3(2), dim3(256), 0, st, (const double*)scr, kT2Parts, scr + 2 * kT2Parts);
+  PMOR_HIP(hipGetLastError());
+  double h[2] = {0.0, 0.0};
+  PMOR_HIP(hipMemcpyAsync(h, scr + 2 * kT2Parts, sizeof(h), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  if (fro_I_minus_A2) *fro_I_minus_A2 = std::sqrt(h[0]);
+  if (fro_A1_minus_A2) *fro_A1_minus_A2 = std::sqrt(h[1]);
   return PMOR_OK;
 }
 

@@ -108,6 +108,7 @@ _SIGS = {
     "pmor_server_step": (C.c_int, [P, C.POINTER(I64), C.POINTER(I32), I32, C.POINTER(I32)]),
     "pmor_server_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]),
     "pmor_table2_norms": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
+    "pmor_table2_norms_noalloc": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
     "pmor_spmm": (C.c_int, [P, P, P, I64, P, I64, I32, D, D]),
     "pmor_prof_set": (C.c_int, [P, C.c_int]),
     "pmor_prof_read": (C.c_int, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]),
