@@ -59,6 +59,7 @@ extern "C" {
 
 #define PMOR_KMAX 16      /* largest block of right-hand sides                 */
 #define PMOR_NROLES 6     /* number of term roles                              */
+#define PMOR_TMAX 8       /* most terms of an affine problem                   */
 #define PMOR_MAX_CYCLES 64
 
 /* Term roles: A(s,p) = s^2 (M0 + p M1) + s (D0 + p D1) + (K0 + p K1). */
@@ -175,16 +176,32 @@ int pmor_ctx_set_stream(pmor_ctx* ctx, void* hip_stream);
  * monotone rowptr, nnz = rowptr[n], columns in range and strictly increasing
  * (PMOR_EINVAL otherwise).  Synchronises the stream. */
 int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_problem** out);
+/* The general affine problem of Section 1.1 (eq. affine_system) and Section
+ * 2.4: A(l) = sum_t c_t^l T_t over nterms (1..PMOR_TMAX) term matrices, the
+ * point l being the coefficient vector c^l (A_0 is a term whose coefficient
+ * the caller passes as 1; the paper's gyroscope model of Section 3 has seven
+ * terms, six of them with free coefficients such as s^2 d and 1/d).  terms[t]
+ * must all be present and share n; validation, pattern and copies as
+ * pmor_problem_create.  Points of such a problem are given as coefficient
+ * vectors to the *_c calls (nterms host doubles, in the order of terms); the
+ * (s, p) calls return PMOR_EINVAL for it.  pmor_problem_create is the special
+ * case of six roles with the coefficients of s^2 M(p) + s D(p) + K(p); the *_c
+ * calls accept its points too, as PMOR_NROLES coefficients in role order
+ * (those of absent roles are ignored). */
+int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, pmor_problem** out);
 void pmor_problem_destroy(pmor_problem* pb);
 /* n and nnz of the union pattern (host outputs). */
 int pmor_problem_info(const pmor_problem* pb, int32_t* n, int32_t* nnz);
 /* Copy the union pattern into caller buffers (device): rowptr (n+1), col (nnz)
- * and maps (PMOR_NROLES*nnz; maps[r*nnz + e] = position of A-slot e in term r's
- * value array, -1 where term r has no entry or is absent).  Any output may be
- * NULL. */
+ * and maps (R*nnz with R = PMOR_NROLES for a problem of roles, nterms for an
+ * affine one; maps[r*nnz + e] = position of A-slot e in term r's value array,
+ * -1 where term r has no entry or is absent).  Any output may be NULL. */
 int pmor_problem_pattern(const pmor_problem* pb, int32_t* rowptr, int32_t* col, int32_t* maps);
 /* Values of A(s,p) on the union pattern into val (device, nnz). */
 int pmor_assemble(pmor_problem* pb, double s, double p, double* val);
+/* Values of A(c) = sum_t coef[t] T_t into val (coef: host, see
+ * pmor_problem_create_affine; PMOR_EINVAL for a non-finite coefficient). */
+int pmor_assemble_c(pmor_problem* pb, const double* coef, double* val);
 
 /* ---- SPAI (Section 2.2) and its update (Sections 2.3-2.4) ---------------- */
 /* Build P = argmin ||I - A(s,p) P||_F on the chosen pattern; (s,p) becomes
@@ -194,9 +211,14 @@ int pmor_assemble(pmor_problem* pb, double s, double p, double* val);
  * PMOR_F64, PMOR_UPD_DIAG).  stats may be NULL; when given, the call
  * synchronises and fills fro_resid and t_* fields.  PMOR_ESINGULAR (with
  * stats->bad_column) when |R_kk| <= 10 |I_j| eps max|R| in some column;
- * PMOR_EINVAL when a column's |J_j| or |I_j| exceeds the supported 64 / 256. */
+ * PMOR_EINVAL when a column's |J_j| exceeds 64 or its least-squares block does
+ * not fit one workgroup's LDS (|I_j| x |J_j| values, about 150 KiB). */
 int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
                pmor_spai** out, pmor_stats* stats);
+/* spai_build at the point with coefficient vector coef (host; see
+ * pmor_problem_create_affine). */
+int spai_build_c(pmor_problem* pb, const double* coef, const pmor_spai_opts* opts,
+                 pmor_spai** out, pmor_stats* stats);
 /* Update at (s,p) (Table 1).  First approach: Q = argmin ||A(1) - A(s,p) Q||_F
  * on the handle's update pattern, then P = Q P_1 (anchor unchanged).  Second
  * approach (U-diag only): q = argmin ||A(prev) - A(s,p) diag(q)||_F, A(prev)
@@ -206,9 +228,26 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
  * ||A(prev) e_i - q_i A(s,p) e_i||.  Errors as spai_build; spai_build returns
  * PMOR_EINVAL for the second approach with PMOR_UPD_PATTERN. */
 int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats);
+int spai_update_c(pmor_spai* h, const double* coef, pmor_stats* stats);
 /* Recompute the SPAI of A(s,p) in place (the rebuild policy); the anchor is
  * moved to (s,p). */
 int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats);
+int spai_rebuild_c(pmor_spai* h, const double* coef, pmor_stats* stats);
+/* A preconditioner from a given P, as the paper's pipeline hands P from one
+ * program to another (Section 3): P in CSR on the device (rowptr n+1, col and
+ * val nnzP; columns strictly increasing per row, every row holding its
+ * diagonal), copied here.  (s,p) or coef is the anchor point A(1) of later
+ * updates.  The handle is spai_build's with PMOR_PAT_EXPLICIT on P's pattern
+ * (opts: precision, update kind and approach of later updates and rebuilds;
+ * its pattern fields are ignored), rho zero until an update.  Export then
+ * import gives back the same preconditioner bit for bit.  PMOR_EINVAL for a
+ * malformed P.  Synchronises. */
+int spai_import(pmor_problem* pb, double s, double p, int32_t nnzP, const int32_t* rowptr,
+                const int32_t* col, const double* val, const pmor_spai_opts* opts,
+                pmor_spai** out);
+int spai_import_c(pmor_problem* pb, const double* coef, int32_t nnzP, const int32_t* rowptr,
+                  const int32_t* col, const double* val, const pmor_spai_opts* opts,
+                  pmor_spai** out);
 /* The current preconditioner.  P in CSR: rowptr (n+1), col (nnzP), val (nnzP);
  * for PMOR_UPD_PATTERN and PMOR_UPD_ADAPTIVE after an update, val holds P_1
  * and qval holds Q (same CSR pattern; an adaptive column that was not
@@ -247,8 +286,12 @@ void spai_free(pmor_spai* h);
 int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p,
                 const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
                 const pmor_solve_opts* opts, pmor_stats* stats);
+int block_solve_c(pmor_problem* pb, const pmor_spai* h, const double* coef,
+                  const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
+                  const pmor_solve_opts* opts, pmor_stats* stats);
 
-/* One system of pmor_batch_solve: A(s,p) of problem pb (assembled by the
+/* One system of pmor_batch_solve: A of problem pb at the point coef (host
+ * coefficient vector) or, when coef is NULL, at (s,p) (assembled by the
  * library), preconditioned by h's current preconditioner (or NULL), B and X as
  * in block_solve. */
 typedef struct pmor_batch_item {
@@ -260,6 +303,7 @@ typedef struct pmor_batch_item {
   int32_t k;
   double* X;
   int64_t ldx;
+  const double* coef;
 } pmor_batch_item;
 
 /* Solve many independent systems together (the batching of the hot path):
@@ -302,6 +346,12 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
                         double* X, int64_t ldx, int32_t policy,
                         const pmor_spai_opts* sopts, const pmor_solve_opts* vopts,
                         pmor_stats* stats);
+/* The same with the points as coefficient vectors: coefs is npts x C (host,
+ * row-major, C = the problem's coefficient count; point l at coefs + l*C). */
+int pmor_sequence_solve_c(pmor_problem* pb, const double* B, int64_t ldb, int32_t k,
+                          const double* coefs, int32_t npts, double* X, int64_t ldx,
+                          int32_t policy, const pmor_spai_opts* sopts,
+                          const pmor_solve_opts* vopts, pmor_stats* stats);
 
 /* ---- serving: continuous batching of sequence jobs ----------------------- */
 /* A server admits whole sequence jobs (one pmor_sequence_solve each) under a
@@ -332,6 +382,8 @@ typedef struct pmor_job {
   int32_t policy;       /* PMOR_UPDATE | PMOR_REBUILD */
   pmor_stats* stats;    /* npts entries or NULL (host, written until the job is done); */
                         /* t_solve_ms = submission to the point's final X            */
+  const double* coefs;  /* npts x C coefficient vectors (host, copied at submission), */
+                        /* as pmor_sequence_solve_c; NULL: the points (s_list, p_list) */
 } pmor_job;
 
 /* sopts, vopts: as pmor_sequence_solve (NULL: defaults; reanchor_tol must be
@@ -363,6 +415,11 @@ int pmor_server_info(const pmor_server* sv, int32_t* queued, int32_t* admitted, 
 /* ||I - A(s,p)||_F and ||A(s1,p1) - A(s2,p2)||_F (host outputs; synchronises). */
 int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double p2,
                       double* fro_I_minus_A2, double* fro_A1_minus_A2);
+/* The same for two coefficient vectors (host): ||I - A(coef2)||_F and
+ * ||A(coef1) - A(coef2)||_F, e.g. the paper's Table 2 for the points of an
+ * affine problem. */
+int pmor_table2_norms_c(pmor_problem* pb, const double* coef1, const double* coef2,
+                        double* fro_I_minus_A2, double* fro_A1_minus_A2);
 
 /* The same two norms for callers that cannot allocate device memory (code
  * under HIP graph capture, serving loops that decide on re-anchoring per point,
@@ -373,7 +430,7 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
  * device array of the library, one per GPU, held until the process ends; it
  * fits every problem size, so no size is rejected.  Calls that overlap on one
  * GPU race for that array.  Host outputs; synchronises the stream.  Errors:
- * PMOR_EINVAL (pb NULL), PMOR_EHIP. */
+ * PMOR_EINVAL (pb NULL, an affine problem, s or p not finite), PMOR_EHIP. */
 int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2, double p2,
                               double* fro_I_minus_A2, double* fro_A1_minus_A2);
 

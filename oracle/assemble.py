@@ -3,6 +3,9 @@
 The frequency-domain matrix of the second-order system (paper, Section 1.1
 and eq. loewner_eq2 in Section 1.2), with each coefficient matrix affine in
 the parameter: M(p) = M0 + p M1, D(p) = D0 + p D1, K(p) = K0 + p K1.
+The general affine form of Section 1.1 (eq. affine_system),
+A = A_0 + s~_1 A_1 + ... + s~_{w+1} A_{w+1}, is ``affine_values``: a list of
+term matrices and one coefficient per term (the coefficient of A_0 is 1).
 
 The pattern of A is the union of the term patterns plus the full diagonal.
 Entries that cancel numerically stay in the pattern, so the pattern does not
@@ -16,16 +19,16 @@ ROLES = ("M0", "M1", "D0", "D1", "K0", "K1")
 
 
 def union_pattern(n, terms):
-    """CSR pattern of the union of ``terms`` (dict role -> CSR) and the diagonal.
+    """CSR pattern of the union of ``terms`` (dict role -> CSR, or a list of CSR
+    indexed by position) and the diagonal.
 
-    Returns (rowptr, col, maps) where maps[role][e] is the position of A-slot e in
+    Returns (rowptr, col, maps) where maps[key][e] is the position of A-slot e in
     that term's value array, or -1 where the term has no entry.
     """
     keys = [np.arange(n, dtype=np.int64) * (n + 1)]  # diagonal keys i*n + i
     term_keys = {}
-    for role in ROLES:
-        if role not in terms:
-            continue
+    names = [r for r in ROLES if r in terms] if isinstance(terms, dict) else list(range(len(terms)))
+    for role in names:
         T = terms[role]
         rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(T.rowptr.astype(np.int64)))
         tk = rows * n + T.col.astype(np.int64)
@@ -59,6 +62,18 @@ def term_values_on_pattern(terms, maps, nnz):
     return out
 
 
+def affine_values(terms, maps, nnz, coef):
+    """Values of sum_t coef[t] T_t on the union pattern (terms: list of CSR, maps by
+    list position), the terms added in list order."""
+    out = np.zeros(nnz)
+    for t, T in enumerate(terms):
+        m = maps[t]
+        v = np.zeros(nnz)
+        v[m >= 0] = T.val[m[m >= 0]]
+        out = out + coef[t] * v
+    return out
+
+
 def assemble_values(terms, maps, nnz, s, p):
     """Values of A(s,p) on the union pattern: s^2 (M0 + p M1) + s (D0 + p D1) + (K0 + p K1)."""
     t = term_values_on_pattern(terms, maps, nnz)
@@ -69,13 +84,20 @@ def assemble_values(terms, maps, nnz, s, p):
 
 
 class Assembled:
-    """A(s,p) of one job on its fixed union pattern."""
+    """A of one job on its fixed union pattern: at (s, p) for a job of roles, at a
+    coefficient vector for an affine job (``job.aterms``)."""
 
     def __init__(self, job):
         self.n = job.n
-        self.terms = job.terms
-        self.rowptr, self.col, self.maps = union_pattern(job.n, job.terms)
+        self.affine = getattr(job, "aterms", None) is not None
+        self.terms = job.aterms if self.affine else job.terms
+        self.rowptr, self.col, self.maps = union_pattern(job.n, self.terms)
         self.nnz = int(self.rowptr[-1])
 
     def values(self, s, p):
+        assert not self.affine, "an affine job takes coefficient vectors (values_c)"
         return assemble_values(self.terms, self.maps, self.nnz, s, p)
+
+    def values_c(self, coef):
+        assert self.affine, "values_c is for affine jobs"
+        return affine_values(self.terms, self.maps, self.nnz, coef)

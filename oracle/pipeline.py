@@ -28,6 +28,14 @@ class JobOracle:
         v = self.asm.values(self.job.s, p)
         return v, to_scipy(self.job.n, self.asm.rowptr, self.asm.col, v)
 
+    def A_at(self, l):
+        """A at point l of the job: (s, p_l), or the coefficient vector coefs[l] of an
+        affine job."""
+        if self.asm.affine:
+            v = self.asm.values_c(self.job.coefs[l])
+            return v, to_scipy(self.job.n, self.asm.rowptr, self.asm.col, v)
+        return self.A(self.job.p_list[l])
+
     def spai(self, val):
         return spai_build(self.job.n, self.asm.rowptr, self.asm.col, val, self.pat)
 
@@ -44,7 +52,7 @@ class JobOracle:
         pv1 = None
         for l in pts:
             t0 = time.perf_counter()
-            val, A = self.A(job.p_list[l])
+            val, A = self.A_at(l)
             t1 = time.perf_counter()
             if pv1 is None or policy == "rebuild":
                 pv, _ = self.spai(val)

@@ -21,6 +21,17 @@ def _dev_f64(x, device):
     return torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
 
 
+def _coef(c):
+    """A point given as a coefficient vector: a host double array for the *_c calls."""
+    vals = [float(x) for x in c]
+    return (C.c_double * max(len(vals), 1))(*vals)
+
+
+def _is_coef(s, p):
+    """Points are (s, p), or a coefficient vector passed as s with p None."""
+    return p is None
+
+
 class Context:
     """A device and the HIP stream all calls are ordered on."""
 
@@ -44,28 +55,33 @@ class Context:
 
 
 class Problem:
-    """A parametric system A(s,p) = s^2 M(p) + s D(p) + K(p) (terms by role)."""
+    """A parametric system: A(s,p) = s^2 M(p) + s D(p) + K(p) (terms by role, a dict),
+    or the affine A(c) = sum_t c_t T_t (terms a list; points are coefficient vectors)."""
 
-    def __init__(self, ctx: Context, terms: Dict[str, object]):
+    def __init__(self, ctx: Context, terms):
         """``terms[role] = (rowptr, col, val)`` arrays (host or device) or an object with
-        ``rowptr``, ``col``, ``val`` attributes; roles M0, M1, D0, D1, K0, K1."""
+        ``rowptr``, ``col``, ``val`` attributes; roles M0, M1, D0, D1, K0, K1.  A list
+        of such terms makes an affine problem (pmor_problem_create_affine)."""
         self.ctx = ctx
         dev = ctx.device
         self._keep = []
-        csrs = [None] * L.PMOR_NROLES
-        n = None
-        for r, role in enumerate(L.ROLES):
-            if role not in terms:
+        self.affine = isinstance(terms, (list, tuple))
+        seq = list(terms) if self.affine else [terms.get(role) for role in L.ROLES]
+        csrs = [None] * len(seq)
+        for r, T in enumerate(seq):
+            if T is None:
                 continue
-            T = terms[role]
             rp, ci, va = (T.rowptr, T.col, T.val) if hasattr(T, "rowptr") else T
             rp, ci, va = _dev_i32(rp, dev), _dev_i32(ci, dev), _dev_f64(va, dev)
             self._keep += [rp, ci, va]
-            n = rp.numel() - 1
-            csrs[r] = L.Csr(n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
-        arr = (C.POINTER(L.Csr) * L.PMOR_NROLES)(*[C.pointer(c) if c is not None else None for c in csrs])
+            csrs[r] = L.Csr(rp.numel() - 1, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+        arr = (C.POINTER(L.Csr) * max(len(seq), 1))(*[C.pointer(c) if c is not None else None for c in csrs])
         h = C.c_void_p()
-        L.check(L.pmor_problem_create(ctx.handle, arr, C.byref(h)), "pmor_problem_create")
+        if self.affine:
+            L.check(L.pmor_problem_create_affine(ctx.handle, len(seq), arr, C.byref(h)), "pmor_problem_create_affine")
+        else:
+            L.check(L.pmor_problem_create(ctx.handle, arr, C.byref(h)), "pmor_problem_create")
+        self.nmaps = len(seq)
         self.handle = h
         self._keep = []  # the library copied the terms
         nn, nz = C.c_int32(), C.c_int32()
@@ -88,13 +104,17 @@ class Problem:
         dev = self.ctx.device
         rp = torch.empty(self.n + 1, dtype=torch.int32, device=dev)
         ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
-        mp = torch.empty(L.PMOR_NROLES * max(self.nnz, 1), dtype=torch.int32, device=dev)
+        mp = torch.empty(self.nmaps * max(self.nnz, 1), dtype=torch.int32, device=dev)
         L.check(L.pmor_problem_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), mp.data_ptr()), "pattern")
-        return rp, ci[: self.nnz], mp[: L.PMOR_NROLES * self.nnz].view(L.PMOR_NROLES, self.nnz)
+        return rp, ci[: self.nnz], mp[: self.nmaps * self.nnz].view(self.nmaps, self.nnz)
 
-    def assemble(self, s: float, p: float) -> torch.Tensor:
+    def assemble(self, s, p=None) -> torch.Tensor:
+        """Values of A at (s, p), or at the coefficient vector s when p is None."""
         out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.ctx.device)
-        L.check(L.pmor_assemble(self.handle, float(s), float(p), out.data_ptr()), "pmor_assemble")
+        if _is_coef(s, p):
+            L.check(L.pmor_assemble_c(self.handle, _coef(s), out.data_ptr()), "pmor_assemble_c")
+        else:
+            L.check(L.pmor_assemble(self.handle, float(s), float(p), out.data_ptr()), "pmor_assemble")
         return out[: self.nnz]
 
     def spmm(self, aval: torch.Tensor, X: torch.Tensor, alpha=1.0, beta=0.0, Y=None) -> torch.Tensor:
@@ -110,6 +130,12 @@ class Problem:
         L.check(L.pmor_table2_norms(self.handle, s1, p1, s2, p2, C.byref(a), C.byref(b)), "pmor_table2_norms")
         return a.value, b.value
 
+    def table2_norms_c(self, coef1, coef2):
+        a, b = C.c_double(), C.c_double()
+        L.check(L.pmor_table2_norms_c(self.handle, _coef(coef1), _coef(coef2), C.byref(a), C.byref(b)),
+                "pmor_table2_norms_c")
+        return a.value, b.value
+
     def table2_norms_noalloc(self, s1, p1, s2, p2):
         """As table2_norms, through the entry point that allocates no device memory."""
         a, b = C.c_double(), C.c_double()
@@ -120,36 +146,55 @@ class Problem:
     # --- preconditioner / solve ------------------------------------------
     def spai_build(self, s, p, pattern=None, precision="f64", update="diag", stats=False, approach="first",
                    adapt_ep=0.0):
+        """SPAI at (s, p), or at the coefficient vector s when p is None."""
         return Spai(self, s, p, pattern=pattern, precision=precision, update=update, stats=stats,
                     approach=approach, adapt_ep=adapt_ep)
 
+    def spai_import(self, s, p, rowptr, col, val, precision="f64", update="diag", approach="first", adapt_ep=0.0):
+        """A preconditioner holding the given P (device CSR), anchored at (s, p) or at the
+        coefficient vector s when p is None."""
+        return Spai(self, s, p, precision=precision, update=update, approach=approach, adapt_ep=adapt_ep,
+                    imported=(rowptr, col, val))
+
     def block_solve(self, spai, s, p, B: torch.Tensor, m=30, tol=1e-8, max_cycles=20, X=None, raise_on_error=True):
+        """Block GMRES at (s, p), or at the coefficient vector s when p is None."""
         n, k = B.shape
         if X is None:
             X = torch.empty((n, k), dtype=torch.float64, device=B.device)
         st = L.Stats()
         o = L.SolveOpts(m, max_cycles, tol)
-        rc = L.block_solve(self.handle, spai.handle if spai is not None else None, float(s), float(p), B.data_ptr(),
-                           B.stride(0), k, X.data_ptr(), X.stride(0), C.byref(o), C.byref(st))
+        sh = spai.handle if spai is not None else None
+        if _is_coef(s, p):
+            rc = L.block_solve_c(self.handle, sh, _coef(s), B.data_ptr(), B.stride(0), k, X.data_ptr(), X.stride(0),
+                                 C.byref(o), C.byref(st))
+        else:
+            rc = L.block_solve(self.handle, sh, float(s), float(p), B.data_ptr(), B.stride(0), k, X.data_ptr(),
+                               X.stride(0), C.byref(o), C.byref(st))
         if raise_on_error:
             L.check(rc, "block_solve")
         return X, st.as_dict(), rc
 
-    def sequence_solve(self, B, s_list: Sequence[float], p_list: Sequence[float], policy="update",
+    def sequence_solve(self, B, s_list: Sequence[float] = None, p_list: Sequence[float] = None, policy="update",
                        pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
-                       raise_on_error=True, approach="first", reanchor_tol=0.0, adapt_ep=0.0):
+                       raise_on_error=True, approach="first", reanchor_tol=0.0, adapt_ep=0.0, coefs=None):
+        """The sequence at the points (s_list[l], p_list[l]), or at the rows of ``coefs``."""
         n, k = B.shape
-        npts = len(p_list)
+        npts = len(coefs) if coefs is not None else len(p_list)
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
-        sl = (C.c_double * npts)(*[float(x) for x in s_list])
-        pl = (C.c_double * npts)(*[float(x) for x in p_list])
         so = _spai_opts(pattern, precision, update, self.ctx.device, self, approach, reanchor_tol, adapt_ep)
         vo = L.SolveOpts(m, max_cycles, tol)
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
-        rc = L.pmor_sequence_solve(self.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(),
-                                   X.stride(1), pol, C.byref(so), C.byref(vo), stats)
+        if coefs is not None:
+            cf = _coef([x for row in coefs for x in row])
+            rc = L.pmor_sequence_solve_c(self.handle, B.data_ptr(), B.stride(0), k, cf, npts, X.data_ptr(),
+                                         X.stride(1), pol, C.byref(so), C.byref(vo), stats)
+        else:
+            sl = (C.c_double * npts)(*[float(x) for x in s_list])
+            pl = (C.c_double * npts)(*[float(x) for x in p_list])
+            rc = L.pmor_sequence_solve(self.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(),
+                                       X.stride(1), pol, C.byref(so), C.byref(vo), stats)
         if raise_on_error:
             L.check(rc, "pmor_sequence_solve")
             return X, [s.as_dict() for s in stats]
@@ -158,18 +203,26 @@ class Problem:
 
 def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_error=True):
     """Solve independent systems together (pmor_batch_solve).  ``items``: sequence of
-    ``(problem, spai_or_None, s, p, B)`` or ``(problem, spai, s, p, B, X)``.
+    ``(problem, spai_or_None, s, p, B)`` or ``(problem, spai, s, p, B, X)``; with p None,
+    s is the point's coefficient vector.
     Returns (list of X, list of stats dicts, list of status codes, rc)."""
     n_it = len(items)
     arr = (L.BatchItem * max(n_it, 1))()
     Xs = []
+    keep = []
     for i, itm in enumerate(items):
         pb, sp, s, p, B = itm[:5]
         X = itm[5] if len(itm) > 5 and itm[5] is not None else torch.empty(B.shape, dtype=torch.float64,
                                                                               device=B.device)
         Xs.append(X)
+        cf = None
+        if _is_coef(s, p):
+            cf = _coef(s)
+            keep.append(cf)
+            s, p = 0.0, 0.0
         arr[i] = L.BatchItem(pb.handle, sp.handle if sp is not None else None, float(s), float(p), B.data_ptr(),
-                             B.stride(0), B.shape[1], X.data_ptr(), X.stride(0))
+                             B.stride(0), B.shape[1], X.data_ptr(), X.stride(0),
+                             C.cast(cf, C.POINTER(C.c_double)) if cf is not None else None)
     stats = (L.Stats * max(n_it, 1))()
     status = (C.c_int32 * max(n_it, 1))()
     o = L.SolveOpts(m, max_cycles, tol)
@@ -203,30 +256,51 @@ class Spai:
     default; approach="second" anchors each update at the previous point)."""
 
     def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False,
-                 approach="first", adapt_ep=0.0):
+                 approach="first", adapt_ep=0.0, imported=None):
         self.pb = pb
         self.update_kind = update
         self.approach = approach
         o = _spai_opts(pattern, precision, update, pb.ctx.device, self, approach, adapt_ep=adapt_ep)
         h = C.c_void_p()
         st = L.Stats()
-        rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), C.byref(st) if stats else None)
+        sb = C.byref(st) if stats else None
+        if imported is not None:
+            rp, ci, va = (t.contiguous() for t in imported)
+            args = (ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr(), C.byref(o), C.byref(h))
+            rc = (L.spai_import_c(pb.handle, _coef(s), *args) if _is_coef(s, p)
+                  else L.spai_import(pb.handle, float(s), float(p), *args))
+            where = "spai_import"
+        elif _is_coef(s, p):
+            rc = L.spai_build_c(pb.handle, _coef(s), C.byref(o), C.byref(h), sb)
+            where = "spai_build_c"
+        else:
+            rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), sb)
+            where = "spai_build"
         self.handle = h if h.value else None
         self.last_stats = st.as_dict() if stats else None
-        L.check(rc, "spai_build")
+        L.check(rc, where)
         nz, mj, mi = C.c_int32(), C.c_int32(), C.c_int32()
         L.check(L.spai_info(self.handle, C.byref(nz), C.byref(mj), C.byref(mi)), "spai_info")
         self.nnzP, self.maxJ, self.maxI = nz.value, mj.value, mi.value
 
-    def update(self, s, p, stats=False):
+    def update(self, s, p=None, stats=False):
+        """Update to (s, p), or to the coefficient vector s when p is None."""
         st = L.Stats()
-        L.check(L.spai_update(self.handle, float(s), float(p), C.byref(st) if stats else None), "spai_update")
+        sb = C.byref(st) if stats else None
+        if _is_coef(s, p):
+            L.check(L.spai_update_c(self.handle, _coef(s), sb), "spai_update_c")
+        else:
+            L.check(L.spai_update(self.handle, float(s), float(p), sb), "spai_update")
         self.last_stats = st.as_dict() if stats else None
         return self.last_stats
 
-    def rebuild(self, s, p, stats=False):
+    def rebuild(self, s, p=None, stats=False):
         st = L.Stats()
-        L.check(L.spai_rebuild(self.handle, float(s), float(p), C.byref(st) if stats else None), "spai_rebuild")
+        sb = C.byref(st) if stats else None
+        if _is_coef(s, p):
+            L.check(L.spai_rebuild_c(self.handle, _coef(s), sb), "spai_rebuild_c")
+        else:
+            L.check(L.spai_rebuild(self.handle, float(s), float(p), sb), "spai_rebuild")
         self.last_stats = st.as_dict() if stats else None
         return self.last_stats
 
@@ -283,17 +357,24 @@ class Server:
         self.handle = h
         self.jobs = {}
 
-    def submit(self, pb: Problem, B: torch.Tensor, s_list, p_list, policy="update", X=None):
-        """Queue a job; returns its id.  X (npts, n, k) is written when the job is reported done."""
+    def submit(self, pb: Problem, B: torch.Tensor, s_list=None, p_list=None, policy="update", X=None, coefs=None):
+        """Queue a job at the points (s_list, p_list) or the rows of ``coefs``; returns its id.
+        X (npts, n, k) is written when the job is reported done."""
         n, k = B.shape
-        npts = len(p_list)
+        npts = len(coefs) if coefs is not None else len(p_list)
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
-        sl = (C.c_double * npts)(*[float(x) for x in s_list])
-        pl = (C.c_double * npts)(*[float(x) for x in p_list])
+        if coefs is not None:
+            cf = _coef([x for row in coefs for x in row])
+            sl = pl = None
+        else:
+            cf = None
+            sl = (C.c_double * npts)(*[float(x) for x in s_list])
+            pl = (C.c_double * npts)(*[float(x) for x in p_list])
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
-        job = L.Job(pb.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(), X.stride(1), pol, stats)
+        job = L.Job(pb.handle, B.data_ptr(), B.stride(0), k, sl, pl, npts, X.data_ptr(), X.stride(1), pol, stats,
+                    C.cast(cf, C.POINTER(C.c_double)) if cf is not None else None)
         jid = C.c_int64()
         L.check(L.pmor_server_submit(self.handle, C.byref(job), C.byref(jid)), "pmor_server_submit")
         self.jobs[jid.value] = {"pb": pb, "B": B, "X": X, "stats": stats, "s": sl, "p": pl}

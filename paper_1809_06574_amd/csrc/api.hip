@@ -109,19 +109,36 @@ static void prof_collect(pmor_ctx* c) {
   P.ent.clear();
 }
 
-int ensure_assembled(pmor_problem* pb, double s, double p) {
-  if (pb->have_cur && pb->cur_s == s && pb->cur_p == p) return PMOR_OK;
-  double c[PMOR_NROLES];
-  role_coefs(s, p, c);
-  PMOR_TRY(launch_assemble(pb, c, pb->aval, pb->ctx->stream));
-  PMOR_TRY(to_sell(pb->sell, pb->aval, pb->aval_s, pb->ctx->stream));
-  pb->cur_s = s;
-  pb->cur_p = p;
-  pb->have_cur = true;
+static bool is_fin(double x) { return std::isfinite(x); }
+
+int point_coef(const pmor_problem* pb, const double* coef, Point* out) {
+  if (!coef) return fail(PMOR_EINVAL, "coefficient vector is NULL");
+  *out = Point{};
+  for (int r = 0; r < pb->ncoef; ++r) {
+    const int t = pb->coef_slot[r];
+    if (t < 0) continue;  // an absent role
+    if (!is_fin(coef[r])) return fail(PMOR_EINVAL, "coefficient " + std::to_string(r) + " is not finite");
+    out->c[t] = coef[r];
+  }
   return PMOR_OK;
 }
 
-static bool is_fin(double x) { return std::isfinite(x); }
+int point_sp(const pmor_problem* pb, double s, double p, Point* out) {
+  if (pb->affine) return fail(PMOR_EINVAL, "an affine problem takes its points as coefficient vectors (*_c calls)");
+  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
+  double c[PMOR_NROLES];
+  role_coefs(s, p, c);
+  return point_coef(pb, c, out);
+}
+
+int ensure_assembled(pmor_problem* pb, const Point& pt) {
+  if (pb->have_cur && same_point(pb->cur, pt, pb->nterms)) return PMOR_OK;
+  PMOR_TRY(launch_assemble(pb, pt, pb->aval, pb->ctx->stream));
+  PMOR_TRY(to_sell(pb->sell, pb->aval, pb->aval_s, pb->ctx->stream));
+  pb->cur = pt;
+  pb->have_cur = true;
+  return PMOR_OK;
+}
 
 struct Timer {
   hipStream_t s;
@@ -185,12 +202,12 @@ static int dfill(double* a, int64_t n, double v, hipStream_t s) {
   return PMOR_OK;
 }
 
-// P_1 of A(s,p) into h (anchor moved to (s,p))
-static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
+// P_1 of A(pt) into h (anchor moved to pt)
+static int build_into(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   pmor_problem* pb = h->pb;
   hipStream_t st = pb->ctx->stream;
   Timer ta(pb->ctx, stats != nullptr);
-  PMOR_TRY(ensure_assembled(pb, s, p));
+  PMOR_TRY(ensure_assembled(pb, pt));
   const double t_asm = ta.stop();
   Timer tp(pb->ctx, stats != nullptr);
   PMOR_TRY(dcopy(pb->aval, h->aval1, pb->nnz, st));
@@ -202,8 +219,7 @@ static int build_into(pmor_spai* h, double s, double p, pmor_stats* stats) {
   if (h->opts.update == PMOR_UPD_DIAG) PMOR_TRY(dfill(h->Qval, pb->n, 1.0, st));
   h->q_active = false;
   h->d_active = false;
-  h->s1 = s;
-  h->p1 = p;
+  h->pt1 = pt;
   const double t_pre = tp.stop();
   if (stats) {
     stats->bad_column = bad;
@@ -302,7 +318,7 @@ static int scratch_setup(int device) {
 }
 
 struct T2Coefs {
-  double c1[PMOR_NROLES], c2[PMOR_NROLES];
+  double c1[PMOR_TMAX], c2[PMOR_TMAX];
   int nt;
 };
 
@@ -458,13 +474,20 @@ int pmor_ctx_set_stream(pmor_ctx* c, void* hip_stream) {
   return PMOR_OK;
 }
 
-int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_problem** out) {
+}  // extern "C"
+
+namespace pmor {
+// shared by both create calls: terms[0..count), NULL entries absent (roles only)
+static int problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, int count, bool affine, pmor_problem** out) {
   if (!ctx || !terms || !out) return fail(PMOR_EINVAL, "NULL argument");
   *out = nullptr;
   int n = -1;
-  for (int r = 0; r < PMOR_NROLES; ++r) {
+  for (int r = 0; r < count; ++r) {
     const pmor_csr* T = terms[r];
-    if (!T) continue;
+    if (!T) {
+      if (affine) return fail(PMOR_EINVAL, "term " + std::to_string(r) + " is NULL");
+      continue;
+    }
     if (T->n <= 0) return fail(PMOR_EINVAL, "term dimension must be positive");
     if (T->nnz < 0) return fail(PMOR_EINVAL, "negative nnz");
     if (!T->rowptr || (T->nnz > 0 && (!T->col || !T->val))) return fail(PMOR_EINVAL, "term with NULL arrays");
@@ -477,13 +500,32 @@ int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_proble
   pb->ctx = ctx;
   ctx_ref(ctx);
   pb->n = n;
-  int rc = build_union_pattern(pb, terms);
+  pb->affine = affine;
+  int rc = build_union_pattern(pb, terms, count);
   if (rc != PMOR_OK) {
-    pmor_problem_destroy(pb);
+    pb_unref(pb);
     return rc;
   }
   *out = pb;
   return PMOR_OK;
+}
+
+// the point of a batch item or job: coefficients when given, else (s, p)
+static int point_of(const pmor_problem* pb, const double* coef, double s, double p, Point* out) {
+  return coef ? point_coef(pb, coef, out) : point_sp(pb, s, p, out);
+}
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_problem** out) {
+  return problem_create(ctx, terms, PMOR_NROLES, false, out);
+}
+
+int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, pmor_problem** out) {
+  if (out) *out = nullptr;
+  if (nterms < 1 || nterms > PMOR_TMAX) return fail(PMOR_EINVAL, "nterms must be in 1..PMOR_TMAX");
+  return problem_create(ctx, terms, nterms, true, out);
 }
 
 void pmor_problem_destroy(pmor_problem* pb) {
@@ -503,25 +545,23 @@ int pmor_problem_pattern(const pmor_problem* pb, int32_t* rowptr, int32_t* col, 
   if (rowptr) PMOR_HIP(hipMemcpyAsync(rowptr, pb->rowptr, sizeof(int32_t) * (pb->n + 1), hipMemcpyDeviceToDevice, s));
   if (col) PMOR_HIP(hipMemcpyAsync(col, pb->col, sizeof(int32_t) * pb->nnz, hipMemcpyDeviceToDevice, s));
   if (maps)
-    PMOR_HIP(hipMemcpyAsync(maps, pb->maps, sizeof(int32_t) * PMOR_NROLES * (size_t)pb->nnz, hipMemcpyDeviceToDevice, s));
+    PMOR_HIP(hipMemcpyAsync(maps, pb->maps, sizeof(int32_t) * pb->nmaps * (size_t)pb->nnz, hipMemcpyDeviceToDevice, s));
   PMOR_HIP(hipStreamSynchronize(s));
   return PMOR_OK;
 }
 
-int pmor_assemble(pmor_problem* pb, double s, double p, double* val) {
-  if (!pb || !val) return fail(PMOR_EINVAL, "NULL argument");
-  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
-  PMOR_TRY(ensure_assembled(pb, s, p));
+}  // extern "C"
+
+namespace pmor {
+static int assemble_pt(pmor_problem* pb, const Point& pt, double* val) {
+  PMOR_TRY(ensure_assembled(pb, pt));
   PMOR_TRY(dcopy(pb->aval, val, pb->nnz, pb->ctx->stream));
   PMOR_HIP(hipStreamSynchronize(pb->ctx->stream));
   return PMOR_OK;
 }
 
-int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts, pmor_spai** out,
-               pmor_stats* stats) {
-  if (!pb || !out) return fail(PMOR_EINVAL, "NULL argument");
-  *out = nullptr;
-  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
+// a handle with its sets and buffers, nothing computed yet (the options checked)
+static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** out) {
   pmor_spai_opts o{};
   o.pattern = PMOR_PAT_A;
   o.precision = PMOR_F64;
@@ -543,6 +583,7 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   h->pb = pb;
   pb_ref(pb);
   h->opts = o;
+  *out = h;
   int rc = build_spai_sets(h);
   if (rc == PMOR_OK) {
     const int64_t n = pb->n;
@@ -559,8 +600,20 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
       ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), pb->ctx->stream) ==
                hipSuccess &&
            dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * 8, pb->ctx->stream) == hipSuccess;
-    rc = ok ? build_into(h, s, p, stats) : fail(PMOR_ENOMEM, "preconditioner allocation failed");
+    if (!ok) rc = fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
+  if (rc != PMOR_OK) {
+    spai_release(h);
+    *out = nullptr;
+  }
+  return rc;
+}
+
+static int spai_build_pt(pmor_problem* pb, const Point& pt, const pmor_spai_opts* opts, pmor_spai** out,
+                         pmor_stats* stats) {
+  pmor_spai* h = nullptr;
+  PMOR_TRY(spai_new(pb, opts, &h));
+  const int rc = build_into(h, pt, stats);
   if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
     spai_release(h);
     return rc;
@@ -569,12 +622,10 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
   return rc;
 }
 
-int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
-  if (!h) return fail(PMOR_EINVAL, "handle is NULL");
-  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
+static int spai_update_pt(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   pmor_problem* pb = h->pb;
   Timer ta(pb->ctx, stats != nullptr);
-  PMOR_TRY(ensure_assembled(pb, s, p));
+  PMOR_TRY(ensure_assembled(pb, pt));
   const double t_asm = ta.stop();
   Timer tp(pb->ctx, stats != nullptr);
   int32_t bad = -1;
@@ -601,10 +652,134 @@ int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
   return PMOR_OK;
 }
 
+// a handle holding a given P (CSR on the device, pattern with the diagonal) anchored at pt
+static int spai_import_pt(pmor_problem* pb, const Point& pt, int32_t nnzP, const int32_t* rowptr, const int32_t* col,
+                          const double* val, const pmor_spai_opts* opts, pmor_spai** out) {
+  if (nnzP < pb->n) return fail(PMOR_EINVAL, "P must hold the diagonal (nnzP >= n)");
+  hipStream_t st = pb->ctx->stream;
+  PMOR_TRY(check_csr(pb->n, nnzP, rowptr, col, st));
+  // the explicit pattern of the handle is P's pattern, as columns (CSC)
+  int32_t *cp = nullptr, *rw = nullptr, *sl = nullptr;
+  int maxc = 0;
+  PMOR_TRY(transpose_pattern(pb->n, nnzP, rowptr, col, &cp, &rw, &sl, &maxc, st));
+  pmor_spai_opts o{};
+  o.precision = PMOR_F64;
+  o.update = PMOR_UPD_DIAG;
+  if (opts) o = *opts;
+  o.pattern = PMOR_PAT_EXPLICIT;
+  o.nnz_explicit = nnzP;
+  o.pat_colptr = cp;
+  o.pat_row = rw;
+  pmor_spai* h = nullptr;
+  int rc = spai_new(pb, &o, &h);
+  dfree(sl, st);
+  if (rc == PMOR_OK) {
+    h->opts.pat_colptr = nullptr;  // the caller's-pattern pointers are not kept
+    h->opts.pat_row = nullptr;
+    rc = ensure_assembled(pb, pt);
+  }
+  // the handle's CSR of P is the transpose of the CSC pattern: P's own CSR when
+  // the input is sorted (checked by the explicit-pattern validation)
+  if (rc == PMOR_OK) rc = dcopy(pb->aval, h->aval1, pb->nnz, st);
+  if (rc == PMOR_OK) rc = dcopy(val, h->P1val, nnzP, st);
+  if (rc == PMOR_OK) rc = dcopy(val, h->Pval, nnzP, st);
+  if (rc == PMOR_OK) rc = to_sell(h->psell, h->P1val, h->P1val_s, st);
+  if (rc == PMOR_OK && h->opts.update == PMOR_UPD_DIAG) rc = dfill(h->Qval, pb->n, 1.0, st);
+  if (rc == PMOR_OK) rc = dfill(h->rho, pb->n, 0.0, st);
+  if (rc == PMOR_OK) {
+    h->pt1 = pt;
+    h->q_active = h->d_active = false;
+    if (hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
+  }
+  dfree(cp, st);
+  dfree(rw, st);
+  if (rc != PMOR_OK) {
+    spai_release(h);
+    return rc;
+  }
+  *out = h;
+  return PMOR_OK;
+}
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_assemble(pmor_problem* pb, double s, double p, double* val) {
+  if (!pb || !val) return fail(PMOR_EINVAL, "NULL argument");
+  Point pt;
+  PMOR_TRY(point_sp(pb, s, p, &pt));
+  return assemble_pt(pb, pt, val);
+}
+
+int pmor_assemble_c(pmor_problem* pb, const double* coef, double* val) {
+  if (!pb || !val) return fail(PMOR_EINVAL, "NULL argument");
+  Point pt;
+  PMOR_TRY(point_coef(pb, coef, &pt));
+  return assemble_pt(pb, pt, val);
+}
+
+int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts, pmor_spai** out,
+               pmor_stats* stats) {
+  if (!pb || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  Point pt;
+  PMOR_TRY(point_sp(pb, s, p, &pt));
+  return spai_build_pt(pb, pt, opts, out, stats);
+}
+
+int spai_build_c(pmor_problem* pb, const double* coef, const pmor_spai_opts* opts, pmor_spai** out,
+                 pmor_stats* stats) {
+  if (!pb || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  Point pt;
+  PMOR_TRY(point_coef(pb, coef, &pt));
+  return spai_build_pt(pb, pt, opts, out, stats);
+}
+
+int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats) {
+  if (!h) return fail(PMOR_EINVAL, "handle is NULL");
+  Point pt;
+  PMOR_TRY(point_sp(h->pb, s, p, &pt));
+  return spai_update_pt(h, pt, stats);
+}
+
+int spai_update_c(pmor_spai* h, const double* coef, pmor_stats* stats) {
+  if (!h) return fail(PMOR_EINVAL, "handle is NULL");
+  Point pt;
+  PMOR_TRY(point_coef(h->pb, coef, &pt));
+  return spai_update_pt(h, pt, stats);
+}
+
 int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats) {
   if (!h) return fail(PMOR_EINVAL, "handle is NULL");
-  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
-  return build_into(h, s, p, stats);
+  Point pt;
+  PMOR_TRY(point_sp(h->pb, s, p, &pt));
+  return build_into(h, pt, stats);
+}
+
+int spai_rebuild_c(pmor_spai* h, const double* coef, pmor_stats* stats) {
+  if (!h) return fail(PMOR_EINVAL, "handle is NULL");
+  Point pt;
+  PMOR_TRY(point_coef(h->pb, coef, &pt));
+  return build_into(h, pt, stats);
+}
+
+int spai_import(pmor_problem* pb, double s, double p, int32_t nnzP, const int32_t* rowptr, const int32_t* col,
+                const double* val, const pmor_spai_opts* opts, pmor_spai** out) {
+  if (!pb || !rowptr || !col || !val || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  Point pt;
+  PMOR_TRY(point_sp(pb, s, p, &pt));
+  return spai_import_pt(pb, pt, nnzP, rowptr, col, val, opts, out);
+}
+
+int spai_import_c(pmor_problem* pb, const double* coef, int32_t nnzP, const int32_t* rowptr, const int32_t* col,
+                  const double* val, const pmor_spai_opts* opts, pmor_spai** out) {
+  if (!pb || !rowptr || !col || !val || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  Point pt;
+  PMOR_TRY(point_coef(pb, coef, &pt));
+  return spai_import_pt(pb, pt, nnzP, rowptr, col, val, opts, out);
 }
 
 int spai_info(const pmor_spai* h, int32_t* nnzP, int32_t* maxJ, int32_t* maxI) {
@@ -652,24 +827,45 @@ int spai_export_sets(const pmor_spai* h, int32_t* J_colptr, int32_t* J_row, int6
 
 void spai_free(pmor_spai* h) { spai_release(h); }
 
-int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p, const double* B, int64_t ldb, int32_t k,
-                double* X, int64_t ldx, const pmor_solve_opts* opts, pmor_stats* stats) {
+}  // extern "C"
+
+namespace pmor {
+static int block_solve_pt(pmor_problem* pb, const pmor_spai* h, const Point* pt, int pt_rc, const double* B,
+                          int64_t ldb, int32_t k, double* X, int64_t ldx, const pmor_solve_opts* opts,
+                          pmor_stats* stats) {
   if (!pb || !B || !X) return fail(PMOR_EINVAL, "NULL argument");
   if (k < 1 || k > PMOR_KMAX) return fail(PMOR_EINVAL, "k must be in 1..16");
   if (ldb < k || ldx < k) return fail(PMOR_EINVAL, "leading dimension smaller than k");
   if (h && h->pb != pb) return fail(PMOR_EINVAL, "preconditioner belongs to another problem");
-  if (!is_fin(s) || !is_fin(p)) return fail(PMOR_EINVAL, "s and p must be finite");
+  if (pt_rc != PMOR_OK) return pt_rc;
   pmor_solve_opts o;
   PMOR_TRY(solve_opts_of(opts, &o));
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   auto t0 = std::chrono::steady_clock::now();
-  PMOR_TRY(ensure_assembled(pb, s, p));
+  PMOR_TRY(ensure_assembled(pb, *pt));
   SolveItem it = item_of(pb, h, pb->aval, pb->aval_s, B, ldb, k, X, ldx, stats);
   PMOR_TRY(krylov_batch(pb->ctx, &it, 1, o));
   if (stats) {
     stats->t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return status_error(it.status);
+}
+}  // namespace pmor
+
+extern "C" {
+
+int block_solve(pmor_problem* pb, const pmor_spai* h, double s, double p, const double* B, int64_t ldb, int32_t k,
+                double* X, int64_t ldx, const pmor_solve_opts* opts, pmor_stats* stats) {
+  Point pt{};
+  const int prc = pb ? point_sp(pb, s, p, &pt) : PMOR_OK;
+  return block_solve_pt(pb, h, &pt, prc, B, ldb, k, X, ldx, opts, stats);
+}
+
+int block_solve_c(pmor_problem* pb, const pmor_spai* h, const double* coef, const double* B, int64_t ldb, int32_t k,
+                  double* X, int64_t ldx, const pmor_solve_opts* opts, pmor_stats* stats) {
+  Point pt{};
+  const int prc = pb ? point_coef(pb, coef, &pt) : PMOR_OK;
+  return block_solve_pt(pb, h, &pt, prc, B, ldb, k, X, ldx, opts, stats);
 }
 
 int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems, const pmor_solve_opts* opts,
@@ -685,7 +881,11 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
     if (b.k < 1 || b.k > PMOR_KMAX || b.ldb < b.k || b.ldx < b.k)
       return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": bad k or leading dimension");
     if (b.h && b.h->pb != b.pb) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": foreign preconditioner");
-    if (!is_fin(b.s) || !is_fin(b.p)) return fail(PMOR_EINVAL, "item " + std::to_string(i) + ": s, p not finite");
+  }
+  std::vector<Point> pts(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    const int prc = point_of(items[i].pb, items[i].coef, items[i].s, items[i].p, &pts[i]);
+    if (prc != PMOR_OK) return fail(prc, "item " + std::to_string(i) + ": " + g_last_error);
   }
   if (nitems == 0) return PMOR_OK;
   PMOR_HIP(hipSetDevice(ctx->device));
@@ -699,7 +899,7 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
     const double* aval = nullptr;
     const double* aval_s = nullptr;
     for (int q = 0; q < i; ++q)
-      if (items[q].pb == b.pb && items[q].s == b.s && items[q].p == b.p) {
+      if (items[q].pb == b.pb && same_point(pts[q], pts[i], b.pb->nterms)) {
         aval = it[q].aval;
         aval_s = it[q].aval_s;
         break;
@@ -709,7 +909,7 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
       for (int q = 0; q < i; ++q)
         if (items[q].pb == b.pb) first = false;
       if (first) {
-        rc = ensure_assembled(b.pb, b.s, b.p);
+        rc = ensure_assembled(b.pb, pts[i]);
         aval = b.pb->aval;
         aval_s = b.pb->aval_s;
       } else {
@@ -721,9 +921,7 @@ int pmor_batch_solve(pmor_ctx* ctx, const pmor_batch_item* items, int32_t nitems
           break;
         }
         extra.push_back(buf);
-        double c[PMOR_NROLES];
-        role_coefs(b.s, b.p, c);
-        rc = launch_assemble(b.pb, c, buf, st);
+        rc = launch_assemble(b.pb, pts[i], buf, st);
         aval = buf;
         if (rc == PMOR_OK && cap > 0) {
           double* bs = buf + std::max<int64_t>(b.pb->nnz, 1);
@@ -825,8 +1023,8 @@ static SolveItem point_item(pmor_problem* pb, pmor_spai* h, const double* Al, co
 // q_l in launches of PTS_MAX points; P_l = diag(q_l) P_1 stays factored and
 // the engine scales the rows of P_1 X.  The batch's assembly and update times
 // are shared evenly among its points in stats.
-static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_list, const double* p_list, int l0,
-                               int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
+static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const Point* pts, int l0, int cnt, const double* B,
+                               int64_t ldb, int k, double* X, int64_t ldx,
                                pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items,
                                int* bad) {
   hipStream_t st = pb->ctx->stream;
@@ -843,10 +1041,8 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
   rec(0);
   for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
     const int m = std::min(PTS_MAX, cnt - c0);
-    rc = sell ? launch_assemble_pts(pb, s_list + l0 + c0, p_list + l0 + c0, m, &pb->sell,
-                                    sb.aval_s + (int64_t)c0 * sb.capA, sb.capA, st)
-              : launch_assemble_pts(pb, s_list + l0 + c0, p_list + l0 + c0, m, nullptr,
-                                    sb.aval + (int64_t)c0 * pb->nnz, pb->nnz, st);
+    rc = sell ? launch_assemble_pts(pb, pts + l0 + c0, m, &pb->sell, sb.aval_s + (int64_t)c0 * sb.capA, sb.capA, st)
+              : launch_assemble_pts(pb, pts + l0 + c0, m, nullptr, sb.aval + (int64_t)c0 * pb->nnz, pb->nnz, st);
   }
   rec(1);
   if (rc == PMOR_OK) {
@@ -857,14 +1053,14 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
     // anchors A(l-1): the points in order, the running scale carried across launches
     for (int c0 = std::max(0, 1 - l0); c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
       const int m = std::min(PTS_MAX, cnt - c0);
-      rc = launch_update_diag_chain(h, s_list, p_list, l0 + c0, m, sb.carry, sb.q + (int64_t)c0 * n,
-                                    sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+      rc = launch_update_diag_chain(h, pts, l0 + c0, m, sb.carry, sb.q + (int64_t)c0 * n, sb.rho + (int64_t)c0 * n,
+                                    sb.bad + c0, st);
     }
   } else {
     for (int c0 = 0; c0 < cnt && rc == PMOR_OK; c0 += PTS_MAX) {
       const int m = std::min(PTS_MAX, cnt - c0);
-      rc = launch_update_diag_pts(h, s_list + l0 + c0, p_list + l0 + c0, m, sb.q + (int64_t)c0 * n,
-                                  sb.rho + (int64_t)c0 * n, sb.bad + c0, st);
+      rc = launch_update_diag_pts(h, pts + l0 + c0, m, sb.q + (int64_t)c0 * n, sb.rho + (int64_t)c0 * n, sb.bad + c0,
+                                  st);
     }
   }
   if (rc == PMOR_OK && stats) rc = sumsq_pts(sb.rho, n, cnt, sb.fro, 260, st);
@@ -924,11 +1120,11 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const double* s_l
 // column of the point's least-squares problems, or -1.  stats (the sequence's
 // array, may be NULL) gets the assembly and preconditioner times, the residual
 // norm and bad_column of each point.  Synchronises the stream.
-static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const double* s_list, const double* p_list,
-                          int l0, int cnt, const double* B, int64_t ldb, int k, double* X, int64_t ldx,
-                          pmor_stats* stats, const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
+static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const Point* pts, int l0, int cnt,
+                          const double* B, int64_t ldb, int k, double* X, int64_t ldx, pmor_stats* stats,
+                          const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
   if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG)
-    return prepare_points_diag(pb, h, s_list, p_list, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, items, bad);
+    return prepare_points_diag(pb, h, pts, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, items, bad);
   hipStream_t st = pb->ctx->stream;
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
   std::vector<hipEvent_t> ev;
@@ -948,9 +1144,7 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
     bad[t] = -1;
     double* Al = sb.aval + (int64_t)t * nnz;
     double* PQ = sb.pq + (int64_t)t * nnzP;
-    double c[PMOR_NROLES];
-    role_coefs(s_list[l], p_list[l], c);
-    rc = launch_assemble(pb, c, Al, st);
+    rc = launch_assemble(pb, pts[l], Al, st);
     double* Al_s = sb.capA > 0 ? sb.aval_s + (int64_t)t * sb.capA : nullptr;
     double* PQ_s = sb.capP > 0 ? sb.pq_s + (int64_t)t * sb.capP : nullptr;
     if (rc == PMOR_OK && Al_s) rc = to_sell(pb->sell, Al, Al_s, st);
@@ -1005,14 +1199,21 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const doub
   return rc;
 }
 
+// the checks of a sequence and its points: coefs (npts x pb->ncoef) when given,
+// else (s_list[l], p_list[l])
 static int sequence_checks(const pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
-                           const double* p_list, int32_t npts, const double* X, int64_t ldx, int32_t policy) {
-  if (!pb || !B || !X || !s_list || !p_list) return fail(PMOR_EINVAL, "NULL argument");
+                           const double* p_list, const double* coefs, int32_t npts, const double* X, int64_t ldx,
+                           int32_t policy, std::vector<Point>* pts) {
+  if (!pb || !B || !X || (!coefs && (!s_list || !p_list))) return fail(PMOR_EINVAL, "NULL argument");
   if (npts < 1) return fail(PMOR_EINVAL, "npts must be positive");
   if (policy != PMOR_REBUILD && policy != PMOR_UPDATE) return fail(PMOR_EINVAL, "bad policy");
   if (k < 1 || k > PMOR_KMAX || ldb < k || ldx < k) return fail(PMOR_EINVAL, "bad k or leading dimension");
-  for (int l = 0; l < npts; ++l)
-    if (!is_fin(s_list[l]) || !is_fin(p_list[l])) return fail(PMOR_EINVAL, "s and p must be finite");
+  pts->assign(npts, Point{});
+  for (int l = 0; l < npts; ++l) {
+    const int rc = coefs ? point_coef(pb, coefs + (int64_t)l * pb->ncoef, &(*pts)[l])
+                         : point_sp(pb, s_list[l], p_list[l], &(*pts)[l]);
+    if (rc != PMOR_OK) return fail(rc, "point " + std::to_string(l) + ": " + g_last_error);
+  }
   return PMOR_OK;
 }
 
@@ -1022,8 +1223,7 @@ static int sequence_checks(const pmor_problem* pb, const double* B, int64_t ldb,
 // a.  The misfit is the root sum of the update's column residuals (formed for
 // up to PTS_MAX points per launch, read back once per launch); a non-finite
 // misfit also re-anchors (the rebuild there reports a singular column).
-static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_list, int npts, double tol,
-                        std::vector<int>* anchors) {
+static int plan_anchors(pmor_problem* pb, const Point* pts, int npts, double tol, std::vector<int>* anchors) {
   hipStream_t st = pb->ctx->stream;
   const int n = pb->n;
   const int64_t nnz = pb->nnz;
@@ -1050,9 +1250,7 @@ static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_
     return fail(PMOR_ENOMEM, "allocation of the re-anchoring scratch failed");
   int a = 0, l = 1;
   while (l < npts) {
-    double c[PMOR_NROLES];
-    role_coefs(s_list[a], p_list[a], c);
-    PMOR_TRY(launch_assemble(pb, c, Aa, st));
+    PMOR_TRY(launch_assemble(pb, pts[a], Aa, st));
     PMOR_TRY(sumsq(Aa, nnz, nrm, st));
     double na2 = 0.0;
     PMOR_HIP(hipMemcpyAsync(&na2, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1060,7 +1258,7 @@ static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_
     int found = -1;
     for (int c0 = l; c0 < npts && found < 0; c0 += PTS_MAX) {
       const int m = std::min(PTS_MAX, npts - c0);
-      PMOR_TRY(launch_update_diag_pts_anchor(pb, Aa, s_list + c0, p_list + c0, m, q, rho, bad, st));
+      PMOR_TRY(launch_update_diag_pts_anchor(pb, Aa, pts + c0, m, q, rho, bad, st));
       PMOR_TRY(sumsq_pts(rho, n, m, fro, 260, st));
       std::vector<double> f((size_t)m * 260);
       PMOR_HIP(hipMemcpyAsync(f.data(), fro, sizeof(double) * 260 * m, hipMemcpyDeviceToHost, st));
@@ -1079,8 +1277,8 @@ static int plan_anchors(pmor_problem* pb, const double* s_list, const double* p_
 // One run of a sequence: P_1 built at its first point, the others updated
 // from it (or rebuilt).  lbase: the run's first point in the caller's sequence
 // (stats[].anchor, messages); t0: the call's start.
-static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
-                        const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
+static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const Point* pts, int32_t npts,
+                        double* X, int64_t ldx, int32_t policy,
                         const pmor_spai_opts* sopts, const pmor_solve_opts& o, pmor_stats* stats, int lbase,
                         std::chrono::steady_clock::time_point t0) {
   auto since = [&]() { return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); };
@@ -1089,7 +1287,7 @@ static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   pmor_stats pre0{};
   pre0.bad_column = -1;
   pmor_spai* h = nullptr;
-  int rc = spai_build(pb, s_list[0], p_list[0], sopts, &h, &pre0);
+  int rc = spai_build_pt(pb, pts[0], sopts, &h, &pre0);
   if (rc != PMOR_OK && rc != PMOR_ESINGULAR) {
     if (stats) { stats[0] = pre0; stats[0].t_solve_ms = since(); stats[0].anchor = lbase; }
     spai_release(h);
@@ -1122,8 +1320,7 @@ static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
     const int cnt = std::min(group, npts - l0);
     std::vector<SolveItem> it(cnt);
     std::vector<int> bad(cnt, -1);
-    rc = prepare_points(pb, h, policy, s_list, p_list, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, it.data(),
-                        bad.data());
+    rc = prepare_points(pb, h, policy, pts, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, it.data(), bad.data());
     if (rc != PMOR_OK) break;
     // solve the points whose preconditioner exists
     std::vector<SolveItem> ok;
@@ -1159,10 +1356,15 @@ static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
 
 extern "C" {
 
-int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
-                        const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
-                        const pmor_spai_opts* sopts, const pmor_solve_opts* vopts, pmor_stats* stats) {
-  PMOR_TRY(sequence_checks(pb, B, ldb, k, s_list, p_list, npts, X, ldx, policy));
+}  // extern "C"
+
+namespace pmor {
+static int sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
+                          const double* p_list, const double* coefs, int32_t npts, double* X, int64_t ldx,
+                          int32_t policy, const pmor_spai_opts* sopts, const pmor_solve_opts* vopts,
+                          pmor_stats* stats) {
+  std::vector<Point> pts;
+  PMOR_TRY(sequence_checks(pb, B, ldb, k, s_list, p_list, coefs, npts, X, ldx, policy, &pts));
   pmor_solve_opts o;
   PMOR_TRY(solve_opts_of(vopts, &o));
   const double tol = sopts ? sopts->reanchor_tol : 0.0;
@@ -1173,13 +1375,13 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   const auto t0 = std::chrono::steady_clock::now();
   if (stats) std::memset(stats, 0, sizeof(pmor_stats) * npts);
   std::vector<int> anchors{0};
-  if (tol > 0.0) PMOR_TRY(plan_anchors(pb, s_list, p_list, npts, tol, &anchors));
+  if (tol > 0.0) PMOR_TRY(plan_anchors(pb, pts.data(), npts, tol, &anchors));
   anchors.push_back(npts);
   int first_bad = PMOR_OK;
   for (size_t a = 0; a + 1 < anchors.size(); ++a) {
     const int l0 = anchors[a], cnt = anchors[a + 1] - l0;
-    const int rc = sequence_run(pb, B, ldb, k, s_list + l0, p_list + l0, cnt, X + (int64_t)l0 * pb->n * ldx, ldx,
-                                policy, sopts, o, stats ? stats + l0 : nullptr, l0, t0);
+    const int rc = sequence_run(pb, B, ldb, k, pts.data() + l0, cnt, X + (int64_t)l0 * pb->n * ldx, ldx, policy, sopts,
+                                o, stats ? stats + l0 : nullptr, l0, t0);
     if (rc == PMOR_ESINGULAR || rc == PMOR_ENOTCONV || rc == PMOR_EBREAKDOWN || rc == PMOR_ENAN) {
       if (first_bad == PMOR_OK) first_bad = rc;
     } else if (rc != PMOR_OK) {
@@ -1187,6 +1389,23 @@ int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
     }
   }
   return first_bad;
+}
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* s_list,
+                        const double* p_list, int32_t npts, double* X, int64_t ldx, int32_t policy,
+                        const pmor_spai_opts* sopts, const pmor_solve_opts* vopts, pmor_stats* stats) {
+  if (!s_list || !p_list) return fail(PMOR_EINVAL, "NULL argument");
+  return sequence_solve(pb, B, ldb, k, s_list, p_list, nullptr, npts, X, ldx, policy, sopts, vopts, stats);
+}
+
+int pmor_sequence_solve_c(pmor_problem* pb, const double* B, int64_t ldb, int32_t k, const double* coefs,
+                          int32_t npts, double* X, int64_t ldx, int32_t policy, const pmor_spai_opts* sopts,
+                          const pmor_solve_opts* vopts, pmor_stats* stats) {
+  if (!coefs) return fail(PMOR_EINVAL, "NULL argument");
+  return sequence_solve(pb, B, ldb, k, nullptr, nullptr, coefs, npts, X, ldx, policy, sopts, vopts, stats);
 }
 
 }  // extern "C"
@@ -1199,7 +1418,7 @@ namespace pmor {
 struct ServerJob {
   int64_t id = 0;
   pmor_job job{};
-  std::vector<double> s_list, p_list;
+  std::vector<Point> pts;
   double t_submit = 0.0;
   int64_t footprint = 0;
   pmor_spai* h = nullptr;
@@ -1262,7 +1481,7 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   pmor_stats pre0{};
   pre0.bad_column = -1;
   sv->jobs[J->id] = J;
-  int rc = spai_build(jb.pb, J->s_list[0], J->p_list[0], &sv->sopts, &J->h, &pre0);
+  int rc = spai_build_pt(jb.pb, J->pts[0], &sv->sopts, &J->h, &pre0);
   if (rc == PMOR_OK) {
     const bool rq = rows_scaled(jb.policy, J->h->opts);
     rc = J->sb.alloc(npts, (rq && jb.pb->sell.cap > 0) ? 0 : jb.pb->nnz, rq ? 0 : J->h->nnzP, jb.pb->n,
@@ -1271,8 +1490,8 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   J->items.assign(npts, SolveItem{});
   J->bad.assign(npts, -1);
   if (rc == PMOR_OK)
-    rc = prepare_points(jb.pb, J->h, jb.policy, J->s_list.data(), J->p_list.data(), 0, npts, jb.B, jb.ldb, jb.k,
-                        jb.X, jb.ldx, jb.stats, pre0, J->sb, J->items.data(), J->bad.data());
+    rc = prepare_points(jb.pb, J->h, jb.policy, J->pts.data(), 0, npts, jb.B, jb.ldb, jb.k, jb.X, jb.ldx, jb.stats,
+                        pre0, J->sb, J->items.data(), J->bad.data());
   if (rc == PMOR_EHIP) return rc;
   if (rc != PMOR_OK) {  // the job fails as a whole (singular anchor, no memory)
     J->status = rc;
@@ -1365,8 +1584,9 @@ void pmor_server_destroy(pmor_server* sv) {
 
 int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
   if (!sv || !job) return fail(PMOR_EINVAL, "NULL argument");
-  PMOR_TRY(sequence_checks(job->pb, job->B, job->ldb, job->k, job->s_list, job->p_list, job->npts, job->X, job->ldx,
-                           job->policy));
+  std::vector<Point> pts;
+  PMOR_TRY(sequence_checks(job->pb, job->B, job->ldb, job->k, job->s_list, job->p_list, job->coefs, job->npts, job->X,
+                           job->ldx, job->policy, &pts));
   if (job->pb->ctx != sv->ctx) return fail(PMOR_EINVAL, "problem of another context");
   if (job->npts >= (1 << 20)) return fail(PMOR_EINVAL, "too many points in one job");
   if (job->k > sv->k) return fail(PMOR_EADMIT, "job wider than the server's block width");
@@ -1374,8 +1594,8 @@ int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
     return fail(PMOR_EADMIT, "system larger than the server's engine");
   ServerJob* J = new ServerJob();
   J->job = *job;
-  J->s_list.assign(job->s_list, job->s_list + job->npts);
-  J->p_list.assign(job->p_list, job->p_list + job->npts);
+  J->pts.swap(pts);
+  J->job.s_list = J->job.p_list = J->job.coefs = nullptr;  // host arrays copied: not referenced later
   J->footprint = job_footprint(job->pb, job->npts, rows_scaled(job->policy, sv->sopts));
   if (J->footprint + sv->engine_bytes > sv->budget) {
     delete J;
@@ -1447,16 +1667,18 @@ int pmor_server_info(const pmor_server* sv, int32_t* queued, int32_t* admitted, 
   return PMOR_OK;
 }
 
-int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double p2, double* fro_I_minus_A2,
-                      double* fro_A1_minus_A2) {
-  if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
+}  // extern "C"
+
+namespace pmor {
+static int table2_norms_pt(pmor_problem* pb, const Point& q1, const Point& q2, double* fro_I_minus_A2,
+                           double* fro_A1_minus_A2) {
   double* tmp = nullptr;
   PMOR_HIP(dmalloc((void**)&tmp, sizeof(double) * std::max<int64_t>(pb->nnz, 1), pb->ctx->stream));
   double a = 0.0, b = 0.0;
   const int rc = [&]() -> int {
-    PMOR_TRY(ensure_assembled(pb, s1, p1));
+    PMOR_TRY(ensure_assembled(pb, q1));
     PMOR_TRY(dcopy(pb->aval, tmp, pb->nnz, pb->ctx->stream));
-    PMOR_TRY(ensure_assembled(pb, s2, p2));
+    PMOR_TRY(ensure_assembled(pb, q2));
     PMOR_TRY(fro_norm2(pb, pb->aval, nullptr, pb->nnz, 1, &a));
     PMOR_TRY(fro_norm2(pb, tmp, pb->aval, pb->nnz, 0, &b));
     return PMOR_OK;
@@ -1467,6 +1689,27 @@ int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double 
   if (fro_A1_minus_A2) *fro_A1_minus_A2 = std::sqrt(b);
   return PMOR_OK;
 }
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_table2_norms(pmor_problem* pb, double s1, double p1, double s2, double p2, double* fro_I_minus_A2,
+                      double* fro_A1_minus_A2) {
+  if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
+  Point q1, q2;
+  PMOR_TRY(point_sp(pb, s1, p1, &q1));
+  PMOR_TRY(point_sp(pb, s2, p2, &q2));
+  return table2_norms_pt(pb, q1, q2, fro_I_minus_A2, fro_A1_minus_A2);
+}
+
+int pmor_table2_norms_c(pmor_problem* pb, const double* coef1, const double* coef2, double* fro_I_minus_A2,
+                        double* fro_A1_minus_A2) {
+  if (!pb) return fail(PMOR_EINVAL, "problem is NULL");
+  Point q1, q2;
+  PMOR_TRY(point_coef(pb, coef1, &q1));
+  PMOR_TRY(point_coef(pb, coef2, &q2));
+  return table2_norms_pt(pb, q1, q2, fro_I_minus_A2, fro_A1_minus_A2);
+}
 
 int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2, double p2,
                               double* fro_I_minus_A2, double* fro_A1_minus_A2) {
@@ -1475,16 +1718,15 @@ int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2,
   double* scr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
   if (!scr) return fail(PMOR_EHIP, "no scratch address for the context's device");
   static_assert(kT2Parts <= 256, "k_table2_sums adds at most 256 partials");
+  Point q1, q2;
+  PMOR_TRY(point_sp(pb, s1, p1, &q1));
+  PMOR_TRY(point_sp(pb, s2, p2, &q2));
   T2Coefs cf{};
   cf.nt = pb->nterms;
-  double c1[PMOR_NROLES], c2[PMOR_NROLES];
-  role_coefs(s1, p1, c1);
-  role_coefs(s2, p2, c2);
-  for (int r = 0; r < PMOR_NROLES; ++r)
-    if (pb->role_slot[r] >= 0) {
-      cf.c1[pb->role_slot[r]] = c1[r];
-      cf.c2[pb->role_slot[r]] = c2[r];
-    }
+  for (int t = 0; t < pb->nterms; ++t) {
+    cf.c1[t] = q1.c[t];
+    cf.c2[t] = q2.c[t];
+  }
   hipStream_t st = pb->ctx->stream;
   hipLaunchKernelGGL(k_table2_partials, dim3(kT2Parts), dim3(256), 0, st, pb->n, pb->rowptr, pb->col,
                      (int64_t)pb->nnz, pb->tval, cf, scr);

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+
 #include <string>
 #include <vector>
 
@@ -113,6 +115,14 @@ struct SegDesc {
 
 struct Engine;
 
+// A point of a parametric family: the coefficient of every stored term of its
+// problem in term-slot order, A = sum_t c[t] T_t (the affine form of Section
+// 1.1, eq. affine_system; for a problem of roles the coefficients of
+// s^2 M(p) + s D(p) + K(p)).
+struct Point {
+  double c[PMOR_TMAX];
+};
+
 // HIP-event timing of one chosen kernel class on the context's stream, with the
 // algorithmic bytes each timed launch has to move (for roofline reports).
 struct ProfRec {
@@ -150,8 +160,11 @@ struct pmor_problem {
   int32_t* rowptr = nullptr;   // union pattern, CSR
   int32_t* col = nullptr;
   int32_t* maps = nullptr;     // PMOR_NROLES x nnz
-  double* tval = nullptr;      // term values on the union pattern, one array per present role
-  int role_slot[PMOR_NROLES];  // index into tval, or -1
+  double* tval = nullptr;      // term values on the union pattern, one array per stored term
+  bool affine = false;         // created by pmor_problem_create_affine (points are coefficient vectors)
+  int ncoef = 0;               // entries of a point's coefficient vector (PMOR_NROLES for a problem of roles)
+  int coef_slot[PMOR_TMAX];    // coefficient index -> index into tval, or -1 (absent role)
+  int nmaps = 0;               // rows of maps: PMOR_NROLES (roles) or nterms (affine)
   int nterms = 0;
   int32_t* colptr = nullptr;   // CSC view of the pattern
   int32_t* rowidx = nullptr;
@@ -160,7 +173,7 @@ struct pmor_problem {
   double* aval = nullptr;      // values of the last assembled point
   pmor::SellView sell;         // sliced ELL view of the pattern (engine SpMM)
   double* aval_s = nullptr;    // aval in the sliced ELL layout
-  double cur_s = 0, cur_p = 0;
+  pmor::Point cur{};           // the point aval holds
   bool have_cur = false;
 };
 
@@ -190,7 +203,7 @@ struct pmor_spai {
   bool identity_order = true;
   bool q_active = false;     // U-pattern update applied (apply Q (P_1 x))
   bool d_active = false;     // U-diag update applied (apply diag(q) (P_1 x), q in Qval)
-  double s1 = 0, p1 = 0;
+  pmor::Point pt1{};          // the anchor point
   pmor::SellView psell;      // sliced ELL view of P's pattern (the problem's for PAT_A)
   bool own_psell = false;
   double* P1val_s = nullptr;  // P1val (= Pval before an update) and Qval in the sliced ELL layout
@@ -209,6 +222,16 @@ inline void role_coefs(double s, double p, double c[PMOR_NROLES]) {
   c[PMOR_K1] = p;
 }
 
+// the point (s, p) of a problem of roles (PMOR_EINVAL for an affine problem or
+// a non-finite s, p)
+int point_sp(const pmor_problem* pb, double s, double p, Point* out);
+// the point of the coefficient vector coef (pb->ncoef host values; PMOR_EINVAL
+// when coef is NULL or a coefficient of a stored term is not finite)
+int point_coef(const pmor_problem* pb, const double* coef, Point* out);
+inline bool same_point(const Point& a, const Point& b, int nt) {
+  return std::memcmp(a.c, b.c, sizeof(double) * nt) == 0;
+}
+
 // Lifetimes: a context lives until its caller and every problem and server of
 // it have let it go; a problem until its caller and every preconditioner and
 // server job of it have.  Destroy calls may therefore come in any order.
@@ -222,7 +245,7 @@ hipError_t dmalloc(void** p, size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 void dtrim();
 
-int ensure_assembled(pmor_problem* pb, double s, double p);
+int ensure_assembled(pmor_problem* pb, const Point& pt);
 // kernel timing: start returns a record index (-1 when kernel class `kid` is not profiled)
 int prof_start(pmor_ctx* c, int kid);
 void prof_stop(pmor_ctx* c, int idx, double bytes, int tag);
@@ -252,9 +275,16 @@ inline void plaunch(pmor_ctx* c, int idx, int part, F kernel, dim3 g, dim3 b, ui
 }
 
 // launchers implemented in the kernel translation units
-int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* out, hipStream_t st);
-int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms);
+int launch_assemble(pmor_problem* pb, const Point& pt, double* out, hipStream_t st);
+// union pattern of terms[0..count) (NULL entries absent); maps rows: one per entry of terms
+int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count);
 int build_spai_sets(pmor_spai* h);
+// PMOR_EINVAL unless (rowptr, col) is an n x n CSR pattern of nnz entries with
+// strictly increasing columns per row (synchronises)
+int check_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, hipStream_t st);
+// CSC view (colptr n+1, rowidx, slot: CSC position -> CSR position) allocated here
+int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
+                      int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st);
 // sliced ELL view of a CSR pattern when its padding is at most max_fill x nnz (else v->cap = 0)
 // stored slots (padding included) allowed per nonzero before the CSR arrays
 // serve instead: a padded slot costs its 12 bytes of column and value only
@@ -273,26 +303,26 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
 // *n_esc (may be NULL) = escalated columns
 int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_t* bad_col, double* fro2,
                         int64_t* n_esc);
-// points of a sequence, at most PTS_MAX per call (s_list, p_list: host arrays of cnt):
+// points of a sequence, at most PTS_MAX per call (pts: host array of cnt):
 // A(l) into out + l * ostride (CSR order, or the sliced ELL layout of sv when not NULL);
 // the U-diag factors q_l, rho_l (stride n) and the first zero column into bad[l]
 // (bad must hold 0x7fffffff); per-point sums of squares into out[l * ostride]
 constexpr int PTS_MAX = 8;
-int launch_assemble_pts(pmor_problem* pb, const double* s_list, const double* p_list, int cnt, const SellView* sv,
-                        double* out, int64_t ostride, hipStream_t st);
-int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
-                           int* bad, hipStream_t st);
+int launch_assemble_pts(pmor_problem* pb, const Point* pts, int cnt, const SellView* sv, double* out, int64_t ostride,
+                        hipStream_t st);
+int launch_update_diag_pts(pmor_spai* h, const Point* pts, int cnt, double* q, double* rho, int* bad, hipStream_t st);
 int sumsq_pts(const double* x, int64_t n, int cnt, double* out, int64_t ostride, hipStream_t st);
 // U-diag factors and column residuals of up to PTS_MAX points against the anchor values given
-int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const double* s_list, const double* p_list,
-                                  int cnt, double* q, double* rho, int* bad, hipStream_t st);
+int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const Point* pts, int cnt, double* q,
+                                  double* rho, int* bad, hipStream_t st);
 // U-diag update into caller buffers (no host synchronisation): P_l = diag(q) P_1
 // into pl, q into q, column residuals into rho, the smallest failing column into
 // *dbad (device int, must hold INT_MAX beforehand)
 int launch_update_diag(pmor_spai* h, const double* aval_l, const double* anchor, const double* qprev, double* pl,
                        double* q, double* rho, int* dbad);
-int launch_update_diag_chain(pmor_spai* h, const double* s_list, const double* p_list, int l0, int cnt, double* carry,
-                             double* q, double* rho, int* bad, hipStream_t st);
+// pts: the whole sequence (point l0 - 1 is the first anchor)
+int launch_update_diag_chain(pmor_spai* h, const Point* pts, int l0, int cnt, double* carry, double* q, double* rho,
+                             int* bad, hipStream_t st);
 int launch_spmm(int n, const int32_t* rowptr, const int32_t* col, const double* val,
                 const double* X, int64_t ldx, double* Y, int64_t ldy, int k,
                 double alpha, double beta, const double* Bsrc, int64_t ldb,

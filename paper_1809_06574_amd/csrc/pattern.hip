@@ -113,11 +113,12 @@ __global__ void k_validate_csr(int n, int nnz, const int32_t* rowptr, const int3
 // union pattern
 // ---------------------------------------------------------------------------
 struct TermPtrs {
-  const int32_t* rowptr[PMOR_NROLES];
-  const int32_t* col[PMOR_NROLES];
-  const double* val[PMOR_NROLES];
-  int present[PMOR_NROLES];
-  int slot[PMOR_NROLES];
+  const int32_t* rowptr[PMOR_TMAX];
+  const int32_t* col[PMOR_TMAX];
+  const double* val[PMOR_TMAX];
+  int present[PMOR_TMAX];
+  int slot[PMOR_TMAX];
+  int nmaps;  // rows of the slot maps (terms given, present or not)
 };
 
 // Walks the sorted column lists of row i of every present term and the diagonal,
@@ -127,9 +128,9 @@ __global__ void k_union_count(int n, TermPtrs t, int64_t* counts, int* maxlen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int cnt = 0;
   if (i < n) {
-    int cur[PMOR_NROLES], end[PMOR_NROLES], head[PMOR_NROLES];
+    int cur[PMOR_TMAX], end[PMOR_TMAX], head[PMOR_TMAX];
 #pragma unroll
-    for (int r = 0; r < PMOR_NROLES; ++r) {
+    for (int r = 0; r < PMOR_TMAX; ++r) {
       cur[r] = t.present[r] ? t.rowptr[r][i] : 0;
       end[r] = t.present[r] ? t.rowptr[r][i + 1] : 0;
       head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
@@ -138,11 +139,11 @@ __global__ void k_union_count(int n, TermPtrs t, int64_t* counts, int* maxlen) {
     while (true) {
       int cmin = diag_done ? 0x7fffffff : i;
 #pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r) cmin = min(cmin, head[r]);
+      for (int r = 0; r < PMOR_TMAX; ++r) cmin = min(cmin, head[r]);
       if (cmin == 0x7fffffff) break;
       if (cmin == i) diag_done = true;
 #pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r)
+      for (int r = 0; r < PMOR_TMAX; ++r)
         if (head[r] == cmin) {
           ++cur[r];
           head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
@@ -174,9 +175,9 @@ __global__ void k_union_fill(int n, TermPtrs t, const int32_t* __restrict__ rowp
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = row_of[e];
     const int k = (int)(e - rowptr_out[i]);
-    int cur[PMOR_NROLES], end[PMOR_NROLES], head[PMOR_NROLES];
+    int cur[PMOR_TMAX], end[PMOR_TMAX], head[PMOR_TMAX];
 #pragma unroll
-    for (int r = 0; r < PMOR_NROLES; ++r) {
+    for (int r = 0; r < PMOR_TMAX; ++r) {
       cur[r] = t.present[r] ? t.rowptr[r][i] : 0;
       end[r] = t.present[r] ? t.rowptr[r][i + 1] : 0;
       head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
@@ -185,21 +186,21 @@ __global__ void k_union_fill(int n, TermPtrs t, const int32_t* __restrict__ rowp
     for (int cnt = 0;; ++cnt) {
       int cmin = diag_done ? 0x7fffffff : i;
 #pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r) cmin = min(cmin, head[r]);
+      for (int r = 0; r < PMOR_TMAX; ++r) cmin = min(cmin, head[r]);
       if (cmin == 0x7fffffff) break;  // not reached for k < the row's length
       if (cmin == i) diag_done = true;
       if (cnt == k) {
         col_out[e] = cmin;
 #pragma unroll
-        for (int r = 0; r < PMOR_NROLES; ++r) {
+        for (int r = 0; r < PMOR_TMAX; ++r) {
           const bool hit = head[r] == cmin;
-          maps[(int64_t)r * nnz_out + e] = hit ? cur[r] : -1;
+          if (r < t.nmaps) maps[(int64_t)r * nnz_out + e] = hit ? cur[r] : -1;
           if (t.present[r]) tval[(int64_t)t.slot[r] * nnz_out + e] = hit ? t.val[r][cur[r]] : 0.0;
         }
         break;
       }
 #pragma unroll
-      for (int r = 0; r < PMOR_NROLES; ++r)
+      for (int r = 0; r < PMOR_TMAX; ++r)
         if (head[r] == cmin) {
           ++cur[r];
           head[r] = cur[r] < end[r] ? t.col[r][cur[r]] : 0x7fffffff;
@@ -248,6 +249,22 @@ __global__ void k_col_sort(int n, const int32_t* colptr, int32_t* rowidx, int32_
   }
 }
 
+int check_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, hipStream_t st) {
+  if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31)) return fail(PMOR_EINVAL, "bad pattern size");
+  int* derr = nullptr;
+  PMOR_HIP(dmalloc((void**)&derr, sizeof(int), st));
+  PMOR_HIP(hipMemsetAsync(derr, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, n, (int)nnz, rowptr, col,
+                     derr);
+  PMOR_HIP(hipGetLastError());
+  int herr = 0;
+  PMOR_HIP(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  dfree(derr, st);
+  if (herr) return fail(PMOR_EINVAL, "malformed CSR pattern (rowptr, column range or column order)");
+  return PMOR_OK;
+}
+
 // pattern (n x n, nnz entries in CSR) -> CSC arrays allocated here
 int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
                       int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st) {
@@ -288,31 +305,35 @@ int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* 
   return PMOR_OK;
 }
 
-int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
+int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count) {
   hipStream_t st = pb->ctx->stream;
   const int n = pb->n;
+  if (count < 1 || count > PMOR_TMAX) return fail(PMOR_EINVAL, "term count out of range");
   int* derr = nullptr;
   PMOR_HIP(dmalloc((void**)&derr, sizeof(int) * 2, st));
   PMOR_HIP(hipMemsetAsync(derr, 0, sizeof(int) * 2, st));
   TermPtrs tp{};
+  tp.nmaps = count;
   int nt = 0;
-  for (int r = 0; r < PMOR_NROLES; ++r) {
-    pb->role_slot[r] = -1;
+  for (int r = 0; r < PMOR_TMAX; ++r) {
+    pb->coef_slot[r] = -1;
     tp.present[r] = 0;
     tp.slot[r] = -1;
-    if (!terms[r]) continue;
+    if (r >= count || !terms[r]) continue;
     const pmor_csr* T = terms[r];
     tp.rowptr[r] = T->rowptr;
     tp.col[r] = T->col;
     tp.val[r] = T->val;
     tp.present[r] = 1;
     tp.slot[r] = nt;
-    pb->role_slot[r] = nt++;
+    pb->coef_slot[r] = nt++;
     hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, n, T->nnz,
                        T->rowptr, T->col, derr);
     PMOR_HIP(hipGetLastError());
   }
   pb->nterms = nt;
+  pb->ncoef = count;
+  pb->nmaps = count;
   int herr = 0;
   PMOR_HIP(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
@@ -342,7 +363,7 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms) {
   const int64_t nnz = nnz64;
   PMOR_HIP(dmalloc((void**)&pb->rowptr, sizeof(int32_t) * (n + 1), st));
   PMOR_HIP(dmalloc((void**)&pb->col, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
-  PMOR_HIP(dmalloc((void**)&pb->maps, sizeof(int32_t) * PMOR_NROLES * (nnz > 0 ? nnz : 1), st));
+  PMOR_HIP(dmalloc((void**)&pb->maps, sizeof(int32_t) * count * (nnz > 0 ? nnz : 1), st));
   PMOR_HIP(dmalloc((void**)&pb->tval, sizeof(double) * (nt > 0 ? nt : 1) * (nnz > 0 ? nnz : 1), st));
   PMOR_HIP(dmalloc((void**)&pb->aval, sizeof(double) * (nnz > 0 ? nnz : 1), st));
   hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, st, cnt, pb->rowptr,

@@ -686,7 +686,7 @@ int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_
 // assembly: a = sum_r c_r T_r on the union pattern (streaming)
 // ---------------------------------------------------------------------------
 struct Coefs {
-  double c[PMOR_NROLES];
+  double c[PMOR_TMAX];
   int nt;
 };
 
@@ -698,11 +698,10 @@ __global__ void k_assemble(int64_t nnz, const double* __restrict__ tval, Coefs c
   }
 }
 
-int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* out, hipStream_t st) {
+int launch_assemble(pmor_problem* pb, const Point& pt, double* out, hipStream_t st) {
   Coefs cf{};
   cf.nt = pb->nterms;
-  for (int r = 0; r < PMOR_NROLES; ++r)
-    if (pb->role_slot[r] >= 0) cf.c[pb->role_slot[r]] = coef[r];
+  for (int t = 0; t < pb->nterms; ++t) cf.c[t] = pt.c[t];
   const int64_t nnz = pb->nnz;
   if (nnz == 0) return PMOR_OK;
   unsigned g = (unsigned)std::min<int64_t>((nnz + 255) / 256, 4096);
@@ -719,26 +718,22 @@ int launch_assemble(pmor_problem* pb, const double coef[PMOR_NROLES], double* ou
 // calls bit for bit.
 // ---------------------------------------------------------------------------
 struct PtsCoefs {
-  double c[PTS_MAX][PMOR_NROLES];  // by term slot
+  double c[PTS_MAX][PMOR_TMAX];  // by term slot
   int cnt, nt;
 };
 
 // the anchor point and up to PTS_MAX points of a second-approach chain
 struct ChainCoefs {
-  double c[PTS_MAX + 1][PMOR_NROLES];  // by term slot
+  double c[PTS_MAX + 1][PMOR_TMAX];  // by term slot
   int cnt, nt;
 };
 
-static PtsCoefs pts_coefs(const pmor_problem* pb, const double* s_list, const double* p_list, int cnt) {
+static PtsCoefs pts_coefs(const pmor_problem* pb, const Point* pts, int cnt) {
   PtsCoefs pc{};
   pc.cnt = cnt;
   pc.nt = pb->nterms;
-  for (int l = 0; l < cnt; ++l) {
-    double c[PMOR_NROLES];
-    role_coefs(s_list[l], p_list[l], c);
-    for (int r = 0; r < PMOR_NROLES; ++r)
-      if (pb->role_slot[r] >= 0) pc.c[l][pb->role_slot[r]] = c[r];
-  }
+  for (int l = 0; l < cnt; ++l)
+    for (int t = 0; t < pb->nterms; ++t) pc.c[l][t] = pts[l].c[t];
   return pc;
 }
 
@@ -748,9 +743,9 @@ __global__ void k_assemble_pts(int64_t len, const int32_t* __restrict__ map, int
                                int64_t ostride) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < len; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = map ? (int64_t)map[q] : q;
-    double tv[PMOR_NROLES];
+    double tv[PMOR_TMAX];
 #pragma unroll
-    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = (e >= 0 && t < pc.nt) ? tval[(int64_t)t * nnz + e] : 0.0;
+    for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = (e >= 0 && t < pc.nt) ? tval[(int64_t)t * nnz + e] : 0.0;
     for (int l = 0; l < pc.cnt; ++l) {
       double acc = 0.0;
       for (int t = 0; t < pc.nt; ++t) acc += pc.c[l][t] * tv[t];
@@ -759,12 +754,12 @@ __global__ void k_assemble_pts(int64_t len, const int32_t* __restrict__ map, int
   }
 }
 
-int launch_assemble_pts(pmor_problem* pb, const double* s_list, const double* p_list, int cnt, const SellView* sv,
-                        double* out, int64_t ostride, hipStream_t st) {
+int launch_assemble_pts(pmor_problem* pb, const Point* pts, int cnt, const SellView* sv, double* out, int64_t ostride,
+                        hipStream_t st) {
   const int64_t len = sv ? sv->cap : pb->nnz;
   if (len == 0 || cnt <= 0) return PMOR_OK;
   if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one assembly launch");
-  const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
+  const PtsCoefs pc = pts_coefs(pb, pts, cnt);
   const unsigned g = (unsigned)std::min<int64_t>((len + 255) / 256, 8192);
   hipLaunchKernelGGL(k_assemble_pts, dim3(g), dim3(256), 0, st, len, sv ? (const int32_t*)sv->map : nullptr,
                      pb->nnz, pb->tval, pc, out, ostride);
@@ -784,9 +779,9 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
   for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = 0.0;
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
-    double tv[PMOR_NROLES];
+    double tv[PMOR_TMAX];
 #pragma unroll
-    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     const double y = a1[s];
 #pragma unroll
     for (int l = 0; l < PTS_MAX; ++l) {
@@ -808,9 +803,9 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
   // were just read, so the second pass hits the caches)
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
-    double tv[PMOR_NROLES];
+    double tv[PMOR_TMAX];
 #pragma unroll
-    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     const double y = a1[s];
 #pragma unroll
     for (int l = 0; l < PTS_MAX; ++l) {
@@ -832,21 +827,21 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
   }
 }
 
-int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const double* s_list, const double* p_list,
-                                  int cnt, double* q, double* rho, int* bad, hipStream_t st) {
+int launch_update_diag_pts_anchor(pmor_problem* pb, const double* anchor, const Point* pts, int cnt, double* q,
+                                  double* rho, int* bad, hipStream_t st) {
   const int n = pb->n;
   if (n == 0 || cnt <= 0) return PMOR_OK;
   if (cnt > PTS_MAX) return fail(PMOR_EINVAL, "too many points for one update launch");
-  const PtsCoefs pc = pts_coefs(pb, s_list, p_list, cnt);
+  const PtsCoefs pc = pts_coefs(pb, pts, cnt);
   hipLaunchKernelGGL(k_update_diag_pts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
                      pb->cscslot, pb->nnz, pb->tval, pc, anchor, q, rho, bad);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }
 
-int launch_update_diag_pts(pmor_spai* h, const double* s_list, const double* p_list, int cnt, double* q, double* rho,
-                           int* bad, hipStream_t st) {
-  return launch_update_diag_pts_anchor(h->pb, h->aval1, s_list, p_list, cnt, q, rho, bad, st);
+int launch_update_diag_pts(pmor_spai* h, const Point* pts, int cnt, double* q, double* rho, int* bad,
+                           hipStream_t st) {
+  return launch_update_diag_pts_anchor(h->pb, h->aval1, pts, cnt, q, rho, bad, st);
 }
 
 // Second approach over points l0 .. l0 + cnt - 1 of a sequence (l0 >= 1, cnt
@@ -867,9 +862,9 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
   for (int l = 0; l < PTS_MAX; ++l) num[l] = den[l] = 0.0;
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
-    double tv[PMOR_NROLES];
+    double tv[PMOR_TMAX];
 #pragma unroll
-    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     double y = 0.0;  // anchor value (point l0 - 1)
     for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
 #pragma unroll
@@ -892,9 +887,9 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
   // step residuals ||A(l-1) e_i - q_l A(l) e_i|| entry by entry
   for (int e = colptr[i]; e < colptr[i + 1]; ++e) {
     const int s = cscslot[e];
-    double tv[PMOR_NROLES];
+    double tv[PMOR_TMAX];
 #pragma unroll
-    for (int t = 0; t < PMOR_NROLES; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
+    for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     double y = 0.0;
     for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
 #pragma unroll
@@ -921,8 +916,8 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
   carry[i] = qc;
 }
 
-int launch_update_diag_chain(pmor_spai* h, const double* s_list, const double* p_list, int l0, int cnt, double* carry,
-                             double* q, double* rho, int* bad, hipStream_t st) {
+int launch_update_diag_chain(pmor_spai* h, const Point* pts, int l0, int cnt, double* carry, double* q, double* rho,
+                             int* bad, hipStream_t st) {
   pmor_problem* pb = h->pb;
   const int n = pb->n;
   if (n == 0 || cnt <= 0) return PMOR_OK;
@@ -931,12 +926,8 @@ int launch_update_diag_chain(pmor_spai* h, const double* s_list, const double* p
   ChainCoefs pc{};
   pc.cnt = cnt;
   pc.nt = pb->nterms;
-  for (int t = 0; t <= cnt; ++t) {
-    double c[PMOR_NROLES];
-    role_coefs(s_list[l0 - 1 + t], p_list[l0 - 1 + t], c);
-    for (int r = 0; r < PMOR_NROLES; ++r)
-      if (pb->role_slot[r] >= 0) pc.c[t][pb->role_slot[r]] = c[r];
-  }
+  for (int t = 0; t <= cnt; ++t)
+    for (int u = 0; u < pb->nterms; ++u) pc.c[t][u] = pts[l0 - 1 + t].c[u];
   hipLaunchKernelGGL(k_update_diag_chain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
                      pb->cscslot, pb->nnz, pb->tval, pc, l0, carry, q, rho, bad);
   PMOR_HIP(hipGetLastError());

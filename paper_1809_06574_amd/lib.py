@@ -22,6 +22,7 @@ PMOR_OK, PMOR_EINVAL, PMOR_ENOMEM, PMOR_ENOTCONV = 0, -1, -2, -3
 PMOR_EBREAKDOWN, PMOR_ESINGULAR, PMOR_ENAN, PMOR_EHIP, PMOR_EADMIT = -4, -5, -6, -7, -8
 PMOR_KMAX = 16
 PMOR_NROLES = 6
+PMOR_TMAX = 8
 PMOR_MAX_CYCLES = 64
 ROLES = ("M0", "M1", "D0", "D1", "K0", "K1")
 PMOR_PAT_A, PMOR_PAT_EXPLICIT = 0, 1
@@ -49,7 +50,8 @@ class SolveOpts(C.Structure):
 
 class BatchItem(C.Structure):
     _fields_ = [("pb", C.c_void_p), ("h", C.c_void_p), ("s", C.c_double), ("p", C.c_double),
-                ("B", C.c_void_p), ("ldb", C.c_int64), ("k", C.c_int32), ("X", C.c_void_p), ("ldx", C.c_int64)]
+                ("B", C.c_void_p), ("ldb", C.c_int64), ("k", C.c_int32), ("X", C.c_void_p), ("ldx", C.c_int64),
+                ("coef", C.POINTER(C.c_double))]
 
 
 class ServerOpts(C.Structure):
@@ -78,7 +80,8 @@ PP = C.POINTER(C.c_void_p)
 class Job(C.Structure):
     _fields_ = [("pb", C.c_void_p), ("B", C.c_void_p), ("ldb", C.c_int64), ("k", C.c_int32),
                 ("s_list", C.POINTER(C.c_double)), ("p_list", C.POINTER(C.c_double)), ("npts", C.c_int32),
-                ("X", C.c_void_p), ("ldx", C.c_int64), ("policy", C.c_int32), ("stats", C.POINTER(Stats))]
+                ("X", C.c_void_p), ("ldx", C.c_int64), ("policy", C.c_int32), ("stats", C.POINTER(Stats)),
+                ("coefs", C.POINTER(C.c_double))]
 
 
 _SIGS = {
@@ -86,28 +89,39 @@ _SIGS = {
     "pmor_ctx_destroy": (None, [P]),
     "pmor_ctx_set_stream": (C.c_int, [P, P]),
     "pmor_problem_create": (C.c_int, [P, C.POINTER(C.POINTER(Csr)), PP]),
+    "pmor_problem_create_affine": (C.c_int, [P, I32, C.POINTER(C.POINTER(Csr)), PP]),
     "pmor_problem_destroy": (None, [P]),
     "pmor_problem_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
     "pmor_problem_pattern": (C.c_int, [P, P, P, P]),
     "pmor_assemble": (C.c_int, [P, D, D, P]),
+    "pmor_assemble_c": (C.c_int, [P, C.POINTER(D), P]),
     "spai_build": (C.c_int, [P, D, D, C.POINTER(SpaiOpts), PP, C.POINTER(Stats)]),
+    "spai_build_c": (C.c_int, [P, C.POINTER(D), C.POINTER(SpaiOpts), PP, C.POINTER(Stats)]),
     "spai_update": (C.c_int, [P, D, D, C.POINTER(Stats)]),
+    "spai_update_c": (C.c_int, [P, C.POINTER(D), C.POINTER(Stats)]),
     "spai_rebuild": (C.c_int, [P, D, D, C.POINTER(Stats)]),
+    "spai_rebuild_c": (C.c_int, [P, C.POINTER(D), C.POINTER(Stats)]),
+    "spai_import": (C.c_int, [P, D, D, I32, P, P, P, C.POINTER(SpaiOpts), PP]),
+    "spai_import_c": (C.c_int, [P, C.POINTER(D), I32, P, P, P, C.POINTER(SpaiOpts), PP]),
     "spai_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
     "spai_export": (C.c_int, [P, P, P, P, P, P]),
     "spai_export_sets": (C.c_int, [P, P, P, P, P, C.POINTER(I64)]),
     "spai_free": (None, [P]),
     "block_solve": (C.c_int, [P, P, D, D, P, I64, I32, P, I64, C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "block_solve_c": (C.c_int, [P, P, C.POINTER(D), P, I64, I32, P, I64, C.POINTER(SolveOpts), C.POINTER(Stats)]),
     "pmor_batch_solve": (C.c_int, [P, C.POINTER(BatchItem), I32, C.POINTER(SolveOpts), C.POINTER(Stats),
                                    C.POINTER(I32)]),
     "pmor_sequence_solve": (C.c_int, [P, P, I64, I32, P, P, I32, P, I64, I32, C.POINTER(SpaiOpts),
                                       C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "pmor_sequence_solve_c": (C.c_int, [P, P, I64, I32, C.POINTER(D), I32, P, I64, I32, C.POINTER(SpaiOpts),
+                                        C.POINTER(SolveOpts), C.POINTER(Stats)]),
     "pmor_server_create": (C.c_int, [P, C.POINTER(ServerOpts), C.POINTER(SpaiOpts), C.POINTER(SolveOpts), PP]),
     "pmor_server_destroy": (None, [P]),
     "pmor_server_submit": (C.c_int, [P, C.POINTER(Job), C.POINTER(I64)]),
     "pmor_server_step": (C.c_int, [P, C.POINTER(I64), C.POINTER(I32), I32, C.POINTER(I32)]),
     "pmor_server_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I64)]),
     "pmor_table2_norms": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
+    "pmor_table2_norms_c": (C.c_int, [P, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pmor_table2_norms_noalloc": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
     "pmor_spmm": (C.c_int, [P, P, P, I64, P, I64, I32, D, D]),
     "pmor_prof_set": (C.c_int, [P, C.c_int]),

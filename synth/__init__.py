@@ -16,4 +16,6 @@ from .gen import (  # noqa: F401
     config4_job,
     appendix1,
     tiny_random_job,
+    gyro_like_job,
+    gyro_coefs,
 )

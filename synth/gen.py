@@ -17,6 +17,8 @@ matrices are a public benchmark not available here):
                 with an explicit power-law SPAI pattern (sizes 5..40).
 * ``config4_job(j)``  serving jobs, n in {16384, 65536, 262144, 1048576}.
 * ``appendix1`` the paper's Appendix I system (non-symmetric, n = 1006).
+* ``gyro_like_job``  an affine job with the term structure of the paper's
+                micro-gyroscope model (seven matrices, six free coefficients).
 
 Grids are ordered lexicographically with x fastest; Dirichlet boundaries are
 modelled by "ghost" edges from each boundary node to the outside, so a
@@ -28,7 +30,7 @@ x-, y-, z-faces), then the M diagonal, then p, then B.
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, Optional, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -62,6 +64,8 @@ class Job:
     B: np.ndarray  # (n, k) float64, row-major
     pattern: Optional[Tuple[np.ndarray, np.ndarray]] = None  # explicit CSC (colptr, row)
     meta: dict = dataclasses.field(default_factory=dict)
+    aterms: Optional[List[CSR]] = None  # affine job: the term matrices T_0..T_{w}
+    coefs: Optional[np.ndarray] = None  # affine job: npts x len(aterms) coefficient vectors
 
     @property
     def k(self) -> int:
@@ -310,3 +314,75 @@ def tiny_random_job(n: int, density: float, seed: int, k: int = 2, npts: int = 3
     p = rng.uniform(0.1, 0.9, size=npts)
     B = rng.standard_normal((n, k))
     return Job(f"tiny_{n}_{seed}", n, terms, 0.7, p, B)
+
+
+def _upwind_x(dims, rng, lo, hi) -> CSR:
+    """Non-symmetric first-difference coupling along x: entry (i, i-1) = -w and
+    (i, i) = w for every x-edge (weights U(lo, hi)), a convection-like term."""
+    nx, ny, nz = dims
+    idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
+    w = rng.uniform(lo, hi, size=(nz, ny, nx - 1))
+    a, b = idx[:, :, 1:].ravel(), idx[:, :, :-1].ravel()
+    diag = np.zeros((nz, ny, nx))
+    diag[:, :, 1:] += w
+    rows = np.concatenate([a, idx.ravel()])
+    cols = np.concatenate([b, idx.ravel()])
+    vals = np.concatenate([-w.ravel(), diag.ravel()])
+    return _coo_to_csr(nx * ny * nz, rows, cols, vals)
+
+
+def _long_range_x(dims, rng, lo, hi) -> CSR:
+    """Symmetric couplings between nodes two apart along x (weights U(lo, hi)),
+    Laplacian-like (diagonal = sum of incident weights): a term whose pattern is
+    not in the 7-point stencil, so the union pattern is wider than any term."""
+    nx, ny, nz = dims
+    idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
+    w = rng.uniform(lo, hi, size=(nz, ny, nx - 2))
+    a, b = idx[:, :, :-2].ravel(), idx[:, :, 2:].ravel()
+    diag = np.zeros((nz, ny, nx))
+    diag[:, :, :-2] += w
+    diag[:, :, 2:] += w
+    rows = np.concatenate([a, b, idx.ravel()])
+    cols = np.concatenate([b, a, idx.ravel()])
+    vals = np.concatenate([-w.ravel(), -w.ravel(), diag.ravel()])
+    return _coo_to_csr(nx * ny * nz, rows, cols, vals)
+
+
+GYRO_POINTS = ((2.0, 0.5, 1.0), (2.0, 0.5, 2.0), (1.5, 0.3, 2.0), (1.5, 0.3, 1.5))
+
+
+def gyro_coefs(s: float, theta: float, d: float) -> np.ndarray:
+    """Coefficients of the seven terms at (s, theta, d), in the order of
+    ``gyro_like_job``'s terms: K1 (1), M1 (s^2), M2 (s^2 d), D1 (s theta),
+    D2 (s theta d), K2 (1/d), K3 (d) -- the model's free parameters with the
+    damping weights alpha = beta = 0."""
+    return np.array([1.0, s * s, s * s * d, s * theta, s * theta * d, 1.0 / d, d])
+
+
+def gyro_like_job(dims=(12, 10, 8), k: int = 2, seed: int = 1010, points=GYRO_POINTS) -> Job:
+    """An affine job shaped like the paper's micro-gyroscope model (Section 3):
+    s^2 M(d) + s D(theta, d) + K(d) with M(d) = M1 + d M2, D = theta (D1 + d D2),
+    K(d) = K1 + (1/d) K2 + d K3, written as seven terms with the coefficients of
+    ``gyro_coefs``.  Synthetic stand-ins on a 3-D grid (the model's matrices are
+    not available): K1 a weighted Laplacian U(1,10), K2 a weighted Laplacian
+    U(0.5,2), K3 couplings two nodes apart U(0.1,0.5), M1 = diag U(0.5,1.5),
+    M2 = diag U(0.1,0.3), D1 = 1e-2 times a weighted Laplacian U(1,10), D2 an
+    upwind x-difference U(0.5,1) (non-symmetric).  Points: (s, theta, d) in
+    ``points`` (the values of d follow the paper's four expansion points; s and
+    theta are real here).  Seed ``seed``; draw order K1, K2, K3, M1, M2, D1, D2, B.
+    """
+    rng = np.random.default_rng(seed)
+    K1 = grid_laplacian(dims, rng, 1.0, 10.0)
+    K2 = grid_laplacian(dims, rng, 0.5, 2.0)
+    K3 = _long_range_x(dims, rng, 0.1, 0.5)
+    n = K1.n
+    M1 = diagonal(rng.uniform(0.5, 1.5, size=n))
+    M2 = diagonal(rng.uniform(0.1, 0.3, size=n))
+    D1 = grid_laplacian(dims, rng, 1.0, 10.0).scaled(1e-2)
+    D2 = _upwind_x(dims, rng, 0.5, 1.0)
+    B = rng.standard_normal((n, k))
+    coefs = np.array([gyro_coefs(*pt) for pt in points])
+    return Job("gyro_like", n, {}, float("nan"), np.arange(len(points), dtype=np.float64), B,
+               meta={"dims": dims, "points": tuple(points),
+                     "matrices": {"K1": K1, "M1": M1, "M2": M2, "D1": D1, "D2": D2, "K2": K2, "K3": K3}},
+               aterms=[K1, M1, M2, D1, D2, K2, K3], coefs=coefs)
