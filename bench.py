@@ -330,8 +330,12 @@ def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, se
     cal = list(range(10_000, 10_000 + n_cal))
     all_ids = cal + list(range(n_jobs))
     # inputs generated and made resident before any timed run
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
+    try:
         jobs = pool.map(config4_job, all_ids)
+    finally:
+        pool.close()  # let the workers exit on their own (no terminate signal)
+        pool.join()
     cache = {}
     for jid, job in zip(all_ids, jobs):
         terms = {r: (torch.as_tensor(T.rowptr, device=dev), torch.as_tensor(T.col, device=dev),
@@ -441,11 +445,12 @@ def _note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def c2_bench(ctx, nsys):
+def c2_bench(ctx, nsys, precision="f32"):
     """Independent systems of the batch workload (n in [4096, 65536], 2-D/3-D,
-    k = 8, power-law SPAI patterns of 5..40 nodes): P_1 at p, the U-diag update
-    at p + 0.02, then the nsys solves at p + 0.02 together (pmor_batch_solve)
-    and one after another (block_solve)."""
+    k = 8, power-law SPAI patterns of 5..40 nodes, least squares in FP32): P_1 at
+    p, the U-diag update at p + 0.02, then the nsys solves at p + 0.02 together
+    (pmor_batch_solve) and one after another (block_solve).  The term matrices,
+    patterns and right-hand sides are on the device before any clock starts."""
     import torch
     import multiprocessing as mp
     from paper_1809_06574_amd import Problem, batch_solve
@@ -453,25 +458,33 @@ def c2_bench(ctx, nsys):
     # the generator runs in fresh interpreters (no fork of a process that holds the GPU)
     _note(f"batch workload: generating {nsys} systems")
     jobs = []
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
+    try:
         for job in pool.imap(_c2_system, range(nsys), chunksize=4):
             jobs.append(job)
             if len(jobs) % 64 == 0:
                 _note(f"batch workload: {len(jobs)}/{nsys} systems generated")
+    finally:
+        pool.close()
+        pool.join()
     dev = ctx.device
-    pbs, hs, Bs = [], [], []
+    dterms, dpats, Bs = [], [], []
+    for job in jobs:
+        dterms.append({r: tuple(torch.as_tensor(x).to(dev) for x in (T.rowptr, T.col, T.val))
+                       for r, T in job.terms.items()})
+        dpats.append(tuple(torch.as_tensor(x).to(dev) for x in job.pattern))
+        Bs.append(torch.as_tensor(job.B, device=dev))
+    pbs, hs = [], []
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for job in jobs:
-        pb = Problem(ctx, job.terms)
-        h = pb.spai_build(job.s, job.p_list[0], pattern=job.pattern)
+    for job, terms, pat in zip(jobs, dterms, dpats):
+        pb = Problem(ctx, terms)
+        h = pb.spai_build(job.s, job.p_list[0], pattern=pat, precision=precision)
         h.update(job.s, job.p_list[1])
         pbs.append(pb)
         hs.append(h)
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t
-    for job in jobs:
-        Bs.append(torch.as_tensor(job.B, device=dev))
     items = [(pb, h, job.s, job.p_list[1], B) for pb, h, job, B in zip(pbs, hs, jobs, Bs)]
     batch_solve(ctx, items)  # warm the engine buffers
     torch.cuda.synchronize()
@@ -485,11 +498,20 @@ def c2_bench(ctx, nsys):
     torch.cuda.synchronize()
     t_point = time.perf_counter() - t
     ns = [job.n for job in jobs]
-    out = {"systems": nsys, "n_min": min(ns), "n_max": max(ns), "k": 8,
+    # least-squares flops of the P_1 builds, sum over columns of 2 |J|^2 (|I| - |J|/3)
+    ls_flops = 0.0
+    for h in hs:
+        jc, _, ic, _ = h.export_sets()
+        nj = torch.diff(jc.to(torch.float64))
+        ni = torch.diff(ic.to(torch.float64))
+        ls_flops += float(torch.sum(2.0 * nj * nj * (ni - nj / 3.0)))
+    out = {"systems": nsys, "n_min": min(ns), "n_max": max(ns), "k": 8, "ls_precision": precision,
            "pattern_sizes": "power law t^-2 on [5, 40]", "all_converged": all(x == 0 for x in status),
            "steps_total": int(sum(st["steps"] for st in stats)),
            "setup_pattern_spai_update_s": t_prep,
            "batched_solves_per_s": nsys / t_batch, "pointwise_solves_per_s": nsys / t_point,
+           "batched_solves_per_s_with_setup": nsys / (t_batch + t_prep),
+           "setup_ls_gflop": ls_flops / 1e9,
            "batched_vs_pointwise": t_point / t_batch}
     for h in hs:
         h.close()

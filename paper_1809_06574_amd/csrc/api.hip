@@ -599,7 +599,7 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
     if (ok && o.update == PMOR_UPD_ADAPTIVE)
       ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), pb->ctx->stream) ==
                hipSuccess &&
-           dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * 8, pb->ctx->stream) == hipSuccess;
+           dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * BUCKET_SLOTS, pb->ctx->stream) == hipSuccess;
     if (!ok) rc = fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
   if (rc != PMOR_OK) {

@@ -197,8 +197,10 @@ struct pmor_spai {
   double* rho = nullptr;     // per-column least-squares residuals
   double* red = nullptr;     // reduction scratch
   int32_t* bucket_cols = nullptr;  // columns sorted into buckets
-  int32_t bucket_count[8] = {0};
-  int32_t bucket_off[8] = {0};
+  int32_t bucket_count[16] = {0};  // per least-squares bucket (slots 0..LS_BUCKETS-1 used)
+  int32_t bucket_off[16] = {0};
+  int32_t bucket_maxJ[16] = {0};  // largest |J_j| and |I_j| of each bucket (sizes the LDS kernels' launches)
+  int32_t bucket_maxI[16] = {0};
   int nbuckets = 0;
   bool identity_order = true;
   bool q_active = false;     // U-pattern update applied (apply Q (P_1 x))
@@ -308,6 +310,11 @@ int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_
 // the U-diag factors q_l, rho_l (stride n) and the first zero column into bad[l]
 // (bad must hold 0x7fffffff); per-point sums of squares into out[l * ostride]
 constexpr int PTS_MAX = 8;
+// least-squares buckets by (|J_j|, |I_j|): 0..7 register kernels (5..7: the LDS
+// kernel in FP64), 8 the LDS kernel; BUCKET_SLOTS bounds the per-bucket arrays,
+// its last slot counts unsupported columns
+constexpr int LS_BUCKETS = 9;
+constexpr int BUCKET_SLOTS = 16;
 int launch_assemble_pts(pmor_problem* pb, const Point* pts, int cnt, const SellView* sv, double* out, int64_t ostride,
                         hipStream_t st);
 int launch_update_diag_pts(pmor_spai* h, const Point* pts, int cnt, double* q, double* rho, int* bad, hipStream_t st);

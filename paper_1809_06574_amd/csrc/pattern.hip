@@ -482,8 +482,9 @@ __global__ __launch_bounds__(256) void k_shadow_small(int n, const int32_t* Jcol
   }
 }
 
-// columns SH_SMALL < |J_j| <= SH_JMAX with at most SH_CAP candidates; a block
-// scans 64 columns at a time and sorts the qualifying ones one after another
+// columns SH_SMALL < |J_j| <= SH_JMAX with at most SH_CAP candidates: one
+// wavefront per column (grid-stride over the columns, the others skipped) copies
+// the candidate rows into LDS, sorts them (bitonic) and keeps the distinct rows
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolptr, const int32_t* Jrow,
                                                     const int32_t* Acolptr, const int32_t* Arowidx, int64_t* counts,
@@ -491,75 +492,67 @@ __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolpt
   __shared__ int buf[SH_CAP];
   const int lane = threadIdx.x;
   int mj = 0, mi = 0;
-  for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
-    const int jl = j0 + lane;
-    const int njl = jl < n ? Jcolptr[jl + 1] - Jcolptr[jl] : 0;
-    if (njl > SH_JMAX) {  // unsupported; reported through maxJ
-      if (!FILL) counts[jl] = 0;
-      mj = max(mj, njl);
+  for (int j = blockIdx.x; j < n; j += gridDim.x) {
+    const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
+    if (nj > SH_JMAX) {  // unsupported; reported through maxJ
+      if (!FILL && lane == 0) counts[j] = 0;
+      mj = max(mj, nj);
+      continue;
     }
-    unsigned long long todo = __ballot(njl > SH_SMALL && njl <= SH_JMAX);
-    while (todo) {
-      const int b = __ffsll((long long)todo) - 1;
-      todo &= todo - 1;
-      const int j = j0 + b;
-      const int ja = Jcolptr[j], nj = Jcolptr[j + 1] - ja;
-      // lane t owns column t of J_j
-      int len = 0, c0 = 0;
-      if (lane < nj) {
-        const int c = Jrow[ja + lane];
-        c0 = Acolptr[c];
-        len = Acolptr[c + 1] - c0;
-      }
-      int incl = len;  // inclusive scan over the lanes
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      const int total = __shfl(incl, 63, 64);
-      if (total > SH_CAP) continue;  // k_shadow_merge
-      const int off = incl - len;
-      int P = 1;
-      while (P < total) P <<= 1;
-      for (int q = 0; q < len; ++q) buf[off + q] = Arowidx[c0 + q];
-      for (int i = total + lane; i < P; i += 64) buf[i] = 0x7fffffff;
-      __syncthreads();
-      for (int k = 2; k <= P; k <<= 1)
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-          for (int i = lane; i < P; i += 64) {
-            const int ixj = i ^ jj;
-            if (ixj > i) {
-              const int x = buf[i], y = buf[ixj];
-              if ((x > y) == ((i & k) == 0)) {
-                buf[i] = y;
-                buf[ixj] = x;
-              }
+    if (nj <= SH_SMALL) continue;  // k_shadow_small
+    // lane t owns column t of J_j
+    int len = 0, c0 = 0;
+    if (lane < nj) {
+      const int c = Jrow[ja + lane];
+      c0 = Acolptr[c];
+      len = Acolptr[c + 1] - c0;
+    }
+    int incl = len;  // inclusive scan over the lanes
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (total > SH_CAP) continue;  // k_shadow_merge
+    const int off = incl - len;
+    int P = 1;
+    while (P < total) P <<= 1;
+    __syncthreads();  // the previous column's reads of buf are done
+    for (int q = 0; q < len; ++q) buf[off + q] = Arowidx[c0 + q];
+    for (int i = total + lane; i < P; i += 64) buf[i] = 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1)
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = lane; i < P; i += 64) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const int x = buf[i], y = buf[ixj];
+            if ((x > y) == ((i & k) == 0)) {
+              buf[i] = y;
+              buf[ixj] = x;
             }
           }
-          __syncthreads();
         }
-      // distinct rows, in order
-      int64_t pos = FILL ? Icolptr[j] : 0;
-      int cnt = 0;
-      for (int i0 = 0; i0 < total; i0 += 64) {
-        const int i = i0 + lane;
-        const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
-        const unsigned long long m = __ballot(keep);
-        if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
-        cnt += __popcll(m);
+        __syncthreads();
       }
-      __syncthreads();
-      if (!FILL && lane == 0) counts[j] = cnt;
-      mj = max(mj, nj);
-      mi = max(mi, cnt);
+    // distinct rows, in order
+    int64_t pos = FILL ? Icolptr[j] : 0;
+    int cnt = 0;
+    for (int i0 = 0; i0 < total; i0 += 64) {
+      const int i = i0 + lane;
+      const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
+      const unsigned long long m = __ballot(keep);
+      if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
+      cnt += __popcll(m);
     }
+    if (!FILL && lane == 0) counts[j] = cnt;
+    mj = max(mj, nj);
+    mi = max(mi, cnt);
   }
-  if (!FILL) {
-    mj = wave_max(mj);
-    if (lane == 0) {
-      atomicMax(maxJ, mj);
-      atomicMax(maxI, mi);
-    }
+  // one atomic per workgroup, and none when it cannot raise the maximum
+  if (!FILL && lane == 0) {
+    if (mj > *(volatile int*)maxJ) atomicMax(maxJ, mj);
+    if (mi > *(volatile int*)maxI) atomicMax(maxI, mi);
   }
 }
 
@@ -616,7 +609,7 @@ static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, con
     PMOR_HIP(hipGetLastError());
     return PMOR_OK;
   }
-  const unsigned gs = (unsigned)std::min((n + 63) / 64, 8192);
+  const unsigned gs = (unsigned)std::min(n, 8192);
   hipLaunchKernelGGL(k_shadow_sort<FILL>, dim3(gs), dim3(64), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
                      Icolptr, Irow, maxJ, maxI);
   hipLaunchKernelGGL(k_shadow_merge<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
@@ -631,28 +624,46 @@ __global__ void k_invert_map(const int32_t* map, int64_t len, int32_t* inv) {
   if (q < len) inv[map[q]] = (int32_t)q;
 }
 
-// bucket of a column: the least-squares kernel that takes it
-// (16 lanes per column with R rows each: |I| <= 16 R; the LDS kernel above)
+// bucket of a column: the least-squares kernel that takes it (16, 32 or 64
+// lanes per column with R rows each, |I| <= G R, in registers; FP64 takes the
+// LDS kernel for buckets 5 to 7; the LDS kernel above, each launch sized to the
+// largest column of its bucket)
 __host__ __device__ inline int bucket_of(int nj, int ni) {
   if (nj <= 8 && ni <= 16) return 0;
   if (nj <= 8 && ni <= 32) return 1;
   if (nj <= 8 && ni <= 64) return 2;
   if (nj <= 16 && ni <= 64) return 3;
   if (nj <= 16 && ni <= 128) return 4;
-  if (nj <= 64 && ni <= 512) return 5;
-  return 7;  // unsupported
+  if (nj <= 32 && ni <= 64) return 5;
+  if (nj <= 32 && ni <= 128) return 6;
+  if (nj <= 64 && ni <= 128) return 7;
+  if (nj <= 64 && ni <= 512) return 8;
+  return BUCKET_SLOTS - 1;  // unsupported
 }
 
 // columns per (|J_j|, |I_j|) bucket from the shadow sizes before their scan
-// (counts[j] = |I_j|): a histogram in LDS, one global atomic per bucket and workgroup
+// (counts[j] = |I_j|): a histogram in LDS, one global atomic per bucket and
+// workgroup into bcount[0..S) (S = BUCKET_SLOTS); the largest |J_j| and |I_j|
+// per bucket into bcount[2S + b], bcount[3S + b]
 __global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* counts, int* bcount) {
-  __shared__ int h[8];
-  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  constexpr int S = BUCKET_SLOTS;
+  __shared__ int h[S], mj[S], mi[S];
+  if (threadIdx.x < S) h[threadIdx.x] = mj[threadIdx.x] = mi[threadIdx.x] = 0;
   __syncthreads();
   int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) atomicAdd(&h[bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)counts[j])], 1);
+  if (j < n) {
+    const int nj = Jcolptr[j + 1] - Jcolptr[j], ni = (int)counts[j];
+    const int b = bucket_of(nj, ni);
+    atomicAdd(&h[b], 1);
+    atomicMax(&mj[b], nj);
+    atomicMax(&mi[b], ni);
+  }
   __syncthreads();
-  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x < S && h[threadIdx.x]) {
+    atomicAdd(&bcount[threadIdx.x], h[threadIdx.x]);
+    atomicMax(&bcount[2 * S + threadIdx.x], mj[threadIdx.x]);
+    atomicMax(&bcount[3 * S + threadIdx.x], mi[threadIdx.x]);
+  }
 }
 
 // Fill the bucket lists: each workgroup counts its columns per bucket in LDS,
@@ -661,19 +672,20 @@ __global__ void k_bucket_count(int n, const int32_t* Jcolptr, const int64_t* cou
 // runs; every column is still solved on its own, so results do not depend on it.
 __global__ __launch_bounds__(256) void k_bucket_fill(int n, const int32_t* Jcolptr, const int64_t* Icolptr,
                                                      const int* boff, int* cursor, int32_t* cols) {
-  __shared__ int cnt[8], base[8], pos[8][256];
+  constexpr int S = BUCKET_SLOTS;
+  __shared__ int cnt[S], base[S], pos[S][256];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = (j < n) ? bucket_of(Jcolptr[j + 1] - Jcolptr[j], (int)(Icolptr[j + 1] - Icolptr[j])) : -1;
-  for (int q = 0; q < 8; ++q) pos[q][threadIdx.x] = (b == q);
+  for (int q = 0; q < S; ++q) pos[q][threadIdx.x] = (b == q);
   __syncthreads();
   for (int o = 1; o < 256; o <<= 1) {  // inclusive scan per bucket
-    int v[8];
-    for (int q = 0; q < 8; ++q) v[q] = (threadIdx.x >= o) ? pos[q][threadIdx.x - o] : 0;
+    int v[S];
+    for (int q = 0; q < S; ++q) v[q] = (threadIdx.x >= o) ? pos[q][threadIdx.x - o] : 0;
     __syncthreads();
-    for (int q = 0; q < 8; ++q) pos[q][threadIdx.x] += v[q];
+    for (int q = 0; q < S; ++q) pos[q][threadIdx.x] += v[q];
     __syncthreads();
   }
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < S) {
     cnt[threadIdx.x] = pos[threadIdx.x][255];
     base[threadIdx.x] = cnt[threadIdx.x] ? boff[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]) : 0;
   }
@@ -741,16 +753,18 @@ int build_spai_sets(pmor_spai* h) {
   PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
   PMOR_TRY(launch_shadow<false>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, cnt, nullptr, nullptr, dflag + 1,
                                 dflag + 2, jmax, st));
-  int* bc = nullptr;
-  PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 16, st));
-  PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 16, st));
+  constexpr int S = BUCKET_SLOTS;
+  int* bc = nullptr;  // counts [0, S), offsets [S, 2S), largest |J| [2S, 3S), largest |I| [3S, 4S)
+  PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 4 * S, st));
+  PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 4 * S, st));
   hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(256), 0, st, n, h->Jcolptr, cnt, bc);
   PMOR_HIP(hipGetLastError());
   PMOR_TRY(scan_exclusive(cnt, n, st));
   int hm[2] = {0, 0};
-  int hb[8];
+  int hb[S], hx[2 * S];
   PMOR_HIP(hipMemcpyAsync(hm, dflag + 1, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-  PMOR_HIP(hipMemcpyAsync(hb, bc, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipMemcpyAsync(hb, bc, sizeof(int) * S, hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipMemcpyAsync(hx, bc + 2 * S, sizeof(int) * 2 * S, hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipMemcpyAsync(&h->nI, cnt + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   h->maxJ = hm[0];
@@ -765,27 +779,31 @@ int build_spai_sets(pmor_spai* h) {
   PMOR_TRY(launch_shadow<true>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, nullptr, h->Icolptr, h->Irow, nullptr,
                                nullptr, jmax, st));
   int off = 0, nonempty = 0;
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < S; ++b) {
     h->bucket_count[b] = hb[b];
     h->bucket_off[b] = off;
+    h->bucket_maxJ[b] = hx[b];
+    h->bucket_maxI[b] = hx[S + b];
     off += hb[b];
     nonempty += hb[b] > 0;
   }
-  h->nbuckets = 8;
+  h->nbuckets = S;
   // when the largest column fits a register kernel, every column takes that one
   // kernel in natural order (no lists, one launch)
   const int bmax = bucket_of(h->maxJ, h->maxI);
   h->identity_order = (bmax <= 4);
   if (h->identity_order) {
-    for (int b = 0; b < 8; ++b) { h->bucket_count[b] = 0; h->bucket_off[b] = 0; }
+    for (int b = 0; b < S; ++b) { h->bucket_count[b] = 0; h->bucket_off[b] = 0; }
     h->bucket_count[bmax] = n;
+    h->bucket_maxJ[bmax] = h->maxJ;
+    h->bucket_maxI[bmax] = h->maxI;
   }
-  for (int b = 0; b < 8; ++b) h->identity_order = h->identity_order || (hb[b] == n);
+  for (int b = 0; b < S; ++b) h->identity_order = h->identity_order || (hb[b] == n);
   if (!h->identity_order) {
-    int* hb_off = reinterpret_cast<int*>(bc) + 8;
-    for (int b = 0; b < 8; ++b) hb[b] = h->bucket_off[b];
-    PMOR_HIP(hipMemcpyAsync(hb_off, hb, sizeof(int) * 8, hipMemcpyHostToDevice, st));
-    PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * 8, st));
+    int* hb_off = reinterpret_cast<int*>(bc) + S;
+    for (int b = 0; b < S; ++b) hb[b] = h->bucket_off[b];
+    PMOR_HIP(hipMemcpyAsync(hb_off, hb, sizeof(int) * S, hipMemcpyHostToDevice, st));
+    PMOR_HIP(hipMemsetAsync(bc, 0, sizeof(int) * S, st));
     PMOR_HIP(dmalloc((void**)&h->bucket_cols, sizeof(int32_t) * (n > 0 ? n : 1), st));
     hipLaunchKernelGGL(k_bucket_fill, dim3(g), dim3(256), 0, st, n, h->Jcolptr, h->Icolptr, hb_off, bc,
                        h->bucket_cols);

@@ -52,6 +52,9 @@ struct LsArgs {
   const int64_t* Icolptr;
   const int32_t* Irow;
   const int32_t* Pslot;
+  const int32_t* Acolptr;  // CSC view of A's pattern (the LDS kernel gathers by columns)
+  const int32_t* Arowidx;
+  const int32_t* Acscslot;  // CSC position -> CSR position of the value
   double* out;     // values in P's CSR order
   double* rho;     // per-column residual norm
   int* bad_col;    // smallest singular column (atomicMin)
@@ -94,7 +97,54 @@ __device__ __forceinline__ T row_max(T x) {
   return x;
 }
 
+// the same over a group of G = 16 or 32 lanes (G = 32: the two rows' results
+// added in the same order on both rows, so every lane of the group holds the
+// same bits)
+template <int G, typename T>
+__device__ __forceinline__ T grp_sum(T x) {
+  x = row_sum(x);
+  if constexpr (G >= 32) {
+    const T y = __shfl_xor(x, 16, 64);
+    x = ((threadIdx.x & 16) == 0) ? x + y : y + x;
+  }
+  if constexpr (G == 64) {
+    const T y = __shfl_xor(x, 32, 64);
+    x = ((threadIdx.x & 32) == 0) ? x + y : y + x;
+  }
+  return x;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T grp_max(T x) {
+  x = row_max(x);
+  if constexpr (G >= 32) {
+    const T y = __shfl_xor(x, 16, 64);
+    x = x > y ? x : y;
+  }
+  if constexpr (G == 64) {
+    const T y = __shfl_xor(x, 32, 64);
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
 // value of lane k (0..15, a constant after unrolling) of this lane's row
+template <typename T>
+__device__ __forceinline__ T row_bcast(T x, int k);
+
+// value of lane k (a constant after unrolling) of this lane's group of G lanes
+template <int G, typename T>
+__device__ __forceinline__ T grp_bcast(T x, int k) {
+  if constexpr (G == 16) return row_bcast(x, k);
+  else return __shfl(x, (int)(threadIdx.x & ~(unsigned)(G - 1)) + k, 64);
+}
+
+// the same for a k known only at run time (uniform over the wavefront)
+template <int G, typename T>
+__device__ __forceinline__ T grp_bcast_dyn(T x, int k) {
+  return __shfl(x, (int)(threadIdx.x & ~(unsigned)(G - 1)) + k, 64);
+}
+
 template <typename T>
 __device__ __forceinline__ T row_bcast(T x, int k) {
   switch (k) {
@@ -130,12 +180,14 @@ __device__ __forceinline__ Q16Scale q16_scale(float mx) {
 }
 __device__ __forceinline__ float q16(float x, Q16Scale q) { return __half2float(__float2half_rn(x * q.sc)) * q.isc; }
 
-template <typename T, int JMAX, int R, bool Q16 = false>
+template <typename T, int JMAX, int R, bool Q16 = false, int G = 16>
 __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
-  static_assert(JMAX <= 16, "row k of R must sit in lane k of the row");
-  const int gl = threadIdx.x & 15;
-  const int wid = (xcd_swizzle(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> 4;
-  if (wid >= a.ncols) return;  // whole 16-lane rows leave together
+  static_assert(G == 16 || G == 32 || G == 64, "groups of one, two or four DPP rows");
+  static_assert(JMAX <= G, "row k of R must sit in lane k of the group");
+  constexpr int LG = G == 16 ? 4 : (G == 32 ? 5 : 6);
+  const int gl = threadIdx.x & (G - 1);
+  const int wid = (xcd_swizzle(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> LG;
+  if (wid >= a.ncols) return;  // whole groups leave together
   const int j = a.cols ? a.cols[wid] : a.col_off + wid;
   const int jb = a.Jcolptr[j];
   const int nj = a.Jcolptr[j + 1] - jb;
@@ -144,25 +196,60 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
 
   T A_[R][JMAX];
   T b_[R];
-  // gather A(I_j, J_j) and the right-hand side
+  // gather A(I_j, J_j) and the right-hand side: a row's first RW entries are
+  // loaded at once (independent loads) and matched against J_j in registers;
+  // longer rows continue with a cursor search
+  constexpr int RW = 8;
+  int Jv[JMAX];
+#pragma unroll
+  for (int t = 0; t < JMAX; ++t) Jv[t] = (t < nj) ? a.Jrow[jb + t] : -1;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int li = gl + 16 * r;
+    const int li = gl + G * r;
     const int row = (li < ni) ? a.Irow[ib + li] : -1;
 #pragma unroll
     for (int t = 0; t < JMAX; ++t) A_[r][t] = T(0);
     b_[r] = T(0);
     if (row >= 0) {
-      int e = a.rowptr[row];
+      const int e0 = a.rowptr[row];
       const int ee = a.rowptr[row + 1];
+      int cc[RW];
+      double vv[RW], ww[RW];
 #pragma unroll
-      for (int t = 0; t < JMAX; ++t)
-        if (t < nj) A_[r][t] = (T)row_lookup(a.colidx, a.aval, e, ee, a.Jrow[jb + t]);
+      for (int u = 0; u < RW; ++u) {
+        const bool in = e0 + u < ee;
+        cc[u] = in ? a.colidx[e0 + u] : -2;
+        vv[u] = in ? a.aval[e0 + u] : 0.0;
+        ww[u] = (in && a.rhs_aval) ? a.rhs_aval[e0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < JMAX; ++t) {
+        double x = 0.0;
+#pragma unroll
+        for (int u = 0; u < RW; ++u) x = (cc[u] == Jv[t]) ? vv[u] : x;
+        A_[r][t] = (T)x;
+      }
       if (a.rhs_aval) {
-        int e2 = a.rowptr[row];
-        b_[r] = (T)row_lookup(a.colidx, a.rhs_aval, e2, ee, j);
+        double x = 0.0;
+#pragma unroll
+        for (int u = 0; u < RW; ++u) x = (cc[u] == j) ? ww[u] : x;
+        b_[r] = (T)x;
       } else {
         b_[r] = (row == j) ? T(1) : T(0);
+      }
+      if (ee - e0 > RW) {  // the rest of a long row
+        int e = e0 + RW;
+#pragma unroll
+        for (int t = 0; t < JMAX; ++t)
+          if (t < nj) {
+            const double x = row_lookup(a.colidx, a.aval, e, ee, Jv[t]);
+            if (x != 0.0) A_[r][t] = (T)x;
+          }
+        if (a.rhs_aval) {
+          int e2 = e0 + RW;
+          const double x = row_lookup(a.colidx, a.rhs_aval, e2, ee, j);
+          if (x != 0.0) b_[r] = (T)x;
+        }
       }
     }
   }
@@ -173,7 +260,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
         T mx = T(0);
 #pragma unroll
         for (int r = 0; r < R; ++r) mx = fmaxf(mx, fabsf(A_[r][t]));
-        const Q16Scale q = q16_scale(row_max(mx));
+        const Q16Scale q = q16_scale(grp_max<G>(mx));
 #pragma unroll
         for (int r = 0; r < R; ++r) A_[r][t] = q16(A_[r][t], q);
       }
@@ -182,68 +269,89 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       T mx = T(0);
 #pragma unroll
       for (int r = 0; r < R; ++r) mx = fmaxf(mx, fabsf(b_[r]));
-      const Q16Scale q = q16_scale(row_max(mx));
+      const Q16Scale q = q16_scale(grp_max<G>(mx));
 #pragma unroll
       for (int r = 0; r < R; ++r) b_[r] = q16(b_[r], q);
     }
   }
   T minDiag = T(3.0e38);
-  // Householder QR, one reflector per column k: one round of row sums gives the
-  // column norm and every inner product the reflector needs
+  // Householder QR, one reflector per column k: one round of group sums gives
+  // the column norm and every inner product the reflector needs.  The loop over
+  // k stays rolled and every register index is static: column k is picked out
+  // by selects and the loops over c run over all columns with a (uniform) test
+  // c >= k, so the block never leaves the registers.
+  for (int k = 0; k < nj; ++k) {
+    T xk[R];  // column k of this lane's rows
 #pragma unroll
-  for (int k = 0; k < JMAX; ++k) {
-    if (k < nj) {
-      T s[JMAX + 1];
+    for (int r = 0; r < R; ++r) {
+      T x = T(0);
 #pragma unroll
-      for (int c = 0; c <= JMAX; ++c) s[c] = T(0);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int li = gl + 16 * r;
-        if (li >= k) {
-          const T x = A_[r][k];
-#pragma unroll
-          for (int c = k; c < JMAX; ++c) s[c] += x * A_[r][c];
-          s[JMAX] += x * b_[r];
-        }
-      }
-#pragma unroll
-      for (int c = k; c <= JMAX; ++c)
-        if (c < nj || c == JMAX) s[c] = row_sum(s[c]);
-      const T alpha = row_bcast(A_[0][k], k);
-      const T sig = s[k];
-      T beta = alpha;
-      if (sig != alpha * alpha) {
-        const T nrm = sqrt(sig);
-        beta = (alpha >= T(0)) ? -nrm : nrm;
-        const T denom = beta * (beta - alpha);
-        T f[JMAX + 1];
-#pragma unroll
-        for (int c = k + 1; c < JMAX; ++c)
-          if (c < nj) f[c] = (s[c] - beta * row_bcast(A_[0][c], k)) / denom;
-        f[JMAX] = (s[JMAX] - beta * row_bcast(b_[0], k)) / denom;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int li = gl + 16 * r;
-          if (li >= k) {
-            const T v = (li == k) ? (alpha - beta) : A_[r][k];
-#pragma unroll
-            for (int c = k + 1; c < JMAX; ++c)
-              if (c < nj) A_[r][c] -= f[c] * v;
-            b_[r] -= f[JMAX] * v;
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int li = gl + 16 * r;
-        if (li == k) A_[r][k] = beta;
-        else if (li > k) A_[r][k] = T(0);
-      }
-      const T ab = beta < T(0) ? -beta : beta;
-      minDiag = ab < minDiag ? ab : minDiag;
+      for (int t = 0; t < JMAX; ++t) x = (t == k) ? A_[r][t] : x;
+      xk[r] = x;
     }
+    T s[JMAX + 1];
+#pragma unroll
+    for (int c = 0; c <= JMAX; ++c) s[c] = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int li = gl + G * r;
+      if (li >= k) {
+        const T x = xk[r];
+#pragma unroll
+        for (int c = 0; c < JMAX; ++c)
+          if (c >= k) s[c] += x * A_[r][c];
+        s[JMAX] += x * b_[r];
+      }
+    }
+    // the sums in chunks of 8 columns: one uniform test per chunk, eight
+    // independent reductions inside it
+#pragma unroll
+    for (int c0 = 0; c0 < JMAX; c0 += 8)
+      if (c0 + 8 > k && c0 < nj) {
+#pragma unroll
+        for (int c = c0; c < c0 + 8 && c < JMAX; ++c) s[c] = grp_sum<G>(s[c]);
+      }
+    s[JMAX] = grp_sum<G>(s[JMAX]);
+    T sig = T(0);
+#pragma unroll
+    for (int c = 0; c < JMAX; ++c) sig = (c == k) ? s[c] : sig;
+    const T alpha = grp_bcast_dyn<G>(xk[0], k);  // row k < nj <= G sits in slot 0 of lane k
+    T beta = alpha;
+    if (sig != alpha * alpha) {
+      const T nrm = sqrt(sig);
+      beta = (alpha >= T(0)) ? -nrm : nrm;
+      const T rden = T(1) / (beta * (beta - alpha));
+      // the reflector's factor of every column replaces its inner product
+#pragma unroll
+      for (int c = 0; c < JMAX; ++c)
+        if (c > k && c < nj) s[c] = (s[c] - beta * grp_bcast_dyn<G>(A_[0][c], k)) * rden;
+      s[JMAX] = (s[JMAX] - beta * grp_bcast_dyn<G>(b_[0], k)) * rden;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int li = gl + G * r;
+        if (li >= k) {
+          const T v = (li == k) ? (alpha - beta) : xk[r];
+#pragma unroll
+          for (int c = 0; c < JMAX; ++c)
+            if (c > k && c < nj) A_[r][c] -= s[c] * v;
+          b_[r] -= s[JMAX] * v;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int li = gl + G * r;
+#pragma unroll
+      for (int t = 0; t < JMAX; ++t)
+        if (t == k) {
+          if (li == k) A_[r][t] = beta;
+          else if (li > k) A_[r][t] = T(0);
+        }
+    }
+    const T ab = beta < T(0) ? -beta : beta;
+    minDiag = ab < minDiag ? ab : minDiag;
   }
-  // max |R| over the triangle (rows < nj <= 16 live in slot 0)
+  // max |R| over the triangle (rows < nj <= G live in slot 0)
   T mx = T(0);
   if (gl < nj) {
 #pragma unroll
@@ -253,7 +361,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
         mx = v > mx ? v : mx;
       }
   }
-  const T maxR = row_max(mx);
+  const T maxR = grp_max<G>(mx);
   // back substitution R p = (Q^T b)(0:nj), one unknown at a time
   T mine = T(0);
   T p[JMAX];
@@ -265,7 +373,7 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
       for (int c = i + 1; c < JMAX; ++c)
         if (c < nj) acc -= A_[0][c] * p[c];
       const T pi = acc / A_[0][i];
-      p[i] = row_bcast(pi, i);
+      p[i] = grp_bcast<G>(pi, i);
       if (gl == i) mine = pi;
     } else {
       p[i] = T(0);
@@ -275,10 +383,10 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
   T rr = T(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int li = gl + 16 * r;
+    const int li = gl + G * r;
     if (li >= nj && li < ni) rr += b_[r] * b_[r];
   }
-  rr = row_sum(rr);
+  rr = grp_sum<G>(rr);
   if (gl < nj) a.out[a.Pslot[jb + gl]] = (double)mine;
   if (gl == 0) {
     a.rho[j] = sqrt((double)rr);
@@ -288,13 +396,30 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS kernel: |J| <= 64, |I| <= 512; one wavefront per workgroup
+// LDS kernel: |J| <= 64, |I| <= 512; one wavefront per workgroup, its LDS sized
+// to the largest column of the launch (ldI x (JM + 1) values and ldI row
+// indices).  The gather goes by the columns of A: all rows of A(:, J_t) lie in
+// I_j (that is how I_j is defined), so lane t takes column J_t's entries in
+// CSC order and places each at its row's position in I_j, found by binary
+// search in the sorted rows held in LDS.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_lower_bound(const int* rows, int len, int r) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (rows[mid] < r) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <typename T, bool Q16 = false>
 __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   extern __shared__ unsigned char smem_raw[];
-  T* S = reinterpret_cast<T*>(smem_raw);  // column-major [JM + 1][ldI]: A_hat then rhs
+  T* S = reinterpret_cast<T*>(smem_raw);  // column-major [nj + 1][ldI]: A_hat then rhs (JM >= nj)
+  int* Is = reinterpret_cast<int*>(S + (size_t)(JM + 1) * ldI);  // the rows I_j
   __shared__ double sv[66];
+  __shared__ T sf[66];  // the reflector's factor per column
   const int lane = threadIdx.x;
   const int wid = blockIdx.x;
   if (wid >= a.ncols) return;
@@ -303,18 +428,28 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   const int nj = a.Jcolptr[j + 1] - jb;
   const int64_t ib = a.Icolptr[j];
   const int ni = (int)(a.Icolptr[j + 1] - ib);
-  T* B = S + (size_t)JM * ldI;
-  for (int li = lane; li < ni; li += 64) {
-    const int row = a.Irow[ib + li];
-    int e = a.rowptr[row];
-    const int ee = a.rowptr[row + 1];
-    for (int t = 0; t < nj; ++t) S[(size_t)t * ldI + li] = (T)row_lookup(a.colidx, a.aval, e, ee, a.Jrow[jb + t]);
-    if (a.rhs_aval) {
-      int e2 = a.rowptr[row];
-      B[li] = (T)row_lookup(a.colidx, a.rhs_aval, e2, ee, j);
-    } else {
-      B[li] = (row == j) ? T(1) : T(0);
+  T* B = S + (size_t)nj * ldI;  // the right-hand side is column nj of S
+  for (int li = lane; li < ni; li += 64) Is[li] = a.Irow[ib + li];
+  for (int t = 0; t <= nj; ++t) {
+    T* colt = (t < nj) ? S + (size_t)t * ldI : B;
+    for (int li = lane; li < ni; li += 64) colt[li] = T(0);
+  }
+  __syncthreads();
+  if (lane < nj) {
+    const int c = a.Jrow[jb + lane];
+    T* colt = S + (size_t)lane * ldI;
+    int q = 0;
+    for (int e = a.Acolptr[c]; e < a.Acolptr[c + 1]; ++e) {
+      const int r = a.Arowidx[e];
+      q += lds_lower_bound(Is + q, ni - q, r);  // rows of A(:, c) ascend: search from the last hit
+      colt[q] = (T)a.aval[a.Acscslot[e]];
     }
+  }
+  if (a.rhs_aval) {  // A(1) e_j on I_j: the entries of column j
+    for (int e = a.Acolptr[j] + lane; e < a.Acolptr[j + 1]; e += 64)
+      B[lds_lower_bound(Is, ni, a.Arowidx[e])] = (T)a.rhs_aval[a.Acscslot[e]];
+  } else if (lane == 0) {
+    B[lds_lower_bound(Is, ni, j)] = T(1);
   }
   __syncthreads();
   if constexpr (Q16) {
@@ -329,32 +464,45 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
     __syncthreads();
   }
   T minDiag = T(3.0e38);
+  constexpr int CH = 8;  // columns per chunk: independent sums side by side
   for (int k = 0; k < nj; ++k) {
-    // one reduction per reflector: s[c] = x . a_c for c in [k, nj) and x . b
-    for (int c = k; c <= nj; ++c) {
-      const T* colc = (c < nj) ? S + (size_t)c * ldI : B;
-      T part = T(0);
-      for (int li = k + lane; li < ni; li += 64) part += S[(size_t)k * ldI + li] * colc[li];
-      part = wave_sum(part);
-      if (lane == 0) sv[c - k] = (double)part;
+    // s[c] = x . a_c for c in [k, nj) and x . b (c = nj), CH columns per pass
+    const T* colk = S + (size_t)k * ldI;
+    for (int c0 = k; c0 <= nj; c0 += CH) {
+      T part[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) part[u] = T(0);
+      for (int li = k + lane; li < ni; li += 64) {
+        const T x = colk[li];
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (c0 + u <= nj) part[u] += x * S[(size_t)(c0 + u) * ldI + li];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (c0 + u <= nj) {
+          const T t = wave_sum(part[u]);
+          if (lane == 0) sv[c0 + u - k] = (double)t;
+        }
     }
     __syncthreads();
-    const T alpha = S[(size_t)k * ldI + k];
+    const T alpha = colk[k];
     const T sig = (T)sv[0];
     T beta = alpha;
     if (sig != alpha * alpha) {
       const T nrm = sqrt(sig);
       beta = (alpha >= T(0)) ? -nrm : nrm;
       const T denom = beta * (beta - alpha);
-      for (int c = k + 1; c <= nj; ++c) {
-        T* colc = (c < nj) ? S + (size_t)c * ldI : B;
-        const T f = ((T)sv[c - k] - beta * colc[k]) / denom;
-        __syncthreads();
-        for (int li = k + lane; li < ni; li += 64) {
-          const T v = (li == k) ? (alpha - beta) : S[(size_t)k * ldI + li];
-          colc[li] -= f * v;
+      // the factors of every column (a_c(k) is read before any lane writes it)
+      for (int c = k + 1 + lane; c <= nj; c += 64) sf[c] = ((T)sv[c - k] - beta * S[(size_t)c * ldI + k]) / denom;
+      __syncthreads();
+      for (int li = k + lane; li < ni; li += 64) {
+        const T v = (li == k) ? (alpha - beta) : colk[li];
+        for (int c0 = k + 1; c0 <= nj; c0 += CH) {
+#pragma unroll
+          for (int u = 0; u < CH; ++u)
+            if (c0 + u <= nj) S[(size_t)(c0 + u) * ldI + li] -= sf[c0 + u] * v;
         }
-        __syncthreads();
       }
     }
     __syncthreads();
@@ -398,15 +546,38 @@ template <typename T, bool Q16 = false>
 static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pmor_ctx* pc, int pidx, int part) {
   if (a.ncols == 0) return PMOR_OK;
   const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
+  const unsigned g32 = (unsigned)((a.ncols + 7) / 8);    // 8 columns (of 32 lanes) per workgroup
+  const unsigned g64 = (unsigned)((a.ncols + 3) / 4);    // 4 columns (of 64 lanes) per workgroup
+  // |J| <= 32 with |I| <= 128 in registers for 4-byte values; FP64 would need
+  // 256 registers for the block, so it takes the LDS kernel
+  constexpr bool REG32 = sizeof(T) == 4;
   switch (b) {
     case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16>, dim3(g16), dim3(256), 0, st, a); break;
     case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16>, dim3(g16), dim3(256), 0, st, a); break;
     case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
     case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
     case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16>, dim3(g16), dim3(256), 0, st, a); break;
-    case 5: {
+    case 5:
+      if constexpr (REG32) {
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32>, dim3(g32), dim3(256), 0, st, a);
+        break;
+      }
+      [[fallthrough]];
+    case 6:
+      if constexpr (REG32) {
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 4, Q16, 32>, dim3(g32), dim3(256), 0, st, a);
+        break;
+      }
+      [[fallthrough]];
+    case 7:
+      if constexpr (REG32) {
+        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64>, dim3(g64), dim3(256), 0, st, a);
+        break;
+      }
+      [[fallthrough]];
+    case 8: {
       const int ldI = ((maxI + 7) / 8) * 8;
-      const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI;
+      const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI + sizeof(int) * (size_t)ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
       PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16>, shm));
       plaunch(pc, pidx, part, k_spai_lds<T, Q16>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
@@ -461,20 +632,22 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
   a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval; a.rhs_aval = rhs_aval;
   a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
   a.Pslot = h->Pslot; a.out = out_val; a.rho = h->rho; a.bad_col = dbad;
+  a.Acolptr = pb->colptr; a.Arowidx = pb->rowidx; a.Acscslot = pb->cscslot;
   const int pr = prof_start(pb->ctx, PMOR_PROF_SPAI_LS);
   int first_b = -1, last_b = -1;
-  for (int b = 0; b < 6; ++b)
+  for (int b = 0; b < LS_BUCKETS; ++b)
     if (h->bucket_count[b]) { if (first_b < 0) first_b = b; last_b = b; }
-  for (int b = 0; b < 6; ++b) {
+  for (int b = 0; b < LS_BUCKETS; ++b) {
     if (h->bucket_count[b] == 0) continue;
     const int part = (b == first_b ? 1 : 0) | (b == last_b ? 2 : 0);
     a.ncols = h->bucket_count[b];
     if (h->identity_order) { a.cols = nullptr; a.col_off = 0; }  // every column sits in bucket b
     else { a.cols = h->bucket_cols + h->bucket_off[b]; a.col_off = 0; }
-    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
+    const int mj = h->bucket_maxJ[b], mi = h->bucket_maxI[b];
+    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, mj, mi, st, pb->ctx, pr, part));
     else if (h->opts.precision == PMOR_F16S)
-      PMOR_TRY((launch_bucket<float, true>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part)));
-    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st, pb->ctx, pr, part));
+      PMOR_TRY((launch_bucket<float, true>(b, a, mj, mi, st, pb->ctx, pr, part)));
+    else PMOR_TRY(launch_bucket<double>(b, a, mj, mi, st, pb->ctx, pr, part));
   }
   prof_stop(pb->ctx, pr,
             12.0 * pb->nnz + 4.0 * pb->n + 4.0 * ((double)h->nI + h->nnzP) + 8.0 * h->nnzP + 8.0 * pb->n, 0);
@@ -638,8 +811,8 @@ int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_
     hipLaunchKernelGGL(k_update_adaptive_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, pb->colptr,
                        pb->cscslot, aval_l, h->aval1, h->opts.adapt_ep, h->Jcolptr, h->Jrow, h->Pslot, qout, h->rho,
                        flags);
-  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, h->esc_cnt, 8);
-  for (int b = 0; b < 6; ++b) {
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, h->esc_cnt, BUCKET_SLOTS);
+  for (int b = 0; b < LS_BUCKETS; ++b) {
     const int cnt = h->bucket_count[b];
     if (cnt == 0) continue;
     const int32_t* cols = h->identity_order ? nullptr : h->bucket_cols + h->bucket_off[b];
@@ -648,24 +821,26 @@ int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_
                        h->esc_list + off, h->esc_cnt + b);
   }
   PMOR_HIP(hipGetLastError());
-  int hc[8] = {0};
-  PMOR_HIP(hipMemcpyAsync(hc, h->esc_cnt, sizeof(int) * 8, hipMemcpyDeviceToHost, st));
+  int hc[BUCKET_SLOTS] = {0};
+  PMOR_HIP(hipMemcpyAsync(hc, h->esc_cnt, sizeof(int) * BUCKET_SLOTS, hipMemcpyDeviceToHost, st));
   PMOR_HIP(hipStreamSynchronize(st));
   int64_t tot = 0;
   LsArgs a{};
   a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval_l; a.rhs_aval = h->aval1;
   a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
   a.Pslot = h->Pslot; a.out = qout; a.rho = h->rho; a.bad_col = dbad;
-  for (int b = 0; b < 6; ++b) {
+  a.Acolptr = pb->colptr; a.Arowidx = pb->rowidx; a.Acscslot = pb->cscslot;
+  for (int b = 0; b < LS_BUCKETS; ++b) {
     if (hc[b] == 0) continue;
     tot += hc[b];
     a.ncols = hc[b];
     a.cols = h->esc_list + (h->identity_order ? 0 : h->bucket_off[b]);
     a.col_off = 0;
-    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0));
+    const int mj = h->bucket_maxJ[b], mi = h->bucket_maxI[b];
+    if (h->opts.precision == PMOR_F32) PMOR_TRY(launch_bucket<float>(b, a, mj, mi, st, pb->ctx, -1, 0));
     else if (h->opts.precision == PMOR_F16S)
-      PMOR_TRY((launch_bucket<float, true>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0)));
-    else PMOR_TRY(launch_bucket<double>(b, a, h->maxJ, h->maxI, st, pb->ctx, -1, 0));
+      PMOR_TRY((launch_bucket<float, true>(b, a, mj, mi, st, pb->ctx, -1, 0)));
+    else PMOR_TRY(launch_bucket<double>(b, a, mj, mi, st, pb->ctx, -1, 0));
   }
   if (n_esc) *n_esc = tot;
   if (bad_col || fro2) {
