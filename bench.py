@@ -95,11 +95,46 @@ def timed(fn, steps):
     return time.perf_counter() - t0, n
 
 
-def cpu_baseline(job, gpu_P):
-    """The oracle on a bounded sample of the job (about 10-20 s of CPU work),
-    scaled to solves/s: the full pattern setup, SPAI of a strided 1/8 of the
-    columns (extrapolated), and the U-diag update and block GMRES(30) solve at
-    the first, middle and last point (averaged over the job's points)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_spai_cols(args):
+    """Pool worker: the oracle's SPAI columns `cols` of the C1 job (fresh process)."""
+    cols, = args
+    from synth import config1
+    from oracle.assemble import Assembled
+    from oracle.spai import SpaiPattern, spai_build
+    job = config1()
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col)
+    v1 = asm.values(job.s, job.p_list[0])
+    t = time.perf_counter()
+    pv, _ = spai_build(job.n, asm.rowptr, asm.col, v1, pat, columns=cols)
+    idx = np.concatenate([pat.P_slot[pat.J_colptr[j]:pat.J_colptr[j + 1]] for j in cols])
+    return idx, pv[idx], time.perf_counter() - t
+
+
+def cpu_baseline(job, kept=None):
+    """The oracle on the C1 job, two ways, on the machine's host cores:
+    (i)  one process, NumPy/SciPy with BLAS threads = the cores: the pattern
+         setup, the SPAI of a strided 1/8 of the columns (scaled to all), and the
+         U-diag update and block GMRES(30) solve at the first, middle and last
+         point (mean over the job's points);
+    (ii) the SPAI columns split over a pool of one process per core (all
+         columns, measured), then the same update and solves, with the oracle's
+         own P_1 from the pool (run (i) uses it too).
+    kept: {precision: {point: X}} from the GPU runs; each is compared with the
+    oracle's FP64 solution at that point (block GMRES(30) to 1e-12 with the
+    oracle's P_1)."""
+    import multiprocessing as mp
     try:
         from threadpoolctl import threadpool_info
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -110,22 +145,39 @@ def cpu_baseline(job, gpu_P):
     from oracle.update import diag_factors, update_diag
     from oracle.sparse import to_scipy
     from oracle.gmres import block_gmres
+    ncores = min(16, os.cpu_count() or 1)
     t = time.perf_counter()
     asm = Assembled(job)
     pat = SpaiPattern(job.n, asm.rowptr, asm.col)
     t_setup = time.perf_counter() - t
     v1 = asm.values(job.s, job.p_list[0])
+    # (ii) the full SPAI over a pool of processes
+    _note("cpu baseline: SPAI columns over a process pool")
+    chunks = [np.arange(c, job.n, ncores) for c in range(ncores)]
+    P1 = np.zeros(pat.J_row.size)
+    pool = mp.get_context("spawn").Pool(ncores)
+    try:
+        t = time.perf_counter()
+        for idx, vals, _ in pool.imap_unordered(_oracle_spai_cols, [(c,) for c in chunks]):
+            P1[idx] = vals
+        t_build_pool = time.perf_counter() - t
+    finally:
+        pool.close()
+        pool.join()
+    # (i) one process: a strided eighth of the columns, scaled
+    _note("cpu baseline: SPAI sample in one process")
     cols = np.arange(0, job.n, 8)
     t = time.perf_counter()
     spai_build(job.n, asm.rowptr, asm.col, v1, pat, columns=cols)
-    t_build = (time.perf_counter() - t) * job.n / len(cols)
+    t_build_one = (time.perf_counter() - t) * job.n / len(cols)
     npts = len(job.p_list)
     t_upd, t_solve, steps = [], [], []
     for l in (0, npts // 2, npts - 1):
+        _note(f"cpu baseline: point {l}")
         vl = asm.values(job.s, job.p_list[l])
         t = time.perf_counter()
         q = diag_factors(job.n, asm.rowptr, asm.col, v1, vl)
-        Pl = update_diag(job.n, pat.P_rowptr, gpu_P, q)
+        Pl = update_diag(job.n, pat.P_rowptr, P1, q)
         t_upd.append(time.perf_counter() - t)
         A = to_scipy(job.n, asm.rowptr, asm.col, vl)
         P = to_scipy(job.n, pat.P_rowptr, pat.P_col, Pl)
@@ -133,13 +185,108 @@ def cpu_baseline(job, gpu_P):
         _, info = block_gmres(A.__matmul__, P.__matmul__, job.B, m=30, tol=1e-8)
         t_solve.append(time.perf_counter() - t)
         steps.append(sum(info.steps))
-    t_job = t_setup + t_build + (npts - 1) * float(np.mean(t_upd)) + npts * float(np.mean(t_solve))
-    return {"value": npts / t_job, "unit": "solves/s", "cores": blas_threads or os.cpu_count(), "kind": "oracle",
-            "sample": (f"one {job.name} job scaled from: full pattern setup {t_setup:.2f}s, SPAI of {len(cols)} of "
-                       f"{job.n} columns ({t_build:.1f}s extrapolated), U-diag update {np.mean(t_upd):.2f}s and block "
-                       f"GMRES(30) solve {np.mean(t_solve):.2f}s (mean of points 0, {npts // 2}, {npts - 1}; steps "
-                       f"{steps}; library-built P_1 as input); {npts} points, update policy"),
-            "host_cpus": os.cpu_count()}
+    vs_oracle = {}
+    if kept:
+        _note("cpu baseline: FP64 oracle solutions for the precision comparison")
+        pts = sorted(next(iter(kept.values())).keys())
+        for l in pts:
+            vl = asm.values(job.s, job.p_list[l])
+            q = diag_factors(job.n, asm.rowptr, asm.col, v1, vl)
+            A = to_scipy(job.n, asm.rowptr, asm.col, vl)
+            P = to_scipy(job.n, pat.P_rowptr, pat.P_col, update_diag(job.n, pat.P_rowptr, P1, q))
+            Xo, _ = block_gmres(A.__matmul__, P.__matmul__, job.B, m=30, tol=1e-12, max_cycles=40)
+            for prec, xs in kept.items():
+                d = float(np.linalg.norm(xs[l] - Xo) / np.linalg.norm(Xo))
+                vs_oracle.setdefault(prec, {})[str(l)] = d
+    per_points = (npts - 1) * float(np.mean(t_upd)) + npts * float(np.mean(t_solve))
+    job_one = t_setup + t_build_one + per_points
+    job_pool = t_setup + t_build_pool + per_points
+    return {"value": npts / job_pool, "unit": "solves/s", "cores": ncores, "kind": "oracle",
+            "sample": (f"one {job.name} job: pattern setup {t_setup:.2f}s; SPAI of all {job.n} columns over a "
+                       f"pool of {ncores} processes {t_build_pool:.1f}s (measured); U-diag update "
+                       f"{np.mean(t_upd):.2f}s and block GMRES(30) solve {np.mean(t_solve):.2f}s with the oracle's "
+                       f"own P_1 (mean of points 0, {npts // 2}, {npts - 1}, steps {steps}, scaled to {npts} "
+                       f"points); update policy"),
+            "single_process": {"value": npts / job_one, "unit": "solves/s", "blas_threads": blas_threads,
+                               "spai_s": t_build_one,
+                               "sample": f"SPAI of {len(cols)} of {job.n} columns in one process, scaled"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "precision_rel_err_vs_oracle_f64": vs_oracle}
+
+
+def _scrub(dev, gib=1):
+    """Write a 1 GiB buffer so that no operand of the next call sits in L2 or the memory-side cache."""
+    import torch
+    buf = torch.empty((gib << 27,), dtype=torch.float64, device=dev)
+    buf.fill_(1.0)
+    torch.cuda.synchronize()
+    del buf
+
+
+def spmm_rooflines(ctx, L, sizes=((64, 64, 64, 20), (128, 128, 64, 20), (128, 128, 256, 4))):
+    """The engine's SpMM with A and with the preconditioner inside the sequence
+    solve (U-diag update, all points together), after a 1 GiB scrub, at C1, C4's
+    largest class and a 128 x 128 x 256 stand-in: GB/s in distinct bytes (A's
+    pattern and P_1 once per launch), from the library's HIP-event timer."""
+    import torch
+    from synth import config1
+    from paper_1809_06574_amd import Problem
+    out = {}
+    for nx, ny, nz, npts in sizes:
+        _note(f"spmm rooflines: {nx}x{ny}x{nz}, {npts} points")
+        job = config1(dims=(nx, ny, nz), npts=npts, k=4, seed=1001)
+        dev = ctx.device
+        terms = {r: (torch.as_tensor(T.rowptr, device=dev), torch.as_tensor(T.col, device=dev),
+                     torch.as_tensor(T.val, device=dev)) for r, T in job.terms.items()}
+        B = torch.as_tensor(job.B, device=dev)
+        X = torch.empty((npts,) + tuple(B.shape), dtype=torch.float64, device=dev)
+        pb = Problem(ctx, terms)
+        pb.sequence_solve(B, [job.s] * npts, job.p_list, X=X)  # untimed: buffers, tuning
+        rec = {"n": job.n, "nnz": pb.nnz, "points": npts}
+        for name in ("spmm_a", "spmm_p"):
+            _scrub(dev)
+            L.check(L.pmor_prof_set(ctx.handle, L.PROF_KERNELS[name]), "prof_set")
+            pb.sequence_solve(B, [job.s] * npts, job.p_list, X=X)
+            n_, ms_, by_ = _prof_read(L, ctx)
+            L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+            rec[name] = {"launches": n_, "avg_us": 1e3 * ms_ / max(n_, 1), "GBps": by_ / max(ms_ * 1e-3, 1e-12) / 1e9,
+                         "bytes_per_launch": by_ / max(n_, 1)}
+            rec[name]["frac"] = rec[name]["GBps"] / HBM_PEAK_GBS
+        pb.close()
+        del terms, B, X
+        torch.cuda.synchronize()
+        out[f"{nx}x{ny}x{nz}"] = rec
+    return out
+
+
+def spai_rooflines(ctx, L, factory, job):
+    """The SPAI of the C1 job after a 1 GiB scrub: the gather-only variant
+    (pmor_spai_gather) against HBM (algorithmic bytes: A once, the index sets, the
+    sums), and the FP64 least squares in GFLOP/s (2 |J|^2 (|I| - |J|/3) per column)."""
+    import torch
+    pb = factory()
+    h = pb.spai_build(job.s, job.p_list[0])
+    h.gather_sums()  # untimed
+    _scrub(ctx.device)
+    L.check(L.pmor_prof_set(ctx.handle, L.PROF_SPAI_GATHER), "prof_set")
+    h.gather_sums()
+    n_, ms_, by_ = _prof_read(L, ctx)
+    gather = {"launches": n_, "ms": ms_, "GBps": by_ / max(ms_ * 1e-3, 1e-12) / 1e9, "bytes": by_}
+    gather["frac"] = gather["GBps"] / HBM_PEAK_GBS
+    _scrub(ctx.device)
+    L.check(L.pmor_prof_set(ctx.handle, L.PROF_KERNELS["spai_ls"]), "prof_set")
+    h.rebuild(job.s, job.p_list[0])
+    n2, ms2, by2 = _prof_read(L, ctx)
+    L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+    jc, _, ic, _ = h.export_sets()
+    nj = torch.diff(jc.to(torch.float64))
+    ni = torch.diff(ic.to(torch.float64))
+    flops = float(torch.sum(2.0 * nj * nj * (ni - nj / 3.0)))
+    h.close()
+    pb.close()
+    return {"gather_only": gather,
+            "least_squares_f64": {"ms": ms2, "gflop": flops / 1e9, "GFLOPs": flops / max(ms2 * 1e-3, 1e-12) / 1e9,
+                                  "GBps": by2 / max(ms2 * 1e-3, 1e-12) / 1e9}}
 
 
 def main():
@@ -154,6 +301,7 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
     ap.add_argument("--c2-systems", type=int, default=512, help="systems of the batch run (0: none)")
     ap.add_argument("--no-precisions", action="store_true", help="skip the least-squares precision runs")
+    ap.add_argument("--no-rooflines", action="store_true", help="skip the SpMM / gather / least-squares rooflines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
@@ -287,9 +435,11 @@ def main():
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
 
+    kept = {}
     if not args.no_precisions:
         _note("least-squares precisions")
-        out["precisions"] = c3_bench(factory, job, B)
+        npts = len(job.p_list)
+        out["precisions"] = c3_bench(factory, job, B, keep_points=(0, npts // 2, npts - 1), kept=kept)
 
     if args.c2_systems > 0:
         out["batch_systems"] = c2_bench(ctx, args.c2_systems)
@@ -299,13 +449,16 @@ def main():
         rhos = [float(x) for x in args.serve_rho.split(",")]
         out["serving"] = serve_bench(ctx, rhos, args.serve_jobs)
 
+    if not args.no_rooflines:
+        _note("spai and spmm rooflines")
+        out["spai_rooflines"] = spai_rooflines(ctx, L, factory, job)
+        out["spmm_rooflines"] = spmm_rooflines(ctx, L)
+
     if not args.no_cpu_baseline:
         _note("cpu baseline")
-        pb = factory()
-        h = pb.spai_build(job.s, job.p_list[0])
-        P1 = h.export()["val"].cpu().numpy()
-        h.close(); pb.close()
-        out["cpu_baseline"] = cpu_baseline(job, P1)
+        out["cpu_baseline"] = cpu_baseline(job, kept)
+        for prec, errs in out["cpu_baseline"].pop("precision_rel_err_vs_oracle_f64").items():
+            out["precisions"][prec]["rel_err_vs_oracle_f64"] = errs
     try:
         with open(tune_file) as f:
             out["tuning"] = json.load(f)
@@ -409,11 +562,12 @@ def _c2_system(i):
     return config2_system(i)
 
 
-def c3_bench(factory, job, B):
+def c3_bench(factory, job, B, keep_points=None, kept=None):
     """The C1 job with the SPAI least squares in FP64, FP32 and FP16s (update
     policy, points solved together): throughput, the P_1 build time and its
     residual ||I - A P_1||_F, block steps per point, and how far each X lies
-    from the FP64 run's."""
+    from the FP64 run's.  kept[prec] receives X at keep_points (host) for the
+    comparison with the oracle's FP64 solution."""
     import torch
     npts = len(job.p_list)
     out, ref = {}, None
@@ -431,6 +585,8 @@ def c3_bench(factory, job, B):
         dt = time.perf_counter() - t
         if ref is None:
             ref = X.clone()
+        if kept is not None:
+            kept[prec] = {l: X[l].cpu().numpy() for l in keep_points}
         dx = max(float(torch.linalg.norm(X[l] - ref[l]) / torch.linalg.norm(ref[l])) for l in range(npts))
         out[prec] = {"solves_per_s": npts / dt, "p1_build_ms": st[0]["t_precond_ms"],
                      "fro_I_minus_AP1": st[0]["fro_resid"],
@@ -485,6 +641,16 @@ def c2_bench(ctx, nsys, precision="f32"):
         hs.append(h)
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t
+    # the least-squares kernels' own time: every P_1 built again under the
+    # library's kernel timer (then the update again)
+    from paper_1809_06574_amd import lib as L
+    L.check(L.pmor_prof_set(ctx.handle, L.PROF_KERNELS["spai_ls"]), "prof_set")
+    for job, h in zip(jobs, hs):
+        h.rebuild(job.s, job.p_list[0])
+    _, ls_ms, _ = _prof_read(L, ctx)
+    L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+    for job, h in zip(jobs, hs):
+        h.update(job.s, job.p_list[1])
     items = [(pb, h, job.s, job.p_list[1], B) for pb, h, job, B in zip(pbs, hs, jobs, Bs)]
     batch_solve(ctx, items)  # warm the engine buffers
     torch.cuda.synchronize()
@@ -511,7 +677,8 @@ def c2_bench(ctx, nsys, precision="f32"):
            "setup_pattern_spai_update_s": t_prep,
            "batched_solves_per_s": nsys / t_batch, "pointwise_solves_per_s": nsys / t_point,
            "batched_solves_per_s_with_setup": nsys / (t_batch + t_prep),
-           "setup_ls_gflop": ls_flops / 1e9,
+           "setup_ls_gflop": ls_flops / 1e9, "setup_ls_kernel_ms": ls_ms,
+           "setup_ls_gflops": ls_flops / max(ls_ms * 1e-3, 1e-12) / 1e9,
            "batched_vs_pointwise": t_point / t_batch}
     for h in hs:
         h.close()

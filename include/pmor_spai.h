@@ -439,6 +439,12 @@ int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2,
  * (device, nnz) on pb's pattern; X, Y: n x k row-major, ld >= k. */
 int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx,
               double* Y, int64_t ldy, int32_t k, double alpha, double beta);
+/* The gather of the SPAI least squares on its own (Section 2.2: the dense block
+ * A(I_j, J_j) of every column j, here of the handle's anchor A(1)), read exactly
+ * as the FP64 least-squares kernels read it, with each block reduced to the sum
+ * of its entries in colsum[j] (device, n).  A data-movement variant of the build
+ * for timing (PMOR_PROF_SPAI_GATHER) and parity. */
+int pmor_spai_gather(const pmor_spai* h, double* colsum);
 
 /* ---- kernel timing (benchmarks) ---------------------------------------- */
 /* Time every launch of one kernel class with HIP events recorded on the
@@ -448,12 +454,16 @@ int pmor_spmm(pmor_problem* pb, const double* aval, const double* X, int64_t ldx
  * counted.  pmor_prof_read synchronises the stream, returns the totals since the
  * last read and resets them. */
 /* Per system of a launch (n rows, kp block width, nblk V blocks swept): */
+/* An array that several systems of one launch share (A's pattern for the points
+ * of one problem, P's pattern and P_1's values for the points of one sequence)
+ * counts once, split evenly among those systems. */
 #define PMOR_PROF_SPMM_A 1        /* W = A Z in a block step: 12 nnz + 4(n+1) + 16 n kp */
 #define PMOR_PROF_CGS_UPD_DOT 2   /* pass 2: W -= V H1; V^T W, W^T W: 8 n kp (nblk + 2) */
 #define PMOR_PROF_CGS_DOT 3       /* pass 1: V^T W, column norms: 8 n kp (nblk + 1) */
 #define PMOR_PROF_SPAI_LS 4       /* SPAI least squares: 12 nnz + 4 n + 4 (sum|I_j| + nnzP) + 8 nnzP + 8 n */
 #define PMOR_PROF_SPMM_P 5        /* Z = P V_j, V_j = W1 R2^-1 written: 12 nnzP + 4(n+1) + 24 n kp */
 #define PMOR_PROF_CGS_UPD_GRAM 6  /* pass 3: W -= V H2; W R1^-1; Gram: 8 n kp (nblk + 2) */
+#define PMOR_PROF_SPAI_GATHER 7   /* gather only (pmor_spai_gather): 12 nnz + 4 n + 4 (sum|I_j| + nnzP) + 8 n */
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id);
 int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
 

@@ -317,6 +317,12 @@ class Spai:
                               rho.data_ptr()), "spai_export")
         return {"rowptr": rp, "col": ci, "val": va, "q": qv, "rho": rho}
 
+    def gather_sums(self):
+        """pmor_spai_gather: the sum of every column's gathered block A(I_j, J_j) (anchor values)."""
+        out = torch.empty(self.pb.n, dtype=torch.float64, device=self.pb.ctx.device)
+        L.check(L.pmor_spai_gather(self.handle, out.data_ptr()), "pmor_spai_gather")
+        return out
+
     def export_sets(self):
         dev = self.pb.ctx.device
         n = self.pb.n

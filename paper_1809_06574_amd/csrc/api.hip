@@ -1740,9 +1740,15 @@ int pmor_table2_norms_noalloc(pmor_problem* pb, double s1, double p1, double s2,
   return PMOR_OK;
 }
 
+int pmor_spai_gather(const pmor_spai* h, double* colsum) {
+  if (!h || !colsum) return fail(PMOR_EINVAL, "NULL argument");
+  PMOR_HIP(hipSetDevice(h->pb->ctx->device));
+  return run_spai_gather(const_cast<pmor_spai*>(h), colsum);
+}
+
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id) {
   if (!ctx) return fail(PMOR_EINVAL, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > PMOR_PROF_CGS_UPD_GRAM) return fail(PMOR_EINVAL, "unknown kernel id");
+  if (kernel_id < 0 || kernel_id > PMOR_PROF_SPAI_GATHER) return fail(PMOR_EINVAL, "unknown kernel id");
   prof_collect(ctx);
   ctx->prof.kernel = kernel_id;
   ctx->prof.launches = 0;

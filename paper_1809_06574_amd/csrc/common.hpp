@@ -301,6 +301,8 @@ int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
+// every column's gathered block A(I_j, J_j) (anchor values) reduced to its sum in colsum (n, device)
+int run_spai_gather(pmor_spai* h, double* colsum);
 // adaptive Q (PMOR_UPD_ADAPTIVE): Q in P's CSR order into qout, residuals into h->rho;
 // *n_esc (may be NULL) = escalated columns
 int run_update_adaptive(pmor_spai* h, const double* aval_l, double* qout, int32_t* bad_col, double* fro2,

@@ -2560,6 +2560,18 @@ class RunnerT final : public Runner {
       prof_stop_seg(ctx, pr, tag, e0);
     };
     auto blkb = [&](int i) { return 8.0 * (double)item_[i]->n * KP; };
+    // distinct bytes: an array shared by several systems of the launch (the
+    // pattern of A for the points of one problem, P_1 for the points of one
+    // sequence) is counted once, split evenly among the systems that share it
+    std::map<const void*, int> share;
+    for (int i : act_) {
+      ++share[item_[i]->acol];
+      if (item_[i]->pkind != 0) {
+        ++share[item_[i]->pcol];
+        ++share[item_[i]->pval];
+      }
+    }
+    auto once = [&](const void* p, double bytes) { return bytes / std::max(1, share[p]); };
     // initial block QR of R_0: V_0 S = R_0 (S -> G)
     hipLaunchKernelGGL(k_init_cycle, dim3(nact), dim3(256), 0, s, a, KP);
     a.mode = 1; a.nbl = 0; a.zero_init = 0; a.ignore_done = 0; a.W = E.W.p;
@@ -2587,16 +2599,22 @@ class RunnerT final : public Runner {
         launch_spmm_seg<KP, false>(ctx, pr, 2, gS, lprP, s, sq);
       }
       prof_seg(pr, jj, [&](int i) {
-        const double mat = 12.0 * item_[i]->nnzP + 4.0 * (item_[i]->n + 1);
-        if (item_[i]->pkind == 0) return 3.0 * blkb(i);
-        if (item_[i]->pkind == 1) return mat + 3.0 * blkb(i);
-        if (item_[i]->pkind == 3) return mat + 8.0 * item_[i]->n + 3.0 * blkb(i);
-        return 2.0 * mat + 5.0 * blkb(i);
+        const SolveItem* x = item_[i];
+        // P_1's values and P's pattern (columns, row pointers) may be shared
+        const double pat = once(x->pcol, 4.0 * x->nnzP + 4.0 * (x->n + 1));
+        const double p1 = once(x->pval, 8.0 * x->nnzP);
+        if (x->pkind == 0) return 3.0 * blkb(i);
+        if (x->pkind == 1) return pat + p1 + 3.0 * blkb(i);
+        if (x->pkind == 3) return pat + p1 + 8.0 * x->n + 3.0 * blkb(i);
+        return pat + p1 + 8.0 * x->nnzP + 5.0 * blkb(i);  // Q_l's own values on P's pattern
       });
       SpArgs sa{E.seg_d, stab_d, E.st, 0, 1, E.Z.p, E.W.p, nullptr, nullptr, 1.0, 0.0, nullptr, 1};
       pr = prof_start(ctx, PMOR_PROF_SPMM_A);
       launch_spmm_seg<KP, false>(ctx, pr, 3, gS, lprA, s, sa);
-      prof_seg(pr, jj, [&](int i) { return 12.0 * item_[i]->nnzA + 4.0 * (item_[i]->n + 1) + 2.0 * blkb(i); });
+      prof_seg(pr, jj, [&](int i) {
+        const SolveItem* x = item_[i];
+        return once(x->acol, 4.0 * x->nnzA + 4.0 * (x->n + 1)) + 8.0 * x->nnzA + 2.0 * blkb(i);
+      });
       a.nbl = jj + 1;
       const int L1 = (jj + 1) * KP * KP + KP, L2 = (jj + 1) * KP * KP + KP * KP;
       pr = prof_start(ctx, PMOR_PROF_CGS_DOT);

@@ -180,7 +180,7 @@ __device__ __forceinline__ Q16Scale q16_scale(float mx) {
 }
 __device__ __forceinline__ float q16(float x, Q16Scale q) { return __half2float(__float2half_rn(x * q.sc)) * q.isc; }
 
-template <typename T, int JMAX, int R, bool Q16 = false, int G = 16>
+template <typename T, int JMAX, int R, bool Q16 = false, int G = 16, bool GO = false>
 __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
   static_assert(G == 16 || G == 32 || G == 64, "groups of one, two or four DPP rows");
   static_assert(JMAX <= G, "row k of R must sit in lane k of the group");
@@ -252,6 +252,16 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
         }
       }
     }
+  }
+  if constexpr (GO) {  // gather only: the block's sum into rho[j]
+    T acc = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < JMAX; ++t) acc += A_[r][t];
+    acc = grp_sum<G>(acc);
+    if (gl == 0) a.rho[j] = (double)acc;
+    return;
   }
   if constexpr (Q16) {
 #pragma unroll
@@ -413,7 +423,7 @@ __device__ __forceinline__ int lds_lower_bound(const int* rows, int len, int r) 
   return lo;
 }
 
-template <typename T, bool Q16 = false>
+template <typename T, bool Q16 = false, bool GO = false>
 __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   extern __shared__ unsigned char smem_raw[];
   T* S = reinterpret_cast<T*>(smem_raw);  // column-major [nj + 1][ldI]: A_hat then rhs (JM >= nj)
@@ -452,6 +462,14 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
     B[lds_lower_bound(Is, ni, j)] = T(1);
   }
   __syncthreads();
+  if constexpr (GO) {  // gather only: the block's sum into rho[j]
+    T acc = T(0);
+    for (int t = 0; t < nj; ++t)
+      for (int li = lane; li < ni; li += 64) acc += S[(size_t)t * ldI + li];
+    acc = wave_sum(acc);
+    if (lane == 0) a.rho[j] = (double)acc;
+    return;
+  }
   if constexpr (Q16) {
     for (int t = 0; t <= nj; ++t) {
       if (t == nj && !a.rhs_aval) break;
@@ -542,7 +560,7 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   }
 }
 
-template <typename T, bool Q16 = false>
+template <typename T, bool Q16 = false, bool GO = false>
 static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pmor_ctx* pc, int pidx, int part) {
   if (a.ncols == 0) return PMOR_OK;
   const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
@@ -552,26 +570,26 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
   // 256 registers for the block, so it takes the LDS kernel
   constexpr bool REG32 = sizeof(T) == 4;
   switch (b) {
-    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16>, dim3(g16), dim3(256), 0, st, a); break;
-    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16>, dim3(g16), dim3(256), 0, st, a); break;
-    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
-    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16>, dim3(g16), dim3(256), 0, st, a); break;
-    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16>, dim3(g16), dim3(256), 0, st, a); break;
+    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
+    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
+    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
+    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
+    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
     case 5:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32>, dim3(g32), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32, GO>, dim3(g32), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
     case 6:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 32, 4, Q16, 32>, dim3(g32), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 4, Q16, 32, GO>, dim3(g32), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
     case 7:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64>, dim3(g64), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64, GO>, dim3(g64), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
@@ -579,8 +597,8 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
       const int ldI = ((maxI + 7) / 8) * 8;
       const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI + sizeof(int) * (size_t)ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
-      PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16>, shm));
-      plaunch(pc, pidx, part, k_spai_lds<T, Q16>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
+      PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16, GO>, shm));
+      plaunch(pc, pidx, part, k_spai_lds<T, Q16, GO>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
       break;
     }
     default: return fail(PMOR_EINVAL, "column outside the supported SPAI pattern sizes");
@@ -717,6 +735,34 @@ int launch_update_diag(pmor_spai* h, const double* aval_l, const double* anchor,
 __global__ void k_copy_vals(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
+}
+
+// Gather only: every column's block A(I_j, J_j) of the anchor values, read as
+// the FP64 least-squares kernels read it, reduced to its sum in colsum[j] (a
+// data-movement variant of the least squares, for timing and parity)
+int run_spai_gather(pmor_spai* h, double* colsum) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  LsArgs a{};
+  a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = h->aval1; a.rhs_aval = nullptr;
+  a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
+  a.Pslot = h->Pslot; a.out = nullptr; a.rho = colsum; a.bad_col = nullptr;
+  a.Acolptr = pb->colptr; a.Arowidx = pb->rowidx; a.Acscslot = pb->cscslot;
+  const int pr = prof_start(pb->ctx, PMOR_PROF_SPAI_GATHER);
+  int first_b = -1, last_b = -1;
+  for (int b = 0; b < LS_BUCKETS; ++b)
+    if (h->bucket_count[b]) { if (first_b < 0) first_b = b; last_b = b; }
+  for (int b = 0; b < LS_BUCKETS; ++b) {
+    if (h->bucket_count[b] == 0) continue;
+    const int part = (b == first_b ? 1 : 0) | (b == last_b ? 2 : 0);
+    a.ncols = h->bucket_count[b];
+    a.cols = h->identity_order ? nullptr : h->bucket_cols + h->bucket_off[b];
+    a.col_off = 0;
+    PMOR_TRY((launch_bucket<double, false, true>(b, a, h->bucket_maxJ[b], h->bucket_maxI[b], st, pb->ctx, pr, part)));
+  }
+  // the algorithmic bytes of a gather: A once, the index sets, the sums written
+  prof_stop(pb->ctx, pr, 12.0 * pb->nnz + 4.0 * pb->n + 4.0 * ((double)h->nI + h->nnzP) + 8.0 * pb->n, 0);
+  return PMOR_OK;
 }
 
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2) {

@@ -31,6 +31,7 @@ PMOR_UPD_DIAG, PMOR_UPD_PATTERN, PMOR_UPD_ADAPTIVE = 0, 1, 2
 PMOR_REBUILD, PMOR_UPDATE = 0, 1
 PMOR_APPROACH_FIRST, PMOR_APPROACH_SECOND = 0, 1
 PROF_KERNELS = {"spmm_a": 1, "cgs_upd_dot": 2, "cgs_dot": 3, "spai_ls": 4, "spmm_p": 5, "cgs_upd_gram": 6}
+PROF_SPAI_GATHER = 7
 
 
 class Csr(C.Structure):
@@ -124,6 +125,7 @@ _SIGS = {
     "pmor_table2_norms_c": (C.c_int, [P, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pmor_table2_norms_noalloc": (C.c_int, [P, D, D, D, D, C.POINTER(D), C.POINTER(D)]),
     "pmor_spmm": (C.c_int, [P, P, P, I64, P, I64, I32, D, D]),
+    "pmor_spai_gather": (C.c_int, [P, P]),
     "pmor_prof_set": (C.c_int, [P, C.c_int]),
     "pmor_prof_read": (C.c_int, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]),
     "pmor_strerror": (C.c_char_p, [C.c_int]),

@@ -405,3 +405,29 @@ def test_empty_and_out_of_range_arguments(ctx):
     assert rc == L.PMOR_OK
     for x in (h, h2, pb, pb2):
         x.close()
+
+
+@pytest.mark.parametrize("which", ["config0", "tiny", "explicit"])
+def test_gather_only_block_sums(ctx, which):
+    """pmor_spai_gather, the data-movement variant of the least squares: every
+    column's block A(I_j, J_j) of the anchor, reduced to its sum, equals the sum of
+    the dense block the oracle's index sets pick out (register and LDS buckets)."""
+    from paper_1809_06574_amd import Problem
+    if which == "config0":
+        job, pattern = config0(), None
+    elif which == "tiny":
+        job, pattern = tiny_random_job(131, 0.03, 3), None
+    else:
+        job = _explicit_pattern_job((9, 8, 7), 9)
+        pattern = job.pattern
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    pat = SpaiPattern(job.n, asm.rowptr, asm.col, explicit=pattern)
+    h = pb.spai_build(job.s, job.p_list[0], pattern=pattern)
+    got = np_(h.gather_sums())
+    A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(job.s, job.p_list[0])).toarray()
+    for j in range(job.n):
+        I = pat.I_row[pat.I_colptr[j]:pat.I_colptr[j + 1]]
+        J = pat.J_row[pat.J_colptr[j]:pat.J_colptr[j + 1]]
+        blk = A[np.ix_(I, J)]
+        assert abs(got[j] - blk.sum()) <= 1e-13 * max(np.abs(blk).sum(), 1e-300), j
