@@ -302,6 +302,11 @@ def main():
     ap.add_argument("--c2-systems", type=int, default=512, help="systems of the batch run (0: none)")
     ap.add_argument("--no-precisions", action="store_true", help="skip the least-squares precision runs")
     ap.add_argument("--no-rooflines", action="store_true", help="skip the SpMM / gather / least-squares rooflines")
+    ap.add_argument("--spmm-sizes", default="64x64x64x20,128x128x64x20,128x128x256x4",
+                    help="grids and point counts of the SpMM rooflines (nx x ny x nz x points, comma-separated; "
+                         "'none' to skip)")
+    ap.add_argument("--read-calibration", action="store_true",
+                    help="also run a plain 1 GiB device read (sum), the read-only reference of the byte counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
@@ -341,6 +346,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.read_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            float(src.sum())
+        del src
 
     # warmup (also builds every lazily created buffer)
     _note("warmup")
@@ -452,7 +462,9 @@ def main():
     if not args.no_rooflines:
         _note("spai and spmm rooflines")
         out["spai_rooflines"] = spai_rooflines(ctx, L, factory, job)
-        out["spmm_rooflines"] = spmm_rooflines(ctx, L)
+        if args.spmm_sizes != "none":
+            sizes = [tuple(int(v) for v in t.split("x")) for t in args.spmm_sizes.split(",")]
+            out["spmm_rooflines"] = spmm_rooflines(ctx, L, sizes)
 
     if not args.no_cpu_baseline:
         _note("cpu baseline")
