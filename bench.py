@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--roofline-kernel", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-arms", action="store_true", help="time only the update policy")
-    ap.add_argument("--serve-jobs", type=int, default=40, help="jobs per serving run (0: no serving run)")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs per serving run (0: no serving run)")
     ap.add_argument("--c2-systems", type=int, default=512, help="systems of the batch run (0: none)")
     ap.add_argument("--no-precisions", action="store_true", help="skip the least-squares precision runs")
     ap.add_argument("--no-rooflines", action="store_true", help="skip the SpMM / gather / least-squares rooflines")
@@ -309,7 +309,7 @@ def main():
                     help="also run a plain 1 GiB device read (sum), the read-only reference of the byte counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
-    ap.add_argument("--serve-rho", default="0.8", help="comma-separated loads rho of the serving runs")
+    ap.add_argument("--serve-rho", default="0.5,0.8,0.95", help="comma-separated loads rho of the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
@@ -550,7 +550,7 @@ def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, se
         arr = np.cumsum(rng.exponential(1.0 / lam, size=n_jobs))
         arr -= arr[0]
         jids = list(range(n_jobs))
-        keep = tuple(range(0, n_jobs, max(1, n_jobs // alone)))[:alone] if rho == rhos[-1] else ()
+        keep = tuple(range(0, n_jobs, max(1, n_jobs // alone)))[:alone]
         mk, fin, slat, kept = run(jids, list(arr), keep)
         jl = [v[0] for v in fin.values()]
         ok = all(v[1] == 0 for v in fin.values())
