@@ -19,6 +19,11 @@ here.  Steps, in order:
 
 Zero columns of B have the solution 0 and are left out of the block.
 
+Complex systems (the expansion points of Section 3 are complex) take the same
+steps in complex arithmetic: the Gram-Schmidt coefficients are V^H W, and the
+QR factors carry a real positive diagonal (each column's unit-modulus phase
+moved from R into Q).  For real data every step is the real one.
+
 Dependent columns (the paper is silent; Section 2.1 only assumes the block
 Krylov space has full dimension).  For a block Y with thin QR Y = Q S, the
 ratio |S_cc| / ||y_c|| is the sine of the angle between column c and the span
@@ -59,10 +64,13 @@ class GmresInfo:
 
 
 def qr_positive(W):
-    """Thin QR with nonnegative diagonal in R (library Householder QR + sign fix)."""
+    """Thin QR with a real nonnegative diagonal in R (library Householder QR, then
+    each column's phase, a sign for real data, moved from R into Q)."""
     Q, R = np.linalg.qr(W, mode="reduced")
-    d = np.where(np.diag(R) < 0.0, -1.0, 1.0)
-    return Q * d[None, :], R * d[:, None]
+    r = np.diag(R)
+    mag = np.abs(r)
+    d = np.where(mag > 0.0, r / np.where(mag > 0.0, mag, 1.0), 1.0)
+    return Q * d[None, :], R * np.conj(d)[:, None]
 
 
 def column_sines(Y, R):
@@ -82,7 +90,8 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
     Returns (X, GmresInfo).
     """
     n, k_all = B.shape
-    X_all = np.zeros((n, k_all))
+    dt = np.result_type(B.dtype, np.float64)
+    X_all = np.zeros((n, k_all), dtype=dt)
     bnorm_all = np.linalg.norm(B, axis=0)
     active = np.nonzero(bnorm_all > 0.0)[0]
     info = GmresInfo(False, False, [], [], np.zeros(k_all), [])
@@ -92,7 +101,7 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
     Bc = B[:, active]
     bnorm = bnorm_all[active]
     k = active.size
-    X = np.zeros((n, k))
+    X = np.zeros((n, k), dtype=dt)
     ncycles = max_cycles if fixed_steps is None else len(fixed_steps)
     for cycle in range(ncycles + 1):
         R = Bc - A_apply(X)
@@ -110,8 +119,8 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
             info.steps.append(0)
             break
         V = [V1]
-        Hbar = np.zeros(((m + 1) * k, m * k))
-        G = np.zeros(((m + 1) * k, k))
+        Hbar = np.zeros(((m + 1) * k, m * k), dtype=dt)
+        G = np.zeros(((m + 1) * k, k), dtype=dt)
         G[:k, :] = S
         nsteps = m if fixed_steps is None else fixed_steps[cycle]
         Y = None
@@ -122,15 +131,15 @@ def block_gmres(A_apply: Callable, P_apply: Callable, B: np.ndarray, m: int = 30
             wscale = np.linalg.norm(W, axis=0).max()
             Vcat = np.hstack(V)
             for _ in range(2):
-                Hp = Vcat.T @ W
+                Hp = Vcat.conj().T @ W
                 W = W - Vcat @ Hp
                 Hbar[: (j + 1) * k, j * k:(j + 1) * k] += Hp
             Vn, Hd = qr_positive(W)
             deficient = (np.abs(np.diag(Hd)).min() <= STEP_DEF * wscale
                          or not np.all(column_sines(W, Hd) > DEP_SINE))
             if deficient:
-                Hd = np.zeros((k, k))
-                Vn = np.zeros((n, k))
+                Hd = np.zeros((k, k), dtype=dt)
+                Vn = np.zeros((n, k), dtype=dt)
             Hbar[(j + 1) * k:(j + 2) * k, j * k:(j + 1) * k] = Hd
             V.append(Vn)
             Hj = Hbar[: (j + 2) * k, : (j + 1) * k]

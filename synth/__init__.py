@@ -18,4 +18,5 @@ from .gen import (  # noqa: F401
     tiny_random_job,
     gyro_like_job,
     gyro_coefs,
+    gyro_complex_job,
 )

@@ -66,6 +66,7 @@ class Job:
     meta: dict = dataclasses.field(default_factory=dict)
     aterms: Optional[List[CSR]] = None  # affine job: the term matrices T_0..T_{w}
     coefs: Optional[np.ndarray] = None  # affine job: npts x len(aterms) coefficient vectors
+    kinds: Optional[List[str]] = None  # complex job: "real", "imag" or "complex" per term
 
     @property
     def k(self) -> int:
@@ -386,3 +387,27 @@ def gyro_like_job(dims=(12, 10, 8), k: int = 2, seed: int = 1010, points=GYRO_PO
                meta={"dims": dims, "points": tuple(points),
                      "matrices": {"K1": K1, "M1": M1, "M2": M2, "D1": D1, "D2": D2, "K2": K2, "K3": K3}},
                aterms=[K1, M1, M2, D1, D2, K2, K3], coefs=coefs)
+
+
+# (f^2, theta, d) of the complex points: s = 2 pi f sqrt(-1), so s^2 = -4 pi^2 f^2
+GYRO_COMPLEX_POINTS = ((0.0225, 0.5, 1.0), (0.0225, 0.5, 2.0), (0.02, 0.3, 2.0), (0.015, 0.3, 1.5))
+GYRO_KINDS = ("real", "real", "real", "imag", "imag", "real", "real")
+
+
+def gyro_complex_job(dims=(12, 10, 8), k: int = 2, seed: int = 1010, points=GYRO_COMPLEX_POINTS,
+                     rhs_seed: int = 2020) -> Job:
+    """The terms of ``gyro_like_job`` at complex points, as in the paper's
+    gyroscope example (Section 3): s = 2 pi f sqrt(-1) makes the coefficients of
+    M1, M2 (s^2, s^2 d) real and those of D1, D2 (s theta, s theta d) imaginary;
+    K1, K2, K3 keep 1, 1/d, d.  The frequencies f^2 in ``points`` follow the
+    paper's (0.0225 at two of its four points) and stay below the lowest
+    resonance of the synthetic K, M pair; theta is O(1) here so that the
+    imaginary part matters.  B is complex: standard normal real and imaginary
+    parts, drawn with seed ``rhs_seed`` (real parts first)."""
+    base = gyro_like_job(dims, k=1, seed=seed)
+    coefs = np.array([gyro_coefs(2j * np.pi * np.sqrt(f2), th, d) for f2, th, d in points])
+    rng = np.random.default_rng(rhs_seed)
+    B = rng.standard_normal((base.n, k)) + 1j * rng.standard_normal((base.n, k))
+    return Job("gyro_complex", base.n, {}, float("nan"), np.arange(len(points), dtype=np.float64), B,
+               meta={"dims": dims, "points": tuple(points), "matrices": base.meta["matrices"]},
+               aterms=base.aterms, coefs=coefs, kinds=list(GYRO_KINDS))
