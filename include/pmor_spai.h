@@ -59,7 +59,7 @@ extern "C" {
 
 #define PMOR_KMAX 16      /* largest block of right-hand sides                 */
 #define PMOR_NROLES 6     /* number of term roles                              */
-#define PMOR_TMAX 8       /* most terms of an affine problem                   */
+#define PMOR_TMAX 16      /* most (real) terms of an affine problem            */
 #define PMOR_MAX_CYCLES 64
 
 /* Term roles: A(s,p) = s^2 (M0 + p M1) + s (D0 + p D1) + (K0 + p K1). */
@@ -189,6 +189,43 @@ int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_proble
  * calls accept its points too, as PMOR_NROLES coefficients in role order
  * (those of absent roles are ignored). */
 int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, pmor_problem** out);
+
+/* Complex coefficients (the paper's expansion points are complex, Section 3:
+ * s = 2 pi f sqrt(-1) makes s theta and s theta d imaginary).  A complex system
+ * A x = b with A = sum_t c_t T_t (real T_t, complex c_t) is solved in its
+ * equivalent real form: unknown i becomes the pair (Re x_i, Im x_i) at rows
+ * 2i, 2i+1, and a complex entry alpha + beta sqrt(-1) the 2x2 block
+ * [[alpha, -beta], [beta, alpha]], i.e. A^ = sum_t Re(c_t) (T_t (x) I_2) +
+ * Im(c_t) (T_t (x) J_2), J_2 = [[0, -1], [1, 0]].  The problem made here is that
+ * real affine problem of order 2n (every call of this header applies to it
+ * unchanged: its SPAI is the SPAI of A^, its update and block GMRES those of
+ * A^, so X^ holds the complex solution exactly as A^ X^ = B^ holds A X = B).
+ * kinds[t] says which parts c_t may have: PMOR_COEF_REAL (T_t (x) I_2 only),
+ * PMOR_COEF_IMAG (T_t (x) J_2 only) or PMOR_COEF_COMPLEX (both); at most
+ * PMOR_TMAX real terms in all.  Points are given to the *_c calls as 2 nterms
+ * doubles (Re c_0, Im c_0, Re c_1, ...); a part a term's kind excludes must be
+ * 0 (PMOR_EINVAL otherwise).  B and X are 2n x k real blocks: row 2i the real
+ * parts of row i, row 2i+1 its imaginary parts.  n of the problem (info) is 2n.
+ * Every term's real form stores whole 2x2 blocks (zeros included), the
+ * diagonal blocks among them, so the pattern of A^ is the real form of A's
+ * pattern (union of the terms plus the diagonal) and each SPAI column pair
+ * 2j, 2j+1 solves the complex least squares of column j (Section 2.2).
+ * Updates: PMOR_UPD_DIAG takes the complex factor q_i of Section 2.3, i.e. the
+ * 2x2 block [[Re q_i, -Im q_i], [Im q_i, Re q_i]], and writes P_l = Q P_1 out
+ * (spai_export's qval holds Re q_i, Im q_i at 2i, 2i+1); PMOR_UPD_PATTERN is
+ * the complex U-pattern update as it stands.  The second approach,
+ * PMOR_UPD_ADAPTIVE and re-anchoring return PMOR_EINVAL; an explicit or
+ * imported P must have a real-form pattern (rows 2i, 2i+1 alike, columns in
+ * pairs), else PMOR_EINVAL.  Block GMRES runs on the real blocks as given: with
+ * B^ = [R(B), R(sqrt(-1) B)] (2k columns) it is complex block GMRES on B (the
+ * real span of both is the complex span of B), and X^'s first k columns are
+ * the complex solution.  Frobenius norms reported (stats, Table 2 norms) are
+ * those of the real form, sqrt(2) times the complex ones. */
+#define PMOR_COEF_REAL 0
+#define PMOR_COEF_IMAG 1
+#define PMOR_COEF_COMPLEX 2
+int pmor_problem_create_complex(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms,
+                                const int32_t* kinds, pmor_problem** out);
 void pmor_problem_destroy(pmor_problem* pb);
 /* n and nnz of the union pattern (host outputs). */
 int pmor_problem_info(const pmor_problem* pb, int32_t* n, int32_t* nnz);

@@ -21,10 +21,43 @@ def _dev_f64(x, device):
     return torch.as_tensor(x, dtype=torch.float64).to(device).contiguous()
 
 
-def _coef(c):
+def _flat(c, pb):
+    """One point's coefficients as the doubles the *_c calls read: a complex
+    problem's as (Re, Im) pairs; the count is checked against the problem."""
+    if pb.complex:
+        vals = [float(v) for x in c for v in (complex(x).real, complex(x).imag)]
+    else:
+        vals = [float(x) for x in c]
+    if len(vals) != pb.ncoef:
+        raise ValueError(f"a point of this problem has {pb.ncoef // (2 if pb.complex else 1)} coefficients, "
+                         f"got {len(c)}")
+    return vals
+
+
+def _coef(c, pb):
     """A point given as a coefficient vector: a host double array for the *_c calls."""
-    vals = [float(x) for x in c]
+    vals = _flat(c, pb)
     return (C.c_double * max(len(vals), 1))(*vals)
+
+
+def _coefs(rows, pb):
+    """The points of a sequence, row after row, as one host double array."""
+    vals = [v for row in rows for v in _flat(row, pb)]
+    return (C.c_double * max(len(vals), 1))(*vals)
+
+
+def complex_to_real(Bc: torch.Tensor) -> torch.Tensor:
+    """An n x k complex block as the 2n x k real block of the equivalent real form
+    (row 2i the real parts of row i, row 2i+1 its imaginary parts)."""
+    return torch.view_as_real(Bc.to(torch.complex128)).permute(0, 2, 1).reshape(2 * Bc.shape[0], Bc.shape[1])
+
+
+def real_to_complex(Xr: torch.Tensor) -> torch.Tensor:
+    """Inverse of complex_to_real (the last two dimensions; a leading batch dimension is kept)."""
+    lead = Xr.shape[:-2]
+    n2, k = Xr.shape[-2:]
+    v = Xr.reshape(*lead, n2 // 2, 2, k).transpose(-1, -2).contiguous()
+    return torch.view_as_complex(v)
 
 
 def _is_coef(s, p):
@@ -58,14 +91,20 @@ class Problem:
     """A parametric system: A(s,p) = s^2 M(p) + s D(p) + K(p) (terms by role, a dict),
     or the affine A(c) = sum_t c_t T_t (terms a list; points are coefficient vectors)."""
 
-    def __init__(self, ctx: Context, terms):
+    def __init__(self, ctx: Context, terms, kinds=None):
         """``terms[role] = (rowptr, col, val)`` arrays (host or device) or an object with
         ``rowptr``, ``col``, ``val`` attributes; roles M0, M1, D0, D1, K0, K1.  A list
-        of such terms makes an affine problem (pmor_problem_create_affine)."""
+        of such terms makes an affine problem (pmor_problem_create_affine); with
+        ``kinds`` (one of "real", "imag", "complex" per term) its coefficients are
+        complex and the problem is the equivalent real one of order 2n
+        (pmor_problem_create_complex; blocks through complex_to_real)."""
         self.ctx = ctx
         dev = ctx.device
         self._keep = []
         self.affine = isinstance(terms, (list, tuple))
+        self.complex = kinds is not None
+        if self.complex and not self.affine:
+            raise ValueError("complex coefficients need a list of terms")
         seq = list(terms) if self.affine else [terms.get(role) for role in L.ROLES]
         csrs = [None] * len(seq)
         for r, T in enumerate(seq):
@@ -77,11 +116,21 @@ class Problem:
             csrs[r] = L.Csr(rp.numel() - 1, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
         arr = (C.POINTER(L.Csr) * max(len(seq), 1))(*[C.pointer(c) if c is not None else None for c in csrs])
         h = C.c_void_p()
-        if self.affine:
+        if self.complex:
+            kd = {"real": L.PMOR_COEF_REAL, "imag": L.PMOR_COEF_IMAG, "complex": L.PMOR_COEF_COMPLEX}
+            if len(kinds) != len(seq):
+                raise ValueError("one kind per term")
+            ka = (C.c_int32 * len(seq))(*[kd[x] for x in kinds])
+            L.check(L.pmor_problem_create_complex(ctx.handle, len(seq), arr, ka, C.byref(h)),
+                    "pmor_problem_create_complex")
+            self.nmaps = sum(2 if x == "complex" else 1 for x in kinds)
+            self.ncoef = 2 * len(seq)
+        elif self.affine:
             L.check(L.pmor_problem_create_affine(ctx.handle, len(seq), arr, C.byref(h)), "pmor_problem_create_affine")
+            self.nmaps = self.ncoef = len(seq)
         else:
             L.check(L.pmor_problem_create(ctx.handle, arr, C.byref(h)), "pmor_problem_create")
-        self.nmaps = len(seq)
+            self.nmaps = self.ncoef = len(seq)
         self.handle = h
         self._keep = []  # the library copied the terms
         nn, nz = C.c_int32(), C.c_int32()
@@ -112,7 +161,7 @@ class Problem:
         """Values of A at (s, p), or at the coefficient vector s when p is None."""
         out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.ctx.device)
         if _is_coef(s, p):
-            L.check(L.pmor_assemble_c(self.handle, _coef(s), out.data_ptr()), "pmor_assemble_c")
+            L.check(L.pmor_assemble_c(self.handle, _coef(s, self), out.data_ptr()), "pmor_assemble_c")
         else:
             L.check(L.pmor_assemble(self.handle, float(s), float(p), out.data_ptr()), "pmor_assemble")
         return out[: self.nnz]
@@ -132,7 +181,7 @@ class Problem:
 
     def table2_norms_c(self, coef1, coef2):
         a, b = C.c_double(), C.c_double()
-        L.check(L.pmor_table2_norms_c(self.handle, _coef(coef1), _coef(coef2), C.byref(a), C.byref(b)),
+        L.check(L.pmor_table2_norms_c(self.handle, _coef(coef1, self), _coef(coef2, self), C.byref(a), C.byref(b)),
                 "pmor_table2_norms_c")
         return a.value, b.value
 
@@ -165,7 +214,7 @@ class Problem:
         o = L.SolveOpts(m, max_cycles, tol)
         sh = spai.handle if spai is not None else None
         if _is_coef(s, p):
-            rc = L.block_solve_c(self.handle, sh, _coef(s), B.data_ptr(), B.stride(0), k, X.data_ptr(), X.stride(0),
+            rc = L.block_solve_c(self.handle, sh, _coef(s, self), B.data_ptr(), B.stride(0), k, X.data_ptr(), X.stride(0),
                                  C.byref(o), C.byref(st))
         else:
             rc = L.block_solve(self.handle, sh, float(s), float(p), B.data_ptr(), B.stride(0), k, X.data_ptr(),
@@ -187,7 +236,7 @@ class Problem:
         stats = (L.Stats * npts)()
         pol = L.PMOR_UPDATE if policy == "update" else L.PMOR_REBUILD
         if coefs is not None:
-            cf = _coef([x for row in coefs for x in row])
+            cf = _coefs(coefs, self)
             rc = L.pmor_sequence_solve_c(self.handle, B.data_ptr(), B.stride(0), k, cf, npts, X.data_ptr(),
                                          X.stride(1), pol, C.byref(so), C.byref(vo), stats)
         else:
@@ -217,7 +266,7 @@ def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_err
         Xs.append(X)
         cf = None
         if _is_coef(s, p):
-            cf = _coef(s)
+            cf = _coef(s, pb)
             keep.append(cf)
             s, p = 0.0, 0.0
         arr[i] = L.BatchItem(pb.handle, sp.handle if sp is not None else None, float(s), float(p), B.data_ptr(),
@@ -267,11 +316,11 @@ class Spai:
         if imported is not None:
             rp, ci, va = (t.contiguous() for t in imported)
             args = (ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr(), C.byref(o), C.byref(h))
-            rc = (L.spai_import_c(pb.handle, _coef(s), *args) if _is_coef(s, p)
+            rc = (L.spai_import_c(pb.handle, _coef(s, pb), *args) if _is_coef(s, p)
                   else L.spai_import(pb.handle, float(s), float(p), *args))
             where = "spai_import"
         elif _is_coef(s, p):
-            rc = L.spai_build_c(pb.handle, _coef(s), C.byref(o), C.byref(h), sb)
+            rc = L.spai_build_c(pb.handle, _coef(s, pb), C.byref(o), C.byref(h), sb)
             where = "spai_build_c"
         else:
             rc = L.spai_build(pb.handle, float(s), float(p), C.byref(o), C.byref(h), sb)
@@ -288,7 +337,7 @@ class Spai:
         st = L.Stats()
         sb = C.byref(st) if stats else None
         if _is_coef(s, p):
-            L.check(L.spai_update_c(self.handle, _coef(s), sb), "spai_update_c")
+            L.check(L.spai_update_c(self.handle, _coef(s, self.pb), sb), "spai_update_c")
         else:
             L.check(L.spai_update(self.handle, float(s), float(p), sb), "spai_update")
         self.last_stats = st.as_dict() if stats else None
@@ -298,7 +347,7 @@ class Spai:
         st = L.Stats()
         sb = C.byref(st) if stats else None
         if _is_coef(s, p):
-            L.check(L.spai_rebuild_c(self.handle, _coef(s), sb), "spai_rebuild_c")
+            L.check(L.spai_rebuild_c(self.handle, _coef(s, self.pb), sb), "spai_rebuild_c")
         else:
             L.check(L.spai_rebuild(self.handle, float(s), float(p), sb), "spai_rebuild")
         self.last_stats = st.as_dict() if stats else None
@@ -371,7 +420,7 @@ class Server:
         if X is None:
             X = torch.empty((npts, n, k), dtype=torch.float64, device=B.device)
         if coefs is not None:
-            cf = _coef([x for row in coefs for x in row])
+            cf = _coefs(coefs, pb)
             sl = pl = None
         else:
             cf = None

@@ -116,7 +116,11 @@ int point_coef(const pmor_problem* pb, const double* coef, Point* out) {
   *out = Point{};
   for (int r = 0; r < pb->ncoef; ++r) {
     const int t = pb->coef_slot[r];
-    if (t < 0) continue;  // an absent role
+    if (t < 0) {  // an absent role, or a part a complex term's kind excludes
+      if (pb->strict_coef && coef[r] != 0.0)
+        return fail(PMOR_EINVAL, "coefficient " + std::to_string(r) + " belongs to no term and must be 0");
+      continue;
+    }
     if (!is_fin(coef[r])) return fail(PMOR_EINVAL, "coefficient " + std::to_string(r) + " is not finite");
     out->c[t] = coef[r];
   }
@@ -202,6 +206,20 @@ static int dfill(double* a, int64_t n, double v, hipStream_t s) {
   return PMOR_OK;
 }
 
+// the U-diag factors of no update: 1, or (1, 0) per complex column of a complex problem
+__global__ void k_unit_factors(double* q, int64_t n, int pairs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) q[i] = (pairs && (i & 1)) ? 0.0 : 1.0;
+}
+static int unit_factors(const pmor_spai* h, hipStream_t s) {
+  const int64_t n = h->pb->n;
+  if (n <= 0) return PMOR_OK;
+  hipLaunchKernelGGL(k_unit_factors, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, h->Qval, n,
+                     h->pb->cplx ? 1 : 0);
+  PMOR_HIP(hipGetLastError());
+  return PMOR_OK;
+}
+
 // P_1 of A(pt) into h (anchor moved to pt)
 static int build_into(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   pmor_problem* pb = h->pb;
@@ -216,9 +234,10 @@ static int build_into(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   PMOR_TRY(run_spai_ls(h, pb->aval, nullptr, h->P1val, &bad, stats ? &fro2 : nullptr));
   PMOR_TRY(dcopy(h->P1val, h->Pval, h->nnzP, st));
   PMOR_TRY(to_sell(h->psell, h->P1val, h->P1val_s, st));
-  if (h->opts.update == PMOR_UPD_DIAG) PMOR_TRY(dfill(h->Qval, pb->n, 1.0, st));
+  if (h->opts.update == PMOR_UPD_DIAG) PMOR_TRY(unit_factors(h, st));
   h->q_active = false;
   h->d_active = false;
+  h->c_active = false;
   h->pt1 = pt;
   const double t_pre = tp.stop();
   if (stats) {
@@ -254,6 +273,10 @@ static SolveItem item_of(pmor_problem* pb, const pmor_spai* h, const double* ava
     it.psell = &h->psell;
     it.pval_s = h->P1val_s;  // Pval equals P1val unless an update is applied
     it.qval_s = h->Qval_s;
+    if (h->c_active) {  // P_l of a complex problem, written out
+      it.pval = h->Pval;
+      it.pval_s = h->Qval_s;
+    }
   }
   it.B = B;
   it.ldb = ldb;
@@ -528,6 +551,63 @@ int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* co
   return problem_create(ctx, terms, nterms, true, out);
 }
 
+int pmor_problem_create_complex(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, const int32_t* kinds,
+                                pmor_problem** out) {
+  if (out) *out = nullptr;
+  if (!ctx || !terms || !kinds || !out) return fail(PMOR_EINVAL, "NULL argument");
+  if (nterms < 1 || nterms > PMOR_TMAX) return fail(PMOR_EINVAL, "nterms must be in 1..PMOR_TMAX");
+  int nreal = 0, n = -1;
+  for (int t = 0; t < nterms; ++t) {
+    if (kinds[t] != PMOR_COEF_REAL && kinds[t] != PMOR_COEF_IMAG && kinds[t] != PMOR_COEF_COMPLEX)
+      return fail(PMOR_EINVAL, "bad coefficient kind");
+    const pmor_csr* T = terms[t];
+    if (!T || !T->rowptr || T->n <= 0 || T->nnz < 0 || (T->nnz > 0 && (!T->col || !T->val)))
+      return fail(PMOR_EINVAL, "term " + std::to_string(t) + " is NULL or malformed");
+    if (n >= 0 && T->n != n) return fail(PMOR_EINVAL, "terms differ in n");
+    n = T->n;
+    nreal += kinds[t] == PMOR_COEF_COMPLEX ? 2 : 1;
+  }
+  if (nreal > PMOR_TMAX) return fail(PMOR_EINVAL, "more than PMOR_TMAX real terms");
+  if ((int64_t)2 * n >= ((int64_t)1 << 31)) return fail(PMOR_EINVAL, "2n too large");
+  PMOR_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  // the real terms T (x) I_2 and T (x) J_2, in the order of the coefficients
+  std::vector<void*> bufs;
+  std::vector<pmor_csr> rt(nreal);
+  std::vector<int> slot_of_coef(2 * nterms, -1);
+  int rc = PMOR_OK, q = 0;
+  for (int t = 0; t < nterms && rc == PMOR_OK; ++t) {
+    for (int part = 0; part < 2 && rc == PMOR_OK; ++part) {
+      if ((part == 0 && kinds[t] == PMOR_COEF_IMAG) || (part == 1 && kinds[t] == PMOR_COEF_REAL)) continue;
+      int32_t *rp = nullptr, *cl = nullptr, nz2 = 0;
+      double* vl = nullptr;
+      rc = real_equiv_term(terms[t], part, &rp, &cl, &vl, &nz2, st);
+      if (rc != PMOR_OK) break;
+      bufs.push_back(rp); bufs.push_back(cl); bufs.push_back(vl);
+      rt[q] = pmor_csr{2 * n, nz2, rp, cl, vl};
+      slot_of_coef[2 * t + part] = q++;
+    }
+  }
+  if (rc == PMOR_OK) {
+    std::vector<const pmor_csr*> ptrs(nreal);
+    for (int i = 0; i < nreal; ++i) ptrs[i] = &rt[i];
+    rc = problem_create(ctx, ptrs.data(), nreal, true, out);
+  }
+  if (rc == PMOR_OK) {  // points: 2 nterms coefficients (Re, Im per term), slots of the real terms
+    pmor_problem* pb = *out;
+    int term_slot[2 * PMOR_TMAX];  // real term q -> its stored slot
+    for (int r = 0; r < 2 * PMOR_TMAX; ++r) term_slot[r] = pb->coef_slot[r];
+    pb->ncoef = 2 * nterms;
+    for (int r = 0; r < 2 * PMOR_TMAX; ++r) pb->coef_slot[r] = -1;
+    for (int r = 0; r < 2 * nterms; ++r) pb->coef_slot[r] = slot_of_coef[r] >= 0 ? term_slot[slot_of_coef[r]] : -1;
+    pb->strict_coef = true;
+    pb->cplx = true;
+  }
+  (void)hipStreamSynchronize(st);
+  for (void* x : bufs) dfree(x, st);
+  return rc;
+}
+
 void pmor_problem_destroy(pmor_problem* pb) {
   if (pb) pb_unref(pb);
 }
@@ -578,6 +658,8 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
     return fail(PMOR_EINVAL, "bad update approach");
   if (o.approach == PMOR_APPROACH_SECOND && o.update != PMOR_UPD_DIAG)
     return fail(PMOR_EINVAL, "the second update approach is built for the U-diag update only");
+  if (pb->cplx && (o.approach == PMOR_APPROACH_SECOND || o.update == PMOR_UPD_ADAPTIVE))
+    return fail(PMOR_EINVAL, "a complex problem takes the first approach with the U-diag or U-pattern update");
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   pmor_spai* h = new pmor_spai();
   h->pb = pb;
@@ -585,6 +667,9 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
   h->opts = o;
   *out = h;
   int rc = build_spai_sets(h);
+  // P of a complex problem must be the real form of a complex pattern (its
+  // least squares are then the complex ones, and Q P_1 keeps the pattern)
+  if (rc == PMOR_OK && pb->cplx) rc = check_pairs(pb->n, h->Prowptr, h->Pcol, pb->ctx->stream);
   if (rc == PMOR_OK) {
     const int64_t n = pb->n;
     auto al = [&](double** p, int64_t cnt) {
@@ -595,7 +680,7 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
               al(&h->rho, n) && al(&h->red, 512);
     if (ok && h->psell.cap > 0)
       ok = al(&h->P1val_s, h->psell.cap) &&
-           (o.update == PMOR_UPD_DIAG || al(&h->Qval_s, h->psell.cap));
+           ((o.update == PMOR_UPD_DIAG && !pb->cplx) || al(&h->Qval_s, h->psell.cap));
     if (ok && o.update == PMOR_UPD_ADAPTIVE)
       ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), pb->ctx->stream) ==
                hipSuccess &&
@@ -630,7 +715,12 @@ static int spai_update_pt(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   Timer tp(pb->ctx, stats != nullptr);
   int32_t bad = -1;
   double fro2 = 0.0;
-  if (h->opts.update == PMOR_UPD_DIAG) {
+  if (h->opts.update == PMOR_UPD_DIAG && pb->cplx) {
+    // complex factors: P_l = Q P_1 written out and applied as it stands
+    PMOR_TRY(run_update_pair(h, pb->aval, h->Pval, h->Qval, h->rho, &bad, stats ? &fro2 : nullptr));
+    PMOR_TRY(to_sell(h->psell, h->Pval, h->Qval_s, pb->ctx->stream));
+    h->c_active = true;
+  } else if (h->opts.update == PMOR_UPD_DIAG) {
     // P_l = diag(q) P_1 is also written out (export); solves apply the factors
     PMOR_TRY(run_update_diag(h, pb->aval, &bad, stats ? &fro2 : nullptr));
     h->d_active = true;
@@ -684,11 +774,11 @@ static int spai_import_pt(pmor_problem* pb, const Point& pt, int32_t nnzP, const
   if (rc == PMOR_OK) rc = dcopy(val, h->P1val, nnzP, st);
   if (rc == PMOR_OK) rc = dcopy(val, h->Pval, nnzP, st);
   if (rc == PMOR_OK) rc = to_sell(h->psell, h->P1val, h->P1val_s, st);
-  if (rc == PMOR_OK && h->opts.update == PMOR_UPD_DIAG) rc = dfill(h->Qval, pb->n, 1.0, st);
+  if (rc == PMOR_OK && h->opts.update == PMOR_UPD_DIAG) rc = unit_factors(h, st);
   if (rc == PMOR_OK) rc = dfill(h->rho, pb->n, 0.0, st);
   if (rc == PMOR_OK) {
     h->pt1 = pt;
-    h->q_active = h->d_active = false;
+    h->q_active = h->d_active = h->c_active = false;
     if (hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
   }
   dfree(cp, st);
@@ -1123,7 +1213,7 @@ static int prepare_points_diag(pmor_problem* pb, pmor_spai* h, const Point* pts,
 static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const Point* pts, int l0, int cnt,
                           const double* B, int64_t ldb, int k, double* X, int64_t ldx, pmor_stats* stats,
                           const pmor_stats& pre0, SeqBuffers& sb, SolveItem* items, int* bad) {
-  if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG)
+  if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG && !pb->cplx)
     return prepare_points_diag(pb, h, pts, l0, cnt, B, ldb, k, X, ldx, stats, pre0, sb, items, bad);
   hipStream_t st = pb->ctx->stream;
   const int64_t nnz = pb->nnz, nnzP = h->nnzP;
@@ -1157,12 +1247,16 @@ static int prepare_points(pmor_problem* pb, pmor_spai* h, int policy, const Poin
     } else {
       int32_t b = -1;
       double fro2 = 0.0;
+      const bool pair = policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG;  // a complex problem
       if (policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_ADAPTIVE)
         rc = run_update_adaptive(h, Al, PQ, &b, stats ? &fro2 : nullptr, nullptr);
+      else if (pair)
+        rc = run_update_pair(h, Al, PQ, sb.q + (int64_t)t * pb->n, sb.rho + (int64_t)t * pb->n, &b,
+                             stats ? &fro2 : nullptr);
       else rc = run_spai_ls(h, Al, policy == PMOR_UPDATE ? h->aval1 : nullptr, PQ, &b, stats ? &fro2 : nullptr);
       bad[t] = b;
       fro_host[t] = fro2;
-      if (policy == PMOR_UPDATE) {
+      if (policy == PMOR_UPDATE && !pair) {
         x.pkind = 2;
         x.pval = h->P1val;
         x.pval_s = h->P1val_s;
@@ -1303,7 +1397,7 @@ static int sequence_run(pmor_problem* pb, const double* B, int64_t ldb, int32_t 
   // points per group: A and P/Q values plus the Krylov blocks of one system
   const int kp = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
   // the U-diag update keeps P_l factored: no per-point P values
-  const bool rowq = policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG;
+  const bool rowq = policy == PMOR_UPDATE && h->opts.update == PMOR_UPD_DIAG && !pb->cplx;
   const int64_t nnzPp = rowq ? 0 : nnzP, capPp = rowq ? 0 : h->psell.cap;
   // and A(l) only in the sliced ELL layout when it has one
   const int64_t nnzA = (rowq && pb->sell.cap > 0) ? 0 : nnz;
@@ -1371,6 +1465,7 @@ static int sequence_solve(pmor_problem* pb, const double* B, int64_t ldb, int32_
   if (!(tol >= 0.0) || !is_fin(tol)) return fail(PMOR_EINVAL, "reanchor_tol must be finite and >= 0");
   if (tol > 0.0 && (policy != PMOR_UPDATE || sopts->update != PMOR_UPD_DIAG || sopts->approach != PMOR_APPROACH_FIRST))
     return fail(PMOR_EINVAL, "re-anchoring is built for the U-diag update with the first approach");
+  if (tol > 0.0 && pb->cplx) return fail(PMOR_EINVAL, "re-anchoring is built for real problems");
   PMOR_HIP(hipSetDevice(pb->ctx->device));
   const auto t0 = std::chrono::steady_clock::now();
   if (stats) std::memset(stats, 0, sizeof(pmor_stats) * npts);
@@ -1442,8 +1537,8 @@ static int64_t job_footprint(const pmor_problem* pb, int npts, bool rowq) {
 }
 
 // the U-diag update policy keeps every P_l factored (no per-point P values)
-static bool rows_scaled(int policy, const pmor_spai_opts& so) {
-  return policy == PMOR_UPDATE && so.update == PMOR_UPD_DIAG;
+static bool rows_scaled(const pmor_problem* pb, int policy, const pmor_spai_opts& so) {
+  return policy == PMOR_UPDATE && so.update == PMOR_UPD_DIAG && !pb->cplx;
 }
 }  // namespace pmor
 
@@ -1483,7 +1578,7 @@ static int job_admit(pmor_server* sv, ServerJob* J) {
   sv->jobs[J->id] = J;
   int rc = spai_build_pt(jb.pb, J->pts[0], &sv->sopts, &J->h, &pre0);
   if (rc == PMOR_OK) {
-    const bool rq = rows_scaled(jb.policy, J->h->opts);
+    const bool rq = rows_scaled(jb.pb, jb.policy, J->h->opts);
     rc = J->sb.alloc(npts, (rq && jb.pb->sell.cap > 0) ? 0 : jb.pb->nnz, rq ? 0 : J->h->nnzP, jb.pb->n,
                      sv->ctx->stream, jb.pb->sell.cap, rq ? 0 : J->h->psell.cap);
   }
@@ -1596,7 +1691,7 @@ int pmor_server_submit(pmor_server* sv, const pmor_job* job, int64_t* job_id) {
   J->job = *job;
   J->pts.swap(pts);
   J->job.s_list = J->job.p_list = J->job.coefs = nullptr;  // host arrays copied: not referenced later
-  J->footprint = job_footprint(job->pb, job->npts, rows_scaled(job->policy, sv->sopts));
+  J->footprint = job_footprint(job->pb, job->npts, rows_scaled(job->pb, job->policy, sv->sopts));
   if (J->footprint + sv->engine_bytes > sv->budget) {
     delete J;
     return fail(PMOR_EADMIT, "job footprint exceeds the server's memory budget");

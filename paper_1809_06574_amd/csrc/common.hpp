@@ -163,7 +163,9 @@ struct pmor_problem {
   double* tval = nullptr;      // term values on the union pattern, one array per stored term
   bool affine = false;         // created by pmor_problem_create_affine (points are coefficient vectors)
   int ncoef = 0;               // entries of a point's coefficient vector (PMOR_NROLES for a problem of roles)
-  int coef_slot[PMOR_TMAX];    // coefficient index -> index into tval, or -1 (absent role)
+  int coef_slot[2 * PMOR_TMAX];  // coefficient index -> index into tval, or -1 (absent role / excluded part)
+  bool strict_coef = false;    // a coefficient without a term must be 0 (complex problems)
+  bool cplx = false;           // equivalent real form of a complex problem (pmor_problem_create_complex)
   int nmaps = 0;               // rows of maps: PMOR_NROLES (roles) or nterms (affine)
   int nterms = 0;
   int32_t* colptr = nullptr;   // CSC view of the pattern
@@ -205,6 +207,7 @@ struct pmor_spai {
   bool identity_order = true;
   bool q_active = false;     // U-pattern update applied (apply Q (P_1 x))
   bool d_active = false;     // U-diag update applied (apply diag(q) (P_1 x), q in Qval)
+  bool c_active = false;     // complex U-diag update applied: P_l written out in Pval (Qval_s: its sliced ELL)
   pmor::Point pt1{};          // the anchor point
   pmor::SellView psell;      // sliced ELL view of P's pattern (the problem's for PAT_A)
   bool own_psell = false;
@@ -284,6 +287,12 @@ int build_spai_sets(pmor_spai* h);
 // PMOR_EINVAL unless (rowptr, col) is an n x n CSR pattern of nnz entries with
 // strictly increasing columns per row (synchronises)
 int check_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, hipStream_t st);
+// the equivalent real form of complex term T (part 0: T (x) I_2, part 1:
+// T (x) J_2), block-closed with the diagonal blocks; arrays allocated here
+int real_equiv_term(const pmor_csr* T, int part, int32_t** rp2, int32_t** col2, double** val2, int32_t* nnz2,
+                    hipStream_t st);
+// PMOR_EINVAL unless the order-n CSR pattern is the real form of a complex one
+int check_pairs(int n, const int32_t* rowptr, const int32_t* col, hipStream_t st);
 // CSC view (colptr n+1, rowidx, slot: CSC position -> CSR position) allocated here
 int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
                       int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st);
@@ -301,6 +310,10 @@ int to_sell(const SellView& v, const double* src, double* dst, hipStream_t st);
 int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double* out_val,
                 int32_t* bad_col, double* fro2);
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
+// the U-diag update of a complex problem (2x2 blocks of the real form): factors
+// into q (n: Re, Im per complex column), residuals into rho (n), P_l = Q P_1 into pl
+int run_update_pair(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int32_t* bad_col,
+                    double* fro2);
 // every column's gathered block A(I_j, J_j) (anchor values) reduced to its sum in colsum (n, device)
 int run_spai_gather(pmor_spai* h, double* colsum);
 // adaptive Q (PMOR_UPD_ADAPTIVE): Q in P's CSR order into qout, residuals into h->rho;

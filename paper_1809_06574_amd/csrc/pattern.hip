@@ -265,6 +265,141 @@ int check_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, hip
   return PMOR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// equivalent real form of a complex term (order n -> 2n).  Row i of T, with
+// its diagonal entry added (value 0) when absent, becomes rows 2i and 2i+1;
+// entry (i, j) becomes the full 2x2 block at columns 2j, 2j+1:
+//   part 0 (T (x) I_2): [[v, 0], [0, v]];  part 1 (T (x) J_2): [[0, -v], [v, 0]].
+// Every block is stored whole (zeros included), so the union of such terms is
+// the real form of a complex pattern: rows 2i and 2i+1 hold the same columns,
+// and columns come in pairs 2j, 2j+1.
+// ---------------------------------------------------------------------------
+__global__ void k_re_count(int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                           int64_t* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool diag = false;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) diag |= col[e] == i;
+  cnt[i] = rowptr[i + 1] - rowptr[i] + (diag ? 0 : 1);
+}
+
+__global__ void k_re_fill(int n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                          const double* __restrict__ val, const int64_t* __restrict__ off, int part,
+                          int32_t* __restrict__ rp2, int32_t* __restrict__ col2, double* __restrict__ val2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t len = off[i + 1] - off[i];
+  const int64_t r0 = 4 * off[i], r1 = r0 + 2 * len;  // starts of rows 2i and 2i+1
+  rp2[2 * i] = (int32_t)r0;
+  rp2[2 * i + 1] = (int32_t)r1;
+  if (i == n - 1) rp2[2 * n] = (int32_t)(4 * off[n]);
+  int e = rowptr[i];
+  const int e1 = rowptr[i + 1];
+  bool diag_done = false;
+  for (int64_t k = 0; k < len; ++k) {
+    int j;
+    double v;
+    if (e < e1 && (diag_done || col[e] <= i)) {  // the row's next entry (the diagonal itself when present)
+      j = col[e];
+      v = val[e];
+      ++e;
+      if (j == i) diag_done = true;
+    } else {  // the absent diagonal, in its sorted place
+      j = i;
+      v = 0.0;
+      diag_done = true;
+    }
+    const int64_t q0 = r0 + 2 * k, q1 = r1 + 2 * k;
+    col2[q0] = 2 * j;
+    col2[q0 + 1] = 2 * j + 1;
+    col2[q1] = 2 * j;
+    col2[q1 + 1] = 2 * j + 1;
+    if (part == 0) {
+      val2[q0] = v;
+      val2[q0 + 1] = 0.0;
+      val2[q1] = 0.0;
+      val2[q1 + 1] = v;
+    } else {
+      val2[q0] = 0.0;
+      val2[q0 + 1] = -v;
+      val2[q1] = v;
+      val2[q1 + 1] = 0.0;
+    }
+  }
+}
+
+int real_equiv_term(const pmor_csr* T, int part, int32_t** rp2, int32_t** col2, double** val2, int32_t* nnz2,
+                    hipStream_t st) {
+  *rp2 = nullptr;
+  *col2 = nullptr;
+  *val2 = nullptr;
+  const int n = T->n;
+  PMOR_TRY(check_csr(n, T->nnz, T->rowptr, T->col, st));
+  if (4 * ((int64_t)T->nnz + n) >= ((int64_t)1 << 31)) return fail(PMOR_EINVAL, "equivalent real term too large");
+  int64_t* off = nullptr;
+  PMOR_HIP(dmalloc((void**)&off, sizeof(int64_t) * ((size_t)n + 1), st));
+  hipLaunchKernelGGL(k_re_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T->rowptr, T->col, off);
+  int rc = hipGetLastError() == hipSuccess ? PMOR_OK : fail(PMOR_EHIP, "launch failed");
+  if (rc == PMOR_OK) rc = scan_exclusive(off, n, st);
+  int64_t tot = 0;
+  if (rc == PMOR_OK && hipMemcpyAsync(&tot, off + n, sizeof(int64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+    rc = fail(PMOR_EHIP, "copy failed");
+  if (rc == PMOR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
+  if (rc == PMOR_OK) {
+    const int64_t nz = 4 * tot;
+    if (dmalloc((void**)rp2, sizeof(int32_t) * (2 * (size_t)n + 1), st) != hipSuccess ||
+        dmalloc((void**)col2, sizeof(int32_t) * (size_t)nz, st) != hipSuccess ||
+        dmalloc((void**)val2, sizeof(double) * (size_t)nz, st) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = fail(PMOR_ENOMEM, "allocation of an equivalent real term failed");
+    } else {
+      hipLaunchKernelGGL(k_re_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, T->rowptr, T->col,
+                         T->val, off, part, *rp2, *col2, *val2);
+      if (hipGetLastError() != hipSuccess) rc = fail(PMOR_EHIP, "launch failed");
+      *nnz2 = (int32_t)nz;
+    }
+  }
+  dfree(off, st);
+  if (rc != PMOR_OK) {
+    dfree(*rp2, st);
+    dfree(*col2, st);
+    dfree(*val2, st);
+    *rp2 = nullptr;
+    *col2 = nullptr;
+    *val2 = nullptr;
+  }
+  return rc;
+}
+
+// a CSR pattern of order 2m is the real form of a complex one: rows 2i and 2i+1
+// hold the same columns, and every row's columns come in pairs 2j, 2j+1
+__global__ void k_check_pairs(int m, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, int* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int a = rowptr[2 * i], b = rowptr[2 * i + 1], c = rowptr[2 * i + 2];
+  bool ok = (b - a == c - b) && ((b - a) % 2 == 0);
+  for (int k = 0; ok && k < b - a; k += 2)
+    ok = (col[a + k] % 2 == 0) && col[a + k + 1] == col[a + k] + 1 && col[b + k] == col[a + k] &&
+         col[b + k + 1] == col[a + k + 1];
+  if (!ok) atomicOr(err, 1);
+}
+
+int check_pairs(int n, const int32_t* rowptr, const int32_t* col, hipStream_t st) {
+  if (n % 2) return fail(PMOR_EINVAL, "odd order");
+  int* derr = nullptr;
+  PMOR_HIP(dmalloc((void**)&derr, sizeof(int), st));
+  PMOR_HIP(hipMemsetAsync(derr, 0, sizeof(int), st));
+  const int m = n / 2;
+  if (m > 0) hipLaunchKernelGGL(k_check_pairs, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, rowptr, col, derr);
+  PMOR_HIP(hipGetLastError());
+  int herr = 0;
+  PMOR_HIP(hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMOR_HIP(hipStreamSynchronize(st));
+  dfree(derr, st);
+  if (herr) return fail(PMOR_EINVAL, "the pattern of P is not the real form of a complex pattern");
+  return PMOR_OK;
+}
+
 // pattern (n x n, nnz entries in CSR) -> CSC arrays allocated here
 int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
                       int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st) {
@@ -315,8 +450,8 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int coun
   TermPtrs tp{};
   tp.nmaps = count;
   int nt = 0;
+  for (int r = 0; r < 2 * PMOR_TMAX; ++r) pb->coef_slot[r] = -1;
   for (int r = 0; r < PMOR_TMAX; ++r) {
-    pb->coef_slot[r] = -1;
     tp.present[r] = 0;
     tp.slot[r] = -1;
     if (r >= count || !terms[r]) continue;

@@ -795,6 +795,83 @@ int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double
 }
 
 // ---------------------------------------------------------------------------
+// U-diag update of a complex problem in its equivalent real form.  The factor
+// of complex column i is the complex q_i = <A(l) e_i, A(1) e_i> / ||A(l) e_i||^2
+// (first approach, Section 2.3); in the real form it is the 2x2 block
+// [[a, -b], [b, a]] (q_i = a + b sqrt(-1)) on rows and columns 2i, 2i+1, and
+// with c0, c1 the real columns 2i, 2i+1 of A(l) (c1 the rotation of c0) and t
+// the real column 2i of A(1): a = <c0, t> / ||c0||^2, b = <c1, t> / ||c0||^2.
+// The pattern is block-closed, so the two columns hold the same rows in the
+// same order, and rows 2i, 2i+1 of P the same columns.  q[2i] = a,
+// q[2i+1] = b; rho of both real columns, entry by entry; P_l = Q P_1 written
+// out: row 2i = a P_1(2i,:) - b P_1(2i+1,:), row 2i+1 = b P_1(2i,:) + a P_1(2i+1,:).
+// ---------------------------------------------------------------------------
+__global__ void k_update_pair(int m, const int32_t* colptr, const int32_t* cscslot, const double* al,
+                              const double* a1, const int32_t* Prowptr, const double* P1, double* Pl, double* q,
+                              double* rho, int* bad_col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int c0 = 2 * i, c1 = 2 * i + 1;
+  const int e0 = colptr[c0], e1 = colptr[c1], len = e1 - e0;
+  double nre = 0.0, nim = 0.0, den = 0.0;
+  for (int k = 0; k < len; ++k) {
+    const int s0 = cscslot[e0 + k], s1 = cscslot[e1 + k];
+    const double x0 = al[s0], x1 = al[s1], y0 = a1[s0];
+    nre += x0 * y0;
+    nim += x1 * y0;
+    den += x0 * x0;
+  }
+  const double a = nre / den, b = nim / den;
+  if (!(den > 0.0)) atomicMin(bad_col, c0);
+  q[c0] = a;
+  q[c1] = b;
+  double r0 = 0.0, r1 = 0.0;
+  for (int k = 0; k < len; ++k) {
+    const int s0 = cscslot[e0 + k], s1 = cscslot[e1 + k];
+    const double x0 = al[s0], x1 = al[s1];
+    const double d0 = a1[s0] - (a * x0 + b * x1);
+    const double d1 = a1[s1] - (a * x1 - b * x0);
+    r0 += d0 * d0;
+    r1 += d1 * d1;
+  }
+  rho[c0] = sqrt(r0);
+  rho[c1] = sqrt(r1);
+  const int p0 = Prowptr[c0], p1 = Prowptr[c1], plen = p1 - p0;
+  for (int k = 0; k < plen; ++k) {
+    const double u = P1[p0 + k], w = P1[p1 + k];
+    Pl[p0 + k] = a * u - b * w;
+    Pl[p1 + k] = b * u + a * w;
+  }
+}
+
+int run_update_pair(pmor_spai* h, const double* aval_l, double* pl, double* q, double* rho, int32_t* bad_col,
+                    double* fro2) {
+  pmor_problem* pb = h->pb;
+  hipStream_t st = pb->ctx->stream;
+  const int n = pb->n, m = n / 2;
+  int* dbad = reinterpret_cast<int*>(h->red);
+  const int big = 0x7fffffff;
+  PMOR_TRY(set_device_int(dbad, big, st));
+  if (m > 0) {
+    hipLaunchKernelGGL(k_update_pair, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, pb->colptr,
+                       pb->cscslot, aval_l, h->aval1, h->Prowptr, h->P1val, pl, q, rho, dbad);
+    PMOR_HIP(hipGetLastError());
+  }
+  if (bad_col || fro2) {
+    double* dsum = h->red + 1;
+    PMOR_TRY(sumsq(rho, n, dsum, st));
+    double hs = 0.0;
+    int hbad = big;
+    PMOR_HIP(hipMemcpyAsync(&hs, dsum, sizeof(double), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipMemcpyAsync(&hbad, dbad, sizeof(int), hipMemcpyDeviceToHost, st));
+    PMOR_HIP(hipStreamSynchronize(st));
+    if (fro2) *fro2 = hs;
+    if (bad_col) *bad_col = (hbad == big) ? -1 : hbad;
+  }
+  return PMOR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Adaptive update pattern: every column first takes its U-diag factor q_i;
 // a column whose diagonal misfit ||A(1) e_i - q_i A(l) e_i|| exceeds
 // ep ||A(1) e_i|| (or is not finite) is escalated to the SPAI pattern J_i, the

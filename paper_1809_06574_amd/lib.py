@@ -22,7 +22,8 @@ PMOR_OK, PMOR_EINVAL, PMOR_ENOMEM, PMOR_ENOTCONV = 0, -1, -2, -3
 PMOR_EBREAKDOWN, PMOR_ESINGULAR, PMOR_ENAN, PMOR_EHIP, PMOR_EADMIT = -4, -5, -6, -7, -8
 PMOR_KMAX = 16
 PMOR_NROLES = 6
-PMOR_TMAX = 8
+PMOR_TMAX = 16
+PMOR_COEF_REAL, PMOR_COEF_IMAG, PMOR_COEF_COMPLEX = 0, 1, 2
 PMOR_MAX_CYCLES = 64
 ROLES = ("M0", "M1", "D0", "D1", "K0", "K1")
 PMOR_PAT_A, PMOR_PAT_EXPLICIT = 0, 1
@@ -91,6 +92,7 @@ _SIGS = {
     "pmor_ctx_set_stream": (C.c_int, [P, P]),
     "pmor_problem_create": (C.c_int, [P, C.POINTER(C.POINTER(Csr)), PP]),
     "pmor_problem_create_affine": (C.c_int, [P, I32, C.POINTER(C.POINTER(Csr)), PP]),
+    "pmor_problem_create_complex": (C.c_int, [P, I32, C.POINTER(C.POINTER(Csr)), C.POINTER(I32), PP]),
     "pmor_problem_destroy": (None, [P]),
     "pmor_problem_info": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
     "pmor_problem_pattern": (C.c_int, [P, P, P, P]),

@@ -203,7 +203,7 @@ def test_affine_argument_errors(ctx, job):
     ci = torch.as_tensor(T.col, device="cuda")
     va = torch.as_tensor(T.val, device="cuda")
     csr = L.Csr(T.n, T.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr())
-    arr = (C.POINTER(L.Csr) * 9)(*([C.pointer(csr)] * 9))
+    arr = (C.POINTER(L.Csr) * (L.PMOR_TMAX + 1))(*([C.pointer(csr)] * (L.PMOR_TMAX + 1)))
     o = C.c_void_p()
     assert L.pmor_problem_create_affine(ctx.handle, 0, arr, C.byref(o)) == L.PMOR_EINVAL
     assert L.pmor_problem_create_affine(ctx.handle, L.PMOR_TMAX + 1, arr, C.byref(o)) == L.PMOR_EINVAL
