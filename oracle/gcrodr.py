@@ -57,24 +57,36 @@ class GcroInfo:
     harmonic: List[np.ndarray]  # the selected mu values of each update
 
 
+REAL_MU = 1e-10  # |Im mu| <= REAL_MU max|mu| counts as a real eigenvalue
+
+
 def harmonic_select(G, WtV, kr):
     """The recycled directions P_k (N x kc, kc <= kr): eigenvectors z of
     G^T WtV z = mu G^T G z taken by decreasing |mu| (equal magnitudes by the
-    library's order); a real mu gives Re z, a complex pair gives Re z, Im z of
-    its member with positive imaginary part; a pair that does not fit in what is
-    left of kr ends the selection.  Returns (P_k, the selected mu)."""
+    library's order).  A real mu (|Im mu| <= REAL_MU max|mu|) gives Re z after
+    z is scaled to unit norm with its largest entry real and positive; a complex
+    pair gives Re z, Im z of its member with positive imaginary part; a pair
+    that does not fit in what is left of kr ends the selection.  Returns (P_k,
+    the selected mu)."""
     if kr <= 0:
         return np.zeros((G.shape[1], 0)), np.zeros(0)
     mu, Z = sla.eig(G.T @ WtV, G.T @ G)
-    order = np.argsort(-np.abs(mu), kind="stable")
+    ok = np.isfinite(mu)
+    if not np.any(ok):
+        return np.zeros((G.shape[1], 0)), np.zeros(0)
+    thr = REAL_MU * np.abs(mu[ok]).max()
+    order = [i for i in np.argsort(-np.abs(np.where(ok, mu, 0.0)), kind="stable") if ok[i]]
     cols, picked, used = [], [], set()
     for i in order:
         if len(cols) >= kr:
             break
         if i in used:
             continue
-        if mu[i].imag == 0.0:
-            cols.append(Z[:, i].real)
+        if abs(mu[i].imag) <= thr:
+            z = Z[:, i] / np.linalg.norm(Z[:, i])
+            t = int(np.argmax(np.abs(z)))
+            z = z * (np.conj(z[t]) / abs(z[t]))
+            cols.append(z.real)
             picked.append(mu[i])
             used.add(i)
             continue
