@@ -327,6 +327,52 @@ int block_solve_c(pmor_problem* pb, const pmor_spai* h, const double* coef,
                   const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
                   const pmor_solve_opts* opts, pmor_stats* stats);
 
+/* ---- Block GCRO-DR: recycling a subspace across the points of a sequence ----
+ * The paper solves its sequences with block GCRO and a recycled subspace
+ * (Section 3, Table 5).  A pmor_recycle holds the recycled basis U~ (n x kc,
+ * kc <= kr) that one solve leaves for the next.  block_solve_gcrodr solves
+ * A(s,p) X = B with right preconditioner h (NULL: none) by block GCRO-DR(m, kr):
+ *  - entering: C = A P U~ = Q R, C <- Q, U <- U~ R^{-1} (Op U = C, C orthonormal;
+ *    if that QR breaks down the solve starts without recycling);
+ *  - each cycle: R = B - A X, projected on C (X += P U C^T R, R -= C C^T R);
+ *    block Arnoldi on (I - C C^T) A P with two Gram-Schmidt passes against
+ *    [C, V]; y2 = argmin ||E1 S - Hbar y2||; X += P (V y2 - U B y2);
+ *  - end of each cycle: the harmonic Ritz vectors of A P on span([U D, V])
+ *    (G^T (What^T Vhat) z = mu G^T G z, G = [[D, B], [0, Hbar]], D = diag
+ *    (1/||u_i||); the kr of largest |mu|, a conjugate pair as Re z, Im z, a pair
+ *    that does not fit ends the choice) become the new C and U;
+ *  - the final U is left in rec for the next call.
+ * X is overwritten (start X0 = 0).  opts as block_solve (m, max_cycles, tol);
+ * stats: cycles, steps, cycle_steps, relres, t_solve_ms.  B must have no zero
+ * column (PMOR_EINVAL).  Errors: PMOR_ENOTCONV, PMOR_EBREAKDOWN (dependent
+ * residual columns), PMOR_ENAN, PMOR_EINVAL (arguments; rec of another size or
+ * context).  Synchronises the stream.  Device work: the library's SpMM, Gram
+ * products and tall-skinny products; the small dense work runs on the host. */
+typedef struct pmor_recycle pmor_recycle;
+/* An empty recycler for problems of order n, recycled dimension at most kr
+ * (0..PMOR_KMAX; 0 makes block_solve_gcrodr block GMRES). */
+int pmor_recycle_create(pmor_ctx* ctx, int32_t n, int32_t kr, pmor_recycle** out);
+void pmor_recycle_destroy(pmor_recycle* r);
+/* kc: the recycled dimension held now (host output). */
+int pmor_recycle_info(const pmor_recycle* r, int32_t* kc);
+/* Forget the recycled basis (the next solve starts without one). */
+int pmor_recycle_reset(pmor_recycle* r);
+/* U~ into U (device, n x kc, row-major, leading dimension ldu >= kc). */
+int pmor_recycle_export(const pmor_recycle* r, double* U, int64_t ldu);
+int block_solve_gcrodr(pmor_problem* pb, const pmor_spai* h, double s, double p,
+                       const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
+                       const pmor_solve_opts* opts, pmor_recycle* rec, pmor_stats* stats);
+int block_solve_gcrodr_c(pmor_problem* pb, const pmor_spai* h, const double* coef,
+                         const double* B, int64_t ldb, int32_t k, double* X, int64_t ldx,
+                         const pmor_solve_opts* opts, pmor_recycle* rec, pmor_stats* stats);
+/* The harmonic Ritz choice of block GCRO-DR on host matrices (row-major): G
+ * and WtV are rows x N (rows >= N); Pk (N x kr, row-major) receives the chosen
+ * directions in its first *count columns, mu_re/mu_im (may be NULL, kr each)
+ * their eigenvalues mu.  PMOR_ESINGULAR when G^T G is not positive definite
+ * or the eigenvalue iteration fails.  Host only (no device work). */
+int pmor_harmonic_ritz(int32_t rows, int32_t N, const double* G, const double* WtV, int32_t kr,
+                       double* Pk, double* mu_re, double* mu_im, int32_t* count);
+
 /* One system of pmor_batch_solve: A of problem pb at the point coef (host
  * coefficient vector) or, when coef is NULL, at (s,p) (assembled by the
  * library), preconditioned by h's current preconditioner (or NULL), B and X as

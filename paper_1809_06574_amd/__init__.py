@@ -14,7 +14,8 @@ import importlib
 
 _LAZY = {"lib": ("lib", None), "Context": ("api", "Context"), "Problem": ("api", "Problem"),
          "Spai": ("api", "Spai"), "batch_solve": ("api", "batch_solve"),
-         "Server": ("api", "Server")}
+         "Server": ("api", "Server"), "Recycler": ("api", "Recycler"),
+         "complex_to_real": ("api", "complex_to_real"), "real_to_complex": ("api", "real_to_complex")}
 
 
 def __getattr__(name):

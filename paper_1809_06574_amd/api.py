@@ -223,6 +223,26 @@ class Problem:
             L.check(rc, "block_solve")
         return X, st.as_dict(), rc
 
+    def block_solve_gcrodr(self, spai, s, p, B: torch.Tensor, recycler: "Recycler", m=30, tol=1e-8, max_cycles=20,
+                           X=None, raise_on_error=True):
+        """Block GCRO-DR at (s, p) (or the coefficient vector s when p is None), using
+        and then updating ``recycler``'s recycled basis."""
+        n, k = B.shape
+        if X is None:
+            X = torch.empty((n, k), dtype=torch.float64, device=B.device)
+        st = L.Stats()
+        o = L.SolveOpts(m, max_cycles, tol)
+        sh = spai.handle if spai is not None else None
+        if _is_coef(s, p):
+            rc = L.block_solve_gcrodr_c(self.handle, sh, _coef(s, self), B.data_ptr(), B.stride(0), k, X.data_ptr(),
+                                        X.stride(0), C.byref(o), recycler.handle, C.byref(st))
+        else:
+            rc = L.block_solve_gcrodr(self.handle, sh, float(s), float(p), B.data_ptr(), B.stride(0), k,
+                                      X.data_ptr(), X.stride(0), C.byref(o), recycler.handle, C.byref(st))
+        if raise_on_error:
+            L.check(rc, "block_solve_gcrodr")
+        return X, st.as_dict(), rc
+
     def sequence_solve(self, B, s_list: Sequence[float] = None, p_list: Sequence[float] = None, policy="update",
                        pattern=None, precision="f64", update="diag", m=30, tol=1e-8, max_cycles=20, X=None,
                        raise_on_error=True, approach="first", reanchor_tol=0.0, adapt_ep=0.0, coefs=None):
@@ -388,6 +408,43 @@ class Spai:
     def close(self):
         if self.handle:
             L.spai_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Recycler:
+    """The recycled subspace of block GCRO-DR, carried across solves (pmor_recycle_*)."""
+
+    def __init__(self, ctx: Context, n: int, kr: int):
+        self.ctx = ctx
+        self.n, self.kr = n, kr
+        h = C.c_void_p()
+        L.check(L.pmor_recycle_create(ctx.handle, n, kr, C.byref(h)), "pmor_recycle_create")
+        self.handle = h
+
+    @property
+    def dim(self) -> int:
+        kc = C.c_int32()
+        L.check(L.pmor_recycle_info(self.handle, C.byref(kc)), "pmor_recycle_info")
+        return kc.value
+
+    def reset(self):
+        L.check(L.pmor_recycle_reset(self.handle), "pmor_recycle_reset")
+
+    def export(self) -> torch.Tensor:
+        kc = self.dim
+        U = torch.empty((self.n, max(kc, 1)), dtype=torch.float64, device=self.ctx.device)
+        L.check(L.pmor_recycle_export(self.handle, U.data_ptr(), U.stride(0)), "pmor_recycle_export")
+        return U[:, :kc]
+
+    def close(self):
+        if self.handle:
+            L.pmor_recycle_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libpmorspai.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["memory.hip", "pattern.hip", "spai.hip", "krylov.hip", "api.hip"]
+SOURCES = ["memory.hip", "pattern.hip", "spai.hip", "krylov.hip", "recycle.hip", "api.hip"]
 ARCH = os.environ.get("PMOR_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code on purpose.

@@ -112,6 +112,16 @@ _SIGS = {
     "spai_free": (None, [P]),
     "block_solve": (C.c_int, [P, P, D, D, P, I64, I32, P, I64, C.POINTER(SolveOpts), C.POINTER(Stats)]),
     "block_solve_c": (C.c_int, [P, P, C.POINTER(D), P, I64, I32, P, I64, C.POINTER(SolveOpts), C.POINTER(Stats)]),
+    "pmor_recycle_create": (C.c_int, [P, I32, I32, PP]),
+    "pmor_recycle_destroy": (None, [P]),
+    "pmor_recycle_info": (C.c_int, [P, C.POINTER(I32)]),
+    "pmor_recycle_reset": (C.c_int, [P]),
+    "pmor_recycle_export": (C.c_int, [P, P, I64]),
+    "block_solve_gcrodr": (C.c_int, [P, P, D, D, P, I64, I32, P, I64, C.POINTER(SolveOpts), P, C.POINTER(Stats)]),
+    "block_solve_gcrodr_c": (C.c_int, [P, P, C.POINTER(D), P, I64, I32, P, I64, C.POINTER(SolveOpts), P,
+                                       C.POINTER(Stats)]),
+    "pmor_harmonic_ritz": (C.c_int, [I32, I32, C.POINTER(D), C.POINTER(D), I32, C.POINTER(D), C.POINTER(D),
+                                     C.POINTER(D), C.POINTER(I32)]),
     "pmor_batch_solve": (C.c_int, [P, C.POINTER(BatchItem), I32, C.POINTER(SolveOpts), C.POINTER(Stats),
                                    C.POINTER(I32)]),
     "pmor_sequence_solve": (C.c_int, [P, P, I64, I32, P, P, I32, P, I64, I32, C.POINTER(SpaiOpts),
