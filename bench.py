@@ -441,6 +441,8 @@ def main():
                                     "steps_per_point_adaptive_ep0.02": st_adapt["0.02"],
                                     "first_update_misfit_max": max(misfit) if misfit else 0.0,
                                     "first_update_misfit_last": misfit[-1] if misfit else 0.0}
+        _note("block GCRO-DR")
+        out["gcrodr_pointwise"] = gcrodr_bench(ctx, factory, job, B)
         out["update_vs_rebuild"] = value / arms["rebuild_batched"][0]
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
@@ -567,6 +569,64 @@ def serve_bench(ctx, rhos, n_jobs, n_cal=12, alone=5, engine_rows=40_000_000, se
             rep["rho"][str(rho)]["alone_vs_mix_bitwise"] = {"jobs": len(same), "equal": all(same)}
     cache.clear()
     return rep
+
+
+def gcrodr_bench(ctx, factory, job, B, configs=((30, 0, "spai"), (30, 8, "spai"), (10, 0, "spai"), (10, 8, "spai"),
+                                                 (10, 0, "none"), (10, 8, "none")), none_points=5):
+    """The sequence solved point by point with block GCRO-DR (SPAI at the first
+    point and the U-diag update, or no preconditioner on the first
+    ``none_points`` points), the recycled basis carried from point to point, for
+    restart lengths m and recycled dimensions kr (kr = 0: no recycling).  The
+    Gram and product kernels are timed live in the (m = 30, kr = 8) run."""
+    import torch
+    from paper_1809_06574_amd import Recycler, lib as L
+
+    def one(m, kr, prec, prof=0):
+        pb = factory()
+        rec = Recycler(ctx, job.n, kr)
+        X = torch.empty_like(B)
+        steps, cyc, rcs = [], [], []
+        pts = job.p_list if prec == "spai" else job.p_list[:none_points]
+        if prof:
+            L.check(L.pmor_prof_set(ctx.handle, prof), "prof_set")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = pb.spai_build(job.s, pts[0]) if prec == "spai" else None
+        for l, p in enumerate(pts):
+            if l and h is not None:
+                h.update(job.s, p)
+            _, st, rc = pb.block_solve_gcrodr(h, job.s, p, B, rec, m=m, tol=1e-8, max_cycles=64, X=X,
+                                              raise_on_error=False)
+            steps.append(st["steps"])
+            cyc.append(st["cycles"])
+            rcs.append(rc)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        prof_out = None
+        if prof:
+            prof_out = _prof_read(L, ctx)
+            L.check(L.pmor_prof_set(ctx.handle, 0), "prof_set")
+        rec.close()
+        if h is not None:
+            h.close()
+        pb.close()
+        return t, steps, cyc, rcs, len(pts), prof_out
+
+    one(*configs[0])  # untimed: first-call allocations and kernel loads
+    out = {}
+    for m, kr, prec in configs:
+        t, steps, cyc, rcs, npts, _ = one(m, kr, prec)
+        out[f"m{m}_kr{kr}_{prec}"] = {"solves_per_s": npts / t, "points": npts, "steps_per_point": steps,
+                                      "cycles_per_point": cyc, "total_steps": sum(steps),
+                                      "all_converged": all(r == 0 for r in rcs)}
+    kern = {}
+    for name, kid in L.PROF_GCRO.items():
+        _, _, _, _, _, (nl, ms, by) = one(30, 8, "spai", prof=kid)
+        gbs = by / max(ms * 1e-3, 1e-12) / 1e9
+        kern[name] = {"launches": nl, "avg_us": 1e3 * ms / max(nl, 1), "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                      "bytes_per_launch": by / max(nl, 1)}
+    out["kernels_m30_kr8"] = kern
+    return out
 
 
 def _c2_system(i):

@@ -547,6 +547,8 @@ int pmor_spai_gather(const pmor_spai* h, double* colsum);
 #define PMOR_PROF_SPMM_P 5        /* Z = P V_j, V_j = W1 R2^-1 written: 12 nnzP + 4(n+1) + 24 n kp */
 #define PMOR_PROF_CGS_UPD_GRAM 6  /* pass 3: W -= V H2; W R1^-1; Gram: 8 n kp (nblk + 2) */
 #define PMOR_PROF_SPAI_GATHER 7   /* gather only (pmor_spai_gather): 12 nnz + 4 n + 4 (sum|I_j| + nnzP) + 8 n */
+#define PMOR_PROF_GCRO_GRAM 8     /* block GCRO-DR Gram product [.]^T W (first stage): 8 n (a + b) */
+#define PMOR_PROF_GCRO_GEMM 9     /* block GCRO-DR product Y = beta Y + alpha A G: 8 n (a + b) (+ 8 n b read when beta != 0) */
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id);
 int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
 

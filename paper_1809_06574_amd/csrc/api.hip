@@ -1843,7 +1843,7 @@ int pmor_spai_gather(const pmor_spai* h, double* colsum) {
 
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id) {
   if (!ctx) return fail(PMOR_EINVAL, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > PMOR_PROF_SPAI_GATHER) return fail(PMOR_EINVAL, "unknown kernel id");
+  if (kernel_id < 0 || kernel_id > PMOR_PROF_GCRO_GEMM) return fail(PMOR_EINVAL, "unknown kernel id");
   prof_collect(ctx);
   ctx->prof.kernel = kernel_id;
   ctx->prof.launches = 0;

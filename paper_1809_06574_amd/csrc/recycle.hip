@@ -38,24 +38,26 @@ namespace pmor {
 // ---------------------------------------------------------------------------
 // device kernels
 // ---------------------------------------------------------------------------
-constexpr int GRAM_ROWS = 8;   // rows staged in LDS per tile
-constexpr int GRAM_GRID = 240;  // workgroups of the first stage (at most)
+constexpr int GRAM_LDS = 32 * 1024;         // bytes of a row tile staged in LDS
+constexpr int64_t GRAM_PART_MAX = 1 << 22;  // doubles of first-stage partial sums (at most)
 
-// part[g][p] = sum over the rows of workgroup g of A[i, p / b] W[i, p % b]
+// part[g][p] = sum over the rows of workgroup g of A[i, p / b] W[i, p % b];
+// the rows go through LDS in tiles of tr rows (every thread loads several
+// values of a tile before the barrier, which keeps many loads in flight)
 template <int PPT>
 __global__ __launch_bounds__(256) void k_gram_part(int64_t n, const double* __restrict__ A, int64_t lda, int a,
                                                    const double* __restrict__ W, int64_t ldw, int b, int64_t per,
-                                                   double* __restrict__ part) {
+                                                   int tr, double* __restrict__ part) {
   extern __shared__ double sh[];
   const int w = a + b, ab = a * b;
   double acc[PPT];
 #pragma unroll
   for (int q = 0; q < PPT; ++q) acc[q] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
-  for (int64_t base = r0; base < r1; base += GRAM_ROWS) {
-    const int nr = (int)min((int64_t)GRAM_ROWS, r1 - base);
+  for (int64_t base = r0; base < r1; base += tr) {
+    const int nr = (int)min((int64_t)tr, r1 - base);
     __syncthreads();
-    for (int t = threadIdx.x; t < GRAM_ROWS * w; t += 256) {
+    for (int t = threadIdx.x; t < tr * w; t += 256) {
       const int rr = t / w, cc = t - rr * w;
       double v = 0.0;
       if (rr < nr) v = cc < a ? A[(base + rr) * lda + cc] : W[(base + rr) * ldw + (cc - a)];
@@ -68,8 +70,7 @@ __global__ __launch_bounds__(256) void k_gram_part(int64_t n, const double* __re
       if (p < ab) {
         const int ia = p / b, ib = p - ia * b;
         double s = acc[q];
-#pragma unroll
-        for (int rr = 0; rr < GRAM_ROWS; ++rr) s = fma(sh[rr * w + ia], sh[rr * w + a + ib], s);
+        for (int rr = 0; rr < nr; ++rr) s = fma(sh[rr * w + ia], sh[rr * w + a + ib], s);
         acc[q] = s;
       }
     }
@@ -81,13 +82,17 @@ __global__ __launch_bounds__(256) void k_gram_part(int64_t n, const double* __re
   }
 }
 
-// out[p] = sum_g part[g][p], g in order
-__global__ void k_gram_reduce(int G, int ab, const double* __restrict__ part, double* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ab) return;
+// out[p] = sum_g part[g][p]: 16 lanes per p, lane l summing g = l, l + 16, ...
+// in order, then a fixed butterfly over the 16 lanes (the same order every call)
+__global__ __launch_bounds__(256) void k_gram_reduce(int G, int ab, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  const int p = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
   double s = 0.0;
-  for (int g = 0; g < G; ++g) s += part[(int64_t)g * ab + p];
-  out[p] = s;
+  if (p < ab)
+    for (int g = l; g < G; g += 16) s += part[(int64_t)g * ab + p];
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (p < ab && l == 0) out[p] = s;
 }
 
 // Y = beta Y + alpha A G (A: n x a, G: a x b row-major in LDS; beta 0 reads no Y)
@@ -560,11 +565,12 @@ struct Work {
   double* Bs = nullptr;           // n x LB: C at columns [kr - kc, kr), V_j at [kr + j k, kr + (j + 1) k)
   double* U = nullptr;            // n x max(kr, 1): U in its first kc columns
   double *Wt = nullptr, *Z = nullptr, *Z2 = nullptr, *tC = nullptr, *tU = nullptr;
-  double* part = nullptr;         // GRAM_GRID x max a b
+  double* part = nullptr;         // first-stage partial sums of the Gram products
   double* dsm = nullptr;          // device small matrices: SLOTS x slot
   double* hsm = nullptr;          // pinned: SLOTS x slot
   int64_t slot = 0;
   static constexpr int SLOTS = 8;
+  bool pend[SLOTS] = {};          // an upload from the slot's pinned buffer may still be in flight
   std::vector<void*> dev;
   ~Work() {
     for (void* p : dev) dfree(p, st);
@@ -588,7 +594,8 @@ int alloc(Work& w) {
   w.slot = w.LB * wmax + 64;
   const bool ok = al(&w.Bs, w.n * w.LB) && al(&w.U, w.n * krp) && al(&w.Wt, w.n * w.k) && al(&w.Z, w.n * w.k) &&
                   al(&w.Z2, w.n * w.k) && al(&w.tC, w.n * krp) && al(&w.tU, w.n * krp) &&
-                  al(&w.part, (int64_t)GRAM_GRID * w.LB * wmax) && al(&w.dsm, Work::SLOTS * w.slot);
+                  al(&w.part, std::min<int64_t>(GRAM_PART_MAX, 1024 * w.LB * wmax)) &&
+                  al(&w.dsm, Work::SLOTS * w.slot);
   if (!ok) return fail(PMOR_ENOMEM, "allocation of the recycling solver's buffers failed");
   if (hipHostMalloc((void**)&w.hsm, sizeof(double) * Work::SLOTS * w.slot, hipHostMallocDefault) != hipSuccess) {
     w.hsm = nullptr;
@@ -599,24 +606,37 @@ int alloc(Work& w) {
 }
 
 // out (a x b, device) = A^T W over n rows
+// workgroups of a Gram product with ab outputs: about one per 256 rows, at
+// most 1024, and at most GRAM_PART_MAX partial sums
+int gram_groups(int64_t n, int ab) {
+  int64_t G = std::min<int64_t>(1024, (n + 255) / 256);
+  G = std::min<int64_t>(G, std::max<int64_t>(1, GRAM_PART_MAX / std::max(ab, 1)));
+  return (int)std::max<int64_t>(G, 1);
+}
+
 int gram(Work& w, const double* A, int64_t lda, int a, const double* W, int64_t ldw, int b, double* out) {
   const int ab = a * b;
   if (ab == 0) return PMOR_OK;
-  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(GRAM_GRID, (w.n + 255) / 256));
+  const int G = gram_groups(w.n, ab);
   const int64_t per = (w.n + G - 1) / G;
-  const size_t lds = sizeof(double) * GRAM_ROWS * (a + b);
+  const int tr = std::max(1, std::min(64, GRAM_LDS / (int)(sizeof(double) * (a + b))));
+  const size_t lds = sizeof(double) * (size_t)tr * (a + b);
   const int ppt = (ab + 255) / 256;
+  if (ppt > 36) return fail(PMOR_EINVAL, "Gram product too wide");
+  const int pr = prof_start(w.ctx, PMOR_PROF_GCRO_GRAM);
   if (ppt <= 2) {
-    hipLaunchKernelGGL(k_gram_part<2>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, w.part);
+    plaunch(w.ctx, pr, 3, k_gram_part<2>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, tr, w.part);
   } else if (ppt <= 8) {
-    hipLaunchKernelGGL(k_gram_part<8>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, w.part);
-  } else if (ppt <= 36) {
-    hipLaunchKernelGGL(k_gram_part<36>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, w.part);
+    plaunch(w.ctx, pr, 3, k_gram_part<8>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, tr, w.part);
   } else {
-    return fail(PMOR_EINVAL, "Gram product too wide");
+    plaunch(w.ctx, pr, 3, k_gram_part<36>, dim3(G), dim3(256), lds, w.st, w.n, A, lda, a, W, ldw, b, per, tr,
+            w.part);
   }
   PMOR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 255) / 256)), dim3(256), 0, w.st, G, ab, w.part, out);
+  // algorithmic bytes: the n rows of A's a and W's b columns (W among A's columns is read once)
+  const bool w_in_a = lda == ldw && W >= A && W + b <= A + a;
+  prof_stop(w.ctx, pr, 8.0 * w.n * (w_in_a ? a : a + b), 0);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 15) / 16)), dim3(256), 0, w.st, G, ab, w.part, out);
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }
@@ -640,9 +660,11 @@ int tall_gemm(Work& w, const double* A, int64_t lda, int a, const double* G, int
     PMOR_TRY(allow_lds(reinterpret_cast<const void*>(k_tall_gemm), 160 * 1024));
     big_lds = true;
   }
-  hipLaunchKernelGGL(k_tall_gemm, dim3((unsigned)((w.n + rows - 1) / rows)), dim3(256), lds, w.st, w.n, A, lda, a, G,
-                     b, alpha, beta, Y, ldy);
+  const int pr = prof_start(w.ctx, PMOR_PROF_GCRO_GEMM);
+  plaunch(w.ctx, pr, 3, k_tall_gemm, dim3((unsigned)((w.n + rows - 1) / rows)), dim3(256), lds, w.st, w.n, A, lda, a,
+          G, b, alpha, beta, Y, ldy);
   PMOR_HIP(hipGetLastError());
+  prof_stop(w.ctx, pr, 8.0 * w.n * (a + b + (beta != 0.0 ? b : 0)), 0);
   return PMOR_OK;
 }
 
@@ -659,13 +681,18 @@ int down(Work& w, int s, const double* dev, int64_t cnt) {
   PMOR_HIP(hipMemcpyAsync(w.hs(s), dev, sizeof(double) * cnt, hipMemcpyDeviceToHost, w.st));
   return PMOR_OK;
 }
-int up(Work& w, int s, const double* host, int64_t cnt) {
-  std::memcpy(w.hs(s), host, sizeof(double) * cnt);
-  PMOR_HIP(hipMemcpyAsync(w.ds(s), w.hs(s), sizeof(double) * cnt, hipMemcpyHostToDevice, w.st));
-  return PMOR_OK;
-}
 int sync(Work& w) {
   PMOR_HIP(hipStreamSynchronize(w.st));
+  for (bool& p : w.pend) p = false;
+  return PMOR_OK;
+}
+// small matrix to the device through the slot's pinned buffer (which is not
+// rewritten while an earlier upload from it may still be in flight)
+int up(Work& w, int s, const double* host, int64_t cnt) {
+  if (w.pend[s]) PMOR_TRY(sync(w));
+  std::memcpy(w.hs(s), host, sizeof(double) * cnt);
+  PMOR_HIP(hipMemcpyAsync(w.ds(s), w.hs(s), sizeof(double) * cnt, hipMemcpyHostToDevice, w.st));
+  w.pend[s] = true;
   return PMOR_OK;
 }
 
@@ -858,27 +885,51 @@ int gcrodr_solve(pmor_problem* pb, const pmor_spai* h, const Point& pt, const do
         Zin = w.Z;
         ldz = k;
       }
-      PMOR_TRY(op.apply_A(w, Zin, ldz, w.Wt, k, k, 1.0, 0.0, nullptr, 0));
-      PMOR_TRY(gram(w, w.Wt, k, k, w.Wt, k, k, w.ds(5)));  // norms before Gram-Schmidt
-      PMOR_TRY(down(w, 5, w.ds(5), (int64_t)k * k));
+      // W lands in the slot of V_{j+1}, right after [C, V_0..V_j], so that each
+      // pass's Gram product [C, V, W]^T W also yields W^T W
+      double* Wj = w.V(j + 1);
+      PMOR_TRY(op.apply_A(w, Zin, ldz, Wj, LB, k, 1.0, 0.0, nullptr, 0));
       const int nb = kc + (j + 1) * k;  // [C, V_0..V_j]
       const double* basis = w.Bs + (kr - kc);
       for (int pass = 0; pass < 2; ++pass) {
-        PMOR_TRY(gram(w, basis, LB, nb, w.Wt, k, k, w.ds(1 + pass)));
-        PMOR_TRY(tall_gemm(w, basis, LB, nb, w.ds(1 + pass), k, -1.0, 1.0, w.Wt, k));
-        PMOR_TRY(down(w, 1 + pass, w.ds(1 + pass), (int64_t)nb * k));
+        PMOR_TRY(gram(w, basis, LB, nb + k, Wj, LB, k, w.ds(1 + pass)));
+        PMOR_TRY(tall_gemm(w, basis, LB, nb, w.ds(1 + pass), k, -1.0, 1.0, Wj, LB));
+        PMOR_TRY(down(w, 1 + pass, w.ds(1 + pass), (int64_t)(nb + k) * k));
       }
-      PMOR_TRY(gram(w, w.Wt, k, k, w.Wt, k, k, w.ds(0)));
-      PMOR_TRY(down(w, 0, w.ds(0), (int64_t)k * k));
       PMOR_TRY(sync(w));
-      double wscale = 0.0;
-      for (int c = 0; c < k; ++c) wscale = std::max(wscale, std::sqrt(std::max(w.hs(5)[c * k + c], 0.0)));
+      const double* g1 = w.hs(1);
+      const double* g2 = w.hs(2);
+      double wscale = 0.0;  // max ||W_c|| before Gram-Schmidt
+      for (int c = 0; c < k; ++c) wscale = std::max(wscale, std::sqrt(std::max(g1[(nb + c) * k + c], 0.0)));
       for (int r = 0; r < nb; ++r)
-        for (int c = 0; c < k; ++c) hc[(size_t)r * k + c] = w.hs(1)[r * k + c] + w.hs(2)[r * k + c];
-      std::vector<double> gw(w.hs(0), w.hs(0) + (size_t)k * k);
-      std::vector<double> Hd;
-      bool okq = false;
-      PMOR_TRY(cholqr2(w, w.Wt, k, k, w.V(j + 1), LB, gw.data(), Hd, &okq));
+        for (int c = 0; c < k; ++c) hc[(size_t)r * k + c] = g1[r * k + c] + g2[r * k + c];
+      // W^T W after the second pass: (W1 - Q H2)^T (W1 - Q H2) = W1^T W1 - H2^T H2 for orthonormal Q
+      std::vector<double> gw((size_t)k * k);
+      for (int a = 0; a < k; ++a)
+        for (int c = 0; c < k; ++c) {
+          double v = g2[(nb + a) * k + c];
+          for (int r = 0; r < nb; ++r) v -= g2[r * k + a] * g2[r * k + c];
+          gw[(size_t)a * k + c] = v;
+        }
+      // Cholesky QR twice: T1 = W R1^{-1} (into Wt), V_{j+1} = T1 R2^{-1}, H_{j+1,j} = R2 R1
+      std::vector<double> Hd((size_t)k * k, 0.0), R1((size_t)k * k), R1i((size_t)k * k), R2((size_t)k * k),
+          R2i((size_t)k * k);
+      bool okq = dense::chol_upper(k, gw.data(), R1.data());
+      if (okq) {
+        dense::inv_upper(k, R1.data(), R1i.data());
+        PMOR_TRY(up(w, 3, R1i.data(), (int64_t)k * k));
+        PMOR_TRY(tall_gemm(w, Wj, LB, k, w.ds(3), k, 1.0, 0.0, w.Wt, k));
+        PMOR_TRY(gram(w, w.Wt, k, k, w.Wt, k, k, w.ds(0)));
+        PMOR_TRY(down(w, 0, w.ds(0), (int64_t)k * k));
+        PMOR_TRY(sync(w));
+        okq = dense::chol_upper(k, w.hs(0), R2.data());
+      }
+      if (okq) {
+        dense::inv_upper(k, R2.data(), R2i.data());
+        PMOR_TRY(up(w, 4, R2i.data(), (int64_t)k * k));
+        PMOR_TRY(tall_gemm(w, w.Wt, k, k, w.ds(4), k, 1.0, 0.0, Wj, LB));
+        dense::matmul(k, k, k, R2.data(), R1.data(), Hd.data());
+      }
       bool deficient = !okq;
       for (int c = 0; okq && c < k; ++c) {
         if (!(std::fabs(Hd[c * k + c]) > 1e-14 * wscale)) deficient = true;

@@ -33,6 +33,7 @@ PMOR_REBUILD, PMOR_UPDATE = 0, 1
 PMOR_APPROACH_FIRST, PMOR_APPROACH_SECOND = 0, 1
 PROF_KERNELS = {"spmm_a": 1, "cgs_upd_dot": 2, "cgs_dot": 3, "spai_ls": 4, "spmm_p": 5, "cgs_upd_gram": 6}
 PROF_SPAI_GATHER = 7
+PROF_GCRO = {"gcro_gram": 8, "gcro_gemm": 9}
 
 
 class Csr(C.Structure):

@@ -172,3 +172,34 @@ def test_c1_least_squares_precisions(c1, prec):
     Xh, X64h = np_(X), np_(X64)
     _check_residuals(job, asm, Xh)
     assert np.linalg.norm(Xh - X64h) / np.linalg.norm(X64h) <= 1e-6
+
+
+def test_c1_block_gcrodr_sequence_properties(c1):
+    """Block GCRO-DR over the first six points at full size, as the benchmark's
+    (m = 30, kr = 8) run solves them: every column's true residual <= 1e-8, and
+    after each point the recycled basis U~ satisfies the recycling invariant of
+    that point, C = A(l) P_l U~ with orthonormal columns (||C^T C - I|| <= 1e-8),
+    with the recycled dimension at most kr."""
+    from paper_1809_06574_amd import Recycler
+    job, asm, pb, B = c1
+    ctx = pb.ctx
+    rec = Recycler(ctx, job.n, 8)
+    h = pb.spai_build(job.s, job.p_list[0])
+    bn = np.linalg.norm(job.B, axis=0)
+    for l, p in enumerate(job.p_list[:6]):
+        if l:
+            h.update(job.s, p)
+        X, st, rc = pb.block_solve_gcrodr(h, job.s, p, B, rec, m=30, tol=1e-8)
+        assert rc == 0
+        A = to_scipy(job.n, asm.rowptr, asm.col, asm.values(job.s, p))
+        rel = np.linalg.norm(job.B - A @ np_(X), axis=0) / bn
+        assert np.all(rel <= 1e-8 * 1.0001), (l, rel)
+        kc = rec.dim
+        assert 0 < kc <= 8
+        e = h.export()
+        P = to_scipy(job.n, np_(e["rowptr"]), np_(e["col"]), np_(e["val"]))
+        U = np_(rec.export())
+        C = A @ (P @ U)
+        assert np.abs(C.T @ C - np.eye(kc)).max() <= 1e-8, l
+    rec.close()
+    h.close()
