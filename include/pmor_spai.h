@@ -256,6 +256,24 @@ int spai_build(pmor_problem* pb, double s, double p, const pmor_spai_opts* opts,
  * pmor_problem_create_affine). */
 int spai_build_c(pmor_problem* pb, const double* coef, const pmor_spai_opts* opts,
                  pmor_spai** out, pmor_stats* stats);
+/* P_1 of several problems, each at its own point, with the least squares of
+ * all of them in shared launches (Section 2.2: every column of every system is
+ * a problem of its own): one launch per (|J|, |I|) bucket over the bucket's
+ * columns of all systems.  Per item: pb (of ctx), the point coef (host, or NULL
+ * for (s, p)), opts (may be NULL; every item the same precision); out: h (the
+ * handle, also on PMOR_ESINGULAR as spai_build returns it), status and
+ * bad_column.  Each handle is bit for bit the one spai_build gives.  Returns
+ * PMOR_OK or the first item's failure; synchronises the stream. */
+typedef struct pmor_spai_build_item {
+  pmor_problem* pb;
+  double s, p;
+  const double* coef;
+  const pmor_spai_opts* opts;
+  pmor_spai* h;         /* out */
+  int32_t status;       /* out */
+  int32_t bad_column;   /* out */
+} pmor_spai_build_item;
+int spai_build_batch(pmor_ctx* ctx, pmor_spai_build_item* items, int32_t count);
 /* Update at (s,p) (Table 1).  First approach: Q = argmin ||A(1) - A(s,p) Q||_F
  * on the handle's update pattern, then P = Q P_1 (anchor unchanged).  Second
  * approach (U-diag only): q = argmin ||A(prev) - A(s,p) diag(q)||_F, A(prev)

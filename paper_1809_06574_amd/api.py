@@ -6,6 +6,7 @@ update and block GMRES runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes as C
+import types
 from typing import Dict, Optional, Sequence
 
 import torch
@@ -270,6 +271,38 @@ class Problem:
         return X, [s.as_dict() for s in stats], rc
 
 
+def spai_build_batch(ctx: Context, items, precision="f64", update="diag", raise_on_error=True):
+    """P_1 of several problems with the least squares of all in shared launches
+    (spai_build_batch).  ``items``: ``(problem, s, p)`` or ``(problem, s, p, pattern)``
+    with p None meaning s is a coefficient vector.  Returns (list of Spai or None,
+    list of status codes, rc)."""
+    n_it = len(items)
+    arr = (L.SpaiBuildItem * max(n_it, 1))()
+    keep = []
+    for i, itm in enumerate(items):
+        pb, s, p = itm[:3]
+        pattern = itm[3] if len(itm) > 3 else None
+        holder = types.SimpleNamespace()  # keeps the pattern tensors alive for the call
+        o = _spai_opts(pattern, precision, update, ctx.device, holder)
+        keep += [o, holder]
+        cf = None
+        if _is_coef(s, p):
+            cf = _coef(s, pb)
+            keep.append(cf)
+            s, p = 0.0, 0.0
+        arr[i] = L.SpaiBuildItem(pb.handle, float(s), float(p),
+                                 C.cast(cf, C.POINTER(C.c_double)) if cf is not None else None,
+                                 C.cast(C.pointer(o), C.c_void_p), None, 0, -1)
+    rc = L.spai_build_batch(ctx.handle, arr, n_it)
+    out, status = [], []
+    for i, itm in enumerate(items):
+        status.append(arr[i].status)
+        out.append(Spai(itm[0], None, None, update=update, _handle=C.c_void_p(arr[i].h)) if arr[i].h else None)
+    if raise_on_error:
+        L.check(rc, "spai_build_batch")
+    return out, status, rc
+
+
 def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_error=True):
     """Solve independent systems together (pmor_batch_solve).  ``items``: sequence of
     ``(problem, spai_or_None, s, p, B)`` or ``(problem, spai, s, p, B, X)``; with p None,
@@ -325,10 +358,17 @@ class Spai:
     default; approach="second" anchors each update at the previous point)."""
 
     def __init__(self, pb: Problem, s, p, pattern=None, precision="f64", update="diag", stats=False,
-                 approach="first", adapt_ep=0.0, imported=None):
+                 approach="first", adapt_ep=0.0, imported=None, _handle=None):
         self.pb = pb
         self.update_kind = update
         self.approach = approach
+        if _handle is not None:  # a handle the library built already (spai_build_batch)
+            self.handle = _handle
+            self.last_stats = None
+            nz, mj, mi = C.c_int32(), C.c_int32(), C.c_int32()
+            L.check(L.spai_info(self.handle, C.byref(nz), C.byref(mj), C.byref(mi)), "spai_info")
+            self.nnzP, self.maxJ, self.maxI = nz.value, mj.value, mi.value
+            return
         o = _spai_opts(pattern, precision, update, pb.ctx.device, self, approach, adapt_ep=adapt_ep)
         h = C.c_void_p()
         st = L.Stats()

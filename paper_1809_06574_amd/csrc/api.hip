@@ -707,6 +707,78 @@ static int spai_build_pt(pmor_problem* pb, const Point& pt, const pmor_spai_opts
   return rc;
 }
 
+// P_1 of several problems at their points with the least squares of all in
+// shared launches (pmor spai_build_batch); per item as spai_build_pt
+static int spai_build_batch_impl(pmor_ctx* ctx, pmor_spai_build_item* items, int32_t count) {
+  if (!ctx || (!items && count > 0)) return fail(PMOR_EINVAL, "NULL argument");
+  if (count < 0) return fail(PMOR_EINVAL, "count must not be negative");
+  PMOR_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  std::vector<pmor_spai*> hs;
+  std::vector<const double*> av;
+  std::vector<int> idx;
+  std::vector<Point> pts;
+  int prec = -1, first_rc = PMOR_OK;
+  auto item_fail = [&](int i, int rc) {
+    items[i].status = rc;
+    if (first_rc == PMOR_OK) first_rc = rc;
+  };
+  for (int i = 0; i < count; ++i) {
+    pmor_spai_build_item& it = items[i];
+    it.h = nullptr;
+    it.status = PMOR_OK;
+    it.bad_column = -1;
+    if (!it.pb) { item_fail(i, fail(PMOR_EINVAL, "item " + std::to_string(i) + ": problem is NULL")); continue; }
+    if (it.pb->ctx != ctx) { item_fail(i, fail(PMOR_EINVAL, "item " + std::to_string(i) + ": another context")); continue; }
+    Point pt{};
+    int rc = it.coef ? point_coef(it.pb, it.coef, &pt) : point_sp(it.pb, it.s, it.p, &pt);
+    const int pr = it.opts ? it.opts->precision : PMOR_F64;
+    if (rc == PMOR_OK && prec >= 0 && pr != prec) rc = fail(PMOR_EINVAL, "a batch takes one least-squares precision");
+    pmor_spai* h = nullptr;
+    if (rc == PMOR_OK) rc = spai_new(it.pb, it.opts, &h);
+    if (rc == PMOR_OK) rc = ensure_assembled(it.pb, pt);
+    if (rc == PMOR_OK) rc = dcopy(it.pb->aval, h->aval1, it.pb->nnz, st);
+    if (rc != PMOR_OK) {
+      if (h) spai_release(h);
+      item_fail(i, rc);
+      continue;
+    }
+    prec = pr;
+    hs.push_back(h);
+    av.push_back(h->aval1);
+    idx.push_back(i);
+    pts.push_back(pt);
+  }
+  int rc = run_spai_ls_multi(hs.data(), (int)hs.size(), av.data(), st);
+  for (size_t t = 0; t < hs.size() && rc == PMOR_OK; ++t) {
+    pmor_spai* h = hs[t];
+    rc = dcopy(h->P1val, h->Pval, h->nnzP, st);
+    if (rc == PMOR_OK) rc = to_sell(h->psell, h->P1val, h->P1val_s, st);
+    if (rc == PMOR_OK && h->opts.update == PMOR_UPD_DIAG) rc = unit_factors(h, st);
+    h->q_active = h->d_active = h->c_active = false;
+    h->pt1 = pts[t];
+  }
+  std::vector<int> bad(hs.size(), 0x7fffffff);
+  for (size_t t = 0; t < hs.size() && rc == PMOR_OK; ++t)
+    if (hipMemcpyAsync(&bad[t], hs[t]->red, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+      rc = fail(PMOR_EHIP, "copy failed");
+  if (rc == PMOR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
+  if (rc != PMOR_OK) {
+    for (pmor_spai* h : hs) spai_release(h);
+    return rc;
+  }
+  for (size_t t = 0; t < hs.size(); ++t) {
+    pmor_spai_build_item& it = items[idx[t]];
+    it.h = hs[t];  // on PMOR_ESINGULAR the handle is returned, as by spai_build
+    if (bad[t] != 0x7fffffff) {
+      it.bad_column = bad[t];
+      item_fail(idx[t], fail(PMOR_ESINGULAR, "rank-deficient least-squares problem in column " +
+                                                  std::to_string(bad[t]) + " (item " + std::to_string(idx[t]) + ")"));
+    }
+  }
+  return first_rc;
+}
+
 static int spai_update_pt(pmor_spai* h, const Point& pt, pmor_stats* stats) {
   pmor_problem* pb = h->pb;
   Timer ta(pb->ctx, stats != nullptr);
@@ -870,6 +942,10 @@ int spai_import_c(pmor_problem* pb, const double* coef, int32_t nnzP, const int3
   Point pt;
   PMOR_TRY(point_coef(pb, coef, &pt));
   return spai_import_pt(pb, pt, nnzP, rowptr, col, val, opts, out);
+}
+
+int spai_build_batch(pmor_ctx* ctx, pmor_spai_build_item* items, int32_t count) {
+  return spai_build_batch_impl(ctx, items, count);
 }
 
 int spai_info(const pmor_spai* h, int32_t* nnzP, int32_t* maxJ, int32_t* maxI) {

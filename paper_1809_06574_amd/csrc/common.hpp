@@ -312,6 +312,9 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
 int run_update_diag(pmor_spai* h, const double* aval_l, int32_t* bad_col, double* fro2);
 // the U-diag update of a complex problem (2x2 blocks of the real form): factors
 // into q (n: Re, Im per complex column), residuals into rho (n), P_l = Q P_1 into pl
+// the SPAI least squares of several handles (one stream, one precision) in
+// shared bucketed launches; aval[i] the values of handle i's matrix
+int run_spai_ls_multi(pmor_spai* const* hs, int count, const double* const* aval, hipStream_t st);
 // block GCRO-DR of one system at pt, carrying rec's recycled basis (recycle.hip)
 int gcrodr_solve(pmor_problem* pb, const pmor_spai* h, const Point& pt, const double* B, int64_t ldb, int k, double* X,
                  int64_t ldx, const pmor_solve_opts& o, pmor_recycle* rec, pmor_stats* stats);

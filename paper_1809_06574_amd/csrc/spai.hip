@@ -16,6 +16,9 @@
 
 #include <algorithm>
 
+#include <cstring>
+#include <vector>
+
 #include "common.hpp"
 
 namespace pmor {
@@ -58,7 +61,25 @@ struct LsArgs {
   double* out;     // values in P's CSR order
   double* rho;     // per-column residual norm
   int* bad_col;    // smallest singular column (atomicMin)
+  // several systems in one launch: the columns of system s are the launch's
+  // columns [seg[s], seg[s + 1]) (each system's count padded to whole
+  // wavefronts), described by sys[s]; null for a launch of one system
+  const LsArgs* sys;
+  const int32_t* seg;
+  int nsys;
 };
+
+// the system of a wavefront's columns in a launch over several systems (every
+// wavefront's columns belong to one system): largest s with seg[s] <= w0
+__device__ __forceinline__ int ls_system(const int32_t* seg, int nsys, int w0) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid] <= w0) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // ---------------------------------------------------------------------------
 // register kernel: 16 lanes (one DPP row) per column, four columns per
@@ -180,15 +201,23 @@ __device__ __forceinline__ Q16Scale q16_scale(float mx) {
 }
 __device__ __forceinline__ float q16(float x, Q16Scale q) { return __half2float(__float2half_rn(x * q.sc)) * q.isc; }
 
-template <typename T, int JMAX, int R, bool Q16 = false, int G = 16, bool GO = false>
-__global__ __launch_bounds__(256) void k_spai_reg(LsArgs a) {
+template <typename T, int JMAX, int R, bool Q16 = false, int G = 16, bool GO = false, bool MULTI = false>
+__global__ __launch_bounds__(256) void k_spai_reg(LsArgs a0) {
   static_assert(G == 16 || G == 32 || G == 64, "groups of one, two or four DPP rows");
   static_assert(JMAX <= G, "row k of R must sit in lane k of the group");
   constexpr int LG = G == 16 ? 4 : (G == 32 ? 5 : 6);
   const int gl = threadIdx.x & (G - 1);
   const int wid = (xcd_swizzle(blockIdx.x, gridDim.x) * 256 + threadIdx.x) >> LG;
-  if (wid >= a.ncols) return;  // whole groups leave together
-  const int j = a.cols ? a.cols[wid] : a.col_off + wid;
+  if (wid >= a0.ncols) return;  // whole groups leave together
+  LsArgs a = a0;
+  int wl = wid;
+  if constexpr (MULTI) {
+    const int sy = ls_system(a0.seg, a0.nsys, __builtin_amdgcn_readfirstlane(wid));
+    a = a0.sys[sy];
+    wl = wid - a0.seg[sy];
+    if (wl >= a.ncols) return;  // the padding of the system's last wavefront
+  }
+  const int j = a.cols ? a.cols[wl] : a.col_off + wl;
   const int jb = a.Jcolptr[j];
   const int nj = a.Jcolptr[j + 1] - jb;
   const int64_t ib = a.Icolptr[j];
@@ -423,8 +452,8 @@ __device__ __forceinline__ int lds_lower_bound(const int* rows, int len, int r) 
   return lo;
 }
 
-template <typename T, bool Q16 = false, bool GO = false>
-__global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
+template <typename T, bool Q16 = false, bool GO = false, bool MULTI = false>
+__global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
   extern __shared__ unsigned char smem_raw[];
   T* S = reinterpret_cast<T*>(smem_raw);  // column-major [nj + 1][ldI]: A_hat then rhs (JM >= nj)
   int* Is = reinterpret_cast<int*>(S + (size_t)(JM + 1) * ldI);  // the rows I_j
@@ -432,8 +461,16 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   __shared__ T sf[66];  // the reflector's factor per column
   const int lane = threadIdx.x;
   const int wid = blockIdx.x;
-  if (wid >= a.ncols) return;
-  const int j = a.cols ? a.cols[wid] : a.col_off + wid;
+  if (wid >= a0.ncols) return;
+  LsArgs a = a0;
+  int wl = wid;
+  if constexpr (MULTI) {
+    const int sy = ls_system(a0.seg, a0.nsys, wid);
+    a = a0.sys[sy];
+    wl = wid - a0.seg[sy];
+    if (wl >= a.ncols) return;
+  }
+  const int j = a.cols ? a.cols[wl] : a.col_off + wl;
   const int jb = a.Jcolptr[j];
   const int nj = a.Jcolptr[j + 1] - jb;
   const int64_t ib = a.Icolptr[j];
@@ -560,7 +597,15 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a, int ldI, int JM) {
   }
 }
 
-template <typename T, bool Q16 = false, bool GO = false>
+// columns per wavefront of bucket b's kernel for values of sizeof(T) bytes
+// (a launch over several systems pads each system's count to a multiple)
+static int bucket_cpw(int b, int tsize) {
+  if (b <= 4) return 4;
+  if (tsize == 4 && (b == 5 || b == 6)) return 2;
+  return 1;
+}
+
+template <typename T, bool Q16 = false, bool GO = false, bool MULTI = false>
 static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pmor_ctx* pc, int pidx, int part) {
   if (a.ncols == 0) return PMOR_OK;
   const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
@@ -570,26 +615,26 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
   // 256 registers for the block, so it takes the LDS kernel
   constexpr bool REG32 = sizeof(T) == 4;
   switch (b) {
-    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
-    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
-    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
-    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
-    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16, 16, GO>, dim3(g16), dim3(256), 0, st, a); break;
+    case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
+    case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
+    case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
+    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
+    case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 5:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32, GO>, dim3(g32), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32, GO, MULTI>, dim3(g32), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
     case 6:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 32, 4, Q16, 32, GO>, dim3(g32), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 32, 4, Q16, 32, GO, MULTI>, dim3(g32), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
     case 7:
       if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64, GO>, dim3(g64), dim3(256), 0, st, a);
+        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64, GO, MULTI>, dim3(g64), dim3(256), 0, st, a);
         break;
       }
       [[fallthrough]];
@@ -597,8 +642,9 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
       const int ldI = ((maxI + 7) / 8) * 8;
       const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI + sizeof(int) * (size_t)ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
-      PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16, GO>, shm));
-      plaunch(pc, pidx, part, k_spai_lds<T, Q16, GO>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a, ldI, maxJ);
+      PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16, GO, MULTI>, shm));
+      plaunch(pc, pidx, part, k_spai_lds<T, Q16, GO, MULTI>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a,
+              ldI, maxJ);
       break;
     }
     default: return fail(PMOR_EINVAL, "column outside the supported SPAI pattern sizes");
@@ -681,6 +727,107 @@ int run_spai_ls(pmor_spai* h, const double* aval, const double* rhs_aval, double
     if (fro2) *fro2 = hs;
   }
   return PMOR_OK;
+}
+
+// The least squares of several preconditioners in shared launches (Section 2.2:
+// every column is a problem of its own, whichever system it belongs to): per
+// bucket one launch over that bucket's columns of all systems, each system's
+// count padded to whole wavefronts so that a wavefront's columns share one
+// system.  hs: the handles (one stream, one precision); aval[i]: the values of
+// system i's matrix; results into each handle's P1val, rho and bad column
+// (its red[0], set here).
+int run_spai_ls_multi(pmor_spai* const* hs, int count, const double* const* aval, hipStream_t st) {
+  if (count <= 0) return PMOR_OK;
+  const int prec = hs[0]->opts.precision;
+  const int tsize = prec == PMOR_F64 ? 8 : 4;
+  std::vector<LsArgs> base(count);
+  for (int i = 0; i < count; ++i) {
+    pmor_spai* h = hs[i];
+    pmor_problem* pb = h->pb;
+    if (h->opts.precision != prec) return fail(PMOR_EINVAL, "a batch of least squares takes one precision");
+    int* dbad = reinterpret_cast<int*>(h->red);
+    PMOR_TRY(set_device_int(dbad, 0x7fffffff, st));
+    LsArgs& a = base[i];
+    a = LsArgs{};
+    a.rowptr = pb->rowptr; a.colidx = pb->col; a.aval = aval[i]; a.rhs_aval = nullptr;
+    a.Jcolptr = h->Jcolptr; a.Jrow = h->Jrow; a.Icolptr = h->Icolptr; a.Irow = h->Irow;
+    a.Pslot = h->Pslot; a.out = h->P1val; a.rho = h->rho; a.bad_col = dbad;
+    a.Acolptr = pb->colptr; a.Arowidx = pb->rowidx; a.Acscslot = pb->cscslot;
+  }
+  // per bucket: the systems' descriptions and the padded column offsets, packed
+  // into one device buffer
+  struct BucketLaunch {
+    int b, nsys, total, maxJ, maxI;
+    size_t off_sys, off_seg;
+  };
+  std::vector<BucketLaunch> bl;
+  std::vector<unsigned char> host;
+  auto align16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+  for (int b = 0; b < LS_BUCKETS; ++b) {
+    std::vector<LsArgs> sys;
+    std::vector<int32_t> seg{0};
+    int mj = 0, mi = 0;
+    const int cpw = bucket_cpw(b, tsize);
+    for (int i = 0; i < count; ++i) {
+      const pmor_spai* h = hs[i];
+      const int cnt = h->bucket_count[b];
+      if (cnt == 0) continue;
+      LsArgs a = base[i];
+      a.ncols = cnt;
+      a.cols = h->identity_order ? nullptr : h->bucket_cols + h->bucket_off[b];
+      a.col_off = 0;
+      sys.push_back(a);
+      const int64_t next = (int64_t)seg.back() + (cnt + cpw - 1) / cpw * cpw;
+      if (next >= ((int64_t)1 << 31)) return fail(PMOR_EINVAL, "too many least-squares columns in one batch");
+      seg.push_back((int32_t)next);
+      mj = std::max(mj, h->bucket_maxJ[b]);
+      mi = std::max(mi, h->bucket_maxI[b]);
+    }
+    if (sys.empty()) continue;
+    BucketLaunch L{b, (int)sys.size(), seg.back(), mj, mi, 0, 0};
+    L.off_sys = align16(host.size());
+    host.resize(L.off_sys + sizeof(LsArgs) * sys.size());
+    std::memcpy(host.data() + L.off_sys, sys.data(), sizeof(LsArgs) * sys.size());
+    L.off_seg = align16(host.size());
+    host.resize(L.off_seg + sizeof(int32_t) * seg.size());
+    std::memcpy(host.data() + L.off_seg, seg.data(), sizeof(int32_t) * seg.size());
+    bl.push_back(L);
+  }
+  if (bl.empty()) return PMOR_OK;
+  unsigned char* dev = nullptr;
+  PMOR_HIP(dmalloc((void**)&dev, host.size(), st));
+  // the descriptions are read by the launches below: a blocking copy, so the
+  // host buffer may go when this function returns
+  if (hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    dfree(dev, st);
+    return fail(PMOR_EHIP, "copy of the batch descriptions failed");
+  }
+  int rc = PMOR_OK;
+  pmor_ctx* ctx = hs[0]->pb->ctx;
+  const int pr = prof_start(ctx, PMOR_PROF_SPAI_LS);
+  double bytes = 0.0;  // the systems' least-squares bytes, as run_spai_ls counts them
+  for (int i = 0; i < count; ++i) {
+    const pmor_spai* h = hs[i];
+    const pmor_problem* pb = h->pb;
+    bytes += 12.0 * pb->nnz + 4.0 * pb->n + 4.0 * ((double)h->nI + h->nnzP) + 8.0 * h->nnzP + 8.0 * pb->n;
+  }
+  for (size_t t = 0; t < bl.size(); ++t) {
+    const BucketLaunch& L = bl[t];
+    const int part = (t == 0 ? 1 : 0) | (t + 1 == bl.size() ? 2 : 0);
+    LsArgs a0{};
+    a0.ncols = L.total;
+    a0.sys = reinterpret_cast<const LsArgs*>(dev + L.off_sys);
+    a0.seg = reinterpret_cast<const int32_t*>(dev + L.off_seg);
+    a0.nsys = L.nsys;
+    if (prec == PMOR_F32) rc = launch_bucket<float, false, false, true>(L.b, a0, L.maxJ, L.maxI, st, ctx, pr, part);
+    else if (prec == PMOR_F16S) rc = launch_bucket<float, true, false, true>(L.b, a0, L.maxJ, L.maxI, st, ctx, pr, part);
+    else rc = launch_bucket<double, false, false, true>(L.b, a0, L.maxJ, L.maxI, st, ctx, pr, part);
+    if (rc != PMOR_OK) break;
+  }
+  prof_stop(ctx, pr, bytes, 0);
+  dfree(dev, st);  // stream-ordered: reused only after the launches
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,7 +1193,9 @@ __global__ void k_assemble_pts(int64_t len, const int32_t* __restrict__ map, int
     for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = (e >= 0 && t < pc.nt) ? tval[(int64_t)t * nnz + e] : 0.0;
     for (int l = 0; l < pc.cnt; ++l) {
       double acc = 0.0;
-      for (int t = 0; t < pc.nt; ++t) acc += pc.c[l][t] * tv[t];
+      #pragma unroll
+      for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) acc += pc.c[l][t] * tv[t];
       out[(int64_t)l * ostride + q] = e >= 0 ? acc : 0.0;
     }
   }
@@ -1085,7 +1234,9 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
     for (int l = 0; l < PTS_MAX; ++l) {
       if (l < pc.cnt) {
         double x = 0.0;
-        for (int t = 0; t < pc.nt; ++t) x += pc.c[l][t] * tv[t];
+        #pragma unroll
+        for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) x += pc.c[l][t] * tv[t];
         num[l] += x * y;
         den[l] += x * x;
       }
@@ -1109,7 +1260,9 @@ __global__ void k_update_diag_pts(int n, const int32_t* colptr, const int32_t* c
     for (int l = 0; l < PTS_MAX; ++l) {
       if (l < pc.cnt) {
         double x = 0.0;
-        for (int t = 0; t < pc.nt; ++t) x += pc.c[l][t] * tv[t];
+        #pragma unroll
+        for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) x += pc.c[l][t] * tv[t];
         const double d = y - qv[l] * x;
         r2[l] += d * d;
       }
@@ -1164,12 +1317,16 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
 #pragma unroll
     for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     double y = 0.0;  // anchor value (point l0 - 1)
-    for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
+    #pragma unroll
+    for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) y += pc.c[0][t] * tv[t];
 #pragma unroll
     for (int l = 0; l < PTS_MAX; ++l) {
       if (l < pc.cnt) {
         double x = 0.0;
-        for (int t = 0; t < pc.nt; ++t) x += pc.c[l + 1][t] * tv[t];
+        #pragma unroll
+        for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) x += pc.c[l + 1][t] * tv[t];
         num[l] += x * y;
         den[l] += x * x;
         y = x;  // the next point's anchor
@@ -1189,12 +1346,16 @@ __global__ void k_update_diag_chain(int n, const int32_t* colptr, const int32_t*
 #pragma unroll
     for (int t = 0; t < PMOR_TMAX; ++t) tv[t] = t < pc.nt ? tval[(int64_t)t * nnz + s] : 0.0;
     double y = 0.0;
-    for (int t = 0; t < pc.nt; ++t) y += pc.c[0][t] * tv[t];
+    #pragma unroll
+    for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) y += pc.c[0][t] * tv[t];
 #pragma unroll
     for (int l = 0; l < PTS_MAX; ++l) {
       if (l < pc.cnt) {
         double x = 0.0;
-        for (int t = 0; t < pc.nt; ++t) x += pc.c[l + 1][t] * tv[t];
+        #pragma unroll
+        for (int t = 0; t < PMOR_TMAX; ++t)
+          if (t < pc.nt) x += pc.c[l + 1][t] * tv[t];
         const double d = y - qv[l] * x;
         r2[l] += d * d;
         y = x;

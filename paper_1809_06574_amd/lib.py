@@ -47,6 +47,11 @@ class SpaiOpts(C.Structure):
                 ("approach", C.c_int32), ("reanchor_tol", C.c_double), ("adapt_ep", C.c_double)]
 
 
+class SpaiBuildItem(C.Structure):
+    _fields_ = [("pb", C.c_void_p), ("s", C.c_double), ("p", C.c_double), ("coef", C.POINTER(C.c_double)),
+                ("opts", C.c_void_p), ("h", C.c_void_p), ("status", C.c_int32), ("bad_column", C.c_int32)]
+
+
 class SolveOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("max_cycles", C.c_int32), ("tol", C.c_double)]
 
@@ -101,6 +106,7 @@ _SIGS = {
     "pmor_assemble_c": (C.c_int, [P, C.POINTER(D), P]),
     "spai_build": (C.c_int, [P, D, D, C.POINTER(SpaiOpts), PP, C.POINTER(Stats)]),
     "spai_build_c": (C.c_int, [P, C.POINTER(D), C.POINTER(SpaiOpts), PP, C.POINTER(Stats)]),
+    "spai_build_batch": (C.c_int, [P, C.POINTER(SpaiBuildItem), I32]),
     "spai_update": (C.c_int, [P, D, D, C.POINTER(Stats)]),
     "spai_update_c": (C.c_int, [P, C.POINTER(D), C.POINTER(Stats)]),
     "spai_rebuild": (C.c_int, [P, D, D, C.POINTER(Stats)]),

@@ -156,3 +156,38 @@ def test_batch_power_law_systems(ctx):
     for (pb, h), job, X in zip(sys_[:2], jobs[:2], Xs[:2]):
         Xa, _, _ = pb.block_solve(h, job.s, job.p_list[1], torch.as_tensor(job.B, device="cuda"))
         assert torch.equal(Xa, X)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_spai_build_batch_equals_single_builds(ctx, precision):
+    """spai_build_batch (the least squares of all systems in shared bucketed
+    launches) gives every system bit for bit the P_1 of spai_build, for systems
+    of the batch workload with explicit power-law patterns (every bucket, the
+    LDS kernel included), a problem of roles and one problem at two points; an
+    item with a bad point fails alone."""
+    from paper_1809_06574_amd import Problem, spai_build_batch, lib as L
+    from synth.gen import config2_system
+    jobs = [config2_system(i) for i in (3, 17, 40)]
+    pbs = [Problem(ctx, j.terms) for j in jobs]
+    c0 = config0()
+    pc0 = Problem(ctx, c0.terms)
+    items = [(pb, j.s, j.p_list[0], j.pattern) for pb, j in zip(pbs, jobs)]
+    items += [(pc0, c0.s, c0.p_list[0]), (pc0, c0.s, c0.p_list[2])]
+    hs, status, rc = spai_build_batch(ctx, items, precision=precision)
+    assert rc == 0 and all(x == 0 for x in status)
+    for itm, h in zip(items, hs):
+        pb, s, p = itm[:3]
+        pat = itm[3] if len(itm) > 3 else None
+        g = pb.spai_build(s, p, pattern=pat, precision=precision)
+        e1, e2 = h.export(), g.export()
+        for key in ("rowptr", "col", "val", "rho"):
+            assert torch.equal(e1[key], e2[key]), key
+        # the batched handle solves and updates like any other
+        h.update(s, p + 0.02)
+        g.update(s, p + 0.02)
+        assert torch.equal(h.export()["val"], g.export()["val"])
+    bad = list(items[:2]) + [(pbs[0], float("nan"), 0.5)]
+    hs2, st2, rc2 = spai_build_batch(ctx, bad, precision=precision, raise_on_error=False)
+    assert rc2 == L.PMOR_EINVAL and st2[:2] == [0, 0] and st2[2] == L.PMOR_EINVAL and hs2[2] is None
+    fresh = pbs[0].spai_build(jobs[0].s, jobs[0].p_list[0], pattern=jobs[0].pattern, precision=precision)
+    assert torch.equal(hs2[0].export()["val"], fresh.export()["val"])
