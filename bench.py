@@ -447,6 +447,10 @@ def main():
         out["update_vs_plain"] = value / arms["plain_nonblock_rebuild"][0]
         out["batched_vs_pointwise_update"] = value / arms["update_pointwise"][0]
 
+    if not args.no_arms:
+        _note("complex points")
+        out["complex_points"] = complex_bench(ctx)
+
     kept = {}
     if not args.no_precisions:
         _note("least-squares precisions")
@@ -626,6 +630,62 @@ def gcrodr_bench(ctx, factory, job, B, configs=((30, 0, "spai"), (30, 8, "spai")
         kern[name] = {"launches": nl, "avg_us": 1e3 * ms / max(nl, 1), "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
                       "bytes_per_launch": by / max(nl, 1)}
     out["kernels_m30_kr8"] = kern
+    return out
+
+
+# (f^2, theta, d) of the complex points on the 64^3 grid: the small job's
+# frequencies divided by 100, which keeps them below the lowest resonance of
+# the grid's K, M pair (min eig M^-1 K falls with the mesh width squared)
+COMPLEX_POINTS_64 = ((2.25e-4, 0.5, 1.0), (2.25e-4, 0.5, 2.0), (2.0e-4, 0.3, 2.0), (1.5e-4, 0.3, 1.5))
+
+
+def complex_bench(ctx, dims=(64, 64, 64), k=4, steps=3, points=COMPLEX_POINTS_64):
+    """The gyroscope-shaped job at four complex points s = 2 pi f sqrt(-1) on a
+    dims grid, solved through the equivalent real form (order 2n): the sequence
+    with the complex U-diag update, all points together, right-hand sides
+    [R(B), R(iB)] (complex block GMRES on k complex columns)."""
+    import torch
+    from synth import gyro_complex_job
+    from paper_1809_06574_amd import Problem
+    job = gyro_complex_job(dims=dims, k=k, points=points)
+    dev = ctx.device
+    terms = [tuple(torch.as_tensor(x, device=dev) for x in (T.rowptr, T.col, T.val)) for T in job.aterms]
+    Bc = job.B
+    Bh = torch.as_tensor(np.hstack([np.stack([Bc.real, Bc.imag], 1).reshape(2 * job.n, k),
+                                    np.stack([-Bc.imag, Bc.real], 1).reshape(2 * job.n, k)]), device=dev)
+    pts = [list(c) for c in job.coefs]
+    X = torch.empty((len(pts), 2 * job.n, 2 * k), dtype=torch.float64, device=dev)
+    pb = Problem(ctx, terms, kinds=job.kinds)
+    _, st = pb.sequence_solve(Bh, coefs=pts, X=X)  # untimed: buffers and tuning
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = pb.sequence_solve(Bh, coefs=pts, X=X)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"n_complex": job.n, "n_real_form": pb.n, "nnz_real_form": pb.nnz, "k_complex": k, "points": len(pts),
+           "solves_per_s": steps * len(pts) / t, "steps_per_point": [s_["steps"] for s_ in st],
+           "relres_max": max(max(s_["relres"]) for s_ in st)}
+    # the same points one by one with block GCRO-DR (SPAI at the first point,
+    # the complex U-diag update), without and with a recycled subspace
+    from paper_1809_06574_amd import Recycler
+    for kr in (0, 16):
+        rec = Recycler(ctx, pb.n, kr)
+        Xp = torch.empty_like(Bh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = pb.spai_build(pts[0], None)
+        stp = []
+        for l, c in enumerate(pts):
+            if l:
+                h.update(c)
+            _, sg, _ = pb.block_solve_gcrodr(h, c, None, Bh, rec, m=30, tol=1e-8, max_cycles=64, X=Xp)
+            stp.append(sg["steps"])
+        torch.cuda.synchronize()
+        out[f"gcrodr_m30_kr{kr}"] = {"solves_per_s": len(pts) / (time.perf_counter() - t0), "steps_per_point": stp}
+        h.close()
+        rec.close()
+    pb.close()
     return out
 
 

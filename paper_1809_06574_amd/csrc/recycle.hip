@@ -311,89 +311,153 @@ struct HessLS {
 
 using cd = std::complex<double>;
 
-// Complex Schur form H = Z T Z^H of an upper Hessenberg matrix (n x n,
-// row-major, overwritten by T), by the shifted QR iteration with Wilkinson
-// shifts and Givens rotations; Z accumulated.  False when it does not converge.
-static bool schur(int n, std::vector<cd>& H, std::vector<cd>& Z) {
-  Z.assign((size_t)n * n, cd(0.0));
-  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+// Eigenvalues of an upper Hessenberg matrix H (n x n, row-major, destroyed)
+// by the Francis double-shift QR iteration in real arithmetic: a 3 x 3
+// Householder bulge is chased down the active window [l, hi], which shrinks as
+// subdiagonal entries become negligible; 1 x 1 and 2 x 2 diagonal blocks give
+// the eigenvalues (a conjugate pair as wr +- i wi, a real one with wi = 0).
+// Only the window is updated (no Schur vectors).  False when it does not
+// converge.
+static bool hess_eig(int n, double* H, double* wr, double* wi) {
+  auto h = [&](int r, int c) -> double& { return H[(size_t)r * n + c]; };
   double nrm = 0.0;
-  for (const cd& x : H) nrm += std::norm(x);
-  nrm = std::sqrt(nrm);
-  if (nrm == 0.0) return true;
+  for (int r = 0; r < n; ++r)
+    for (int c = std::max(0, r - 1); c < n; ++c) nrm += std::fabs(h(r, c));
   const double eps = 2.220446049250313e-16;
   int hi = n - 1, iter = 0;
-  std::vector<double> gc(n);
-  std::vector<cd> gs(n);
-  while (hi > 0) {
+  while (hi >= 0) {
     int l = hi;
     for (; l > 0; --l) {
-      double s = std::abs(H[(size_t)(l - 1) * n + l - 1]) + std::abs(H[(size_t)l * n + l]);
+      double s = std::fabs(h(l - 1, l - 1)) + std::fabs(h(l, l));
       if (s == 0.0) s = nrm;
-      if (std::abs(H[(size_t)l * n + l - 1]) <= eps * s) {
-        H[(size_t)l * n + l - 1] = 0.0;
+      if (std::fabs(h(l, l - 1)) <= eps * s) {
+        h(l, l - 1) = 0.0;
         break;
       }
     }
-    if (l == hi) {
+    if (l == hi) {  // a 1 x 1 block
+      wr[hi] = h(hi, hi);
+      wi[hi] = 0.0;
       --hi;
       iter = 0;
       continue;
     }
-    if (++iter > 60 * n) return false;
-    const cd a = H[(size_t)(hi - 1) * n + hi - 1], b = H[(size_t)(hi - 1) * n + hi];
-    const cd c = H[(size_t)hi * n + hi - 1], d = H[(size_t)hi * n + hi];
-    cd mu;
-    if (iter % 11 == 10) {  // an exceptional shift breaks a cycle of the iteration
-      mu = d + std::abs(c) * 0.75;
-    } else {
-      const cd half = 0.5 * (a - d);
-      const cd disc = std::sqrt(half * half + b * c);
-      const cd m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
-      mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
-    }
-    for (int i = l; i <= hi; ++i) H[(size_t)i * n + i] -= mu;
-    for (int kk = l; kk < hi; ++kk) {  // H - mu I = Q R by rotations of rows kk, kk+1
-      const cd x = H[(size_t)kk * n + kk], y = H[(size_t)(kk + 1) * n + kk];
-      const double r = std::sqrt(std::norm(x) + std::norm(y));
-      double cc;
-      cd ss;
-      if (r == 0.0) {
-        cc = 1.0;
-        ss = 0.0;
-      } else if (std::abs(x) == 0.0) {
-        cc = 0.0;
-        ss = std::conj(y) / std::abs(y);
+    if (l == hi - 1) {  // a 2 x 2 block
+      const double a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+      const double p = 0.5 * (a - d), q = p * p + b * c;
+      if (q >= 0.0) {
+        const double z = p + std::copysign(std::sqrt(q), p);
+        wr[hi - 1] = d + z;
+        wr[hi] = z != 0.0 ? d - b * c / z : d + z;
+        wi[hi - 1] = wi[hi] = 0.0;
       } else {
-        cc = std::abs(x) / r;
-        ss = (x / std::abs(x)) * std::conj(y) / r;
+        wr[hi - 1] = wr[hi] = d + p;
+        wi[hi - 1] = std::sqrt(-q);
+        wi[hi] = -wi[hi - 1];
       }
-      gc[kk] = cc;
-      gs[kk] = ss;
-      for (int jj = kk; jj < n; ++jj) {
-        const cd u = H[(size_t)kk * n + jj], w = H[(size_t)(kk + 1) * n + jj];
-        H[(size_t)kk * n + jj] = cc * u + ss * w;
-        H[(size_t)(kk + 1) * n + jj] = -std::conj(ss) * u + cc * w;
+      hi -= 2;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 40 * n) return false;
+    // the double shift: the trailing 2 x 2 block's eigenvalues (sum s, product
+    // t), or an exceptional shift after 10 and 20 iterations without deflation
+    double s = h(hi - 1, hi - 1) + h(hi, hi);
+    double t = h(hi - 1, hi - 1) * h(hi, hi) - h(hi - 1, hi) * h(hi, hi - 1);
+    if (iter % 10 == 0) {
+      const double x = std::fabs(h(hi, hi - 1)) + std::fabs(h(hi - 1, hi - 2));
+      s = 1.5 * x + h(hi, hi);
+      t = x * x;
+    }
+    // first column of (H - s1)(H - s2) in the window
+    double x = h(l, l) * h(l, l) + h(l, l + 1) * h(l + 1, l) - s * h(l, l) + t;
+    double y = h(l + 1, l) * (h(l, l) + h(l + 1, l + 1) - s);
+    double z = h(l + 1, l) * h(l + 2, l + 1);
+    for (int k = l; k <= hi - 1; ++k) {
+      const int len = k < hi - 1 ? 3 : 2;
+      double v[3] = {x, y, len == 3 ? z : 0.0};
+      double tau, beta;
+      house(len, v, &tau, &beta);
+      if (tau != 0.0) {
+        const int c0 = std::max(l, k - 1);
+        for (int c = c0; c <= hi; ++c) {  // rows k..k+len-1 from the left
+          double sm = 0.0;
+          for (int i = 0; i < len; ++i) sm += v[i] * h(k + i, c);
+          sm *= tau;
+          for (int i = 0; i < len; ++i) h(k + i, c) -= sm * v[i];
+        }
+        const int r1 = std::min(k + 3, hi);
+        for (int r = l; r <= r1; ++r) {  // columns k..k+len-1 from the right
+          double sm = 0.0;
+          for (int i = 0; i < len; ++i) sm += h(r, k + i) * v[i];
+          sm *= tau;
+          for (int i = 0; i < len; ++i) h(r, k + i) -= sm * v[i];
+        }
+      }
+      if (k > l) {  // the bulge below the subdiagonal is gone
+        h(k + 1, k - 1) = 0.0;
+        if (len == 3) h(k + 2, k - 1) = 0.0;
+      }
+      if (k < hi - 1) {
+        x = h(k + 1, k);
+        y = h(k + 2, k);
+        z = k < hi - 2 ? h(k + 3, k) : 0.0;
       }
     }
-    for (int kk = l; kk < hi; ++kk) {  // R Q: rotations of columns kk, kk+1
-      const double cc = gc[kk];
-      const cd ss = gs[kk];
-      const int top = std::min(kk + 2, hi);
-      for (int ii = 0; ii <= top; ++ii) {
-        const cd u = H[(size_t)ii * n + kk], w = H[(size_t)ii * n + kk + 1];
-        H[(size_t)ii * n + kk] = u * cc + w * std::conj(ss);
-        H[(size_t)ii * n + kk + 1] = -u * ss + w * cc;
-      }
-      for (int ii = 0; ii < n; ++ii) {
-        const cd u = Z[(size_t)ii * n + kk], w = Z[(size_t)ii * n + kk + 1];
-        Z[(size_t)ii * n + kk] = u * cc + w * std::conj(ss);
-        Z[(size_t)ii * n + kk + 1] = -u * ss + w * cc;
-      }
-    }
-    for (int i = l; i <= hi; ++i) H[(size_t)i * n + i] += mu;
   }
   return true;
+}
+
+using cd = std::complex<double>;
+
+// An eigenvector of the upper Hessenberg H (n x n, row-major) for the
+// eigenvalue mu by inverse iteration: (H - sigma I) x = b twice, sigma = mu
+// moved by a relative 1e-10 so that the factor is not exactly singular, LU
+// with partial pivoting between neighbouring rows (the Hessenberg form keeps
+// the factor's work O(n^2)); b a fixed start vector depending on seed.
+static void hess_invit(int n, const double* H, cd mu, int seed, std::vector<cd>& x) {
+  double hn = 0.0;
+  for (int r = 0; r < n; ++r)
+    for (int c = std::max(0, r - 1); c < n; ++c) hn = std::max(hn, std::fabs(H[(size_t)r * n + c]));
+  const cd sigma = mu + cd(1e-10 * std::max(hn, 1e-300), 0.0);
+  std::vector<cd> U((size_t)n * n);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) U[(size_t)r * n + c] = (c >= r - 1) ? cd(H[(size_t)r * n + c]) : cd(0.0);
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] -= sigma;
+  std::vector<cd> mult(n, cd(0.0));
+  std::vector<char> swp(n, 0);
+  const double tiny = 2.220446049250313e-16 * std::max(hn, 1e-300);
+  for (int c = 0; c + 1 < n; ++c) {
+    cd* r0 = &U[(size_t)c * n];
+    cd* r1 = &U[(size_t)(c + 1) * n];
+    if (std::abs(r1[c]) > std::abs(r0[c])) {
+      for (int j = c; j < n; ++j) std::swap(r0[j], r1[j]);
+      swp[c] = 1;
+    }
+    if (std::abs(r0[c]) < tiny) r0[c] = tiny;
+    const cd m = r1[c] / r0[c];
+    mult[c] = m;
+    r1[c] = 0.0;
+    for (int j = c + 1; j < n; ++j) r1[j] -= m * r0[j];
+  }
+  if (std::abs(U[(size_t)(n - 1) * n + n - 1]) < tiny) U[(size_t)(n - 1) * n + n - 1] = tiny;
+  x.assign(n, cd(0.0));
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.25 * ((i * 7919 + seed * 104729) % 101) / 101.0;
+  for (int it = 0; it < 2; ++it) {
+    for (int c = 0; c + 1 < n; ++c) {  // the row operations on the right-hand side
+      if (swp[c]) std::swap(x[c], x[c + 1]);
+      x[c + 1] -= mult[c] * x[c];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      cd sm = x[i];
+      for (int j = i + 1; j < n; ++j) sm -= U[(size_t)i * n + j] * x[j];
+      x[i] = sm / U[(size_t)i * n + i];
+    }
+    double nz = 0.0;
+    for (const cd& v : x) nz += std::norm(v);
+    nz = std::sqrt(nz);
+    for (cd& v : x) v /= nz;
+  }
 }
 
 // The harmonic Ritz selection: eigenpairs of G^T WtV z = mu G^T G z (G, WtV:
@@ -403,40 +467,54 @@ static bool schur(int n, std::vector<cd>& H, std::vector<cd>& Z) {
 // that does not fit in what is left of kr ends the selection.  Pk: N x kr
 // row-major (the first returned count of columns used); mu_re/mu_im (may be
 // NULL) the selected values.  Returns the count, or -1 when G^T G is not
-// positive definite or the iteration fails.
+// positive definite or the iteration fails.  Steps: M = (G^T G)^{-1} G^T WtV by
+// Cholesky, M = Qh Hh Qh^T (Householder), the eigenvalues of Hh by the Francis
+// iteration, the chosen eigenvectors by inverse iteration on Hh, z = Qh x.
 static int harmonic_select(int rows, int N, const double* G, const double* WtV, int kr, double* Pk, double* mu_re,
                            double* mu_im) {
   if (kr <= 0 || N <= 0) return 0;
   std::vector<double> A1((size_t)N * N, 0.0), A2((size_t)N * N, 0.0), Rc((size_t)N * N);
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      double s1 = 0.0, s2 = 0.0;
-      for (int r = 0; r < rows; ++r) {
-        s1 += G[(size_t)r * N + i] * G[(size_t)r * N + j];
-        s2 += G[(size_t)r * N + i] * WtV[(size_t)r * N + j];
-      }
-      A1[(size_t)i * N + j] = s1;
-      A2[(size_t)i * N + j] = s2;
-    }
-  if (!chol_upper(N, A1.data(), Rc.data())) return -1;
-  // M = (R^T R)^{-1} A2: forward then back substitution per column
-  std::vector<double> M((size_t)N * N);
-  for (int c = 0; c < N; ++c) {
-    std::vector<double> x(N);
+  for (int r = 0; r < rows; ++r) {  // row by row: contiguous accesses
+    const double* g = G + (size_t)r * N;
+    const double* w = WtV + (size_t)r * N;
     for (int i = 0; i < N; ++i) {
-      double s = A2[(size_t)i * N + c];
-      for (int t = 0; t < i; ++t) s -= Rc[(size_t)t * N + i] * x[t];
-      x[i] = s / Rc[(size_t)i * N + i];
+      const double gi = g[i];
+      if (gi == 0.0) continue;
+      double* a1 = &A1[(size_t)i * N];
+      double* a2 = &A2[(size_t)i * N];
+      for (int j = 0; j < N; ++j) {
+        a1[j] += gi * g[j];
+        a2[j] += gi * w[j];
+      }
     }
-    for (int i = N - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int t = i + 1; t < N; ++t) s -= Rc[(size_t)i * N + t] * x[t];
-      x[i] = s / Rc[(size_t)i * N + i];
+  }
+  if (!chol_upper(N, A1.data(), Rc.data())) return -1;
+  // M = R^{-1} R^{-T} A2, all columns at once: forward (R^T Y = A2) then back (R M = Y)
+  std::vector<double> M(A2);
+  for (int i = 0; i < N; ++i) {
+    double* mi = &M[(size_t)i * N];
+    for (int t = 0; t < i; ++t) {
+      const double rti = Rc[(size_t)t * N + i];
+      if (rti == 0.0) continue;
+      const double* mt = &M[(size_t)t * N];
+      for (int c = 0; c < N; ++c) mi[c] -= rti * mt[c];
     }
-    for (int i = 0; i < N; ++i) M[(size_t)i * N + c] = x[i];
+    const double d = 1.0 / Rc[(size_t)i * N + i];
+    for (int c = 0; c < N; ++c) mi[c] *= d;
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double* mi = &M[(size_t)i * N];
+    for (int t = i + 1; t < N; ++t) {
+      const double rit = Rc[(size_t)i * N + t];
+      if (rit == 0.0) continue;
+      const double* mt = &M[(size_t)t * N];
+      for (int c = 0; c < N; ++c) mi[c] -= rit * mt[c];
+    }
+    const double d = 1.0 / Rc[(size_t)i * N + i];
+    for (int c = 0; c < N; ++c) mi[c] *= d;
   }
   // Hessenberg form M = Qh Hh Qh^T by Householder reflections
-  std::vector<double> Hh(M), Qh((size_t)N * N, 0.0);
+  std::vector<double> Hh(M), Qh((size_t)N * N, 0.0), tmp(N);
   for (int i = 0; i < N; ++i) Qh[(size_t)i * N + i] = 1.0;
   for (int c = 0; c + 2 < N; ++c) {
     const int len = N - c - 1;
@@ -445,61 +523,58 @@ static int harmonic_select(int rows, int N, const double* G, const double* WtV, 
     double tau, beta;
     house(len, x.data(), &tau, &beta);
     if (tau == 0.0) continue;
-    for (int j = 0; j < N; ++j) {  // rows c+1.. : H <- (I - tau v v^T) H
-      double s = 0.0;
-      for (int r = 0; r < len; ++r) s += x[r] * Hh[(size_t)(c + 1 + r) * N + j];
-      s *= tau;
-      for (int r = 0; r < len; ++r) Hh[(size_t)(c + 1 + r) * N + j] -= s * x[r];
+    // rows c+1.. : H <- (I - tau v v^T) H, by rows (contiguous)
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    for (int r = 0; r < len; ++r) {
+      const double* hr = &Hh[(size_t)(c + 1 + r) * N];
+      for (int j = 0; j < N; ++j) tmp[j] += x[r] * hr[j];
     }
-    for (int i = 0; i < N; ++i) {  // columns c+1.. : H <- H (I - tau v v^T), Q <- Q (I - tau v v^T)
-      double s = 0.0, q = 0.0;
+    for (int r = 0; r < len; ++r) {
+      double* hr = &Hh[(size_t)(c + 1 + r) * N];
+      const double f = tau * x[r];
+      for (int j = 0; j < N; ++j) hr[j] -= f * tmp[j];
+    }
+    // columns c+1.. : H <- H (I - tau v v^T) and Q <- Q (I - tau v v^T)
+    for (int i = 0; i < N; ++i) {
+      double* hr = &Hh[(size_t)i * N + c + 1];
+      double* qr = &Qh[(size_t)i * N + c + 1];
+      double sh = 0.0, sq = 0.0;
       for (int r = 0; r < len; ++r) {
-        s += Hh[(size_t)i * N + c + 1 + r] * x[r];
-        q += Qh[(size_t)i * N + c + 1 + r] * x[r];
+        sh += hr[r] * x[r];
+        sq += qr[r] * x[r];
       }
-      s *= tau;
-      q *= tau;
+      sh *= tau;
+      sq *= tau;
       for (int r = 0; r < len; ++r) {
-        Hh[(size_t)i * N + c + 1 + r] -= s * x[r];
-        Qh[(size_t)i * N + c + 1 + r] -= q * x[r];
+        hr[r] -= sh * x[r];
+        qr[r] -= sq * x[r];
       }
     }
     for (int r = c + 2; r < N; ++r) Hh[(size_t)r * N + c] = 0.0;
   }
-  std::vector<cd> T((size_t)N * N), Z;
-  for (size_t i = 0; i < T.size(); ++i) T[i] = Hh[i];
-  if (!schur(N, T, Z)) return -1;
+  std::vector<double> W(Hh), wr(N), wi(N);
+  if (!hess_eig(N, W.data(), wr.data(), wi.data())) return -1;
   std::vector<cd> mu(N);
-  double mmax = 0.0, tn = 0.0;
+  double mmax = 0.0;
   for (int i = 0; i < N; ++i) {
-    mu[i] = T[(size_t)i * N + i];
+    mu[i] = cd(wr[i], wi[i]);
     mmax = std::max(mmax, std::abs(mu[i]));
   }
-  for (const cd& x : T) tn += std::norm(x);
-  tn = std::sqrt(tn);
-  const double thr = 1e-10 * mmax, small = 2.220446049250313e-16 * std::max(tn, 1e-300);
-  // the eigenvector of M for eigenvalue index i: T v = mu_i v by back
-  // substitution, then Qh Z v
-  auto eigvec = [&](int i, std::vector<cd>& z) {
-    std::vector<cd> v(N, cd(0.0));
-    v[i] = 1.0;
-    for (int j = i - 1; j >= 0; --j) {
-      cd s = 0.0;
-      for (int t = j + 1; t <= i; ++t) s += T[(size_t)j * N + t] * v[t];
-      cd den = T[(size_t)j * N + j] - mu[i];
-      if (std::abs(den) < small) den = small;
-      v[j] = -s / den;
-    }
-    std::vector<cd> y(N, cd(0.0));
-    for (int r = 0; r < N; ++r)
-      for (int t = 0; t <= i; ++t) y[r] += Z[(size_t)r * N + t] * v[t];
+  const double thr = 1e-10 * mmax;
+  auto eigvec = [&](int i, int seed, std::vector<cd>& z) {
+    std::vector<cd> x;
+    hess_invit(N, Hh.data(), mu[i], seed, x);
     z.assign(N, cd(0.0));
-    for (int r = 0; r < N; ++r)
-      for (int t = 0; t < N; ++t) z[r] += Qh[(size_t)r * N + t] * y[t];
+    for (int r = 0; r < N; ++r) {
+      const double* q = &Qh[(size_t)r * N];
+      cd sm = 0.0;
+      for (int t = 0; t < N; ++t) sm += q[t] * x[t];
+      z[r] = sm;
+    }
     double nz = 0.0;
-    for (const cd& x : z) nz += std::norm(x);
+    for (const cd& v : z) nz += std::norm(v);
     nz = std::sqrt(nz);
-    for (cd& x : z) x /= nz;
+    for (cd& v : z) v /= nz;
   };
   std::vector<int> order(N);
   for (int i = 0; i < N; ++i) order[i] = i;
@@ -511,14 +586,15 @@ static int harmonic_select(int rows, int N, const double* G, const double* WtV, 
     const int i = order[oi];
     if (used[i]) continue;
     if (std::abs(mu[i].imag()) <= thr) {
-      eigvec(i, z);
+      mu[i] = cd(mu[i].real(), 0.0);
+      eigvec(i, cnt, z);
       int tm = 0;
       for (int r = 1; r < N; ++r)
         if (std::abs(z[r]) > std::abs(z[tm])) tm = r;
       const cd ph = std::conj(z[tm]) / std::abs(z[tm]);
       for (int r = 0; r < N; ++r) Pk[(size_t)r * kr + cnt] = (z[r] * ph).real();
       if (mu_re) mu_re[cnt] = mu[i].real();
-      if (mu_im) mu_im[cnt] = mu[i].imag();
+      if (mu_im) mu_im[cnt] = 0.0;
       used[i] = 1;
       ++cnt;
       continue;
@@ -530,7 +606,7 @@ static int harmonic_select(int rows, int N, const double* G, const double* WtV, 
       if (j < 0 || std::abs(mu[t] - std::conj(mu[i])) < std::abs(mu[j] - std::conj(mu[i]))) j = t;
     }
     if (j < 0 || cnt + 2 > kr) break;
-    eigvec(mu[i].imag() > 0.0 ? i : j, z);
+    eigvec(mu[i].imag() > 0.0 ? i : j, cnt, z);
     for (int r = 0; r < N; ++r) {
       Pk[(size_t)r * kr + cnt] = z[r].real();
       Pk[(size_t)r * kr + cnt + 1] = z[r].imag();
