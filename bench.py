@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.5,0.8,0.95", help="comma-separated loads rho of the serving runs")
+    ap.add_argument("--only", choices=["gcrodr", "complex", "batch"],
+                    help="run one arm by itself and print its JSON (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
@@ -338,6 +340,16 @@ def main():
 
     def factory():
         return Problem(ctx, terms)
+
+    if args.only:
+        if args.only == "gcrodr":
+            res = gcrodr_bench(ctx, factory, job, B)
+        elif args.only == "complex":
+            res = complex_bench(ctx)
+        else:
+            res = c2_bench(ctx, args.c2_systems)
+        print(json.dumps({"only": args.only, args.only: res}), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)

@@ -610,7 +610,6 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
   if (a.ncols == 0) return PMOR_OK;
   const unsigned g16 = (unsigned)((a.ncols + 15) / 16);  // 16 columns per workgroup
   const unsigned g32 = (unsigned)((a.ncols + 7) / 8);    // 8 columns (of 32 lanes) per workgroup
-  const unsigned g64 = (unsigned)((a.ncols + 3) / 4);    // 4 columns (of 64 lanes) per workgroup
   // |J| <= 32 with |I| <= 128 in registers for 4-byte values; FP64 would need
   // 256 registers for the block, so it takes the LDS kernel
   constexpr bool REG32 = sizeof(T) == 4;
@@ -632,11 +631,8 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
         break;
       }
       [[fallthrough]];
-    case 7:
-      if constexpr (REG32) {
-        plaunch(pc, pidx, part, k_spai_reg<T, 64, 2, Q16, 64, GO, MULTI>, dim3(g64), dim3(256), 0, st, a);
-        break;
-      }
+    case 7:  // |J| <= 64 with |I| <= 128: the LDS kernel (measured faster than a 64-lane register form,
+             // whose 64-column block left 2 waves per SIMD and spilled scalar registers)
       [[fallthrough]];
     case 8: {
       const int ldI = ((maxI + 7) / 8) * 8;
