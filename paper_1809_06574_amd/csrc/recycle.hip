@@ -82,17 +82,28 @@ __global__ __launch_bounds__(256) void k_gram_part(int64_t n, const double* __re
   }
 }
 
-// out[p] = sum_g part[g][p]: 16 lanes per p, lane l summing g = l, l + 16, ...
-// in order, then a fixed butterfly over the 16 lanes (the same order every call)
+// out[p] = sum_g part[g][p]: LPE lanes per p, lane l summing g = l, l + LPE,
+// ... in order, then a fixed tree over the LPE lanes in LDS (the same order
+// for the same G and ab).  Few outputs take many lanes each, so the partials
+// of a small Gram product are read with many loads in flight.
+template <int LPE>
 __global__ __launch_bounds__(256) void k_gram_reduce(int G, int ab, const double* __restrict__ part,
                                                      double* __restrict__ out) {
-  const int p = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+  constexpr int EPB = 256 / LPE;
+  __shared__ double sh[256];
+  const int e = threadIdx.x / LPE, l = threadIdx.x - e * LPE;
+  const int p = blockIdx.x * EPB + e;
   double s = 0.0;
   if (p < ab)
-    for (int g = l; g < G; g += 16) s += part[(int64_t)g * ab + p];
+    for (int g = l; g < G; g += LPE) s += part[(int64_t)g * ab + p];
+  sh[threadIdx.x] = s;
+  __syncthreads();
 #pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, 16);
-  if (p < ab && l == 0) out[p] = s;
+  for (int o = LPE / 2; o >= 1; o >>= 1) {
+    if (l < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (p < ab && l == 0) out[p] = sh[threadIdx.x];
 }
 
 // Y = beta Y + alpha A G (A: n x a, G: a x b row-major in LDS; beta 0 reads no Y)
@@ -712,7 +723,13 @@ int gram(Work& w, const double* A, int64_t lda, int a, const double* W, int64_t 
   // algorithmic bytes: the n rows of A's a and W's b columns (W among A's columns is read once)
   const bool w_in_a = lda == ldw && W >= A && W + b <= A + a;
   prof_stop(w.ctx, pr, 8.0 * w.n * (w_in_a ? a : a + b), 0);
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((ab + 15) / 16)), dim3(256), 0, w.st, G, ab, w.part, out);
+  if (ab <= 64) {
+    hipLaunchKernelGGL(k_gram_reduce<256>, dim3((unsigned)ab), dim3(256), 0, w.st, G, ab, w.part, out);
+  } else if (ab <= 1024) {
+    hipLaunchKernelGGL(k_gram_reduce<64>, dim3((unsigned)((ab + 3) / 4)), dim3(256), 0, w.st, G, ab, w.part, out);
+  } else {
+    hipLaunchKernelGGL(k_gram_reduce<16>, dim3((unsigned)((ab + 15) / 16)), dim3(256), 0, w.st, G, ab, w.part, out);
+  }
   PMOR_HIP(hipGetLastError());
   return PMOR_OK;
 }
