@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--serve-rho", default="0.5,0.8,0.95", help="comma-separated loads rho of the serving runs")
     ap.add_argument("--only", choices=["gcrodr", "complex", "batch"],
                     help="run one arm by itself and print its JSON (for profiling it)")
+    ap.add_argument("--c2-no-pool", action="store_true",
+                    help="generate the batch workload's systems in this process (no worker processes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: a job of this workload fits one GPU and the library does not "
@@ -347,7 +349,7 @@ def main():
         elif args.only == "complex":
             res = complex_bench(ctx)
         else:
-            res = c2_bench(ctx, args.c2_systems)
+            res = c2_bench(ctx, args.c2_systems, pool=not args.c2_no_pool)
         print(json.dumps({"only": args.only, args.only: res}), flush=True)
         return
 
@@ -470,7 +472,7 @@ def main():
         out["precisions"] = c3_bench(factory, job, B, keep_points=(0, npts // 2, npts - 1), kept=kept)
 
     if args.c2_systems > 0:
-        out["batch_systems"] = c2_bench(ctx, args.c2_systems)
+        out["batch_systems"] = c2_bench(ctx, args.c2_systems, pool=not args.c2_no_pool)
 
     if args.serve_jobs > 0:
         _note("serving")
@@ -745,7 +747,7 @@ def _note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def c2_bench(ctx, nsys, precision="f32"):
+def c2_bench(ctx, nsys, precision="f32", pool=True):
     """Independent systems of the batch workload (n in [4096, 65536], 2-D/3-D,
     k = 8, power-law SPAI patterns of 5..40 nodes, least squares in FP32): P_1 at
     p, the U-diag update at p + 0.02, then the nsys solves at p + 0.02 together
@@ -758,15 +760,18 @@ def c2_bench(ctx, nsys, precision="f32"):
     # the generator runs in fresh interpreters (no fork of a process that holds the GPU)
     _note(f"batch workload: generating {nsys} systems")
     jobs = []
-    pool = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
-    try:
-        for job in pool.imap(_c2_system, range(nsys), chunksize=4):
-            jobs.append(job)
-            if len(jobs) % 64 == 0:
-                _note(f"batch workload: {len(jobs)}/{nsys} systems generated")
-    finally:
-        pool.close()
-        pool.join()
+    if pool:
+        workers = mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1))
+        try:
+            for job in workers.imap(_c2_system, range(nsys), chunksize=4):
+                jobs.append(job)
+                if len(jobs) % 64 == 0:
+                    _note(f"batch workload: {len(jobs)}/{nsys} systems generated")
+        finally:
+            workers.close()
+            workers.join()
+    else:  # in this process (under a counter-collecting profiler every child process would open the GPU)
+        jobs = [_c2_system(i) for i in range(nsys)]
     dev = ctx.device
     dterms, dpats, Bs = [], [], []
     for job in jobs:
