@@ -763,8 +763,11 @@ static int spai_build_batch_impl(pmor_ctx* ctx, pmor_spai_build_item* items, int
     if (hipMemcpyAsync(&bad[t], hs[t]->red, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
       rc = fail(PMOR_EHIP, "copy failed");
   if (rc == PMOR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
-  if (rc != PMOR_OK) {
-    for (pmor_spai* h : hs) spai_release(h);
+  if (rc != PMOR_OK) {  // the shared work failed: no item of it has a preconditioner
+    for (size_t t = 0; t < hs.size(); ++t) {
+      spai_release(hs[t]);
+      items[idx[t]].status = rc;
+    }
     return rc;
   }
   for (size_t t = 0; t < hs.size(); ++t) {

@@ -748,11 +748,7 @@ int tall_gemm(Work& w, const double* A, int64_t lda, int a, const double* G, int
   }
   const int rows = 256 / b;
   const size_t lds = sizeof(double) * (size_t)a * b;
-  static bool big_lds = false;
-  if (lds > 64 * 1024 && !big_lds) {
-    PMOR_TRY(allow_lds(reinterpret_cast<const void*>(k_tall_gemm), 160 * 1024));
-    big_lds = true;
-  }
+  if (lds > 64 * 1024) PMOR_TRY(allow_lds(reinterpret_cast<const void*>(k_tall_gemm), lds));  // per device, per call
   const int pr = prof_start(w.ctx, PMOR_PROF_GCRO_GEMM);
   plaunch(w.ctx, pr, 3, k_tall_gemm, dim3((unsigned)((w.n + rows - 1) / rows)), dim3(256), lds, w.st, w.n, A, lda, a,
           G, b, alpha, beta, Y, ldy);

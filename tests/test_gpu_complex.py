@@ -214,3 +214,23 @@ def test_complex_argument_errors(ctx, job):
     L.pmor_problem_destroy(o)
     kinds[0] = 7
     assert L.pmor_problem_create_complex(ctx.handle, 2, arr, kinds, C.byref(o)) == L.PMOR_EINVAL
+
+
+def test_batched_build_of_complex_problems(ctx, job):
+    """spai_build_batch on the complex problem at two points (and with an
+    explicit real-form pattern) gives the handles spai_build gives, bit for bit."""
+    from paper_1809_06574_amd import spai_build_batch
+    pb = _problem(ctx, job)
+    pts = [list(c) for c in job.coefs[:2]]
+    e = pb.spai_build(pts[0], None).export_sets()
+    pat = (e[0], e[1])
+    items = [(pb, pts[0], None), (pb, pts[1], None), (pb, pts[1], None, pat)]
+    hs, status, rc = spai_build_batch(ctx, items)
+    assert rc == 0 and status == [0, 0, 0]
+    for itm, h in zip(items, hs):
+        g = pb.spai_build(itm[1], None, pattern=itm[3] if len(itm) > 3 else None)
+        for key in ("rowptr", "col", "val"):
+            assert torch.equal(h.export()[key], g.export()[key]), key
+        h.update(pts[0])
+        g.update(pts[0])
+        assert torch.equal(h.export()["val"], g.export()["val"])

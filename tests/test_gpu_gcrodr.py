@@ -168,3 +168,18 @@ def test_argument_errors(ctx):
     assert rc == L.PMOR_ENOTCONV and st["cycles"] == 1
     rec.reset()
     assert rec.dim == 0
+
+
+@pytest.mark.parametrize("k,kr,m", [(1, 16, 31), (16, 16, 3)])
+def test_block_sizes_at_the_limits(ctx, k, kr, m):
+    """One right-hand side with the largest recycled space and the longest
+    cycle; sixteen right-hand sides (the largest block) with kr = 16: X against
+    the oracle's replay at every point, equal recycled dimensions."""
+    from paper_1809_06574_amd import Problem
+    job = config0()
+    pb = Problem(ctx, job.terms)
+    asm = Assembled(job)
+    B = np.random.default_rng(50 + k).standard_normal((job.n, k))
+    pts = [(job.s, p) for p in job.p_list[:3]]
+    _sequence(ctx, pb, asm, lambda pt: asm.values(*pt), pts, B, kr=kr, m=m, tol=1e-10,
+              h_of=lambda pt: pb.spai_build(*pt))
