@@ -10,6 +10,8 @@
 #include <mutex>
 #include <string>
 #include <vector>
+#include <thread>
+#include <atomic>
 
 #include "common.hpp"
 
@@ -641,7 +643,8 @@ static int assemble_pt(pmor_problem* pb, const Point& pt, double* val) {
 }
 
 // a handle with its sets and buffers, nothing computed yet (the options checked)
-static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** out) {
+static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** out, hipStream_t st = nullptr) {
+  if (!st) st = pb->ctx->stream;
   pmor_spai_opts o{};
   o.pattern = PMOR_PAT_A;
   o.precision = PMOR_F64;
@@ -666,14 +669,14 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
   pb_ref(pb);
   h->opts = o;
   *out = h;
-  int rc = build_spai_sets(h);
+  int rc = build_spai_sets(h, st);
   // P of a complex problem must be the real form of a complex pattern (its
   // least squares are then the complex ones, and Q P_1 keeps the pattern)
-  if (rc == PMOR_OK && pb->cplx) rc = check_pairs(pb->n, h->Prowptr, h->Pcol, pb->ctx->stream);
+  if (rc == PMOR_OK && pb->cplx) rc = check_pairs(pb->n, h->Prowptr, h->Pcol, st);
   if (rc == PMOR_OK) {
     const int64_t n = pb->n;
     auto al = [&](double** p, int64_t cnt) {
-      return dmalloc((void**)p, sizeof(double) * std::max<int64_t>(cnt, 1), pb->ctx->stream) == hipSuccess;
+      return dmalloc((void**)p, sizeof(double) * std::max<int64_t>(cnt, 1), st) == hipSuccess;
     };
     bool ok = al(&h->Pval, h->nnzP) && al(&h->P1val, h->nnzP) &&
               al(&h->Qval, o.update != PMOR_UPD_DIAG ? h->nnzP : n) && al(&h->aval1, pb->nnz) &&
@@ -682,11 +685,13 @@ static int spai_new(pmor_problem* pb, const pmor_spai_opts* opts, pmor_spai** ou
       ok = al(&h->P1val_s, h->psell.cap) &&
            ((o.update == PMOR_UPD_DIAG && !pb->cplx) || al(&h->Qval_s, h->psell.cap));
     if (ok && o.update == PMOR_UPD_ADAPTIVE)
-      ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), pb->ctx->stream) ==
-               hipSuccess &&
-           dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * BUCKET_SLOTS, pb->ctx->stream) == hipSuccess;
+      ok = dmalloc((void**)&h->esc_list, sizeof(int32_t) * 2 * std::max<int64_t>(n, 1), st) == hipSuccess &&
+           dmalloc((void**)&h->esc_cnt, sizeof(int32_t) * BUCKET_SLOTS, st) == hipSuccess;
     if (!ok) rc = fail(PMOR_ENOMEM, "preconditioner allocation failed");
   }
+  // built on another stream than the problem's: complete before the handle is used there
+  if (st != pb->ctx->stream && hipStreamSynchronize(st) != hipSuccess && rc == PMOR_OK)
+    rc = fail(PMOR_EHIP, "synchronise failed");
   if (rc != PMOR_OK) {
     spai_release(h);
     *out = nullptr;
@@ -723,19 +728,57 @@ static int spai_build_batch_impl(pmor_ctx* ctx, pmor_spai_build_item* items, int
     items[i].status = rc;
     if (first_rc == PMOR_OK) first_rc = rc;
   };
+  // the items' points, then every handle's index sets and buckets: a few small
+  // kernels per system with host synchronisations between them, so the systems
+  // are spread over worker threads, each with a stream of its own
+  std::vector<Point> ipt(count);
+  std::vector<int> irc(count, PMOR_OK);
+  std::vector<pmor_spai*> ih(count, nullptr);
+  std::vector<std::string> imsg(count);
   for (int i = 0; i < count; ++i) {
     pmor_spai_build_item& it = items[i];
     it.h = nullptr;
     it.status = PMOR_OK;
     it.bad_column = -1;
-    if (!it.pb) { item_fail(i, fail(PMOR_EINVAL, "item " + std::to_string(i) + ": problem is NULL")); continue; }
-    if (it.pb->ctx != ctx) { item_fail(i, fail(PMOR_EINVAL, "item " + std::to_string(i) + ": another context")); continue; }
-    Point pt{};
-    int rc = it.coef ? point_coef(it.pb, it.coef, &pt) : point_sp(it.pb, it.s, it.p, &pt);
+    if (!it.pb) { irc[i] = fail(PMOR_EINVAL, "item " + std::to_string(i) + ": problem is NULL"); continue; }
+    if (it.pb->ctx != ctx) { irc[i] = fail(PMOR_EINVAL, "item " + std::to_string(i) + ": another context"); continue; }
+    irc[i] = it.coef ? point_coef(it.pb, it.coef, &ipt[i]) : point_sp(it.pb, it.s, it.p, &ipt[i]);
     const int pr = it.opts ? it.opts->precision : PMOR_F64;
-    if (rc == PMOR_OK && prec >= 0 && pr != prec) rc = fail(PMOR_EINVAL, "a batch takes one least-squares precision");
-    pmor_spai* h = nullptr;
-    if (rc == PMOR_OK) rc = spai_new(it.pb, it.opts, &h);
+    if (irc[i] == PMOR_OK && prec >= 0 && pr != prec) irc[i] = fail(PMOR_EINVAL, "a batch takes one least-squares precision");
+    if (irc[i] == PMOR_OK) prec = pr;
+    if (irc[i] != PMOR_OK) imsg[i] = pmor_last_error();
+  }
+  PMOR_HIP(hipStreamSynchronize(st));  // the problems' earlier work precedes the workers' reads
+  {
+    const int nthr = std::max(1, std::min(count, 8));
+    std::vector<hipStream_t> ws(nthr, nullptr);
+    for (auto& x : ws)
+      if (hipStreamCreate(&x) != hipSuccess) { (void)hipGetLastError(); x = nullptr; }
+    std::atomic<int> next{0};
+    auto work = [&](int t) {
+      (void)hipSetDevice(ctx->device);
+      for (int i = next++; i < count; i = next++) {
+        if (irc[i] != PMOR_OK) continue;
+        irc[i] = spai_new(items[i].pb, items[i].opts, &ih[i], ws[t] ? ws[t] : st);
+        if (irc[i] != PMOR_OK) imsg[i] = pmor_last_error();
+      }
+    };
+    std::vector<std::thread> thr;
+    for (int t = 1; t < nthr; ++t) thr.emplace_back(work, t);
+    work(0);
+    for (auto& x : thr) x.join();
+    for (auto& x : ws)
+      if (x) (void)hipStreamDestroy(x);
+  }
+  for (int i = 0; i < count; ++i) {
+    pmor_spai_build_item& it = items[i];
+    const Point& pt = ipt[i];
+    pmor_spai* h = ih[i];
+    int rc = irc[i];
+    if (rc != PMOR_OK) {
+      item_fail(i, fail(rc, imsg[i]));
+      continue;
+    }
     if (rc == PMOR_OK) rc = ensure_assembled(it.pb, pt);
     if (rc == PMOR_OK) rc = dcopy(it.pb->aval, h->aval1, it.pb->nnz, st);
     if (rc != PMOR_OK) {
@@ -743,7 +786,6 @@ static int spai_build_batch_impl(pmor_ctx* ctx, pmor_spai_build_item* items, int
       item_fail(i, rc);
       continue;
     }
-    prec = pr;
     hs.push_back(h);
     av.push_back(h->aval1);
     idx.push_back(i);

@@ -283,7 +283,8 @@ inline void plaunch(pmor_ctx* c, int idx, int part, F kernel, dim3 g, dim3 b, ui
 int launch_assemble(pmor_problem* pb, const Point& pt, double* out, hipStream_t st);
 // union pattern of terms[0..count) (NULL entries absent); maps rows: one per entry of terms
 int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count);
-int build_spai_sets(pmor_spai* h);
+// the SPAI index sets and buckets of h (on stream st, or the problem's when null)
+int build_spai_sets(pmor_spai* h, hipStream_t st = nullptr);
 // PMOR_EINVAL unless (rowptr, col) is an n x n CSR pattern of nnz entries with
 // strictly increasing columns per row (synchronises)
 int check_csr(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, hipStream_t st);

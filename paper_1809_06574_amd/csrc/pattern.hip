@@ -828,9 +828,9 @@ __global__ __launch_bounds__(256) void k_bucket_fill(int n, const int32_t* Jcolp
   if (b >= 0) cols[base[b] + pos[b][threadIdx.x] - 1] = j;
 }
 
-int build_spai_sets(pmor_spai* h) {
+int build_spai_sets(pmor_spai* h, hipStream_t st) {
   pmor_problem* pb = h->pb;
-  hipStream_t st = pb->ctx->stream;
+  if (!st) st = pb->ctx->stream;
   const int n = pb->n;
   int* dflag = nullptr;
   PMOR_HIP(dmalloc((void**)&dflag, sizeof(int) * 4, st));
