@@ -779,7 +779,7 @@ def c2_bench(ctx, nsys, precision="f32", pool=True):
                        for r, T in job.terms.items()})
         dpats.append(tuple(torch.as_tensor(x).to(dev) for x in job.pattern))
         Bs.append(torch.as_tensor(job.B, device=dev))
-    from paper_1809_06574_amd import lib as L, spai_build_batch
+    from paper_1809_06574_amd import lib as L, spai_build_batch, problem_create_batch
     # one system after another: problem, P_1 (spai_build), update
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -795,14 +795,16 @@ def c2_bench(ctx, nsys, precision="f32", pool=True):
     # shared bucketed launches (spai_build_batch), then the updates
     torch.cuda.synchronize()
     t = time.perf_counter()
-    pbs = [Problem(ctx, terms) for terms in dterms]
+    pbs, _, _ = problem_create_batch(ctx, dterms)
     t_problems = time.perf_counter() - t
     bitems = [(pb, job.s, job.p_list[0], pat) for pb, job, pat in zip(pbs, jobs, dpats)]
     hs, _, _ = spai_build_batch(ctx, bitems, precision=precision)
+    t_spai = time.perf_counter() - t - t_problems
     for job, h in zip(jobs, hs):
         h.update(job.s, job.p_list[1])
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t
+    t_updates = t_prep - t_problems - t_spai
     # the least-squares kernels' own time: the batched P_1 once more under the
     # library's kernel timer
     L.check(L.pmor_prof_set(ctx.handle, L.PROF_KERNELS["spai_ls"]), "prof_set")
@@ -835,6 +837,7 @@ def c2_bench(ctx, nsys, precision="f32", pool=True):
            "pattern_sizes": "power law t^-2 on [5, 40]", "all_converged": all(x == 0 for x in status),
            "steps_total": int(sum(st["steps"] for st in stats)),
            "setup_pattern_spai_update_s": t_prep, "setup_problems_s": t_problems,
+           "setup_spai_batch_s": t_spai, "setup_updates_s": t_updates,
            "setup_one_system_at_a_time_s": t_prep_single,
            "batched_solves_per_s": nsys / t_batch, "pointwise_solves_per_s": nsys / t_point,
            "batched_solves_per_s_with_setup": nsys / (t_batch + t_prep),

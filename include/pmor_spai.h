@@ -189,6 +189,23 @@ int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_proble
  * calls accept its points too, as PMOR_NROLES coefficients in role order
  * (those of absent roles are ignored). */
 int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, pmor_problem** out);
+/* Several problems at once (the batches of independent systems of Section 3:
+ * each system is set up on its own, so the set-ups run side by side).  Item i
+ * is the call pmor_problem_create (nterms = 0: terms holds PMOR_NROLES role
+ * entries, NULL for an absent role) or pmor_problem_create_affine (nterms in
+ * 1..PMOR_TMAX); out: pb and status (PMOR_OK, or that call's error; pb NULL on
+ * error).  The union patterns are built on worker streams of the library
+ * (threads of the calling process), after the work already queued on ctx's
+ * stream; every problem is bit for bit the one the single call gives.  Complex
+ * problems are not taken here.  Returns PMOR_OK or the first item's failure;
+ * synchronises. */
+typedef struct pmor_problem_item {
+  int32_t nterms;
+  const pmor_csr* const* terms;
+  pmor_problem* pb;     /* out */
+  int32_t status;       /* out */
+} pmor_problem_item;
+int pmor_problem_create_batch(pmor_ctx* ctx, pmor_problem_item* items, int32_t count);
 
 /* Complex coefficients (the paper's expansion points are complex, Section 3:
  * s = 2 pi f sqrt(-1) makes s theta and s theta d imaginary).  A complex system

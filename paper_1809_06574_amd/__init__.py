@@ -16,6 +16,7 @@ _LAZY = {"lib": ("lib", None), "Context": ("api", "Context"), "Problem": ("api",
          "Spai": ("api", "Spai"), "batch_solve": ("api", "batch_solve"),
          "Server": ("api", "Server"), "Recycler": ("api", "Recycler"),
          "spai_build_batch": ("api", "spai_build_batch"),
+         "problem_create_batch": ("api", "problem_create_batch"),
          "complex_to_real": ("api", "complex_to_real"), "real_to_complex": ("api", "real_to_complex")}
 
 

@@ -88,11 +88,28 @@ class Context:
             pass
 
 
+def _csr_array(terms, affine, dev, keep):
+    """The pmor_csr array of a problem's terms (a list, or a dict by role with
+    absent roles NULL); the device tensors it points to go into ``keep``."""
+    seq = list(terms) if affine else [terms.get(role) for role in L.ROLES]
+    csrs = [None] * len(seq)
+    for r, T in enumerate(seq):
+        if T is None:
+            continue
+        rp, ci, va = (T.rowptr, T.col, T.val) if hasattr(T, "rowptr") else T
+        rp, ci, va = _dev_i32(rp, dev), _dev_i32(ci, dev), _dev_f64(va, dev)
+        keep += [rp, ci, va]
+        csrs[r] = L.Csr(rp.numel() - 1, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+    keep.append(csrs)
+    arr = (C.POINTER(L.Csr) * max(len(seq), 1))(*[C.pointer(c) if c is not None else None for c in csrs])
+    return seq, arr
+
+
 class Problem:
     """A parametric system: A(s,p) = s^2 M(p) + s D(p) + K(p) (terms by role, a dict),
     or the affine A(c) = sum_t c_t T_t (terms a list; points are coefficient vectors)."""
 
-    def __init__(self, ctx: Context, terms, kinds=None):
+    def __init__(self, ctx: Context, terms, kinds=None, _handle=None):
         """``terms[role] = (rowptr, col, val)`` arrays (host or device) or an object with
         ``rowptr``, ``col``, ``val`` attributes; roles M0, M1, D0, D1, K0, K1.  A list
         of such terms makes an affine problem (pmor_problem_create_affine); with
@@ -100,22 +117,16 @@ class Problem:
         complex and the problem is the equivalent real one of order 2n
         (pmor_problem_create_complex; blocks through complex_to_real)."""
         self.ctx = ctx
-        dev = ctx.device
         self._keep = []
         self.affine = isinstance(terms, (list, tuple))
         self.complex = kinds is not None
         if self.complex and not self.affine:
             raise ValueError("complex coefficients need a list of terms")
-        seq = list(terms) if self.affine else [terms.get(role) for role in L.ROLES]
-        csrs = [None] * len(seq)
-        for r, T in enumerate(seq):
-            if T is None:
-                continue
-            rp, ci, va = (T.rowptr, T.col, T.val) if hasattr(T, "rowptr") else T
-            rp, ci, va = _dev_i32(rp, dev), _dev_i32(ci, dev), _dev_f64(va, dev)
-            self._keep += [rp, ci, va]
-            csrs[r] = L.Csr(rp.numel() - 1, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
-        arr = (C.POINTER(L.Csr) * max(len(seq), 1))(*[C.pointer(c) if c is not None else None for c in csrs])
+        if _handle is not None:  # made by problem_create_batch
+            self.nmaps = self.ncoef = len(terms) if self.affine else len(L.ROLES)
+            self._finish(_handle)
+            return
+        seq, arr = _csr_array(terms, self.affine, ctx.device, self._keep)
         h = C.c_void_p()
         if self.complex:
             kd = {"real": L.PMOR_COEF_REAL, "imag": L.PMOR_COEF_IMAG, "complex": L.PMOR_COEF_COMPLEX}
@@ -132,6 +143,9 @@ class Problem:
         else:
             L.check(L.pmor_problem_create(ctx.handle, arr, C.byref(h)), "pmor_problem_create")
             self.nmaps = self.ncoef = len(seq)
+        self._finish(h)
+
+    def _finish(self, h):
         self.handle = h
         self._keep = []  # the library copied the terms
         nn, nz = C.c_int32(), C.c_int32()
@@ -269,6 +283,28 @@ class Problem:
             L.check(rc, "pmor_sequence_solve")
             return X, [s.as_dict() for s in stats]
         return X, [s.as_dict() for s in stats], rc
+
+
+def problem_create_batch(ctx: Context, terms_list, raise_on_error=True):
+    """Several real problems at once (pmor_problem_create_batch): each entry of
+    ``terms_list`` is what ``Problem`` takes (a dict by role, or a list of affine
+    terms).  Returns (list of Problem or None, list of status codes, rc)."""
+    n_it = len(terms_list)
+    arr = (L.ProblemItem * max(n_it, 1))()
+    keep = []
+    for i, terms in enumerate(terms_list):
+        affine = isinstance(terms, (list, tuple))
+        seq, carr = _csr_array(terms, affine, ctx.device, keep)
+        keep.append(carr)
+        arr[i] = L.ProblemItem(len(seq) if affine else 0, C.cast(carr, C.c_void_p), None, 0)
+    rc = L.pmor_problem_create_batch(ctx.handle, arr, n_it)
+    out, status = [], []
+    for i, terms in enumerate(terms_list):
+        status.append(arr[i].status)
+        out.append(Problem(ctx, terms, _handle=C.c_void_p(arr[i].pb)) if arr[i].pb else None)
+    if raise_on_error:
+        L.check(rc, "pmor_problem_create_batch")
+    return out, status, rc
 
 
 def spai_build_batch(ctx: Context, items, precision="f64", update="diag", raise_on_error=True):

@@ -495,6 +495,7 @@ int pmor_ctx_set_stream(pmor_ctx* c, void* hip_stream) {
   // work queued on the old stream (and the device memory it released into the
   // cache) completes before anything is ordered on the new one
   PMOR_HIP(hipStreamSynchronize(c->stream));
+  dstream_retire(c->stream);  // the caller may destroy the old stream
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   return PMOR_OK;
 }
@@ -502,10 +503,9 @@ int pmor_ctx_set_stream(pmor_ctx* c, void* hip_stream) {
 }  // extern "C"
 
 namespace pmor {
-// shared by both create calls: terms[0..count), NULL entries absent (roles only)
-static int problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, int count, bool affine, pmor_problem** out) {
-  if (!ctx || !terms || !out) return fail(PMOR_EINVAL, "NULL argument");
-  *out = nullptr;
+// checks shared by the create calls: terms[0..count), NULL entries absent
+// (roles only); *n_out the terms' common order
+static int check_terms(const pmor_csr* const* terms, int count, bool affine, int* n_out) {
   int n = -1;
   for (int r = 0; r < count; ++r) {
     const pmor_csr* T = terms[r];
@@ -520,18 +520,100 @@ static int problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, int count
     n = T->n;
   }
   if (n < 0) return fail(PMOR_EINVAL, "no term given");
-  PMOR_HIP(hipSetDevice(ctx->device));
+  *n_out = n;
+  return PMOR_OK;
+}
+
+static pmor_problem* problem_new(pmor_ctx* ctx, int n, bool affine) {
   pmor_problem* pb = new pmor_problem();
   pb->ctx = ctx;
   ctx_ref(ctx);
   pb->n = n;
   pb->affine = affine;
+  return pb;
+}
+
+static int problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, int count, bool affine, pmor_problem** out) {
+  if (!ctx || !terms || !out) return fail(PMOR_EINVAL, "NULL argument");
+  *out = nullptr;
+  int n = -1;
+  PMOR_TRY(check_terms(terms, count, affine, &n));
+  PMOR_HIP(hipSetDevice(ctx->device));
+  pmor_problem* pb = problem_new(ctx, n, affine);
   int rc = build_union_pattern(pb, terms, count);
   if (rc != PMOR_OK) {
     pb_unref(pb);
     return rc;
   }
   *out = pb;
+  return PMOR_OK;
+}
+
+// The union patterns of independent problems: a few small kernels per problem
+// with host synchronisations between them, so the problems are spread over
+// worker threads, each with a stream of its own (the handles themselves are
+// made and released on the calling thread).
+static int problem_create_batch_impl(pmor_ctx* ctx, pmor_problem_item* items, int32_t count) {
+  if (!ctx || (!items && count > 0)) return fail(PMOR_EINVAL, "NULL argument");
+  if (count < 0) return fail(PMOR_EINVAL, "count must not be negative");
+  PMOR_HIP(hipSetDevice(ctx->device));
+  std::vector<pmor_problem*> pbs(count, nullptr);
+  std::vector<int> irc(count, PMOR_OK);
+  std::vector<std::string> imsg(count);
+  auto nterms_of = [&](int i) { return items[i].nterms > 0 ? (int)items[i].nterms : (int)PMOR_NROLES; };
+  for (int i = 0; i < count; ++i) {
+    pmor_problem_item& it = items[i];
+    it.pb = nullptr;
+    it.status = PMOR_OK;
+    int n = -1;
+    if (it.nterms < 0 || it.nterms > PMOR_TMAX) irc[i] = fail(PMOR_EINVAL, "nterms must be in 0..PMOR_TMAX");
+    else if (!it.terms) irc[i] = fail(PMOR_EINVAL, "terms is NULL");
+    else irc[i] = check_terms(it.terms, nterms_of(i), it.nterms > 0, &n);
+    if (irc[i] != PMOR_OK) {
+      imsg[i] = g_last_error;
+      continue;
+    }
+    pbs[i] = problem_new(ctx, n, it.nterms > 0);
+  }
+  PMOR_HIP(hipStreamSynchronize(ctx->stream));  // the caller's work on the terms precedes the workers' reads
+  {
+    const int nthr = std::max(1, std::min<int>(count, 8));
+    std::vector<hipStream_t> ws(nthr, nullptr);
+    for (auto& x : ws)
+      if (hipStreamCreate(&x) != hipSuccess) { (void)hipGetLastError(); x = nullptr; }
+    std::atomic<int> next{0};
+    auto work = [&](int t) {
+      (void)hipSetDevice(ctx->device);
+      const hipStream_t s = ws[t] ? ws[t] : ctx->stream;
+      for (int i = next++; i < count; i = next++) {
+        if (!pbs[i]) continue;
+        irc[i] = build_union_pattern(pbs[i], items[i].terms, nterms_of(i), s);
+        if (irc[i] == PMOR_OK && hipStreamSynchronize(s) != hipSuccess) irc[i] = fail(PMOR_EHIP, "synchronise failed");
+        if (irc[i] != PMOR_OK) imsg[i] = g_last_error;
+      }
+    };
+    std::vector<std::thread> thr;
+    for (int t = 1; t < nthr; ++t) thr.emplace_back(work, t);
+    work(0);
+    for (auto& x : thr) x.join();
+    for (auto& x : ws)
+      if (x) {
+        (void)hipStreamSynchronize(x);
+        dstream_retire(x);
+        (void)hipStreamDestroy(x);
+      }
+  }
+  int first = -1;
+  for (int i = 0; i < count; ++i) {
+    items[i].status = irc[i];
+    if (irc[i] == PMOR_OK) {
+      items[i].pb = pbs[i];
+      continue;
+    }
+    if (pbs[i]) pb_unref(pbs[i]);
+    if (first < 0) first = i;
+  }
+  if (first >= 0) return fail(irc[first], "item " + std::to_string(first) + ": " + imsg[first]);
   return PMOR_OK;
 }
 
@@ -545,6 +627,10 @@ extern "C" {
 
 int pmor_problem_create(pmor_ctx* ctx, const pmor_csr* const* terms, pmor_problem** out) {
   return problem_create(ctx, terms, PMOR_NROLES, false, out);
+}
+
+int pmor_problem_create_batch(pmor_ctx* ctx, pmor_problem_item* items, int32_t count) {
+  return problem_create_batch_impl(ctx, items, count);
 }
 
 int pmor_problem_create_affine(pmor_ctx* ctx, int32_t nterms, const pmor_csr* const* terms, pmor_problem** out) {
@@ -768,7 +854,11 @@ static int spai_build_batch_impl(pmor_ctx* ctx, pmor_spai_build_item* items, int
     work(0);
     for (auto& x : thr) x.join();
     for (auto& x : ws)
-      if (x) (void)hipStreamDestroy(x);
+      if (x) {
+        (void)hipStreamSynchronize(x);
+        dstream_retire(x);
+        (void)hipStreamDestroy(x);
+      }
   }
   for (int i = 0; i < count; ++i) {
     pmor_spai_build_item& it = items[i];

@@ -249,6 +249,8 @@ void pb_unref(pmor_problem* pb);
 hipError_t dmalloc(void** p, size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 void dtrim();
+// before a stream of the library or a caller's old stream is destroyed (it is complete)
+void dstream_retire(hipStream_t s);
 
 int ensure_assembled(pmor_problem* pb, const Point& pt);
 // kernel timing: start returns a record index (-1 when kernel class `kid` is not profiled)
@@ -282,7 +284,7 @@ inline void plaunch(pmor_ctx* c, int idx, int part, F kernel, dim3 g, dim3 b, ui
 // launchers implemented in the kernel translation units
 int launch_assemble(pmor_problem* pb, const Point& pt, double* out, hipStream_t st);
 // union pattern of terms[0..count) (NULL entries absent); maps rows: one per entry of terms
-int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count);
+int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count, hipStream_t st = nullptr);
 // the SPAI index sets and buckets of h (on stream st, or the problem's when null)
 int build_spai_sets(pmor_spai* h, hipStream_t st = nullptr);
 // PMOR_EINVAL unless (rowptr, col) is an n x n CSR pattern of nnz entries with

@@ -440,8 +440,8 @@ int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* 
   return PMOR_OK;
 }
 
-int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count) {
-  hipStream_t st = pb->ctx->stream;
+int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int count, hipStream_t st) {
+  if (!st) st = pb->ctx->stream;
   const int n = pb->n;
   if (count < 1 || count > PMOR_TMAX) return fail(PMOR_EINVAL, "term count out of range");
   int* derr = nullptr;

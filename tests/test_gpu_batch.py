@@ -191,3 +191,38 @@ def test_spai_build_batch_equals_single_builds(ctx, precision):
     assert rc2 == L.PMOR_EINVAL and st2[:2] == [0, 0] and st2[2] == L.PMOR_EINVAL and hs2[2] is None
     fresh = pbs[0].spai_build(jobs[0].s, jobs[0].p_list[0], pattern=jobs[0].pattern, precision=precision)
     assert torch.equal(hs2[0].export()["val"], fresh.export()["val"])
+
+
+def test_problem_create_batch_equals_single_creates(ctx):
+    """pmor_problem_create_batch (union patterns built on worker streams) gives
+    every problem bit for bit the pattern, maps and assembled values of the
+    single create call, for problems of roles (the batch workload's systems and
+    the 64^3-like job) and an affine one; a malformed item fails alone."""
+    from paper_1809_06574_amd import Problem, problem_create_batch, lib as L
+    from synth.gen import config2_system
+    jobs = [config2_system(i) for i in (3, 17, 40, 41, 42, 43, 44, 45, 46, 47)]
+    c0 = config0()
+    aff = [c0.terms[r] for r in ("K0", "M0", "D0")]
+    terms_list = [j.terms for j in jobs] + [c0.terms, aff]
+    pbs, status, rc = problem_create_batch(ctx, terms_list)
+    assert rc == 0 and all(x == 0 for x in status)
+    for terms, pb in zip(terms_list, pbs):
+        ref = Problem(ctx, terms)
+        assert (pb.n, pb.nnz, pb.nmaps, pb.affine) == (ref.n, ref.nnz, ref.nmaps, ref.affine)
+        for a, b in zip(pb.pattern(), ref.pattern()):
+            assert torch.equal(a, b)
+        pt = ([1.0, 0.25, 2.0], None) if pb.affine else (2.0, 0.4)
+        assert torch.equal(pb.assemble(*pt), ref.assemble(*pt))
+    # a problem from the batch builds, updates and solves like any other
+    j = jobs[0]
+    h = pbs[0].spai_build(j.s, j.p_list[0], pattern=j.pattern)
+    h.update(j.s, j.p_list[1])
+    X, st, rc1 = pbs[0].block_solve(h, j.s, j.p_list[1], torch.as_tensor(j.B, device="cuda"))
+    assert rc1 == 0
+    _oracle_parity(j, j.s, j.p_list[1], h, np_(X), st)
+    # terms of different orders in one item: that item fails, the others are built
+    bad = dict(jobs[1].terms)
+    bad["K1"] = jobs[2].terms["K0"]
+    pbs2, st2, rc2 = problem_create_batch(ctx, [jobs[0].terms, bad, aff], raise_on_error=False)
+    assert rc2 == L.PMOR_EINVAL and st2 == [0, L.PMOR_EINVAL, 0] and pbs2[1] is None
+    assert torch.equal(pbs2[0].pattern()[1], pbs[0].pattern()[1])
