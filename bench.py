@@ -411,6 +411,10 @@ def main():
                         "avg_launch_us": 1e3 * ms / max(nl, 1),
                         "bytes_per_launch": by / max(nl, 1)},
            }
+    ceil = stream_ceiling(ctx, L, dom, 8 * job.n * _kp(job.k) * len(job.p_list), by / max(nl, 1))
+    if ceil is not None:
+        out["roofline"]["stream_ceiling"] = ceil
+        out["roofline"]["frac_of_stream_ceiling"] = achieved / ceil["at_kernel_mix"]
     if per_kernel:
         out["kernels"] = per_kernel
 
@@ -745,6 +749,39 @@ def c3_bench(factory, job, B, keep_points=None, kept=None):
 def _note(msg):
     """A progress line on stderr (the JSON result is the only stdout line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# blocks each Gram-Schmidt pass writes (kp = 4: pass 2 keeps W' in registers)
+SWEEP_WRITES = {"cgs_dot": 0, "cgs_upd_dot": 0, "cgs_upd_gram": 1}
+
+
+def _kp(k):
+    return 1 if k <= 1 else 2 if k <= 2 else 4 if k <= 4 else 8 if k <= 8 else 16
+
+
+def stream_ceiling(ctx, L, kernel, block_bytes, bytes_per_launch):
+    """What the chip streams with the read/write mix of a Gram-Schmidt sweep
+    (pmor_stream_probe: nread blocks of the workload's block size read, one more
+    written when the sweep writes one): GB/s at 8, 12 and 16 blocks read, with
+    and without the written block, and the kernel's achieved rate over the
+    ceiling interpolated at its own mix.  None for the other kernels."""
+    import ctypes as C
+    if kernel not in SWEEP_WRITES:
+        return None
+    rates = {}
+    for nr in (8, 12, 16):
+        for w in (0, 1):
+            us = C.c_double()
+            L.check(L.pmor_stream_probe(ctx.handle, nr, w, int(block_bytes), 10, C.byref(us)), "pmor_stream_probe")
+            rates[f"read{nr}" + ("_write1" if w else "")] = (nr + w) * block_bytes / (us.value * 1e-6) / 1e9
+    w = SWEEP_WRITES[kernel]
+    reads = min(max(bytes_per_launch / block_bytes - w, 8.0), 16.0)
+    lo = 8 if reads < 12 else 12
+    suf = "_write1" if w else ""
+    a, b = rates[f"read{lo}{suf}"], rates[f"read{lo + 4}{suf}"]
+    at_mix = a + (b - a) * (reads - lo) / 4.0
+    return {"unit": "GB/s", "block_MB": block_bytes / 1e6, "rates": rates, "kernel_reads_blocks": reads,
+            "kernel_writes_blocks": w, "at_kernel_mix": at_mix}
 
 
 def c2_bench(ctx, nsys, precision="f32", pool=True):

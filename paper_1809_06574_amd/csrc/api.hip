@@ -2052,6 +2052,86 @@ int pmor_spai_gather(const pmor_spai* h, double* colsum) {
   return run_spai_gather(const_cast<pmor_spai*>(h), colsum);
 }
 
+}  // extern "C"
+
+namespace pmor {
+// nread streams in, their element-wise sum out (WR) or kept (the sink store
+// never happens; it only keeps the loads)
+template <int NB, bool WR>
+__global__ __launch_bounds__(512) void k_stream_probe(const double* __restrict__ in, double* out, int64_t n,
+                                                      double* sink) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = __builtin_nontemporal_load(in + (int64_t)b * n + i);
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) s += v[b];
+    if (WR) out[i] = s;
+    else acc += s;
+  }
+  if (!WR && acc == -1.0) sink[0] = acc;
+}
+
+template <int NB>
+static void launch_stream_probe(bool wr, unsigned grid, hipStream_t st, const double* in, double* out, int64_t n,
+                                double* sink) {
+  if (wr) hipLaunchKernelGGL((k_stream_probe<NB, true>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
+  else hipLaunchKernelGGL((k_stream_probe<NB, false>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
+}
+}  // namespace pmor
+
+extern "C" {
+
+int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t write, int64_t nbytes, int32_t reps, double* us) {
+  if (!ctx || !us) return fail(PMOR_EINVAL, "NULL argument");
+  if (nread < 4 || nread > 32 || nread % 4 != 0) return fail(PMOR_EINVAL, "nread must be 4, 8, ..., 32");
+  if (nbytes <= 0 || nbytes % 8 != 0 || reps < 1) return fail(PMOR_EINVAL, "nbytes a positive multiple of 8, reps >= 1");
+  PMOR_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int64_t n = nbytes / 8;
+  double *in = nullptr, *out = nullptr;
+  PMOR_HIP(hipMalloc((void**)&in, (size_t)nbytes * nread));
+  if (hipMalloc((void**)&out, (size_t)nbytes + 64) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(in);
+    return fail(PMOR_ENOMEM, "stream probe: device memory");
+  }
+  int rc = PMOR_OK;
+  float ms = 0.0f;
+  if (hipMemsetAsync(in, 0, (size_t)nbytes * nread, st) != hipSuccess) rc = fail(PMOR_EHIP, "memset failed");
+  const unsigned grid = 8192;
+  auto pass = [&]() {
+    switch (nread) {
+      case 4: launch_stream_probe<4>(write != 0, grid, st, in, out, n, out + n); break;
+      case 8: launch_stream_probe<8>(write != 0, grid, st, in, out, n, out + n); break;
+      case 12: launch_stream_probe<12>(write != 0, grid, st, in, out, n, out + n); break;
+      case 16: launch_stream_probe<16>(write != 0, grid, st, in, out, n, out + n); break;
+      case 20: launch_stream_probe<20>(write != 0, grid, st, in, out, n, out + n); break;
+      case 24: launch_stream_probe<24>(write != 0, grid, st, in, out, n, out + n); break;
+      case 28: launch_stream_probe<28>(write != 0, grid, st, in, out, n, out + n); break;
+      default: launch_stream_probe<32>(write != 0, grid, st, in, out, n, out + n); break;
+    }
+  };
+  if (rc == PMOR_OK) {
+    pass();
+    pass();
+    if (hipEventRecord(ctx->ev0, st) != hipSuccess) rc = fail(PMOR_EHIP, "event record failed");
+    for (int r = 0; r < reps && rc == PMOR_OK; ++r) pass();
+    if (rc == PMOR_OK && hipGetLastError() != hipSuccess) rc = fail(PMOR_EHIP, "stream probe launch failed");
+    if (rc == PMOR_OK && (hipEventRecord(ctx->ev1, st) != hipSuccess || hipEventSynchronize(ctx->ev1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess))
+      rc = fail(PMOR_EHIP, "event timing failed");
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(in);
+  (void)hipFree(out);
+  if (rc != PMOR_OK) return rc;
+  *us = 1000.0 * (double)ms / reps;
+  return PMOR_OK;
+}
+
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id) {
   if (!ctx) return fail(PMOR_EINVAL, "ctx is NULL");
   if (kernel_id < 0 || kernel_id > PMOR_PROF_GCRO_GEMM) return fail(PMOR_EINVAL, "unknown kernel id");

@@ -152,6 +152,7 @@ _SIGS = {
     "pmor_spai_gather": (C.c_int, [P, P]),
     "pmor_prof_set": (C.c_int, [P, C.c_int]),
     "pmor_prof_read": (C.c_int, [P, C.POINTER(I64), C.POINTER(D), C.POINTER(D)]),
+    "pmor_stream_probe": (C.c_int, [P, I32, I32, I64, I32, C.POINTER(D)]),
     "pmor_strerror": (C.c_char_p, [C.c_int]),
     "pmor_last_error": (C.c_char_p, []),
 }
