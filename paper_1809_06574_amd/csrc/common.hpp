@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <cstring>
 
 #include <string>
@@ -144,7 +145,8 @@ struct Profiler {
 }  // namespace pmor
 
 struct pmor_ctx {
-  int refs = 1;                  // the caller's reference + one per problem and server
+  std::atomic<int> refs{1};      // the caller's reference + one per problem and server (batch calls take
+                                 // references from worker threads)
   int device = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -154,7 +156,7 @@ struct pmor_ctx {
 };
 
 struct pmor_problem {
-  int refs = 1;                // the caller's reference + one per preconditioner and queued job
+  std::atomic<int> refs{1};    // the caller's reference + one per preconditioner and queued job
   pmor_ctx* ctx = nullptr;
   int32_t n = 0, nnz = 0;
   int32_t* rowptr = nullptr;   // union pattern, CSR
