@@ -435,13 +435,19 @@ __global__ __launch_bounds__(256) void k_spai_reg(LsArgs a0) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS kernel: |J| <= 64, |I| <= 512; one wavefront per workgroup, its LDS sized
-// to the largest column of the launch (ldI x (JM + 1) values and ldI row
-// indices).  The gather goes by the columns of A: all rows of A(:, J_t) lie in
-// I_j (that is how I_j is defined), so lane t takes column J_t's entries in
-// CSC order and places each at its row's position in I_j, found by binary
-// search in the sorted rows held in LDS.
+// LDS kernel: |J| <= 64, |I| <= 512; one workgroup of LDS_NW wavefronts per
+// column, its LDS sized to the largest column of the launch (ldI x (JM + 1)
+// values and ldI row indices).  The gather goes by the columns of A: all rows
+// of A(:, J_t) lie in I_j (that is how I_j is defined), so thread t takes
+// column J_t's entries in CSC order and places each at its row's position in
+// I_j, found by binary search in the sorted rows held in LDS.  In the
+// Householder steps wavefront w owns the columns k + w CH, k + (w + NW) CH, ...
+// (chunks of CH): it forms their inner products with the reflector over all
+// rows and updates them, each sum taken by one wavefront in one order, so the
+// result does not depend on the number of wavefronts.
 // ---------------------------------------------------------------------------
+constexpr int LDS_NW = 4;
+
 __device__ __forceinline__ int lds_lower_bound(const int* rows, int len, int r) {
   int lo = 0, hi = len;
   while (lo < hi) {
@@ -453,13 +459,14 @@ __device__ __forceinline__ int lds_lower_bound(const int* rows, int len, int r) 
 }
 
 template <typename T, bool Q16 = false, bool GO = false, bool MULTI = false>
-__global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
+__global__ __launch_bounds__(64 * LDS_NW) void k_spai_lds(LsArgs a0, int ldI, int JM) {
+  constexpr int NW = LDS_NW, NT = 64 * NW;
   extern __shared__ unsigned char smem_raw[];
   T* S = reinterpret_cast<T*>(smem_raw);  // column-major [nj + 1][ldI]: A_hat then rhs (JM >= nj)
   int* Is = reinterpret_cast<int*>(S + (size_t)(JM + 1) * ldI);  // the rows I_j
   __shared__ double sv[66];
   __shared__ T sf[66];  // the reflector's factor per column
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wid = blockIdx.x;
   if (wid >= a0.ncols) return;
   LsArgs a = a0;
@@ -476,15 +483,15 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
   const int64_t ib = a.Icolptr[j];
   const int ni = (int)(a.Icolptr[j + 1] - ib);
   T* B = S + (size_t)nj * ldI;  // the right-hand side is column nj of S
-  for (int li = lane; li < ni; li += 64) Is[li] = a.Irow[ib + li];
+  for (int li = tid; li < ni; li += NT) Is[li] = a.Irow[ib + li];
   for (int t = 0; t <= nj; ++t) {
     T* colt = (t < nj) ? S + (size_t)t * ldI : B;
-    for (int li = lane; li < ni; li += 64) colt[li] = T(0);
+    for (int li = tid; li < ni; li += NT) colt[li] = T(0);
   }
   __syncthreads();
-  if (lane < nj) {
-    const int c = a.Jrow[jb + lane];
-    T* colt = S + (size_t)lane * ldI;
+  if (tid < nj) {
+    const int c = a.Jrow[jb + tid];
+    T* colt = S + (size_t)tid * ldI;
     int q = 0;
     for (int e = a.Acolptr[c]; e < a.Acolptr[c + 1]; ++e) {
       const int r = a.Arowidx[e];
@@ -493,13 +500,14 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
     }
   }
   if (a.rhs_aval) {  // A(1) e_j on I_j: the entries of column j
-    for (int e = a.Acolptr[j] + lane; e < a.Acolptr[j + 1]; e += 64)
+    for (int e = a.Acolptr[j] + tid; e < a.Acolptr[j + 1]; e += NT)
       B[lds_lower_bound(Is, ni, a.Arowidx[e])] = (T)a.rhs_aval[a.Acscslot[e]];
-  } else if (lane == 0) {
+  } else if (tid == 0) {
     B[lds_lower_bound(Is, ni, j)] = T(1);
   }
   __syncthreads();
   if constexpr (GO) {  // gather only: the block's sum into rho[j]
+    if (w != 0) return;
     T acc = T(0);
     for (int t = 0; t < nj; ++t)
       for (int li = lane; li < ni; li += 64) acc += S[(size_t)t * ldI + li];
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
     return;
   }
   if constexpr (Q16) {
-    for (int t = 0; t <= nj; ++t) {
+    for (int t = w; t <= nj; t += NW) {
       if (t == nj && !a.rhs_aval) break;
       T* colt = (t < nj) ? S + (size_t)t * ldI : B;
       T mx = T(0);
@@ -521,9 +529,10 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
   T minDiag = T(3.0e38);
   constexpr int CH = 8;  // columns per chunk: independent sums side by side
   for (int k = 0; k < nj; ++k) {
-    // s[c] = x . a_c for c in [k, nj) and x . b (c = nj), CH columns per pass
+    // s[c] = x . a_c for c in [k, nj) and x . b (c = nj), CH columns per pass,
+    // the chunks dealt out to the wavefronts
     const T* colk = S + (size_t)k * ldI;
-    for (int c0 = k; c0 <= nj; c0 += CH) {
+    for (int c0 = k + w * CH; c0 <= nj; c0 += NW * CH) {
       T part[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) part[u] = T(0);
@@ -548,12 +557,13 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
       const T nrm = sqrt(sig);
       beta = (alpha >= T(0)) ? -nrm : nrm;
       const T denom = beta * (beta - alpha);
-      // the factors of every column (a_c(k) is read before any lane writes it)
-      for (int c = k + 1 + lane; c <= nj; c += 64) sf[c] = ((T)sv[c - k] - beta * S[(size_t)c * ldI + k]) / denom;
+      // the factors of every column (a_c(k) is read before any thread writes it)
+      for (int c = k + 1 + tid; c <= nj; c += NT) sf[c] = ((T)sv[c - k] - beta * S[(size_t)c * ldI + k]) / denom;
       __syncthreads();
+      // wavefront w updates the columns of its chunks, starting after column k
       for (int li = k + lane; li < ni; li += 64) {
         const T v = (li == k) ? (alpha - beta) : colk[li];
-        for (int c0 = k + 1; c0 <= nj; c0 += CH) {
+        for (int c0 = k + 1 + w * CH; c0 <= nj; c0 += NW * CH) {
 #pragma unroll
           for (int u = 0; u < CH; ++u)
             if (c0 + u <= nj) S[(size_t)(c0 + u) * ldI + li] -= sf[c0 + u] * v;
@@ -561,12 +571,13 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
       }
     }
     __syncthreads();
-    if (lane == 0) S[(size_t)k * ldI + k] = beta;
-    for (int li = k + 1 + lane; li < ni; li += 64) S[(size_t)k * ldI + li] = T(0);
+    if (tid == 0) S[(size_t)k * ldI + k] = beta;
+    for (int li = k + 1 + tid; li < ni; li += NT) S[(size_t)k * ldI + li] = T(0);
     __syncthreads();
     const T ab = beta < T(0) ? -beta : beta;
     minDiag = ab < minDiag ? ab : minDiag;
   }
+  // every wavefront forms max|R| and the residual itself (same values in each)
   T mx = T(0);
   for (int q = lane; q < nj * nj; q += 64) {
     const int r = q % nj, c = q / nj;
@@ -582,10 +593,11 @@ __global__ __launch_bounds__(64) void k_spai_lds(LsArgs a0, int ldI, int JM) {
     __syncthreads();
     const T pi = B[i] / S[(size_t)i * ldI + i];
     __syncthreads();
-    if (lane == 0) B[i] = pi;
-    for (int r = lane; r < i; r += 64) B[r] -= S[(size_t)i * ldI + r] * pi;
+    if (tid == 0) B[i] = pi;
+    for (int r = tid; r < i; r += NT) B[r] -= S[(size_t)i * ldI + r] * pi;
   }
   __syncthreads();
+  if (w != 0) return;
   T rr = T(0);
   for (int li = nj + lane; li < ni; li += 64) rr += B[li] * B[li];
   rr = wave_sum(rr);
@@ -639,7 +651,7 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
       const size_t shm = sizeof(T) * (size_t)(maxJ + 1) * ldI + sizeof(int) * (size_t)ldI;
       if (shm > 150 * 1024) return fail(PMOR_EINVAL, "SPAI pattern too large for the LDS least-squares kernel");
       PMOR_TRY(allow_lds((const void*)k_spai_lds<T, Q16, GO, MULTI>, shm));
-      plaunch(pc, pidx, part, k_spai_lds<T, Q16, GO, MULTI>, dim3((unsigned)a.ncols), dim3(64), (uint32_t)shm, st, a,
+      plaunch(pc, pidx, part, k_spai_lds<T, Q16, GO, MULTI>, dim3((unsigned)a.ncols), dim3(64 * LDS_NW), (uint32_t)shm, st, a,
               ldI, maxJ);
       break;
     }
