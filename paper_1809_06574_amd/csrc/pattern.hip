@@ -619,11 +619,16 @@ __global__ __launch_bounds__(256) void k_shadow_small(int n, const int32_t* Jcol
 
 // columns SH_SMALL < |J_j| <= SH_JMAX with at most SH_CAP candidates: one
 // wavefront per column (grid-stride over the columns, the others skipped) copies
-// the candidate rows into LDS, sorts them (bitonic) and keeps the distinct rows
+// the candidate rows into LDS, sorts them (bitonic) and keeps the distinct rows.
+// With a staging array (tmp, non-null in both passes) the counting pass also
+// leaves the distinct rows of column j at tmp + Jcolptr[j] mcl (there are at
+// most |J_j| mcl candidates, mcl the longest column of A) and the filling pass
+// copies them to their place instead of sorting again.
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolptr, const int32_t* Jrow,
                                                     const int32_t* Acolptr, const int32_t* Arowidx, int64_t* counts,
-                                                    const int64_t* Icolptr, int32_t* Irow, int* maxJ, int* maxI) {
+                                                    const int64_t* Icolptr, int32_t* Irow, int* maxJ, int* maxI,
+                                                    int32_t* tmp, int mcl) {
   __shared__ int buf[SH_CAP];
   const int lane = threadIdx.x;
   int mj = 0, mi = 0;
@@ -649,6 +654,11 @@ __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolpt
     }
     const int total = __shfl(incl, 63, 64);
     if (total > SH_CAP) continue;  // k_shadow_merge
+    if (FILL && tmp) {  // the counting pass left the rows in tmp
+      const int64_t src = (int64_t)ja * mcl, dst = Icolptr[j], cnt = Icolptr[j + 1] - dst;
+      for (int64_t q = lane; q < cnt; q += 64) Irow[dst + q] = tmp[src + q];
+      continue;
+    }
     const int off = incl - len;
     int P = 1;
     while (P < total) P <<= 1;
@@ -678,6 +688,7 @@ __global__ __launch_bounds__(64) void k_shadow_sort(int n, const int32_t* Jcolpt
       const bool keep = i < total && (i == 0 || buf[i] != buf[i - 1]);
       const unsigned long long m = __ballot(keep);
       if (FILL && keep) Irow[pos + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
+      if (!FILL && tmp && keep) tmp[(int64_t)ja * mcl + cnt + __popcll(m & ((1ull << lane) - 1ull))] = buf[i];
       cnt += __popcll(m);
     }
     if (!FILL && lane == 0) counts[j] = cnt;
@@ -731,11 +742,12 @@ __global__ void k_shadow_merge(int n, const int32_t* Jcolptr, const int32_t* Jro
   }
 }
 
-// jmax: an upper bound of |J_j| known on the host, or -1
+// jmax: an upper bound of |J_j| known on the host, or -1; tmp, mcl: the
+// staging array of k_shadow_sort (or null)
 template <bool FILL>
 static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, const int32_t* Acolptr,
                          const int32_t* Arowidx, int64_t* counts, const int64_t* Icolptr, int32_t* Irow, int* maxJ,
-                         int* maxI, int jmax, hipStream_t st) {
+                         int* maxI, int jmax, hipStream_t st, int32_t* tmp = nullptr, int mcl = 0) {
   if (n <= 0) return PMOR_OK;
   const unsigned g1 = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_shadow_small<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
@@ -746,7 +758,7 @@ static int launch_shadow(int n, const int32_t* Jcolptr, const int32_t* Jrow, con
   }
   const unsigned gs = (unsigned)std::min(n, 8192);
   hipLaunchKernelGGL(k_shadow_sort<FILL>, dim3(gs), dim3(64), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
-                     Icolptr, Irow, maxJ, maxI);
+                     Icolptr, Irow, maxJ, maxI, tmp, mcl);
   hipLaunchKernelGGL(k_shadow_merge<FILL>, dim3(g1), dim3(256), 0, st, n, Jcolptr, Jrow, Acolptr, Arowidx, counts,
                      Icolptr, Irow, maxJ, maxI);
   PMOR_HIP(hipGetLastError());
@@ -886,8 +898,15 @@ int build_spai_sets(pmor_spai* h, hipStream_t st) {
   const int jmax = h->opts.pattern == PMOR_PAT_A ? pb->max_col_len : -1;
   int64_t* cnt = nullptr;
   PMOR_HIP(dmalloc((void**)&cnt, sizeof(int64_t) * (n + 1), st));
+  // the sorted shadows of the sorting kernel staged between the two passes (one
+  // sort instead of two) when |J| mcl bounds fit in 256 MiB
+  const int mcl = pb->max_col_len;
+  const int64_t tcap = (int64_t)h->nnzP * mcl;
+  int32_t* stage = nullptr;
+  if (tcap > 0 && tcap <= ((int64_t)64 << 20) && !(jmax >= 0 && jmax <= SH_SMALL))
+    PMOR_HIP(dmalloc((void**)&stage, sizeof(int32_t) * tcap, st));
   PMOR_TRY(launch_shadow<false>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, cnt, nullptr, nullptr, dflag + 1,
-                                dflag + 2, jmax, st));
+                                dflag + 2, jmax, st, stage, mcl));
   constexpr int S = BUCKET_SLOTS;
   int* bc = nullptr;  // counts [0, S), offsets [S, 2S), largest |J| [2S, 3S), largest |I| [3S, 4S)
   PMOR_HIP(dmalloc((void**)&bc, sizeof(int) * 4 * S, st));
@@ -907,12 +926,14 @@ int build_spai_sets(pmor_spai* h, hipStream_t st) {
   h->Icolptr = cnt;
   if (h->maxJ > 64 || h->maxI > 512) {
     dfree(bc, st); dfree(dflag, st);
+    if (stage) dfree(stage, st);
     return fail(PMOR_EINVAL, "SPAI pattern too large: |J_j| <= 64 and |I_j| <= 512 are supported (got " +
                                  std::to_string(h->maxJ) + ", " + std::to_string(h->maxI) + ")");
   }
   PMOR_HIP(dmalloc((void**)&h->Irow, sizeof(int32_t) * (h->nI > 0 ? h->nI : 1), st));
   PMOR_TRY(launch_shadow<true>(n, h->Jcolptr, h->Jrow, pb->colptr, pb->rowidx, nullptr, h->Icolptr, h->Irow, nullptr,
-                               nullptr, jmax, st));
+                               nullptr, jmax, st, stage, mcl));
+  if (stage) dfree(stage, st);
   int off = 0, nonempty = 0;
   for (int b = 0; b < S; ++b) {
     h->bucket_count[b] = hb[b];
