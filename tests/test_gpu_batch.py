@@ -226,3 +226,12 @@ def test_problem_create_batch_equals_single_creates(ctx):
     pbs2, st2, rc2 = problem_create_batch(ctx, [jobs[0].terms, bad, aff], raise_on_error=False)
     assert rc2 == L.PMOR_EINVAL and st2 == [0, L.PMOR_EINVAL, 0] and pbs2[1] is None
     assert torch.equal(pbs2[0].pattern()[1], pbs[0].pattern()[1])
+    # a column index out of range, found by the device validation on a worker stream
+    K = jobs[3].terms["K0"]
+    col = np.array(K.col, copy=True)
+    col[5] = jobs[3].n + 7
+    broken = dict(jobs[3].terms)
+    broken["K0"] = (np.asarray(K.rowptr), col, np.asarray(K.val))
+    pbs3, st3, rc3 = problem_create_batch(ctx, [aff, broken, jobs[4].terms], raise_on_error=False)
+    assert rc3 == L.PMOR_EINVAL and st3 == [0, L.PMOR_EINVAL, 0] and pbs3[1] is None
+    assert torch.equal(pbs3[2].pattern()[1], pbs[4].pattern()[1])
