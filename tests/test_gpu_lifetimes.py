@@ -45,3 +45,36 @@ def test_destroy_in_any_order(gpu_lib, order):
     job, pb2, h2 = _problem_and_spai(ctx2)
     X2, st2, rc2 = pb2.block_solve(h2, job.s, job.p_list[0], torch.as_tensor(job.B, device="cuda"))
     assert rc2 == 0 and torch.equal(X, X2)
+
+
+def test_stream_replaced_and_destroyed(gpu_lib):
+    """A context's stream replaced (pmor_ctx_set_stream) and the old one destroyed
+    (hipStreamDestroy): device blocks the library released on the old stream are
+    handed out again afterwards without touching it, and the results equal those
+    of a context that kept one stream."""
+    from paper_1809_06574_amd import lib as L, Problem
+    hip = C.CDLL("libamdhip64.so")
+    ctx = make_ctx()
+    job = config0()
+    B = torch.as_tensor(job.B, device="cuda")
+    ref_pb = Problem(ctx, job.terms)
+    ref_h = ref_pb.spai_build(job.s, job.p_list[1])
+    Xr, _, _ = ref_pb.block_solve(ref_h, job.s, job.p_list[1], B)
+    torch.cuda.synchronize()
+    side = C.c_void_p()
+    assert hip.hipStreamCreate(C.byref(side)) == 0
+    assert L.pmor_ctx_set_stream(ctx.handle, side) == 0
+    for _ in range(3):  # blocks released on the side stream
+        pb = Problem(ctx, job.terms)
+        h = pb.spai_build(job.s, job.p_list[0])
+        pb.block_solve(h, job.s, job.p_list[0], B)
+        h.close()
+        pb.close()
+    assert L.pmor_ctx_set_stream(ctx.handle, C.c_void_p(ctx.stream.cuda_stream)) == 0
+    assert hip.hipStreamDestroy(side) == 0
+    pb = Problem(ctx, job.terms)
+    h = pb.spai_build(job.s, job.p_list[1])
+    X, st, rc = pb.block_solve(h, job.s, job.p_list[1], B)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(X, Xr)
