@@ -252,6 +252,14 @@ def spmm_rooflines(ctx, L, sizes=((64, 64, 64, 20), (128, 128, 64, 20), (128, 12
             rec[name] = {"launches": n_, "avg_us": 1e3 * ms_ / max(n_, 1), "GBps": by_ / max(ms_ * 1e-3, 1e-12) / 1e9,
                          "bytes_per_launch": by_ / max(n_, 1)}
             rec[name]["frac"] = rec[name]["GBps"] / HBM_PEAK_GBS
+            # the streaming ceiling at the launch's mix of distinct bytes: blocks of
+            # n kp doubles per point, W written (A) or V_j and Z written (P)
+            blk = 8.0 * job.n * 4 * npts
+            wr = 1 if name == "spmm_a" else 2
+            at, rates = mix_ceiling(ctx, L, blk, rec[name]["bytes_per_launch"] / blk - wr, wr, {})
+            rec[name]["stream_ceiling"] = {"reads_blocks": rec[name]["bytes_per_launch"] / blk - wr,
+                                           "writes_blocks": wr, "at_mix_GBps": at, "rates": rates}
+            rec[name]["frac_of_stream_ceiling"] = rec[name]["GBps"] / at
         pb.close()
         del terms, B, X
         torch.cuda.synchronize()
@@ -753,35 +761,52 @@ def _note(msg):
 
 # blocks each Gram-Schmidt pass writes (kp = 4: pass 2 keeps W' in registers)
 SWEEP_WRITES = {"cgs_dot": 0, "cgs_upd_dot": 0, "cgs_upd_gram": 1}
+PROBE_READS = (1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24, 28, 32)
 
 
 def _kp(k):
     return 1 if k <= 1 else 2 if k <= 2 else 4 if k <= 4 else 8 if k <= 8 else 16
 
 
-def stream_ceiling(ctx, L, kernel, block_bytes, bytes_per_launch):
-    """What the chip streams with the read/write mix of a Gram-Schmidt sweep
-    (pmor_stream_probe: nread blocks of the workload's block size read, one more
-    written when the sweep writes one): GB/s at 8, 12 and 16 blocks read, with
-    and without the written block, and the kernel's achieved rate over the
-    ceiling interpolated at its own mix.  None for the other kernels."""
+def mix_ceiling(ctx, L, block_bytes, reads, writes, cache):
+    """What the chip streams with a kernel's read/write mix (pmor_stream_probe:
+    blocks of block_bytes, `writes` of them written): the probe at the two
+    allowed read counts around `reads`, interpolated linearly.  Returns
+    (GB/s at the mix, {probe key: GB/s})."""
     import ctypes as C
+    reads = min(max(reads, PROBE_READS[0]), PROBE_READS[-1])
+    lo = max(r for r in PROBE_READS if r <= reads)
+    hi = min(r for r in PROBE_READS if r >= reads)
+    rates = {}
+    for nr in sorted({lo, hi}):
+        key = (int(block_bytes), nr, writes)
+        if key not in cache:
+            us = C.c_double()
+            L.check(L.pmor_stream_probe(ctx.handle, nr, writes, int(block_bytes), 10, C.byref(us)),
+                    "pmor_stream_probe")
+            cache[key] = (nr + writes) * block_bytes / (us.value * 1e-6) / 1e9
+        rates[f"read{nr}_write{writes}"] = cache[key]
+    a, b = rates[f"read{lo}_write{writes}"], rates[f"read{hi}_write{writes}"]
+    at = a if hi == lo else a + (b - a) * (reads - lo) / (hi - lo)
+    return at, rates
+
+
+def stream_ceiling(ctx, L, kernel, block_bytes, bytes_per_launch):
+    """The streaming ceiling of a Gram-Schmidt sweep at its own read/write mix
+    (None for the other kernels), with the read-only and one-write rates at 8,
+    12 and 16 blocks for reference."""
     if kernel not in SWEEP_WRITES:
         return None
-    rates = {}
+    cache = {}
     for nr in (8, 12, 16):
         for w in (0, 1):
-            us = C.c_double()
-            L.check(L.pmor_stream_probe(ctx.handle, nr, w, int(block_bytes), 10, C.byref(us)), "pmor_stream_probe")
-            rates[f"read{nr}" + ("_write1" if w else "")] = (nr + w) * block_bytes / (us.value * 1e-6) / 1e9
+            mix_ceiling(ctx, L, block_bytes, nr, w, cache)
     w = SWEEP_WRITES[kernel]
-    reads = min(max(bytes_per_launch / block_bytes - w, 8.0), 16.0)
-    lo = 8 if reads < 12 else 12
-    suf = "_write1" if w else ""
-    a, b = rates[f"read{lo}{suf}"], rates[f"read{lo + 4}{suf}"]
-    at_mix = a + (b - a) * (reads - lo) / 4.0
+    reads = bytes_per_launch / block_bytes - w
+    at, _ = mix_ceiling(ctx, L, block_bytes, reads, w, cache)
+    rates = {f"read{k[1]}_write{k[2]}": v for k, v in sorted(cache.items(), key=lambda kv: (kv[0][2], kv[0][1]))}
     return {"unit": "GB/s", "block_MB": block_bytes / 1e6, "rates": rates, "kernel_reads_blocks": reads,
-            "kernel_writes_blocks": w, "at_kernel_mix": at_mix}
+            "kernel_writes_blocks": w, "at_kernel_mix": at}
 
 
 def c2_bench(ctx, nsys, precision="f32", pool=True):

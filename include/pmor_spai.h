@@ -586,15 +586,15 @@ int pmor_spai_gather(const pmor_spai* h, double* colsum);
 #define PMOR_PROF_GCRO_GEMM 9     /* block GCRO-DR product Y = beta Y + alpha A G: 8 n (a + b) (+ 8 n b read when beta != 0) */
 int pmor_prof_set(pmor_ctx* ctx, int kernel_id);
 int pmor_prof_read(pmor_ctx* ctx, int64_t* launches, double* total_ms, double* total_bytes);
-/* The streaming rate the row sweeps run against: nread arrays of nbytes each
- * (nread in 4, 8, ..., 32; nbytes a positive multiple of 8) read once with
- * non-temporal loads over the whole device, the element-wise sum written to one
- * more array of nbytes when write != 0 (the read/write mix of an update pass),
- * else kept in registers.  *us: average microseconds of one pass over reps
+/* The streaming rate a kernel with a given read/write mix runs against: nread
+ * arrays of nbytes each (nread 1..8 or 12, 16, ..., 32; nbytes a positive
+ * multiple of 8) read once with non-temporal loads over the whole device, their
+ * element-wise sum written to nwrite (0, 1 or 2) more arrays of nbytes (kept in
+ * registers when nwrite is 0).  *us: average microseconds of one pass over reps
  * (>= 1) timed passes after two untimed ones, on ctx's stream.  Allocates and
- * frees (nread + 1) nbytes of device memory itself (hipMalloc, hipFree) and
+ * frees (nread + nwrite) nbytes of device memory itself (hipMalloc, hipFree) and
  * synchronises.  A measurement aid, no step of the method. */
-int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t write, int64_t nbytes, int32_t reps, double* us);
+int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t nwrite, int64_t nbytes, int32_t reps, double* us);
 
 /* ---- errors ------------------------------------------------------------ */
 const char* pmor_strerror(int code);

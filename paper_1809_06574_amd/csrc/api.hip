@@ -2055,9 +2055,9 @@ int pmor_spai_gather(const pmor_spai* h, double* colsum) {
 }  // extern "C"
 
 namespace pmor {
-// nread streams in, their element-wise sum out (WR) or kept (the sink store
-// never happens; it only keeps the loads)
-template <int NB, bool WR>
+// nread streams in; their element-wise sum out to NWR streams, or kept (the
+// sink store never happens; it only keeps the loads)
+template <int NB, int NWR>
 __global__ __launch_bounds__(512) void k_stream_probe(const double* __restrict__ in, double* out, int64_t n,
                                                       double* sink) {
   double acc = 0.0;
@@ -2068,32 +2068,36 @@ __global__ __launch_bounds__(512) void k_stream_probe(const double* __restrict__
     double s = 0.0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) s += v[b];
-    if (WR) out[i] = s;
-    else acc += s;
+    if (NWR >= 1) out[i] = s;
+    if (NWR >= 2) out[n + i] = 0.5 * s;
+    if (NWR == 0) acc += s;
   }
-  if (!WR && acc == -1.0) sink[0] = acc;
+  if (NWR == 0 && acc == -1.0) sink[0] = acc;
 }
 
 template <int NB>
-static void launch_stream_probe(bool wr, unsigned grid, hipStream_t st, const double* in, double* out, int64_t n,
+static void launch_stream_probe(int nwr, unsigned grid, hipStream_t st, const double* in, double* out, int64_t n,
                                 double* sink) {
-  if (wr) hipLaunchKernelGGL((k_stream_probe<NB, true>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
-  else hipLaunchKernelGGL((k_stream_probe<NB, false>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
+  if (nwr == 0) hipLaunchKernelGGL((k_stream_probe<NB, 0>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
+  else if (nwr == 1) hipLaunchKernelGGL((k_stream_probe<NB, 1>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
+  else hipLaunchKernelGGL((k_stream_probe<NB, 2>), dim3(grid), dim3(512), 0, st, in, out, n, sink);
 }
 }  // namespace pmor
 
 extern "C" {
 
-int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t write, int64_t nbytes, int32_t reps, double* us) {
+int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t nwrite, int64_t nbytes, int32_t reps, double* us) {
   if (!ctx || !us) return fail(PMOR_EINVAL, "NULL argument");
-  if (nread < 4 || nread > 32 || nread % 4 != 0) return fail(PMOR_EINVAL, "nread must be 4, 8, ..., 32");
+  if (!(nread >= 1 && (nread <= 8 || (nread <= 32 && nread % 4 == 0))))
+    return fail(PMOR_EINVAL, "nread must be 1..8 or 12, 16, ..., 32");
+  if (nwrite < 0 || nwrite > 2) return fail(PMOR_EINVAL, "nwrite must be 0, 1 or 2");
   if (nbytes <= 0 || nbytes % 8 != 0 || reps < 1) return fail(PMOR_EINVAL, "nbytes a positive multiple of 8, reps >= 1");
   PMOR_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   const int64_t n = nbytes / 8;
   double *in = nullptr, *out = nullptr;
   PMOR_HIP(hipMalloc((void**)&in, (size_t)nbytes * nread));
-  if (hipMalloc((void**)&out, (size_t)nbytes + 64) != hipSuccess) {
+  if (hipMalloc((void**)&out, (size_t)nbytes * nwrite + 64) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(in);
     return fail(PMOR_ENOMEM, "stream probe: device memory");
@@ -2102,16 +2106,23 @@ int pmor_stream_probe(pmor_ctx* ctx, int32_t nread, int32_t write, int64_t nbyte
   float ms = 0.0f;
   if (hipMemsetAsync(in, 0, (size_t)nbytes * nread, st) != hipSuccess) rc = fail(PMOR_EHIP, "memset failed");
   const unsigned grid = 8192;
+  double* sink = out + (int64_t)nwrite * n;
   auto pass = [&]() {
     switch (nread) {
-      case 4: launch_stream_probe<4>(write != 0, grid, st, in, out, n, out + n); break;
-      case 8: launch_stream_probe<8>(write != 0, grid, st, in, out, n, out + n); break;
-      case 12: launch_stream_probe<12>(write != 0, grid, st, in, out, n, out + n); break;
-      case 16: launch_stream_probe<16>(write != 0, grid, st, in, out, n, out + n); break;
-      case 20: launch_stream_probe<20>(write != 0, grid, st, in, out, n, out + n); break;
-      case 24: launch_stream_probe<24>(write != 0, grid, st, in, out, n, out + n); break;
-      case 28: launch_stream_probe<28>(write != 0, grid, st, in, out, n, out + n); break;
-      default: launch_stream_probe<32>(write != 0, grid, st, in, out, n, out + n); break;
+      case 1: launch_stream_probe<1>(nwrite, grid, st, in, out, n, sink); break;
+      case 2: launch_stream_probe<2>(nwrite, grid, st, in, out, n, sink); break;
+      case 3: launch_stream_probe<3>(nwrite, grid, st, in, out, n, sink); break;
+      case 4: launch_stream_probe<4>(nwrite, grid, st, in, out, n, sink); break;
+      case 5: launch_stream_probe<5>(nwrite, grid, st, in, out, n, sink); break;
+      case 6: launch_stream_probe<6>(nwrite, grid, st, in, out, n, sink); break;
+      case 7: launch_stream_probe<7>(nwrite, grid, st, in, out, n, sink); break;
+      case 8: launch_stream_probe<8>(nwrite, grid, st, in, out, n, sink); break;
+      case 12: launch_stream_probe<12>(nwrite, grid, st, in, out, n, sink); break;
+      case 16: launch_stream_probe<16>(nwrite, grid, st, in, out, n, sink); break;
+      case 20: launch_stream_probe<20>(nwrite, grid, st, in, out, n, sink); break;
+      case 24: launch_stream_probe<24>(nwrite, grid, st, in, out, n, sink); break;
+      case 28: launch_stream_probe<28>(nwrite, grid, st, in, out, n, sink); break;
+      default: launch_stream_probe<32>(nwrite, grid, st, in, out, n, sink); break;
     }
   };
   if (rc == PMOR_OK) {
