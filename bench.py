@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain 1 GiB device copies (reference for the HBM byte counters)")
     ap.add_argument("--serve-rho", default="0.5,0.8,0.95", help="comma-separated loads rho of the serving runs")
-    ap.add_argument("--only", choices=["gcrodr", "complex", "batch"],
+    ap.add_argument("--only", choices=["gcrodr", "complex", "batch", "ceiling"],
                     help="run one arm by itself and print its JSON (for profiling it)")
     ap.add_argument("--c2-no-pool", action="store_true",
                     help="generate the batch workload's systems in this process (no worker processes)")
@@ -356,6 +356,13 @@ def main():
             res = gcrodr_bench(ctx, factory, job, B)
         elif args.only == "complex":
             res = complex_bench(ctx)
+        elif args.only == "ceiling":  # the streaming probe at the job's block size, reads 1..32 with 0..2 writes
+            cache = {}
+            blk = 8 * job.n * _kp(job.k) * len(job.p_list)
+            for w in (0, 1, 2):
+                for nr in (1, 2, 3, 4, 8, 12, 16, 24, 32):
+                    mix_ceiling(ctx, L, blk, nr, w, cache)
+            res = {"block_MB": blk / 1e6, "GBps": {f"read{k[1]}_write{k[2]}": v for k, v in cache.items()}}
         else:
             res = c2_bench(ctx, args.c2_systems, pool=not args.c2_no_pool)
         print(json.dumps({"only": args.only, args.only: res}), flush=True)
