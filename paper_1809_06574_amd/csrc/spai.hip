@@ -609,9 +609,162 @@ __global__ __launch_bounds__(64 * LDS_NW) void k_spai_lds(LsArgs a0, int ldI, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column-owner kernel: |J| <= JM, |I| <= 64, 4-byte values (the (32, 64)
+// bucket: against the register kernel's two columns per wavefront it takes 0.54
+// of the time on the batch workload; for |J| <= 16 the register kernel's four
+// columns per wavefront stay faster, most lanes here would idle).  One
+// 64-lane workgroup per column j.  Lane c holds column c of A(I_j, J_j), all 64
+// rows in registers, and lane |J_j| the right-hand side, so every inner product
+// a reflector step needs is a sum inside one lane; only the reflector crosses
+// lanes (its owner writes it to LDS, every lane reads it back as a broadcast).
+// The reflector loop is unrolled over k, so every register index is static.
+// The gather and the back substitution go through LDS as in k_spai_lds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float readlane_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+template <typename T, int JM, bool Q16 = false, bool MULTI = false>
+__global__ __launch_bounds__(64) void k_spai_col(LsArgs a0) {
+  static_assert(sizeof(T) == 4, "four-byte values");
+  constexpr int IM = 64, LD = IM + 1;  // rows; LDS column stride (odd: the column reads spread over the banks)
+  __shared__ T S[(JM + 1) * LD];       // column-major: A_hat's columns, then the right-hand side
+  __shared__ int Is[IM];
+  __shared__ T sv[IM];                 // the reflector's column of the current step
+  const int lane = threadIdx.x;
+  const int wid = xcd_swizzle(blockIdx.x, gridDim.x);
+  if (wid >= a0.ncols) return;
+  LsArgs a = a0;
+  int wl = wid;
+  if constexpr (MULTI) {
+    const int sy = ls_system(a0.seg, a0.nsys, wid);
+    a = a0.sys[sy];
+    wl = wid - a0.seg[sy];
+    if (wl >= a.ncols) return;
+  }
+  const int j = a.cols ? a.cols[wl] : a.col_off + wl;
+  const int jb = a.Jcolptr[j];
+  const int nj = a.Jcolptr[j + 1] - jb;
+  const int64_t ib = a.Icolptr[j];
+  const int ni = (int)(a.Icolptr[j + 1] - ib);
+  if (lane < ni) Is[lane] = a.Irow[ib + lane];
+  for (int q = lane; q < (JM + 1) * LD; q += 64) S[q] = T(0);
+  __syncthreads();
+  if (lane < nj) {
+    const int c = a.Jrow[jb + lane];
+    T* colt = S + lane * LD;
+    int q = 0;
+    for (int e = a.Acolptr[c]; e < a.Acolptr[c + 1]; ++e) {
+      const int r = a.Arowidx[e];
+      q += lds_lower_bound(Is + q, ni - q, r);  // rows of A(:, c) ascend: search from the last hit
+      colt[q] = (T)a.aval[a.Acscslot[e]];
+    }
+  }
+  T* B = S + nj * LD;
+  if (a.rhs_aval) {  // A(1) e_j on I_j: the entries of column j
+    for (int e = a.Acolptr[j] + lane; e < a.Acolptr[j + 1]; e += 64)
+      B[lds_lower_bound(Is, ni, a.Arowidx[e])] = (T)a.rhs_aval[a.Acscslot[e]];
+  } else if (lane == 0) {
+    B[lds_lower_bound(Is, ni, j)] = T(1);
+  }
+  __syncthreads();
+  // lane c <= nj: its column (lanes beyond take the right-hand side again and
+  // are never read)
+  const int cl = lane <= nj ? lane : nj;
+  T A_[IM];
+#pragma unroll
+  for (int r = 0; r < IM; ++r) A_[r] = S[cl * LD + r];
+  if constexpr (Q16) {
+    if (lane < nj || (lane == nj && a.rhs_aval)) {
+      T mx = T(0);
+#pragma unroll
+      for (int r = 0; r < IM; ++r) mx = fmaxf(mx, fabsf(A_[r]));
+      const Q16Scale q = q16_scale(mx);
+#pragma unroll
+      for (int r = 0; r < IM; ++r) A_[r] = q16(A_[r], q);
+    }
+  }
+  T minDiag = T(3.0e38);
+#pragma unroll
+  for (int k = 0; k < JM; ++k) {
+    if (k < nj) {
+      if (lane == k) {
+#pragma unroll
+        for (int r = k; r < IM; ++r) sv[r] = A_[r];
+      }
+      __syncthreads();
+      T x[IM];
+      T dot = T(0);
+#pragma unroll
+      for (int r = k; r < IM; ++r) {
+        x[r] = sv[r];
+        dot += x[r] * A_[r];
+      }
+      const T sig = readlane_f(dot, k);
+      const T alpha = x[k];
+      T beta = alpha;
+      if (sig != alpha * alpha) {
+        const T nrm = sqrt(sig);
+        beta = (alpha >= T(0)) ? -nrm : nrm;
+        const T denom = beta * (beta - alpha);
+        if (lane > k) {
+          const T f = (dot - beta * A_[k]) / denom;
+          A_[k] -= f * (alpha - beta);
+#pragma unroll
+          for (int r = k + 1; r < IM; ++r) A_[r] -= f * x[r];
+        }
+      }
+      if (lane == k) {
+        A_[k] = beta;
+#pragma unroll
+        for (int r = k + 1; r < IM; ++r) A_[r] = T(0);
+      }
+      const T ab = beta < T(0) ? -beta : beta;
+      minDiag = ab < minDiag ? ab : minDiag;
+      __syncthreads();  // sv is written again by the next step
+    }
+  }
+  // R (columns 0..nj-1) and Q^T b (column nj) back to LDS
+  if (lane <= nj) {
+#pragma unroll
+    for (int r = 0; r < IM; ++r) S[lane * LD + r] = A_[r];
+  }
+  __syncthreads();
+  T mx = T(0);
+  for (int q = lane; q < nj * nj; q += 64) {
+    const int r = q % nj, c = q / nj;
+    if (r <= c) {
+      T v = S[c * LD + r];
+      v = v < T(0) ? -v : v;
+      mx = v > mx ? v : mx;
+    }
+  }
+  const T maxR = wave_max(mx);
+  // back substitution, column oriented: y in B[0:nj]
+  for (int i = nj - 1; i >= 0; --i) {
+    __syncthreads();
+    const T pi = B[i] / S[i * LD + i];
+    __syncthreads();
+    if (lane == 0) B[i] = pi;
+    if (lane < i) B[lane] -= S[i * LD + lane] * pi;
+  }
+  __syncthreads();
+  T rr = T(0);
+  for (int li = nj + lane; li < ni; li += 64) rr += B[li] * B[li];
+  rr = wave_sum(rr);
+  if (lane < nj) a.out[a.Pslot[jb + lane]] = (double)B[lane];
+  if (lane == 0) {
+    a.rho[j] = sqrt((double)rr);
+    const bool singular = (ni < nj) || !(minDiag > T(10.0 * ni * Eps<T>::v) * maxR);
+    if (singular) atomicMin(a.bad_col, j);
+  }
+}
+
 // columns per wavefront of bucket b's kernel for values of sizeof(T) bytes
 // (a launch over several systems pads each system's count to a multiple)
 static int bucket_cpw(int b, int tsize) {
+  if (tsize == 4 && b == 5) return 1;  // the column-owner kernel
   if (b <= 4) return 4;
   if (tsize == 4 && (b == 5 || b == 6)) return 2;
   return 1;
@@ -632,6 +785,10 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
     case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 5:
+      if constexpr (REG32 && !GO) {
+        plaunch(pc, pidx, part, k_spai_col<T, 32, Q16, MULTI>, dim3((unsigned)a.ncols), dim3(64), 0, st, a);
+        break;
+      }
       if constexpr (REG32) {
         plaunch(pc, pidx, part, k_spai_reg<T, 32, 2, Q16, 32, GO, MULTI>, dim3(g32), dim3(256), 0, st, a);
         break;
