@@ -54,10 +54,48 @@ __global__ void k_set_total(int64_t* out, int64_t n, const int64_t* in_last, con
   if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = *excl_last + *in_last;
 }
 
+// the whole scan in one workgroup (sizes up to SCAN_ONE_MAX): thread t owns the
+// contiguous chunk [t per, (t + 1) per), sums it, the 1024 sums are scanned in
+// LDS, and the chunk is rewritten with its exclusive prefix; buf[n] = total.
+// One launch instead of the tile/recursion/add/total sequence, which for the
+// pattern set-up of many small systems is mostly launch overhead.
+constexpr int SCAN_ONE_T = 1024;
+constexpr int64_t SCAN_ONE_MAX = 131072;
+
+__global__ __launch_bounds__(SCAN_ONE_T) void k_scan_one(int64_t* buf, int64_t n) {
+  __shared__ int64_t s[SCAN_ONE_T];
+  const int t = threadIdx.x;
+  const int64_t per = (n + SCAN_ONE_T - 1) / SCAN_ONE_T;
+  const int64_t b = (int64_t)t * per, e = b + per < n ? b + per : n;
+  int64_t sum = 0;
+#pragma unroll 8
+  for (int64_t i = b; i < e; ++i) sum += buf[i];
+  s[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < SCAN_ONE_T; o <<= 1) {
+    const int64_t add = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int64_t run = s[t] - sum;
+  for (int64_t i = b; i < e; ++i) {
+    const int64_t x = buf[i];
+    buf[i] = run;
+    run += x;
+  }
+  if (t == SCAN_ONE_T - 1) buf[n] = s[t];
+}
+
 // in and out have n+1 slots; in[0..n) are counts (in may alias out).
 int scan_exclusive(int64_t* buf, int64_t n, hipStream_t st) {
   if (n == 0) {
     PMOR_HIP(hipMemsetAsync(buf, 0, sizeof(int64_t), st));
+    return PMOR_OK;
+  }
+  if (n <= SCAN_ONE_MAX) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(SCAN_ONE_T), 0, st, buf, n);
+    PMOR_HIP(hipGetLastError());
     return PMOR_OK;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
