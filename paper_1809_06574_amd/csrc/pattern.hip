@@ -441,18 +441,16 @@ int check_pairs(int n, const int32_t* rowptr, const int32_t* col, hipStream_t st
 // pattern (n x n, nnz entries in CSR) -> CSC arrays allocated here
 int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* col, int32_t** colptr,
                       int32_t** rowidx, int32_t** slot, int* maxcol, hipStream_t st) {
+  // counts (int64), cursors (int32) and the maximum in one zeroed scratch block
   int64_t* cc = nullptr;
-  int32_t* cursor = nullptr;
-  int* dmax = nullptr;
-  PMOR_HIP(dmalloc((void**)&cc, sizeof(int64_t) * (n + 1), st));
-  PMOR_HIP(dmalloc((void**)&cursor, sizeof(int32_t) * (n + 1), st));
-  PMOR_HIP(dmalloc((void**)&dmax, sizeof(int), st));
+  const size_t scratch_bytes = sizeof(int64_t) * (n + 1) + sizeof(int32_t) * (n + 2);
+  PMOR_HIP(dmalloc((void**)&cc, scratch_bytes, st));
+  int32_t* cursor = reinterpret_cast<int32_t*>(cc + (n + 1));
+  int* dmax = cursor + (n + 1);
   PMOR_HIP(dmalloc((void**)colptr, sizeof(int32_t) * (n + 1), st));
   PMOR_HIP(dmalloc((void**)rowidx, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
   PMOR_HIP(dmalloc((void**)slot, sizeof(int32_t) * (nnz > 0 ? nnz : 1), st));
-  PMOR_HIP(hipMemsetAsync(cc, 0, sizeof(int64_t) * (n + 1), st));
-  PMOR_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (n + 1), st));
-  PMOR_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
+  PMOR_HIP(hipMemsetAsync(cc, 0, scratch_bytes, st));
   unsigned g = (unsigned)((n + 255) / 256);
   if (n > 0) {
     hipLaunchKernelGGL(k_col_count, dim3(g), dim3(256), 0, st, n, rowptr, col, cc);
@@ -473,8 +471,6 @@ int transpose_pattern(int n, int64_t nnz, const int32_t* rowptr, const int32_t* 
   PMOR_HIP(hipStreamSynchronize(st));
   *maxcol = hmax;
   dfree(cc, st);
-  dfree(cursor, st);
-  dfree(dmax, st);
   return PMOR_OK;
 }
 
@@ -550,11 +546,16 @@ int build_union_pattern(pmor_problem* pb, const pmor_csr* const* terms, int coun
                        n, tp, pb->rowptr, pb->col, nnz, pb->col, pb->maps, pb->tval);
   }
   PMOR_HIP(hipGetLastError());
-  PMOR_HIP(hipStreamSynchronize(st));
+  // (no wait here: the transpose below ends with a synchronisation of the same
+  // stream, after which the fill has read the caller's term arrays)
   dfree(cnt, st);
   dfree(derr, st);
   int maxcol = 0;
-  PMOR_TRY(transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st));
+  const int trc = transpose_pattern(n, nnz, pb->rowptr, pb->col, &pb->colptr, &pb->rowidx, &pb->cscslot, &maxcol, st);
+  if (trc != PMOR_OK) {
+    (void)hipStreamSynchronize(st);  // the fill is done with the caller's terms before the error returns
+    return trc;
+  }
   pb->max_col_len = maxcol;
   PMOR_TRY(build_sell(n, pb->rowptr, pb->col, nnz, sell_max_fill(), &pb->sell, st));
   if (pb->sell.cap > 0) PMOR_HIP(dmalloc((void**)&pb->aval_s, sizeof(double) * pb->sell.cap, st));
