@@ -925,8 +925,7 @@ int build_spai_sets(pmor_spai* h, hipStream_t st) {
     PMOR_HIP(dmalloc((void**)&h->Pslot, sizeof(int32_t) * nnzP, st));
     hipLaunchKernelGGL(k_invert_map, dim3((unsigned)((nnzP + 255) / 256)), dim3(256), 0, st, back, nnzP, h->Pslot);
     PMOR_HIP(hipGetLastError());
-    PMOR_HIP(hipStreamSynchronize(st));
-    dfree(back, st);
+    dfree(back, st);  // stream-ordered: reused only after the inversion
     h->own_P = true;
     h->nnzP = (int32_t)nnzP;
     PMOR_TRY(build_sell(n, h->Prowptr, h->Pcol, nnzP, sell_max_fill(), &h->psell, st));
