@@ -848,7 +848,7 @@ def c2_bench(ctx, nsys, precision="f32", pool=True):
                        for r, T in job.terms.items()})
         dpats.append(tuple(torch.as_tensor(x).to(dev) for x in job.pattern))
         Bs.append(torch.as_tensor(job.B, device=dev))
-    from paper_1809_06574_amd import lib as L, spai_build_batch, problem_create_batch
+    from paper_1809_06574_amd import lib as L, spai_build_batch, problem_create_batch, spai_update_batch
     # one system after another: problem, P_1 (spai_build), update
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -869,8 +869,7 @@ def c2_bench(ctx, nsys, precision="f32", pool=True):
     bitems = [(pb, job.s, job.p_list[0], pat) for pb, job, pat in zip(pbs, jobs, dpats)]
     hs, _, _ = spai_build_batch(ctx, bitems, precision=precision)
     t_spai = time.perf_counter() - t - t_problems
-    for job, h in zip(jobs, hs):
-        h.update(job.s, job.p_list[1])
+    spai_update_batch(ctx, [(h, job.s, job.p_list[1]) for job, h in zip(jobs, hs)])
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t
     t_updates = t_prep - t_problems - t_spai

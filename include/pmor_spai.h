@@ -301,6 +301,22 @@ int spai_build_batch(pmor_ctx* ctx, pmor_spai_build_item* items, int32_t count);
  * PMOR_EINVAL for the second approach with PMOR_UPD_PATTERN. */
 int spai_update(pmor_spai* h, double s, double p, pmor_stats* stats);
 int spai_update_c(pmor_spai* h, const double* coef, pmor_stats* stats);
+/* spai_update of several handles (of ctx), each at its own point (the batches
+ * of independent systems of Section 3: every system's update is its own).  Per
+ * item: h, the point coef (host, or NULL for (s, p)); out: status (as
+ * spai_update returns it; PMOR_ESINGULAR with bad_column).  The real U-diag
+ * updates (either approach) are queued back to back on ctx's stream and their
+ * flags read back together; other update kinds run one after another as
+ * spai_update.  Every handle ends bit for bit as after spai_update.  Returns
+ * PMOR_OK or the first item's failure; synchronises. */
+typedef struct pmor_spai_update_item {
+  pmor_spai* h;
+  double s, p;
+  const double* coef;
+  int32_t status;       /* out */
+  int32_t bad_column;   /* out */
+} pmor_spai_update_item;
+int spai_update_batch(pmor_ctx* ctx, pmor_spai_update_item* items, int32_t count);
 /* Recompute the SPAI of A(s,p) in place (the rebuild policy); the anchor is
  * moved to (s,p). */
 int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats);

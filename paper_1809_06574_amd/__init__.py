@@ -17,6 +17,7 @@ _LAZY = {"lib": ("lib", None), "Context": ("api", "Context"), "Problem": ("api",
          "Server": ("api", "Server"), "Recycler": ("api", "Recycler"),
          "spai_build_batch": ("api", "spai_build_batch"),
          "problem_create_batch": ("api", "problem_create_batch"),
+         "spai_update_batch": ("api", "spai_update_batch"),
          "complex_to_real": ("api", "complex_to_real"), "real_to_complex": ("api", "real_to_complex")}
 
 

@@ -339,6 +339,28 @@ def spai_build_batch(ctx: Context, items, precision="f64", update="diag", raise_
     return out, status, rc
 
 
+def spai_update_batch(ctx: Context, items, raise_on_error=True):
+    """spai_update of several handles, each at its own point (spai_update_batch).
+    ``items``: ``(spai, s, p)`` with p None meaning s is a coefficient vector.
+    Returns (list of status codes, rc)."""
+    n_it = len(items)
+    arr = (L.SpaiUpdateItem * max(n_it, 1))()
+    keep = []
+    for i, (h, s, p) in enumerate(items):
+        cf = None
+        if _is_coef(s, p):
+            cf = _coef(s, h.pb)
+            keep.append(cf)
+            s, p = 0.0, 0.0
+        arr[i] = L.SpaiUpdateItem(h.handle, float(s), float(p),
+                                  C.cast(cf, C.POINTER(C.c_double)) if cf is not None else None, 0, -1)
+    rc = L.spai_update_batch(ctx.handle, arr, n_it)
+    status = [arr[i].status for i in range(n_it)]
+    if raise_on_error:
+        L.check(rc, "spai_update_batch")
+    return status, rc
+
+
 def batch_solve(ctx: Context, items, m=30, tol=1e-8, max_cycles=20, raise_on_error=True):
     """Solve independent systems together (pmor_batch_solve).  ``items``: sequence of
     ``(problem, spai_or_None, s, p, B)`` or ``(problem, spai, s, p, B, X)``; with p None,

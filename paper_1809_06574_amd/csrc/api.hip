@@ -1047,6 +1047,72 @@ int spai_update_c(pmor_spai* h, const double* coef, pmor_stats* stats) {
   return spai_update_pt(h, pt, stats);
 }
 
+int spai_update_batch(pmor_ctx* ctx, pmor_spai_update_item* items, int32_t count) {
+  if (!ctx || (!items && count > 0)) return fail(PMOR_EINVAL, "NULL argument");
+  if (count < 0) return fail(PMOR_EINVAL, "count must not be negative");
+  PMOR_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  int first = -1;
+  std::string first_msg;
+  auto item_fail = [&](int i, int rc) {
+    items[i].status = rc;
+    if (first < 0) {
+      first = i;
+      first_msg = g_last_error;
+    }
+  };
+  std::vector<int> queued;  // items whose update was queued without a readback
+  for (int i = 0; i < count; ++i) {
+    pmor_spai_update_item& it = items[i];
+    it.status = PMOR_OK;
+    it.bad_column = -1;
+    pmor_spai* h = it.h;
+    if (!h) { item_fail(i, fail(PMOR_EINVAL, "handle is NULL")); continue; }
+    if (h->pb->ctx != ctx) { item_fail(i, fail(PMOR_EINVAL, "handle of another context")); continue; }
+    Point pt;
+    int rc = it.coef ? point_coef(h->pb, it.coef, &pt) : point_sp(h->pb, it.s, it.p, &pt);
+    if (rc != PMOR_OK) { item_fail(i, rc); continue; }
+    if (h->opts.update != PMOR_UPD_DIAG || h->pb->cplx) {  // one after another, as spai_update
+      pmor_stats stt{};
+      rc = spai_update_pt(h, pt, &stt);
+      if (rc != PMOR_OK) {
+        it.bad_column = stt.bad_column;
+        item_fail(i, rc);
+      }
+      continue;
+    }
+    rc = ensure_assembled(h->pb, pt);
+    if (rc == PMOR_OK) rc = run_update_diag(h, h->pb->aval, nullptr, nullptr);
+    if (rc != PMOR_OK) { item_fail(i, rc); continue; }
+    h->d_active = true;
+    queued.push_back(i);
+  }
+  // the queued updates' singular-column flags (the first int of each handle's
+  // reduction block), read back together
+  if (!queued.empty()) {
+    std::vector<int> hbad(queued.size(), 0x7fffffff);
+    int rc = PMOR_OK;
+    for (size_t q = 0; q < queued.size() && rc == PMOR_OK; ++q)
+      if (hipMemcpyAsync(&hbad[q], items[queued[q]].h->red, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = fail(PMOR_EHIP, "copy of the update flags failed");
+    if (rc == PMOR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(PMOR_EHIP, "synchronise failed");
+    for (size_t q = 0; q < queued.size(); ++q) {
+      const int i = queued[q];
+      if (rc != PMOR_OK) {
+        item_fail(i, rc);
+      } else if (hbad[q] != 0x7fffffff) {
+        items[i].bad_column = hbad[q];
+        item_fail(i, fail(PMOR_ESINGULAR, "rank-deficient update problem in column " + std::to_string(hbad[q]) +
+                                              " (item " + std::to_string(i) + ")"));
+      }
+    }
+  } else {
+    PMOR_HIP(hipStreamSynchronize(st));
+  }
+  if (first >= 0) return fail(items[first].status, "item " + std::to_string(first) + ": " + first_msg);
+  return PMOR_OK;
+}
+
 int spai_rebuild(pmor_spai* h, double s, double p, pmor_stats* stats) {
   if (!h) return fail(PMOR_EINVAL, "handle is NULL");
   Point pt;

@@ -52,6 +52,11 @@ class SpaiBuildItem(C.Structure):
                 ("opts", C.c_void_p), ("h", C.c_void_p), ("status", C.c_int32), ("bad_column", C.c_int32)]
 
 
+class SpaiUpdateItem(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("s", C.c_double), ("p", C.c_double), ("coef", C.POINTER(C.c_double)),
+                ("status", C.c_int32), ("bad_column", C.c_int32)]
+
+
 class ProblemItem(C.Structure):
     _fields_ = [("nterms", C.c_int32), ("terms", C.c_void_p), ("pb", C.c_void_p), ("status", C.c_int32)]
 
@@ -112,6 +117,7 @@ _SIGS = {
     "spai_build_c": (C.c_int, [P, C.POINTER(D), C.POINTER(SpaiOpts), PP, C.POINTER(Stats)]),
     "spai_build_batch": (C.c_int, [P, C.POINTER(SpaiBuildItem), I32]),
     "pmor_problem_create_batch": (C.c_int, [P, C.POINTER(ProblemItem), I32]),
+    "spai_update_batch": (C.c_int, [P, C.POINTER(SpaiUpdateItem), I32]),
     "spai_update": (C.c_int, [P, D, D, C.POINTER(Stats)]),
     "spai_update_c": (C.c_int, [P, C.POINTER(D), C.POINTER(Stats)]),
     "spai_rebuild": (C.c_int, [P, D, D, C.POINTER(Stats)]),

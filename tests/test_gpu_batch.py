@@ -235,3 +235,43 @@ def test_problem_create_batch_equals_single_creates(ctx):
     pbs3, st3, rc3 = problem_create_batch(ctx, [aff, broken, jobs[4].terms], raise_on_error=False)
     assert rc3 == L.PMOR_EINVAL and st3 == [0, L.PMOR_EINVAL, 0] and pbs3[1] is None
     assert torch.equal(pbs3[2].pattern()[1], pbs[4].pattern()[1])
+
+
+def test_spai_update_batch_equals_sequential_updates(ctx):
+    """spai_update_batch leaves every handle bit for bit as spai_update does: the
+    real U-diag updates queued together (first and second approach, FP32 and FP64
+    least squares, two handles of one problem), a U-pattern handle and an affine
+    problem's handle updated one after another; an item with a bad point fails
+    alone."""
+    from paper_1809_06574_amd import Problem, spai_update_batch, lib as L
+    from synth.gen import config2_system
+    jobs = [config2_system(i) for i in (5, 23)]
+    c0 = config0()
+    pbs = [Problem(ctx, j.terms) for j in jobs]
+    p0 = Problem(ctx, c0.terms)
+    aff = Problem(ctx, [c0.terms[r] for r in ("K0", "M0", "D0")])
+    specs = [(pbs[0], jobs[0].s, jobs[0].p_list, dict(pattern=jobs[0].pattern, precision="f32")),
+             (pbs[1], jobs[1].s, jobs[1].p_list, dict(pattern=jobs[1].pattern, approach="second")),
+             (p0, c0.s, c0.p_list, dict()),
+             (p0, c0.s, c0.p_list, dict(update="pattern")),
+             (p0, c0.s, c0.p_list, dict(approach="second"))]
+
+    def handles():
+        hs = [pb.spai_build(s, pl[0], **kw) for pb, s, pl, kw in specs]
+        hs.append(aff.spai_build([1.0, 0.5, 0.2], None))
+        return hs
+
+    ha, hb = handles(), handles()
+    pts = [(s, pl[1]) for _, s, pl, _ in specs] + [([1.0, 0.6, 0.25], None)]
+    for _ in range(2):  # two rounds: the second approach chains its anchor
+        status, rc = spai_update_batch(ctx, [(h, *pt) for h, pt in zip(ha, pts)])
+        assert rc == 0 and all(x == 0 for x in status)
+        for h, pt in zip(hb, pts):
+            h.update(*pt)
+        for x, y in zip(ha, hb):
+            ex, ey = x.export(), y.export()
+            for key in ("val", "q", "rho"):
+                assert torch.equal(ex[key], ey[key]), key
+    st2, rc2 = spai_update_batch(ctx, [(ha[0], *pts[0]), (ha[2], float("nan"), 0.3), (ha[5], *pts[5])],
+                                 raise_on_error=False)
+    assert rc2 == L.PMOR_EINVAL and st2 == [0, L.PMOR_EINVAL, 0]
