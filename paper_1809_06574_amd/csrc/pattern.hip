@@ -63,28 +63,52 @@ constexpr int SCAN_ONE_T = 1024;
 constexpr int64_t SCAN_ONE_MAX = 131072;
 
 __global__ __launch_bounds__(SCAN_ONE_T) void k_scan_one(int64_t* buf, int64_t n) {
-  __shared__ int64_t s[SCAN_ONE_T];
+  __shared__ int64_t s[2 * (SCAN_ONE_T / 64)];  // wavefront totals, then their inclusive scan
   const int t = threadIdx.x;
   const int64_t per = (n + SCAN_ONE_T - 1) / SCAN_ONE_T;
   const int64_t b = (int64_t)t * per, e = b + per < n ? b + per : n;
   int64_t sum = 0;
-#pragma unroll 8
-  for (int64_t i = b; i < e; ++i) sum += buf[i];
-  s[t] = sum;
+  for (int64_t i0 = b; i0 < e; i0 += 8) {
+    int64_t v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v8[u] = (i0 + u < e) ? buf[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += v8[u];
+  }
+  // inclusive scan of the chunk sums: inside each wavefront by shuffles, then
+  // over the 16 wavefront totals (two barriers)
+  const int lane = t & 63, w = t >> 6;
+  int64_t x = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s[w] = x;
   __syncthreads();
-  for (int o = 1; o < SCAN_ONE_T; o <<= 1) {
-    const int64_t add = t >= o ? s[t - o] : 0;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
+  if (w == 0) {
+    int64_t v = lane < SCAN_ONE_T / 64 ? s[lane] : 0;
+    for (int o = 1; o < SCAN_ONE_T / 64; o <<= 1) {
+      const int64_t y = __shfl_up(v, o, 64);
+      if (lane >= o) v += y;
+    }
+    if (lane < SCAN_ONE_T / 64) s[SCAN_ONE_T / 64 + lane] = v;
   }
-  int64_t run = s[t] - sum;
-  for (int64_t i = b; i < e; ++i) {
-    const int64_t x = buf[i];
-    buf[i] = run;
-    run += x;
+  __syncthreads();
+  // the chunk in blocks of 8: the block's loads are issued together, then its
+  // prefixes stored
+  int64_t run = x - sum + (w > 0 ? s[SCAN_ONE_T / 64 + w - 1] : 0);
+  for (int64_t i0 = b; i0 < e; i0 += 8) {
+    int64_t v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v8[u] = (i0 + u < e) ? buf[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < e) {
+        buf[i0 + u] = run;
+        run += v8[u];
+      }
   }
-  if (t == SCAN_ONE_T - 1) buf[n] = s[t];
+  if (t == SCAN_ONE_T - 1) buf[n] = s[2 * (SCAN_ONE_T / 64) - 1];
 }
 
 // in and out have n+1 slots; in[0..n) are counts (in may alias out).
