@@ -612,8 +612,8 @@ __global__ __launch_bounds__(64 * LDS_NW) void k_spai_lds(LsArgs a0, int ldI, in
 // ---------------------------------------------------------------------------
 // Column-owner kernel: |J| <= JM, |I| <= 64, 4-byte values (the (32, 64)
 // bucket: against the register kernel's two columns per wavefront it takes 0.54
-// of the time on the batch workload; for |J| <= 16 the register kernel's four
-// columns per wavefront stay faster, most lanes here would idle).  One
+// of the time on the batch workload; |J| <= 16 takes k_spai_col2 below, two
+// columns per workgroup, since one column would leave most lanes idle).  One
 // 64-lane workgroup per column j.  Lane c holds column c of A(I_j, J_j), all 64
 // rows in registers, and lane |J_j| the right-hand side, so every inner product
 // a reflector step needs is a sum inside one lane; only the reflector crosses
@@ -761,10 +761,166 @@ __global__ __launch_bounds__(64) void k_spai_col(LsArgs a0) {
   }
 }
 
+// The same with two columns per 64-lane workgroup for |J| <= 16 (the (16, 64)
+// bucket): lanes 32 g .. 32 g + 31 work on the workgroup's column g, each half
+// with its own LDS block; the halves share the barriers, so the reflector loop
+// runs to the larger |J| of the two and each half works while k is below its own.
+template <typename T, bool Q16 = false, bool MULTI = false>
+__global__ __launch_bounds__(64) void k_spai_col2(LsArgs a0) {
+  static_assert(sizeof(T) == 4, "four-byte values");
+  constexpr int JM = 16, IM = 64, LD = IM + 1;
+  __shared__ T S[2][(JM + 1) * LD];
+  __shared__ int Is[2][IM];
+  __shared__ T sv[2][IM];
+  const int lane = threadIdx.x, g = lane >> 5, gl = lane & 31;
+  const int wid = xcd_swizzle(blockIdx.x, gridDim.x) * 2 + g;
+  bool valid = wid < a0.ncols;
+  LsArgs a = a0;
+  int wl = wid;
+  if (MULTI && valid) {
+    const int sy = ls_system(a0.seg, a0.nsys, wid);
+    a = a0.sys[sy];
+    wl = wid - a0.seg[sy];
+    valid = wl < a.ncols;
+  }
+  int j = 0, jb = 0, nj = 0, ni = 0;
+  int64_t ib = 0;
+  if (valid) {
+    j = a.cols ? a.cols[wl] : a.col_off + wl;
+    jb = a.Jcolptr[j];
+    nj = a.Jcolptr[j + 1] - jb;
+    ib = a.Icolptr[j];
+    ni = (int)(a.Icolptr[j + 1] - ib);
+  }
+  const int njmax = max(__builtin_amdgcn_readlane(nj, 0), __builtin_amdgcn_readlane(nj, 32));
+  if (njmax == 0) return;  // both halves empty (a column always holds its diagonal)
+  T* Sg = S[g];
+  int* Ig = Is[g];
+  for (int li = gl; li < ni; li += 32) Ig[li] = a.Irow[ib + li];
+  for (int q = gl; q < (JM + 1) * LD; q += 32) Sg[q] = T(0);
+  __syncthreads();
+  if (gl < nj) {
+    const int c = a.Jrow[jb + gl];
+    T* colt = Sg + gl * LD;
+    int q = 0;
+    for (int e = a.Acolptr[c]; e < a.Acolptr[c + 1]; ++e) {
+      const int r = a.Arowidx[e];
+      q += lds_lower_bound(Ig + q, ni - q, r);
+      colt[q] = (T)a.aval[a.Acscslot[e]];
+    }
+  }
+  T* B = Sg + nj * LD;
+  if (valid) {
+    if (a.rhs_aval) {
+      for (int e = a.Acolptr[j] + gl; e < a.Acolptr[j + 1]; e += 32)
+        B[lds_lower_bound(Ig, ni, a.Arowidx[e])] = (T)a.rhs_aval[a.Acscslot[e]];
+    } else if (gl == 0) {
+      B[lds_lower_bound(Ig, ni, j)] = T(1);
+    }
+  }
+  __syncthreads();
+  const int cl = gl <= nj ? gl : nj;
+  T A_[IM];
+#pragma unroll
+  for (int r = 0; r < IM; ++r) A_[r] = Sg[cl * LD + r];
+  if constexpr (Q16) {
+    if (valid && (gl < nj || (gl == nj && a.rhs_aval))) {
+      T mx = T(0);
+#pragma unroll
+      for (int r = 0; r < IM; ++r) mx = fmaxf(mx, fabsf(A_[r]));
+      const Q16Scale q = q16_scale(mx);
+#pragma unroll
+      for (int r = 0; r < IM; ++r) A_[r] = q16(A_[r], q);
+    }
+  }
+  T minDiag = T(3.0e38);
+#pragma unroll
+  for (int k = 0; k < JM; ++k) {
+    if (k < njmax) {
+      const bool act = k < nj;  // this half still reflects
+      if (act && gl == k) {
+#pragma unroll
+        for (int r = k; r < IM; ++r) sv[g][r] = A_[r];
+      }
+      __syncthreads();
+      if (act) {
+        T x[IM];
+        T dot = T(0);
+#pragma unroll
+        for (int r = k; r < IM; ++r) {
+          x[r] = sv[g][r];
+          dot += x[r] * A_[r];
+        }
+        const T s0 = readlane_f(dot, k), s1 = readlane_f(dot, 32 + k);
+        const T sig = g ? s1 : s0;
+        const T alpha = x[k];
+        T beta = alpha;
+        if (sig != alpha * alpha) {
+          const T nrm = sqrt(sig);
+          beta = (alpha >= T(0)) ? -nrm : nrm;
+          const T denom = beta * (beta - alpha);
+          if (gl > k) {
+            const T f = (dot - beta * A_[k]) / denom;
+            A_[k] -= f * (alpha - beta);
+#pragma unroll
+            for (int r = k + 1; r < IM; ++r) A_[r] -= f * x[r];
+          }
+        }
+        if (gl == k) {
+          A_[k] = beta;
+#pragma unroll
+          for (int r = k + 1; r < IM; ++r) A_[r] = T(0);
+        }
+        const T ab = beta < T(0) ? -beta : beta;
+        minDiag = ab < minDiag ? ab : minDiag;
+      }
+      __syncthreads();
+    }
+  }
+  if (valid && gl <= nj) {
+#pragma unroll
+    for (int r = 0; r < IM; ++r) Sg[gl * LD + r] = A_[r];
+  }
+  __syncthreads();
+  T mx = T(0);
+  for (int q = gl; q < nj * nj; q += 32) {
+    const int r = q % nj, c = q / nj;
+    if (r <= c) {
+      T v = Sg[c * LD + r];
+      v = v < T(0) ? -v : v;
+      mx = v > mx ? v : mx;
+    }
+  }
+  // the maximum over each half's 32 lanes
+  for (int o = 16; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  const T maxR = mx;
+  for (int i = njmax - 1; i >= 0; --i) {
+    __syncthreads();
+    const T pi = i < nj ? B[i] / Sg[i * LD + i] : T(0);
+    __syncthreads();
+    if (i < nj) {
+      if (gl == 0) B[i] = pi;
+      if (gl < i) B[gl] -= Sg[i * LD + gl] * pi;
+    }
+  }
+  __syncthreads();
+  T rr = T(0);
+  for (int li = nj + gl; li < ni; li += 32) rr += B[li] * B[li];
+  for (int o = 16; o >= 1; o >>= 1) rr += __shfl_xor(rr, o, 64);
+  if (!valid) return;
+  if (gl < nj) a.out[a.Pslot[jb + gl]] = (double)B[gl];
+  if (gl == 0) {
+    a.rho[j] = sqrt((double)rr);
+    const bool singular = (ni < nj) || !(minDiag > T(10.0 * ni * Eps<T>::v) * maxR);
+    if (singular) atomicMin(a.bad_col, j);
+  }
+}
+
 // columns per wavefront of bucket b's kernel for values of sizeof(T) bytes
 // (a launch over several systems pads each system's count to a multiple)
 static int bucket_cpw(int b, int tsize) {
-  if (tsize == 4 && b == 5) return 1;  // the column-owner kernel
+  if (tsize == 4 && b == 5) return 1;  // the column-owner kernels
+  if (tsize == 4 && b == 3) return 2;
   if (b <= 4) return 4;
   if (tsize == 4 && (b == 5 || b == 6)) return 2;
   return 1;
@@ -782,7 +938,13 @@ static int launch_bucket(int b, LsArgs a, int maxJ, int maxI, hipStream_t st, pm
     case 0: plaunch(pc, pidx, part, k_spai_reg<T, 8, 1, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 1: plaunch(pc, pidx, part, k_spai_reg<T, 8, 2, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 2: plaunch(pc, pidx, part, k_spai_reg<T, 8, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
-    case 3: plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
+    case 3:
+      if constexpr (REG32 && !GO) {
+        plaunch(pc, pidx, part, k_spai_col2<T, Q16, MULTI>, dim3((unsigned)((a.ncols + 1) / 2)), dim3(64), 0, st, a);
+        break;
+      }
+      plaunch(pc, pidx, part, k_spai_reg<T, 16, 4, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a);
+      break;
     case 4: plaunch(pc, pidx, part, k_spai_reg<T, 16, 8, Q16, 16, GO, MULTI>, dim3(g16), dim3(256), 0, st, a); break;
     case 5:
       if constexpr (REG32 && !GO) {
